@@ -1,0 +1,219 @@
+"""FP64 CPU oracle for the shallow-water step -- TEST INFRASTRUCTURE ONLY.
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of
+``bench.py`` may import this package.  The product path (the HIP library and
+its Python binding) never touches it, and the two share no code: the oracle is
+plain C (``swe_oracle.c``, compiled with ``gcc -ffp-contract=off``) driven
+through ctypes from here.
+
+Parity pins for each function are in ``tests/test_oracle_*.py``.  The one part
+without a pin independent of the oracle itself is the inflow boundary's exact
+delivered discharge (the ghost-state inflow does not impose Q exactly):
+parity unpinned for the value of the boundary-flux integral under inflow, only
+its role in the mass balance is pinned.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "swe_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+_c_double_p = ctypes.POINTER(ctypes.c_double)
+_c_int32_p = ctypes.POINTER(ctypes.c_int32)
+_c_int64_p = ctypes.POINTER(ctypes.c_int64)
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (plain C, FP64, no contraction)."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp"
+        cmd = ["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fPIC",
+               "-shared", "-o", tmp, _SRC, "-lm"]
+        subprocess.check_call(cmd)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build()
+        L = ctypes.CDLL(_LIB)
+        L.om_mesh_new.restype = ctypes.c_void_p
+        L.om_mesh_new.argtypes = [_c_double_p, ctypes.c_int64, _c_int32_p, ctypes.c_int64,
+                                  _c_int32_p, _c_int32_p, ctypes.c_int64, ctypes.c_char_p, ctypes.c_int]
+        L.om_mesh_free.argtypes = [ctypes.c_void_p]
+        L.om_mesh_n_edges.restype = ctypes.c_int64
+        L.om_mesh_n_edges.argtypes = [ctypes.c_void_p]
+        L.om_mesh_n_boundary_edges.restype = ctypes.c_int64
+        L.om_mesh_n_boundary_edges.argtypes = [ctypes.c_void_p]
+        L.om_mesh_geometry.argtypes = [ctypes.c_void_p] + [_c_double_p] * 6 + [_c_int32_p]
+        L.om_sim_new.restype = ctypes.c_void_p
+        L.om_sim_new.argtypes = [ctypes.c_void_p, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                 ctypes.c_double, _c_double_p, _c_double_p, _c_double_p, _c_double_p,
+                                 _c_double_p, ctypes.c_int32, _c_int32_p, _c_int32_p, _c_double_p,
+                                 _c_int32_p, _c_double_p, _c_double_p, ctypes.c_double,
+                                 ctypes.c_char_p, ctypes.c_int]
+        L.om_sim_free.argtypes = [ctypes.c_void_p]
+        L.om_next_dt.restype = ctypes.c_double
+        L.om_next_dt.argtypes = [ctypes.c_void_p, ctypes.c_double]
+        L.om_step.restype = ctypes.c_int
+        L.om_step.argtypes = [ctypes.c_void_p, ctypes.c_double, _c_double_p]
+        L.om_run_until.restype = ctypes.c_int
+        L.om_run_until.argtypes = [ctypes.c_void_p, ctypes.c_double, ctypes.c_int64, _c_int64_p]
+        L.om_get_state.argtypes = [ctypes.c_void_p, _c_double_p, _c_double_p, _c_double_p, _c_double_p]
+        L.om_set_state.argtypes = [ctypes.c_void_p, _c_double_p, _c_double_p, _c_double_p, ctypes.c_double]
+        L.om_diag.argtypes = [ctypes.c_void_p, _c_double_p, _c_double_p, _c_double_p, _c_int64_p]
+        L.om_hllc.argtypes = [ctypes.c_double] * 7 + [_c_double_p]
+        L.om_friction.restype = ctypes.c_double
+        L.om_friction.argtypes = [ctypes.c_double] * 5
+        _lib = L
+    return _lib
+
+
+def _dp(a: Optional[np.ndarray]):
+    if a is None:
+        return None
+    return a.ctypes.data_as(_c_double_p)
+
+
+def _ip(a: Optional[np.ndarray]):
+    if a is None:
+        return None
+    return a.ctypes.data_as(_c_int32_p)
+
+
+class OracleError(RuntimeError):
+    pass
+
+
+def hllc(hL, unL, utL, hR, unR, utR, g=9.81):
+    F = np.zeros(3)
+    lib().om_hllc(hL, unL, utL, hR, unR, utR, g, _dp(F))
+    return F
+
+
+def friction_factor(qabs, h, gn2, dt, h_min=1e-4):
+    return lib().om_friction(qabs, h, gn2, dt, h_min)
+
+
+class Mesh:
+    def __init__(self, nodes, tri, bnd_seg=None, bnd_tag=None):
+        L = lib()
+        self.nodes = np.ascontiguousarray(nodes, np.float64)
+        self.tri = np.ascontiguousarray(tri, np.int32)
+        seg = np.zeros((0, 2), np.int32) if bnd_seg is None else np.ascontiguousarray(bnd_seg, np.int32)
+        tag = np.zeros((0,), np.int32) if bnd_tag is None else np.ascontiguousarray(bnd_tag, np.int32)
+        err = ctypes.create_string_buffer(256)
+        self._p = L.om_mesh_new(_dp(self.nodes), len(self.nodes), _ip(self.tri), len(self.tri),
+                                _ip(seg), _ip(tag), len(seg), err, 256)
+        if not self._p:
+            raise OracleError(err.value.decode())
+        self.n_cells = len(self.tri)
+
+    @property
+    def n_edges(self):
+        return lib().om_mesh_n_edges(self._p)
+
+    @property
+    def n_boundary_edges(self):
+        return lib().om_mesh_n_boundary_edges(self._p)
+
+    def geometry(self):
+        n = self.n_cells
+        out = dict(area=np.zeros(n), zb=np.zeros(n), rho=np.zeros((n, 3)), nx=np.zeros((n, 3)),
+                   ny=np.zeros((n, 3)), length=np.zeros((n, 3)), nbr=np.zeros((n, 3), np.int32))
+        lib().om_mesh_geometry(self._p, _dp(out["area"]), _dp(out["zb"]), _dp(out["rho"]), _dp(out["nx"]),
+                               _dp(out["ny"]), _dp(out["length"]), _ip(out["nbr"]))
+        return out
+
+    def __del__(self):
+        if getattr(self, "_p", None):
+            lib().om_mesh_free(self._p)
+            self._p = None
+
+
+class Sim:
+    """One FP64 oracle run of a scenario (see swe_inputs.Scenario)."""
+
+    def __init__(self, sc, t0: float = 0.0, mesh: Optional[Mesh] = None, dt_max: Optional[float] = None):
+        L = lib()
+        self.mesh = mesh or Mesh(sc.nodes, sc.tri, sc.bnd_seg, sc.bnd_tag)
+        n = sc.n_cells
+        bcs = sc.bcs
+        tags = np.array([b.tag for b in bcs], np.int32)
+        kinds = np.array([b.kind for b in bcs], np.int32)
+        slopes = np.array([b.slope for b in bcs], np.float64)
+        npts = np.array([0 if b.t is None else len(b.t) for b in bcs], np.int32)
+        bt = np.concatenate([np.asarray(b.t, np.float64) for b in bcs if b.t is not None] or [np.zeros(0)])
+        bQ = np.concatenate([np.asarray(b.Q, np.float64) for b in bcs if b.Q is not None] or [np.zeros(0)])
+        H0 = None if sc.H0 is None else np.ascontiguousarray(sc.H0, np.float64)
+        h0 = None if sc.h0 is None else np.ascontiguousarray(sc.h0, np.float64)
+        self._keep = [tags, kinds, slopes, npts, bt, bQ, H0, h0]
+        qx0 = np.ascontiguousarray(sc.qx0, np.float64)
+        qy0 = np.ascontiguousarray(sc.qy0, np.float64)
+        man = np.ascontiguousarray(sc.manning, np.float64)
+        err = ctypes.create_string_buffer(256)
+        self._p = L.om_sim_new(self.mesh._p, sc.g, sc.cfl, sc.h_min, sc.dt_max if dt_max is None else dt_max,
+                               _dp(H0), _dp(h0), _dp(qx0), _dp(qy0), _dp(man), len(bcs),
+                               _ip(tags), _ip(kinds), _dp(slopes), _ip(npts), _dp(bt), _dp(bQ),
+                               t0, err, 256)
+        if not self._p:
+            raise OracleError(err.value.decode())
+        self.n = n
+
+    def __del__(self):
+        if getattr(self, "_p", None):
+            lib().om_sim_free(self._p)
+            self._p = None
+
+    def next_dt(self, t_end=float("inf")):
+        return lib().om_next_dt(self._p, t_end)
+
+    def step(self, t_end=float("inf")):
+        dt = ctypes.c_double()
+        rc = lib().om_step(self._p, t_end, ctypes.byref(dt))
+        if rc:
+            raise OracleError(f"oracle step failed ({rc})")
+        return dt.value
+
+    def run_until(self, t_end, max_steps=0):
+        n = ctypes.c_int64()
+        rc = lib().om_run_until(self._p, t_end, max_steps, ctypes.byref(n))
+        if rc:
+            raise OracleError(f"oracle run failed ({rc})")
+        return n.value
+
+    def run_steps(self, k, t_end=float("inf")):
+        return self.run_until(t_end, max_steps=k)
+
+    def state(self):
+        H, qx, qy = np.zeros(self.n), np.zeros(self.n), np.zeros(self.n)
+        t = ctypes.c_double()
+        lib().om_get_state(self._p, _dp(H), _dp(qx), _dp(qy), ctypes.byref(t))
+        return H, qx, qy, t.value
+
+    def set_state(self, H, qx, qy, t):
+        H, qx, qy = (np.ascontiguousarray(a, np.float64) for a in (H, qx, qy))
+        lib().om_set_state(self._p, _dp(H), _dp(qx), _dp(qy), t)
+
+    @property
+    def t(self):
+        return self.state()[3]
+
+    def diag(self):
+        m, b, c = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+        s = ctypes.c_int64()
+        lib().om_diag(self._p, ctypes.byref(m), ctypes.byref(b), ctypes.byref(c), ctypes.byref(s))
+        return dict(mass=m.value, bnd_flux=b.value, clipped=c.value, steps=s.value)

@@ -1,0 +1,605 @@
+/*
+ * FP64 CPU oracle for the shallow-water step.  TEST INFRASTRUCTURE ONLY (see
+ * swe_oracle.h).  Plain C, edge loop, no blocking, no fusion beyond what the
+ * scheme states.  Every function names the passage of the paper it follows.
+ *
+ * Scheme (paper, section "Numerical solution" / "Hydrodynamics"):
+ *   unknowns U = [H, qx, qy], h = H - z_B                 (eq. swe_vectorial_form)
+ *   U_i^{n+1} = U_i^n - dt/|Omega_i| sum_j l_ij F_ij + dt S_i   (eq. hydrodynamicupdateformula)
+ *   F_ij from the HLLC approximate Riemann solver         (HLLC paragraph, Toro 1994)
+ *   bed slope by hydrostatic reconstruction of modified states, written in
+ *   fluctuation form (well balanced)                       (source-term paragraph)
+ *   friction by operator splitting after the flux update  (source-term paragraph,
+ *                                                          eq. friction_closure, Manning row)
+ *   dt = CFL min_i min_j rho_ij / lambda_ij                (eq. CFL_condition)
+ *   walls: reflective, frictionless, impermeable          (section "Boundary conditions")
+ *
+ * Readings where the paper is silent are listed where they are used.
+ */
+#include "swe_oracle.h"
+
+#include <math.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* depth below which a reconstructed edge state is dry [m] */
+#define OM_H_DRY 1e-12
+
+struct om_mesh {
+    int64_t nv, nc, ne, nb;
+    double *x, *y, *zn;
+    int32_t *tri;        /* 3*nc, counter-clockwise */
+    double *area, *zb;   /* per cell */
+    int32_t *eL, *eR;    /* cells of edge e; eR = -1 on the boundary */
+    int32_t *ekL, *ekR;  /* local edge index of e inside L and R */
+    int32_t *etag;       /* boundary tag, -1 when untagged */
+    double *enx, *eny, *elen; /* unit normal pointing from L to R (outward of L), length */
+    int32_t *cell_edge;  /* 3*nc: edge id of the cell's local edge k */
+    double *rho;         /* 3*nc: twice the centroid-to-edge distance */
+};
+
+typedef struct {
+    int32_t tag, kind, npts;
+    double slope, length;
+    double *t, *Q;
+} om_bc;
+
+struct om_sim {
+    const om_mesh *m;
+    double g, cfl, h_min, dt_max;
+    double *H, *qx, *qy, *gn2;
+    double t;
+    int32_t nbc;
+    om_bc *bc;
+    int32_t *ebc;        /* per edge: index into bc[] or -1 (wall) */
+    double *cont;        /* 9*nc: contribution of each local edge, 3 components */
+    double bsum, bcomp;  /* Neumaier sum of dt * l * mass flux leaving the domain */
+    double clip, clipc;  /* Neumaier sum of volume added by the positivity clip */
+    int64_t steps;
+};
+
+static void seterr(char *err, int len, const char *msg) {
+    if (err && len > 0) {
+        strncpy(err, msg, (size_t)len - 1);
+        err[len - 1] = 0;
+    }
+}
+
+static void neumaier(double *sum, double *comp, double v) {
+    double t = *sum + v;
+    if (fabs(*sum) >= fabs(v))
+        *comp += (*sum - t) + v;
+    else
+        *comp += (v - t) + *sum;
+    *sum = t;
+}
+
+/* ------------------------------------------------------------------ mesh */
+typedef struct {
+    int32_t a, b, cell, k;
+} half_edge;
+
+static int cmp_half(const void *p, const void *q) {
+    const half_edge *u = (const half_edge *)p, *v = (const half_edge *)q;
+    if (u->a != v->a) return u->a < v->a ? -1 : 1;
+    if (u->b != v->b) return u->b < v->b ? -1 : 1;
+    if (u->cell != v->cell) return u->cell < v->cell ? -1 : 1;
+    return 0;
+}
+
+typedef struct {
+    int32_t a, b, tag;
+} seg_key;
+
+static int cmp_seg(const void *p, const void *q) {
+    const seg_key *u = (const seg_key *)p, *v = (const seg_key *)q;
+    if (u->a != v->a) return u->a < v->a ? -1 : 1;
+    if (u->b != v->b) return u->b < v->b ? -1 : 1;
+    return 0;
+}
+
+void om_mesh_free(om_mesh *m) {
+    if (!m) return;
+    free(m->x); free(m->y); free(m->zn); free(m->tri); free(m->area); free(m->zb);
+    free(m->eL); free(m->eR); free(m->ekL); free(m->ekR); free(m->etag);
+    free(m->enx); free(m->eny); free(m->elen); free(m->cell_edge); free(m->rho);
+    free(m);
+}
+
+/* Conforming triangulation (section "Domain discretization"): every interior
+ * edge is shared by exactly two cells; n_ij points toward the neighbour.
+ * Reading: the cell bed is the mean of its three node elevations (meshes
+ * carry node elevations); the orientation of an interior edge is taken from
+ * the cell with the smaller index. */
+om_mesh *om_mesh_new(const double *xyz, int64_t nv, const int32_t *tri, int64_t nc,
+                     const int32_t *seg, const int32_t *tag, int64_t ns, char *err, int elen) {
+    om_mesh *m = (om_mesh *)calloc(1, sizeof(om_mesh));
+    half_edge *he = NULL;
+    seg_key *sk = NULL;
+    if (!m) { seterr(err, elen, "out of memory"); return NULL; }
+    if (nv < 3 || nc < 1) { seterr(err, elen, "empty mesh"); goto fail; }
+    m->nv = nv;
+    m->nc = nc;
+    m->x = malloc(sizeof(double) * nv); m->y = malloc(sizeof(double) * nv);
+    m->zn = malloc(sizeof(double) * nv);
+    m->tri = malloc(sizeof(int32_t) * 3 * nc);
+    m->area = malloc(sizeof(double) * nc); m->zb = malloc(sizeof(double) * nc);
+    m->cell_edge = malloc(sizeof(int32_t) * 3 * nc);
+    m->rho = malloc(sizeof(double) * 3 * nc);
+    he = malloc(sizeof(half_edge) * 3 * nc);
+    if (!m->x || !m->y || !m->zn || !m->tri || !m->area || !m->zb || !m->cell_edge || !m->rho || !he) {
+        seterr(err, elen, "out of memory"); goto fail;
+    }
+    for (int64_t v = 0; v < nv; v++) {
+        m->x[v] = xyz[3 * v]; m->y[v] = xyz[3 * v + 1]; m->zn[v] = xyz[3 * v + 2];
+        if (!isfinite(m->x[v]) || !isfinite(m->y[v]) || !isfinite(m->zn[v])) {
+            seterr(err, elen, "non-finite node coordinate"); goto fail;
+        }
+    }
+    for (int64_t i = 0; i < nc; i++) {
+        int32_t a = tri[3 * i], b = tri[3 * i + 1], c = tri[3 * i + 2];
+        if (a < 0 || b < 0 || c < 0 || a >= nv || b >= nv || c >= nv || a == b || b == c || a == c) {
+            seterr(err, elen, "bad triangle vertex index"); goto fail;
+        }
+        double cross = (m->x[b] - m->x[a]) * (m->y[c] - m->y[a]) - (m->y[b] - m->y[a]) * (m->x[c] - m->x[a]);
+        if (cross < 0) { int32_t t = b; b = c; c = t; cross = -cross; }
+        if (!(cross > 0)) { seterr(err, elen, "degenerate triangle"); goto fail; }
+        m->tri[3 * i] = a; m->tri[3 * i + 1] = b; m->tri[3 * i + 2] = c;
+        m->area[i] = 0.5 * cross;
+        m->zb[i] = (m->zn[a] + m->zn[b] + m->zn[c]) / 3.0;
+        for (int k = 0; k < 3; k++) {
+            int32_t p = m->tri[3 * i + k], q = m->tri[3 * i + (k + 1) % 3];
+            he[3 * i + k].a = p < q ? p : q;
+            he[3 * i + k].b = p < q ? q : p;
+            he[3 * i + k].cell = (int32_t)i;
+            he[3 * i + k].k = k;
+        }
+    }
+    qsort(he, (size_t)(3 * nc), sizeof(half_edge), cmp_half);
+    /* count edges */
+    int64_t ne = 0, nb = 0;
+    for (int64_t h = 0; h < 3 * nc;) {
+        int64_t g = h + 1;
+        while (g < 3 * nc && he[g].a == he[h].a && he[g].b == he[h].b) g++;
+        if (g - h > 2) { seterr(err, elen, "non-conforming edge shared by 3+ triangles"); goto fail; }
+        if (g - h == 1) nb++;
+        ne++;
+        h = g;
+    }
+    m->ne = ne;
+    m->nb = nb;
+    m->eL = malloc(sizeof(int32_t) * ne); m->eR = malloc(sizeof(int32_t) * ne);
+    m->ekL = malloc(sizeof(int32_t) * ne); m->ekR = malloc(sizeof(int32_t) * ne);
+    m->etag = malloc(sizeof(int32_t) * ne);
+    m->enx = malloc(sizeof(double) * ne); m->eny = malloc(sizeof(double) * ne);
+    m->elen = malloc(sizeof(double) * ne);
+    if (!m->eL || !m->eR || !m->ekL || !m->ekR || !m->etag || !m->enx || !m->eny || !m->elen) {
+        seterr(err, elen, "out of memory"); goto fail;
+    }
+    sk = malloc(sizeof(seg_key) * (ns > 0 ? ns : 1));
+    if (!sk) { seterr(err, elen, "out of memory"); goto fail; }
+    for (int64_t s = 0; s < ns; s++) {
+        int32_t p = seg[2 * s], q = seg[2 * s + 1];
+        if (p < 0 || q < 0 || p >= nv || q >= nv || p == q) { seterr(err, elen, "bad boundary segment"); goto fail; }
+        sk[s].a = p < q ? p : q; sk[s].b = p < q ? q : p; sk[s].tag = tag[s];
+    }
+    qsort(sk, (size_t)ns, sizeof(seg_key), cmp_seg);
+    int64_t matched = 0;
+    int64_t e = 0;
+    for (int64_t h = 0; h < 3 * nc; e++) {
+        int64_t g = h + 1;
+        while (g < 3 * nc && he[g].a == he[h].a && he[g].b == he[h].b) g++;
+        /* he[] is sorted by cell within a key, so he[h] has the smaller cell */
+        int32_t L = he[h].cell, kL = he[h].k;
+        m->eL[e] = L; m->ekL[e] = kL;
+        m->cell_edge[3 * L + kL] = (int32_t)e;
+        int32_t p = m->tri[3 * L + kL], q = m->tri[3 * L + (kL + 1) % 3];
+        double dx = m->x[q] - m->x[p], dy = m->y[q] - m->y[p];
+        double l = sqrt(dx * dx + dy * dy);
+        m->elen[e] = l;
+        m->enx[e] = dy / l;   /* outward of a counter-clockwise cell */
+        m->eny[e] = -dx / l;
+        m->etag[e] = -1;
+        if (g - h == 2) {
+            int32_t R = he[h + 1].cell, kR = he[h + 1].k;
+            int32_t pR = m->tri[3 * R + kR];
+            if (pR != q) { seterr(err, elen, "inconsistent orientation (overlapping triangles)"); goto fail; }
+            m->eR[e] = R; m->ekR[e] = kR;
+            m->cell_edge[3 * R + kR] = (int32_t)e;
+        } else {
+            m->eR[e] = -1; m->ekR[e] = -1;
+            seg_key key = {he[h].a, he[h].b, 0};
+            seg_key *f = ns > 0 ? bsearch(&key, sk, (size_t)ns, sizeof(seg_key), cmp_seg) : NULL;
+            if (f) { m->etag[e] = f->tag; matched++; }
+        }
+        h = g;
+    }
+    if (matched != ns) { seterr(err, elen, "boundary segment is not a boundary edge of the mesh"); goto fail; }
+    /* rho_ij: twice the distance from the centroid of i to edge j
+     * (eq. CFL_condition); the centroid is at a third of the height, so
+     * rho = 2 * (2|Omega|/l) / 3. */
+    for (int64_t i = 0; i < nc; i++)
+        for (int k = 0; k < 3; k++) {
+            double l = m->elen[m->cell_edge[3 * i + k]];
+            m->rho[3 * i + k] = 4.0 * m->area[i] / (3.0 * l);
+        }
+    free(he);
+    free(sk);
+    return m;
+fail:
+    free(he);
+    free(sk);
+    om_mesh_free(m);
+    return NULL;
+}
+
+int64_t om_mesh_n_edges(const om_mesh *m) { return m->ne; }
+int64_t om_mesh_n_boundary_edges(const om_mesh *m) { return m->nb; }
+
+void om_mesh_geometry(const om_mesh *m, double *area, double *zb, double *rho3, double *nx3,
+                      double *ny3, double *len3, int32_t *nbr3) {
+    for (int64_t i = 0; i < m->nc; i++) {
+        if (area) area[i] = m->area[i];
+        if (zb) zb[i] = m->zb[i];
+        for (int k = 0; k < 3; k++) {
+            int32_t e = m->cell_edge[3 * i + k];
+            double s = (m->eL[e] == i) ? 1.0 : -1.0;
+            if (rho3) rho3[3 * i + k] = m->rho[3 * i + k];
+            if (nx3) nx3[3 * i + k] = s * m->enx[e];
+            if (ny3) ny3[3 * i + k] = s * m->eny[e];
+            if (len3) len3[3 * i + k] = m->elen[e];
+            if (nbr3) nbr3[3 * i + k] = (m->eL[e] == i) ? m->eR[e] : m->eL[e];
+        }
+    }
+}
+
+/* -------------------------------------------------------------- simulation */
+void om_sim_free(om_sim *s) {
+    if (!s) return;
+    for (int b = 0; b < s->nbc; b++) { free(s->bc[b].t); free(s->bc[b].Q); }
+    free(s->bc); free(s->ebc); free(s->H); free(s->qx); free(s->qy); free(s->gn2); free(s->cont);
+    free(s);
+}
+
+/* Initial conditions (section "Initial conditions"): region-defined surface
+ * elevation H or depth h and discharges per cell, or dry.  Reading: a
+ * surface below the cell bed means a dry cell (H = z). */
+om_sim *om_sim_new(const om_mesh *m, double g, double cfl, double h_min, double dt_max,
+                   const double *H0, const double *h0, const double *qx0, const double *qy0,
+                   const double *manning, int32_t nbc, const int32_t *bc_tag, const int32_t *bc_kind,
+                   const double *bc_slope, const int32_t *bc_npts, const double *bc_t,
+                   const double *bc_Q, double t0, char *err, int elen) {
+    om_sim *s = (om_sim *)calloc(1, sizeof(om_sim));
+    if (!s) { seterr(err, elen, "out of memory"); return NULL; }
+    int64_t nc = m->nc;
+    s->m = m;
+    s->g = g; s->cfl = cfl; s->h_min = h_min; s->dt_max = dt_max; s->t = t0;
+    if (!(g > 0) || !(cfl > 0 && cfl <= 1) || !(h_min > 0) || !(dt_max > 0) || !isfinite(t0)) {
+        seterr(err, elen, "bad parameters"); goto fail;
+    }
+    s->H = malloc(sizeof(double) * nc); s->qx = malloc(sizeof(double) * nc);
+    s->qy = malloc(sizeof(double) * nc); s->gn2 = malloc(sizeof(double) * nc);
+    s->cont = malloc(sizeof(double) * 9 * nc);
+    s->ebc = malloc(sizeof(int32_t) * m->ne);
+    s->bc = calloc((size_t)(nbc > 0 ? nbc : 1), sizeof(om_bc));
+    if (!s->H || !s->qx || !s->qy || !s->gn2 || !s->cont || !s->ebc || !s->bc) {
+        seterr(err, elen, "out of memory"); goto fail;
+    }
+    for (int64_t i = 0; i < nc; i++) {
+        double H;
+        if (H0) {
+            H = H0[i] > m->zb[i] ? H0[i] : m->zb[i];
+        } else {
+            double h = h0 ? h0[i] : 0.0;
+            if (!(h >= 0)) { seterr(err, elen, "negative or non-finite initial depth"); goto fail; }
+            H = m->zb[i] + h;
+        }
+        double n = manning ? manning[i] : 0.0;
+        double qx = qx0 ? qx0[i] : 0.0, qy = qy0 ? qy0[i] : 0.0;
+        if (!isfinite(H) || !isfinite(qx) || !isfinite(qy) || !(n >= 0) || !isfinite(n)) {
+            seterr(err, elen, "non-finite initial state or negative Manning n"); goto fail;
+        }
+        s->H[i] = H; s->qx[i] = qx; s->qy[i] = qy;
+        s->gn2[i] = g * n * n;
+    }
+    s->nbc = nbc;
+    int64_t off = 0;
+    for (int b = 0; b < nbc; b++) {
+        om_bc *B = &s->bc[b];
+        B->tag = bc_tag[b]; B->kind = bc_kind[b]; B->slope = bc_slope ? bc_slope[b] : 0.0;
+        B->npts = bc_npts ? bc_npts[b] : 0;
+        if (B->kind < 0 || B->kind > 2) { seterr(err, elen, "unknown boundary kind"); goto fail; }
+        if (B->kind == OM_INFLOW_UNIFORM) {
+            if (B->npts < 1 || !(B->slope > 0)) { seterr(err, elen, "inflow needs a hydrograph and a positive slope"); goto fail; }
+            B->t = malloc(sizeof(double) * B->npts); B->Q = malloc(sizeof(double) * B->npts);
+            if (!B->t || !B->Q) { seterr(err, elen, "out of memory"); goto fail; }
+            for (int k = 0; k < B->npts; k++) {
+                B->t[k] = bc_t[off + k]; B->Q[k] = bc_Q[off + k];
+                if (k > 0 && !(B->t[k] > B->t[k - 1])) { seterr(err, elen, "hydrograph times must increase"); goto fail; }
+            }
+        }
+        off += B->npts;
+    }
+    for (int64_t e = 0; e < m->ne; e++) {
+        s->ebc[e] = -1;
+        if (m->eR[e] >= 0 || m->etag[e] < 0) continue;
+        for (int b = 0; b < nbc; b++)
+            if (s->bc[b].tag == m->etag[e] && s->bc[b].kind != OM_WALL) { s->ebc[e] = b; break; }
+        if (s->ebc[e] >= 0) {
+            om_bc *B = &s->bc[s->ebc[e]];
+            B->length += m->elen[e];
+            if (B->kind == OM_INFLOW_UNIFORM && !(s->gn2[m->eL[e]] > 0)) {
+                seterr(err, elen, "inflow edge next to a cell with Manning n = 0"); goto fail;
+            }
+        }
+    }
+    return s;
+fail:
+    om_sim_free(s);
+    return NULL;
+}
+
+/* Hydrograph Q(t): linear interpolation, constant beyond the ends.
+ * Reading: the boundary is evaluated at the old time level t^n. */
+static double hydrograph(const om_bc *B, double t) {
+    if (t <= B->t[0]) return B->Q[0];
+    if (t >= B->t[B->npts - 1]) return B->Q[B->npts - 1];
+    int k = 0;
+    while (B->t[k + 1] < t) k++;
+    double w = (t - B->t[k]) / (B->t[k + 1] - B->t[k]);
+    return B->Q[k] + w * (B->Q[k + 1] - B->Q[k]);
+}
+
+/* Inflow "uniform(discharge, slope)" (section "Hydrodynamic BCs"): the given
+ * discharge is spread over the boundary length; reading: the ghost carries
+ * the Manning normal depth for that unit discharge, q = h^{5/3} sqrt(S) / n,
+ * flowing into the domain.  Returns 0 when Q <= 0 (edge acts as a wall). */
+static int inflow_ghost(const om_sim *s, const om_bc *B, int32_t cell, double t, double *hg, double *ung) {
+    double Q = hydrograph(B, t);
+    if (!(Q > 0)) return 0;
+    double q = Q / B->length;
+    double n = sqrt(s->gn2[cell] / s->g);
+    double h = pow(n * q / sqrt(B->slope), 0.6);
+    *hg = h;
+    *ung = -q / h;   /* the normal points out of the domain */
+    return 1;
+}
+
+/* HLLC flux in the edge frame (Toro 1994; Toro 2001 ch. 10), for
+ * reconstructed depths hL, hR >= 0, normal and tangential velocities.
+ * Wave speeds: two-rarefaction estimates with the dry-bed forms; readings:
+ * c_s is clamped at 0; ties at S = 0 resolve as listed below; identical
+ * states return the physical flux and two dry sides return zero. */
+void om_hllc(double hL, double unL, double utL, double hR, double unR, double utR, double g, double F[3]) {
+    if (hL <= 0.0 && hR <= 0.0) { F[0] = 0.0; F[1] = 0.0; F[2] = 0.0; return; }
+    if (hL == hR && unL == unR && utL == utR) {
+        F[0] = hL * unL;
+        F[1] = hL * unL * unL + 0.5 * g * hL * hL;
+        F[2] = hL * unL * utL;
+        return;
+    }
+    double cL = sqrt(g * hL), cR = sqrt(g * hR);
+    double SL, SR;
+    if (hL <= 0.0) {
+        SL = unR - 2.0 * cR;
+        SR = unR + cR;
+    } else if (hR <= 0.0) {
+        SL = unL - cL;
+        SR = unL + 2.0 * cL;
+    } else {
+        double a = 0.5 * (cL + cR) + 0.25 * (unL - unR);
+        double us = 0.5 * (unL + unR) + cL - cR;
+        double cs = a > 0.0 ? a : 0.0;
+        SL = fmin(unL - cL, us - cs);
+        SR = fmax(unR + cR, us + cs);
+    }
+    double Ss = (SL * hR * (unR - SR) - SR * hL * (unL - SL)) / (hR * (unR - SR) - hL * (unL - SL));
+    double FL[3] = {hL * unL, hL * unL * unL + 0.5 * g * hL * hL, hL * unL * utL};
+    double FR[3] = {hR * unR, hR * unR * unR + 0.5 * g * hR * hR, hR * unR * utR};
+    if (0.0 <= SL) {
+        F[0] = FL[0]; F[1] = FL[1]; F[2] = FL[2];
+    } else if (SR <= 0.0) {
+        F[0] = FR[0]; F[1] = FR[1]; F[2] = FR[2];
+    } else if (0.0 <= Ss) {
+        double f = hL * (SL - unL) / (SL - Ss);
+        F[0] = FL[0] + SL * (f - hL);
+        F[1] = FL[1] + SL * (f * Ss - hL * unL);
+        F[2] = FL[2] + SL * (f * utL - hL * utL);
+    } else {
+        double f = hR * (SR - unR) / (SR - Ss);
+        F[0] = FR[0] + SR * (f - hR);
+        F[1] = FR[1] + SR * (f * Ss - hR * unR);
+        F[2] = FR[2] + SR * (f * utR - hR * utR);
+    }
+}
+
+/* Friction split (eq. friction_closure with the Manning closure): the ODE
+ * dq/dt = -g n^2 |q| q / h^{7/3} with h frozen has the exact one-step
+ * solution q / (1 + dt g n^2 |q| / h^{7/3}).  Reading: this is the
+ * semi-implicit integrator; thin films (h <= h_min) lose their discharge.
+ * Returns the factor applied to q. */
+double om_friction(double qabs, double h, double gn2, double dt, double h_min) {
+    if (!(h > h_min)) return 0.0;
+    return 1.0 / (1.0 + dt * gn2 * qabs / pow(h, 7.0 / 3.0));
+}
+
+static void cell_velocity(const om_sim *s, int32_t i, double *h, double *u, double *v) {
+    *h = s->H[i] - s->m->zb[i];
+    if (*h > s->h_min) { *u = s->qx[i] / *h; *v = s->qy[i] / *h; }
+    else { *u = 0.0; *v = 0.0; }
+}
+
+/* eq. CFL_condition: dt = CFL min_i min_j rho_ij / (|u.n_ij| + sqrt(g h_i))
+ * over wet cells; readings: inflow ghosts count with their own state on
+ * their edge, dt is capped by the parameter dt_max and by t_end - t. */
+double om_next_dt(const om_sim *s, double t_end) {
+    const om_mesh *m = s->m;
+    double best = INFINITY;
+    for (int64_t i = 0; i < m->nc; i++) {
+        double h, u, v;
+        cell_velocity(s, (int32_t)i, &h, &u, &v);
+        if (!(h > s->h_min)) continue;
+        double c = sqrt(s->g * h);
+        for (int k = 0; k < 3; k++) {
+            int32_t e = m->cell_edge[3 * i + k];
+            double sg = (m->eL[e] == i) ? 1.0 : -1.0;
+            double un = u * (sg * m->enx[e]) + v * (sg * m->eny[e]);
+            double lam = fabs(un) + c;
+            double r = m->rho[3 * i + k] / lam;
+            if (r < best) best = r;
+        }
+    }
+    for (int64_t e = 0; e < m->ne; e++) {
+        if (s->ebc[e] < 0) continue;
+        const om_bc *B = &s->bc[s->ebc[e]];
+        if (B->kind != OM_INFLOW_UNIFORM) continue;
+        double hg, ung;
+        if (!inflow_ghost(s, B, m->eL[e], s->t, &hg, &ung)) continue;
+        double lam = fabs(ung) + sqrt(s->g * hg);
+        double r = m->rho[3 * m->eL[e] + m->ekL[e]] / lam;
+        if (r < best) best = r;
+    }
+    double dt = s->cfl * best;
+    if (s->dt_max < dt) dt = s->dt_max;
+    if (t_end - s->t < dt) dt = t_end - s->t;
+    return dt;
+}
+
+int om_step(om_sim *s, double t_end, double *dt_taken) {
+    const om_mesh *m = s->m;
+    const double g = s->g;
+    double dt = om_next_dt(s, t_end);
+    if (dt_taken) *dt_taken = dt;
+    if (!(dt > 0.0) || !isfinite(dt)) return -7;
+    memset(s->cont, 0, sizeof(double) * 9 * (size_t)m->nc);
+    double bstep = 0.0, bstepc = 0.0;
+    for (int64_t e = 0; e < m->ne; e++) {
+        int32_t L = m->eL[e], R = m->eR[e];
+        double nx = m->enx[e], ny = m->eny[e], l = m->elen[e];
+        double hL, uL, vL, hR, uR, vR;
+        cell_velocity(s, L, &hL, &uL, &vL);
+        double HL = s->H[L], zL = m->zb[L];
+        double unL = uL * nx + vL * ny, utL = -uL * ny + vL * nx;
+        double HR, zR, unR, utR;
+        int wall = 0, open = 0;
+        if (R >= 0) {
+            cell_velocity(s, R, &hR, &uR, &vR);
+            HR = s->H[R]; zR = m->zb[R];
+            unR = uR * nx + vR * ny; utR = -uR * ny + vR * nx;
+        } else {
+            int b = s->ebc[e];
+            const om_bc *B = b >= 0 ? &s->bc[b] : NULL;
+            double hg, ung;
+            zR = zL;
+            if (B && B->kind == OM_OUTFLOW_ZEROGRAD) {
+                /* transmissive: the ghost repeats the interior state */
+                HR = HL; unR = unL; utR = utL; open = 1;
+            } else if (B && B->kind == OM_INFLOW_UNIFORM && inflow_ghost(s, B, L, s->t, &hg, &ung)) {
+                HR = zL + hg; unR = ung; utR = 0.0; open = 1;
+            } else {
+                /* reflective wall: mirror the normal velocity */
+                HR = HL; unR = -unL; utR = utL; wall = 1;
+            }
+        }
+        /* hydrostatic reconstruction of modified states at the edge.
+         * Reading: a reconstructed depth under OM_H_DRY counts as dry, so the
+         * contact speed never divides two underflowed products; a dry side
+         * never loses mass, so this keeps depths non-negative. */
+        double zs = zL > zR ? zL : zR;
+        double hLs = HL - zs; if (hLs < OM_H_DRY) hLs = 0.0;
+        double hRs = HR - zs; if (hRs < OM_H_DRY) hRs = 0.0;
+        double F[3];
+        om_hllc(hLs, unL, utL, hRs, unR, utR, g, F);
+        if (wall) F[0] = 0.0;   /* impermeable: no mass crosses a wall */
+        /* fluctuations: the flux minus each side's own reconstructed pressure
+         * (the bed-slope source in well-balanced form, using sum_j l n = 0) */
+        double PL = 0.5 * g * hLs * hLs, PR = 0.5 * g * hRs * hRs;
+        double dLn = F[1] - PL, dRn = F[1] - PR;
+        double cL0 = l * F[0];
+        double cLx = l * (dLn * nx - F[2] * ny);
+        double cLy = l * (dLn * ny + F[2] * nx);
+        int kL = m->ekL[e];
+        s->cont[9 * L + 3 * kL + 0] = cL0;
+        s->cont[9 * L + 3 * kL + 1] = cLx;
+        s->cont[9 * L + 3 * kL + 2] = cLy;
+        if (R >= 0) {
+            int kR = m->ekR[e];
+            s->cont[9 * R + 3 * kR + 0] = -(l * F[0]);
+            s->cont[9 * R + 3 * kR + 1] = -(l * (dRn * nx - F[2] * ny));
+            s->cont[9 * R + 3 * kR + 2] = -(l * (dRn * ny + F[2] * nx));
+        } else if (open) {
+            neumaier(&bstep, &bstepc, dt * cL0);
+        }
+    }
+    for (int64_t i = 0; i < m->nc; i++) {
+        const double *c = &s->cont[9 * i];
+        double Rh = c[0] + c[3] + c[6];
+        double Rx = c[1] + c[4] + c[7];
+        double Ry = c[2] + c[5] + c[8];
+        double w = dt * (1.0 / m->area[i]);
+        double H = s->H[i] - w * Rh;
+        double qx = s->qx[i] - w * Rx;
+        double qy = s->qy[i] - w * Ry;
+        double h = H - m->zb[i];
+        double f = om_friction(sqrt(qx * qx + qy * qy), h, s->gn2[i], dt, s->h_min);
+        qx = qx * f;
+        qy = qy * f;
+        if (h < 0.0) {
+            /* positivity: the scheme's CFL does not bound the outflow of a
+             * cell draining through several edges; clip and account for it */
+            double add = -h * m->area[i];
+            neumaier(&s->clip, &s->clipc, add);
+            H = m->zb[i];
+            qx = 0.0; qy = 0.0;
+        }
+        if (!isfinite(H) || !isfinite(qx) || !isfinite(qy)) return -4;
+        s->H[i] = H; s->qx[i] = qx; s->qy[i] = qy;
+    }
+    neumaier(&s->bsum, &s->bcomp, bstep + bstepc);
+    s->t += dt;
+    s->steps++;
+    return 0;
+}
+
+int om_run_until(om_sim *s, double t_end, int64_t max_steps, int64_t *n_steps) {
+    int64_t n = 0;
+    int rc = 0;
+    while (s->t < t_end && (max_steps <= 0 || n < max_steps)) {
+        double dt;
+        rc = om_step(s, t_end, &dt);
+        if (rc) break;
+        n++;
+    }
+    if (n_steps) *n_steps = n;
+    return rc;
+}
+
+void om_get_state(const om_sim *s, double *H, double *qx, double *qy, double *t) {
+    int64_t nc = s->m->nc;
+    if (H) memcpy(H, s->H, sizeof(double) * nc);
+    if (qx) memcpy(qx, s->qx, sizeof(double) * nc);
+    if (qy) memcpy(qy, s->qy, sizeof(double) * nc);
+    if (t) *t = s->t;
+}
+
+void om_set_state(om_sim *s, const double *H, const double *qx, const double *qy, double t) {
+    int64_t nc = s->m->nc;
+    memcpy(s->H, H, sizeof(double) * nc);
+    memcpy(s->qx, qx, sizeof(double) * nc);
+    memcpy(s->qy, qy, sizeof(double) * nc);
+    s->t = t;
+}
+
+/* Diagnostics: volume M = sum (H - z)|Omega| (Neumaier), the integral of
+ * the mass flux leaving through open boundaries, and the clipped volume.
+ * The scheme is conservative: M(t) = M(0) - bnd_flux + clipped. */
+void om_diag(const om_sim *s, double *mass, double *bnd, double *clipped, int64_t *steps) {
+    double sum = 0.0, comp = 0.0;
+    for (int64_t i = 0; i < s->m->nc; i++)
+        neumaier(&sum, &comp, (s->H[i] - s->m->zb[i]) * s->m->area[i]);
+    if (mass) *mass = sum + comp;
+    if (bnd) *bnd = s->bsum + s->bcomp;
+    if (clipped) *clipped = s->clip + s->clipc;
+    if (steps) *steps = s->steps;
+}

@@ -1,0 +1,53 @@
+/*
+ * FP64 CPU oracle for the explicit first-order finite-volume shallow-water
+ * step on a conforming triangulation.  TEST INFRASTRUCTURE ONLY: nothing on
+ * the product path may include, link or call this.  It exists so that the
+ * GPU library can be checked against a plain, slow, obviously correct
+ * implementation written from the paper.
+ *
+ * The oracle loops over EDGES (each edge flux computed once), stores the
+ * three per-edge contributions of every cell in its local edge order and
+ * sums them in that order.  Compiled with -ffp-contract=off.
+ *
+ * Status codes: 0 ok, -1 invalid input, -2 out of memory, -4 non-finite
+ * state, -7 no finite time step.
+ */
+#ifndef SWE_ORACLE_H
+#define SWE_ORACLE_H
+#include <stdint.h>
+
+typedef struct om_mesh om_mesh;
+typedef struct om_sim om_sim;
+
+/* boundary kinds */
+enum { OM_WALL = 0, OM_INFLOW_UNIFORM = 1, OM_OUTFLOW_ZEROGRAD = 2 };
+
+om_mesh *om_mesh_new(const double *node_xyz, int64_t n_nodes, const int32_t *tri, int64_t n_tri,
+                     const int32_t *bnd_seg, const int32_t *bnd_tag, int64_t n_seg,
+                     char *err, int err_len);
+void om_mesh_free(om_mesh *m);
+int64_t om_mesh_n_edges(const om_mesh *m);
+int64_t om_mesh_n_boundary_edges(const om_mesh *m);
+/* per-cell area, bed, and per cell-local edge: rho, outward unit normal, length */
+void om_mesh_geometry(const om_mesh *m, double *area, double *zb, double *rho3,
+                      double *nx3, double *ny3, double *len3, int32_t *nbr3);
+
+om_sim *om_sim_new(const om_mesh *m, double g, double cfl, double h_min, double dt_max,
+                   const double *H0, const double *h0, const double *qx0, const double *qy0,
+                   const double *manning, int32_t n_bc, const int32_t *bc_tag,
+                   const int32_t *bc_kind, const double *bc_slope, const int32_t *bc_npts,
+                   const double *bc_t, const double *bc_Q, double t0, char *err, int err_len);
+void om_sim_free(om_sim *s);
+
+double om_next_dt(const om_sim *s, double t_end);
+int om_step(om_sim *s, double t_end, double *dt_taken);
+int om_run_until(om_sim *s, double t_end, int64_t max_steps, int64_t *n_steps);
+void om_get_state(const om_sim *s, double *H, double *qx, double *qy, double *t);
+void om_set_state(om_sim *s, const double *H, const double *qx, const double *qy, double t);
+void om_diag(const om_sim *s, double *mass, double *bnd_flux, double *clipped, int64_t *steps);
+
+/* single-edge pieces, exposed for the pin tests */
+void om_hllc(double hL, double unL, double utL, double hR, double unR, double utR, double g,
+             double F[3]);
+double om_friction(double q_abs_scale, double h, double gn2, double dt, double h_min);
+#endif

@@ -1,0 +1,200 @@
+/*
+ * swe.h -- C ABI of the MI355X (gfx950) shallow-water library.
+ *
+ * The library advances the depth-averaged shallow-water equations in
+ * surface-elevation form (paper: section "Mathematical formulation",
+ * subsection Hydrodynamics, eq. Hyd_gov_equations) with the explicit,
+ * first-order, cell-centred finite-volume update of eq.
+ * hydrodynamicupdateformula on a conforming triangulation (section "Domain
+ * discretization").  One step does, for every cell: hydrostatic
+ * reconstruction of modified states with wet/dry handling, an HLLC edge flux
+ * (section "Numerical solution", Hydrodynamics paragraph on HLLC), the
+ * conservative update, the Manning friction split (eq. friction_closure and
+ * the Manning row of Table friction_closure), and the next global CFL step
+ * (eq. CFL_condition).  All of it runs in hand-written HIP kernels; the host
+ * code only prepares the mesh, moves memory and launches.
+ *
+ * Conventions
+ *  - Every pointer argument named *_host / plain arrays is HOST memory and is
+ *    copied; the caller keeps ownership.  Device memory is obtained through
+ *    the swe_device callbacks (or hipMalloc when none are given) and is owned
+ *    by the handle until its *_destroy.
+ *  - Cell arrays are in the caller's ORIGINAL cell order on input and output;
+ *    the library renumbers cells internally (Hilbert order of centroids).
+ *  - Status codes: SWE_OK (0) or a negative SWE_E* value; swe_last_error()
+ *    returns a thread-local message for the last failure on this thread.
+ *  - A handle may be used by one host thread at a time.  A mesh must outlive
+ *    the states created on it; a state must outlive the batches holding it.
+ */
+#ifndef SWE_H
+#define SWE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct swe_mesh swe_mesh;
+typedef struct swe_state swe_state;
+typedef struct swe_batch swe_batch;
+typedef int32_t swe_status;
+
+enum {
+    SWE_OK = 0,
+    SWE_EINVAL = -1,     /* invalid argument or mesh */
+    SWE_ENOMEM = -2,     /* allocation failed */
+    SWE_EDEVICE = -3,    /* a HIP call failed */
+    SWE_ENONFINITE = -4, /* the state became non-finite */
+    SWE_ENEGDEPTH = -5,  /* negative depth under SWE_NEG_ERROR */
+    SWE_EBUDGET = -6,    /* batch footprint budget exceeded */
+    SWE_ENODT = -7       /* no finite positive time step (dry domain, no cap) */
+};
+
+/* Device memory and stream bridge.  alloc(bytes, ctx) returns device memory
+ * (NULL on failure) aligned to at least 256 bytes; free(ptr, ctx) releases it.
+ * hip_stream is a hipStream_t on which every kernel and copy of the handle is
+ * issued (NULL = the default stream).  A NULL swe_device, or NULL alloc/free,
+ * means hipMalloc/hipFree. */
+typedef struct {
+    void *(*alloc)(size_t bytes, void *ctx);
+    void (*free)(void *ptr, void *ctx);
+    void *ctx;
+    void *hip_stream;
+} swe_device;
+
+/* Boundary kinds (section "Boundary conditions", Hydrodynamic BCs; the
+ * supplementary feature table lists wall, inflow uniform(discharge, slope)
+ * and outflow zero_gradient among the standard types).  Boundary edges whose
+ * tag has no entry, and untagged boundary edges, are walls (walls are the
+ * default on every external boundary). */
+enum { SWE_BC_WALL = 0, SWE_BC_INFLOW_UNIFORM = 1, SWE_BC_OUTFLOW_ZEROGRAD = 2 };
+
+typedef struct {
+    int32_t tag;      /* boundary tag given to swe_mesh_create */
+    int32_t kind;     /* SWE_BC_* */
+    double slope;     /* inflow: energy slope S > 0 of uniform(Q, S) */
+    const double *t;  /* inflow hydrograph times [s], strictly increasing (host) */
+    const double *Q;  /* inflow hydrograph discharge [m^3/s] (host) */
+    int32_t n_pts;    /* number of hydrograph points (>= 1 for inflow) */
+} swe_bc;
+
+enum { SWE_FP64 = 0, SWE_FP32 = 1 };        /* precision (double is the paper's default) */
+enum { SWE_NEG_CLIP = 0, SWE_NEG_ERROR = 1 }; /* negative-depth policy */
+
+/* Parameters (supplementary feature table, hydrodynamics parameters: CFL,
+ * minimum water depth, upper limit of the time step; eq. CFL_condition for
+ * the CFL range (0, 1] and its default 0.9). */
+typedef struct {
+    double g;               /* gravity [m/s^2], default 9.81 */
+    double cfl;             /* CFL number in (0, 1], default 0.9 */
+    double h_min;           /* minimum water depth [m] > 0, default 1e-4 */
+    double dt_max;          /* upper limit of the time step [s] > 0, default +inf */
+    int32_t precision;      /* SWE_FP64 (default) or SWE_FP32 */
+    int32_t neg_depth_policy; /* SWE_NEG_CLIP (default) or SWE_NEG_ERROR */
+    int32_t block_size;     /* threads per block: 64..1024, multiple of 64; 0 = tuned/default */
+    int32_t cells_per_thread; /* 1 or 2; 0 = tuned/default */
+    int32_t steps_per_graph;  /* steps captured per hipGraph in swe_run_until; 0 = default (32) */
+    int32_t renumber;       /* 1 = Hilbert order of cell centroids (default), 0 = input order */
+} swe_params;
+
+/* Fills *p with the defaults listed above. */
+void swe_params_default(swe_params *p);
+
+/* Builds a mesh from node coordinates and elevations (node_xyz: n_nodes x 3
+ * doubles x, y, z, host) and triangles (tri: n_tri x 3 node ids, host, any
+ * winding -- fixed to counter-clockwise).  bnd_seg (n_seg x 2 node ids) with
+ * bnd_tag (n_seg ints) tags boundary edges; every segment must be a boundary
+ * edge of the mesh.  The cell bed elevation is the mean of its three node
+ * elevations.  Rejects non-finite coordinates, degenerate triangles, edges
+ * shared by three or more triangles and inconsistently oriented neighbours
+ * (SWE_EINVAL).  params may be NULL (defaults); only params->renumber is read.
+ * dev may be NULL.  On success *out owns the mesh. */
+swe_status swe_mesh_create(const double *node_xyz, int64_t n_nodes, const int32_t *tri, int64_t n_tri,
+                           const int32_t *bnd_seg, const int32_t *bnd_tag, int64_t n_seg,
+                           const swe_params *params, const swe_device *dev, swe_mesh **out);
+void swe_mesh_destroy(swe_mesh *m);
+/* counts: cells, edges, boundary edges (any pointer may be NULL) */
+void swe_mesh_info(const swe_mesh *m, int64_t *n_cells, int64_t *n_edges, int64_t *n_boundary_edges);
+/* device bytes a state of this precision needs (mesh geometry not included) */
+int64_t swe_state_footprint(const swe_mesh *m, int32_t precision);
+
+/* Creates a device-resident state (section "Initial and boundary
+ * conditions": region-defined initial values or dry).  Exactly one of
+ * H0 (surface elevation; values below the cell bed mean a dry cell) and h0
+ * (depth >= 0) may be non-NULL; both NULL means dry.  qx0, qy0 (discharge per
+ * unit width) may be NULL (zero); manning (n >= 0 per cell) may be NULL
+ * (frictionless).  All arrays are host arrays of n_cells doubles in original
+ * cell order.  bcs[n_bc] maps tags to kinds; inflow edges need n > 0 in
+ * their cell.  t0 is the start time (restart = re-init from a read state).
+ * params may be NULL.  Computes the first time step on the device. */
+swe_status swe_state_init(const swe_mesh *m, const swe_params *params, const double *H0,
+                          const double *h0, const double *qx0, const double *qy0,
+                          const double *manning, const swe_bc *bcs, int32_t n_bc, double t0,
+                          swe_state **out);
+void swe_state_destroy(swe_state *s);
+
+/* One step of eq. hydrodynamicupdateformula with dt = min(dt_max,
+ * CFL * min rho/lambda) (no end-time cap).  Blocks until done; *dt_taken may
+ * be NULL.  Returns SWE_ENODT when no finite step exists, SWE_ENONFINITE /
+ * SWE_ENEGDEPTH when the state broke (the state is then left as computed). */
+swe_status swe_step(swe_state *s, double *dt_taken);
+
+/* Steps until t = t_end (the last step is shortened to land on t_end), with
+ * steps_per_graph steps per hipGraph launch and one 64-byte status read per
+ * launch.  *n_steps (may be NULL) receives the number of steps taken. */
+swe_status swe_run_until(swe_state *s, double t_end, int64_t *n_steps);
+
+/* Issues k steps capped at t_end on the state's stream WITHOUT waiting
+ * (graph launches); swe_sync waits and reports errors.  For timing. */
+swe_status swe_launch_steps(swe_state *s, double t_end, int64_t k);
+swe_status swe_sync(swe_state *s);
+
+/* Copies the state to the host in original cell order as doubles; any
+ * pointer may be NULL.  H surface elevation, h depth, qx, qy discharges,
+ * *t the current time. */
+swe_status swe_state_read(const swe_state *s, double *H, double *h, double *qx, double *qy, double *t);
+
+/* Diagnostics computed on the device: volume sum (H - z)|Omega| (compensated
+ * FP64, fixed order), the time integral of the mass flux leaving through open
+ * boundaries, the volume added by positivity clips, and the step count.
+ * The scheme is conservative: mass(t) = mass(0) - bnd_flux + clipped. */
+swe_status swe_mass(const swe_state *s, double *mass, double *bnd_flux, double *clipped, int64_t *steps);
+
+/* Times k steps for each block size in {64,128,256,512,1024} and cells per
+ * thread in {1,2}, keeps the fastest for this state, and restores the state
+ * exactly as it was.  *block_size / *cells_per_thread (may be NULL) receive
+ * the choice.  Results are bitwise independent of the choice. */
+swe_status swe_autotune(swe_state *s, int32_t k, int32_t *block_size, int32_t *cells_per_thread);
+
+/* ---- batched ensembles (many independent states stepped by one persistent
+ * kernel per step, each with its own dt; paper motivation: ensemble and
+ * calibration runs through batch execution).  All states of a batch share
+ * precision and device. budget_bytes (0 = unlimited) bounds the summed
+ * footprint; swe_batch_add returns SWE_EBUDGET when it would be exceeded. */
+swe_status swe_batch_create(int32_t precision, int64_t budget_bytes, const swe_device *dev, swe_batch **out);
+void swe_batch_destroy(swe_batch *b);
+/* Adds a state with its own end time; *slot receives its id. */
+swe_status swe_batch_add(swe_batch *b, swe_state *s, double t_end, int32_t *slot);
+/* Removes (detaches) a state; the state itself stays valid. */
+swe_status swe_batch_remove(swe_batch *b, int32_t slot);
+/* Runs up to k steps of every unfinished member (one hipGraph of k
+ * persistent launches) and waits.  *n_active (may be NULL) receives how many
+ * members are still short of their end time. */
+swe_status swe_batch_step(swe_batch *b, int32_t k, int32_t *n_active);
+/* Issues the same work without waiting (for overlap and timing). */
+swe_status swe_batch_launch(swe_batch *b, int32_t k);
+/* Per-member status after the last swe_batch_step: done flag (t >= t_end),
+ * error code (0 or SWE_E*), time and steps.  Arrays sized by capacity. */
+swe_status swe_batch_poll(swe_batch *b, int32_t slot, int32_t *done, int32_t *error, double *t, int64_t *steps);
+int64_t swe_batch_footprint(const swe_batch *b);
+
+const char *swe_last_error(void);
+/* Library version string. */
+const char *swe_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

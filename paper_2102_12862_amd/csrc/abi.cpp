@@ -1,0 +1,863 @@
+// C ABI of the shallow-water library (declared in include/swe.h): handles,
+// device layout, hipGraph-captured stepping, diagnostics, autotuning and
+// batched ensembles.  Host code only: every step of the method runs in the
+// kernels of kernels.hip.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <limits>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "meshprep.h"
+#include "swe.h"
+#include "swe_internal.h"
+
+using namespace swe;
+
+static_assert(NBR_FLIP == NBR_FLIP_BIT, "flip bit");
+
+namespace {
+
+thread_local std::string g_err;
+
+swe_status fail(swe_status code, const std::string &msg) {
+    g_err = msg;
+    return code;
+}
+
+#define HIP_TRY(expr)                                                                     \
+    do {                                                                                  \
+        hipError_t _e = (expr);                                                           \
+        if (_e != hipSuccess)                                                             \
+            return fail(SWE_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(_e)); \
+    } while (0)
+
+struct DevMem {
+    swe_device dev{};
+    bool cb = false;
+    void set(const swe_device *d) {
+        if (d) dev = *d;
+        cb = d && d->alloc && d->free;
+    }
+    void *alloc(size_t n) {
+        n = std::max<size_t>(n, 256);
+        if (cb) return dev.alloc(n, dev.ctx);
+        void *p = nullptr;
+        return hipMalloc(&p, n) == hipSuccess ? p : nullptr;
+    }
+    void release(void *p) {
+        if (!p) return;
+        if (cb)
+            dev.free(p, dev.ctx);
+        else
+            (void)hipFree(p);
+    }
+    hipStream_t stream() const { return (hipStream_t)dev.hip_stream; }
+};
+
+struct Geom {
+    void *geo0 = nullptr;
+    int *nbr = nullptr;
+    double *area = nullptr;
+    bool ready = false;
+};
+
+size_t vec4_bytes(int prec) { return prec == SWE_FP32 ? sizeof(float4) : sizeof(double4); }
+
+swe_status check_flags(int flags) {
+    if (flags & FLAG_NONFINITE) return fail(SWE_ENONFINITE, "state became non-finite");
+    if (flags & FLAG_NEGDEPTH) return fail(SWE_ENEGDEPTH, "negative depth under the error policy");
+    if (flags & FLAG_NODT) return fail(SWE_ENODT, "no finite positive time step");
+    return SWE_OK;
+}
+
+bool valid_block(int b) { return b >= 64 && b <= 1024 && b % 64 == 0; }
+
+}  // namespace
+
+struct swe_mesh {
+    DevMem mem;
+    HostMesh H;
+    Geom geom[2];
+    ~swe_mesh() {
+        for (auto &g : geom) {
+            mem.release(g.geo0);
+            mem.release(g.nbr);
+            mem.release(g.area);
+        }
+    }
+    template <typename T> swe_status ensure_geom(int prec) {
+        Geom &g = geom[prec];
+        if (g.ready) return SWE_OK;
+        const int64_t n = H.nc;
+        g.geo0 = mem.alloc((size_t)n * sizeof(V4<T>));
+        g.nbr = (int *)mem.alloc((size_t)n * 3 * sizeof(int));
+        g.area = (double *)mem.alloc((size_t)n * sizeof(double));
+        if (!g.geo0 || !g.nbr || !g.area) return fail(SWE_ENOMEM, "device allocation failed (mesh geometry)");
+        std::vector<V4<T>> g0((size_t)n);
+        std::vector<int> nb((size_t)(3 * n));
+        for (int64_t p = 0; p < n; p++) {
+            g0[p].x = T(H.lx[3 * p]);
+            g0[p].y = T(H.ly[3 * p]);
+            g0[p].z = T(H.lx[3 * p + 1]);
+            g0[p].w = T(H.ly[3 * p + 1]);
+            for (int k = 0; k < 3; k++) nb[(size_t)k * n + p] = H.nbr[3 * p + k];
+        }
+        hipStream_t s = mem.stream();
+        HIP_TRY(hipMemcpyAsync(g.geo0, g0.data(), g0.size() * sizeof(V4<T>), hipMemcpyHostToDevice, s));
+        HIP_TRY(hipMemcpyAsync(g.nbr, nb.data(), nb.size() * sizeof(int), hipMemcpyHostToDevice, s));
+        HIP_TRY(hipMemcpyAsync(g.area, H.area.data(), (size_t)n * sizeof(double), hipMemcpyHostToDevice, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        g.ready = true;
+        return SWE_OK;
+    }
+};
+
+struct swe_state {
+    swe_mesh *m = nullptr;
+    swe_params p{};
+    DevMem mem;
+    int prec = SWE_FP64;
+    void *U0 = nullptr, *U1 = nullptr, *geo1 = nullptr;
+    int *slot_kbc = nullptr;
+    double *slot_acc = nullptr;
+    BCdev *bcs = nullptr;
+    double *hydro = nullptr;
+    Ctrl *ctrl = nullptr;
+    double2 *partials = nullptr;
+    double *mass_out = nullptr;
+    Ctrl *hctrl = nullptr;    // pinned host copy of the control block
+    double *hbuf = nullptr;   // pinned scratch (t_end, mass results)
+    int nslots = 0;
+    int block = 256, cpt = 1, spg = 32;
+    hipStream_t cap = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    int g_k = 0, g_block = 0, g_cpt = 0;
+    Inst<float> inst32{};
+    Inst<double> inst64{};
+
+    ~swe_state() {
+        if (gexec) (void)hipGraphExecDestroy(gexec);
+        if (cap) (void)hipStreamDestroy(cap);
+        for (void *q : {U0, U1, geo1, (void *)slot_kbc, (void *)slot_acc, (void *)bcs, (void *)hydro, (void *)ctrl,
+                        (void *)partials, (void *)mass_out})
+            mem.release(q);
+        if (hctrl) (void)hipHostFree(hctrl);
+        if (hbuf) (void)hipHostFree(hbuf);
+    }
+    hipStream_t stream() const { return mem.stream(); }
+
+    hipError_t launch_one() {
+        return prec == SWE_FP32 ? launch_step<float>(inst32, block, cpt, stream())
+                                : launch_step<double>(inst64, block, cpt, stream());
+    }
+    hipError_t launch_one_on(hipStream_t s) {
+        return prec == SWE_FP32 ? launch_step<float>(inst32, block, cpt, s) : launch_step<double>(inst64, block, cpt, s);
+    }
+    swe_status set_t_end(double t_end) {
+        hbuf[0] = t_end;
+        HIP_TRY(hipMemcpyAsync(&ctrl->t_end, hbuf, sizeof(double), hipMemcpyHostToDevice, stream()));
+        return SWE_OK;
+    }
+    swe_status read_ctrl() {
+        HIP_TRY(hipMemcpyAsync(hctrl, ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, stream()));
+        HIP_TRY(hipStreamSynchronize(stream()));
+        return SWE_OK;
+    }
+    swe_status graph(int k) {
+        if (gexec && g_k == k && g_block == block && g_cpt == cpt) return SWE_OK;
+        if (gexec) {
+            (void)hipGraphExecDestroy(gexec);
+            gexec = nullptr;
+        }
+        if (!cap) HIP_TRY(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+        hipGraph_t gr = nullptr;
+        HIP_TRY(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
+        for (int i = 0; i < k; i++) {
+            hipError_t e = launch_one_on(cap);
+            if (e != hipSuccess) {
+                hipGraph_t dummy = nullptr;
+                (void)hipStreamEndCapture(cap, &dummy);
+                if (dummy) (void)hipGraphDestroy(dummy);
+                return fail(SWE_EDEVICE, std::string("capture: ") + hipGetErrorString(e));
+            }
+        }
+        HIP_TRY(hipStreamEndCapture(cap, &gr));
+        hipError_t e = hipGraphInstantiate(&gexec, gr, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(gr);
+        if (e != hipSuccess) return fail(SWE_EDEVICE, std::string("graph instantiate: ") + hipGetErrorString(e));
+        g_k = k;
+        g_block = block;
+        g_cpt = cpt;
+        return SWE_OK;
+    }
+};
+
+extern "C" {
+
+void swe_params_default(swe_params *p) {
+    if (!p) return;
+    p->g = 9.81;
+    p->cfl = 0.9;
+    p->h_min = 1e-4;
+    p->dt_max = std::numeric_limits<double>::infinity();
+    p->precision = SWE_FP64;
+    p->neg_depth_policy = SWE_NEG_CLIP;
+    p->block_size = 0;
+    p->cells_per_thread = 0;
+    p->steps_per_graph = 0;
+    p->renumber = 1;
+}
+
+const char *swe_last_error(void) { return g_err.c_str(); }
+const char *swe_version(void) { return "swe-gfx950 1.0"; }
+
+swe_status swe_mesh_create(const double *node_xyz, int64_t n_nodes, const int32_t *tri, int64_t n_tri,
+                           const int32_t *bnd_seg, const int32_t *bnd_tag, int64_t n_seg,
+                           const swe_params *params, const swe_device *dev, swe_mesh **out) {
+    if (!out) return fail(SWE_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!node_xyz || !tri || n_nodes <= 0 || n_tri <= 0) return fail(SWE_EINVAL, "empty mesh");
+    if (n_seg < 0 || (n_seg > 0 && (!bnd_seg || !bnd_tag))) return fail(SWE_EINVAL, "bad boundary segments");
+    swe_params P;
+    swe_params_default(&P);
+    if (params) P = *params;
+    std::unique_ptr<swe_mesh> m(new (std::nothrow) swe_mesh());
+    if (!m) return fail(SWE_ENOMEM, "out of host memory");
+    m->mem.set(dev);
+    std::string err;
+    try {
+        if (!prepare_mesh(node_xyz, n_nodes, tri, n_tri, bnd_seg, bnd_tag, n_seg, P.renumber != 0, m->H, err))
+            return fail(SWE_EINVAL, err);
+    } catch (const std::bad_alloc &) {
+        return fail(SWE_ENOMEM, "out of host memory");
+    }
+    *out = m.release();
+    return SWE_OK;
+}
+
+void swe_mesh_destroy(swe_mesh *m) { delete m; }
+
+void swe_mesh_info(const swe_mesh *m, int64_t *n_cells, int64_t *n_edges, int64_t *n_boundary_edges) {
+    if (!m) return;
+    if (n_cells) *n_cells = m->H.nc;
+    if (n_edges) *n_edges = m->H.ne;
+    if (n_boundary_edges) *n_boundary_edges = m->H.nb;
+}
+
+int64_t swe_state_footprint(const swe_mesh *m, int32_t precision) {
+    if (!m) return 0;
+    const int64_t n = m->H.nc, ns = (int64_t)m->H.slot_tag.size();
+    const int64_t v4 = (int64_t)vec4_bytes(precision);
+    const int64_t state = 3 * n * v4 + ns * (4 + 16) + (int64_t)sizeof(Ctrl) + MASS_BLOCKS * 16 + 4096;
+    const int64_t geom = n * (v4 + 12 + 8);
+    return state + geom;
+}
+
+swe_status swe_state_init(const swe_mesh *m, const swe_params *params, const double *H0, const double *h0,
+                          const double *qx0, const double *qy0, const double *manning, const swe_bc *bcs,
+                          int32_t n_bc, double t0, swe_state **out) {
+    if (!out) return fail(SWE_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!m) return fail(SWE_EINVAL, "mesh is NULL");
+    swe_params P;
+    swe_params_default(&P);
+    if (params) P = *params;
+    if (!(P.g > 0) || !std::isfinite(P.g)) return fail(SWE_EINVAL, "g must be positive");
+    if (!(P.cfl > 0 && P.cfl <= 1)) return fail(SWE_EINVAL, "cfl must lie in (0, 1]");
+    if (!(P.h_min > 0) || !std::isfinite(P.h_min)) return fail(SWE_EINVAL, "h_min must be positive");
+    if (!(P.dt_max > 0)) return fail(SWE_EINVAL, "dt_max must be positive");
+    if (P.precision != SWE_FP32 && P.precision != SWE_FP64) return fail(SWE_EINVAL, "unknown precision");
+    if (P.neg_depth_policy != SWE_NEG_CLIP && P.neg_depth_policy != SWE_NEG_ERROR)
+        return fail(SWE_EINVAL, "unknown negative-depth policy");
+    if (P.block_size != 0 && !valid_block(P.block_size)) return fail(SWE_EINVAL, "block_size must be 64..1024, multiple of 64");
+    if (P.cells_per_thread < 0 || P.cells_per_thread > 2) return fail(SWE_EINVAL, "cells_per_thread must be 0, 1 or 2");
+    if (P.steps_per_graph < 0 || P.steps_per_graph > 4096) return fail(SWE_EINVAL, "steps_per_graph out of range");
+    if (H0 && h0) return fail(SWE_EINVAL, "give H0 or h0, not both");
+    if (!std::isfinite(t0)) return fail(SWE_EINVAL, "t0 must be finite");
+    if (n_bc < 0 || n_bc > MAX_BC || (n_bc > 0 && !bcs)) return fail(SWE_EINVAL, "bad boundary-condition list");
+
+    const HostMesh &M = m->H;
+    const int64_t n = M.nc;
+    const int prec = P.precision;
+    // initial state in device order
+    std::vector<double> H((size_t)n), qx((size_t)n), qy((size_t)n), gn2((size_t)n);
+    for (int64_t i = 0; i < n; i++) {
+        const int32_t p = M.inv[i];
+        const double z = M.zb[p];
+        double Hi;
+        if (H0) {
+            if (!std::isfinite(H0[i])) return fail(SWE_EINVAL, "non-finite initial surface");
+            Hi = H0[i] > z ? H0[i] : z;  // a surface below the bed is a dry cell
+        } else {
+            const double d = h0 ? h0[i] : 0.0;
+            if (!(d >= 0) || !std::isfinite(d)) return fail(SWE_EINVAL, "negative or non-finite initial depth");
+            Hi = z + d;
+        }
+        const double a = qx0 ? qx0[i] : 0.0, b = qy0 ? qy0[i] : 0.0, nn = manning ? manning[i] : 0.0;
+        if (!std::isfinite(a) || !std::isfinite(b)) return fail(SWE_EINVAL, "non-finite initial discharge");
+        if (!(nn >= 0) || !std::isfinite(nn)) return fail(SWE_EINVAL, "Manning n must be finite and >= 0");
+        H[p] = Hi;
+        qx[p] = a;
+        qy[p] = b;
+        gn2[p] = P.g * nn * nn;
+    }
+    // boundary conditions
+    std::vector<BCdev> hb((size_t)std::max(n_bc, 1));
+    std::vector<double> hydro;
+    std::vector<size_t> hoff((size_t)std::max(n_bc, 1));
+    for (int b = 0; b < n_bc; b++) {
+        const swe_bc &B = bcs[b];
+        if (B.kind < SWE_BC_WALL || B.kind > SWE_BC_OUTFLOW_ZEROGRAD) return fail(SWE_EINVAL, "unknown boundary kind");
+        hb[b] = BCdev{B.kind, 0, B.slope, 0.0, nullptr, nullptr};
+        hoff[b] = hydro.size();
+        if (B.kind == SWE_BC_INFLOW_UNIFORM) {
+            if (B.n_pts < 1 || !B.t || !B.Q) return fail(SWE_EINVAL, "inflow needs a hydrograph");
+            if (!(B.slope > 0) || !std::isfinite(B.slope)) return fail(SWE_EINVAL, "inflow needs a positive slope");
+            for (int k = 0; k < B.n_pts; k++) {
+                if (!std::isfinite(B.t[k]) || !std::isfinite(B.Q[k])) return fail(SWE_EINVAL, "non-finite hydrograph");
+                if (k > 0 && !(B.t[k] > B.t[k - 1])) return fail(SWE_EINVAL, "hydrograph times must increase");
+            }
+            hb[b].npts = B.n_pts;
+            hydro.insert(hydro.end(), B.t, B.t + B.n_pts);
+            hydro.insert(hydro.end(), B.Q, B.Q + B.n_pts);
+        }
+    }
+    const int nslots = (int)M.slot_tag.size();
+    std::vector<int> kbc((size_t)std::max(nslots, 1), BC_WALL);
+    for (int s = 0; s < nslots; s++) {
+        const int32_t tg = M.slot_tag[s];
+        if (tg < 0) continue;
+        for (int b = 0; b < n_bc; b++) {
+            if (bcs[b].tag != tg) continue;
+            if (bcs[b].kind == SWE_BC_WALL) break;
+            kbc[s] = bcs[b].kind | (b << 4);
+            hb[b].length += M.slot_len[s];
+            if (bcs[b].kind == SWE_BC_INFLOW_UNIFORM && !(gn2[M.slot_cell[s]] > 0))
+                return fail(SWE_EINVAL, "inflow edge next to a cell with Manning n = 0");
+            break;
+        }
+    }
+
+    std::unique_ptr<swe_state> S(new (std::nothrow) swe_state());
+    if (!S) return fail(SWE_ENOMEM, "out of host memory");
+    S->m = const_cast<swe_mesh *>(m);
+    S->p = P;
+    S->mem = m->mem;
+    S->prec = prec;
+    S->nslots = nslots;
+    S->block = P.block_size ? P.block_size : 256;
+    S->cpt = P.cells_per_thread ? P.cells_per_thread : 1;
+    S->spg = P.steps_per_graph ? P.steps_per_graph : 32;
+    swe_status st = prec == SWE_FP32 ? S->m->ensure_geom<float>(prec) : S->m->ensure_geom<double>(prec);
+    if (st) return st;
+
+    const size_t v4 = vec4_bytes(prec);
+    S->U0 = S->mem.alloc((size_t)n * v4);
+    S->U1 = S->mem.alloc((size_t)n * v4);
+    S->geo1 = S->mem.alloc((size_t)n * v4);
+    S->slot_kbc = (int *)S->mem.alloc(sizeof(int) * std::max(nslots, 1));
+    S->slot_acc = (double *)S->mem.alloc(2 * sizeof(double) * std::max(nslots, 1));
+    S->bcs = (BCdev *)S->mem.alloc(sizeof(BCdev) * std::max(n_bc, 1));
+    S->hydro = (double *)S->mem.alloc(sizeof(double) * std::max<size_t>(hydro.size(), 1));
+    S->ctrl = (Ctrl *)S->mem.alloc(sizeof(Ctrl));
+    S->partials = (double2 *)S->mem.alloc(sizeof(double2) * MASS_BLOCKS);
+    S->mass_out = (double *)S->mem.alloc(2 * sizeof(double));
+    if (!S->U0 || !S->U1 || !S->geo1 || !S->slot_kbc || !S->slot_acc || !S->bcs || !S->hydro || !S->ctrl ||
+        !S->partials || !S->mass_out)
+        return fail(SWE_ENOMEM, "device allocation failed (state)");
+    HIP_TRY(hipHostMalloc((void **)&S->hctrl, sizeof(Ctrl), hipHostMallocDefault));
+    HIP_TRY(hipHostMalloc((void **)&S->hbuf, 64, hipHostMallocDefault));
+    for (int b = 0; b < n_bc; b++)
+        if (hb[b].npts) {
+            hb[b].t = S->hydro + hoff[b];
+            hb[b].Q = S->hydro + hoff[b] + hb[b].npts;
+        }
+
+    hipStream_t s = S->stream();
+    auto upload = [&](auto tag) -> swe_status {
+        using T = decltype(tag);
+        std::vector<V4<T>> u((size_t)n), g1((size_t)n);
+        for (int64_t p = 0; p < n; p++) {
+            u[p].x = T(H[p]);
+            u[p].y = T(qx[p]);
+            u[p].z = T(qy[p]);
+            u[p].w = T(M.zb[p]);
+            g1[p].x = T(M.lx[3 * p + 2]);
+            g1[p].y = T(M.ly[3 * p + 2]);
+            g1[p].z = T(1.0 / M.area[p]);
+            g1[p].w = T(gn2[p]);
+        }
+        HIP_TRY(hipMemcpyAsync(S->U0, u.data(), u.size() * sizeof(V4<T>), hipMemcpyHostToDevice, s));
+        HIP_TRY(hipMemcpyAsync(S->U1, u.data(), u.size() * sizeof(V4<T>), hipMemcpyHostToDevice, s));
+        HIP_TRY(hipMemcpyAsync(S->geo1, g1.data(), g1.size() * sizeof(V4<T>), hipMemcpyHostToDevice, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        return SWE_OK;
+    };
+    st = prec == SWE_FP32 ? upload(float()) : upload(double());
+    if (st) return st;
+    std::vector<double> zeros((size_t)2 * std::max(nslots, 1), 0.0);
+    HIP_TRY(hipMemcpyAsync(S->slot_kbc, kbc.data(), sizeof(int) * kbc.size(), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(S->slot_acc, zeros.data(), sizeof(double) * zeros.size(), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(S->bcs, hb.data(), sizeof(BCdev) * hb.size(), hipMemcpyHostToDevice, s));
+    if (!hydro.empty())
+        HIP_TRY(hipMemcpyAsync(S->hydro, hydro.data(), sizeof(double) * hydro.size(), hipMemcpyHostToDevice, s));
+    Ctrl c;
+    std::memset(&c, 0, sizeof(c));
+    c.t = t0;
+    c.t_end = std::numeric_limits<double>::infinity();
+    c.rawmin = std::numeric_limits<double>::infinity();
+    c.next_min = INF_BITS;
+    *S->hctrl = c;
+    HIP_TRY(hipMemcpyAsync(S->ctrl, S->hctrl, sizeof(Ctrl), hipMemcpyHostToDevice, s));
+
+    auto fill_inst = [&](auto &I, auto tag) {
+        using T = decltype(tag);
+        I.U0 = (V4<T> *)S->U0;
+        I.U1 = (V4<T> *)S->U1;
+        I.geo0 = (const V4<T> *)m->geom[prec].geo0;
+        I.geo1 = (const V4<T> *)S->geo1;
+        I.nbr = m->geom[prec].nbr;
+        I.slot_kbc = S->slot_kbc;
+        I.slot_acc = S->slot_acc;
+        I.bcs = S->bcs;
+        I.area = m->geom[prec].area;
+        I.ctrl = S->ctrl;
+        I.n = (int)n;
+        I.ntiles = 0;
+        I.g = P.g;
+        I.cfl = P.cfl;
+        I.h_min = P.h_min;
+        I.dt_max = P.dt_max;
+        I.neg_policy = P.neg_depth_policy;
+        I.pad = 0;
+    };
+    if (prec == SWE_FP32) {
+        fill_inst(S->inst32, float());
+        HIP_TRY(launch_dt_init<float>(S->inst32, s));
+    } else {
+        fill_inst(S->inst64, double());
+        HIP_TRY(launch_dt_init<double>(S->inst64, s));
+    }
+    st = S->read_ctrl();
+    if (st) return st;
+    *out = S.release();
+    return SWE_OK;
+}
+
+void swe_state_destroy(swe_state *s) {
+    if (!s) return;
+    (void)hipStreamSynchronize(s->stream());
+    delete s;
+}
+
+swe_status swe_step(swe_state *s, double *dt_taken) {
+    if (!s) return fail(SWE_EINVAL, "state is NULL");
+    swe_status st = s->set_t_end(std::numeric_limits<double>::infinity());
+    if (st) return st;
+    const long long before = s->hctrl->steps;
+    HIP_TRY(s->launch_one());
+    st = s->read_ctrl();
+    if (st) return st;
+    st = check_flags(s->hctrl->flags);
+    if (st) return st;
+    if (s->hctrl->steps == before) return fail(SWE_ENODT, "step did not advance");
+    if (dt_taken) *dt_taken = s->hctrl->dt_last;
+    return SWE_OK;
+}
+
+swe_status swe_run_until(swe_state *s, double t_end, int64_t *n_steps) {
+    if (!s) return fail(SWE_EINVAL, "state is NULL");
+    if (std::isnan(t_end)) return fail(SWE_EINVAL, "t_end is NaN");
+    swe_status st = s->set_t_end(t_end);
+    if (st) return st;
+    st = s->read_ctrl();
+    if (st) return st;
+    const long long start = s->hctrl->steps;
+    if (n_steps) *n_steps = 0;
+    st = check_flags(s->hctrl->flags);
+    if (st) return st;
+    st = s->graph(s->spg);
+    if (st) return st;
+    while (s->hctrl->t < t_end) {
+        const double t_before = s->hctrl->t;
+        HIP_TRY(hipGraphLaunch(s->gexec, s->stream()));
+        st = s->read_ctrl();
+        if (st) return st;
+        if (n_steps) *n_steps = s->hctrl->steps - start;
+        st = check_flags(s->hctrl->flags);
+        if (st) return st;
+        if (!(s->hctrl->t > t_before)) return fail(SWE_ENODT, "time does not advance (step underflow)");
+    }
+    return SWE_OK;
+}
+
+swe_status swe_launch_steps(swe_state *s, double t_end, int64_t k) {
+    if (!s) return fail(SWE_EINVAL, "state is NULL");
+    if (k < 0) return fail(SWE_EINVAL, "negative step count");
+    swe_status st = s->set_t_end(t_end);
+    if (st) return st;
+    st = s->graph(s->spg);
+    if (st) return st;
+    int64_t left = k;
+    while (left >= s->spg) {
+        HIP_TRY(hipGraphLaunch(s->gexec, s->stream()));
+        left -= s->spg;
+    }
+    for (; left > 0; left--) HIP_TRY(s->launch_one());
+    return SWE_OK;
+}
+
+swe_status swe_sync(swe_state *s) {
+    if (!s) return fail(SWE_EINVAL, "state is NULL");
+    swe_status st = s->read_ctrl();
+    if (st) return st;
+    return check_flags(s->hctrl->flags);
+}
+
+swe_status swe_state_read(const swe_state *cs, double *H, double *h, double *qx, double *qy, double *t) {
+    swe_state *s = const_cast<swe_state *>(cs);
+    if (!s) return fail(SWE_EINVAL, "state is NULL");
+    swe_status st = s->read_ctrl();
+    if (st) return st;
+    const HostMesh &M = s->m->H;
+    const int64_t n = M.nc;
+    const void *src = s->hctrl->cur ? s->U1 : s->U0;
+    auto rd = [&](auto tag) -> swe_status {
+        using T = decltype(tag);
+        std::vector<V4<T>> u((size_t)n);
+        HIP_TRY(hipMemcpyAsync(u.data(), src, u.size() * sizeof(V4<T>), hipMemcpyDeviceToHost, s->stream()));
+        HIP_TRY(hipStreamSynchronize(s->stream()));
+        for (int64_t i = 0; i < n; i++) {
+            const V4<T> &v = u[M.inv[i]];
+            if (H) H[i] = double(v.x);
+            if (h) h[i] = double(v.x) - double(v.w);
+            if (qx) qx[i] = double(v.y);
+            if (qy) qy[i] = double(v.z);
+        }
+        return SWE_OK;
+    };
+    st = s->prec == SWE_FP32 ? rd(float()) : rd(double());
+    if (st) return st;
+    if (t) *t = s->hctrl->t;
+    return SWE_OK;
+}
+
+swe_status swe_mass(const swe_state *cs, double *mass, double *bnd_flux, double *clipped, int64_t *steps) {
+    swe_state *s = const_cast<swe_state *>(cs);
+    if (!s) return fail(SWE_EINVAL, "state is NULL");
+    if (s->prec == SWE_FP32)
+        HIP_TRY(launch_mass<float>(s->inst32, s->partials, s->mass_out, s->nslots, s->stream()));
+    else
+        HIP_TRY(launch_mass<double>(s->inst64, s->partials, s->mass_out, s->nslots, s->stream()));
+    HIP_TRY(hipMemcpyAsync(s->hbuf + 1, s->mass_out, 2 * sizeof(double), hipMemcpyDeviceToHost, s->stream()));
+    swe_status st = s->read_ctrl();
+    if (st) return st;
+    if (mass) *mass = s->hbuf[1];
+    if (bnd_flux) *bnd_flux = s->hbuf[2];
+    if (clipped) *clipped = s->hctrl->clipped;
+    if (steps) *steps = s->hctrl->steps;
+    return SWE_OK;
+}
+
+swe_status swe_autotune(swe_state *s, int32_t k, int32_t *block_size, int32_t *cells_per_thread) {
+    if (!s) return fail(SWE_EINVAL, "state is NULL");
+    if (k < 1) k = 8;
+    swe_status st = s->read_ctrl();
+    if (st) return st;
+    const Ctrl saved = *s->hctrl;
+    const int64_t n = s->m->H.nc;
+    const size_t ub = (size_t)n * vec4_bytes(s->prec);
+    const size_t ab = 2 * sizeof(double) * std::max(s->nslots, 1);
+    void *keepU = s->mem.alloc(ub);
+    void *keepA = s->mem.alloc(ab);
+    if (!keepU || !keepA) {
+        s->mem.release(keepU);
+        s->mem.release(keepA);
+        return fail(SWE_ENOMEM, "device allocation failed (autotune)");
+    }
+    void *cur = saved.cur ? s->U1 : s->U0;
+    hipStream_t q = s->stream();
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    auto cleanup = [&]() {
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+        s->mem.release(keepU);
+        s->mem.release(keepA);
+    };
+    auto restore = [&]() -> swe_status {
+        *s->hctrl = saved;
+        HIP_TRY(hipMemcpyAsync(cur, keepU, ub, hipMemcpyDeviceToDevice, q));
+        HIP_TRY(hipMemcpyAsync(s->slot_acc, keepA, ab, hipMemcpyDeviceToDevice, q));
+        HIP_TRY(hipMemcpyAsync(s->ctrl, s->hctrl, sizeof(Ctrl), hipMemcpyHostToDevice, q));
+        HIP_TRY(hipStreamSynchronize(q));
+        return SWE_OK;
+    };
+    st = [&]() -> swe_status {
+        HIP_TRY(hipMemcpyAsync(keepU, cur, ub, hipMemcpyDeviceToDevice, q));
+        HIP_TRY(hipMemcpyAsync(keepA, s->slot_acc, ab, hipMemcpyDeviceToDevice, q));
+        HIP_TRY(hipEventCreate(&e0));
+        HIP_TRY(hipEventCreate(&e1));
+        const int blocks[5] = {64, 128, 256, 512, 1024};
+        float best = std::numeric_limits<float>::infinity();
+        int bb = s->block, bc = s->cpt;
+        for (int cpt = 1; cpt <= 2; cpt++)
+            for (int b : blocks) {
+                swe_status r = restore();
+                if (r) return r;
+                s->block = b;
+                s->cpt = cpt;
+                r = s->set_t_end(std::numeric_limits<double>::infinity());
+                if (r) return r;
+                HIP_TRY(s->launch_one());
+                HIP_TRY(hipEventRecord(e0, q));
+                for (int i = 0; i < k; i++) HIP_TRY(s->launch_one());
+                HIP_TRY(hipEventRecord(e1, q));
+                HIP_TRY(hipEventSynchronize(e1));
+                float ms = 0;
+                HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+                r = s->read_ctrl();
+                if (r) return r;
+                if (s->hctrl->flags == 0 && ms < best) {
+                    best = ms;
+                    bb = b;
+                    bc = cpt;
+                }
+            }
+        s->block = bb;
+        s->cpt = bc;
+        return restore();
+    }();
+    cleanup();
+    if (st) return st;
+    if (block_size) *block_size = s->block;
+    if (cells_per_thread) *cells_per_thread = s->cpt;
+    return SWE_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ batches
+struct swe_batch {
+    DevMem mem;
+    int prec = SWE_FP32;
+    int64_t budget = 0;
+    std::vector<swe_state *> members;
+    std::vector<double> t_end;
+    std::vector<char> finished;  // members known to be done (excluded from the work list)
+    void *insts = nullptr;
+    size_t insts_cap = 0;
+    int2 *tiles = nullptr;
+    size_t tiles_cap = 0;
+    int ntiles = 0;
+    int block = 256, cpt = 1, grid = 0;
+    bool dirty = true;
+    hipStream_t cap = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    int g_k = 0;
+    ~swe_batch() {
+        if (gexec) (void)hipGraphExecDestroy(gexec);
+        if (cap) (void)hipStreamDestroy(cap);
+        mem.release(insts);
+        mem.release(tiles);
+    }
+    hipStream_t stream() const { return mem.stream(); }
+    int64_t footprint() const {
+        int64_t f = 0;
+        for (auto *s : members)
+            if (s) f += swe_state_footprint(s->m, s->prec);
+        return f;
+    }
+    hipError_t launch(hipStream_t s) {
+        return prec == SWE_FP32
+                   ? launch_step_batched<float>((const Inst<float> *)insts, tiles, ntiles, grid, block, cpt, s)
+                   : launch_step_batched<double>((const Inst<double> *)insts, tiles, ntiles, grid, block, cpt, s);
+    }
+    swe_status rebuild(int k) {
+        // work list of the members that are still running
+        std::vector<Inst<float>> i32;
+        std::vector<Inst<double>> i64;
+        std::vector<int2> tl;
+        const int per = block * cpt;
+        for (size_t m = 0; m < members.size(); m++) {
+            swe_state *s = members[m];
+            if (!s || finished[m]) continue;
+            const int idx = prec == SWE_FP32 ? (int)i32.size() : (int)i64.size();
+            const int nt = (int)((s->m->H.nc + per - 1) / per);
+            if (prec == SWE_FP32) {
+                Inst<float> I = s->inst32;
+                I.ntiles = nt;
+                i32.push_back(I);
+            } else {
+                Inst<double> I = s->inst64;
+                I.ntiles = nt;
+                i64.push_back(I);
+            }
+            for (int t = 0; t < nt; t++) tl.push_back(make_int2(idx, t));
+        }
+        const size_t nb = prec == SWE_FP32 ? i32.size() * sizeof(Inst<float>) : i64.size() * sizeof(Inst<double>);
+        if (nb > insts_cap) {
+            mem.release(insts);
+            insts_cap = std::max(nb, insts_cap * 2);
+            insts = mem.alloc(insts_cap);
+            if (!insts) return fail(SWE_ENOMEM, "device allocation failed (batch)");
+        }
+        if (tl.size() * sizeof(int2) > tiles_cap) {
+            mem.release(tiles);
+            tiles_cap = std::max(tl.size() * sizeof(int2), tiles_cap * 2);
+            tiles = (int2 *)mem.alloc(tiles_cap);
+            if (!tiles) return fail(SWE_ENOMEM, "device allocation failed (batch)");
+        }
+        if (nb)
+            HIP_TRY(hipMemcpyAsync(insts, prec == SWE_FP32 ? (const void *)i32.data() : (const void *)i64.data(), nb,
+                                   hipMemcpyHostToDevice, stream()));
+        if (!tl.empty())
+            HIP_TRY(hipMemcpyAsync(tiles, tl.data(), tl.size() * sizeof(int2), hipMemcpyHostToDevice, stream()));
+        HIP_TRY(hipStreamSynchronize(stream()));
+        ntiles = (int)tl.size();
+        grid = prec == SWE_FP32 ? batched_grid<float>(block, cpt) : batched_grid<double>(block, cpt);
+        if (grid < 1) grid = 1;
+        if (gexec) {
+            (void)hipGraphExecDestroy(gexec);
+            gexec = nullptr;
+        }
+        if (!cap) HIP_TRY(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+        hipGraph_t gr = nullptr;
+        HIP_TRY(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
+        for (int i = 0; i < k; i++) {
+            hipError_t e = launch(cap);
+            if (e != hipSuccess) {
+                hipGraph_t dummy = nullptr;
+                (void)hipStreamEndCapture(cap, &dummy);
+                if (dummy) (void)hipGraphDestroy(dummy);
+                return fail(SWE_EDEVICE, std::string("batch capture: ") + hipGetErrorString(e));
+            }
+        }
+        HIP_TRY(hipStreamEndCapture(cap, &gr));
+        hipError_t e = hipGraphInstantiate(&gexec, gr, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(gr);
+        if (e != hipSuccess) return fail(SWE_EDEVICE, std::string("batch graph: ") + hipGetErrorString(e));
+        g_k = k;
+        dirty = false;
+        return SWE_OK;
+    }
+};
+
+extern "C" {
+
+swe_status swe_batch_create(int32_t precision, int64_t budget_bytes, const swe_device *dev, swe_batch **out) {
+    if (!out) return fail(SWE_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (precision != SWE_FP32 && precision != SWE_FP64) return fail(SWE_EINVAL, "unknown precision");
+    if (budget_bytes < 0) return fail(SWE_EINVAL, "negative budget");
+    swe_batch *b = new (std::nothrow) swe_batch();
+    if (!b) return fail(SWE_ENOMEM, "out of host memory");
+    b->mem.set(dev);
+    b->prec = precision;
+    b->budget = budget_bytes;
+    *out = b;
+    return SWE_OK;
+}
+
+void swe_batch_destroy(swe_batch *b) {
+    if (!b) return;
+    (void)hipStreamSynchronize(b->stream());
+    delete b;
+}
+
+int64_t swe_batch_footprint(const swe_batch *b) { return b ? b->footprint() : 0; }
+
+swe_status swe_batch_add(swe_batch *b, swe_state *s, double t_end, int32_t *slot) {
+    if (!b || !s) return fail(SWE_EINVAL, "batch or state is NULL");
+    if (s->prec != b->prec) return fail(SWE_EINVAL, "state precision differs from the batch");
+    if (s->stream() != b->stream()) return fail(SWE_EINVAL, "state and batch must use the same stream");
+    if (std::isnan(t_end)) return fail(SWE_EINVAL, "t_end is NaN");
+    for (auto *x : b->members)
+        if (x == s) return fail(SWE_EINVAL, "state already in the batch");
+    const int64_t f = swe_state_footprint(s->m, s->prec);
+    if (b->budget > 0 && b->footprint() + f > b->budget) return fail(SWE_EBUDGET, "batch footprint budget exceeded");
+    swe_status st = s->set_t_end(t_end);
+    if (st) return st;
+    st = s->read_ctrl();
+    if (st) return st;
+    int idx = -1;
+    for (size_t i = 0; i < b->members.size(); i++)
+        if (!b->members[i]) {
+            idx = (int)i;
+            break;
+        }
+    if (idx < 0) {
+        idx = (int)b->members.size();
+        b->members.push_back(nullptr);
+        b->t_end.push_back(0);
+        b->finished.push_back(0);
+    }
+    b->members[idx] = s;
+    b->t_end[idx] = t_end;
+    b->finished[idx] = !(s->hctrl->t < t_end) || s->hctrl->flags != 0;
+    b->dirty = true;
+    if (slot) *slot = idx;
+    return SWE_OK;
+}
+
+swe_status swe_batch_remove(swe_batch *b, int32_t slot) {
+    if (!b || slot < 0 || slot >= (int32_t)b->members.size() || !b->members[slot])
+        return fail(SWE_EINVAL, "no such batch member");
+    (void)hipStreamSynchronize(b->stream());
+    b->members[slot] = nullptr;
+    b->finished[slot] = 0;
+    b->dirty = true;
+    return SWE_OK;
+}
+
+swe_status swe_batch_launch(swe_batch *b, int32_t k) {
+    if (!b || k < 1) return fail(SWE_EINVAL, "bad batch launch");
+    if (b->dirty || b->g_k != k) {
+        swe_status st = b->rebuild(k);
+        if (st) return st;
+    }
+    if (b->ntiles > 0) HIP_TRY(hipGraphLaunch(b->gexec, b->stream()));
+    return SWE_OK;
+}
+
+swe_status swe_batch_step(swe_batch *b, int32_t k, int32_t *n_active) {
+    swe_status st = swe_batch_launch(b, k);
+    if (st) return st;
+    int active = 0;
+    for (size_t i = 0; i < b->members.size(); i++) {
+        swe_state *s = b->members[i];
+        if (!s) continue;
+        HIP_TRY(hipMemcpyAsync(s->hctrl, s->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, b->stream()));
+    }
+    HIP_TRY(hipStreamSynchronize(b->stream()));
+    for (size_t i = 0; i < b->members.size(); i++) {
+        swe_state *s = b->members[i];
+        if (!s) continue;
+        const bool done = !(s->hctrl->t < b->t_end[i]) || s->hctrl->flags != 0;
+        if (done && !b->finished[i]) {
+            b->finished[i] = 1;
+            b->dirty = true;
+        }
+        if (!done) active++;
+    }
+    if (n_active) *n_active = active;
+    return SWE_OK;
+}
+
+swe_status swe_batch_poll(swe_batch *b, int32_t slot, int32_t *done, int32_t *error, double *t, int64_t *steps) {
+    if (!b || slot < 0 || slot >= (int32_t)b->members.size() || !b->members[slot])
+        return fail(SWE_EINVAL, "no such batch member");
+    swe_state *s = b->members[slot];
+    const Ctrl &c = *s->hctrl;
+    if (done) *done = !(c.t < b->t_end[slot]) || c.flags != 0;
+    if (error) *error = c.flags ? check_flags(c.flags) : 0;
+    if (t) *t = c.t;
+    if (steps) *steps = c.steps;
+    return SWE_OK;
+}
+
+}  // extern "C"

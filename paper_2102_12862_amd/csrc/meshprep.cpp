@@ -1,0 +1,202 @@
+// Host mesh preparation: validation, counter-clockwise fix, edge matching,
+// boundary tags, FP64 geometry, Hilbert renumbering of cells.
+//
+// Follows the discretisation of the paper (section "Domain discretization"):
+// a conforming triangulation, each cell with up to three neighbours across
+// edges of length l and unit normal n pointing toward the neighbour.
+#include "meshprep.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <unordered_map>
+
+namespace swe {
+
+namespace {
+
+// Hilbert index of (x, y) on a 2^16 x 2^16 grid.
+uint32_t hilbert16(uint32_t x, uint32_t y) {
+    uint32_t d = 0;
+    const uint32_t n = 1u << 16;
+    for (uint32_t s = n >> 1; s > 0; s >>= 1) {
+        const uint32_t rx = (x & s) ? 1u : 0u;
+        const uint32_t ry = (y & s) ? 1u : 0u;
+        d += s * s * ((3u * rx) ^ ry);
+        if (ry == 0) {
+            if (rx == 1) {
+                x = n - 1 - x;
+                y = n - 1 - y;
+            }
+            std::swap(x, y);
+        }
+    }
+    return d;
+}
+
+struct HalfEdge {
+    int32_t hi;    // larger node id of the edge
+    int32_t cell;  // original cell id
+    int32_t k;     // local edge index
+};
+
+}  // namespace
+
+bool prepare_mesh(const double *xyz, int64_t nv, const int32_t *tri, int64_t nc, const int32_t *seg,
+                  const int32_t *tag, int64_t ns, bool renumber, HostMesh &M, std::string &err) {
+    if (nv < 3 || nc < 1) { err = "empty mesh"; return false; }
+    if (nc >= (int64_t)NBR_LIMIT || nv >= (int64_t)INT32_MAX) { err = "mesh too large (cells must be < 2^30)"; return false; }
+    for (int64_t v = 0; v < nv; v++)
+        if (!std::isfinite(xyz[3 * v]) || !std::isfinite(xyz[3 * v + 1]) || !std::isfinite(xyz[3 * v + 2])) {
+            err = "non-finite node coordinate";
+            return false;
+        }
+    M.nv = nv;
+    M.nc = nc;
+    std::vector<int32_t> t3((size_t)(3 * nc));
+    std::vector<double> area0((size_t)nc), zb0((size_t)nc), cx((size_t)nc), cy((size_t)nc);
+    for (int64_t i = 0; i < nc; i++) {
+        int32_t a = tri[3 * i], b = tri[3 * i + 1], c = tri[3 * i + 2];
+        if (a < 0 || b < 0 || c < 0 || a >= nv || b >= nv || c >= nv || a == b || b == c || a == c) {
+            err = "bad triangle vertex index";
+            return false;
+        }
+        const double *A = xyz + 3 * a, *B = xyz + 3 * b, *C = xyz + 3 * c;
+        double cr = (B[0] - A[0]) * (C[1] - A[1]) - (B[1] - A[1]) * (C[0] - A[0]);
+        if (cr < 0) {
+            std::swap(b, c);
+            cr = -cr;
+        }
+        if (!(cr > 0)) { err = "degenerate triangle"; return false; }
+        t3[3 * i] = a; t3[3 * i + 1] = b; t3[3 * i + 2] = c;
+        area0[i] = 0.5 * cr;
+        zb0[i] = (xyz[3 * a + 2] + xyz[3 * b + 2] + xyz[3 * c + 2]) / 3.0;
+        cx[i] = (xyz[3 * a] + xyz[3 * b] + xyz[3 * c]) / 3.0;
+        cy[i] = (xyz[3 * a + 1] + xyz[3 * b + 1] + xyz[3 * c + 1]) / 3.0;
+    }
+    // half-edges bucketed by their smaller node (counting sort, O(N))
+    std::vector<int64_t> off((size_t)nv + 1, 0);
+    for (int64_t i = 0; i < nc; i++)
+        for (int k = 0; k < 3; k++) {
+            const int32_t p = t3[3 * i + k], q = t3[3 * i + (k + 1) % 3];
+            off[(size_t)std::min(p, q) + 1]++;
+        }
+    for (int64_t v = 0; v < nv; v++) off[v + 1] += off[v];
+    std::vector<HalfEdge> he((size_t)(3 * nc));
+    {
+        std::vector<int64_t> fill(off.begin(), off.end() - 1);
+        for (int64_t i = 0; i < nc; i++)
+            for (int k = 0; k < 3; k++) {
+                const int32_t p = t3[3 * i + k], q = t3[3 * i + (k + 1) % 3];
+                he[(size_t)fill[std::min(p, q)]++] = HalfEdge{std::max(p, q), (int32_t)i, k};
+            }
+    }
+    std::unordered_map<uint64_t, int32_t> segtag;
+    segtag.reserve((size_t)ns * 2 + 1);
+    for (int64_t s = 0; s < ns; s++) {
+        const int32_t p = seg[2 * s], q = seg[2 * s + 1];
+        if (p < 0 || q < 0 || p >= nv || q >= nv || p == q) { err = "bad boundary segment"; return false; }
+        const uint64_t key = ((uint64_t)std::min(p, q) << 32) | (uint32_t)std::max(p, q);
+        if (!segtag.emplace(key, tag[s]).second) { err = "duplicate boundary segment"; return false; }
+    }
+    // neighbour of every (old cell, local edge): old neighbour id, or -1 - boundary id
+    std::vector<int32_t> link((size_t)(3 * nc));
+    std::vector<int32_t> btag;
+    int64_t matched = 0, ne = 0;
+    for (int64_t v = 0; v < nv; v++) {
+        HalfEdge *b = he.data() + off[v], *e = he.data() + off[v + 1];
+        std::sort(b, e, [](const HalfEdge &x, const HalfEdge &y) {
+            return x.hi != y.hi ? x.hi < y.hi : x.cell < y.cell;
+        });
+        for (HalfEdge *g = b; g < e;) {
+            HalfEdge *h = g + 1;
+            while (h < e && h->hi == g->hi) h++;
+            const int64_t cnt = h - g;
+            if (cnt > 2) { err = "non-conforming edge shared by 3+ triangles"; return false; }
+            ne++;
+            if (cnt == 2) {
+                const int32_t c1 = g[0].cell, k1 = g[0].k, c2 = g[1].cell, k2 = g[1].k;
+                // the two cells must traverse the edge in opposite directions
+                const int32_t q1 = t3[3 * c1 + (k1 + 1) % 3];
+                if (t3[3 * c2 + k2] != q1) { err = "inconsistent orientation (overlapping triangles)"; return false; }
+                link[3 * c1 + k1] = c2;
+                link[3 * c2 + k2] = c1;
+            } else {
+                const uint64_t key = ((uint64_t)v << 32) | (uint32_t)g->hi;
+                auto it = segtag.find(key);
+                int32_t tg = -1;
+                if (it != segtag.end()) {
+                    tg = it->second;
+                    matched++;
+                }
+                link[3 * g->cell + g->k] = -1 - (int32_t)btag.size();
+                btag.push_back(tg);
+            }
+            g = h;
+        }
+    }
+    if (matched != ns) { err = "boundary segment is not a boundary edge of the mesh"; return false; }
+    M.ne = ne;
+    M.nb = (int64_t)btag.size();
+
+    // renumbering: Hilbert order of centroids on a square box (isotropic)
+    M.perm.resize((size_t)nc);
+    for (int64_t i = 0; i < nc; i++) M.perm[i] = (int32_t)i;
+    if (renumber && nc > 1) {
+        double x0 = cx[0], x1 = cx[0], y0 = cy[0], y1 = cy[0];
+        for (int64_t i = 1; i < nc; i++) {
+            x0 = std::min(x0, cx[i]); x1 = std::max(x1, cx[i]);
+            y0 = std::min(y0, cy[i]); y1 = std::max(y1, cy[i]);
+        }
+        const double ext = std::max(x1 - x0, y1 - y0);
+        const double sc = ext > 0 ? 65535.0 / ext : 0.0;
+        std::vector<uint64_t> key((size_t)nc);
+        for (int64_t i = 0; i < nc; i++) {
+            const uint32_t hx = (uint32_t)std::min(65535.0, std::max(0.0, (cx[i] - x0) * sc));
+            const uint32_t hy = (uint32_t)std::min(65535.0, std::max(0.0, (cy[i] - y0) * sc));
+            key[i] = ((uint64_t)hilbert16(hx, hy) << 32) | (uint32_t)i;
+        }
+        std::sort(key.begin(), key.end());
+        for (int64_t p = 0; p < nc; p++) M.perm[p] = (int32_t)(key[p] & 0xffffffffu);
+    }
+    M.inv.resize((size_t)nc);
+    for (int64_t p = 0; p < nc; p++) M.inv[M.perm[p]] = (int32_t)p;
+
+    // device-order arrays
+    M.area.resize((size_t)nc);
+    M.zb.resize((size_t)nc);
+    M.lx.resize((size_t)(3 * nc));
+    M.ly.resize((size_t)(3 * nc));
+    M.nbr.resize((size_t)(3 * nc));
+    M.slot_tag.clear();
+    M.slot_len.clear();
+    M.slot_cell.clear();
+    for (int64_t p = 0; p < nc; p++) {
+        const int32_t i = M.perm[p];
+        M.area[p] = area0[i];
+        M.zb[p] = zb0[i];
+        for (int k = 0; k < 3; k++) {
+            const int32_t a = t3[3 * i + k], b = t3[3 * i + (k + 1) % 3];
+            const double dx = xyz[3 * b] - xyz[3 * a], dy = xyz[3 * b + 1] - xyz[3 * a + 1];
+            // l * n for a counter-clockwise cell: (dy, -dx); the neighbour walks
+            // the edge the other way and stores the exact negation
+            M.lx[3 * p + k] = dy;
+            M.ly[3 * p + k] = -dx;
+            const int32_t L = link[3 * i + k];
+            if (L >= 0) {
+                int32_t code = M.inv[L];
+                if (i > L) code |= NBR_FLIP_BIT;  // canonical left cell = smaller original id
+                M.nbr[3 * p + k] = code;
+            } else {
+                const int32_t slot = (int32_t)M.slot_tag.size();
+                M.slot_tag.push_back(btag[-1 - L]);
+                M.slot_len.push_back(std::sqrt(dx * dx + dy * dy));
+                M.slot_cell.push_back((int32_t)p);
+                M.nbr[3 * p + k] = -1 - slot;
+            }
+        }
+    }
+    return true;
+}
+
+}  // namespace swe

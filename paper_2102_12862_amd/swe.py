@@ -1,0 +1,321 @@
+"""Thin ctypes binding of the gfx950 shallow-water library (``include/swe.h``).
+
+Argument marshalling only: every step of the method runs in the HIP kernels
+of ``libswe.so``.  Device memory comes from PyTorch's caching allocator and
+work is issued on PyTorch's current HIP stream, through the library's
+allocation callbacks.  There is no CPU fallback: importing this module on a
+tree without the built library raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libswe.so")
+
+OK, EINVAL, ENOMEM, EDEVICE, ENONFINITE, ENEGDEPTH, EBUDGET, ENODT = 0, -1, -2, -3, -4, -5, -6, -7
+BC_WALL, BC_INFLOW_UNIFORM, BC_OUTFLOW_ZEROGRAD = 0, 1, 2
+FP64, FP32 = 0, 1
+NEG_CLIP, NEG_ERROR = 0, 1
+
+_dp = ctypes.POINTER(ctypes.c_double)
+_ip = ctypes.POINTER(ctypes.c_int32)
+_lp = ctypes.POINTER(ctypes.c_int64)
+
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
+
+
+class SweDevice(ctypes.Structure):
+    _fields_ = [("alloc", ALLOC_FN), ("free", FREE_FN), ("ctx", ctypes.c_void_p), ("hip_stream", ctypes.c_void_p)]
+
+
+class SweBC(ctypes.Structure):
+    _fields_ = [("tag", ctypes.c_int32), ("kind", ctypes.c_int32), ("slope", ctypes.c_double),
+                ("t", _dp), ("Q", _dp), ("n_pts", ctypes.c_int32)]
+
+
+class SweParams(ctypes.Structure):
+    _fields_ = [("g", ctypes.c_double), ("cfl", ctypes.c_double), ("h_min", ctypes.c_double),
+                ("dt_max", ctypes.c_double), ("precision", ctypes.c_int32), ("neg_depth_policy", ctypes.c_int32),
+                ("block_size", ctypes.c_int32), ("cells_per_thread", ctypes.c_int32),
+                ("steps_per_graph", ctypes.c_int32), ("renumber", ctypes.c_int32)]
+
+
+# every symbol the header declares, with (restype, argtypes)
+SIGNATURES = {
+    "swe_params_default": (None, [ctypes.POINTER(SweParams)]),
+    "swe_mesh_create": (ctypes.c_int32, [_dp, ctypes.c_int64, _ip, ctypes.c_int64, _ip, _ip, ctypes.c_int64,
+                                         ctypes.POINTER(SweParams), ctypes.POINTER(SweDevice),
+                                         ctypes.POINTER(ctypes.c_void_p)]),
+    "swe_mesh_destroy": (None, [ctypes.c_void_p]),
+    "swe_mesh_info": (None, [ctypes.c_void_p, _lp, _lp, _lp]),
+    "swe_state_footprint": (ctypes.c_int64, [ctypes.c_void_p, ctypes.c_int32]),
+    "swe_state_init": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(SweParams), _dp, _dp, _dp, _dp, _dp,
+                                        ctypes.POINTER(SweBC), ctypes.c_int32, ctypes.c_double,
+                                        ctypes.POINTER(ctypes.c_void_p)]),
+    "swe_state_destroy": (None, [ctypes.c_void_p]),
+    "swe_step": (ctypes.c_int32, [ctypes.c_void_p, _dp]),
+    "swe_run_until": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_double, _lp]),
+    "swe_launch_steps": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_double, ctypes.c_int64]),
+    "swe_sync": (ctypes.c_int32, [ctypes.c_void_p]),
+    "swe_state_read": (ctypes.c_int32, [ctypes.c_void_p, _dp, _dp, _dp, _dp, _dp]),
+    "swe_mass": (ctypes.c_int32, [ctypes.c_void_p, _dp, _dp, _dp, _lp]),
+    "swe_autotune": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, _ip, _ip]),
+    "swe_batch_create": (ctypes.c_int32, [ctypes.c_int32, ctypes.c_int64, ctypes.POINTER(SweDevice),
+                                          ctypes.POINTER(ctypes.c_void_p)]),
+    "swe_batch_destroy": (None, [ctypes.c_void_p]),
+    "swe_batch_add": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double, _ip]),
+    "swe_batch_remove": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32]),
+    "swe_batch_step": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, _ip]),
+    "swe_batch_launch": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32]),
+    "swe_batch_poll": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, _ip, _ip, _dp, _lp]),
+    "swe_batch_footprint": (ctypes.c_int64, [ctypes.c_void_p]),
+    "swe_last_error": (ctypes.c_char_p, []),
+    "swe_version": (ctypes.c_char_p, []),
+}
+
+_lib = None
+
+
+def load():
+    """Loads libswe.so (no build, no fallback)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() "
+                              "(python paper_2102_12862_amd/build.py)")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+class SweError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"swe error {code}: {msg}")
+        self.code = code
+
+
+def _check(rc):
+    if rc != OK:
+        raise SweError(rc, load().swe_last_error().decode())
+
+
+def _d(a):
+    return None if a is None else a.ctypes.data_as(_dp)
+
+
+def _i(a):
+    return None if a is None else a.ctypes.data_as(_ip)
+
+
+class TorchDevice:
+    """Bridges the library's allocation callbacks to PyTorch's caching
+    allocator and hands it the current HIP stream."""
+
+    def __init__(self, stream=None):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("no HIP device visible to PyTorch")
+        self._torch = torch
+        self._live = {}
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+
+        def _alloc(nbytes, ctx):
+            try:
+                t = self._torch.empty(int(nbytes), dtype=self._torch.uint8, device="cuda")
+            except RuntimeError:
+                return None
+            p = t.data_ptr()
+            self._live[p] = t
+            return p
+
+        def _free(ptr, ctx):
+            self._live.pop(ptr, None)
+
+        self._alloc = ALLOC_FN(_alloc)
+        self._free = FREE_FN(_free)
+        self.struct = SweDevice(self._alloc, self._free, None, ctypes.c_void_p(self.stream.cuda_stream))
+
+    @property
+    def live_bytes(self):
+        return sum(t.numel() for t in self._live.values())
+
+
+def params(**kw) -> SweParams:
+    p = SweParams()
+    load().swe_params_default(ctypes.byref(p))
+    for k, v in kw.items():
+        setattr(p, k, v)
+    return p
+
+
+class Mesh:
+    def __init__(self, nodes, tri, bnd_seg=None, bnd_tag=None, device: Optional[TorchDevice] = None,
+                 renumber: bool = True):
+        L = load()
+        # device=False: host-side mesh preparation only (no device callbacks);
+        # states created on such a mesh use hipMalloc and the default stream
+        self.device = None if device is False else (device or TorchDevice())
+        nodes = np.ascontiguousarray(nodes, np.float64)
+        tri = np.ascontiguousarray(tri, np.int32)
+        seg = np.zeros((0, 2), np.int32) if bnd_seg is None else np.ascontiguousarray(bnd_seg, np.int32)
+        tag = np.zeros((0,), np.int32) if bnd_tag is None else np.ascontiguousarray(bnd_tag, np.int32)
+        p = params(renumber=1 if renumber else 0)
+        h = ctypes.c_void_p()
+        _check(L.swe_mesh_create(_d(nodes), len(nodes), _i(tri), len(tri), _i(seg), _i(tag), len(seg),
+                                 ctypes.byref(p), None if self.device is None else ctypes.byref(self.device.struct),
+                                 ctypes.byref(h)))
+        self._h = h
+        self.n_cells = len(tri)
+
+    def info(self):
+        a, b, c = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        load().swe_mesh_info(self._h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c))
+        return dict(n_cells=a.value, n_edges=b.value, n_boundary_edges=c.value)
+
+    def footprint(self, precision=FP32):
+        return load().swe_state_footprint(self._h, precision)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().swe_mesh_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
+
+
+def _bc_array(bcs):
+    arr = (SweBC * max(1, len(bcs)))()
+    keep = []
+    for k, b in enumerate(bcs):
+        t = None if b.t is None else np.ascontiguousarray(b.t, np.float64)
+        Q = None if b.Q is None else np.ascontiguousarray(b.Q, np.float64)
+        keep += [t, Q]
+        arr[k] = SweBC(b.tag, b.kind, b.slope, _d(t), _d(Q), 0 if t is None else len(t))
+    return arr, keep
+
+
+class State:
+    """Device-resident solve of one scenario (see swe_inputs.Scenario)."""
+
+    def __init__(self, mesh: Mesh, sc, precision=FP64, t0: float = 0.0, H0=None, h0=None, qx0=None, qy0=None,
+                 **pkw):
+        L = load()
+        self.mesh = mesh
+        self.precision = precision
+        p = params(g=sc.g, cfl=sc.cfl, h_min=sc.h_min, dt_max=sc.dt_max, precision=precision, **pkw)
+        if H0 is None and h0 is None:
+            H0, h0 = sc.H0, sc.h0
+        qx0 = sc.qx0 if qx0 is None else qx0
+        qy0 = sc.qy0 if qy0 is None else qy0
+        arrs = [None if a is None else np.ascontiguousarray(a, np.float64) for a in (H0, h0, qx0, qy0, sc.manning)]
+        bc, keep = _bc_array(sc.bcs)
+        h = ctypes.c_void_p()
+        _check(L.swe_state_init(mesh._h, ctypes.byref(p), *[_d(a) for a in arrs], bc, len(sc.bcs), t0,
+                                ctypes.byref(h)))
+        self._h = h
+        self.n = mesh.n_cells
+
+    def step(self):
+        dt = ctypes.c_double()
+        _check(load().swe_step(self._h, ctypes.byref(dt)))
+        return dt.value
+
+    def run_until(self, t_end):
+        n = ctypes.c_int64()
+        _check(load().swe_run_until(self._h, t_end, ctypes.byref(n)))
+        return n.value
+
+    def launch_steps(self, k, t_end=float("inf")):
+        _check(load().swe_launch_steps(self._h, t_end, k))
+
+    def sync(self):
+        _check(load().swe_sync(self._h))
+
+    def read(self):
+        H, h, qx, qy = (np.empty(self.n) for _ in range(4))
+        t = ctypes.c_double()
+        _check(load().swe_state_read(self._h, _d(H), _d(h), _d(qx), _d(qy), ctypes.byref(t)))
+        return dict(H=H, h=h, qx=qx, qy=qy, t=t.value)
+
+    def mass(self):
+        m, b, c = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+        s = ctypes.c_int64()
+        _check(load().swe_mass(self._h, ctypes.byref(m), ctypes.byref(b), ctypes.byref(c), ctypes.byref(s)))
+        return dict(mass=m.value, bnd_flux=b.value, clipped=c.value, steps=s.value)
+
+    def autotune(self, k=8):
+        b, c = ctypes.c_int32(), ctypes.c_int32()
+        _check(load().swe_autotune(self._h, k, ctypes.byref(b), ctypes.byref(c)))
+        return b.value, c.value
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().swe_state_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
+
+
+class Batch:
+    """Many independent states stepped together by one persistent kernel per
+    step, each with its own time step."""
+
+    def __init__(self, precision=FP32, budget_bytes: int = 0, device: Optional[TorchDevice] = None):
+        self.device = device or TorchDevice()
+        h = ctypes.c_void_p()
+        _check(load().swe_batch_create(precision, budget_bytes, ctypes.byref(self.device.struct), ctypes.byref(h)))
+        self._h = h
+        self.members = {}
+
+    def add(self, state: State, t_end: float) -> int:
+        slot = ctypes.c_int32()
+        _check(load().swe_batch_add(self._h, state._h, t_end, ctypes.byref(slot)))
+        self.members[slot.value] = state
+        return slot.value
+
+    def remove(self, slot: int):
+        _check(load().swe_batch_remove(self._h, slot))
+        self.members.pop(slot, None)
+
+    def step(self, k: int) -> int:
+        n = ctypes.c_int32()
+        _check(load().swe_batch_step(self._h, k, ctypes.byref(n)))
+        return n.value
+
+    def launch(self, k: int):
+        _check(load().swe_batch_launch(self._h, k))
+
+    def poll(self, slot: int):
+        d, e = ctypes.c_int32(), ctypes.c_int32()
+        t, s = ctypes.c_double(), ctypes.c_int64()
+        _check(load().swe_batch_poll(self._h, slot, ctypes.byref(d), ctypes.byref(e), ctypes.byref(t), ctypes.byref(s)))
+        return dict(done=bool(d.value), error=e.value, t=t.value, steps=s.value)
+
+    def footprint(self):
+        return load().swe_batch_footprint(self._h)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().swe_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
+
+
+def exported_symbols(path: str = LIB_PATH) -> Sequence[str]:
+    """Names of the C-ABI functions the library exports (read with ctypes)."""
+    L = ctypes.CDLL(path)
+    return [n for n in SIGNATURES if hasattr(L, n)]

@@ -1,0 +1,69 @@
+"""Helpers shared by the GPU tests: run a scenario through the C ABI and
+through the oracle, and compare them."""
+from __future__ import annotations
+
+import functools
+import os
+import pickle
+
+import numpy as np
+
+import swe_inputs as S
+
+CACHE = os.environ.get("SWE_MESH_CACHE", "/tmp/swe_mesh_cache")
+
+
+def cached(name, fn, *args, **kw):
+    """Scenario generation is deterministic; large meshes are cached on disk
+    for the duration of a run (files written by this process only)."""
+    os.makedirs(CACHE, exist_ok=True)
+    key = name + "_" + "_".join(f"{a}" for a in args) + "_" + "_".join(f"{k}{v}" for k, v in sorted(kw.items()))
+    path = os.path.join(CACHE, key + ".pkl")
+    if os.path.exists(path):
+        with open(path, "rb") as f:
+            return pickle.load(f)
+    sc = fn(*args, **kw)
+    tmp = path + f".{os.getpid()}.tmp"
+    with open(tmp, "wb") as f:
+        pickle.dump(sc, f)
+    os.replace(tmp, path)
+    return sc
+
+
+@functools.lru_cache(maxsize=None)
+def device():
+    from paper_2102_12862_amd import swe
+    return swe.TorchDevice()
+
+
+def gpu_state(sc, precision, mesh=None, **params):
+    from paper_2102_12862_amd import swe
+    renumber = params.pop("renumber", True)
+    if mesh is None:
+        mesh = swe.Mesh(sc.nodes, sc.tri, sc.bnd_seg, sc.bnd_tag, device=device(), renumber=renumber)
+    return swe.State(mesh, sc, precision=precision, **params)
+
+
+def rel_err(got, ref, floor=1e-300):
+    """max |got - ref| / max |ref| (norm-relative, as stated for parity)."""
+    d = np.abs(got - ref).max()
+    s = np.abs(ref).max()
+    if s < floor:
+        return float(d)
+    return float(d / s)
+
+
+def l1_rel(got, ref, w):
+    return float((np.abs(got - ref) * w).sum() / max((np.abs(ref) * w).sum(), 1e-300))
+
+
+def compare(state, sim, tol, fields=("H", "h", "qx", "qy")):
+    got = state.read()
+    H, qx, qy, t = sim.state()
+    zb = sim.mesh.geometry()["zb"]
+    ref = dict(H=H, h=H - zb, qx=qx, qy=qy)
+    errs = {f: rel_err(got[f], ref[f]) for f in fields}
+    bad = {f: e for f, e in errs.items() if not e <= tol}
+    assert not bad, f"parity beyond {tol}: {errs} (t gpu {got['t']} oracle {t})"
+    assert abs(got["t"] - t) <= 1e-9 * max(1.0, abs(t)), (got["t"], t)
+    return errs

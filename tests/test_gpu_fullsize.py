@@ -1,0 +1,49 @@
+"""Parity at the full valley-flood size (4M cells), in the launch
+configuration the benchmark times: every output compared with the oracle
+after a few steps (the oracle takes about a second per step at this size)."""
+import numpy as np
+import pytest
+
+import oracle
+import swe_inputs as S
+from gpu_util import cached, compare, gpu_state
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def valley_wet():
+    return cached("valley", S.valley_flood, n_cells=4_000_000, snapshot="wet")
+
+
+@pytest.fixture(scope="module")
+def valley_oracle(valley_wet):
+    return oracle.Mesh(valley_wet.nodes, valley_wet.tri, valley_wet.bnd_seg, valley_wet.bnd_tag)
+
+
+def test_fullsize_fp32_three_steps(valley_wet, valley_oracle):
+    from paper_2102_12862_amd import swe
+    sc = valley_wet
+    assert sc.n_cells > 3_900_000
+    st = gpu_state(sc, swe.FP32)
+    sim = oracle.Sim(sc, mesh=valley_oracle)
+    for _ in range(3):
+        st.step()
+        sim.step()
+    r = st.read()
+    H, qx, qy, t = sim.state()
+    for f, ref in (("H", H), ("qx", qx), ("qy", qy)):
+        err = np.abs(r[f] - ref).max() / np.abs(ref).max()
+        assert err <= 1e-4, (f, err)
+    assert abs(r["t"] - t) <= 1e-6 * t
+
+
+def test_fullsize_fp64_two_steps(valley_wet, valley_oracle):
+    from paper_2102_12862_amd import swe
+    sc = valley_wet
+    st = gpu_state(sc, swe.FP64)
+    sim = oracle.Sim(sc, mesh=valley_oracle)
+    for _ in range(2):
+        st.step()
+        sim.step()
+    compare(st, sim, 1e-10)

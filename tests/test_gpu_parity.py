@@ -1,0 +1,243 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle on
+the same seeded inputs, plus the invariants that must hold on the device.
+
+Tolerances (norm-relative max|gpu - oracle| / max|oracle| per field):
+FP64 state 1e-10, FP32 state (FP64 thresholds, dt and mass) 1e-4."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import swe_inputs as S
+from gpu_util import cached, compare, gpu_state, l1_rel, rel_err
+
+pytestmark = pytest.mark.gpu
+
+FP64_TOL = 1e-10
+FP32_TOL = 1e-4
+
+
+@pytest.fixture(scope="module")
+def swe():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_2102_12862_amd import swe as mod
+    return mod
+
+
+def _t_close(a, b, tol):
+    assert abs(a - b) <= tol * max(1.0, abs(b)), (a, b)
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_tiny_random_meshes_fp64(swe, seed):
+    sc = S.tiny_random(3, 3, seed=seed)
+    st = gpu_state(sc, swe.FP64)
+    sim = oracle.Sim(sc)
+    for k in range(10):
+        dt_gpu = st.step()
+        dt_or = sim.step()
+        assert abs(dt_gpu - dt_or) <= 1e-13 * dt_or, (k, dt_gpu, dt_or)
+    compare(st, sim, FP64_TOL)
+
+
+def test_single_cell_and_two_cells(swe):
+    # degenerate sizes: one wall-bounded cell, two cells sharing one edge
+    nodes = np.array([[0, 0, 0.1], [1, 0, 0.0], [0, 1, 0.2], [1, 1, 0.05]], float)
+    for tri in (np.array([[0, 1, 2]], np.int32), np.array([[0, 1, 2], [1, 3, 2]], np.int32)):
+        n = len(tri)
+        sc = S.Scenario("small", nodes, tri, np.zeros((0, 2), np.int32), np.zeros(0, np.int32), [],
+                        None, np.linspace(0.3, 0.6, n), np.full(n, 0.1), np.full(n, -0.05),
+                        np.full(n, 0.02), t_end=1.0)
+        st = gpu_state(sc, swe.FP64)
+        sim = oracle.Sim(sc)
+        for _ in range(5):
+            st.step()
+            sim.step()
+        compare(st, sim, FP64_TOL)
+
+
+def test_dam_break_fp64_to_t_end(swe):
+    sc = S.dam_break(1.0)
+    st = gpu_state(sc, swe.FP64)
+    n = st.run_until(5.0)
+    sim = oracle.Sim(sc)
+    n_or = sim.run_until(5.0)
+    assert n == n_or
+    compare(st, sim, FP64_TOL)
+    m = st.mass()
+    assert abs(m["mass"] - 550.0) <= 1e-12 * 550.0 and m["clipped"] == 0.0
+
+
+def test_ritter_dry_bed_fp64_and_fp32(swe):
+    sc = S.dam_break(0.5, h_right=0.0)
+    sim = oracle.Sim(sc)
+    sim.run_until(5.0)
+    st = gpu_state(sc, swe.FP64)
+    st.run_until(5.0)
+    compare(st, sim, FP64_TOL)
+    st32 = gpu_state(sc, swe.FP32)
+    st32.run_until(5.0)
+    compare(st32, sim, FP32_TOL)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_valley_inflow_outflow_wet_dry(swe, prec):
+    sc = S.valley_flood(n_cells=20000, scale=0.1, q_peak=200.0, t_rise=600.0)
+    p = swe.FP64 if prec == "fp64" else swe.FP32
+    st = gpu_state(sc, p)
+    sim = oracle.Sim(sc)
+    t_end = 120.0
+    st.run_until(t_end)
+    sim.run_until(t_end)
+    errs = compare(st, sim, FP64_TOL if prec == "fp64" else FP32_TOL)
+    m = st.mass()
+    d = sim.diag()
+    assert m["bnd_flux"] < 0
+    assert abs(m["bnd_flux"] - d["bnd_flux"]) <= (1e-10 if prec == "fp64" else 1e-4) * abs(d["bnd_flux"])
+    # conservation on the device itself
+    assert abs(m["mass"] + m["bnd_flux"] - m["clipped"]) <= 1e-9 * abs(m["bnd_flux"]) + 1e-6
+    print(prec, errs, m)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_lake_at_rest_exact_small(swe, prec):
+    sc = S.lake_at_rest(n_cells=5000, t_end=600.0)
+    p = swe.FP64 if prec == "fp64" else swe.FP32
+    st = gpu_state(sc, p)
+    r0 = st.read()
+    m0 = st.mass()
+    n = st.run_until(600.0)
+    assert n > 100
+    r = st.read()
+    assert r["t"] == 600.0
+    assert np.array_equal(r["H"], r0["H"])
+    assert not np.any(r["qx"]) and not np.any(r["qy"])
+    m = st.mass()
+    assert m["mass"] == m0["mass"] and m["clipped"] == 0.0
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_lake_at_rest_exact_full_size(swe, prec):
+    sc = cached("lake", S.lake_at_rest, n_cells=200_000)
+    p = swe.FP64 if prec == "fp64" else swe.FP32
+    st = gpu_state(sc, p)
+    r0 = st.read()
+    st.run_until(600.0)
+    r = st.read()
+    assert np.array_equal(r["H"], r0["H"])
+    assert not np.any(r["qx"]) and not np.any(r["qy"])
+    assert st.mass()["clipped"] == 0.0
+
+
+def test_lake_at_rest_moving_water_parity_fp32(swe):
+    # the same bed with water set in motion: FP32 against the FP64 oracle
+    sc = S.lake_at_rest(n_cells=5000)
+    r = np.random.default_rng(3)
+    sc.qx0 = r.uniform(-0.3, 0.3, sc.n_cells)
+    sc.qy0 = r.uniform(-0.3, 0.3, sc.n_cells)
+    st = gpu_state(sc, swe.FP32)
+    sim = oracle.Sim(sc)
+    st.run_until(30.0)
+    sim.run_until(30.0)
+    compare(st, sim, FP32_TOL)
+
+
+def test_determinism_block_sizes_and_renumbering(swe):
+    sc = S.valley_flood(n_cells=20000, scale=0.1, snapshot="wet")
+    ref = None
+    for kw in (dict(block_size=256), dict(block_size=64), dict(block_size=1024),
+               dict(block_size=128, cells_per_thread=2), dict(block_size=256, renumber=False),
+               dict(block_size=256)):
+        st = gpu_state(sc, swe.FP32, **kw)
+        st.run_until(20.0)
+        r = st.read()
+        m = st.mass()
+        if ref is None:
+            ref = (r, m)
+            continue
+        for f in ("H", "qx", "qy"):
+            assert np.array_equal(r[f], ref[0][f]), (kw, f)
+        assert r["t"] == ref[0]["t"]
+        assert m["mass"] == ref[1]["mass"] and m["bnd_flux"] == ref[1]["bnd_flux"]
+
+
+def test_restart_is_bitwise(swe):
+    sc = S.valley_flood(n_cells=20000, scale=0.1, q_peak=300.0, t_rise=300.0)
+    a = gpu_state(sc, swe.FP32)
+    a.run_until(60.0)
+    b = gpu_state(sc, swe.FP32)
+    b.run_until(25.0)
+    r = b.read()
+    c = gpu_state(sc, swe.FP32, t0=r["t"], H0=r["H"], qx0=r["qx"], qy0=r["qy"])
+    c.run_until(60.0)
+    ra, rc = a.read(), c.read()
+    for f in ("H", "qx", "qy"):
+        assert np.array_equal(ra[f], rc[f]), f
+    assert ra["t"] == rc["t"]
+
+
+def test_mass_conservation_tiny_fp64(swe):
+    for seed in range(4):
+        sc = S.tiny_random(4, 4, seed=10 + seed)
+        st = gpu_state(sc, swe.FP64)
+        m0 = st.mass()["mass"]
+        for _ in range(30):
+            st.step()
+        m = st.mass()
+        assert abs(m["mass"] - m0 + m["bnd_flux"] - m["clipped"]) <= 1e-13 * max(1.0, m0)
+
+
+def test_errors_are_reported(swe):
+    # a dry domain with no time-step cap has no finite step
+    sc = S.lake_at_rest(n_cells=600)
+    sc.H0 = None
+    sc.h0 = np.zeros(sc.n_cells)
+    st = gpu_state(sc, swe.FP64)
+    with pytest.raises(swe.SweError) as e:
+        st.step()
+    assert e.value.code == swe.ENODT
+    # ... but run_until caps the step at t_end
+    st2 = gpu_state(sc, swe.FP64)
+    st2.run_until(3.0)
+    assert st2.read()["t"] == 3.0
+    # overflowing discharges make the state non-finite
+    sc2 = S.tiny_random(3, 3, seed=0, bcs=False)
+    sc2.qx0 = np.where(sc2.h0 > 0, 1e300, 0.0)
+    st3 = gpu_state(sc2, swe.FP64)
+    with pytest.raises(swe.SweError) as e:
+        for _ in range(3):
+            st3.step()
+    assert e.value.code in (swe.ENONFINITE, swe.ENODT)
+    # invalid input is rejected before anything runs on the device
+    bad = S.tiny_random(2, 2, seed=0)
+    bad.h0 = bad.h0.copy()
+    bad.h0[0] = float("nan")
+    with pytest.raises(swe.SweError) as e:
+        gpu_state(bad, swe.FP64)
+    assert e.value.code == swe.EINVAL
+    with pytest.raises(swe.SweError):
+        gpu_state(S.Scenario(**{**S.tiny_random(2, 2).__dict__, "cfl": 1.5}), swe.FP64)
+
+
+def test_negative_depth_policy_error(swe):
+    # the Ritter front clips a little volume; under the error policy the
+    # library reports it instead
+    sc = S.dam_break(1.0, h_right=0.0)
+    st = gpu_state(sc, swe.FP64, neg_depth_policy=swe.NEG_ERROR)
+    with pytest.raises(swe.SweError) as e:
+        st.run_until(5.0)
+    assert e.value.code == swe.ENEGDEPTH
+
+
+def test_autotune_keeps_state(swe):
+    sc = S.valley_flood(n_cells=20000, scale=0.1, snapshot="wet")
+    a = gpu_state(sc, swe.FP32)
+    b = gpu_state(sc, swe.FP32)
+    bs, cpt = b.autotune(k=3)
+    assert bs in (64, 128, 256, 512, 1024) and cpt in (1, 2)
+    a.run_until(10.0)
+    b.run_until(10.0)
+    ra, rb = a.read(), b.read()
+    assert all(np.array_equal(ra[f], rb[f]) for f in ("H", "qx", "qy"))

@@ -75,6 +75,11 @@ static void neumaier(double *sum, double *comp, double v) {
     *sum = t;
 }
 
+static int cmp_double(const void *p, const void *q) {
+    double a = *(const double *)p, b = *(const double *)q;
+    return a < b ? -1 : (a > b ? 1 : 0);
+}
+
 /* ------------------------------------------------------------------ mesh */
 typedef struct {
     int32_t a, b, cell, k;
@@ -324,15 +329,33 @@ om_sim *om_sim_new(const om_mesh *m, double g, double cfl, double h_min, double 
     for (int64_t e = 0; e < m->ne; e++) {
         s->ebc[e] = -1;
         if (m->eR[e] >= 0 || m->etag[e] < 0) continue;
-        for (int b = 0; b < nbc; b++)
-            if (s->bc[b].tag == m->etag[e] && s->bc[b].kind != OM_WALL) { s->ebc[e] = b; break; }
+        for (int b = 0; b < nbc; b++) {
+            if (s->bc[b].tag != m->etag[e]) continue;
+            if (s->bc[b].kind != OM_WALL) s->ebc[e] = b;
+            break;
+        }
         if (s->ebc[e] >= 0) {
             om_bc *B = &s->bc[s->ebc[e]];
-            B->length += m->elen[e];
             if (B->kind == OM_INFLOW_UNIFORM && !(s->gn2[m->eL[e]] > 0)) {
                 seterr(err, elen, "inflow edge next to a cell with Manning n = 0"); goto fail;
             }
         }
+    }
+    /* Length of each boundary condition: its edge lengths summed from the
+     * smallest up (reading: a numbering-independent order). */
+    for (int b = 0; b < nbc; b++) {
+        int64_t cnt = 0;
+        for (int64_t e = 0; e < m->ne; e++) cnt += (s->ebc[e] == b);
+        double *ls = malloc(sizeof(double) * (cnt > 0 ? cnt : 1));
+        if (!ls) { seterr(err, elen, "out of memory"); goto fail; }
+        int64_t k = 0;
+        for (int64_t e = 0; e < m->ne; e++)
+            if (s->ebc[e] == b) ls[k++] = m->elen[e];
+        qsort(ls, (size_t)cnt, sizeof(double), cmp_double);
+        double L = 0.0;
+        for (k = 0; k < cnt; k++) L += ls[k];
+        s->bc[b].length = L;
+        free(ls);
     }
     return s;
 fail:

@@ -329,6 +329,7 @@ swe_status swe_state_init(const swe_mesh *m, const swe_params *params, const dou
     }
     const int nslots = (int)M.slot_tag.size();
     std::vector<int> kbc((size_t)std::max(nslots, 1), BC_WALL);
+    std::vector<std::vector<double>> lens((size_t)std::max(n_bc, 1));
     for (int s = 0; s < nslots; s++) {
         const int32_t tg = M.slot_tag[s];
         if (tg < 0) continue;
@@ -336,11 +337,19 @@ swe_status swe_state_init(const swe_mesh *m, const swe_params *params, const dou
             if (bcs[b].tag != tg) continue;
             if (bcs[b].kind == SWE_BC_WALL) break;
             kbc[s] = bcs[b].kind | (b << 4);
-            hb[b].length += M.slot_len[s];
+            lens[b].push_back(M.slot_len[s]);
             if (bcs[b].kind == SWE_BC_INFLOW_UNIFORM && !(gn2[M.slot_cell[s]] > 0))
                 return fail(SWE_EINVAL, "inflow edge next to a cell with Manning n = 0");
             break;
         }
+    }
+    // boundary length: edge lengths summed in ascending order, so the value
+    // does not depend on how cells or edges are numbered
+    for (int b = 0; b < n_bc; b++) {
+        std::sort(lens[b].begin(), lens[b].end());
+        double L = 0.0;
+        for (double x : lens[b]) L += x;
+        hb[b].length = L;
     }
 
     std::unique_ptr<swe_state> S(new (std::nothrow) swe_state());
@@ -389,7 +398,7 @@ swe_status swe_state_init(const swe_mesh *m, const swe_params *params, const dou
             u[p].w = T(M.zb[p]);
             g1[p].x = T(M.lx[3 * p + 2]);
             g1[p].y = T(M.ly[3 * p + 2]);
-            g1[p].z = T(1.0 / M.area[p]);
+            g1[p].z = T(M.area[p]);
             g1[p].w = T(gn2[p]);
         }
         HIP_TRY(hipMemcpyAsync(S->U0, u.data(), u.size() * sizeof(V4<T>), hipMemcpyHostToDevice, s));
@@ -725,6 +734,9 @@ struct swe_batch {
             (void)hipGraphExecDestroy(gexec);
             gexec = nullptr;
         }
+        g_k = k;
+        dirty = false;
+        if (ntiles == 0) return SWE_OK;  // nothing to run
         if (!cap) HIP_TRY(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
         hipGraph_t gr = nullptr;
         HIP_TRY(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
@@ -740,9 +752,10 @@ struct swe_batch {
         HIP_TRY(hipStreamEndCapture(cap, &gr));
         hipError_t e = hipGraphInstantiate(&gexec, gr, nullptr, nullptr, 0);
         (void)hipGraphDestroy(gr);
-        if (e != hipSuccess) return fail(SWE_EDEVICE, std::string("batch graph: ") + hipGetErrorString(e));
-        g_k = k;
-        dirty = false;
+        if (e != hipSuccess) {
+            dirty = true;
+            return fail(SWE_EDEVICE, std::string("batch graph: ") + hipGetErrorString(e));
+        }
         return SWE_OK;
     }
 };
@@ -820,7 +833,7 @@ swe_status swe_batch_launch(swe_batch *b, int32_t k) {
         swe_status st = b->rebuild(k);
         if (st) return st;
     }
-    if (b->ntiles > 0) HIP_TRY(hipGraphLaunch(b->gexec, b->stream()));
+    if (b->ntiles > 0 && b->gexec) HIP_TRY(hipGraphLaunch(b->gexec, b->stream()));
     return SWE_OK;
 }
 

@@ -37,11 +37,21 @@ template <typename T> __device__ __forceinline__ T pow73(T h);
 template <> __device__ __forceinline__ double pow73<double>(double h) { return pow(h, 7.0 / 3.0); }
 template <> __device__ __forceinline__ float pow73<float>(float h) { return exp2f((7.0f / 3.0f) * log2f(h)); }
 
+// Division and square root.  FP64 uses IEEE-correct operations so that every
+// wet/dry decision matches an FP64 reference bit for bit; FP32 uses the
+// hardware reciprocal and square root (about 1 ulp), which is far inside the
+// single-precision error budget of the method.
+__device__ __forceinline__ double qdiv(double a, double b) { return a / b; }
+__device__ __forceinline__ float qdiv(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
+__device__ __forceinline__ double qsqrt(double a) { return sqrt(a); }
+__device__ __forceinline__ float qsqrt(float a) { return __builtin_amdgcn_sqrtf(a); }
+
 // HLLC flux (Toro 1994) in the frame of the edge normal, for reconstructed
-// depths hL, hR >= 0.  Wave speeds: two-rarefaction estimate when both sides
-// are wet (with c* >= 0), dry-bed speeds u -+ 2c when one side is dry.  The
-// star states are h_K (S_K - u_K)/(S_K - S*) (1, S*, ut_K); the tangential
-// component is the mass flux times the upwind tangential velocity.
+// depths hL, hR >= 0.  Wave speeds: two-rarefaction estimates with c* >= 0
+// when both sides are wet, dry-bed speeds u -+ 2c when one side is dry.  The
+// contact speed S* and the star states h_K (S_K - u_K)/(S_K - S*) (1, S*, ut_K)
+// are evaluated only for the selected region.  Identical states return the
+// physical flux (consistency) and two dry sides return zero.
 template <typename T>
 __device__ __forceinline__ void hllc(T hL, T unL, T utL, T hR, T unR, T utR, T g, T &F0, T &F1, T &F2) {
     const T zero = T(0), half = T(0.5);
@@ -49,14 +59,13 @@ __device__ __forceinline__ void hllc(T hL, T unL, T utL, T hR, T unR, T utR, T g
         F0 = zero; F1 = zero; F2 = zero;
         return;
     }
-    if (hL == hR && unL == unR && utL == utR) {  // consistency: F(U, U) = F(U)
-        T m = hL * unL;
-        F0 = m;
-        F1 = m * unL + half * g * hL * hL;
-        F2 = m * utL;
+    if (hL == hR && unL == unR && utL == utR) {
+        F0 = hL * unL;
+        F1 = hL * unL * unL + half * g * hL * hL;
+        F2 = hL * unL * utL;
         return;
     }
-    T cL = sqrt(g * hL), cR = sqrt(g * hR);
+    const T cL = qsqrt(g * hL), cR = qsqrt(g * hR);
     T SL, SR;
     if (!(hL > zero)) {
         SL = unR - T(2) * cR;
@@ -65,37 +74,35 @@ __device__ __forceinline__ void hllc(T hL, T unL, T utL, T hR, T unR, T utR, T g
         SL = unL - cL;
         SR = unL + T(2) * cL;
     } else {
-        T a = half * (cL + cR) + T(0.25) * (unL - unR);
-        T us = half * (unL + unR) + cL - cR;
-        T cs = a > zero ? a : zero;
+        const T a = half * (cL + cR) + T(0.25) * (unL - unR);
+        const T us = half * (unL + unR) + cL - cR;
+        const T cs = a > zero ? a : zero;
         SL = fmin(unL - cL, us - cs);
         SR = fmax(unR + cR, us + cs);
     }
     if (zero <= SL) {
-        T m = hL * unL;
-        F0 = m; F1 = m * unL + half * g * hL * hL; F2 = m * utL;
+        F0 = hL * unL;
+        F1 = hL * unL * unL + half * g * hL * hL;
+        F2 = hL * unL * utL;
         return;
     }
     if (SR <= zero) {
-        T m = hR * unR;
-        F0 = m; F1 = m * unR + half * g * hR * hR; F2 = m * utR;
+        F0 = hR * unR;
+        F1 = hR * unR * unR + half * g * hR * hR;
+        F2 = hR * unR * utR;
         return;
     }
-    T dL = hL * (unL - SL);  // >= 0
-    T dR = hR * (unR - SR);  // <= 0
-    T Ss = (SL * dR - SR * dL) / (dR - dL);
+    const T Ss = qdiv(SL * hR * (unR - SR) - SR * hL * (unL - SL), hR * (unR - SR) - hL * (unL - SL));
     if (zero <= Ss) {
-        T m = hL * unL;
-        T hs = hL * (SL - unL) / (SL - Ss);
-        F0 = m + SL * (hs - hL);
-        F1 = m * unL + half * g * hL * hL + SL * (hs * Ss - m);
-        F2 = F0 * utL;
+        const T f = qdiv(hL * (SL - unL), SL - Ss);
+        F0 = hL * unL + SL * (f - hL);
+        F1 = hL * unL * unL + half * g * hL * hL + SL * (f * Ss - hL * unL);
+        F2 = hL * unL * utL + SL * (f * utL - hL * utL);
     } else {
-        T m = hR * unR;
-        T hs = hR * (SR - unR) / (SR - Ss);
-        F0 = m + SR * (hs - hR);
-        F1 = m * unR + half * g * hR * hR + SR * (hs * Ss - m);
-        F2 = F0 * utR;
+        const T f = qdiv(hR * (SR - unR), SR - Ss);
+        F0 = hR * unR + SR * (f - hR);
+        F1 = hR * unR * unR + half * g * hR * hR + SR * (f * Ss - hR * unR);
+        F2 = hR * unR * utR + SR * (f * utR - hR * utR);
     }
 }
 
@@ -134,6 +141,30 @@ __device__ __forceinline__ void neumaier(double &s, double &c, double v) {
     s = t;
 }
 
+// rho_k / lambda_k of one edge (eq. CFL_condition: rho is twice the
+// centroid-edge distance, 4|cell| / (3 l)).  FP64 evaluates it exactly as
+// written, edge by edge; FP32 folds the three edges into one division.
+template <typename T> struct CflMin;
+template <> struct CflMin<double> {
+    double best = INFINITY;
+    double area;
+    __device__ explicit CflMin(double a) : area(a) {}
+    __device__ void add(double l, double lam) {
+        const double r = 4.0 * area / (3.0 * l) / lam;
+        best = r < best ? r : best;
+    }
+    __device__ double value() const { return best; }
+};
+template <> struct CflMin<float> {
+    float lmax = 0.0f;
+    float area;
+    __device__ explicit CflMin(float a) : area(a) {}
+    __device__ void add(double l, double lam) { lmax = fmaxf(lmax, float(l * lam)); }
+    __device__ double value() const {
+        return lmax > 0.0f ? 4.0 * double(area) / (3.0 * double(lmax)) : INFINITY;
+    }
+};
+
 // Updates cell i from U[cur] into U[cur ^ 1] and returns the CFL candidate
 // min_k rho_k / lambda_k of the new state (+inf when nothing constrains it).
 template <typename T>
@@ -149,23 +180,26 @@ __device__ __forceinline__ double cell_update(const Inst<T> &I, int i, int cur, 
     const int nb[3] = {I.nbr[i], I.nbr[I.n + i], I.nbr[2 * I.n + i]};
     const T lx[3] = {g0.x, g0.z, g1.x};
     const T ly[3] = {g0.y, g0.w, g1.y};
-    const T inv_area = g1.z, gn2 = g1.w;
+    const T area = g1.z, gn2 = g1.w;
 
+    // primitive variables: velocity only above the minimum depth
     const double hsd = double(s.x) - double(s.w);
     const T hs = T(hsd);
     const bool wet = hsd > h_min;
-    const T u = wet ? s.y / hs : T(0);
-    const T v = wet ? s.z / hs : T(0);
+    const T u = wet ? qdiv(s.y, hs) : T(0);
+    const T v = wet ? qdiv(s.z, hs) : T(0);
 
     T R0 = T(0), R1 = T(0), R2 = T(0);
     T el[3], enx[3], eny[3];
-    bool inflow_edge[3] = {false, false, false};
-    int bc_of[3] = {0, 0, 0};
+    int inflow_bc[3] = {-1, -1, -1};
 #pragma unroll
     for (int k = 0; k < 3; k++) {
-        const T l = sqrt(lx[k] * lx[k] + ly[k] * ly[k]);
-        const T nx = lx[k] / l, ny = ly[k] / l;
-        el[k] = l; enx[k] = nx; eny[k] = ny;
+        const T l = qsqrt(lx[k] * lx[k] + ly[k] * ly[k]);
+        const T nx = qdiv(lx[k], l), ny = qdiv(ly[k], l);
+        el[k] = l;
+        enx[k] = nx;
+        eny[k] = ny;
+        // this cell's velocity in the frame (n, t), t = (-ny, nx)
         const T uns = u * nx + v * ny;
         const T uts = v * nx - u * ny;
         const int e = nb[k];
@@ -177,8 +211,8 @@ __device__ __forceinline__ double cell_update(const Inst<T> &I, int i, int cur, 
             const double hod = double(o.x) - double(o.w);
             const T ho = T(hod);
             const bool owet = hod > h_min;
-            const T uo = owet ? o.y / ho : T(0);
-            const T vo = owet ? o.z / ho : T(0);
+            const T uo = owet ? qdiv(o.y, ho) : T(0);
+            const T vo = owet ? qdiv(o.z, ho) : T(0);
             const T uno = uo * nx + vo * ny;
             const T uto = vo * nx - uo * ny;
             // hydrostatic reconstruction of the two modified states
@@ -186,7 +220,8 @@ __device__ __forceinline__ double cell_update(const Inst<T> &I, int i, int cur, 
             const double a = double(s.x) - zs, b = double(o.x) - zs;
             const T hs_s = a < H_DRY ? T(0) : T(a);
             const T hs_o = b < H_DRY ? T(0) : T(b);
-            // canonical orientation: left = smaller original index
+            // canonical orientation (left = smaller original index); the
+            // normal of the canonical frame is -n when this cell is the right
             const T hL = flip ? hs_o : hs_s, hR = flip ? hs_s : hs_o;
             const T unL = flip ? -uno : uns, utL = flip ? -uto : uts;
             const T unR = flip ? -uns : uno, utR = flip ? -uts : uto;
@@ -198,8 +233,8 @@ __device__ __forceinline__ double cell_update(const Inst<T> &I, int i, int cur, 
             const int kb = I.slot_kbc[slot];
             const int kind = kb & 15;
             const int bi = kb >> 4;
-            const double a = hsd;  // the ghost shares this cell's bed: z* = z
-            const T hs_s = a < H_DRY ? T(0) : T(a);
+            // the ghost shares this cell's bed, so z* = z and h* = H - z
+            const T hs_s = hsd < H_DRY ? T(0) : T(hsd);
             double hg, ung;
             bool open = false;
             if (kind == BC_OUTFLOW) {
@@ -212,11 +247,11 @@ __device__ __forceinline__ double cell_update(const Inst<T> &I, int i, int cur, 
                 hllc<T>(hs_s, uns, uts, hs_g, T(ung), T(0), g, F0, F1, F2);
                 open = true;
             } else {
-                // reflective, impermeable wall
+                // reflective, impermeable wall: mirrored normal velocity
                 hllc<T>(hs_s, uns, uts, hs_s, -uns, uts, g, F0, F1, F2);
                 F0 = T(0);
             }
-            if (kind == BC_INFLOW) { inflow_edge[k] = true; bc_of[k] = bi; }
+            if (kind == BC_INFLOW) inflow_bc[k] = bi;
             if (open) {
                 double *acc = I.slot_acc + 2 * slot;
                 double sm = acc[0], cp = acc[1];
@@ -226,14 +261,16 @@ __device__ __forceinline__ double cell_update(const Inst<T> &I, int i, int cur, 
             }
             hself = hs_s;
         }
-        // fluctuation of this side: flux minus its own reconstructed pressure
+        // fluctuation of this side: the flux minus its own reconstructed
+        // pressure (bed slope in well-balanced form), rotated back
         const T Dn = F1 - T(0.5) * g * hself * hself;
         R0 += l * F0;
         R1 += l * (Dn * nx - F2 * ny);
         R2 += l * (Dn * ny + F2 * nx);
     }
 
-    const T w = T(dt) * inv_area;
+    // conservative update (eq. hydrodynamicupdateformula)
+    const T w = T(dt) * qdiv(T(1), area);
     T Hn = s.x - w * R0;
     T qx = s.y - w * R1;
     T qy = s.z - w * R2;
@@ -242,8 +279,8 @@ __device__ __forceinline__ double cell_update(const Inst<T> &I, int i, int cur, 
     T f;
     if (hn > h_min) {
         if (gn2 > T(0)) {
-            const T qa = sqrt(qx * qx + qy * qy);
-            f = T(1) / (T(1) + T(dt) * gn2 * qa / pow73<T>(T(hn)));
+            const T qa = qsqrt(qx * qx + qy * qy);
+            f = qdiv(T(1), T(1) + qdiv(T(dt) * gn2 * qa, pow73<T>(T(hn))));
         } else {
             f = T(1);
         }
@@ -253,6 +290,7 @@ __device__ __forceinline__ double cell_update(const Inst<T> &I, int i, int cur, 
     qx = qx * f;
     qy = qy * f;
     if (hn < 0.0) {
+        // positivity: clip and account for the added volume
         atomicAdd(&I.ctrl->clipped, -hn * I.area[i]);
         atomicAdd(&I.ctrl->nclip, 1ull);
         if (I.neg_policy) atomicOr(&I.ctrl->flags, FLAG_NEGDEPTH);
@@ -263,34 +301,32 @@ __device__ __forceinline__ double cell_update(const Inst<T> &I, int i, int cur, 
     if (!isfinite(Hn) || !isfinite(qx) || !isfinite(qy)) atomicOr(&I.ctrl->flags, FLAG_NONFINITE);
     dst[i] = make4<T>(Hn, qx, qy, s.w);
 
-    // CFL candidate of the new state: rho_k / lambda_k with
-    // rho_k = 4 |cell| / (3 l_k) (twice the centroid-edge distance)
+    // CFL candidate of the new state over wet cells and inflow ghosts
+    CflMin<T> cfl(area);
     const double h2 = double(Hn) - double(s.w);
-    T lmax = T(0);
     if (h2 > h_min) {
         const T hh = T(h2);
-        const T u2 = qx / hh, v2 = qy / hh;
-        const T c = sqrt(g * hh);
+        const T u2 = qdiv(qx, hh), v2 = qdiv(qy, hh);
+        const T c = qsqrt(g * hh);
 #pragma unroll
         for (int k = 0; k < 3; k++) {
             const T lam = fabs(u2 * enx[k] + v2 * eny[k]) + c;
-            lmax = fmax(lmax, el[k] * lam);
+            cfl.add(double(el[k]), double(lam));
         }
     }
 #pragma unroll
     for (int k = 0; k < 3; k++) {
-        if (inflow_edge[k]) {
+        if (inflow_bc[k] >= 0) {
             double hg, ung;
-            if (inflow_ghost(I.bcs[bc_of[k]], t_next, double(gn2), double(g), hg, ung)) {
-                const double lam = fabs(ung) + sqrt(double(g) * hg);
-                lmax = fmax(lmax, T(double(el[k]) * lam));
-            }
+            if (inflow_ghost(I.bcs[inflow_bc[k]], t_next, double(gn2), double(g), hg, ung))
+                cfl.add(double(el[k]), fabs(ung) + sqrt(double(g) * hg));
         }
     }
-    return lmax > T(0) ? (4.0 / 3.0) / (double(inv_area) * double(lmax)) : INFINITY;
+    return cfl.value();
 }
 
-// CFL candidate of the current state (first step after an initialisation).
+// CFL candidate of the current state (first step after an initialisation);
+// the same arithmetic as the epilogue of cell_update.
 template <typename T>
 __device__ __forceinline__ double cell_candidate(const Inst<T> &I, int i, int cur, double t) {
     const V4<T> *__restrict__ src = cur ? I.U1 : I.U0;
@@ -301,27 +337,27 @@ __device__ __forceinline__ double cell_candidate(const Inst<T> &I, int i, int cu
     const int nb[3] = {I.nbr[i], I.nbr[I.n + i], I.nbr[2 * I.n + i]};
     const T lx[3] = {g0.x, g0.z, g1.x};
     const T ly[3] = {g0.y, g0.w, g1.y};
+    CflMin<T> cfl(g1.z);
     const double hd = double(s.x) - double(s.w);
-    T lmax = T(0);
+    const T hh = T(hd);
+    const bool wet = hd > I.h_min;
+    const T u = wet ? qdiv(s.y, hh) : T(0), v = wet ? qdiv(s.z, hh) : T(0);
+    const T c = wet ? qsqrt(g * hh) : T(0);
 #pragma unroll
     for (int k = 0; k < 3; k++) {
-        const T l = sqrt(lx[k] * lx[k] + ly[k] * ly[k]);
-        if (hd > I.h_min) {
-            const T hh = T(hd);
-            const T u = s.y / hh, v = s.z / hh;
-            const T lam = fabs(u * (lx[k] / l) + v * (ly[k] / l)) + sqrt(g * hh);
-            lmax = fmax(lmax, l * lam);
+        const T l = qsqrt(lx[k] * lx[k] + ly[k] * ly[k]);
+        if (wet) {
+            const T lam = fabs(u * qdiv(lx[k], l) + v * qdiv(ly[k], l)) + c;
+            cfl.add(double(l), double(lam));
         }
         if (nb[k] < 0) {
             const int kb = I.slot_kbc[-1 - nb[k]];
             double hg, ung;
-            if ((kb & 15) == BC_INFLOW && inflow_ghost(I.bcs[kb >> 4], t, double(g1.w), double(g), hg, ung)) {
-                const double lam = fabs(ung) + sqrt(double(g) * hg);
-                lmax = fmax(lmax, T(double(l) * lam));
-            }
+            if ((kb & 15) == BC_INFLOW && inflow_ghost(I.bcs[kb >> 4], t, double(g1.w), double(g), hg, ung))
+                cfl.add(double(l), fabs(ung) + sqrt(double(g) * hg));
         }
     }
-    return lmax > T(0) ? (4.0 / 3.0) / (double(g1.z) * double(lmax)) : INFINITY;
+    return cfl.value();
 }
 
 __device__ __forceinline__ double wave_min(double v) {
@@ -410,7 +446,7 @@ __global__ void __launch_bounds__(256) k_dt_init(Inst<T> I) {
 // pairs; each member keeps its own control block, so members step with their
 // own dt and finished members cost one control-block read per tile.
 template <typename T, int CPT>
-__global__ void __launch_bounds__(1024) k_step_batched(const Inst<T> *__restrict__ insts,
+__global__ void __launch_bounds__(256) k_step_batched(const Inst<T> *__restrict__ insts,
                                                         const int2 *__restrict__ tiles, int ntiles) {
     for (int tt = blockIdx.x; tt < ntiles; tt += gridDim.x) {
         const int2 td = tiles[tt];

@@ -22,10 +22,14 @@ def valley_oracle(valley_wet):
 
 
 def test_fullsize_fp32_three_steps(valley_wet, valley_oracle):
+    # FP32 and FP64 states can take different CFL steps (a thin film on one
+    # side of the minimum depth changes the global minimum), so the FP32
+    # comparison runs with the step fixed just below the CFL limit
     from paper_2102_12862_amd import swe
-    sc = valley_wet
+    sc = S.Scenario(**{**valley_wet.__dict__})
     assert sc.n_cells > 3_900_000
-    st = gpu_state(sc, swe.FP32)
+    sc.dt_max = 0.5 * oracle.Sim(sc, mesh=valley_oracle).next_dt()
+    st = gpu_state(sc, swe.FP32, block_size=1024, cells_per_thread=2)
     sim = oracle.Sim(sc, mesh=valley_oracle)
     for _ in range(3):
         st.step()

@@ -70,6 +70,23 @@ def test_dam_break_fp64_to_t_end(swe):
     assert abs(m["mass"] - 550.0) <= 1e-12 * 550.0 and m["clipped"] == 0.0
 
 
+def fixed_dt(sc, frac=0.5):
+    """FP32 and FP64 states make different CFL steps, and one thin film
+    crossing the minimum depth changes the global step, so FP32 parity is
+    taken with the step fixed by dt_max below the CFL limit."""
+    sc = S.Scenario(**{**sc.__dict__})
+    sc.dt_max = frac * oracle.Sim(sc).next_dt()
+    return sc
+
+
+def fp32_conservation_bound(sc, steps):
+    # every update rounds H to FP32: at most one ulp of the surface per cell
+    # and step, times the cell area
+    geo = oracle.Mesh(sc.nodes, sc.tri).geometry()
+    Hmax = max(np.abs(geo["zb"]).max() + 10.0, 1.0)
+    return steps * float(np.spacing(np.float32(Hmax))) * geo["area"].sum()
+
+
 def test_ritter_dry_bed_fp64_and_fp32(swe):
     sc = S.dam_break(0.5, h_right=0.0)
     sim = oracle.Sim(sc)
@@ -77,15 +94,20 @@ def test_ritter_dry_bed_fp64_and_fp32(swe):
     st = gpu_state(sc, swe.FP64)
     st.run_until(5.0)
     compare(st, sim, FP64_TOL)
-    st32 = gpu_state(sc, swe.FP32)
-    st32.run_until(5.0)
-    compare(st32, sim, FP32_TOL)
+    sc32 = fixed_dt(sc)
+    sim32 = oracle.Sim(sc32)
+    sim32.run_until(2.0)
+    st32 = gpu_state(sc32, swe.FP32)
+    st32.run_until(2.0)
+    compare(st32, sim32, FP32_TOL)
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_valley_inflow_outflow_wet_dry(swe, prec):
     sc = S.valley_flood(n_cells=20000, scale=0.1, q_peak=200.0, t_rise=600.0)
     p = swe.FP64 if prec == "fp64" else swe.FP32
+    if prec == "fp32":
+        sc = fixed_dt(sc, 0.25)
     st = gpu_state(sc, p)
     sim = oracle.Sim(sc)
     t_end = 120.0
@@ -97,8 +119,22 @@ def test_valley_inflow_outflow_wet_dry(swe, prec):
     assert m["bnd_flux"] < 0
     assert abs(m["bnd_flux"] - d["bnd_flux"]) <= (1e-10 if prec == "fp64" else 1e-4) * abs(d["bnd_flux"])
     # conservation on the device itself
-    assert abs(m["mass"] + m["bnd_flux"] - m["clipped"]) <= 1e-9 * abs(m["bnd_flux"]) + 1e-6
-    print(prec, errs, m)
+    resid = abs(m["mass"] + m["bnd_flux"] - m["clipped"])
+    if prec == "fp64":
+        assert resid <= 1e-11 * abs(m["bnd_flux"])
+    else:
+        assert resid <= fp32_conservation_bound(sc, m["steps"])
+    print(prec, errs, m, resid)
+
+
+def test_cfl_step_fp32_matches_oracle_on_the_same_state(swe):
+    sc = S.valley_flood(n_cells=20000, scale=0.1, snapshot="wet")
+    st = gpu_state(sc, swe.FP32)
+    r = st.read()
+    # the oracle on the FP32-rounded state
+    sim = oracle.Sim(sc)
+    sim.set_state(r["H"], r["qx"], r["qy"], 0.0)
+    assert abs(st.step() - sim.next_dt()) <= 1e-5 * sim.next_dt()
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
@@ -164,14 +200,19 @@ def test_determinism_block_sizes_and_renumbering(swe):
 
 
 def test_restart_is_bitwise(swe):
+    # run(0 -> n2) equals run(0 -> n1) + read + re-init at t1 + run(n1 -> n2):
+    # the step is a function of the state and the time alone
     sc = S.valley_flood(n_cells=20000, scale=0.1, q_peak=300.0, t_rise=300.0)
     a = gpu_state(sc, swe.FP32)
-    a.run_until(60.0)
+    for _ in range(60):
+        a.step()
     b = gpu_state(sc, swe.FP32)
-    b.run_until(25.0)
+    for _ in range(25):
+        b.step()
     r = b.read()
     c = gpu_state(sc, swe.FP32, t0=r["t"], H0=r["H"], qx0=r["qx"], qy0=r["qy"])
-    c.run_until(60.0)
+    for _ in range(35):
+        c.step()
     ra, rc = a.read(), c.read()
     for f in ("H", "qx", "qy"):
         assert np.array_equal(ra[f], rc[f]), f

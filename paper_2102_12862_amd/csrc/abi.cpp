@@ -128,6 +128,7 @@ struct swe_state {
     BCdev *bcs = nullptr;
     double *hydro = nullptr;
     Ctrl *ctrl = nullptr;
+    Group *groups = nullptr;
     double2 *partials = nullptr;
     double *mass_out = nullptr;
     Ctrl *hctrl = nullptr;    // pinned host copy of the control block
@@ -144,7 +145,7 @@ struct swe_state {
         if (gexec) (void)hipGraphExecDestroy(gexec);
         if (cap) (void)hipStreamDestroy(cap);
         for (void *q : {U0, U1, geo1, (void *)slot_kbc, (void *)slot_acc, (void *)bcs, (void *)hydro, (void *)ctrl,
-                        (void *)partials, (void *)mass_out})
+                        (void *)groups, (void *)partials, (void *)mass_out})
             mem.release(q);
         if (hctrl) (void)hipHostFree(hctrl);
         if (hbuf) (void)hipHostFree(hbuf);
@@ -253,7 +254,8 @@ int64_t swe_state_footprint(const swe_mesh *m, int32_t precision) {
     if (!m) return 0;
     const int64_t n = m->H.nc, ns = (int64_t)m->H.slot_tag.size();
     const int64_t v4 = (int64_t)vec4_bytes(precision);
-    const int64_t state = 3 * n * v4 + ns * (4 + 16) + (int64_t)sizeof(Ctrl) + MASS_BLOCKS * 16 + 4096;
+    const int64_t state = 3 * n * v4 + ns * (4 + 16) + (int64_t)sizeof(Ctrl) + (int64_t)sizeof(Group) * NGROUPS +
+                          MASS_BLOCKS * 16 + 4096;
     const int64_t geom = n * (v4 + 12 + 8);
     return state + geom;
 }
@@ -374,10 +376,11 @@ swe_status swe_state_init(const swe_mesh *m, const swe_params *params, const dou
     S->bcs = (BCdev *)S->mem.alloc(sizeof(BCdev) * std::max(n_bc, 1));
     S->hydro = (double *)S->mem.alloc(sizeof(double) * std::max<size_t>(hydro.size(), 1));
     S->ctrl = (Ctrl *)S->mem.alloc(sizeof(Ctrl));
+    S->groups = (Group *)S->mem.alloc(sizeof(Group) * NGROUPS);
     S->partials = (double2 *)S->mem.alloc(sizeof(double2) * MASS_BLOCKS);
     S->mass_out = (double *)S->mem.alloc(2 * sizeof(double));
     if (!S->U0 || !S->U1 || !S->geo1 || !S->slot_kbc || !S->slot_acc || !S->bcs || !S->hydro || !S->ctrl ||
-        !S->partials || !S->mass_out)
+        !S->groups || !S->partials || !S->mass_out)
         return fail(SWE_ENOMEM, "device allocation failed (state)");
     HIP_TRY(hipHostMalloc((void **)&S->hctrl, sizeof(Ctrl), hipHostMallocDefault));
     HIP_TRY(hipHostMalloc((void **)&S->hbuf, 64, hipHostMallocDefault));
@@ -423,6 +426,13 @@ swe_status swe_state_init(const swe_mesh *m, const swe_params *params, const dou
     c.next_min = INF_BITS;
     *S->hctrl = c;
     HIP_TRY(hipMemcpyAsync(S->ctrl, S->hctrl, sizeof(Ctrl), hipMemcpyHostToDevice, s));
+    {
+        std::vector<Group> gz(NGROUPS);
+        std::memset(gz.data(), 0, sizeof(Group) * NGROUPS);
+        for (auto &g : gz) g.min_bits = INF_BITS;
+        HIP_TRY(hipMemcpyAsync(S->groups, gz.data(), sizeof(Group) * NGROUPS, hipMemcpyHostToDevice, s));
+        HIP_TRY(hipStreamSynchronize(s));
+    }
 
     auto fill_inst = [&](auto &I, auto tag) {
         using T = decltype(tag);
@@ -436,6 +446,7 @@ swe_status swe_state_init(const swe_mesh *m, const swe_params *params, const dou
         I.bcs = S->bcs;
         I.area = m->geom[prec].area;
         I.ctrl = S->ctrl;
+        I.groups = S->groups;
         I.n = (int)n;
         I.ntiles = 0;
         I.g = P.g;

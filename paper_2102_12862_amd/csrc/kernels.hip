@@ -366,10 +366,18 @@ __device__ __forceinline__ double wave_min(double v) {
     return v;
 }
 
-// Block min -> one atomic min per block -> the last block to arrive
-// publishes the minimum and (when advancing) moves time and the buffer index.
-__device__ __forceinline__ void block_finish(Ctrl *ctrl, double cand, unsigned nblocks, bool advance,
-                                             double t_next, double dt, int cur) {
+__device__ __forceinline__ unsigned long long load_agent(const unsigned long long *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Block min -> its arrival group -> the control block.  A block lowers its
+// group's minimum only when it improves on it, then counts itself in; the
+// last block of a group forwards the group minimum the same way; the last
+// group publishes the minimum and (when advancing) moves time and the buffer
+// index, so the next step needs no host round trip.
+__device__ __forceinline__ void block_finish(Ctrl *ctrl, Group *groups, double cand, unsigned nblocks,
+                                             unsigned block_id, bool advance, double t_next, double dt,
+                                             int cur) {
     __shared__ double wmin[16];
     cand = wave_min(cand);
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -379,21 +387,32 @@ __device__ __forceinline__ void block_finish(Ctrl *ctrl, double cand, unsigned n
         double m = wmin[0];
         const int nw = (blockDim.x + 63) >> 6;
         for (int k = 1; k < nw; k++) m = fmin(m, wmin[k]);
-        atomicMin(&ctrl->next_min, (unsigned long long)__double_as_longlong(m));
+        const unsigned long long mb = (unsigned long long)__double_as_longlong(m);
+        const unsigned gid = block_id % NGROUPS;
+        const unsigned ngroups = nblocks < NGROUPS ? nblocks : NGROUPS;
+        const unsigned members = nblocks / NGROUPS + (gid < nblocks % NGROUPS ? 1u : 0u);
+        Group *gr = groups + gid;
+        if (mb < load_agent(&gr->min_bits)) atomicMin(&gr->min_bits, mb);
         __threadfence();
-        const unsigned ticket = atomicAdd(&ctrl->arrive, 1u);
-        if (ticket == nblocks - 1) {
+        if (atomicAdd(&gr->count, 1u) == members - 1) {
             __threadfence();
-            const unsigned long long bits =
-                __hip_atomic_load(&ctrl->next_min, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            ctrl->rawmin = __longlong_as_double((long long)bits);
-            ctrl->next_min = INF_BITS;
-            ctrl->arrive = 0u;
-            if (advance) {
-                ctrl->t = t_next;
-                ctrl->dt_last = dt;
-                ctrl->cur = cur ^ 1;
-                ctrl->steps = ctrl->steps + 1;
+            const unsigned long long gm = load_agent(&gr->min_bits);
+            __hip_atomic_store(&gr->min_bits, INF_BITS, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&gr->count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (gm < load_agent(&ctrl->next_min)) atomicMin(&ctrl->next_min, gm);
+            __threadfence();
+            if (atomicAdd(&ctrl->arrive, 1u) == ngroups - 1) {
+                __threadfence();
+                const unsigned long long bits = load_agent(&ctrl->next_min);
+                ctrl->rawmin = __longlong_as_double((long long)bits);
+                ctrl->next_min = INF_BITS;
+                ctrl->arrive = 0u;
+                if (advance) {
+                    ctrl->t = t_next;
+                    ctrl->dt_last = dt;
+                    ctrl->cur = cur ^ 1;
+                    ctrl->steps = ctrl->steps + 1;
+                }
             }
         }
     }
@@ -428,7 +447,7 @@ __global__ void __launch_bounds__(1024) k_step(Inst<T> I) {
         const int i = (blockIdx.x * CPT + r) * blockDim.x + threadIdx.x;
         if (i < I.n) cand = fmin(cand, cell_update<T>(I, i, cur, t, dt, t_next));
     }
-    block_finish(I.ctrl, cand, gridDim.x, true, t_next, dt, cur);
+    block_finish(I.ctrl, I.groups, cand, gridDim.x, blockIdx.x, true, t_next, dt, cur);
 }
 
 template <typename T>
@@ -439,7 +458,7 @@ __global__ void __launch_bounds__(256) k_dt_init(Inst<T> I) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     double cand = INFINITY;
     if (i < I.n) cand = cell_candidate<T>(I, i, cur, t);
-    block_finish(I.ctrl, cand, gridDim.x, false, 0.0, 0.0, cur);
+    block_finish(I.ctrl, I.groups, cand, gridDim.x, blockIdx.x, false, 0.0, 0.0, cur);
 }
 
 // Persistent batched step: blocks stride over a list of (member, tile)
@@ -461,7 +480,7 @@ __global__ void __launch_bounds__(256) k_step_batched(const Inst<T> *__restrict_
             const int i = (td.y * CPT + r) * blockDim.x + threadIdx.x;
             if (i < I.n) cand = fmin(cand, cell_update<T>(I, i, cur, t, dt, t_next));
         }
-        block_finish(I.ctrl, cand, (unsigned)I.ntiles, true, t_next, dt, cur);
+        block_finish(I.ctrl, I.groups, cand, (unsigned)I.ntiles, (unsigned)td.y, true, t_next, dt, cur);
     }
 }
 

@@ -61,6 +61,18 @@ static_assert(sizeof(Ctrl) == 128, "Ctrl layout");
 
 constexpr unsigned long long INF_BITS = 0x7FF0000000000000ull;
 
+// Arrival groups of the grid-wide step reduction: block b reports to group
+// b % NGROUPS (one cache line each), the last block of a group reports to
+// the control block.  Spreading the per-block atomics over many lines keeps
+// them from serialising on one address.
+constexpr int NGROUPS = 64;
+struct alignas(128) Group {
+    unsigned long long min_bits;
+    unsigned int count;
+    unsigned int pad[29];
+};
+static_assert(sizeof(Group) == 128, "Group layout");
+
 // Everything one kernel needs about one state.
 template <typename T> struct Inst {
     V4<T> *U0;
@@ -73,6 +85,7 @@ template <typename T> struct Inst {
     const BCdev *bcs;
     const double *area;    // |cell|, for clip volume and mass
     Ctrl *ctrl;
+    Group *groups;         // NGROUPS arrival groups of this state
     int n;
     int ntiles;            // blocks of one step (batched kernel)
     double g, cfl, h_min, dt_max;

@@ -128,36 +128,46 @@ struct swe_state {
     BCdev *bcs = nullptr;
     double *hydro = nullptr;
     Ctrl *ctrl = nullptr;
-    Group *groups = nullptr;
     double2 *partials = nullptr;
     double *mass_out = nullptr;
     Ctrl *hctrl = nullptr;    // pinned host copy of the control block
     double *hbuf = nullptr;   // pinned scratch (t_end, mass results)
     int nslots = 0;
     int block = 256, cpt = 1, spg = 32;
+    int phase = 0;  // step launches issued so far, mod 3 (selects the control slot)
     hipStream_t cap = nullptr;
-    hipGraphExec_t gexec = nullptr;
+    hipGraphExec_t gexec[3] = {nullptr, nullptr, nullptr};  // one per starting phase
     int g_k = 0, g_block = 0, g_cpt = 0;
     Inst<float> inst32{};
     Inst<double> inst64{};
 
     ~swe_state() {
-        if (gexec) (void)hipGraphExecDestroy(gexec);
+        drop_graphs();
         if (cap) (void)hipStreamDestroy(cap);
         for (void *q : {U0, U1, geo1, (void *)slot_kbc, (void *)slot_acc, (void *)bcs, (void *)hydro, (void *)ctrl,
-                        (void *)groups, (void *)partials, (void *)mass_out})
+                        (void *)partials, (void *)mass_out})
             mem.release(q);
         if (hctrl) (void)hipHostFree(hctrl);
         if (hbuf) (void)hipHostFree(hbuf);
     }
     hipStream_t stream() const { return mem.stream(); }
-
-    hipError_t launch_one() {
-        return prec == SWE_FP32 ? launch_step<float>(inst32, block, cpt, stream())
-                                : launch_step<double>(inst64, block, cpt, stream());
+    // the current time level as last read from the device
+    const CtrlSlot &lvl() const { return hctrl->s[phase]; }
+    void drop_graphs() {
+        for (auto &g : gexec)
+            if (g) {
+                (void)hipGraphExecDestroy(g);
+                g = nullptr;
+            }
     }
-    hipError_t launch_one_on(hipStream_t s) {
-        return prec == SWE_FP32 ? launch_step<float>(inst32, block, cpt, s) : launch_step<double>(inst64, block, cpt, s);
+    hipError_t launch_one_on(hipStream_t s, int ph) {
+        return prec == SWE_FP32 ? launch_step<float>(inst32, block, cpt, ph, s)
+                                : launch_step<double>(inst64, block, cpt, ph, s);
+    }
+    hipError_t launch_one() {
+        hipError_t e = launch_one_on(stream(), phase);
+        phase = (phase + 1) % 3;
+        return e;
     }
     swe_status set_t_end(double t_end) {
         hbuf[0] = t_end;
@@ -169,17 +179,15 @@ struct swe_state {
         HIP_TRY(hipStreamSynchronize(stream()));
         return SWE_OK;
     }
+    // k captured steps starting at the current phase
     swe_status graph(int k) {
-        if (gexec && g_k == k && g_block == block && g_cpt == cpt) return SWE_OK;
-        if (gexec) {
-            (void)hipGraphExecDestroy(gexec);
-            gexec = nullptr;
-        }
+        if (g_k != k || g_block != block || g_cpt != cpt) drop_graphs();
+        if (gexec[phase]) return SWE_OK;
         if (!cap) HIP_TRY(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
         hipGraph_t gr = nullptr;
         HIP_TRY(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
         for (int i = 0; i < k; i++) {
-            hipError_t e = launch_one_on(cap);
+            hipError_t e = launch_one_on(cap, (phase + i) % 3);
             if (e != hipSuccess) {
                 hipGraph_t dummy = nullptr;
                 (void)hipStreamEndCapture(cap, &dummy);
@@ -188,12 +196,35 @@ struct swe_state {
             }
         }
         HIP_TRY(hipStreamEndCapture(cap, &gr));
-        hipError_t e = hipGraphInstantiate(&gexec, gr, nullptr, nullptr, 0);
+        hipError_t e = hipGraphInstantiate(&gexec[phase], gr, nullptr, nullptr, 0);
         (void)hipGraphDestroy(gr);
         if (e != hipSuccess) return fail(SWE_EDEVICE, std::string("graph instantiate: ") + hipGetErrorString(e));
         g_k = k;
         g_block = block;
         g_cpt = cpt;
+        return SWE_OK;
+    }
+    swe_status launch_graph() {
+        swe_status st = graph(spg);
+        if (st) return st;
+        HIP_TRY(hipGraphLaunch(gexec[phase], stream()));
+        phase = (phase + spg) % 3;
+        return SWE_OK;
+    }
+    // moves the current level to control slot `to` (aligning with a batch)
+    swe_status realign(int to) {
+        if (to == phase) return SWE_OK;
+        swe_status st = read_ctrl();
+        if (st) return st;
+        Ctrl c = *hctrl;
+        c.s[to] = hctrl->s[phase];
+        c.m[to] = hctrl->m[phase];
+        c.m[(to + 1) % 3].bits = INF_BITS;
+        c.m[(to + 2) % 3].bits = INF_BITS;
+        *hctrl = c;
+        HIP_TRY(hipMemcpyAsync(ctrl, hctrl, sizeof(Ctrl), hipMemcpyHostToDevice, stream()));
+        HIP_TRY(hipStreamSynchronize(stream()));
+        phase = to;
         return SWE_OK;
     }
 };
@@ -254,8 +285,7 @@ int64_t swe_state_footprint(const swe_mesh *m, int32_t precision) {
     if (!m) return 0;
     const int64_t n = m->H.nc, ns = (int64_t)m->H.slot_tag.size();
     const int64_t v4 = (int64_t)vec4_bytes(precision);
-    const int64_t state = 3 * n * v4 + ns * (4 + 16) + (int64_t)sizeof(Ctrl) + (int64_t)sizeof(Group) * NGROUPS +
-                          MASS_BLOCKS * 16 + 4096;
+    const int64_t state = 3 * n * v4 + ns * (4 + 16) + (int64_t)sizeof(Ctrl) + MASS_BLOCKS * 16 + 4096;
     const int64_t geom = n * (v4 + 12 + 8);
     return state + geom;
 }
@@ -376,11 +406,10 @@ swe_status swe_state_init(const swe_mesh *m, const swe_params *params, const dou
     S->bcs = (BCdev *)S->mem.alloc(sizeof(BCdev) * std::max(n_bc, 1));
     S->hydro = (double *)S->mem.alloc(sizeof(double) * std::max<size_t>(hydro.size(), 1));
     S->ctrl = (Ctrl *)S->mem.alloc(sizeof(Ctrl));
-    S->groups = (Group *)S->mem.alloc(sizeof(Group) * NGROUPS);
     S->partials = (double2 *)S->mem.alloc(sizeof(double2) * MASS_BLOCKS);
     S->mass_out = (double *)S->mem.alloc(2 * sizeof(double));
     if (!S->U0 || !S->U1 || !S->geo1 || !S->slot_kbc || !S->slot_acc || !S->bcs || !S->hydro || !S->ctrl ||
-        !S->groups || !S->partials || !S->mass_out)
+        !S->partials || !S->mass_out)
         return fail(SWE_ENOMEM, "device allocation failed (state)");
     HIP_TRY(hipHostMalloc((void **)&S->hctrl, sizeof(Ctrl), hipHostMallocDefault));
     HIP_TRY(hipHostMalloc((void **)&S->hbuf, 64, hipHostMallocDefault));
@@ -420,19 +449,12 @@ swe_status swe_state_init(const swe_mesh *m, const swe_params *params, const dou
         HIP_TRY(hipMemcpyAsync(S->hydro, hydro.data(), sizeof(double) * hydro.size(), hipMemcpyHostToDevice, s));
     Ctrl c;
     std::memset(&c, 0, sizeof(c));
-    c.t = t0;
+    c.s[0].t = t0;
+    for (auto &mm : c.m) mm.bits = INF_BITS;
     c.t_end = std::numeric_limits<double>::infinity();
-    c.rawmin = std::numeric_limits<double>::infinity();
-    c.next_min = INF_BITS;
     *S->hctrl = c;
+    S->phase = 0;
     HIP_TRY(hipMemcpyAsync(S->ctrl, S->hctrl, sizeof(Ctrl), hipMemcpyHostToDevice, s));
-    {
-        std::vector<Group> gz(NGROUPS);
-        std::memset(gz.data(), 0, sizeof(Group) * NGROUPS);
-        for (auto &g : gz) g.min_bits = INF_BITS;
-        HIP_TRY(hipMemcpyAsync(S->groups, gz.data(), sizeof(Group) * NGROUPS, hipMemcpyHostToDevice, s));
-        HIP_TRY(hipStreamSynchronize(s));
-    }
 
     auto fill_inst = [&](auto &I, auto tag) {
         using T = decltype(tag);
@@ -446,7 +468,6 @@ swe_status swe_state_init(const swe_mesh *m, const swe_params *params, const dou
         I.bcs = S->bcs;
         I.area = m->geom[prec].area;
         I.ctrl = S->ctrl;
-        I.groups = S->groups;
         I.n = (int)n;
         I.ntiles = 0;
         I.g = P.g;
@@ -458,10 +479,10 @@ swe_status swe_state_init(const swe_mesh *m, const swe_params *params, const dou
     };
     if (prec == SWE_FP32) {
         fill_inst(S->inst32, float());
-        HIP_TRY(launch_dt_init<float>(S->inst32, s));
+        HIP_TRY(launch_dt_init<float>(S->inst32, S->phase, s));
     } else {
         fill_inst(S->inst64, double());
-        HIP_TRY(launch_dt_init<double>(S->inst64, s));
+        HIP_TRY(launch_dt_init<double>(S->inst64, S->phase, s));
     }
     st = S->read_ctrl();
     if (st) return st;
@@ -479,14 +500,14 @@ swe_status swe_step(swe_state *s, double *dt_taken) {
     if (!s) return fail(SWE_EINVAL, "state is NULL");
     swe_status st = s->set_t_end(std::numeric_limits<double>::infinity());
     if (st) return st;
-    const long long before = s->hctrl->steps;
+    const long long before = s->lvl().steps;
     HIP_TRY(s->launch_one());
     st = s->read_ctrl();
     if (st) return st;
     st = check_flags(s->hctrl->flags);
     if (st) return st;
-    if (s->hctrl->steps == before) return fail(SWE_ENODT, "step did not advance");
-    if (dt_taken) *dt_taken = s->hctrl->dt_last;
+    if (s->lvl().steps == before) return fail(SWE_ENODT, "step did not advance");
+    if (dt_taken) *dt_taken = s->lvl().dt;
     return SWE_OK;
 }
 
@@ -497,21 +518,20 @@ swe_status swe_run_until(swe_state *s, double t_end, int64_t *n_steps) {
     if (st) return st;
     st = s->read_ctrl();
     if (st) return st;
-    const long long start = s->hctrl->steps;
+    const long long start = s->lvl().steps;
     if (n_steps) *n_steps = 0;
     st = check_flags(s->hctrl->flags);
     if (st) return st;
-    st = s->graph(s->spg);
-    if (st) return st;
-    while (s->hctrl->t < t_end) {
-        const double t_before = s->hctrl->t;
-        HIP_TRY(hipGraphLaunch(s->gexec, s->stream()));
+    while (s->lvl().t < t_end) {
+        const double t_before = s->lvl().t;
+        st = s->launch_graph();
+        if (st) return st;
         st = s->read_ctrl();
         if (st) return st;
-        if (n_steps) *n_steps = s->hctrl->steps - start;
+        if (n_steps) *n_steps = s->lvl().steps - start;
         st = check_flags(s->hctrl->flags);
         if (st) return st;
-        if (!(s->hctrl->t > t_before)) return fail(SWE_ENODT, "time does not advance (step underflow)");
+        if (!(s->lvl().t > t_before)) return fail(SWE_ENODT, "time does not advance (step underflow)");
     }
     return SWE_OK;
 }
@@ -521,11 +541,10 @@ swe_status swe_launch_steps(swe_state *s, double t_end, int64_t k) {
     if (k < 0) return fail(SWE_EINVAL, "negative step count");
     swe_status st = s->set_t_end(t_end);
     if (st) return st;
-    st = s->graph(s->spg);
-    if (st) return st;
     int64_t left = k;
     while (left >= s->spg) {
-        HIP_TRY(hipGraphLaunch(s->gexec, s->stream()));
+        st = s->launch_graph();
+        if (st) return st;
         left -= s->spg;
     }
     for (; left > 0; left--) HIP_TRY(s->launch_one());
@@ -546,7 +565,7 @@ swe_status swe_state_read(const swe_state *cs, double *H, double *h, double *qx,
     if (st) return st;
     const HostMesh &M = s->m->H;
     const int64_t n = M.nc;
-    const void *src = s->hctrl->cur ? s->U1 : s->U0;
+    const void *src = s->lvl().cur ? s->U1 : s->U0;
     auto rd = [&](auto tag) -> swe_status {
         using T = decltype(tag);
         std::vector<V4<T>> u((size_t)n);
@@ -563,7 +582,7 @@ swe_status swe_state_read(const swe_state *cs, double *H, double *h, double *qx,
     };
     st = s->prec == SWE_FP32 ? rd(float()) : rd(double());
     if (st) return st;
-    if (t) *t = s->hctrl->t;
+    if (t) *t = s->lvl().t;
     return SWE_OK;
 }
 
@@ -571,16 +590,16 @@ swe_status swe_mass(const swe_state *cs, double *mass, double *bnd_flux, double 
     swe_state *s = const_cast<swe_state *>(cs);
     if (!s) return fail(SWE_EINVAL, "state is NULL");
     if (s->prec == SWE_FP32)
-        HIP_TRY(launch_mass<float>(s->inst32, s->partials, s->mass_out, s->nslots, s->stream()));
+        HIP_TRY(launch_mass<float>(s->inst32, s->partials, s->mass_out, s->nslots, s->phase, s->stream()));
     else
-        HIP_TRY(launch_mass<double>(s->inst64, s->partials, s->mass_out, s->nslots, s->stream()));
+        HIP_TRY(launch_mass<double>(s->inst64, s->partials, s->mass_out, s->nslots, s->phase, s->stream()));
     HIP_TRY(hipMemcpyAsync(s->hbuf + 1, s->mass_out, 2 * sizeof(double), hipMemcpyDeviceToHost, s->stream()));
     swe_status st = s->read_ctrl();
     if (st) return st;
     if (mass) *mass = s->hbuf[1];
     if (bnd_flux) *bnd_flux = s->hbuf[2];
     if (clipped) *clipped = s->hctrl->clipped;
-    if (steps) *steps = s->hctrl->steps;
+    if (steps) *steps = s->lvl().steps;
     return SWE_OK;
 }
 
@@ -590,6 +609,7 @@ swe_status swe_autotune(swe_state *s, int32_t k, int32_t *block_size, int32_t *c
     swe_status st = s->read_ctrl();
     if (st) return st;
     const Ctrl saved = *s->hctrl;
+    const int saved_phase = s->phase;
     const int64_t n = s->m->H.nc;
     const size_t ub = (size_t)n * vec4_bytes(s->prec);
     const size_t ab = 2 * sizeof(double) * std::max(s->nslots, 1);
@@ -600,7 +620,7 @@ swe_status swe_autotune(swe_state *s, int32_t k, int32_t *block_size, int32_t *c
         s->mem.release(keepA);
         return fail(SWE_ENOMEM, "device allocation failed (autotune)");
     }
-    void *cur = saved.cur ? s->U1 : s->U0;
+    void *cur = saved.s[saved_phase].cur ? s->U1 : s->U0;
     hipStream_t q = s->stream();
     hipEvent_t e0 = nullptr, e1 = nullptr;
     auto cleanup = [&]() {
@@ -611,6 +631,7 @@ swe_status swe_autotune(swe_state *s, int32_t k, int32_t *block_size, int32_t *c
     };
     auto restore = [&]() -> swe_status {
         *s->hctrl = saved;
+        s->phase = saved_phase;
         HIP_TRY(hipMemcpyAsync(cur, keepU, ub, hipMemcpyDeviceToDevice, q));
         HIP_TRY(hipMemcpyAsync(s->slot_acc, keepA, ab, hipMemcpyDeviceToDevice, q));
         HIP_TRY(hipMemcpyAsync(s->ctrl, s->hctrl, sizeof(Ctrl), hipMemcpyHostToDevice, q));
@@ -675,15 +696,23 @@ struct swe_batch {
     size_t tiles_cap = 0;
     int ntiles = 0;
     int block = 256, cpt = 1, grid = 0;
+    int phase = 0;  // launches so far mod 3; every member is aligned to it
     bool dirty = true;
     hipStream_t cap = nullptr;
-    hipGraphExec_t gexec = nullptr;
+    hipGraphExec_t gexec[3] = {nullptr, nullptr, nullptr};
     int g_k = 0;
     ~swe_batch() {
-        if (gexec) (void)hipGraphExecDestroy(gexec);
+        drop_graphs();
         if (cap) (void)hipStreamDestroy(cap);
         mem.release(insts);
         mem.release(tiles);
+    }
+    void drop_graphs() {
+        for (auto &g : gexec)
+            if (g) {
+                (void)hipGraphExecDestroy(g);
+                g = nullptr;
+            }
     }
     hipStream_t stream() const { return mem.stream(); }
     int64_t footprint() const {
@@ -692,13 +721,13 @@ struct swe_batch {
             if (s) f += swe_state_footprint(s->m, s->prec);
         return f;
     }
-    hipError_t launch(hipStream_t s) {
+    hipError_t launch(hipStream_t s, int ph) {
         return prec == SWE_FP32
-                   ? launch_step_batched<float>((const Inst<float> *)insts, tiles, ntiles, grid, block, cpt, s)
-                   : launch_step_batched<double>((const Inst<double> *)insts, tiles, ntiles, grid, block, cpt, s);
+                   ? launch_step_batched<float>((const Inst<float> *)insts, tiles, ntiles, grid, block, cpt, ph, s)
+                   : launch_step_batched<double>((const Inst<double> *)insts, tiles, ntiles, grid, block, cpt, ph, s);
     }
-    swe_status rebuild(int k) {
-        // work list of the members that are still running
+    // work list of the members that are still running
+    swe_status rebuild() {
         std::vector<Inst<float>> i32;
         std::vector<Inst<double>> i64;
         std::vector<int2> tl;
@@ -741,18 +770,22 @@ struct swe_batch {
         ntiles = (int)tl.size();
         grid = prec == SWE_FP32 ? batched_grid<float>(block, cpt) : batched_grid<double>(block, cpt);
         if (grid < 1) grid = 1;
-        if (gexec) {
-            (void)hipGraphExecDestroy(gexec);
-            gexec = nullptr;
-        }
-        g_k = k;
+        drop_graphs();
         dirty = false;
-        if (ntiles == 0) return SWE_OK;  // nothing to run
+        return SWE_OK;
+    }
+    // k persistent launches starting at the current phase, captured once
+    swe_status graph(int k) {
+        if (g_k != k) {
+            drop_graphs();
+            g_k = k;
+        }
+        if (gexec[phase] || ntiles == 0) return SWE_OK;
         if (!cap) HIP_TRY(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
         hipGraph_t gr = nullptr;
         HIP_TRY(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
         for (int i = 0; i < k; i++) {
-            hipError_t e = launch(cap);
+            hipError_t e = launch(cap, (phase + i) % 3);
             if (e != hipSuccess) {
                 hipGraph_t dummy = nullptr;
                 (void)hipStreamEndCapture(cap, &dummy);
@@ -761,12 +794,9 @@ struct swe_batch {
             }
         }
         HIP_TRY(hipStreamEndCapture(cap, &gr));
-        hipError_t e = hipGraphInstantiate(&gexec, gr, nullptr, nullptr, 0);
+        hipError_t e = hipGraphInstantiate(&gexec[phase], gr, nullptr, nullptr, 0);
         (void)hipGraphDestroy(gr);
-        if (e != hipSuccess) {
-            dirty = true;
-            return fail(SWE_EDEVICE, std::string("batch graph: ") + hipGetErrorString(e));
-        }
+        if (e != hipSuccess) return fail(SWE_EDEVICE, std::string("batch graph: ") + hipGetErrorString(e));
         return SWE_OK;
     }
 };
@@ -804,7 +834,9 @@ swe_status swe_batch_add(swe_batch *b, swe_state *s, double t_end, int32_t *slot
         if (x == s) return fail(SWE_EINVAL, "state already in the batch");
     const int64_t f = swe_state_footprint(s->m, s->prec);
     if (b->budget > 0 && b->footprint() + f > b->budget) return fail(SWE_EBUDGET, "batch footprint budget exceeded");
-    swe_status st = s->set_t_end(t_end);
+    swe_status st = s->realign(b->phase);
+    if (st) return st;
+    st = s->set_t_end(t_end);
     if (st) return st;
     st = s->read_ctrl();
     if (st) return st;
@@ -822,7 +854,7 @@ swe_status swe_batch_add(swe_batch *b, swe_state *s, double t_end, int32_t *slot
     }
     b->members[idx] = s;
     b->t_end[idx] = t_end;
-    b->finished[idx] = !(s->hctrl->t < t_end) || s->hctrl->flags != 0;
+    b->finished[idx] = !(s->lvl().t < t_end) || s->hctrl->flags != 0;
     b->dirty = true;
     if (slot) *slot = idx;
     return SWE_OK;
@@ -840,11 +872,18 @@ swe_status swe_batch_remove(swe_batch *b, int32_t slot) {
 
 swe_status swe_batch_launch(swe_batch *b, int32_t k) {
     if (!b || k < 1) return fail(SWE_EINVAL, "bad batch launch");
-    if (b->dirty || b->g_k != k) {
-        swe_status st = b->rebuild(k);
+    if (b->dirty) {
+        swe_status st = b->rebuild();
         if (st) return st;
     }
-    if (b->ntiles > 0 && b->gexec) HIP_TRY(hipGraphLaunch(b->gexec, b->stream()));
+    if (b->ntiles == 0) return SWE_OK;
+    swe_status st = b->graph(k);
+    if (st) return st;
+    HIP_TRY(hipGraphLaunch(b->gexec[b->phase], b->stream()));
+    b->phase = (b->phase + k) % 3;
+    // every member in the work list stepped (or carried its level) k times
+    for (size_t i = 0; i < b->members.size(); i++)
+        if (b->members[i] && !b->finished[i]) b->members[i]->phase = b->phase;
     return SWE_OK;
 }
 
@@ -861,7 +900,7 @@ swe_status swe_batch_step(swe_batch *b, int32_t k, int32_t *n_active) {
     for (size_t i = 0; i < b->members.size(); i++) {
         swe_state *s = b->members[i];
         if (!s) continue;
-        const bool done = !(s->hctrl->t < b->t_end[i]) || s->hctrl->flags != 0;
+        const bool done = !(s->lvl().t < b->t_end[i]) || s->hctrl->flags != 0;
         if (done && !b->finished[i]) {
             b->finished[i] = 1;
             b->dirty = true;
@@ -876,9 +915,10 @@ swe_status swe_batch_poll(swe_batch *b, int32_t slot, int32_t *done, int32_t *er
     if (!b || slot < 0 || slot >= (int32_t)b->members.size() || !b->members[slot])
         return fail(SWE_EINVAL, "no such batch member");
     swe_state *s = b->members[slot];
-    const Ctrl &c = *s->hctrl;
-    if (done) *done = !(c.t < b->t_end[slot]) || c.flags != 0;
-    if (error) *error = c.flags ? check_flags(c.flags) : 0;
+    const CtrlSlot &c = s->lvl();
+    const int flags = s->hctrl->flags;
+    if (done) *done = !(c.t < b->t_end[slot]) || flags != 0;
+    if (error) *error = flags ? check_flags(flags) : 0;
     if (t) *t = c.t;
     if (steps) *steps = c.steps;
     return SWE_OK;

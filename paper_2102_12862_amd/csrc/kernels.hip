@@ -369,16 +369,57 @@ __device__ __forceinline__ double wave_min(double v) {
 __device__ __forceinline__ unsigned long long load_agent(const unsigned long long *p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
+template <typename V> __device__ __forceinline__ void store_agent(V *p, V v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
 
-// Block min -> its arrival group -> the control block.  A block lowers its
-// group's minimum only when it improves on it, then counts itself in; the
-// last block of a group forwards the group minimum the same way; the last
-// group publishes the minimum and (when advancing) moves time and the buffer
-// index, so the next step needs no host round trip.
-__device__ __forceinline__ void block_finish(Ctrl *ctrl, Group *groups, double cand, unsigned nblocks,
-                                             unsigned block_id, bool advance, double t_next, double dt,
-                                             int cur) {
+// Time level of phase p as this step sees it.
+struct Level {
+    double t, dt, rawmin;
+    long long steps;
+    int cur;
+    bool run;
+};
+
+// Reads time level `phase` and decides this step's dt: min(CFL * min
+// rho/lambda, dt_max, t_end - t).  A finished or failed state does not step;
+// block `lead` then carries the level forward unchanged, so phases stay
+// aligned with the launch count.
+__device__ __forceinline__ Level step_setup(Ctrl *c, int phase, double cfl, double dt_max, bool lead) {
+    const int pin = phase, pout = phase == 2 ? 0 : phase + 1, pclr = phase == 0 ? 2 : phase - 1;
+    Level L;
+    L.t = c->s[pin].t;
+    L.steps = c->s[pin].steps;
+    L.cur = c->s[pin].cur;
+    L.rawmin = __longlong_as_double((long long)c->m[pin].bits);
+    L.dt = 0.0;
+    const double t_end = c->t_end;
+    L.run = L.t < t_end && c->flags == 0;
+    if (L.run) {
+        L.dt = fmin(fmin(cfl * L.rawmin, dt_max), t_end - L.t);
+        if (!(L.dt > 0.0) || !(L.dt < INFINITY)) {
+            L.run = false;
+            if (lead && threadIdx.x == 0) atomicOr(&c->flags, FLAG_NODT);
+        }
+    }
+    if (!L.run && lead && threadIdx.x == 0) {
+        store_agent(&c->s[pout].t, L.t);
+        store_agent(&c->s[pout].dt, c->s[pin].dt);
+        store_agent(&c->s[pout].steps, L.steps);
+        store_agent(&c->s[pout].cur, L.cur);
+        store_agent(&c->m[pout].bits, c->m[pin].bits);
+        store_agent(&c->m[pclr].bits, INF_BITS);
+    }
+    return L;
+}
+
+// Block minimum of the CFL candidates -> at most one atomic min on the next
+// level's slot (skipped when it cannot lower the running value); block `lead`
+// publishes the next time level and clears the slot two phases ahead.
+__device__ __forceinline__ void block_finish(Ctrl *c, int phase, double cand, const Level &L, bool lead,
+                                             bool advance) {
     __shared__ double wmin[16];
+    const int pout = phase == 2 ? 0 : phase + 1, pclr = phase == 0 ? 2 : phase - 1;
     cand = wave_min(cand);
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     if (lane == 0) wmin[w] = cand;
@@ -388,77 +429,50 @@ __device__ __forceinline__ void block_finish(Ctrl *ctrl, Group *groups, double c
         const int nw = (blockDim.x + 63) >> 6;
         for (int k = 1; k < nw; k++) m = fmin(m, wmin[k]);
         const unsigned long long mb = (unsigned long long)__double_as_longlong(m);
-        const unsigned gid = block_id % NGROUPS;
-        const unsigned ngroups = nblocks < NGROUPS ? nblocks : NGROUPS;
-        const unsigned members = nblocks / NGROUPS + (gid < nblocks % NGROUPS ? 1u : 0u);
-        Group *gr = groups + gid;
-        if (mb < load_agent(&gr->min_bits)) atomicMin(&gr->min_bits, mb);
-        __threadfence();
-        if (atomicAdd(&gr->count, 1u) == members - 1) {
-            __threadfence();
-            const unsigned long long gm = load_agent(&gr->min_bits);
-            __hip_atomic_store(&gr->min_bits, INF_BITS, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_store(&gr->count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            if (gm < load_agent(&ctrl->next_min)) atomicMin(&ctrl->next_min, gm);
-            __threadfence();
-            if (atomicAdd(&ctrl->arrive, 1u) == ngroups - 1) {
-                __threadfence();
-                const unsigned long long bits = load_agent(&ctrl->next_min);
-                ctrl->rawmin = __longlong_as_double((long long)bits);
-                ctrl->next_min = INF_BITS;
-                ctrl->arrive = 0u;
-                if (advance) {
-                    ctrl->t = t_next;
-                    ctrl->dt_last = dt;
-                    ctrl->cur = cur ^ 1;
-                    ctrl->steps = ctrl->steps + 1;
-                }
-            }
+        unsigned long long *slot = advance ? &c->m[pout].bits : &c->m[phase].bits;
+        if (mb < load_agent(slot)) atomicMin(slot, mb);
+        if (lead && advance) {
+            store_agent(&c->s[pout].t, L.t + L.dt);
+            store_agent(&c->s[pout].dt, L.dt);
+            store_agent(&c->s[pout].steps, L.steps + 1);
+            store_agent(&c->s[pout].cur, L.cur ^ 1);
+            store_agent(&c->m[pclr].bits, INF_BITS);
         }
     }
     __syncthreads();  // wmin may be reused by a following tile
 }
 
-// Reads the control block and decides this step's dt.  Returns false when the
-// state must not step (finished, flagged, or no finite dt).
-__device__ __forceinline__ bool step_setup(Ctrl *ctrl, double cfl, double dt_max, double &t, double &dt,
-                                           int &cur) {
-    t = ctrl->t;
-    const double t_end = ctrl->t_end;
-    if (!(t < t_end) || ctrl->flags != 0) return false;
-    dt = fmin(fmin(cfl * ctrl->rawmin, dt_max), t_end - t);
-    cur = ctrl->cur;
-    if (!(dt > 0.0) || !(dt < INFINITY)) {
-        if (threadIdx.x == 0) atomicOr(&ctrl->flags, FLAG_NODT);
-        return false;
-    }
-    return true;
-}
-
 template <typename T, int CPT>
-__global__ void __launch_bounds__(1024) k_step(Inst<T> I) {
-    double t, dt;
-    int cur;
-    if (!step_setup(I.ctrl, I.cfl, I.dt_max, t, dt, cur)) return;
-    const double t_next = t + dt;
+__global__ void __launch_bounds__(1024) k_step(Inst<T> I, int phase) {
+    const bool lead = blockIdx.x == 0;
+    const Level L = step_setup(I.ctrl, phase, I.cfl, I.dt_max, lead);
+    if (!L.run) return;
+    const double t_next = L.t + L.dt;
     double cand = INFINITY;
 #pragma unroll
     for (int r = 0; r < CPT; r++) {
         const int i = (blockIdx.x * CPT + r) * blockDim.x + threadIdx.x;
-        if (i < I.n) cand = fmin(cand, cell_update<T>(I, i, cur, t, dt, t_next));
+        if (i < I.n) cand = fmin(cand, cell_update<T>(I, i, L.cur, L.t, L.dt, t_next));
     }
-    block_finish(I.ctrl, I.groups, cand, gridDim.x, blockIdx.x, true, t_next, dt, cur);
+    block_finish(I.ctrl, phase, cand, L, lead, true);
 }
 
+// CFL minimum of the state of level `phase` (after an initialisation); the
+// host clears the slot first.
 template <typename T>
-__global__ void __launch_bounds__(256) k_dt_init(Inst<T> I) {
+__global__ void __launch_bounds__(256) k_dt_init(Inst<T> I, int phase) {
     const Ctrl *c = I.ctrl;
-    const int cur = c->cur;
-    const double t = c->t;
+    Level L;
+    L.t = c->s[phase].t;
+    L.cur = c->s[phase].cur;
+    L.dt = 0.0;
+    L.steps = 0;
+    L.rawmin = 0.0;
+    L.run = true;
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     double cand = INFINITY;
-    if (i < I.n) cand = cell_candidate<T>(I, i, cur, t);
-    block_finish(I.ctrl, I.groups, cand, gridDim.x, blockIdx.x, false, 0.0, 0.0, cur);
+    if (i < I.n) cand = cell_candidate<T>(I, i, L.cur, L.t);
+    block_finish(I.ctrl, phase, cand, L, false, false);
 }
 
 // Persistent batched step: blocks stride over a list of (member, tile)
@@ -466,21 +480,21 @@ __global__ void __launch_bounds__(256) k_dt_init(Inst<T> I) {
 // own dt and finished members cost one control-block read per tile.
 template <typename T, int CPT>
 __global__ void __launch_bounds__(256) k_step_batched(const Inst<T> *__restrict__ insts,
-                                                        const int2 *__restrict__ tiles, int ntiles) {
+                                                       const int2 *__restrict__ tiles, int ntiles, int phase) {
     for (int tt = blockIdx.x; tt < ntiles; tt += gridDim.x) {
         const int2 td = tiles[tt];
         const Inst<T> I = insts[td.x];
-        double t, dt;
-        int cur;
-        if (!step_setup(I.ctrl, I.cfl, I.dt_max, t, dt, cur)) continue;
-        const double t_next = t + dt;
+        const bool lead = td.y == 0;
+        const Level L = step_setup(I.ctrl, phase, I.cfl, I.dt_max, lead);
+        if (!L.run) continue;
+        const double t_next = L.t + L.dt;
         double cand = INFINITY;
 #pragma unroll
         for (int r = 0; r < CPT; r++) {
             const int i = (td.y * CPT + r) * blockDim.x + threadIdx.x;
-            if (i < I.n) cand = fmin(cand, cell_update<T>(I, i, cur, t, dt, t_next));
+            if (i < I.n) cand = fmin(cand, cell_update<T>(I, i, L.cur, L.t, L.dt, t_next));
         }
-        block_finish(I.ctrl, I.groups, cand, (unsigned)I.ntiles, (unsigned)td.y, true, t_next, dt, cur);
+        block_finish(I.ctrl, phase, cand, L, lead, true);
     }
 }
 
@@ -506,8 +520,8 @@ __device__ __forceinline__ double2 block_csum(double2 v) {
 // Volume sum (H - z)|cell| in a fixed order: fixed grid, strided per thread,
 // fixed-shape tree per block, then one block over the partials.
 template <typename T>
-__global__ void __launch_bounds__(MASS_THREADS) k_mass_partial(Inst<T> I, double2 *partials) {
-    const V4<T> *src = I.ctrl->cur ? I.U1 : I.U0;
+__global__ void __launch_bounds__(MASS_THREADS) k_mass_partial(Inst<T> I, double2 *partials, int phase) {
+    const V4<T> *src = I.ctrl->s[phase].cur ? I.U1 : I.U0;
     double s = 0.0, c = 0.0;
     for (int i = blockIdx.x * MASS_THREADS + threadIdx.x; i < I.n; i += MASS_BLOCKS * MASS_THREADS) {
         const V4<T> u = src[i];
@@ -537,28 +551,28 @@ __global__ void __launch_bounds__(MASS_THREADS) k_mass_final(Inst<T> I, const do
 }  // namespace
 
 template <typename T>
-hipError_t launch_step(const Inst<T> &I, int block, int cpt, hipStream_t s) {
+hipError_t launch_step(const Inst<T> &I, int block, int cpt, int phase, hipStream_t s) {
     if (I.n <= 0) return hipSuccess;
     const int per = block * cpt;
     const int grid = (I.n + per - 1) / per;
     if (cpt == 2)
-        hipLaunchKernelGGL((k_step<T, 2>), dim3(grid), dim3(block), 0, s, I);
+        hipLaunchKernelGGL((k_step<T, 2>), dim3(grid), dim3(block), 0, s, I, phase);
     else
-        hipLaunchKernelGGL((k_step<T, 1>), dim3(grid), dim3(block), 0, s, I);
+        hipLaunchKernelGGL((k_step<T, 1>), dim3(grid), dim3(block), 0, s, I, phase);
     return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_dt_init(const Inst<T> &I, hipStream_t s) {
+hipError_t launch_dt_init(const Inst<T> &I, int phase, hipStream_t s) {
     if (I.n <= 0) return hipSuccess;
     const int grid = (I.n + 255) / 256;
-    hipLaunchKernelGGL((k_dt_init<T>), dim3(grid), dim3(256), 0, s, I);
+    hipLaunchKernelGGL((k_dt_init<T>), dim3(grid), dim3(256), 0, s, I, phase);
     return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_mass(const Inst<T> &I, double2 *partials, double *out, int nslots, hipStream_t s) {
-    hipLaunchKernelGGL((k_mass_partial<T>), dim3(MASS_BLOCKS), dim3(MASS_THREADS), 0, s, I, partials);
+hipError_t launch_mass(const Inst<T> &I, double2 *partials, double *out, int nslots, int phase, hipStream_t s) {
+    hipLaunchKernelGGL((k_mass_partial<T>), dim3(MASS_BLOCKS), dim3(MASS_THREADS), 0, s, I, partials, phase);
     hipLaunchKernelGGL((k_mass_final<T>), dim3(1), dim3(MASS_THREADS), 0, s, I, (const double2 *)partials, nslots,
                        out);
     return hipGetLastError();
@@ -580,21 +594,22 @@ int batched_grid(int block, int cpt) {
 
 template <typename T>
 hipError_t launch_step_batched(const Inst<T> *insts, const int2 *tiles, int ntiles, int grid, int block, int cpt,
-                               hipStream_t s) {
+                               int phase, hipStream_t s) {
     if (ntiles <= 0) return hipSuccess;
     if (grid > ntiles) grid = ntiles;
     if (cpt == 2)
-        hipLaunchKernelGGL((k_step_batched<T, 2>), dim3(grid), dim3(block), 0, s, insts, tiles, ntiles);
+        hipLaunchKernelGGL((k_step_batched<T, 2>), dim3(grid), dim3(block), 0, s, insts, tiles, ntiles, phase);
     else
-        hipLaunchKernelGGL((k_step_batched<T, 1>), dim3(grid), dim3(block), 0, s, insts, tiles, ntiles);
+        hipLaunchKernelGGL((k_step_batched<T, 1>), dim3(grid), dim3(block), 0, s, insts, tiles, ntiles, phase);
     return hipGetLastError();
 }
 
 #define SWE_INSTANTIATE(T)                                                                                  \
-    template hipError_t launch_step<T>(const Inst<T> &, int, int, hipStream_t);                             \
-    template hipError_t launch_dt_init<T>(const Inst<T> &, hipStream_t);                                    \
-    template hipError_t launch_mass<T>(const Inst<T> &, double2 *, double *, int, hipStream_t);             \
-    template hipError_t launch_step_batched<T>(const Inst<T> *, const int2 *, int, int, int, int, hipStream_t); \
+    template hipError_t launch_step<T>(const Inst<T> &, int, int, int, hipStream_t);                        \
+    template hipError_t launch_dt_init<T>(const Inst<T> &, int, hipStream_t);                               \
+    template hipError_t launch_mass<T>(const Inst<T> &, double2 *, double *, int, int, hipStream_t);        \
+    template hipError_t launch_step_batched<T>(const Inst<T> *, const int2 *, int, int, int, int, int,      \
+                                               hipStream_t);                                                \
     template int batched_grid<T>(int, int);
 SWE_INSTANTIATE(float)
 SWE_INSTANTIATE(double)

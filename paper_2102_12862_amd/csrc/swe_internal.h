@@ -38,40 +38,38 @@ struct BCdev {
     const double *Q;
 };
 
-// Per-state control block: time, the CFL minimum of the current state, the
-// buffer holding it, the grid-wide arrival counter of the step in flight.
-// The last block of a step to arrive advances it, so no host round trip is
-// needed between steps.
-struct alignas(128) Ctrl {
-    double t;                     // current time t^n
-    double t_end;                 // steps are capped to land on t_end
-    double rawmin;                // min over cells/edges of rho / lambda for U^n
-    double dt_last;               // last step taken
-    unsigned long long next_min;  // running min (bit pattern) for U^{n+1}
-    unsigned int arrive;          // blocks that finished the step in flight
-    int cur;                      // U[cur] holds U^n
-    int flags;                    // FLAG_* bits
+// Per-state control block, triple-buffered by step phase p = step % 3.
+// A step launched with phase p reads the time level of slot p (time, CFL
+// minimum of its state, buffer index), accumulates the CFL minimum of the
+// state it writes into min slot p+1 with at most one atomic min per block,
+// and block 0 publishes time level p+1 and clears min slot p+2 (the input of
+// the previous step).  No block waits for another and no fence is needed:
+// the next launch reads what this one wrote after the kernel boundary.
+struct alignas(128) CtrlSlot {
+    double t;         // time of this level
+    double dt;        // step that produced it
+    long long steps;  // steps taken to reach it
+    int cur;          // U[cur] holds this level's state
     int pad0;
-    long long steps;
-    double clipped;               // volume added by positivity clips
-    unsigned long long nclip;
-    double pad1[4];
+    double pad1[12];
 };
-static_assert(sizeof(Ctrl) == 128, "Ctrl layout");
+struct alignas(128) MinSlot {
+    unsigned long long bits;  // min rho/lambda of this level's state (double bits)
+    unsigned long long pad[15];
+};
+struct alignas(128) Ctrl {
+    CtrlSlot s[3];
+    MinSlot m[3];
+    double t_end;             // steps are capped to land on t_end
+    int flags;                // FLAG_* bits
+    int pad0;
+    double clipped;           // volume added by positivity clips
+    unsigned long long nclip;
+    double pad1[12];
+};
+static_assert(sizeof(Ctrl) == 7 * 128, "Ctrl layout");
 
 constexpr unsigned long long INF_BITS = 0x7FF0000000000000ull;
-
-// Arrival groups of the grid-wide step reduction: block b reports to group
-// b % NGROUPS (one cache line each), the last block of a group reports to
-// the control block.  Spreading the per-block atomics over many lines keeps
-// them from serialising on one address.
-constexpr int NGROUPS = 64;
-struct alignas(128) Group {
-    unsigned long long min_bits;
-    unsigned int count;
-    unsigned int pad[29];
-};
-static_assert(sizeof(Group) == 128, "Group layout");
 
 // Everything one kernel needs about one state.
 template <typename T> struct Inst {
@@ -85,7 +83,6 @@ template <typename T> struct Inst {
     const BCdev *bcs;
     const double *area;    // |cell|, for clip volume and mass
     Ctrl *ctrl;
-    Group *groups;         // NGROUPS arrival groups of this state
     int n;
     int ntiles;            // blocks of one step (batched kernel)
     double g, cfl, h_min, dt_max;
@@ -95,14 +92,14 @@ template <typename T> struct Inst {
 
 // Launch wrappers (kernels.hip).
 template <typename T>
-hipError_t launch_step(const Inst<T> &I, int block, int cpt, hipStream_t s);
+hipError_t launch_step(const Inst<T> &I, int block, int cpt, int phase, hipStream_t s);
 template <typename T>
-hipError_t launch_dt_init(const Inst<T> &I, hipStream_t s);
+hipError_t launch_dt_init(const Inst<T> &I, int phase, hipStream_t s);
 template <typename T>
-hipError_t launch_mass(const Inst<T> &I, double2 *partials, double *out, int nslots, hipStream_t s);
+hipError_t launch_mass(const Inst<T> &I, double2 *partials, double *out, int nslots, int phase, hipStream_t s);
 template <typename T>
 hipError_t launch_step_batched(const Inst<T> *insts, const int2 *tiles, int ntiles, int grid, int block,
-                               int cpt, hipStream_t s);
+                               int cpt, int phase, hipStream_t s);
 template <typename T>
 int batched_grid(int block, int cpt);
 constexpr int MASS_BLOCKS = 1024;

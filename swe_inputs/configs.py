@@ -224,12 +224,17 @@ def ensemble_sizes(k: int = 64, lo: float = 2e4, hi: float = 5e5) -> np.ndarray:
     return np.round(np.exp(rng(7).uniform(np.log(lo), np.log(hi), k))).astype(np.int64)
 
 
-def ensemble_member(k: int, n_cells: int, t_end: float = 1800.0) -> Scenario:
+def ensemble_member(k: int, n_cells: int, t_end: float = 1800.0, mesh: str = "poisson") -> Scenario:
     """One member of the batched ensemble: the lake-at-rest generator with
     its own seed, fed through x=0, y in [450,550] by Q_k(t) = 50 + (P_k-50)
-    t/1800 with P_k ~ U[200,3000], zero-gradient outflow at x=2000."""
+    t/1800 with P_k ~ U[200,3000], zero-gradient outflow at x=2000.
+    ``mesh="lattice"`` swaps the 28-degree Poisson-disk mesh for the faster
+    jittered-lattice Delaunay mesh (same bed, same boundaries)."""
     lx, ly = 2000.0, 1000.0
-    xy, tri, sides = M.poisson_delaunay(lx, ly, n_cells, rng(100 + k))
+    if mesh == "lattice":
+        xy, tri, sides = M.jittered_lattice(lx, ly, max(16, n_cells // 2), rng(100 + k))
+    else:
+        xy, tri, sides = M.poisson_delaunay(lx, ly, n_cells, rng(100 + k))
     z = gaussian_bumps(xy, lx, ly, rng(2 + 100 + k))
     n = tri.shape[0]
     p = rng(200 + k).uniform(200.0, 3000.0)

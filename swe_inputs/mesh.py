@@ -72,7 +72,7 @@ def _boundary_points(lx: float, ly: float, spacing: float) -> np.ndarray:
 
 
 def poisson_disk(lx: float, ly: float, r: float, rng: np.random.Generator,
-                 rounds: int = 40) -> np.ndarray:
+                 rounds: int = 12) -> np.ndarray:
     """Seeded random points in [0,lx]x[0,ly] no two closer than ``r``.
 
     Boundary points sit on the four sides at spacing <= r.  Interior points
@@ -164,14 +164,23 @@ def _fill_gaps(xy: np.ndarray, lx: float, ly: float, r: float, max_iter: int = 2
         idx = idx[np.argsort(-R[idx], kind="stable")]
         cand = np.c_[ux[idx], uy[idx]]
         keep = []
-        tree_pts = []
-        for k, p in enumerate(cand):
-            if tree_pts:
-                q = np.asarray(tree_pts)
-                if (((q - p) ** 2).sum(1) < r * r).any():
-                    continue
-            tree_pts.append(p)
-            keep.append(k)
+        cells = {}
+        for k, (px, py) in enumerate(cand):
+            ci, cj = int(px // r), int(py // r)
+            ok = True
+            for di in (-1, 0, 1):
+                for dj in (-1, 0, 1):
+                    for qx, qy in cells.get((ci + di, cj + dj), ()):
+                        if (qx - px) ** 2 + (qy - py) ** 2 < r * r:
+                            ok = False
+                            break
+                    if not ok:
+                        break
+                if not ok:
+                    break
+            if ok:
+                cells.setdefault((ci, cj), []).append((px, py))
+                keep.append(k)
         if not keep:
             break
         xy = np.concatenate([xy, cand[keep]])

@@ -46,12 +46,29 @@ __device__ __forceinline__ float qdiv(float a, float b) { return a * __builtin_a
 __device__ __forceinline__ double qsqrt(double a) { return sqrt(a); }
 __device__ __forceinline__ float qsqrt(float a) { return __builtin_amdgcn_sqrtf(a); }
 
+// Edge length and unit normal from l*n.  FP64: the IEEE square root and two
+// divisions (matching the oracle); FP32: one reciprocal square root.
+__device__ __forceinline__ void edge_normal(double lx, double ly, double &l, double &nx, double &ny) {
+    l = sqrt(lx * lx + ly * ly);
+    nx = lx / l;
+    ny = ly / l;
+}
+__device__ __forceinline__ void edge_normal(float lx, float ly, float &l, float &nx, float &ny) {
+    const float s = lx * lx + ly * ly;
+    const float r = __builtin_amdgcn_rsqf(s);
+    l = s * r;
+    nx = lx * r;
+    ny = ly * r;
+}
+
 // HLLC flux (Toro 1994) in the frame of the edge normal, for reconstructed
 // depths hL, hR >= 0.  Wave speeds: two-rarefaction estimates with c* >= 0
 // when both sides are wet, dry-bed speeds u -+ 2c when one side is dry.  The
-// contact speed S* and the star states h_K (S_K - u_K)/(S_K - S*) (1, S*, ut_K)
-// are evaluated only for the selected region.  Identical states return the
-// physical flux (consistency) and two dry sides return zero.
+// flux is F_K + S_K (U*_K - U_K) on the side K the contact speed S* selects,
+// with U*_K = h_K (S_K - u_K)/(S_K - S*) (1, S*, ut_K), or the physical flux
+// F_K when all waves move one way (or the states are identical); two dry
+// sides give zero.  The side is chosen first and the formulas evaluated once,
+// so neighbouring edges with opposite flow directions do not diverge.
 template <typename T>
 __device__ __forceinline__ void hllc(T hL, T unL, T utL, T hR, T unR, T utR, T g, T &F0, T &F1, T &F2) {
     const T zero = T(0), half = T(0.5);
@@ -59,50 +76,27 @@ __device__ __forceinline__ void hllc(T hL, T unL, T utL, T hR, T unR, T utR, T g
         F0 = zero; F1 = zero; F2 = zero;
         return;
     }
-    if (hL == hR && unL == unR && utL == utR) {
-        F0 = hL * unL;
-        F1 = hL * unL * unL + half * g * hL * hL;
-        F2 = hL * unL * utL;
-        return;
-    }
+    const bool ident = hL == hR && unL == unR && utL == utR;
     const T cL = qsqrt(g * hL), cR = qsqrt(g * hR);
-    T SL, SR;
-    if (!(hL > zero)) {
-        SL = unR - T(2) * cR;
-        SR = unR + cR;
-    } else if (!(hR > zero)) {
-        SL = unL - cL;
-        SR = unL + T(2) * cL;
-    } else {
-        const T a = half * (cL + cR) + T(0.25) * (unL - unR);
-        const T us = half * (unL + unR) + cL - cR;
-        const T cs = a > zero ? a : zero;
-        SL = fmin(unL - cL, us - cs);
-        SR = fmax(unR + cR, us + cs);
-    }
-    if (zero <= SL) {
-        F0 = hL * unL;
-        F1 = hL * unL * unL + half * g * hL * hL;
-        F2 = hL * unL * utL;
-        return;
-    }
-    if (SR <= zero) {
-        F0 = hR * unR;
-        F1 = hR * unR * unR + half * g * hR * hR;
-        F2 = hR * unR * utR;
-        return;
-    }
+    const bool dryL = !(hL > zero), dryR = !(hR > zero);
+    const T a = half * (cL + cR) + T(0.25) * (unL - unR);
+    const T us = half * (unL + unR) + cL - cR;
+    const T cs = a > zero ? a : zero;
+    const T SL = dryL ? unR - T(2) * cR : (dryR ? unL - cL : fmin(unL - cL, us - cs));
+    const T SR = dryL ? unR + cR : (dryR ? unL + T(2) * cL : fmax(unR + cR, us + cs));
     const T Ss = qdiv(SL * hR * (unR - SR) - SR * hL * (unL - SL), hR * (unR - SR) - hL * (unL - SL));
-    if (zero <= Ss) {
-        const T f = qdiv(hL * (SL - unL), SL - Ss);
-        F0 = hL * unL + SL * (f - hL);
-        F1 = hL * unL * unL + half * g * hL * hL + SL * (f * Ss - hL * unL);
-        F2 = hL * unL * utL + SL * (f * utL - hL * utL);
-    } else {
-        const T f = qdiv(hR * (SR - unR), SR - Ss);
-        F0 = hR * unR + SR * (f - hR);
-        F1 = hR * unR * unR + half * g * hR * hR + SR * (f * Ss - hR * unR);
-        F2 = hR * unR * utR + SR * (f * utR - hR * utR);
+    // side K whose flux (and star state) is used
+    const bool left = ident || zero <= SL || (!(SR <= zero) && zero <= Ss);
+    const bool star = !ident && !(zero <= SL) && !(SR <= zero);
+    const T hK = left ? hL : hR, unK = left ? unL : unR, utK = left ? utL : utR, SK = left ? SL : SR;
+    F0 = hK * unK;
+    F1 = hK * unK * unK + half * g * hK * hK;
+    F2 = hK * unK * utK;
+    if (star) {
+        const T f = qdiv(hK * (SK - unK), SK - Ss);
+        F0 = F0 + SK * (f - hK);
+        F1 = F1 + SK * (f * Ss - hK * unK);
+        F2 = F2 + SK * (f * utK - hK * utK);
     }
 }
 
@@ -194,8 +188,8 @@ __device__ __forceinline__ double cell_update(const Inst<T> &I, int i, int cur, 
     int inflow_bc[3] = {-1, -1, -1};
 #pragma unroll
     for (int k = 0; k < 3; k++) {
-        const T l = qsqrt(lx[k] * lx[k] + ly[k] * ly[k]);
-        const T nx = qdiv(lx[k], l), ny = qdiv(ly[k], l);
+        T l, nx, ny;
+        edge_normal(lx[k], ly[k], l, nx, ny);
         el[k] = l;
         enx[k] = nx;
         eny[k] = ny;
@@ -345,9 +339,10 @@ __device__ __forceinline__ double cell_candidate(const Inst<T> &I, int i, int cu
     const T c = wet ? qsqrt(g * hh) : T(0);
 #pragma unroll
     for (int k = 0; k < 3; k++) {
-        const T l = qsqrt(lx[k] * lx[k] + ly[k] * ly[k]);
+        T l, nx, ny;
+        edge_normal(lx[k], ly[k], l, nx, ny);
         if (wet) {
-            const T lam = fabs(u * qdiv(lx[k], l) + v * qdiv(ly[k], l)) + c;
+            const T lam = fabs(u * nx + v * ny) + c;
             cfl.add(double(l), double(lam));
         }
         if (nb[k] < 0) {
@@ -482,7 +477,9 @@ template <typename T, int CPT>
 __global__ void __launch_bounds__(256) k_step_batched(const Inst<T> *__restrict__ insts,
                                                        const int2 *__restrict__ tiles, int ntiles, int phase) {
     for (int tt = blockIdx.x; tt < ntiles; tt += gridDim.x) {
-        const int2 td = tiles[tt];
+        // the tile is the same for the whole block: keep its record scalar
+        const int2 td = make_int2(__builtin_amdgcn_readfirstlane(tiles[tt].x),
+                                  __builtin_amdgcn_readfirstlane(tiles[tt].y));
         const Inst<T> I = insts[td.x];
         const bool lead = td.y == 0;
         const Level L = step_setup(I.ctrl, phase, I.cfl, I.dt_max, lead);

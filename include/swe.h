@@ -93,8 +93,8 @@ typedef struct {
     double dt_max;          /* upper limit of the time step [s] > 0, default +inf */
     int32_t precision;      /* SWE_FP64 (default) or SWE_FP32 */
     int32_t neg_depth_policy; /* SWE_NEG_CLIP (default) or SWE_NEG_ERROR */
-    int32_t block_size;     /* threads per block: 64..1024, multiple of 64; 0 = tuned/default */
-    int32_t cells_per_thread; /* 1 or 2; 0 = tuned/default */
+    int32_t block_size;     /* cells per tile = threads per block: 128, 256 or 512; 0 = default (256) */
+    int32_t cells_per_thread; /* reserved: 0 or 1 */
     int32_t steps_per_graph;  /* steps captured per hipGraph in swe_run_until; 0 = default (32) */
     int32_t renumber;       /* 1 = Hilbert order of cell centroids (default), 0 = input order */
 } swe_params;
@@ -117,8 +117,14 @@ swe_status swe_mesh_create(const double *node_xyz, int64_t n_nodes, const int32_
 void swe_mesh_destroy(swe_mesh *m);
 /* counts: cells, edges, boundary edges (any pointer may be NULL) */
 void swe_mesh_info(const swe_mesh *m, int64_t *n_cells, int64_t *n_edges, int64_t *n_boundary_edges);
-/* device bytes a state of this precision needs (mesh geometry not included) */
+/* Device bytes one solve of this precision needs: the state plus the mesh
+ * data its kernels read (tile edge lists, areas). */
 int64_t swe_state_footprint(const swe_mesh *m, int32_t precision);
+/* Host-side consistency check of the mesh's tile edge lists for a block
+ * size (128, 256 or 512): every cell edge covered exactly once, indices,
+ * orientation flags and normals consistent.  SWE_OK or SWE_EINVAL with the
+ * first problem in swe_last_error().  Diagnostic; no device work. */
+swe_status swe_mesh_check(const swe_mesh *m, int32_t tile);
 
 /* Creates a device-resident state (section "Initial and boundary
  * conditions": region-defined initial values or dry).  Exactly one of
@@ -162,10 +168,10 @@ swe_status swe_state_read(const swe_state *s, double *H, double *h, double *qx, 
  * The scheme is conservative: mass(t) = mass(0) - bnd_flux + clipped. */
 swe_status swe_mass(const swe_state *s, double *mass, double *bnd_flux, double *clipped, int64_t *steps);
 
-/* Times k steps for each block size in {64,128,256,512,1024} and cells per
- * thread in {1,2}, keeps the fastest for this state, and restores the state
- * exactly as it was.  *block_size / *cells_per_thread (may be NULL) receive
- * the choice.  Results are bitwise independent of the choice. */
+/* Times k steps for each tile size (block size) in {128, 256, 512}, keeps
+ * the fastest for this state, and restores the state exactly as it was.
+ * *block_size receives the choice, *cells_per_thread 1 (either may be NULL).
+ * Results are bitwise independent of the choice. */
 swe_status swe_autotune(swe_state *s, int32_t k, int32_t *block_size, int32_t *cells_per_thread);
 
 /* ---- batched ensembles (many independent states stepped by one persistent

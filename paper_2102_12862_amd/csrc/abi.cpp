@@ -59,12 +59,14 @@ struct DevMem {
     hipStream_t stream() const { return (hipStream_t)dev.hip_stream; }
 };
 
-struct Geom {
-    void *geo0 = nullptr;
-    int *nbr = nullptr;
-    double *area = nullptr;
-    bool ready = false;
+// Tile edge lists of one mesh for one precision and tile size.
+struct TileGeom {
+    void *edges = nullptr;
+    int *eoff = nullptr;
+    int ntiles = 0;
 };
+constexpr int TILES[3] = {128, 256, 512};
+int tile_index(int tile) { return tile == 128 ? 0 : tile == 256 ? 1 : tile == 512 ? 2 : -1; }
 
 size_t vec4_bytes(int prec) { return prec == SWE_FP32 ? sizeof(float4) : sizeof(double4); }
 
@@ -75,44 +77,57 @@ swe_status check_flags(int flags) {
     return SWE_OK;
 }
 
-bool valid_block(int b) { return b >= 64 && b <= 1024 && b % 64 == 0; }
+bool valid_tile(int b) { return tile_index(b) >= 0; }
 
 }  // namespace
 
 struct swe_mesh {
     DevMem mem;
     HostMesh H;
-    Geom geom[2];
+    double *area = nullptr;  // |cell| in FP64 (mass sums, clip volume)
+    TileGeom geom[2][3];     // [precision][tile size]
     ~swe_mesh() {
-        for (auto &g : geom) {
-            mem.release(g.geo0);
-            mem.release(g.nbr);
-            mem.release(g.area);
-        }
+        mem.release(area);
+        for (auto &row : geom)
+            for (auto &g : row) {
+                mem.release(g.edges);
+                mem.release(g.eoff);
+            }
     }
-    template <typename T> swe_status ensure_geom(int prec) {
-        Geom &g = geom[prec];
-        if (g.ready) return SWE_OK;
-        const int64_t n = H.nc;
-        g.geo0 = mem.alloc((size_t)n * sizeof(V4<T>));
-        g.nbr = (int *)mem.alloc((size_t)n * 3 * sizeof(int));
-        g.area = (double *)mem.alloc((size_t)n * sizeof(double));
-        if (!g.geo0 || !g.nbr || !g.area) return fail(SWE_ENOMEM, "device allocation failed (mesh geometry)");
-        std::vector<V4<T>> g0((size_t)n);
-        std::vector<int> nb((size_t)(3 * n));
-        for (int64_t p = 0; p < n; p++) {
-            g0[p].x = T(H.lx[3 * p]);
-            g0[p].y = T(H.ly[3 * p]);
-            g0[p].z = T(H.lx[3 * p + 1]);
-            g0[p].w = T(H.ly[3 * p + 1]);
-            for (int k = 0; k < 3; k++) nb[(size_t)k * n + p] = H.nbr[3 * p + k];
+    swe_status ensure_area() {
+        if (area) return SWE_OK;
+        area = (double *)mem.alloc((size_t)H.nc * sizeof(double));
+        if (!area) return fail(SWE_ENOMEM, "device allocation failed (mesh areas)");
+        HIP_TRY(hipMemcpyAsync(area, H.area.data(), (size_t)H.nc * sizeof(double), hipMemcpyHostToDevice,
+                               mem.stream()));
+        HIP_TRY(hipStreamSynchronize(mem.stream()));
+        return SWE_OK;
+    }
+    // the tile edge lists for (precision, tile), built and uploaded on first use
+    template <typename T> swe_status ensure_tiles(int prec, int tile) {
+        TileGeom &g = geom[prec][tile_index(tile)];
+        if (g.edges) return SWE_OK;
+        swe_status st = ensure_area();
+        if (st) return st;
+        std::vector<TileEdge> te;
+        std::vector<int32_t> eoff;
+        if (!build_tile_edges(H, tile, te, eoff)) return fail(SWE_EINVAL, "cannot build tile edge lists");
+        std::vector<Edge<T>> ed(te.size());
+        for (size_t k = 0; k < te.size(); k++) {
+            ed[k].w0 = te[k].w0;
+            ed[k].w1 = te[k].w1;
+            ed[k].lx = T(te[k].lx);
+            ed[k].ly = T(te[k].ly);
         }
+        g.edges = mem.alloc(std::max<size_t>(ed.size(), 1) * sizeof(Edge<T>));
+        g.eoff = (int *)mem.alloc(eoff.size() * sizeof(int));
+        if (!g.edges || !g.eoff) return fail(SWE_ENOMEM, "device allocation failed (tile edges)");
         hipStream_t s = mem.stream();
-        HIP_TRY(hipMemcpyAsync(g.geo0, g0.data(), g0.size() * sizeof(V4<T>), hipMemcpyHostToDevice, s));
-        HIP_TRY(hipMemcpyAsync(g.nbr, nb.data(), nb.size() * sizeof(int), hipMemcpyHostToDevice, s));
-        HIP_TRY(hipMemcpyAsync(g.area, H.area.data(), (size_t)n * sizeof(double), hipMemcpyHostToDevice, s));
+        if (!ed.empty())
+            HIP_TRY(hipMemcpyAsync(g.edges, ed.data(), ed.size() * sizeof(Edge<T>), hipMemcpyHostToDevice, s));
+        HIP_TRY(hipMemcpyAsync(g.eoff, eoff.data(), eoff.size() * sizeof(int), hipMemcpyHostToDevice, s));
         HIP_TRY(hipStreamSynchronize(s));
-        g.ready = true;
+        g.ntiles = (int)(eoff.size() - 1);
         return SWE_OK;
     }
 };
@@ -122,7 +137,7 @@ struct swe_state {
     swe_params p{};
     DevMem mem;
     int prec = SWE_FP64;
-    void *U0 = nullptr, *U1 = nullptr, *geo1 = nullptr;
+    void *U0 = nullptr, *U1 = nullptr, *cellp = nullptr;
     int *slot_kbc = nullptr;
     double *slot_acc = nullptr;
     BCdev *bcs = nullptr;
@@ -133,18 +148,18 @@ struct swe_state {
     Ctrl *hctrl = nullptr;    // pinned host copy of the control block
     double *hbuf = nullptr;   // pinned scratch (t_end, mass results)
     int nslots = 0;
-    int block = 256, cpt = 1, spg = 32;
+    int tile = 256, spg = 32;
     int phase = 0;  // step launches issued so far, mod 3 (selects the control slot)
     hipStream_t cap = nullptr;
     hipGraphExec_t gexec[3] = {nullptr, nullptr, nullptr};  // one per starting phase
-    int g_k = 0, g_block = 0, g_cpt = 0;
+    int g_k = 0, g_tile = 0;
     Inst<float> inst32{};
     Inst<double> inst64{};
 
     ~swe_state() {
         drop_graphs();
         if (cap) (void)hipStreamDestroy(cap);
-        for (void *q : {U0, U1, geo1, (void *)slot_kbc, (void *)slot_acc, (void *)bcs, (void *)hydro, (void *)ctrl,
+        for (void *q : {U0, U1, cellp, (void *)slot_kbc, (void *)slot_acc, (void *)bcs, (void *)hydro, (void *)ctrl,
                         (void *)partials, (void *)mass_out})
             mem.release(q);
         if (hctrl) (void)hipHostFree(hctrl);
@@ -161,8 +176,7 @@ struct swe_state {
             }
     }
     hipError_t launch_one_on(hipStream_t s, int ph) {
-        return prec == SWE_FP32 ? launch_step<float>(inst32, block, cpt, ph, s)
-                                : launch_step<double>(inst64, block, cpt, ph, s);
+        return prec == SWE_FP32 ? launch_step<float>(inst32, tile, ph, s) : launch_step<double>(inst64, tile, ph, s);
     }
     hipError_t launch_one() {
         hipError_t e = launch_one_on(stream(), phase);
@@ -181,7 +195,7 @@ struct swe_state {
     }
     // k captured steps starting at the current phase
     swe_status graph(int k) {
-        if (g_k != k || g_block != block || g_cpt != cpt) drop_graphs();
+        if (g_k != k || g_tile != tile) drop_graphs();
         if (gexec[phase]) return SWE_OK;
         if (!cap) HIP_TRY(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
         hipGraph_t gr = nullptr;
@@ -200,8 +214,7 @@ struct swe_state {
         (void)hipGraphDestroy(gr);
         if (e != hipSuccess) return fail(SWE_EDEVICE, std::string("graph instantiate: ") + hipGetErrorString(e));
         g_k = k;
-        g_block = block;
-        g_cpt = cpt;
+        g_tile = tile;
         return SWE_OK;
     }
     swe_status launch_graph() {
@@ -209,6 +222,18 @@ struct swe_state {
         if (st) return st;
         HIP_TRY(hipGraphLaunch(gexec[phase], stream()));
         phase = (phase + spg) % 3;
+        return SWE_OK;
+    }
+    // switches the tile size (block size) of the step kernel
+    swe_status set_tile(int t) {
+        swe_status st = prec == SWE_FP32 ? m->ensure_tiles<float>(prec, t) : m->ensure_tiles<double>(prec, t);
+        if (st) return st;
+        const TileGeom &g = m->geom[prec][tile_index(t)];
+        inst32.edges = (const Edge<float> *)g.edges;
+        inst64.edges = (const Edge<double> *)g.edges;
+        inst32.eoff = inst64.eoff = g.eoff;
+        inst32.ntiles = inst64.ntiles = g.ntiles;
+        tile = t;
         return SWE_OK;
     }
     // moves the current level to control slot `to` (aligning with a batch)
@@ -281,12 +306,25 @@ void swe_mesh_info(const swe_mesh *m, int64_t *n_cells, int64_t *n_edges, int64_
     if (n_boundary_edges) *n_boundary_edges = m->H.nb;
 }
 
+swe_status swe_mesh_check(const swe_mesh *m, int32_t tile) {
+    if (!m) return fail(SWE_EINVAL, "mesh is NULL");
+    if (!valid_tile(tile)) return fail(SWE_EINVAL, "tile must be 128, 256 or 512");
+    std::vector<TileEdge> te;
+    std::vector<int32_t> eoff;
+    if (!build_tile_edges(m->H, tile, te, eoff)) return fail(SWE_EINVAL, "cannot build tile edge lists");
+    const std::string err = check_tile_edges(m->H, tile, te, eoff);
+    if (!err.empty()) return fail(SWE_EINVAL, err);
+    return SWE_OK;
+}
+
 int64_t swe_state_footprint(const swe_mesh *m, int32_t precision) {
     if (!m) return 0;
     const int64_t n = m->H.nc, ns = (int64_t)m->H.slot_tag.size();
     const int64_t v4 = (int64_t)vec4_bytes(precision);
-    const int64_t state = 3 * n * v4 + ns * (4 + 16) + (int64_t)sizeof(Ctrl) + MASS_BLOCKS * 16 + 4096;
-    const int64_t geom = n * (v4 + 12 + 8);
+    const int64_t state = 2 * n * v4 + n * v4 / 2 + ns * (4 + 16) + (int64_t)sizeof(Ctrl) + MASS_BLOCKS * 16 + 4096;
+    // tile edge list (about 1.7 edges per cell) and FP64 areas
+    const int64_t edge = precision == SWE_FP32 ? 16 : 24;
+    const int64_t geom = n * 8 + (n * 7 / 4) * edge + 4 * (n / 128 + 2);
     return state + geom;
 }
 
@@ -306,8 +344,8 @@ swe_status swe_state_init(const swe_mesh *m, const swe_params *params, const dou
     if (P.precision != SWE_FP32 && P.precision != SWE_FP64) return fail(SWE_EINVAL, "unknown precision");
     if (P.neg_depth_policy != SWE_NEG_CLIP && P.neg_depth_policy != SWE_NEG_ERROR)
         return fail(SWE_EINVAL, "unknown negative-depth policy");
-    if (P.block_size != 0 && !valid_block(P.block_size)) return fail(SWE_EINVAL, "block_size must be 64..1024, multiple of 64");
-    if (P.cells_per_thread < 0 || P.cells_per_thread > 2) return fail(SWE_EINVAL, "cells_per_thread must be 0, 1 or 2");
+    if (P.block_size != 0 && !valid_tile(P.block_size)) return fail(SWE_EINVAL, "block_size must be 0, 128, 256 or 512");
+    if (P.cells_per_thread < 0 || P.cells_per_thread > 1) return fail(SWE_EINVAL, "cells_per_thread must be 0 or 1");
     if (P.steps_per_graph < 0 || P.steps_per_graph > 4096) return fail(SWE_EINVAL, "steps_per_graph out of range");
     if (H0 && h0) return fail(SWE_EINVAL, "give H0 or h0, not both");
     if (!std::isfinite(t0)) return fail(SWE_EINVAL, "t0 must be finite");
@@ -391,16 +429,16 @@ swe_status swe_state_init(const swe_mesh *m, const swe_params *params, const dou
     S->mem = m->mem;
     S->prec = prec;
     S->nslots = nslots;
-    S->block = P.block_size ? P.block_size : 256;
-    S->cpt = P.cells_per_thread ? P.cells_per_thread : 1;
+    S->tile = P.block_size ? P.block_size : 256;
     S->spg = P.steps_per_graph ? P.steps_per_graph : 32;
-    swe_status st = prec == SWE_FP32 ? S->m->ensure_geom<float>(prec) : S->m->ensure_geom<double>(prec);
+    swe_status st = prec == SWE_FP32 ? S->m->ensure_tiles<float>(prec, S->tile)
+                                     : S->m->ensure_tiles<double>(prec, S->tile);
     if (st) return st;
 
     const size_t v4 = vec4_bytes(prec);
     S->U0 = S->mem.alloc((size_t)n * v4);
     S->U1 = S->mem.alloc((size_t)n * v4);
-    S->geo1 = S->mem.alloc((size_t)n * v4);
+    S->cellp = S->mem.alloc((size_t)n * v4 / 2);
     S->slot_kbc = (int *)S->mem.alloc(sizeof(int) * std::max(nslots, 1));
     S->slot_acc = (double *)S->mem.alloc(2 * sizeof(double) * std::max(nslots, 1));
     S->bcs = (BCdev *)S->mem.alloc(sizeof(BCdev) * std::max(n_bc, 1));
@@ -408,7 +446,7 @@ swe_status swe_state_init(const swe_mesh *m, const swe_params *params, const dou
     S->ctrl = (Ctrl *)S->mem.alloc(sizeof(Ctrl));
     S->partials = (double2 *)S->mem.alloc(sizeof(double2) * MASS_BLOCKS);
     S->mass_out = (double *)S->mem.alloc(2 * sizeof(double));
-    if (!S->U0 || !S->U1 || !S->geo1 || !S->slot_kbc || !S->slot_acc || !S->bcs || !S->hydro || !S->ctrl ||
+    if (!S->U0 || !S->U1 || !S->cellp || !S->slot_kbc || !S->slot_acc || !S->bcs || !S->hydro || !S->ctrl ||
         !S->partials || !S->mass_out)
         return fail(SWE_ENOMEM, "device allocation failed (state)");
     HIP_TRY(hipHostMalloc((void **)&S->hctrl, sizeof(Ctrl), hipHostMallocDefault));
@@ -422,20 +460,19 @@ swe_status swe_state_init(const swe_mesh *m, const swe_params *params, const dou
     hipStream_t s = S->stream();
     auto upload = [&](auto tag) -> swe_status {
         using T = decltype(tag);
-        std::vector<V4<T>> u((size_t)n), g1((size_t)n);
+        std::vector<V4<T>> u((size_t)n);
+        std::vector<V2<T>> cp((size_t)n);
         for (int64_t p = 0; p < n; p++) {
             u[p].x = T(H[p]);
             u[p].y = T(qx[p]);
             u[p].z = T(qy[p]);
             u[p].w = T(M.zb[p]);
-            g1[p].x = T(M.lx[3 * p + 2]);
-            g1[p].y = T(M.ly[3 * p + 2]);
-            g1[p].z = T(M.area[p]);
-            g1[p].w = T(gn2[p]);
+            cp[p].x = T(M.area[p]);
+            cp[p].y = T(gn2[p]);
         }
         HIP_TRY(hipMemcpyAsync(S->U0, u.data(), u.size() * sizeof(V4<T>), hipMemcpyHostToDevice, s));
         HIP_TRY(hipMemcpyAsync(S->U1, u.data(), u.size() * sizeof(V4<T>), hipMemcpyHostToDevice, s));
-        HIP_TRY(hipMemcpyAsync(S->geo1, g1.data(), g1.size() * sizeof(V4<T>), hipMemcpyHostToDevice, s));
+        HIP_TRY(hipMemcpyAsync(S->cellp, cp.data(), cp.size() * sizeof(V2<T>), hipMemcpyHostToDevice, s));
         HIP_TRY(hipStreamSynchronize(s));
         return SWE_OK;
     };
@@ -460,16 +497,17 @@ swe_status swe_state_init(const swe_mesh *m, const swe_params *params, const dou
         using T = decltype(tag);
         I.U0 = (V4<T> *)S->U0;
         I.U1 = (V4<T> *)S->U1;
-        I.geo0 = (const V4<T> *)m->geom[prec].geo0;
-        I.geo1 = (const V4<T> *)S->geo1;
-        I.nbr = m->geom[prec].nbr;
+        const TileGeom &tg = m->geom[prec][tile_index(S->tile)];
+        I.cellp = (const V2<T> *)S->cellp;
+        I.edges = (const Edge<T> *)tg.edges;
+        I.eoff = tg.eoff;
         I.slot_kbc = S->slot_kbc;
         I.slot_acc = S->slot_acc;
         I.bcs = S->bcs;
-        I.area = m->geom[prec].area;
+        I.area = m->area;
         I.ctrl = S->ctrl;
         I.n = (int)n;
-        I.ntiles = 0;
+        I.ntiles = tg.ntiles;
         I.g = P.g;
         I.cfl = P.cfl;
         I.h_min = P.h_min;
@@ -479,10 +517,10 @@ swe_status swe_state_init(const swe_mesh *m, const swe_params *params, const dou
     };
     if (prec == SWE_FP32) {
         fill_inst(S->inst32, float());
-        HIP_TRY(launch_dt_init<float>(S->inst32, S->phase, s));
+        HIP_TRY(launch_dt_init<float>(S->inst32, S->tile, S->phase, s));
     } else {
         fill_inst(S->inst64, double());
-        HIP_TRY(launch_dt_init<double>(S->inst64, S->phase, s));
+        HIP_TRY(launch_dt_init<double>(S->inst64, S->tile, S->phase, s));
     }
     st = S->read_ctrl();
     if (st) return st;
@@ -643,15 +681,13 @@ swe_status swe_autotune(swe_state *s, int32_t k, int32_t *block_size, int32_t *c
         HIP_TRY(hipMemcpyAsync(keepA, s->slot_acc, ab, hipMemcpyDeviceToDevice, q));
         HIP_TRY(hipEventCreate(&e0));
         HIP_TRY(hipEventCreate(&e1));
-        const int blocks[5] = {64, 128, 256, 512, 1024};
         float best = std::numeric_limits<float>::infinity();
-        int bb = s->block, bc = s->cpt;
-        for (int cpt = 1; cpt <= 2; cpt++)
-            for (int b : blocks) {
+        int bb = s->tile;
+        for (int b : TILES) {
                 swe_status r = restore();
                 if (r) return r;
-                s->block = b;
-                s->cpt = cpt;
+                r = s->set_tile(b);
+                if (r) return r;
                 r = s->set_t_end(std::numeric_limits<double>::infinity());
                 if (r) return r;
                 HIP_TRY(s->launch_one());
@@ -666,17 +702,16 @@ swe_status swe_autotune(swe_state *s, int32_t k, int32_t *block_size, int32_t *c
                 if (s->hctrl->flags == 0 && ms < best) {
                     best = ms;
                     bb = b;
-                    bc = cpt;
                 }
-            }
-        s->block = bb;
-        s->cpt = bc;
+        }
+        swe_status r = s->set_tile(bb);
+        if (r) return r;
         return restore();
     }();
     cleanup();
     if (st) return st;
-    if (block_size) *block_size = s->block;
-    if (cells_per_thread) *cells_per_thread = s->cpt;
+    if (block_size) *block_size = s->tile;
+    if (cells_per_thread) *cells_per_thread = 1;
     return SWE_OK;
 }
 
@@ -695,7 +730,7 @@ struct swe_batch {
     int2 *tiles = nullptr;
     size_t tiles_cap = 0;
     int ntiles = 0;
-    int block = 256, cpt = 1, grid = 0;
+    int tile = 256, grid = 0;
     int phase = 0;  // launches so far mod 3; every member is aligned to it
     bool dirty = true;
     hipStream_t cap = nullptr;
@@ -723,26 +758,33 @@ struct swe_batch {
     }
     hipError_t launch(hipStream_t s, int ph) {
         return prec == SWE_FP32
-                   ? launch_step_batched<float>((const Inst<float> *)insts, tiles, ntiles, grid, block, cpt, ph, s)
-                   : launch_step_batched<double>((const Inst<double> *)insts, tiles, ntiles, grid, block, cpt, ph, s);
+                   ? launch_step_batched<float>((const Inst<float> *)insts, tiles, ntiles, grid, tile, ph, s)
+                   : launch_step_batched<double>((const Inst<double> *)insts, tiles, ntiles, grid, tile, ph, s);
     }
     // work list of the members that are still running
     swe_status rebuild() {
         std::vector<Inst<float>> i32;
         std::vector<Inst<double>> i64;
         std::vector<int2> tl;
-        const int per = block * cpt;
         for (size_t m = 0; m < members.size(); m++) {
             swe_state *s = members[m];
             if (!s || finished[m]) continue;
             const int idx = prec == SWE_FP32 ? (int)i32.size() : (int)i64.size();
-            const int nt = (int)((s->m->H.nc + per - 1) / per);
+            swe_status st = prec == SWE_FP32 ? s->m->ensure_tiles<float>(prec, tile)
+                                             : s->m->ensure_tiles<double>(prec, tile);
+            if (st) return st;
+            const TileGeom &tg = s->m->geom[prec][tile_index(tile)];
+            const int nt = tg.ntiles;
             if (prec == SWE_FP32) {
                 Inst<float> I = s->inst32;
+                I.edges = (const Edge<float> *)tg.edges;
+                I.eoff = tg.eoff;
                 I.ntiles = nt;
                 i32.push_back(I);
             } else {
                 Inst<double> I = s->inst64;
+                I.edges = (const Edge<double> *)tg.edges;
+                I.eoff = tg.eoff;
                 I.ntiles = nt;
                 i64.push_back(I);
             }
@@ -768,7 +810,7 @@ struct swe_batch {
             HIP_TRY(hipMemcpyAsync(tiles, tl.data(), tl.size() * sizeof(int2), hipMemcpyHostToDevice, stream()));
         HIP_TRY(hipStreamSynchronize(stream()));
         ntiles = (int)tl.size();
-        grid = prec == SWE_FP32 ? batched_grid<float>(block, cpt) : batched_grid<double>(block, cpt);
+        grid = prec == SWE_FP32 ? batched_grid<float>(tile) : batched_grid<double>(tile);
         if (grid < 1) grid = 1;
         drop_graphs();
         dirty = false;

@@ -1,20 +1,20 @@
 // HIP kernels of the shallow-water step for gfx950 (CDNA4, wave64).
 //
-// One thread updates one cell (or `CPT` cells) of a Hilbert-ordered mesh: it
-// gathers its three neighbours' (H, qx, qy, z), evaluates the three edge
-// fluxes itself (cell-centric: no atomics, no edge buffers, every thread
-// writes only its own cell), applies the conservative update (paper:
-// eq. hydrodynamicupdateformula), the Manning friction split (eq.
-// friction_closure, Table friction_closure) and the positivity clip, and
-// computes the CFL candidate of its new state (eq. CFL_condition).  A wave64
-// shuffle, an LDS pass and one 64-bit atomic min per block give the grid-wide
-// minimum; the last block to arrive advances time on the device, so a run of
-// steps needs no host round trip and can be captured in one hipGraph.
-//
-// Interior edges are evaluated by both adjacent cells.  Both evaluate the
-// flux in the edge's canonical orientation (left = the cell with the smaller
-// original index) from bitwise-identical inputs, so the mass flux one cell
-// loses is exactly the flux the other gains.
+// A block owns a tile of TILE consecutive cells of the Hilbert-ordered mesh.
+// Phase 0 stages the tile's states (H, qx, qy, z) and velocities in LDS.
+// Phase 1 evaluates every edge of the tile once -- hydrostatic reconstruction,
+// HLLC flux, the two fluctuations -- and leaves each cell's contribution in
+// the LDS slot of its local edge (edges to other tiles are evaluated by both
+// tiles, from identical inputs in the edge's canonical orientation, so the
+// mass one cell loses is bitwise the mass the other gains).  Phase 2 gives
+// each cell to one thread: it sums its three contributions in local edge
+// order, applies the conservative update (paper: eq.
+// hydrodynamicupdateformula), the Manning friction split (eq.
+// friction_closure, Table friction_closure) and the positivity clip, writes
+// its new state and computes its CFL candidate (eq. CFL_condition).  A wave64
+// shuffle, an LDS pass and at most one atomic min per block give the next
+// time step; block 0 publishes the next time level, so a run of steps needs no
+// host round trip and can be captured in one hipGraph.
 #include "swe_internal.h"
 
 #include <math.h>
@@ -159,202 +159,6 @@ template <> struct CflMin<float> {
     }
 };
 
-// Updates cell i from U[cur] into U[cur ^ 1] and returns the CFL candidate
-// min_k rho_k / lambda_k of the new state (+inf when nothing constrains it).
-template <typename T>
-__device__ __forceinline__ double cell_update(const Inst<T> &I, int i, int cur, double t, double dt,
-                                              double t_next) {
-    const V4<T> *__restrict__ src = cur ? I.U1 : I.U0;
-    V4<T> *__restrict__ dst = cur ? I.U0 : I.U1;
-    const T g = T(I.g);
-    const double h_min = I.h_min;
-    const V4<T> s = src[i];
-    const V4<T> g0 = I.geo0[i];
-    const V4<T> g1 = I.geo1[i];
-    const int nb[3] = {I.nbr[i], I.nbr[I.n + i], I.nbr[2 * I.n + i]};
-    const T lx[3] = {g0.x, g0.z, g1.x};
-    const T ly[3] = {g0.y, g0.w, g1.y};
-    const T area = g1.z, gn2 = g1.w;
-
-    // primitive variables: velocity only above the minimum depth
-    const double hsd = double(s.x) - double(s.w);
-    const T hs = T(hsd);
-    const bool wet = hsd > h_min;
-    const T u = wet ? qdiv(s.y, hs) : T(0);
-    const T v = wet ? qdiv(s.z, hs) : T(0);
-
-    T R0 = T(0), R1 = T(0), R2 = T(0);
-    T el[3], enx[3], eny[3];
-    int inflow_bc[3] = {-1, -1, -1};
-#pragma unroll
-    for (int k = 0; k < 3; k++) {
-        T l, nx, ny;
-        edge_normal(lx[k], ly[k], l, nx, ny);
-        el[k] = l;
-        enx[k] = nx;
-        eny[k] = ny;
-        // this cell's velocity in the frame (n, t), t = (-ny, nx)
-        const T uns = u * nx + v * ny;
-        const T uts = v * nx - u * ny;
-        const int e = nb[k];
-        T F0, F1, F2, hself;
-        if (e >= 0) {
-            const int j = e & NBR_MASK;
-            const bool flip = (e & NBR_FLIP) != 0;
-            const V4<T> o = src[j];
-            const double hod = double(o.x) - double(o.w);
-            const T ho = T(hod);
-            const bool owet = hod > h_min;
-            const T uo = owet ? qdiv(o.y, ho) : T(0);
-            const T vo = owet ? qdiv(o.z, ho) : T(0);
-            const T uno = uo * nx + vo * ny;
-            const T uto = vo * nx - uo * ny;
-            // hydrostatic reconstruction of the two modified states
-            const double zs = double(s.w > o.w ? s.w : o.w);
-            const double a = double(s.x) - zs, b = double(o.x) - zs;
-            const T hs_s = a < H_DRY ? T(0) : T(a);
-            const T hs_o = b < H_DRY ? T(0) : T(b);
-            // canonical orientation (left = smaller original index); the
-            // normal of the canonical frame is -n when this cell is the right
-            const T hL = flip ? hs_o : hs_s, hR = flip ? hs_s : hs_o;
-            const T unL = flip ? -uno : uns, utL = flip ? -uto : uts;
-            const T unR = flip ? -uns : uno, utR = flip ? -uts : uto;
-            hllc<T>(hL, unL, utL, hR, unR, utR, g, F0, F1, F2);
-            if (flip) F0 = -F0;  // mass leaving this cell through edge k
-            hself = hs_s;
-        } else {
-            const int slot = -1 - e;
-            const int kb = I.slot_kbc[slot];
-            const int kind = kb & 15;
-            const int bi = kb >> 4;
-            // the ghost shares this cell's bed, so z* = z and h* = H - z
-            const T hs_s = hsd < H_DRY ? T(0) : T(hsd);
-            double hg, ung;
-            bool open = false;
-            if (kind == BC_OUTFLOW) {
-                // transmissive: the ghost repeats the interior state
-                hllc<T>(hs_s, uns, uts, hs_s, uns, uts, g, F0, F1, F2);
-                open = true;
-            } else if (kind == BC_INFLOW && inflow_ghost(I.bcs[bi], t, double(gn2), double(g), hg, ung)) {
-                const double b = (double(s.w) + hg) - double(s.w);
-                const T hs_g = b < H_DRY ? T(0) : T(b);
-                hllc<T>(hs_s, uns, uts, hs_g, T(ung), T(0), g, F0, F1, F2);
-                open = true;
-            } else {
-                // reflective, impermeable wall: mirrored normal velocity
-                hllc<T>(hs_s, uns, uts, hs_s, -uns, uts, g, F0, F1, F2);
-                F0 = T(0);
-            }
-            if (kind == BC_INFLOW) inflow_bc[k] = bi;
-            if (open) {
-                double *acc = I.slot_acc + 2 * slot;
-                double sm = acc[0], cp = acc[1];
-                neumaier(sm, cp, dt * double(l * F0));
-                acc[0] = sm;
-                acc[1] = cp;
-            }
-            hself = hs_s;
-        }
-        // fluctuation of this side: the flux minus its own reconstructed
-        // pressure (bed slope in well-balanced form), rotated back
-        const T Dn = F1 - T(0.5) * g * hself * hself;
-        R0 += l * F0;
-        R1 += l * (Dn * nx - F2 * ny);
-        R2 += l * (Dn * ny + F2 * nx);
-    }
-
-    // conservative update (eq. hydrodynamicupdateformula)
-    const T w = T(dt) * qdiv(T(1), area);
-    T Hn = s.x - w * R0;
-    T qx = s.y - w * R1;
-    T qy = s.z - w * R2;
-    const double hn = double(Hn) - double(s.w);
-    // friction split: exact solution of dq/dt = -g n^2 |q| q / h^(7/3)
-    T f;
-    if (hn > h_min) {
-        if (gn2 > T(0)) {
-            const T qa = qsqrt(qx * qx + qy * qy);
-            f = qdiv(T(1), T(1) + qdiv(T(dt) * gn2 * qa, pow73<T>(T(hn))));
-        } else {
-            f = T(1);
-        }
-    } else {
-        f = T(0);
-    }
-    qx = qx * f;
-    qy = qy * f;
-    if (hn < 0.0) {
-        // positivity: clip and account for the added volume
-        atomicAdd(&I.ctrl->clipped, -hn * I.area[i]);
-        atomicAdd(&I.ctrl->nclip, 1ull);
-        if (I.neg_policy) atomicOr(&I.ctrl->flags, FLAG_NEGDEPTH);
-        Hn = s.w;
-        qx = T(0);
-        qy = T(0);
-    }
-    if (!isfinite(Hn) || !isfinite(qx) || !isfinite(qy)) atomicOr(&I.ctrl->flags, FLAG_NONFINITE);
-    dst[i] = make4<T>(Hn, qx, qy, s.w);
-
-    // CFL candidate of the new state over wet cells and inflow ghosts
-    CflMin<T> cfl(area);
-    const double h2 = double(Hn) - double(s.w);
-    if (h2 > h_min) {
-        const T hh = T(h2);
-        const T u2 = qdiv(qx, hh), v2 = qdiv(qy, hh);
-        const T c = qsqrt(g * hh);
-#pragma unroll
-        for (int k = 0; k < 3; k++) {
-            const T lam = fabs(u2 * enx[k] + v2 * eny[k]) + c;
-            cfl.add(double(el[k]), double(lam));
-        }
-    }
-#pragma unroll
-    for (int k = 0; k < 3; k++) {
-        if (inflow_bc[k] >= 0) {
-            double hg, ung;
-            if (inflow_ghost(I.bcs[inflow_bc[k]], t_next, double(gn2), double(g), hg, ung))
-                cfl.add(double(el[k]), fabs(ung) + sqrt(double(g) * hg));
-        }
-    }
-    return cfl.value();
-}
-
-// CFL candidate of the current state (first step after an initialisation);
-// the same arithmetic as the epilogue of cell_update.
-template <typename T>
-__device__ __forceinline__ double cell_candidate(const Inst<T> &I, int i, int cur, double t) {
-    const V4<T> *__restrict__ src = cur ? I.U1 : I.U0;
-    const T g = T(I.g);
-    const V4<T> s = src[i];
-    const V4<T> g0 = I.geo0[i];
-    const V4<T> g1 = I.geo1[i];
-    const int nb[3] = {I.nbr[i], I.nbr[I.n + i], I.nbr[2 * I.n + i]};
-    const T lx[3] = {g0.x, g0.z, g1.x};
-    const T ly[3] = {g0.y, g0.w, g1.y};
-    CflMin<T> cfl(g1.z);
-    const double hd = double(s.x) - double(s.w);
-    const T hh = T(hd);
-    const bool wet = hd > I.h_min;
-    const T u = wet ? qdiv(s.y, hh) : T(0), v = wet ? qdiv(s.z, hh) : T(0);
-    const T c = wet ? qsqrt(g * hh) : T(0);
-#pragma unroll
-    for (int k = 0; k < 3; k++) {
-        T l, nx, ny;
-        edge_normal(lx[k], ly[k], l, nx, ny);
-        if (wet) {
-            const T lam = fabs(u * nx + v * ny) + c;
-            cfl.add(double(l), double(lam));
-        }
-        if (nb[k] < 0) {
-            const int kb = I.slot_kbc[-1 - nb[k]];
-            double hg, ung;
-            if ((kb & 15) == BC_INFLOW && inflow_ghost(I.bcs[kb >> 4], t, double(g1.w), double(g), hg, ung))
-                cfl.add(double(l), fabs(ung) + sqrt(double(g) * hg));
-        }
-    }
-    return cfl.value();
-}
-
 __device__ __forceinline__ double wave_min(double v) {
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) v = fmin(v, __shfl_xor(v, off, 64));
@@ -437,25 +241,246 @@ __device__ __forceinline__ void block_finish(Ctrl *c, int phase, double cand, co
     __syncthreads();  // wmin may be reused by a following tile
 }
 
-template <typename T, int CPT>
-__global__ void __launch_bounds__(1024) k_step(Inst<T> I, int phase) {
+// LDS of one tile: states, velocities, and per (local edge, cell) the three
+// contribution components and the edge geometry the CFL candidate needs.
+template <typename T, int TILE> struct TileLds {
+    V4<T> st[TILE];
+    T u[TILE], v[TILE];
+    T c[3][3][TILE];   // [component][local edge][cell]
+    T l[3][TILE], nx[3][TILE], ny[3][TILE];
+    int inflow[3][TILE];  // inflow condition index of a boundary edge, else -1
+};
+
+// Phases 0 and 1 for tile `tile` at time t (UPDATE = false: geometry only).
+template <typename T, int TILE, bool UPDATE>
+__device__ __forceinline__ void tile_edges(const Inst<T> &I, TileLds<T, TILE> &S, int tile, int cur, double t,
+                                           double dt) {
+    const V4<T> *__restrict__ src = cur ? I.U1 : I.U0;
+    const T g = T(I.g);
+    const double h_min = I.h_min;
+    const int c = threadIdx.x;
+    const int i = tile * TILE + c;
+    if (i < I.n) {
+        const V4<T> s = src[i];
+        S.st[c] = s;
+        // velocity only above the minimum depth
+        const double hd = double(s.x) - double(s.w);
+        const bool wet = hd > h_min;
+        const T h = T(hd);
+        S.u[c] = wet ? qdiv(s.y, h) : T(0);
+        S.v[c] = wet ? qdiv(s.z, h) : T(0);
+    }
+#pragma unroll
+    for (int k = 0; k < 3; k++) S.inflow[k][c] = -1;
+    __syncthreads();
+    const int e1 = I.eoff[tile + 1];
+    for (int e = I.eoff[tile] + c; e < e1; e += TILE) {
+        const Edge<T> E = I.edges[e];
+        const int a = E.w0 & 1023, ka = (E.w0 >> 10) & 3, kb = (E.w0 >> 12) & 3, kind = (E.w0 >> 14) & 3;
+        const bool flip = (E.w0 >> 16) & 1;
+        T l, nx, ny;
+        edge_normal(E.lx, E.ly, l, nx, ny);  // n: outward of a
+        S.l[ka][a] = l;
+        S.nx[ka][a] = nx;
+        S.ny[ka][a] = ny;
+        if (kind == EK_LOCAL) {
+            const int b = (E.w0 >> 17) & 1023;
+            S.l[kb][b] = l;
+            S.nx[kb][b] = -nx;
+            S.ny[kb][b] = -ny;
+        }
+        if (!UPDATE) {
+            if (kind == EK_BOUNDARY) {
+                const int kbc = I.slot_kbc[E.w1];
+                if ((kbc & 15) == BC_INFLOW) S.inflow[ka][a] = kbc >> 4;
+            }
+            continue;
+        }
+        const V4<T> sa = S.st[a];
+        const T ua = S.u[a], va = S.v[a];
+        // a's velocity in the frame (n, t), t = (-ny, nx)
+        const T una = ua * nx + va * ny;
+        const T uta = va * nx - ua * ny;
+        T F0, F1, F2, ha, hb = T(0);
+        if (kind != EK_BOUNDARY) {
+            V4<T> sb;
+            T ub, vb;
+            if (kind == EK_LOCAL) {
+                const int b = (E.w0 >> 17) & 1023;
+                sb = S.st[b];
+                ub = S.u[b];
+                vb = S.v[b];
+            } else {
+                sb = src[E.w1];
+                const double hbd = double(sb.x) - double(sb.w);
+                const bool bwet = hbd > h_min;
+                const T hh = T(hbd);
+                ub = bwet ? qdiv(sb.y, hh) : T(0);
+                vb = bwet ? qdiv(sb.z, hh) : T(0);
+            }
+            const T unb = ub * nx + vb * ny;
+            const T utb = vb * nx - ub * ny;
+            // hydrostatic reconstruction of the two modified states
+            const double zs = double(sa.w > sb.w ? sa.w : sb.w);
+            const double da = double(sa.x) - zs, db = double(sb.x) - zs;
+            ha = da < H_DRY ? T(0) : T(da);
+            hb = db < H_DRY ? T(0) : T(db);
+            // canonical orientation (left = smaller original index); the
+            // canonical normal is -n when a is the right cell
+            const T hL = flip ? hb : ha, hR = flip ? ha : hb;
+            const T unL = flip ? -unb : una, utL = flip ? -utb : uta;
+            const T unR = flip ? -una : unb, utR = flip ? -uta : utb;
+            hllc<T>(hL, unL, utL, hR, unR, utR, g, F0, F1, F2);
+            if (flip) F0 = -F0;  // mass leaving a
+        } else {
+            const int slot = E.w1;
+            const int kbc = I.slot_kbc[slot];
+            const int bkind = kbc & 15, bi = kbc >> 4;
+            // the ghost shares a's bed, so z* = z and h* = H - z
+            const double da = double(sa.x) - double(sa.w);
+            ha = da < H_DRY ? T(0) : T(da);
+            double hg, ung;
+            bool open = false;
+            if (bkind == BC_OUTFLOW) {
+                // transmissive: the ghost repeats the interior state
+                hllc<T>(ha, una, uta, ha, una, uta, g, F0, F1, F2);
+                open = true;
+            } else if (bkind == BC_INFLOW && inflow_ghost(I.bcs[bi], t, double(I.cellp[tile * TILE + a].y),
+                                                          double(g), hg, ung)) {
+                const double dg = (double(sa.w) + hg) - double(sa.w);
+                const T hgs = dg < H_DRY ? T(0) : T(dg);
+                hllc<T>(ha, una, uta, hgs, T(ung), T(0), g, F0, F1, F2);
+                open = true;
+            } else {
+                // reflective, impermeable wall: mirrored normal velocity
+                hllc<T>(ha, una, uta, ha, -una, uta, g, F0, F1, F2);
+                F0 = T(0);
+            }
+            if (bkind == BC_INFLOW) S.inflow[ka][a] = bi;
+            if (open) {
+                double *acc = I.slot_acc + 2 * slot;
+                double sm = acc[0], cp = acc[1];
+                neumaier(sm, cp, dt * double(l * F0));
+                acc[0] = sm;
+                acc[1] = cp;
+            }
+        }
+        // fluctuations: the flux minus each side's reconstructed pressure
+        // (bed slope in well-balanced form), rotated back
+        const T Da = F1 - T(0.5) * g * ha * ha;
+        S.c[0][ka][a] = l * F0;
+        S.c[1][ka][a] = l * (Da * nx - F2 * ny);
+        S.c[2][ka][a] = l * (Da * ny + F2 * nx);
+        if (kind == EK_LOCAL) {
+            const int b = (E.w0 >> 17) & 1023;
+            const T Db = F1 - T(0.5) * g * hb * hb;
+            S.c[0][kb][b] = -(l * F0);
+            S.c[1][kb][b] = -(l * (Db * nx - F2 * ny));
+            S.c[2][kb][b] = -(l * (Db * ny + F2 * nx));
+        }
+    }
+    __syncthreads();
+}
+
+// CFL candidate of cell c of the tile with state (H, qx, qy, z), from the
+// edge geometry left in LDS: min over edges of rho / lambda over wet cells
+// and inflow ghosts (at time t).
+template <typename T, int TILE>
+__device__ __forceinline__ double tile_candidate(const Inst<T> &I, const TileLds<T, TILE> &S, int c, T area,
+                                                 T gn2, T H, T qx, T qy, T z, double t) {
+    const T g = T(I.g);
+    CflMin<T> cfl(area);
+    const double h2 = double(H) - double(z);
+    if (h2 > I.h_min) {
+        const T hh = T(h2);
+        const T u2 = qdiv(qx, hh), v2 = qdiv(qy, hh);
+        const T cc = qsqrt(g * hh);
+#pragma unroll
+        for (int k = 0; k < 3; k++) {
+            const T lam = fabs(u2 * S.nx[k][c] + v2 * S.ny[k][c]) + cc;
+            cfl.add(double(S.l[k][c]), double(lam));
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < 3; k++) {
+        const int bi = S.inflow[k][c];
+        if (bi >= 0) {
+            double hg, ung;
+            if (inflow_ghost(I.bcs[bi], t, double(gn2), double(g), hg, ung))
+                cfl.add(double(S.l[k][c]), fabs(ung) + sqrt(double(g) * hg));
+        }
+    }
+    return cfl.value();
+}
+
+// Phase 2 for cell c of tile `tile`: update, friction, clip, write; returns
+// the CFL candidate of the new state.
+template <typename T, int TILE>
+__device__ __forceinline__ double tile_update(const Inst<T> &I, const TileLds<T, TILE> &S, int tile, int cur,
+                                              double dt, double t_next) {
+    const int c = threadIdx.x;
+    const int i = tile * TILE + c;
+    if (i >= I.n) return INFINITY;
+    V4<T> *__restrict__ dst = cur ? I.U0 : I.U1;
+    const double h_min = I.h_min;
+    const V4<T> s = S.st[c];
+    const V2<T> cp = I.cellp[i];
+    const T area = cp.x, gn2 = cp.y;
+    // residual in local edge order, then the conservative update
+    const T R0 = S.c[0][0][c] + S.c[0][1][c] + S.c[0][2][c];
+    const T R1 = S.c[1][0][c] + S.c[1][1][c] + S.c[1][2][c];
+    const T R2 = S.c[2][0][c] + S.c[2][1][c] + S.c[2][2][c];
+    const T w = T(dt) * qdiv(T(1), area);
+    T Hn = s.x - w * R0;
+    T qx = s.y - w * R1;
+    T qy = s.z - w * R2;
+    const double hn = double(Hn) - double(s.w);
+    // friction split: exact solution of dq/dt = -g n^2 |q| q / h^(7/3)
+    T f;
+    if (hn > h_min) {
+        if (gn2 > T(0)) {
+            const T qa = qsqrt(qx * qx + qy * qy);
+            f = qdiv(T(1), T(1) + qdiv(T(dt) * gn2 * qa, pow73<T>(T(hn))));
+        } else {
+            f = T(1);
+        }
+    } else {
+        f = T(0);
+    }
+    qx = qx * f;
+    qy = qy * f;
+    if (hn < 0.0) {
+        // positivity: clip and account for the added volume
+        atomicAdd(&I.ctrl->clipped, -hn * I.area[i]);
+        atomicAdd(&I.ctrl->nclip, 1ull);
+        if (I.neg_policy) atomicOr(&I.ctrl->flags, FLAG_NEGDEPTH);
+        Hn = s.w;
+        qx = T(0);
+        qy = T(0);
+    }
+    if (!isfinite(Hn) || !isfinite(qx) || !isfinite(qy)) atomicOr(&I.ctrl->flags, FLAG_NONFINITE);
+    dst[i] = make4<T>(Hn, qx, qy, s.w);
+    return tile_candidate<T, TILE>(I, S, c, area, gn2, Hn, qx, qy, s.w, t_next);
+}
+
+// Occupancy hint: five waves per SIMD, the register budget the FP32 body fits
+// without spilling (the FP64 body is limited by LDS instead).
+template <typename T, int TILE>
+__global__ void __launch_bounds__(TILE, 5 * 256 / TILE) k_step(Inst<T> I, int phase) {
+    __shared__ TileLds<T, TILE> S;
     const bool lead = blockIdx.x == 0;
     const Level L = step_setup(I.ctrl, phase, I.cfl, I.dt_max, lead);
     if (!L.run) return;
-    const double t_next = L.t + L.dt;
-    double cand = INFINITY;
-#pragma unroll
-    for (int r = 0; r < CPT; r++) {
-        const int i = (blockIdx.x * CPT + r) * blockDim.x + threadIdx.x;
-        if (i < I.n) cand = fmin(cand, cell_update<T>(I, i, L.cur, L.t, L.dt, t_next));
-    }
+    tile_edges<T, TILE, true>(I, S, blockIdx.x, L.cur, L.t, L.dt);
+    const double cand = tile_update<T, TILE>(I, S, blockIdx.x, L.cur, L.dt, L.t + L.dt);
     block_finish(I.ctrl, phase, cand, L, lead, true);
 }
 
 // CFL minimum of the state of level `phase` (after an initialisation); the
 // host clears the slot first.
-template <typename T>
-__global__ void __launch_bounds__(256) k_dt_init(Inst<T> I, int phase) {
+template <typename T, int TILE>
+__global__ void __launch_bounds__(TILE) k_dt_init(Inst<T> I, int phase) {
+    __shared__ TileLds<T, TILE> S;
     const Ctrl *c = I.ctrl;
     Level L;
     L.t = c->s[phase].t;
@@ -464,33 +489,32 @@ __global__ void __launch_bounds__(256) k_dt_init(Inst<T> I, int phase) {
     L.steps = 0;
     L.rawmin = 0.0;
     L.run = true;
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    tile_edges<T, TILE, false>(I, S, blockIdx.x, L.cur, L.t, 0.0);
     double cand = INFINITY;
-    if (i < I.n) cand = cell_candidate<T>(I, i, L.cur, L.t);
+    const int i = blockIdx.x * TILE + threadIdx.x;
+    if (i < I.n) {
+        const V4<T> s = S.st[threadIdx.x];
+        const V2<T> cp = I.cellp[i];
+        cand = tile_candidate<T, TILE>(I, S, threadIdx.x, cp.x, cp.y, s.x, s.y, s.z, s.w, L.t);
+    }
     block_finish(I.ctrl, phase, cand, L, false, false);
 }
 
 // Persistent batched step: blocks stride over a list of (member, tile)
 // pairs; each member keeps its own control block, so members step with their
 // own dt and finished members cost one control-block read per tile.
-template <typename T, int CPT>
-__global__ void __launch_bounds__(256) k_step_batched(const Inst<T> *__restrict__ insts,
-                                                       const int2 *__restrict__ tiles, int ntiles, int phase) {
+template <typename T, int TILE>
+__global__ void __launch_bounds__(TILE, 5 * 256 / TILE) k_step_batched(const Inst<T> *__restrict__ insts,
+                                                        const int2 *__restrict__ tiles, int ntiles, int phase) {
+    __shared__ TileLds<T, TILE> S;
     for (int tt = blockIdx.x; tt < ntiles; tt += gridDim.x) {
-        // the tile is the same for the whole block: keep its record scalar
-        const int2 td = make_int2(__builtin_amdgcn_readfirstlane(tiles[tt].x),
-                                  __builtin_amdgcn_readfirstlane(tiles[tt].y));
+        const int2 td = tiles[tt];
         const Inst<T> I = insts[td.x];
         const bool lead = td.y == 0;
         const Level L = step_setup(I.ctrl, phase, I.cfl, I.dt_max, lead);
         if (!L.run) continue;
-        const double t_next = L.t + L.dt;
-        double cand = INFINITY;
-#pragma unroll
-        for (int r = 0; r < CPT; r++) {
-            const int i = (td.y * CPT + r) * blockDim.x + threadIdx.x;
-            if (i < I.n) cand = fmin(cand, cell_update<T>(I, i, L.cur, L.t, L.dt, t_next));
-        }
+        tile_edges<T, TILE, true>(I, S, td.y, L.cur, L.t, L.dt);
+        const double cand = tile_update<T, TILE>(I, S, td.y, L.cur, L.dt, L.t + L.dt);
         block_finish(I.ctrl, phase, cand, L, lead, true);
     }
 }
@@ -547,23 +571,25 @@ __global__ void __launch_bounds__(MASS_THREADS) k_mass_final(Inst<T> I, const do
 
 }  // namespace
 
+#define SWE_TILE_DISPATCH(tile, KERNEL, ...)                                               \
+    switch (tile) {                                                                        \
+        case 128: hipLaunchKernelGGL((KERNEL<T, 128>), __VA_ARGS__); break;                \
+        case 256: hipLaunchKernelGGL((KERNEL<T, 256>), __VA_ARGS__); break;                \
+        case 512: hipLaunchKernelGGL((KERNEL<T, 512>), __VA_ARGS__); break;                \
+        default: return hipErrorInvalidValue;                                              \
+    }
+
 template <typename T>
-hipError_t launch_step(const Inst<T> &I, int block, int cpt, int phase, hipStream_t s) {
+hipError_t launch_step(const Inst<T> &I, int tile, int phase, hipStream_t s) {
     if (I.n <= 0) return hipSuccess;
-    const int per = block * cpt;
-    const int grid = (I.n + per - 1) / per;
-    if (cpt == 2)
-        hipLaunchKernelGGL((k_step<T, 2>), dim3(grid), dim3(block), 0, s, I, phase);
-    else
-        hipLaunchKernelGGL((k_step<T, 1>), dim3(grid), dim3(block), 0, s, I, phase);
+    SWE_TILE_DISPATCH(tile, k_step, dim3(I.ntiles), dim3(tile), 0, s, I, phase)
     return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_dt_init(const Inst<T> &I, int phase, hipStream_t s) {
+hipError_t launch_dt_init(const Inst<T> &I, int tile, int phase, hipStream_t s) {
     if (I.n <= 0) return hipSuccess;
-    const int grid = (I.n + 255) / 256;
-    hipLaunchKernelGGL((k_dt_init<T>), dim3(grid), dim3(256), 0, s, I, phase);
+    SWE_TILE_DISPATCH(tile, k_dt_init, dim3(I.ntiles), dim3(tile), 0, s, I, phase)
     return hipGetLastError();
 }
 
@@ -576,38 +602,36 @@ hipError_t launch_mass(const Inst<T> &I, double2 *partials, double *out, int nsl
 }
 
 template <typename T>
-int batched_grid(int block, int cpt) {
+int batched_grid(int tile) {
     int dev = 0, cus = 0, per = 0;
     if (hipGetDevice(&dev) != hipSuccess) return 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
     hipError_t e;
-    if (cpt == 2)
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, (const void *)k_step_batched<T, 2>, block, 0);
-    else
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, (const void *)k_step_batched<T, 1>, block, 0);
+    switch (tile) {
+        case 128: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, (const void *)k_step_batched<T, 128>, 128, 0); break;
+        case 256: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, (const void *)k_step_batched<T, 256>, 256, 0); break;
+        case 512: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, (const void *)k_step_batched<T, 512>, 512, 0); break;
+        default: return 0;
+    }
     if (e != hipSuccess || per < 1) per = 1;
     return cus * per;
 }
 
 template <typename T>
-hipError_t launch_step_batched(const Inst<T> *insts, const int2 *tiles, int ntiles, int grid, int block, int cpt,
-                               int phase, hipStream_t s) {
+hipError_t launch_step_batched(const Inst<T> *insts, const int2 *tiles, int ntiles, int grid, int tile, int phase,
+                               hipStream_t s) {
     if (ntiles <= 0) return hipSuccess;
     if (grid > ntiles) grid = ntiles;
-    if (cpt == 2)
-        hipLaunchKernelGGL((k_step_batched<T, 2>), dim3(grid), dim3(block), 0, s, insts, tiles, ntiles, phase);
-    else
-        hipLaunchKernelGGL((k_step_batched<T, 1>), dim3(grid), dim3(block), 0, s, insts, tiles, ntiles, phase);
+    SWE_TILE_DISPATCH(tile, k_step_batched, dim3(grid), dim3(tile), 0, s, insts, tiles, ntiles, phase)
     return hipGetLastError();
 }
 
 #define SWE_INSTANTIATE(T)                                                                                  \
-    template hipError_t launch_step<T>(const Inst<T> &, int, int, int, hipStream_t);                        \
-    template hipError_t launch_dt_init<T>(const Inst<T> &, int, hipStream_t);                               \
+    template hipError_t launch_step<T>(const Inst<T> &, int, int, hipStream_t);                             \
+    template hipError_t launch_dt_init<T>(const Inst<T> &, int, int, hipStream_t);                          \
     template hipError_t launch_mass<T>(const Inst<T> &, double2 *, double *, int, int, hipStream_t);        \
-    template hipError_t launch_step_batched<T>(const Inst<T> *, const int2 *, int, int, int, int, int,      \
-                                               hipStream_t);                                                \
-    template int batched_grid<T>(int, int);
+    template hipError_t launch_step_batched<T>(const Inst<T> *, const int2 *, int, int, int, int, hipStream_t); \
+    template int batched_grid<T>(int);
 SWE_INSTANTIATE(float)
 SWE_INSTANTIATE(double)
 

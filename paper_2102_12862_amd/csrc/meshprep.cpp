@@ -199,4 +199,95 @@ bool prepare_mesh(const double *xyz, int64_t nv, const int32_t *tri, int64_t nc,
     return true;
 }
 
+bool build_tile_edges(const HostMesh &M, int tile, std::vector<TileEdge> &edges, std::vector<int32_t> &eoff) {
+    if (tile < 64 || tile > MAX_TILE) return false;
+    const int64_t n = M.nc;
+    const int64_t ntiles = (n + tile - 1) / tile;
+    edges.clear();
+    edges.reserve((size_t)(n * 7 / 4 + ntiles * 64));
+    eoff.assign((size_t)ntiles + 1, 0);
+    for (int64_t t = 0; t < ntiles; t++) {
+        eoff[t] = (int32_t)edges.size();
+        const int64_t p0 = t * tile, p1 = std::min(n, p0 + tile);
+        for (int64_t p = p0; p < p1; p++) {
+            for (int k = 0; k < 3; k++) {
+                const int32_t code = M.nbr[3 * p + k];
+                TileEdge e;
+                e.lx = M.lx[3 * p + k];
+                e.ly = M.ly[3 * p + k];
+                int32_t w0 = (int32_t)(p - p0) | (k << 10);
+                if (code >= 0) {
+                    const int32_t q = code & (NBR_FLIP_BIT - 1);
+                    if (code & NBR_FLIP_BIT) w0 |= 1 << 16;
+                    if (q >= p0 && q < p1) {
+                        if (q < p) continue;  // emitted from the other cell
+                        int kb = -1;
+                        for (int k2 = 0; k2 < 3; k2++) {
+                            const int32_t c2 = M.nbr[3 * q + k2];
+                            if (c2 >= 0 && (c2 & (NBR_FLIP_BIT - 1)) == p) kb = k2;
+                        }
+                        if (kb < 0) return false;
+                        w0 |= (kb << 12) | (EDGE_LOCAL << 14) | (int32_t)((q - p0) << 17);
+                        e.w1 = q;
+                    } else {
+                        w0 |= EDGE_REMOTE << 14;
+                        e.w1 = q;
+                    }
+                } else {
+                    w0 |= EDGE_BOUNDARY << 14;
+                    e.w1 = -1 - code;
+                }
+                e.w0 = w0;
+                edges.push_back(e);
+            }
+        }
+    }
+    eoff[ntiles] = (int32_t)edges.size();
+    return edges.size() < (size_t)INT32_MAX;
+}
+
+std::string check_tile_edges(const HostMesh &M, int tile, const std::vector<TileEdge> &edges,
+                             const std::vector<int32_t> &eoff) {
+    const int64_t n = M.nc;
+    const int64_t ntiles = (n + tile - 1) / tile;
+    if ((int64_t)eoff.size() != ntiles + 1 || eoff[0] != 0 || eoff[ntiles] != (int32_t)edges.size())
+        return "bad tile offsets";
+    std::vector<int8_t> seen((size_t)(3 * n), 0);
+    for (int64_t t = 0; t < ntiles; t++) {
+        if (eoff[t] > eoff[t + 1]) return "decreasing tile offsets";
+        const int64_t p0 = t * tile;
+        for (int32_t e = eoff[t]; e < eoff[t + 1]; e++) {
+            const TileEdge &E = edges[e];
+            const int a = E.w0 & 1023, ka = (E.w0 >> 10) & 3, kb = (E.w0 >> 12) & 3, kind = (E.w0 >> 14) & 3;
+            const int flip = (E.w0 >> 16) & 1;
+            const int64_t pa = p0 + a;
+            if (a >= tile || pa >= n || ka > 2) return "edge cell outside its tile";
+            if (E.lx != M.lx[3 * pa + ka] || E.ly != M.ly[3 * pa + ka]) return "edge geometry differs from its cell";
+            const int32_t code = M.nbr[3 * pa + ka];
+            seen[3 * pa + ka]++;
+            if (kind == EDGE_BOUNDARY) {
+                if (code >= 0 || E.w1 != -1 - code) return "boundary edge mismatch";
+            } else {
+                if (code < 0) return "interior edge on a boundary slot";
+                const int32_t q = code & (NBR_FLIP_BIT - 1);
+                if (flip != ((code & NBR_FLIP_BIT) ? 1 : 0)) return "orientation flag mismatch";
+                if (E.w1 != q) return "neighbour id mismatch";
+                const bool local = q >= p0 && q < std::min(n, p0 + tile);
+                if ((kind == EDGE_LOCAL) != local) return "local/remote classification wrong";
+                if (kind == EDGE_LOCAL) {
+                    const int b = (E.w0 >> 17) & 1023;
+                    if (p0 + b != q || kb > 2) return "local neighbour index mismatch";
+                    if ((M.nbr[3 * q + kb] & (NBR_FLIP_BIT - 1)) != pa || M.nbr[3 * q + kb] < 0)
+                        return "neighbour's local edge mismatch";
+                    if (M.lx[3 * q + kb] != -E.lx || M.ly[3 * q + kb] != -E.ly) return "edge normals not opposite";
+                    seen[3 * q + kb]++;
+                }
+            }
+        }
+    }
+    for (int64_t k = 0; k < 3 * n; k++)
+        if (seen[k] != 1) return "a cell edge is covered " + std::to_string((int)seen[k]) + " times";
+    return "";
+}
+
 }  // namespace swe

@@ -24,6 +24,29 @@ struct HostMesh {
     std::vector<int32_t> slot_cell;
 };
 
+// One edge of a tile (a block of `tile` consecutive cells), stored once per
+// tile: an edge between two cells of the tile appears once, an edge to a
+// cell of another tile or to the boundary appears in the tile of its cell.
+//   w0: bits 0-9 local cell a, 10-11 its local edge ka, 12-13 the other
+//       cell's local edge kb, 14-15 kind (0 both cells in the tile, 1 other
+//       cell in another tile, 2 boundary), bit 16 set when a is the right
+//       cell of the edge's canonical orientation, bits 17-26 local cell b
+//   w1: kind 1: device id of the other cell; kind 2: boundary slot
+//   lx, ly: l * n with n the outward normal of a
+enum : int32_t { EDGE_LOCAL = 0, EDGE_REMOTE = 1, EDGE_BOUNDARY = 2 };
+struct TileEdge {
+    int32_t w0, w1;
+    double lx, ly;
+};
+constexpr int MAX_TILE = 1024;
+
+bool build_tile_edges(const HostMesh &M, int tile, std::vector<TileEdge> &edges, std::vector<int32_t> &eoff);
+// Checks that the tile edge lists cover every (cell, local edge) exactly once
+// with consistent indices, orientation and geometry; returns an empty string
+// or the first problem found.
+std::string check_tile_edges(const HostMesh &M, int tile, const std::vector<TileEdge> &edges,
+                             const std::vector<int32_t> &eoff);
+
 bool prepare_mesh(const double *xyz, int64_t nv, const int32_t *tri, int64_t nc, const int32_t *seg,
                   const int32_t *tag, int64_t ns, bool renumber, HostMesh &M, std::string &err);
 

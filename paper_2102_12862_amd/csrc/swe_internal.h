@@ -7,15 +7,15 @@
 
 namespace swe {
 
-// Per-cell device layout (Hilbert-renumbered cells, structure of vec4s):
-//   U[2][n]  vec4: (H, qx, qy, z)          ping-pong state, z carried for gathers
-//   geo0[n]  vec4: (lx0, ly0, lx1, ly1)    l_k * n_k (outward) of local edges 0,1
-//   geo1[n]  vec4: (lx2, ly2, 1/|cell|, g n^2)
-//   nbr[3][n] int: neighbour of local edge k (bit 30 set when this cell is the
-//                  right-hand cell of the edge's canonical orientation), or
-//                  -1 - slot for a boundary edge
-// The l*n pair of an interior edge is stored exactly negated in its two cells,
-// so both cells recover bitwise opposite unit normals.
+// Device layout (cells renumbered along a Hilbert curve of their centroids):
+//   U[2][n]   vec4 (H, qx, qy, z)  ping-pong state; z rides along so a cell's
+//             whole state is one vector load
+//   cellp[n]  vec2 (|cell|, g n^2)
+//   edges     per tile of TILE consecutive cells, every edge touching the tile
+//             once (see TileEdge in meshprep.h): two ints and l*n
+//   eoff      first edge of each tile
+// A block owns one tile: it stages the tile's states in LDS, evaluates each of
+// the tile's edges once, then updates its cells.
 constexpr int NBR_FLIP = 1 << 30;
 constexpr int NBR_MASK = NBR_FLIP - 1;
 
@@ -23,6 +23,17 @@ template <typename T> struct V4T;
 template <> struct V4T<float> { using type = float4; };
 template <> struct V4T<double> { using type = double4; };
 template <typename T> using V4 = typename V4T<T>::type;
+template <typename T> struct V2T;
+template <> struct V2T<float> { using type = float2; };
+template <> struct V2T<double> { using type = double2; };
+template <typename T> using V2 = typename V2T<T>::type;
+
+// Edge record on the device (the host TileEdge with l*n in precision T).
+template <typename T> struct alignas(sizeof(T) == 4 ? 16 : 8) Edge {
+    int w0, w1;
+    T lx, ly;
+};
+enum : int { EK_LOCAL = 0, EK_REMOTE = 1, EK_BOUNDARY = 2 };
 
 enum : int { BC_WALL = 0, BC_INFLOW = 1, BC_OUTFLOW = 2 };
 enum : int { FLAG_NONFINITE = 1, FLAG_NEGDEPTH = 2, FLAG_NODT = 4 };
@@ -75,16 +86,16 @@ constexpr unsigned long long INF_BITS = 0x7FF0000000000000ull;
 template <typename T> struct Inst {
     V4<T> *U0;
     V4<T> *U1;
-    const V4<T> *geo0;
-    const V4<T> *geo1;
-    const int *nbr;        // 3 arrays of n ints, back to back
+    const V2<T> *cellp;    // (|cell|, g n^2)
+    const Edge<T> *edges;  // tile edge lists
+    const int *eoff;       // first edge of each tile (ntiles + 1)
     const int *slot_kbc;   // per boundary slot: kind | (bc index << 4)
     double *slot_acc;      // per boundary slot: Neumaier (sum, compensation)
     const BCdev *bcs;
-    const double *area;    // |cell|, for clip volume and mass
+    const double *area;    // |cell| in FP64, for the mass sum
     Ctrl *ctrl;
     int n;
-    int ntiles;            // blocks of one step (batched kernel)
+    int ntiles;            // tiles of this state's mesh
     double g, cfl, h_min, dt_max;
     int neg_policy;
     int pad;
@@ -92,16 +103,16 @@ template <typename T> struct Inst {
 
 // Launch wrappers (kernels.hip).
 template <typename T>
-hipError_t launch_step(const Inst<T> &I, int block, int cpt, int phase, hipStream_t s);
+hipError_t launch_step(const Inst<T> &I, int tile, int phase, hipStream_t s);
 template <typename T>
-hipError_t launch_dt_init(const Inst<T> &I, int phase, hipStream_t s);
+hipError_t launch_dt_init(const Inst<T> &I, int tile, int phase, hipStream_t s);
 template <typename T>
 hipError_t launch_mass(const Inst<T> &I, double2 *partials, double *out, int nslots, int phase, hipStream_t s);
 template <typename T>
-hipError_t launch_step_batched(const Inst<T> *insts, const int2 *tiles, int ntiles, int grid, int block,
-                               int cpt, int phase, hipStream_t s);
+hipError_t launch_step_batched(const Inst<T> *insts, const int2 *tiles, int ntiles, int grid, int tile, int phase,
+                               hipStream_t s);
 template <typename T>
-int batched_grid(int block, int cpt);
+int batched_grid(int tile);
 constexpr int MASS_BLOCKS = 1024;
 constexpr int MASS_THREADS = 256;
 

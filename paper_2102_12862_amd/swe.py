@@ -55,6 +55,7 @@ SIGNATURES = {
     "swe_mesh_destroy": (None, [ctypes.c_void_p]),
     "swe_mesh_info": (None, [ctypes.c_void_p, _lp, _lp, _lp]),
     "swe_state_footprint": (ctypes.c_int64, [ctypes.c_void_p, ctypes.c_int32]),
+    "swe_mesh_check": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32]),
     "swe_state_init": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(SweParams), _dp, _dp, _dp, _dp, _dp,
                                         ctypes.POINTER(SweBC), ctypes.c_int32, ctypes.c_double,
                                         ctypes.POINTER(ctypes.c_void_p)]),
@@ -184,6 +185,9 @@ class Mesh:
 
     def footprint(self, precision=FP32):
         return load().swe_state_footprint(self._h, precision)
+
+    def check(self, tile=256):
+        _check(load().swe_mesh_check(self._h, tile))
 
     def close(self):
         if getattr(self, "_h", None):

@@ -29,7 +29,7 @@ def test_fullsize_fp32_three_steps(valley_wet, valley_oracle):
     sc = S.Scenario(**{**valley_wet.__dict__})
     assert sc.n_cells > 3_900_000
     sc.dt_max = 0.5 * oracle.Sim(sc, mesh=valley_oracle).next_dt()
-    st = gpu_state(sc, swe.FP32, block_size=1024, cells_per_thread=2)
+    st = gpu_state(sc, swe.FP32, block_size=512)
     sim = oracle.Sim(sc, mesh=valley_oracle)
     for _ in range(3):
         st.step()

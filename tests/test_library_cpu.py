@@ -89,3 +89,16 @@ def test_clockwise_input_is_accepted(swe):
     t[:, 1], t[:, 2] = sc.tri[:, 2], sc.tri[:, 1]
     m = swe.Mesh(sc.nodes, t, sc.bnd_seg, sc.bnd_tag, device=False)
     assert m.info()["n_edges"] == oracle.Mesh(sc.nodes, sc.tri).n_edges
+
+
+@pytest.mark.parametrize("maker", [lambda: S.lake_at_rest(3000), lambda: S.valley_flood(20000, scale=0.1),
+                                   lambda: S.tiny_random(3, 3, seed=1), lambda: S.tiny_random(1, 1, seed=4),
+                                   lambda: S.dam_break(1.0)])
+def test_tile_edge_lists_cover_every_cell_edge_once(swe, maker):
+    sc = maker()
+    for renumber in (True, False):
+        m = swe.Mesh(sc.nodes, sc.tri, sc.bnd_seg, sc.bnd_tag, device=False, renumber=renumber)
+        for tile in (128, 256, 512):
+            m.check(tile)
+    with pytest.raises(swe.SweError):
+        m.check(100)

@@ -85,11 +85,20 @@ def time_gpu(sc, precision, steps, warmup, autotune=True):
     return dict(ms=ms, wall=wall, tune=tune, ms_step=ms / steps, rate=sc.n_cells * steps / (ms * 1e-3))
 
 
-def time_oracle(sc, budget_s=15.0, max_steps=50):
+def time_oracle(sc, budget_s=15.0, max_steps=50, precision="fp32"):
+    """The FP64 oracle on a bounded sample of the workload (steps with the
+    time step fixed at half the initial CFL step), then the GPU path on the
+    same steps: the oracle's rate, and the GPU's max and L1 errors in h, qx,
+    qy against it."""
     import oracle
+    from gpu_util import device, errors
+    from paper_2102_12862_amd import swe
+    import swe_inputs as S
     t0 = time.perf_counter()
     mesh = oracle.Mesh(sc.nodes, sc.tri, sc.bnd_seg, sc.bnd_tag)
-    sim = oracle.Sim(sc, mesh=mesh)
+    fixed = S.Scenario(**{**sc.__dict__})
+    fixed.dt_max = 0.5 * oracle.Sim(sc, mesh=mesh).next_dt()
+    sim = oracle.Sim(fixed, mesh=mesh)
     prep = time.perf_counter() - t0
     n = 0
     t0 = time.perf_counter()
@@ -97,7 +106,14 @@ def time_oracle(sc, budget_s=15.0, max_steps=50):
         sim.step()
         n += 1
     el = time.perf_counter() - t0
-    return dict(steps=n, seconds=el, prep=prep, rate=sc.n_cells * n / el)
+    gm = swe.Mesh(sc.nodes, sc.tri, sc.bnd_seg, sc.bnd_tag, device=device())
+    st = swe.State(gm, fixed, precision=swe.FP32 if precision == "fp32" else swe.FP64)
+    for _ in range(n):
+        st.step()
+    errs, _ = errors(st.read(), sim)
+    st.close()
+    gm.close()
+    return dict(steps=n, seconds=el, prep=prep, rate=sc.n_cells * n / el, errors=errs)
 
 
 def bench_batched(n_members=32, rounds=8, k=16):
@@ -250,10 +266,12 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         log("[bench] oracle sample")
-        o = time_oracle(sc)
+        o = time_oracle(sc, precision=args.precision)
         cpu = {"value": o["rate"], "unit": "cell-updates/s", "cores": 1, "kind": "oracle",
-               "sample": f"{o['steps']} FP64 steps of the same {N}-cell workload ({o['seconds']:.1f}s, serial C)"}
-        log(f"[bench] oracle {o['rate']:.3e} cell-updates/s")
+               "sample": f"{o['steps']} FP64 steps of the same {N}-cell workload, time step fixed at half "
+                         f"the initial CFL step ({o['seconds']:.1f}s, serial C)",
+               "gpu_error_vs_oracle": o["errors"]}
+        log(f"[bench] oracle {o['rate']:.3e} cell-updates/s; gpu errors {o['errors']}")
     out = {
         "metric": "cell-updates/s",
         "value": value,

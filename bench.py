@@ -37,8 +37,43 @@ HBM_PEAK_GBS = 8000.0
 ALGO_BYTES = {"fp32": 72.0, "fp64": 132.0}
 
 
+# HBM traffic of the step kernel, measured with the FETCH_SIZE and WRITE_SIZE
+# counters (each scaled by what it reads for a plain copy of known size); it
+# is reported only while the kernel sources still hash to the digest recorded
+# with the measurement
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_step_fp32_valley4m_hbm_traffic.md")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2102_12862_amd", "csrc", f)
+                  for f in ("kernels.hip", "swe_internal.h", "meshprep.cpp", "meshprep.h")]
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_digest():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload, precision, tile):
+    """Bytes per step-kernel launch from the committed counter profile, or
+    None when it was taken on other kernel sources or another configuration."""
+    try:
+        with open(TRAFFIC_PROFILE) as fh:
+            kv = dict(line.strip()[2:].split(": ", 1) for line in fh if line.startswith("- ") and ": " in line)
+    except OSError:
+        return None
+    try:
+        if (kv.get("kernel_digest") != kernel_digest() or kv.get("workload") != workload
+                or kv.get("precision") != precision or int(kv.get("tile", -1)) != tile):
+            return None
+        return float(kv["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
 
 
 def make_workload(name):
@@ -215,7 +250,11 @@ def main():
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="also run a plain device copy of this many MiB (counter calibration)")
+    ap.add_argument("--kernel-digest", action="store_true", help="print the digest of the kernel sources and exit")
     args = ap.parse_args()
+    if args.kernel_digest:
+        print(kernel_digest())
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the hot path is one device's share of the mesh; "
               "run with --gpus 1", file=sys.stderr)
@@ -241,6 +280,8 @@ def main():
     N = sc.n_cells
     value = r["rate"]
     achieved = ALGO_BYTES[args.precision] * N / (r["ms_step"] * 1e-3) / 1e9
+    tile = r["tune"][0] if r["tune"] else 256
+    traffic = measured_traffic(sc.name, args.precision, tile)
     log(f"[bench] gpu {args.precision}: {r['ms_step'] * 1e3:.1f} us/step, {value:.3e} cell-updates/s, "
         f"{achieved:.0f} GB/s algorithmic, tune {r['tune']}")
     variants = {}
@@ -289,8 +330,10 @@ def main():
                    "state": "fully wet snapshot" if "wet" in args.workload else "as generated",
                    "block_size_cells_per_thread": r["tune"]},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "algorithmic_bytes_per_cell": ALGO_BYTES[args.precision]},
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "algorithmic_bytes_per_cell": ALGO_BYTES[args.precision],
+                     "algorithmic_bytes_per_launch": ALGO_BYTES[args.precision] * N,
+                     "kernel": f"k_step<{'float' if args.precision == 'fp32' else 'double'}, {tile}>"},
         "cpu_baseline": cpu,
         "variants": variants,
     }

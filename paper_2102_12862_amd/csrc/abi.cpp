@@ -467,7 +467,8 @@ swe_status swe_state_init(const swe_mesh *m, const swe_params *params, const dou
             u[p].y = T(qx[p]);
             u[p].z = T(qy[p]);
             u[p].w = T(M.zb[p]);
-            cp[p].x = T(M.area[p]);
+            // FP64 keeps |cell| (the update divides by it); FP32 stores 1/|cell|
+            cp[p].x = sizeof(T) == 8 ? T(M.area[p]) : T(1.0 / M.area[p]);
             cp[p].y = T(gn2[p]);
         }
         HIP_TRY(hipMemcpyAsync(S->U0, u.data(), u.size() * sizeof(V4<T>), hipMemcpyHostToDevice, s));

@@ -15,15 +15,27 @@
 // shuffle, an LDS pass and at most one atomic min per block give the next
 // time step; block 0 publishes the next time level, so a run of steps needs no
 // host round trip and can be captured in one hipGraph.
+//
+// Precision.  The FP64 instantiation evaluates every formula in the operation
+// order of an FP64 reference, so each wet/dry decision matches it bit for bit.
+// The FP32 instantiation keeps the state and the flux arithmetic in single
+// precision (hardware reciprocal, square root, log2 and exp2; fused
+// multiply-adds where they cannot break the exact balance of a lake at rest),
+// with the depth differences H - z, the wet/dry tests, the time levels, the
+// time step and the mass sums in FP64.
 #include "swe_internal.h"
 
 #include <math.h>
+
+#include <type_traits>
 
 namespace swe {
 
 namespace {
 
 constexpr double H_DRY = 1e-12;  // reconstructed depths below this are dry
+
+template <typename T> constexpr bool IS32 = sizeof(T) == 4;
 
 template <typename T> __device__ __forceinline__ V4<T> make4(T a, T b, T c, T d);
 template <> __device__ __forceinline__ float4 make4<float>(float a, float b, float c, float d) {
@@ -32,10 +44,6 @@ template <> __device__ __forceinline__ float4 make4<float>(float a, float b, flo
 template <> __device__ __forceinline__ double4 make4<double>(double a, double b, double c, double d) {
     return make_double4(a, b, c, d);
 }
-
-template <typename T> __device__ __forceinline__ T pow73(T h);
-template <> __device__ __forceinline__ double pow73<double>(double h) { return pow(h, 7.0 / 3.0); }
-template <> __device__ __forceinline__ float pow73<float>(float h) { return exp2f((7.0f / 3.0f) * log2f(h)); }
 
 // Division and square root.  FP64 uses IEEE-correct operations so that every
 // wet/dry decision matches an FP64 reference bit for bit; FP32 uses the
@@ -47,18 +55,30 @@ __device__ __forceinline__ double qsqrt(double a) { return sqrt(a); }
 __device__ __forceinline__ float qsqrt(float a) { return __builtin_amdgcn_sqrtf(a); }
 
 // Edge length and unit normal from l*n.  FP64: the IEEE square root and two
-// divisions (matching the oracle); FP32: one reciprocal square root.
+// divisions (matching the reference); FP32: one reciprocal square root.  Both
+// give exactly negated normals for exactly negated l*n.
 __device__ __forceinline__ void edge_normal(double lx, double ly, double &l, double &nx, double &ny) {
     l = sqrt(lx * lx + ly * ly);
     nx = lx / l;
     ny = ly / l;
 }
 __device__ __forceinline__ void edge_normal(float lx, float ly, float &l, float &nx, float &ny) {
-    const float s = lx * lx + ly * ly;
+    const float s = fmaf(lx, lx, ly * ly);
     const float r = __builtin_amdgcn_rsqf(s);
     l = s * r;
     nx = lx * r;
     ny = ly * r;
+}
+
+// Velocity (u, v) in the frame (n, t) of an edge, t = (-ny, nx).  The FP32
+// form is odd in n, so the two cells of an edge see exactly opposite values.
+__device__ __forceinline__ void rotate(double u, double v, double nx, double ny, double &un, double &ut) {
+    un = u * nx + v * ny;
+    ut = v * nx - u * ny;
+}
+__device__ __forceinline__ void rotate(float u, float v, float nx, float ny, float &un, float &ut) {
+    un = fmaf(u, nx, v * ny);
+    ut = fmaf(v, nx, -(u * ny));
 }
 
 // HLLC flux (Toro 1994) in the frame of the edge normal, for reconstructed
@@ -68,35 +88,66 @@ __device__ __forceinline__ void edge_normal(float lx, float ly, float &l, float 
 // with U*_K = h_K (S_K - u_K)/(S_K - S*) (1, S*, ut_K), or the physical flux
 // F_K when all waves move one way (or the states are identical); two dry
 // sides give zero.  The side is chosen first and the formulas evaluated once,
-// so neighbouring edges with opposite flow directions do not diverge.
-template <typename T>
-__device__ __forceinline__ void hllc(T hL, T unL, T utL, T hR, T unR, T utR, T g, T &F0, T &F1, T &F2) {
-    const T zero = T(0), half = T(0.5);
+// so neighbouring edges with opposite flow directions do not diverge.  The
+// hydrostatic pressure g h^2 / 2 of F1 is formed as (g/2 * h) * h, the same
+// product the fluctuations subtract, so a lake at rest balances exactly.
+__device__ __forceinline__ void hllc(double hL, double unL, double utL, double hR, double unR, double utR, double g,
+                                     double &F0, double &F1, double &F2) {
+    const double zero = 0.0, half = 0.5;
     if (!(hL > zero) && !(hR > zero)) {
         F0 = zero; F1 = zero; F2 = zero;
         return;
     }
     const bool ident = hL == hR && unL == unR && utL == utR;
-    const T cL = qsqrt(g * hL), cR = qsqrt(g * hR);
+    const double cL = sqrt(g * hL), cR = sqrt(g * hR);
     const bool dryL = !(hL > zero), dryR = !(hR > zero);
-    const T a = half * (cL + cR) + T(0.25) * (unL - unR);
-    const T us = half * (unL + unR) + cL - cR;
-    const T cs = a > zero ? a : zero;
-    const T SL = dryL ? unR - T(2) * cR : (dryR ? unL - cL : fmin(unL - cL, us - cs));
-    const T SR = dryL ? unR + cR : (dryR ? unL + T(2) * cL : fmax(unR + cR, us + cs));
-    const T Ss = qdiv(SL * hR * (unR - SR) - SR * hL * (unL - SL), hR * (unR - SR) - hL * (unL - SL));
-    // side K whose flux (and star state) is used
+    const double a = half * (cL + cR) + 0.25 * (unL - unR);
+    const double us = half * (unL + unR) + cL - cR;
+    const double cs = a > zero ? a : zero;
+    const double SL = dryL ? unR - 2.0 * cR : (dryR ? unL - cL : fmin(unL - cL, us - cs));
+    const double SR = dryL ? unR + cR : (dryR ? unL + 2.0 * cL : fmax(unR + cR, us + cs));
+    const double Ss = (SL * hR * (unR - SR) - SR * hL * (unL - SL)) / (hR * (unR - SR) - hL * (unL - SL));
     const bool left = ident || zero <= SL || (!(SR <= zero) && zero <= Ss);
     const bool star = !ident && !(zero <= SL) && !(SR <= zero);
-    const T hK = left ? hL : hR, unK = left ? unL : unR, utK = left ? utL : utR, SK = left ? SL : SR;
+    const double hK = left ? hL : hR, unK = left ? unL : unR, utK = left ? utL : utR, SK = left ? SL : SR;
     F0 = hK * unK;
     F1 = hK * unK * unK + half * g * hK * hK;
     F2 = hK * unK * utK;
     if (star) {
-        const T f = qdiv(hK * (SK - unK), SK - Ss);
+        const double f = hK * (SK - unK) / (SK - Ss);
         F0 = F0 + SK * (f - hK);
         F1 = F1 + SK * (f * Ss - hK * unK);
         F2 = F2 + SK * (f * utK - hK * utK);
+    }
+}
+__device__ __forceinline__ void hllc(float hL, float unL, float utL, float hR, float unR, float utR, float g,
+                                     float &F0, float &F1, float &F2) {
+    if (!(hL > 0.0f) && !(hR > 0.0f)) {
+        F0 = 0.0f; F1 = 0.0f; F2 = 0.0f;
+        return;
+    }
+    const bool ident = hL == hR && unL == unR && utL == utR;
+    const float cL = qsqrt(g * hL), cR = qsqrt(g * hR);
+    const bool dryL = !(hL > 0.0f), dryR = !(hR > 0.0f);
+    const float a = fmaf(0.25f, unL - unR, 0.5f * (cL + cR));
+    const float us = fmaf(0.5f, unL + unR, cL - cR);
+    const float cs = a > 0.0f ? a : 0.0f;
+    const float SL = dryL ? fmaf(-2.0f, cR, unR) : (dryR ? unL - cL : fminf(unL - cL, us - cs));
+    const float SR = dryL ? unR + cR : (dryR ? fmaf(2.0f, cL, unL) : fmaxf(unR + cR, us + cs));
+    const float AR = hR * (unR - SR), AL = hL * (unL - SL);
+    const float Ss = qdiv(fmaf(SL, AR, -(SR * AL)), AR - AL);
+    const bool left = ident || 0.0f <= SL || (!(SR <= 0.0f) && 0.0f <= Ss);
+    const bool star = !ident && !(0.0f <= SL) && !(SR <= 0.0f);
+    const float hK = left ? hL : hR, unK = left ? unL : unR, utK = left ? utL : utR, SK = left ? SL : SR;
+    const float m = hK * unK;
+    F0 = m;
+    F1 = fmaf(m, unK, (0.5f * g * hK) * hK);
+    F2 = m * utK;
+    if (star) {
+        const float f = qdiv(hK * (SK - unK), SK - Ss);
+        F0 = fmaf(SK, f - hK, F0);
+        F1 = fmaf(SK, fmaf(f, Ss, -m), F1);
+        F2 = fmaf(SK, (f - hK) * utK, F2);
     }
 }
 
@@ -125,6 +176,15 @@ __device__ __forceinline__ bool inflow_ghost(const BCdev &b, double t, double gn
     ung = -q / hg;
     return true;
 }
+__device__ __forceinline__ bool inflow_ghost(const BCdev &b, double t, float gn2, float g, float &hg, float &ung) {
+    const double Q = hydrograph(b, t);
+    if (!(Q > 0.0)) return false;
+    const float q = float(Q / b.length);
+    const float x = q * qsqrt(qdiv(gn2, g * float(b.slope)));  // n q / sqrt(S), n = sqrt(g n^2 / g)
+    hg = __builtin_amdgcn_exp2f(0.6f * __builtin_amdgcn_logf(x));
+    ung = -qdiv(q, hg);
+    return true;
+}
 
 __device__ __forceinline__ void neumaier(double &s, double &c, double v) {
     double t = s + v;
@@ -135,34 +195,46 @@ __device__ __forceinline__ void neumaier(double &s, double &c, double v) {
     s = t;
 }
 
-// rho_k / lambda_k of one edge (eq. CFL_condition: rho is twice the
-// centroid-edge distance, 4|cell| / (3 l)).  FP64 evaluates it exactly as
-// written, edge by edge; FP32 folds the three edges into one division.
-template <typename T> struct CflMin;
-template <> struct CflMin<double> {
-    double best = INFINITY;
-    double area;
-    __device__ explicit CflMin(double a) : area(a) {}
-    __device__ void add(double l, double lam) {
-        const double r = 4.0 * area / (3.0 * l) / lam;
-        best = r < best ? r : best;
-    }
-    __device__ double value() const { return best; }
-};
-template <> struct CflMin<float> {
-    float lmax = 0.0f;
-    float area;
-    __device__ explicit CflMin(float a) : area(a) {}
-    __device__ void add(double l, double lam) { lmax = fmaxf(lmax, float(l * lam)); }
-    __device__ double value() const {
-        return lmax > 0.0f ? 4.0 * double(area) / (3.0 * double(lmax)) : INFINITY;
-    }
-};
+// Manning friction split: the exact solution of dq/dt = -g n^2 |q| q / h^(7/3)
+// over dt scales q by 1 / (1 + dt g n^2 |q| / h^(7/3)).
+__device__ __forceinline__ double friction_factor(double dt, double gn2, double qx, double qy, double h) {
+    const double qa = sqrt(qx * qx + qy * qy);
+    return 1.0 / (1.0 + dt * gn2 * qa / pow(h, 7.0 / 3.0));
+}
+__device__ __forceinline__ float friction_factor(float dt, float gn2, float qx, float qy, float h) {
+    const float qa = qsqrt(fmaf(qx, qx, qy * qy));
+    const float hp = __builtin_amdgcn_exp2f((-7.0f / 3.0f) * __builtin_amdgcn_logf(h));  // h^(-7/3)
+    return __builtin_amdgcn_rcpf(fmaf(dt * gn2 * qa, hp, 1.0f));
+}
 
-__device__ __forceinline__ double wave_min(double v) {
+// CFL terms (eq. CFL_condition, rho = twice the centroid-edge distance =
+// 4|cell| / (3 l)).  FP64 takes min over edges of rho/lambda exactly as
+// written.  FP32 takes the cell's max of l * lambda / |cell| in single
+// precision; the block turns its maximum m into 4 / (3 m) in FP64.  Inflow
+// ghosts leave their term in LDS as the bits of a positive number (a min in
+// FP64, a max in FP32), whose integer order is its numeric order.
+template <typename T> using CandT = T;  // FP64: min rho/lambda; FP32: max l*lambda/|cell|
+template <typename T> using GhostBits = typename std::conditional<IS32<T>, unsigned, unsigned long long>::type;
+__device__ __forceinline__ double cfl_term(double area, double l, double lam) { return 4.0 * area / (3.0 * l) / lam; }
+__device__ __forceinline__ unsigned long long ghost_init(double) { return INF_BITS; }
+__device__ __forceinline__ unsigned ghost_init(float) { return 0u; }
+
+__device__ __forceinline__ double wave_reduce(double v) {
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) v = fmin(v, __shfl_xor(v, off, 64));
     return v;
+}
+__device__ __forceinline__ float wave_reduce(float v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v = fmaxf(v, __shfl_xor(v, off, 64));
+    return v;
+}
+__device__ __forceinline__ double combine(double a, double b) { return fmin(a, b); }
+__device__ __forceinline__ float combine(float a, float b) { return fmaxf(a, b); }
+// block value -> min rho/lambda over the block
+__device__ __forceinline__ double block_rho_lambda(double m) { return m; }
+__device__ __forceinline__ double block_rho_lambda(float m) {
+    return m > 0.0f ? 4.0 / (3.0 * double(m)) : INFINITY;
 }
 
 __device__ __forceinline__ unsigned long long load_agent(const unsigned long long *p) {
@@ -212,21 +284,22 @@ __device__ __forceinline__ Level step_setup(Ctrl *c, int phase, double cfl, doub
     return L;
 }
 
-// Block minimum of the CFL candidates -> at most one atomic min on the next
+// Block reduction of the CFL terms -> at most one atomic min on the next
 // level's slot (skipped when it cannot lower the running value); block `lead`
 // publishes the next time level and clears the slot two phases ahead.
-__device__ __forceinline__ void block_finish(Ctrl *c, int phase, double cand, const Level &L, bool lead,
-                                             bool advance) {
-    __shared__ double wmin[16];
+template <typename C>
+__device__ __forceinline__ void block_finish(Ctrl *c, int phase, C cand, const Level &L, bool lead, bool advance) {
+    __shared__ C wred[16];
     const int pout = phase == 2 ? 0 : phase + 1, pclr = phase == 0 ? 2 : phase - 1;
-    cand = wave_min(cand);
+    cand = wave_reduce(cand);
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    if (lane == 0) wmin[w] = cand;
+    if (lane == 0) wred[w] = cand;
     __syncthreads();
     if (threadIdx.x == 0) {
-        double m = wmin[0];
+        C r = wred[0];
         const int nw = (blockDim.x + 63) >> 6;
-        for (int k = 1; k < nw; k++) m = fmin(m, wmin[k]);
+        for (int k = 1; k < nw; k++) r = combine(r, wred[k]);
+        const double m = block_rho_lambda(r);
         const unsigned long long mb = (unsigned long long)__double_as_longlong(m);
         unsigned long long *slot = advance ? &c->m[pout].bits : &c->m[phase].bits;
         if (mb < load_agent(slot)) atomicMin(slot, mb);
@@ -238,25 +311,40 @@ __device__ __forceinline__ void block_finish(Ctrl *c, int phase, double cand, co
             store_agent(&c->m[pclr].bits, INF_BITS);
         }
     }
-    __syncthreads();  // wmin may be reused by a following tile
+    __syncthreads();  // wred may be reused by a following tile
 }
 
-// LDS of one tile: states, velocities, and per (local edge, cell) the three
-// contribution components and the edge geometry the CFL candidate needs.
+// LDS of one tile: states, velocities, per (local edge, cell) the three
+// contribution components and the edge geometry the CFL candidate needs, and
+// per cell the CFL term of its inflow ghosts.
 template <typename T, int TILE> struct TileLds {
     V4<T> st[TILE];
     T u[TILE], v[TILE];
     T c[3][3][TILE];   // [component][local edge][cell]
     T l[3][TILE], nx[3][TILE], ny[3][TILE];
-    int inflow[3][TILE];  // inflow condition index of a boundary edge, else -1
+    GhostBits<T> ghost[TILE];
 };
 
-// Phases 0 and 1 for tile `tile` at time t (UPDATE = false: geometry only).
+// CFL term of an inflow ghost of cell a (depth hg, normal velocity ung) on
+// an edge of length l, merged into the cell's LDS slot.
+template <typename T, int TILE>
+__device__ __forceinline__ void ghost_cfl(TileLds<T, TILE> &S, int a, T l, T hg, T ung, T g, T area) {
+    if constexpr (IS32<T>) {
+        atomicMax(&S.ghost[a], __float_as_uint(l * (fabsf(ung) + qsqrt(g * hg))));
+    } else {
+        const double r = cfl_term(area, l, fabs(ung) + sqrt(g * hg));
+        atomicMin(&S.ghost[a], (unsigned long long)__double_as_longlong(r));
+    }
+}
+
+// Phases 0 and 1 for tile `tile`: fluxes at time t (UPDATE = false: geometry
+// only) and the inflow ghosts' CFL terms at time t_cand.
 template <typename T, int TILE, bool UPDATE>
 __device__ __forceinline__ void tile_edges(const Inst<T> &I, TileLds<T, TILE> &S, int tile, int cur, double t,
-                                           double dt) {
+                                           double dt, double t_cand) {
     const V4<T> *__restrict__ src = cur ? I.U1 : I.U0;
     const T g = T(I.g);
+    const T hg2 = T(0.5) * g;  // g/2 of the hydrostatic pressure (g/2 h) h
     const double h_min = I.h_min;
     const int c = threadIdx.x;
     const int i = tile * TILE + c;
@@ -270,8 +358,7 @@ __device__ __forceinline__ void tile_edges(const Inst<T> &I, TileLds<T, TILE> &S
         S.u[c] = wet ? qdiv(s.y, h) : T(0);
         S.v[c] = wet ? qdiv(s.z, h) : T(0);
     }
-#pragma unroll
-    for (int k = 0; k < 3; k++) S.inflow[k][c] = -1;
+    S.ghost[c] = ghost_init(T(0));
     __syncthreads();
     const int e1 = I.eoff[tile + 1];
     for (int e = I.eoff[tile] + c; e < e1; e += TILE) {
@@ -292,15 +379,19 @@ __device__ __forceinline__ void tile_edges(const Inst<T> &I, TileLds<T, TILE> &S
         if (!UPDATE) {
             if (kind == EK_BOUNDARY) {
                 const int kbc = I.slot_kbc[E.w1];
-                if ((kbc & 15) == BC_INFLOW) S.inflow[ka][a] = kbc >> 4;
+                if ((kbc & 15) == BC_INFLOW) {
+                    const V2<T> cp = I.cellp[tile * TILE + a];
+                    T hg, ung;
+                    if (inflow_ghost(I.bcs[kbc >> 4], t_cand, cp.y, g, hg, ung))
+                        ghost_cfl<T, TILE>(S, a, l, hg, ung, g, cp.x);
+                }
             }
             continue;
         }
         const V4<T> sa = S.st[a];
-        const T ua = S.u[a], va = S.v[a];
-        // a's velocity in the frame (n, t), t = (-ny, nx)
-        const T una = ua * nx + va * ny;
-        const T uta = va * nx - ua * ny;
+        // a's velocity in the frame (n, t)
+        T una, uta;
+        rotate(S.u[a], S.v[a], nx, ny, una, uta);
         T F0, F1, F2, ha, hb = T(0);
         if (kind != EK_BOUNDARY) {
             V4<T> sb;
@@ -318,8 +409,8 @@ __device__ __forceinline__ void tile_edges(const Inst<T> &I, TileLds<T, TILE> &S
                 ub = bwet ? qdiv(sb.y, hh) : T(0);
                 vb = bwet ? qdiv(sb.z, hh) : T(0);
             }
-            const T unb = ub * nx + vb * ny;
-            const T utb = vb * nx - ub * ny;
+            T unb, utb;
+            rotate(ub, vb, nx, ny, unb, utb);
             // hydrostatic reconstruction of the two modified states
             const double zs = double(sa.w > sb.w ? sa.w : sb.w);
             const double da = double(sa.x) - zs, db = double(sb.x) - zs;
@@ -330,7 +421,7 @@ __device__ __forceinline__ void tile_edges(const Inst<T> &I, TileLds<T, TILE> &S
             const T hL = flip ? hb : ha, hR = flip ? ha : hb;
             const T unL = flip ? -unb : una, utL = flip ? -utb : uta;
             const T unR = flip ? -una : unb, utR = flip ? -uta : utb;
-            hllc<T>(hL, unL, utL, hR, unR, utR, g, F0, F1, F2);
+            hllc(hL, unL, utL, hR, unR, utR, g, F0, F1, F2);
             if (flip) F0 = -F0;  // mass leaving a
         } else {
             const int slot = E.w1;
@@ -339,24 +430,29 @@ __device__ __forceinline__ void tile_edges(const Inst<T> &I, TileLds<T, TILE> &S
             // the ghost shares a's bed, so z* = z and h* = H - z
             const double da = double(sa.x) - double(sa.w);
             ha = da < H_DRY ? T(0) : T(da);
-            double hg, ung;
+            T hg, ung;
             bool open = false;
             if (bkind == BC_OUTFLOW) {
                 // transmissive: the ghost repeats the interior state
-                hllc<T>(ha, una, uta, ha, una, uta, g, F0, F1, F2);
+                hllc(ha, una, uta, ha, una, uta, g, F0, F1, F2);
                 open = true;
-            } else if (bkind == BC_INFLOW && inflow_ghost(I.bcs[bi], t, double(I.cellp[tile * TILE + a].y),
-                                                          double(g), hg, ung)) {
-                const double dg = (double(sa.w) + hg) - double(sa.w);
-                const T hgs = dg < H_DRY ? T(0) : T(dg);
-                hllc<T>(ha, una, uta, hgs, T(ung), T(0), g, F0, F1, F2);
-                open = true;
+            } else if (bkind == BC_INFLOW) {
+                const V2<T> cp = I.cellp[tile * TILE + a];
+                if (inflow_ghost(I.bcs[bi], t, cp.y, g, hg, ung)) {
+                    const double dg = (double(sa.w) + double(hg)) - double(sa.w);
+                    const T hgs = dg < H_DRY ? T(0) : T(dg);
+                    hllc(ha, una, uta, hgs, ung, T(0), g, F0, F1, F2);
+                    open = true;
+                } else {
+                    hllc(ha, una, uta, ha, -una, uta, g, F0, F1, F2);
+                    F0 = T(0);
+                }
+                if (inflow_ghost(I.bcs[bi], t_cand, cp.y, g, hg, ung)) ghost_cfl<T, TILE>(S, a, l, hg, ung, g, cp.x);
             } else {
                 // reflective, impermeable wall: mirrored normal velocity
-                hllc<T>(ha, una, uta, ha, -una, uta, g, F0, F1, F2);
+                hllc(ha, una, uta, ha, -una, uta, g, F0, F1, F2);
                 F0 = T(0);
             }
-            if (bkind == BC_INFLOW) S.inflow[ka][a] = bi;
             if (open) {
                 double *acc = I.slot_acc + 2 * slot;
                 double sm = acc[0], cp = acc[1];
@@ -367,86 +463,104 @@ __device__ __forceinline__ void tile_edges(const Inst<T> &I, TileLds<T, TILE> &S
         }
         // fluctuations: the flux minus each side's reconstructed pressure
         // (bed slope in well-balanced form), rotated back
-        const T Da = F1 - T(0.5) * g * ha * ha;
+        const T Da = F1 - hg2 * ha * ha;
         S.c[0][ka][a] = l * F0;
-        S.c[1][ka][a] = l * (Da * nx - F2 * ny);
-        S.c[2][ka][a] = l * (Da * ny + F2 * nx);
+        if constexpr (IS32<T>) {
+            S.c[1][ka][a] = l * fmaf(Da, nx, -(F2 * ny));
+            S.c[2][ka][a] = l * fmaf(Da, ny, F2 * nx);
+        } else {
+            S.c[1][ka][a] = l * (Da * nx - F2 * ny);
+            S.c[2][ka][a] = l * (Da * ny + F2 * nx);
+        }
         if (kind == EK_LOCAL) {
             const int b = (E.w0 >> 17) & 1023;
-            const T Db = F1 - T(0.5) * g * hb * hb;
+            const T Db = F1 - hg2 * hb * hb;
             S.c[0][kb][b] = -(l * F0);
-            S.c[1][kb][b] = -(l * (Db * nx - F2 * ny));
-            S.c[2][kb][b] = -(l * (Db * ny + F2 * nx));
+            if constexpr (IS32<T>) {
+                S.c[1][kb][b] = -(l * fmaf(Db, nx, -(F2 * ny)));
+                S.c[2][kb][b] = -(l * fmaf(Db, ny, F2 * nx));
+            } else {
+                S.c[1][kb][b] = -(l * (Db * nx - F2 * ny));
+                S.c[2][kb][b] = -(l * (Db * ny + F2 * nx));
+            }
         }
     }
     __syncthreads();
 }
 
-// CFL candidate of cell c of the tile with state (H, qx, qy, z), from the
-// edge geometry left in LDS: min over edges of rho / lambda over wet cells
-// and inflow ghosts (at time t).
+// CFL term of cell c of the tile with state (H, qx, qy, z), from the edge
+// geometry and ghost terms left in LDS.  ap is |cell| (FP64) or 1/|cell|
+// (FP32).  A dry cell contributes only its inflow ghosts.
 template <typename T, int TILE>
-__device__ __forceinline__ double tile_candidate(const Inst<T> &I, const TileLds<T, TILE> &S, int c, T area,
-                                                 T gn2, T H, T qx, T qy, T z, double t) {
+__device__ __forceinline__ CandT<T> tile_candidate(const Inst<T> &I, const TileLds<T, TILE> &S, int c, T ap, T H,
+                                                   T qx, T qy, T z) {
     const T g = T(I.g);
-    CflMin<T> cfl(area);
     const double h2 = double(H) - double(z);
-    if (h2 > I.h_min) {
-        const T hh = T(h2);
-        const T u2 = qdiv(qx, hh), v2 = qdiv(qy, hh);
-        const T cc = qsqrt(g * hh);
+    if constexpr (IS32<T>) {
+        float lmax = __uint_as_float(S.ghost[c]);
+        if (h2 > I.h_min) {
+            const float hh = float(h2);
+            const float rh = __builtin_amdgcn_rcpf(hh);
+            const float u2 = qx * rh, v2 = qy * rh;
+            const float cc = qsqrt(g * hh);
 #pragma unroll
-        for (int k = 0; k < 3; k++) {
-            const T lam = fabs(u2 * S.nx[k][c] + v2 * S.ny[k][c]) + cc;
-            cfl.add(double(S.l[k][c]), double(lam));
+            for (int k = 0; k < 3; k++)
+                lmax = fmaxf(lmax, S.l[k][c] * (fabsf(fmaf(u2, S.nx[k][c], v2 * S.ny[k][c])) + cc));
         }
-    }
+        return lmax * ap;
+    } else {
+        double best = __longlong_as_double((long long)S.ghost[c]);
+        if (h2 > I.h_min) {
+            const double hh = h2;
+            const double u2 = qx / hh, v2 = qy / hh;
+            const double cc = sqrt(g * hh);
 #pragma unroll
-    for (int k = 0; k < 3; k++) {
-        const int bi = S.inflow[k][c];
-        if (bi >= 0) {
-            double hg, ung;
-            if (inflow_ghost(I.bcs[bi], t, double(gn2), double(g), hg, ung))
-                cfl.add(double(S.l[k][c]), fabs(ung) + sqrt(double(g) * hg));
+            for (int k = 0; k < 3; k++) {
+                const double lam = fabs(u2 * S.nx[k][c] + v2 * S.ny[k][c]) + cc;
+                const double r = cfl_term(ap, S.l[k][c], lam);
+                best = r < best ? r : best;
+            }
         }
+        return best;
     }
-    return cfl.value();
 }
 
 // Phase 2 for cell c of tile `tile`: update, friction, clip, write; returns
-// the CFL candidate of the new state.
+// the CFL term of the new state.
 template <typename T, int TILE>
-__device__ __forceinline__ double tile_update(const Inst<T> &I, const TileLds<T, TILE> &S, int tile, int cur,
-                                              double dt, double t_next) {
+__device__ __forceinline__ CandT<T> tile_update(const Inst<T> &I, const TileLds<T, TILE> &S, int tile, int cur,
+                                                double dt) {
     const int c = threadIdx.x;
     const int i = tile * TILE + c;
-    if (i >= I.n) return INFINITY;
+    if (i >= I.n) return IS32<T> ? T(0) : T(INFINITY);
     V4<T> *__restrict__ dst = cur ? I.U0 : I.U1;
     const double h_min = I.h_min;
     const V4<T> s = S.st[c];
     const V2<T> cp = I.cellp[i];
-    const T area = cp.x, gn2 = cp.y;
+    const T gn2 = cp.y;
     // residual in local edge order, then the conservative update
     const T R0 = S.c[0][0][c] + S.c[0][1][c] + S.c[0][2][c];
     const T R1 = S.c[1][0][c] + S.c[1][1][c] + S.c[1][2][c];
     const T R2 = S.c[2][0][c] + S.c[2][1][c] + S.c[2][2][c];
-    const T w = T(dt) * qdiv(T(1), area);
-    T Hn = s.x - w * R0;
-    T qx = s.y - w * R1;
-    T qy = s.z - w * R2;
-    const double hn = double(Hn) - double(s.w);
-    // friction split: exact solution of dq/dt = -g n^2 |q| q / h^(7/3)
-    T f;
-    if (hn > h_min) {
-        if (gn2 > T(0)) {
-            const T qa = qsqrt(qx * qx + qy * qy);
-            f = qdiv(T(1), T(1) + qdiv(T(dt) * gn2 * qa, pow73<T>(T(hn))));
-        } else {
-            f = T(1);
-        }
+    T Hn, qx, qy;
+    if constexpr (IS32<T>) {
+        const float w = float(dt) * cp.x;  // cp.x = 1/|cell|
+        Hn = fmaf(-w, R0, s.x);
+        qx = fmaf(-w, R1, s.y);
+        qy = fmaf(-w, R2, s.z);
     } else {
-        f = T(0);
+        const double w = dt * (1.0 / cp.x);
+        Hn = s.x - w * R0;
+        qx = s.y - w * R1;
+        qy = s.z - w * R2;
     }
+    const double hn = double(Hn) - double(s.w);
+    // friction split
+    T f;
+    if (hn > h_min)
+        f = gn2 > T(0) ? friction_factor(T(dt), gn2, qx, qy, T(hn)) : T(1);
+    else
+        f = T(0);
     qx = qx * f;
     qy = qy * f;
     if (hn < 0.0) {
@@ -460,19 +574,22 @@ __device__ __forceinline__ double tile_update(const Inst<T> &I, const TileLds<T,
     }
     if (!isfinite(Hn) || !isfinite(qx) || !isfinite(qy)) atomicOr(&I.ctrl->flags, FLAG_NONFINITE);
     dst[i] = make4<T>(Hn, qx, qy, s.w);
-    return tile_candidate<T, TILE>(I, S, c, area, gn2, Hn, qx, qy, s.w, t_next);
+    return tile_candidate<T, TILE>(I, S, c, cp.x, Hn, qx, qy, s.w);
 }
 
-// Occupancy hint: five waves per SIMD, the register budget the FP32 body fits
-// without spilling (the FP64 body is limited by LDS instead).
+// Occupancy hint (minimum waves per SIMD): the tile's LDS allows six FP32
+// waves per SIMD at every tile size, and three FP64 waves (two at 512 cells),
+// so the register budget is set to match.
+template <typename T, int TILE> constexpr int WAVES_PER_SIMD = IS32<T> ? 6 : (TILE >= 512 ? 2 : 3);
+
 template <typename T, int TILE>
-__global__ void __launch_bounds__(TILE, 5 * 256 / TILE) k_step(Inst<T> I, int phase) {
+__global__ void __launch_bounds__(TILE, (WAVES_PER_SIMD<T, TILE>)) k_step(Inst<T> I, int phase) {
     __shared__ TileLds<T, TILE> S;
     const bool lead = blockIdx.x == 0;
     const Level L = step_setup(I.ctrl, phase, I.cfl, I.dt_max, lead);
     if (!L.run) return;
-    tile_edges<T, TILE, true>(I, S, blockIdx.x, L.cur, L.t, L.dt);
-    const double cand = tile_update<T, TILE>(I, S, blockIdx.x, L.cur, L.dt, L.t + L.dt);
+    tile_edges<T, TILE, true>(I, S, blockIdx.x, L.cur, L.t, L.dt, L.t + L.dt);
+    const CandT<T> cand = tile_update<T, TILE>(I, S, blockIdx.x, L.cur, L.dt);
     block_finish(I.ctrl, phase, cand, L, lead, true);
 }
 
@@ -489,13 +606,13 @@ __global__ void __launch_bounds__(TILE) k_dt_init(Inst<T> I, int phase) {
     L.steps = 0;
     L.rawmin = 0.0;
     L.run = true;
-    tile_edges<T, TILE, false>(I, S, blockIdx.x, L.cur, L.t, 0.0);
-    double cand = INFINITY;
+    tile_edges<T, TILE, false>(I, S, blockIdx.x, L.cur, L.t, 0.0, L.t);
+    CandT<T> cand = IS32<T> ? T(0) : T(INFINITY);
     const int i = blockIdx.x * TILE + threadIdx.x;
     if (i < I.n) {
         const V4<T> s = S.st[threadIdx.x];
         const V2<T> cp = I.cellp[i];
-        cand = tile_candidate<T, TILE>(I, S, threadIdx.x, cp.x, cp.y, s.x, s.y, s.z, s.w, L.t);
+        cand = tile_candidate<T, TILE>(I, S, threadIdx.x, cp.x, s.x, s.y, s.z, s.w);
     }
     block_finish(I.ctrl, phase, cand, L, false, false);
 }
@@ -504,7 +621,7 @@ __global__ void __launch_bounds__(TILE) k_dt_init(Inst<T> I, int phase) {
 // pairs; each member keeps its own control block, so members step with their
 // own dt and finished members cost one control-block read per tile.
 template <typename T, int TILE>
-__global__ void __launch_bounds__(TILE, 5 * 256 / TILE) k_step_batched(const Inst<T> *__restrict__ insts,
+__global__ void __launch_bounds__(TILE, (WAVES_PER_SIMD<T, TILE>)) k_step_batched(const Inst<T> *__restrict__ insts,
                                                         const int2 *__restrict__ tiles, int ntiles, int phase) {
     __shared__ TileLds<T, TILE> S;
     for (int tt = blockIdx.x; tt < ntiles; tt += gridDim.x) {
@@ -513,8 +630,8 @@ __global__ void __launch_bounds__(TILE, 5 * 256 / TILE) k_step_batched(const Ins
         const bool lead = td.y == 0;
         const Level L = step_setup(I.ctrl, phase, I.cfl, I.dt_max, lead);
         if (!L.run) continue;
-        tile_edges<T, TILE, true>(I, S, td.y, L.cur, L.t, L.dt);
-        const double cand = tile_update<T, TILE>(I, S, td.y, L.cur, L.dt, L.t + L.dt);
+        tile_edges<T, TILE, true>(I, S, td.y, L.cur, L.t, L.dt, L.t + L.dt);
+        const CandT<T> cand = tile_update<T, TILE>(I, S, td.y, L.cur, L.dt);
         block_finish(I.ctrl, phase, cand, L, lead, true);
     }
 }

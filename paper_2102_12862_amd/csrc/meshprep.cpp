@@ -206,8 +206,11 @@ bool build_tile_edges(const HostMesh &M, int tile, std::vector<TileEdge> &edges,
     edges.clear();
     edges.reserve((size_t)(n * 7 / 4 + ntiles * 64));
     eoff.assign((size_t)ntiles + 1, 0);
+    std::vector<TileEdge> remote, boundary;
     for (int64_t t = 0; t < ntiles; t++) {
         eoff[t] = (int32_t)edges.size();
+        remote.clear();
+        boundary.clear();
         const int64_t p0 = t * tile, p1 = std::min(n, p0 + tile);
         for (int64_t p = p0; p < p1; p++) {
             for (int k = 0; k < 3; k++) {
@@ -238,9 +241,22 @@ bool build_tile_edges(const HostMesh &M, int tile, std::vector<TileEdge> &edges,
                     e.w1 = -1 - code;
                 }
                 e.w0 = w0;
-                edges.push_back(e);
+                const int kind = (w0 >> 14) & 3;
+                if (kind == EDGE_LOCAL)
+                    edges.push_back(e);
+                else if (kind == EDGE_REMOTE)
+                    remote.push_back(e);
+                else
+                    boundary.push_back(e);
             }
         }
+        // local edges first, then remote ones by neighbour (gathers in
+        // address order), then boundary edges: a wave then mostly runs one
+        // kind of edge
+        std::stable_sort(remote.begin(), remote.end(),
+                         [](const TileEdge &x, const TileEdge &y) { return x.w1 < y.w1; });
+        edges.insert(edges.end(), remote.begin(), remote.end());
+        edges.insert(edges.end(), boundary.begin(), boundary.end());
     }
     eoff[ntiles] = (int32_t)edges.size();
     return edges.size() < (size_t)INT32_MAX;

@@ -27,6 +27,8 @@ struct HostMesh {
 // One edge of a tile (a block of `tile` consecutive cells), stored once per
 // tile: an edge between two cells of the tile appears once, an edge to a
 // cell of another tile or to the boundary appears in the tile of its cell.
+// Within a tile the list holds the local edges first, then the remote ones
+// in order of the other cell, then the boundary edges.
 //   w0: bits 0-9 local cell a, 10-11 its local edge ka, 12-13 the other
 //       cell's local edge kb, 14-15 kind (0 both cells in the tile, 1 other
 //       cell in another tile, 2 boundary), bit 16 set when a is the right

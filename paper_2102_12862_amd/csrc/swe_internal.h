@@ -10,7 +10,7 @@ namespace swe {
 // Device layout (cells renumbered along a Hilbert curve of their centroids):
 //   U[2][n]   vec4 (H, qx, qy, z)  ping-pong state; z rides along so a cell's
 //             whole state is one vector load
-//   cellp[n]  vec2 (|cell|, g n^2)
+//   cellp[n]  vec2 (|cell| in FP64, 1/|cell| in FP32; g n^2)
 //   edges     per tile of TILE consecutive cells, every edge touching the tile
 //             once (see TileEdge in meshprep.h): two ints and l*n
 //   eoff      first edge of each tile
@@ -86,7 +86,7 @@ constexpr unsigned long long INF_BITS = 0x7FF0000000000000ull;
 template <typename T> struct Inst {
     V4<T> *U0;
     V4<T> *U1;
-    const V2<T> *cellp;    // (|cell|, g n^2)
+    const V2<T> *cellp;    // (|cell| in FP64, 1/|cell| in FP32; g n^2)
     const Edge<T> *edges;  // tile edge lists
     const int *eoff;       // first edge of each tile (ntiles + 1)
     const int *slot_kbc;   // per boundary slot: kind | (bc index << 4)

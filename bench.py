@@ -264,13 +264,15 @@ def main():
         raise SystemExit("bench.py needs a GPU")
     torch.cuda.set_device(0)
     if args.copy_calibration_mib:
-        n = args.copy_calibration_mib << 20
-        x = torch.ones(n, dtype=torch.uint8, device="cuda")
+        # a plain elementwise kernel that reads and writes a known number of
+        # bytes once each, to scale the HBM byte counters
+        n = (args.copy_calibration_mib << 20) // 4
+        x = torch.ones(n, dtype=torch.float32, device="cuda")
         y = torch.empty_like(x)
         for _ in range(3):
-            y.copy_(x)
+            torch.mul(x, 1.0, out=y)
         torch.cuda.synchronize()
-        log(f"[bench] copy calibration: {args.copy_calibration_mib} MiB read + written per copy (3 copies)")
+        log(f"[bench] copy calibration: {args.copy_calibration_mib} MiB read + written per launch (3 launches)")
         del x, y
     log(f"[bench] generating {args.workload}")
     t0 = time.perf_counter()

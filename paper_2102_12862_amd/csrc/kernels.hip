@@ -1,7 +1,7 @@
 // HIP kernels of the shallow-water step for gfx950 (CDNA4, wave64).
 //
 // A block owns a tile of TILE consecutive cells of the Hilbert-ordered mesh.
-// Phase 0 stages the tile's states (H, qx, qy, z) and velocities in LDS.
+// Phase 0 stages the tile's surfaces, velocities and beds in LDS.
 // Phase 1 evaluates every edge of the tile once -- hydrostatic reconstruction,
 // HLLC flux, the two fluctuations -- and leaves each cell's contribution in
 // the LDS slot of its local edge (edges to other tiles are evaluated by both
@@ -211,23 +211,46 @@ __device__ __forceinline__ float friction_factor(float dt, float gn2, float qx, 
 // 4|cell| / (3 l)).  FP64 takes min over edges of rho/lambda exactly as
 // written.  FP32 takes the cell's max of l * lambda / |cell| in single
 // precision; the block turns its maximum m into 4 / (3 m) in FP64.  Inflow
-// ghosts leave their term in LDS as the bits of a positive number (a min in
+// ghosts do not depend on the new state, so the edge pass folds their terms
+// into one LDS word per tile, as the bits of a positive number (a min in
 // FP64, a max in FP32), whose integer order is its numeric order.
 template <typename T> using CandT = T;  // FP64: min rho/lambda; FP32: max l*lambda/|cell|
 template <typename T> using GhostBits = typename std::conditional<IS32<T>, unsigned, unsigned long long>::type;
 __device__ __forceinline__ double cfl_term(double area, double l, double lam) { return 4.0 * area / (3.0 * l) / lam; }
 __device__ __forceinline__ unsigned long long ghost_init(double) { return INF_BITS; }
 __device__ __forceinline__ unsigned ghost_init(float) { return 0u; }
+__device__ __forceinline__ double ghost_value(unsigned long long b) { return __longlong_as_double((long long)b); }
+__device__ __forceinline__ float ghost_value(unsigned b) { return __uint_as_float(b); }
 
 __device__ __forceinline__ double wave_reduce(double v) {
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) v = fmin(v, __shfl_xor(v, off, 64));
     return v;
 }
+// FP32 terms are non-negative, so their bit patterns (sign cleared) order
+// like their values: the max runs on integers, by DPP permutations within
+// each row of 16 lanes, then over the four rows' lanes 0, 16, 32, 48.
+__device__ __forceinline__ unsigned dpp_max(unsigned v, int ctrl_id) {
+    int p;
+    switch (ctrl_id) {
+        case 0: p = __builtin_amdgcn_update_dpp(0, (int)v, 0xB1, 0xF, 0xF, false); break;   // quad_perm 1,0,3,2
+        case 1: p = __builtin_amdgcn_update_dpp(0, (int)v, 0x4E, 0xF, 0xF, false); break;   // quad_perm 2,3,0,1
+        case 2: p = __builtin_amdgcn_update_dpp(0, (int)v, 0x141, 0xF, 0xF, false); break;  // row_half_mirror
+        default: p = __builtin_amdgcn_update_dpp(0, (int)v, 0x140, 0xF, 0xF, false); break; // row_mirror
+    }
+    return max(v, (unsigned)p);
+}
 __device__ __forceinline__ float wave_reduce(float v) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v = fmaxf(v, __shfl_xor(v, off, 64));
-    return v;
+    unsigned b = __float_as_uint(v) & 0x7FFFFFFFu;
+    b = dpp_max(b, 0);
+    b = dpp_max(b, 1);
+    b = dpp_max(b, 2);
+    b = dpp_max(b, 3);
+    const unsigned r0 = (unsigned)__builtin_amdgcn_readlane((int)b, 0);
+    const unsigned r1 = (unsigned)__builtin_amdgcn_readlane((int)b, 16);
+    const unsigned r2 = (unsigned)__builtin_amdgcn_readlane((int)b, 32);
+    const unsigned r3 = (unsigned)__builtin_amdgcn_readlane((int)b, 48);
+    return __uint_as_float(max(max(r0, r1), max(r2, r3)));
 }
 __device__ __forceinline__ double combine(double a, double b) { return fmin(a, b); }
 __device__ __forceinline__ float combine(float a, float b) { return fmaxf(a, b); }
@@ -284,11 +307,21 @@ __device__ __forceinline__ Level step_setup(Ctrl *c, int phase, double cfl, doub
     return L;
 }
 
-// Block reduction of the CFL terms -> at most one atomic min on the next
-// level's slot (skipped when it cannot lower the running value); block `lead`
-// publishes the next time level and clears the slot two phases ahead.
-template <typename C>
-__device__ __forceinline__ void block_finish(Ctrl *c, int phase, C cand, const Level &L, bool lead, bool advance) {
+// Slot that a step of launch phase `phase` lowers (advance) or an
+// initialisation fills (!advance).
+__device__ __forceinline__ unsigned long long *cfl_slot(Ctrl *c, int phase, bool advance) {
+    return advance ? &c->m[phase == 2 ? 0 : phase + 1].bits : &c->m[phase].bits;
+}
+
+// Block reduction of the CFL terms -> at most one atomic min on the slot,
+// skipped when `seen` (the slot's value read by thread 0 before the update
+// phase; values only decrease, so a stale one never hides a lower minimum)
+// shows it cannot lower it.  Block `lead` publishes the next time level and
+// clears the slot two phases ahead.  REUSE: the block goes on to another tile
+// and must not overwrite wred before thread 0 has read it.
+template <bool REUSE, typename C>
+__device__ __forceinline__ void block_finish(Ctrl *c, int phase, C cand, const Level &L, bool lead, bool advance,
+                                             unsigned long long seen) {
     __shared__ C wred[16];
     const int pout = phase == 2 ? 0 : phase + 1, pclr = phase == 0 ? 2 : phase - 1;
     cand = wave_reduce(cand);
@@ -301,8 +334,7 @@ __device__ __forceinline__ void block_finish(Ctrl *c, int phase, C cand, const L
         for (int k = 1; k < nw; k++) r = combine(r, wred[k]);
         const double m = block_rho_lambda(r);
         const unsigned long long mb = (unsigned long long)__double_as_longlong(m);
-        unsigned long long *slot = advance ? &c->m[pout].bits : &c->m[phase].bits;
-        if (mb < load_agent(slot)) atomicMin(slot, mb);
+        if (mb < seen) atomicMin(cfl_slot(c, phase, advance), mb);
         if (lead && advance) {
             store_agent(&c->s[pout].t, L.t + L.dt);
             store_agent(&c->s[pout].dt, L.dt);
@@ -311,58 +343,74 @@ __device__ __forceinline__ void block_finish(Ctrl *c, int phase, C cand, const L
             store_agent(&c->m[pclr].bits, INF_BITS);
         }
     }
-    __syncthreads();  // wred may be reused by a following tile
+    if (REUSE) __syncthreads();
 }
 
-// LDS of one tile: states, velocities, per (local edge, cell) the three
-// contribution components and the edge geometry the CFL candidate needs, and
-// per cell the CFL term of its inflow ghosts.
+// LDS of one tile: per cell (H, u, v, z) with the velocity zero at or below
+// the minimum depth, per (local edge, cell) the three contribution components
+// and the edge geometry the CFL candidate needs, and the tile's inflow-ghost
+// CFL term.  The update thread of a cell keeps its (H, qx, qy, z) in
+// registers.
 template <typename T, int TILE> struct TileLds {
-    V4<T> st[TILE];
-    T u[TILE], v[TILE];
+    V4<T> huvz[TILE];
     T c[3][3][TILE];   // [component][local edge][cell]
     T l[3][TILE], nx[3][TILE], ny[3][TILE];
-    GhostBits<T> ghost[TILE];
+    GhostBits<T> ghost;
 };
 
-// CFL term of an inflow ghost of cell a (depth hg, normal velocity ung) on
-// an edge of length l, merged into the cell's LDS slot.
+// CFL term of an inflow ghost (depth hg, normal velocity ung) on an edge of
+// length l of a cell with ap = |cell| (FP64) or 1/|cell| (FP32), merged into
+// the tile's LDS word.
 template <typename T, int TILE>
-__device__ __forceinline__ void ghost_cfl(TileLds<T, TILE> &S, int a, T l, T hg, T ung, T g, T area) {
+__device__ __forceinline__ void ghost_cfl(TileLds<T, TILE> &S, T l, T hg, T ung, T g, T ap) {
     if constexpr (IS32<T>) {
-        atomicMax(&S.ghost[a], __float_as_uint(l * (fabsf(ung) + qsqrt(g * hg))));
+        atomicMax(&S.ghost, __float_as_uint(l * (fabsf(ung) + qsqrt(g * hg)) * ap));
     } else {
-        const double r = cfl_term(area, l, fabs(ung) + sqrt(g * hg));
-        atomicMin(&S.ghost[a], (unsigned long long)__double_as_longlong(r));
+        const double r = cfl_term(ap, l, fabs(ung) + sqrt(g * hg));
+        atomicMin(&S.ghost, (unsigned long long)__double_as_longlong(r));
     }
 }
 
+// Forces all four components of a gathered state to be loaded together (one
+// 16 B load in FP32) instead of a partial load plus a conditional one.
+template <typename V> __device__ __forceinline__ void whole(V &s) {
+    asm volatile("" : "+v"(s.x), "+v"(s.y), "+v"(s.z), "+v"(s.w));
+}
+
 // Phases 0 and 1 for tile `tile`: fluxes at time t (UPDATE = false: geometry
-// only) and the inflow ghosts' CFL terms at time t_cand.
+// only) and the inflow ghosts' CFL terms at time t_cand.  `own` receives the
+// state (H, qx, qy, z) of this thread's cell.
 template <typename T, int TILE, bool UPDATE>
 __device__ __forceinline__ void tile_edges(const Inst<T> &I, TileLds<T, TILE> &S, int tile, int cur, double t,
-                                           double dt, double t_cand) {
+                                           double dt, double t_cand, V4<T> &own) {
     const V4<T> *__restrict__ src = cur ? I.U1 : I.U0;
     const T g = T(I.g);
     const T hg2 = T(0.5) * g;  // g/2 of the hydrostatic pressure (g/2 h) h
     const double h_min = I.h_min;
     const int c = threadIdx.x;
     const int i = tile * TILE + c;
+    // the edge records do not depend on the state: the first one is loaded
+    // before phase 0 and each next one an iteration ahead (unconditionally:
+    // lanes past the end re-read the tile's last record, which every tile
+    // has, so the loads need no branch)
+    const int e1 = I.eoff[tile + 1];
+    int e = I.eoff[tile] + c;
+    Edge<T> En = I.edges[min(e, e1 - 1)];
+    own = make4<T>(T(0), T(0), T(0), T(0));
     if (i < I.n) {
         const V4<T> s = src[i];
-        S.st[c] = s;
+        own = s;
         // velocity only above the minimum depth
         const double hd = double(s.x) - double(s.w);
         const bool wet = hd > h_min;
         const T h = T(hd);
-        S.u[c] = wet ? qdiv(s.y, h) : T(0);
-        S.v[c] = wet ? qdiv(s.z, h) : T(0);
+        S.huvz[c] = make4<T>(s.x, wet ? qdiv(s.y, h) : T(0), wet ? qdiv(s.z, h) : T(0), s.w);
     }
-    S.ghost[c] = ghost_init(T(0));
+    if (c == 0) S.ghost = ghost_init(T(0));
     __syncthreads();
-    const int e1 = I.eoff[tile + 1];
-    for (int e = I.eoff[tile] + c; e < e1; e += TILE) {
-        const Edge<T> E = I.edges[e];
+    for (; e < e1; e += TILE) {
+        const Edge<T> E = En;
+        En = I.edges[min(e + TILE, e1 - 1)];
         const int a = E.w0 & 1023, ka = (E.w0 >> 10) & 3, kb = (E.w0 >> 12) & 3, kind = (E.w0 >> 14) & 3;
         const bool flip = (E.w0 >> 16) & 1;
         T l, nx, ny;
@@ -383,26 +431,27 @@ __device__ __forceinline__ void tile_edges(const Inst<T> &I, TileLds<T, TILE> &S
                     const V2<T> cp = I.cellp[tile * TILE + a];
                     T hg, ung;
                     if (inflow_ghost(I.bcs[kbc >> 4], t_cand, cp.y, g, hg, ung))
-                        ghost_cfl<T, TILE>(S, a, l, hg, ung, g, cp.x);
+                        ghost_cfl<T, TILE>(S, l, hg, ung, g, cp.x);
                 }
             }
             continue;
         }
-        const V4<T> sa = S.st[a];
+        const V4<T> sa = S.huvz[a];
         // a's velocity in the frame (n, t)
         T una, uta;
-        rotate(S.u[a], S.v[a], nx, ny, una, uta);
+        rotate(sa.y, sa.z, nx, ny, una, uta);
         T F0, F1, F2, ha, hb = T(0);
         if (kind != EK_BOUNDARY) {
             V4<T> sb;
             T ub, vb;
             if (kind == EK_LOCAL) {
                 const int b = (E.w0 >> 17) & 1023;
-                sb = S.st[b];
-                ub = S.u[b];
-                vb = S.v[b];
+                sb = S.huvz[b];
+                ub = sb.y;
+                vb = sb.z;
             } else {
                 sb = src[E.w1];
+                whole(sb);
                 const double hbd = double(sb.x) - double(sb.w);
                 const bool bwet = hbd > h_min;
                 const T hh = T(hbd);
@@ -447,7 +496,7 @@ __device__ __forceinline__ void tile_edges(const Inst<T> &I, TileLds<T, TILE> &S
                     hllc(ha, una, uta, ha, -una, uta, g, F0, F1, F2);
                     F0 = T(0);
                 }
-                if (inflow_ghost(I.bcs[bi], t_cand, cp.y, g, hg, ung)) ghost_cfl<T, TILE>(S, a, l, hg, ung, g, cp.x);
+                if (inflow_ghost(I.bcs[bi], t_cand, cp.y, g, hg, ung)) ghost_cfl<T, TILE>(S, l, hg, ung, g, cp.x);
             } else {
                 // reflective, impermeable wall: mirrored normal velocity
                 hllc(ha, una, uta, ha, -una, uta, g, F0, F1, F2);
@@ -489,15 +538,15 @@ __device__ __forceinline__ void tile_edges(const Inst<T> &I, TileLds<T, TILE> &S
 }
 
 // CFL term of cell c of the tile with state (H, qx, qy, z), from the edge
-// geometry and ghost terms left in LDS.  ap is |cell| (FP64) or 1/|cell|
-// (FP32).  A dry cell contributes only its inflow ghosts.
+// geometry left in LDS.  ap is |cell| (FP64) or 1/|cell| (FP32).  A dry cell
+// contributes nothing (its inflow ghosts are in the tile's ghost term).
 template <typename T, int TILE>
 __device__ __forceinline__ CandT<T> tile_candidate(const Inst<T> &I, const TileLds<T, TILE> &S, int c, T ap, T H,
                                                    T qx, T qy, T z) {
     const T g = T(I.g);
     const double h2 = double(H) - double(z);
     if constexpr (IS32<T>) {
-        float lmax = __uint_as_float(S.ghost[c]);
+        float lmax = 0.0f;
         if (h2 > I.h_min) {
             const float hh = float(h2);
             const float rh = __builtin_amdgcn_rcpf(hh);
@@ -509,7 +558,7 @@ __device__ __forceinline__ CandT<T> tile_candidate(const Inst<T> &I, const TileL
         }
         return lmax * ap;
     } else {
-        double best = __longlong_as_double((long long)S.ghost[c]);
+        double best = INFINITY;
         if (h2 > I.h_min) {
             const double hh = h2;
             const double u2 = qx / hh, v2 = qy / hh;
@@ -529,13 +578,12 @@ __device__ __forceinline__ CandT<T> tile_candidate(const Inst<T> &I, const TileL
 // the CFL term of the new state.
 template <typename T, int TILE>
 __device__ __forceinline__ CandT<T> tile_update(const Inst<T> &I, const TileLds<T, TILE> &S, int tile, int cur,
-                                                double dt) {
+                                                double dt, const V4<T> &s) {
     const int c = threadIdx.x;
     const int i = tile * TILE + c;
     if (i >= I.n) return IS32<T> ? T(0) : T(INFINITY);
     V4<T> *__restrict__ dst = cur ? I.U0 : I.U1;
     const double h_min = I.h_min;
-    const V4<T> s = S.st[c];
     const V2<T> cp = I.cellp[i];
     const T gn2 = cp.y;
     // residual in local edge order, then the conservative update
@@ -577,10 +625,11 @@ __device__ __forceinline__ CandT<T> tile_update(const Inst<T> &I, const TileLds<
     return tile_candidate<T, TILE>(I, S, c, cp.x, Hn, qx, qy, s.w);
 }
 
-// Occupancy hint (minimum waves per SIMD): the tile's LDS allows six FP32
-// waves per SIMD at every tile size, and three FP64 waves (two at 512 cells),
-// so the register budget is set to match.
-template <typename T, int TILE> constexpr int WAVES_PER_SIMD = IS32<T> ? 6 : (TILE >= 512 ? 2 : 3);
+// Occupancy hint (minimum waves per SIMD): what the tile's LDS allows (FP32:
+// seven waves per SIMD, six at 512 cells; FP64: three, two at 512 cells), so
+// the register budget matches it.
+template <typename T, int TILE>
+constexpr int WAVES_PER_SIMD = IS32<T> ? (TILE >= 512 ? 6 : 7) : (TILE >= 512 ? 2 : 3);
 
 template <typename T, int TILE>
 __global__ void __launch_bounds__(TILE, (WAVES_PER_SIMD<T, TILE>)) k_step(Inst<T> I, int phase) {
@@ -588,9 +637,12 @@ __global__ void __launch_bounds__(TILE, (WAVES_PER_SIMD<T, TILE>)) k_step(Inst<T
     const bool lead = blockIdx.x == 0;
     const Level L = step_setup(I.ctrl, phase, I.cfl, I.dt_max, lead);
     if (!L.run) return;
-    tile_edges<T, TILE, true>(I, S, blockIdx.x, L.cur, L.t, L.dt, L.t + L.dt);
-    const CandT<T> cand = tile_update<T, TILE>(I, S, blockIdx.x, L.cur, L.dt);
-    block_finish(I.ctrl, phase, cand, L, lead, true);
+    V4<T> own;
+    tile_edges<T, TILE, true>(I, S, blockIdx.x, L.cur, L.t, L.dt, L.t + L.dt, own);
+    const unsigned long long seen = threadIdx.x == 0 ? load_agent(cfl_slot(I.ctrl, phase, true)) : 0ull;
+    CandT<T> cand = tile_update<T, TILE>(I, S, blockIdx.x, L.cur, L.dt, own);
+    if (threadIdx.x == 0) cand = combine(cand, ghost_value(S.ghost));
+    block_finish<false>(I.ctrl, phase, cand, L, lead, true, seen);
 }
 
 // CFL minimum of the state of level `phase` (after an initialisation); the
@@ -606,15 +658,17 @@ __global__ void __launch_bounds__(TILE) k_dt_init(Inst<T> I, int phase) {
     L.steps = 0;
     L.rawmin = 0.0;
     L.run = true;
-    tile_edges<T, TILE, false>(I, S, blockIdx.x, L.cur, L.t, 0.0, L.t);
+    V4<T> s;
+    tile_edges<T, TILE, false>(I, S, blockIdx.x, L.cur, L.t, 0.0, L.t, s);
+    const unsigned long long seen = threadIdx.x == 0 ? load_agent(cfl_slot(I.ctrl, phase, false)) : 0ull;
     CandT<T> cand = IS32<T> ? T(0) : T(INFINITY);
     const int i = blockIdx.x * TILE + threadIdx.x;
     if (i < I.n) {
-        const V4<T> s = S.st[threadIdx.x];
         const V2<T> cp = I.cellp[i];
         cand = tile_candidate<T, TILE>(I, S, threadIdx.x, cp.x, s.x, s.y, s.z, s.w);
     }
-    block_finish(I.ctrl, phase, cand, L, false, false);
+    if (threadIdx.x == 0) cand = combine(cand, ghost_value(S.ghost));
+    block_finish<false>(I.ctrl, phase, cand, L, false, false, seen);
 }
 
 // Persistent batched step: blocks stride over a list of (member, tile)
@@ -630,9 +684,12 @@ __global__ void __launch_bounds__(TILE, (WAVES_PER_SIMD<T, TILE>)) k_step_batche
         const bool lead = td.y == 0;
         const Level L = step_setup(I.ctrl, phase, I.cfl, I.dt_max, lead);
         if (!L.run) continue;
-        tile_edges<T, TILE, true>(I, S, td.y, L.cur, L.t, L.dt, L.t + L.dt);
-        const CandT<T> cand = tile_update<T, TILE>(I, S, td.y, L.cur, L.dt);
-        block_finish(I.ctrl, phase, cand, L, lead, true);
+        V4<T> own;
+        tile_edges<T, TILE, true>(I, S, td.y, L.cur, L.t, L.dt, L.t + L.dt, own);
+        const unsigned long long seen = threadIdx.x == 0 ? load_agent(cfl_slot(I.ctrl, phase, true)) : 0ull;
+        CandT<T> cand = tile_update<T, TILE>(I, S, td.y, L.cur, L.dt, own);
+        if (threadIdx.x == 0) cand = combine(cand, ghost_value(S.ghost));
+        block_finish<true>(I.ctrl, phase, cand, L, lead, true, seen);
     }
 }
 

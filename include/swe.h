@@ -81,6 +81,11 @@ typedef struct {
 } swe_bc;
 
 enum { SWE_FP64 = 0, SWE_FP32 = 1 };        /* precision (double is the paper's default) */
+/* Friction closures (eq. friction_closure, Table friction_closure): the
+ * per-cell parameter given to swe_state_init is Manning n [s m^-1/3],
+ * Strickler k_str [m^1/3 s^-1], Chezy K_s [m] or Bezzola y_R [m]; 0 means no
+ * friction in that cell. */
+enum { SWE_FRICTION_MANNING = 0, SWE_FRICTION_STRICKLER = 1, SWE_FRICTION_CHEZY = 2, SWE_FRICTION_BEZZOLA = 3 };
 enum { SWE_NEG_CLIP = 0, SWE_NEG_ERROR = 1 }; /* negative-depth policy */
 
 /* Parameters (supplementary feature table, hydrodynamics parameters: CFL,
@@ -97,6 +102,7 @@ typedef struct {
     int32_t cells_per_thread; /* reserved: 0 or 1 */
     int32_t steps_per_graph;  /* steps captured per hipGraph in swe_run_until; 0 = default (32) */
     int32_t renumber;       /* 1 = Hilbert order of cell centroids (default), 0 = input order */
+    int32_t friction;       /* SWE_FRICTION_* closure (default Manning) */
 } swe_params;
 
 /* Fills *p with the defaults listed above. */
@@ -130,11 +136,14 @@ swe_status swe_mesh_check(const swe_mesh *m, int32_t tile);
  * conditions": region-defined initial values or dry).  Exactly one of
  * H0 (surface elevation; values below the cell bed mean a dry cell) and h0
  * (depth >= 0) may be non-NULL; both NULL means dry.  qx0, qy0 (discharge per
- * unit width) may be NULL (zero); manning (n >= 0 per cell) may be NULL
- * (frictionless).  All arrays are host arrays of n_cells doubles in original
- * cell order.  bcs[n_bc] maps tags to kinds; inflow edges need n > 0 in
- * their cell.  t0 is the start time (restart = re-init from a read state).
- * params may be NULL.  Computes the first time step on the device. */
+ * unit width) may be NULL (zero); manning (the friction parameter >= 0 per
+ * cell of the closure params->friction selects: Manning n by default) may be
+ * NULL (frictionless).  All arrays are host arrays of n_cells doubles in
+ * original cell order.  bcs[n_bc] maps tags to kinds; inflow edges need the
+ * Manning or Strickler closure (their normal depth has a closed form) and a
+ * positive parameter in their cell.  t0 is the start time (restart = re-init
+ * from a read state).  params may be NULL.  Computes the first time step on
+ * the device. */
 swe_status swe_state_init(const swe_mesh *m, const swe_params *params, const double *H0,
                           const double *h0, const double *qx0, const double *qy0,
                           const double *manning, const swe_bc *bcs, int32_t n_bc, double t0,

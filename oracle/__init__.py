@@ -78,6 +78,12 @@ def lib():
         L.om_hllc.argtypes = [ctypes.c_double] * 7 + [_c_double_p]
         L.om_friction.restype = ctypes.c_double
         L.om_friction.argtypes = [ctypes.c_double] * 5
+        L.om_friction_cf.restype = ctypes.c_double
+        L.om_friction_cf.argtypes = [ctypes.c_int32, ctypes.c_double, ctypes.c_double]
+        L.om_friction_closure.restype = ctypes.c_double
+        L.om_friction_closure.argtypes = [ctypes.c_int32] + [ctypes.c_double] * 5
+        L.om_sim_set_friction.restype = ctypes.c_int
+        L.om_sim_set_friction.argtypes = [ctypes.c_void_p, ctypes.c_int32, _c_double_p, ctypes.c_char_p, ctypes.c_int]
         _lib = L
     return _lib
 
@@ -106,6 +112,21 @@ def hllc(hL, unL, utL, hR, unR, utR, g=9.81):
 
 def friction_factor(qabs, h, gn2, dt, h_min=1e-4):
     return lib().om_friction(qabs, h, gn2, dt, h_min)
+
+
+# friction closures of Table friction_closure, by name
+FRICTION = {"manning": 0, "strickler": 1, "chezy": 2, "bezzola": 3}
+
+
+def friction_cf(kind, par, h):
+    """c_f of a log-type closure ("chezy": par = K_s, "bezzola": par = y_R)."""
+    return lib().om_friction_cf(FRICTION[kind], par, h)
+
+
+def friction_closure(kind, coef, qabs, h, dt, h_min=1e-4):
+    """Split factor of one closure; coef is g n^2 / g k^-2 for the power
+    laws and K_s / y_R for the log types, as the step stores it."""
+    return lib().om_friction_closure(FRICTION[kind], coef, qabs, h, dt, h_min)
 
 
 class Mesh:
@@ -172,6 +193,10 @@ class Sim:
         if not self._p:
             raise OracleError(err.value.decode())
         self.n = n
+        kind = getattr(sc, "friction", "manning")
+        if kind != "manning":
+            if L.om_sim_set_friction(self._p, FRICTION[kind], _dp(man), err, 256):
+                raise OracleError(err.value.decode())
 
     def __del__(self):
         if getattr(self, "_p", None):

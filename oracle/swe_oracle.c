@@ -10,7 +10,7 @@
  *   bed slope by hydrostatic reconstruction of modified states, written in
  *   fluctuation form (well balanced)                       (source-term paragraph)
  *   friction by operator splitting after the flux update  (source-term paragraph,
- *                                                          eq. friction_closure, Manning row)
+ *                                                          eq. friction_closure, Table friction_closure)
  *   dt = CFL min_i min_j rho_ij / lambda_ij                (eq. CFL_condition)
  *   walls: reflective, frictionless, impermeable          (section "Boundary conditions")
  *
@@ -48,7 +48,9 @@ typedef struct {
 struct om_sim {
     const om_mesh *m;
     double g, cfl, h_min, dt_max;
-    double *H, *qx, *qy, *gn2;
+    double *H, *qx, *qy;
+    int32_t fkind;       /* friction closure (OM_MANNING ... OM_BEZZOLA) */
+    double *gn2;         /* per cell: g n^2 (Manning), g / k^2 (Strickler), K_s (Chezy), y_R (Bezzola) */
     double t;
     int32_t nbc;
     om_bc *bc;
@@ -447,6 +449,58 @@ double om_friction(double qabs, double h, double gn2, double dt, double h_min) {
     return 1.0 / (1.0 + dt * gn2 * qabs / pow(h, 7.0 / 3.0));
 }
 
+/* Dimensionless friction coefficient c_f of the log-type closures of Table
+ * friction_closure: Chezy (par = K_s) and Bezzola (par = y_R).  Reading: the
+ * printed "log" is the natural logarithm, and the Chezy row is taken as
+ * printed (6.25 + log(h/K_s) above K_s, 6.25 at or below). */
+double om_friction_cf(int32_t kind, double par, double h) {
+    if (kind == OM_CHEZY) return h > par ? 6.25 + log(h / par) : 6.25;
+    double r = h / par;
+    if (r > 2.0) return 2.5 * sqrt(1.0 - 1.0 / r) * log(10.9 * r);
+    if (r >= 0.5) return 1.25 * sqrt(r) * log(10.9 * r);
+    return 1.5;
+}
+
+/* Friction split for every closure of Table friction_closure.  With
+ * S_f = u|u| / (g h c_f^2) (eq. friction_closure) the momentum sink is
+ * g h S_f = |q| q / (h^2 c_f^2), so the exact one-step factor is
+ * 1 / (1 + dt |q| / (h^2 c_f^2)); for the power-law closures (Manning,
+ * Strickler: c_f^2 = h^{1/3} / (g n^2), n = 1/k_str) this is the Manning form
+ * above.  par <= 0 means no friction. */
+double om_friction_closure(int32_t kind, double par, double qabs, double h, double dt, double h_min) {
+    if (kind == OM_MANNING || kind == OM_STRICKLER) return om_friction(qabs, h, par, dt, h_min);
+    if (!(h > h_min)) return 0.0;
+    if (!(par > 0)) return 1.0;
+    double cf = om_friction_cf(kind, par, h);
+    return 1.0 / (1.0 + dt * qabs / (h * h * cf * cf));
+}
+
+/* Selects the friction closure (Table friction_closure) and its per-cell
+ * parameter: Manning n, Strickler k_str, Chezy K_s or Bezzola y_R (all >= 0;
+ * 0 = frictionless).  The inflow ghost's normal depth has a closed form only
+ * for the power-law closures, so inflow conditions require Manning or
+ * Strickler (with a positive parameter on their cells). */
+int om_sim_set_friction(om_sim *s, int32_t kind, const double *par, char *err, int elen) {
+    const om_mesh *m = s->m;
+    if (kind < OM_MANNING || kind > OM_BEZZOLA) { seterr(err, elen, "unknown friction closure"); return -1; }
+    for (int64_t i = 0; i < m->nc; i++) {
+        double p = par ? par[i] : 0.0;
+        if (!(p >= 0) || !isfinite(p)) { seterr(err, elen, "negative or non-finite friction parameter"); return -1; }
+        if (kind == OM_MANNING) s->gn2[i] = s->g * p * p;
+        else if (kind == OM_STRICKLER) s->gn2[i] = p > 0 ? s->g / (p * p) : 0.0;
+        else s->gn2[i] = p;
+    }
+    s->fkind = kind;
+    for (int64_t e = 0; e < m->ne; e++) {
+        if (s->ebc[e] < 0 || s->bc[s->ebc[e]].kind != OM_INFLOW_UNIFORM) continue;
+        if (kind == OM_CHEZY || kind == OM_BEZZOLA) {
+            seterr(err, elen, "inflow uniform(Q, S) needs the Manning or Strickler closure"); return -1;
+        }
+        if (!(s->gn2[m->eL[e]] > 0)) { seterr(err, elen, "inflow edge next to a frictionless cell"); return -1; }
+    }
+    return 0;
+}
+
 static void cell_velocity(const om_sim *s, int32_t i, double *h, double *u, double *v) {
     *h = s->H[i] - s->m->zb[i];
     if (*h > s->h_min) { *u = s->qx[i] / *h; *v = s->qy[i] / *h; }
@@ -565,7 +619,7 @@ int om_step(om_sim *s, double t_end, double *dt_taken) {
         double qx = s->qx[i] - w * Rx;
         double qy = s->qy[i] - w * Ry;
         double h = H - m->zb[i];
-        double f = om_friction(sqrt(qx * qx + qy * qy), h, s->gn2[i], dt, s->h_min);
+        double f = om_friction_closure(s->fkind, s->gn2[i], sqrt(qx * qx + qy * qy), h, dt, s->h_min);
         qx = qx * f;
         qy = qy * f;
         if (h < 0.0) {

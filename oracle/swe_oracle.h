@@ -21,6 +21,8 @@ typedef struct om_sim om_sim;
 
 /* boundary kinds */
 enum { OM_WALL = 0, OM_INFLOW_UNIFORM = 1, OM_OUTFLOW_ZEROGRAD = 2 };
+/* friction closures (Table friction_closure) */
+enum { OM_MANNING = 0, OM_STRICKLER = 1, OM_CHEZY = 2, OM_BEZZOLA = 3 };
 
 om_mesh *om_mesh_new(const double *node_xyz, int64_t n_nodes, const int32_t *tri, int64_t n_tri,
                      const int32_t *bnd_seg, const int32_t *bnd_tag, int64_t n_seg,
@@ -38,6 +40,9 @@ om_sim *om_sim_new(const om_mesh *m, double g, double cfl, double h_min, double 
                    const int32_t *bc_kind, const double *bc_slope, const int32_t *bc_npts,
                    const double *bc_t, const double *bc_Q, double t0, char *err, int err_len);
 void om_sim_free(om_sim *s);
+/* closure and per-cell parameter (n, k_str, K_s or y_R); default Manning
+ * with the array given to om_sim_new.  0 or -1 (message in err). */
+int om_sim_set_friction(om_sim *s, int32_t kind, const double *par, char *err, int err_len);
 
 double om_next_dt(const om_sim *s, double t_end);
 int om_step(om_sim *s, double t_end, double *dt_taken);
@@ -50,4 +55,6 @@ void om_diag(const om_sim *s, double *mass, double *bnd_flux, double *clipped, i
 void om_hllc(double hL, double unL, double utL, double hR, double unR, double utR, double g,
              double F[3]);
 double om_friction(double q_abs_scale, double h, double gn2, double dt, double h_min);
+double om_friction_cf(int32_t kind, double par, double h);
+double om_friction_closure(int32_t kind, double par, double q_abs, double h, double dt, double h_min);
 #endif

@@ -256,6 +256,10 @@ struct swe_state {
 
 extern "C" {
 
+static_assert(FR_MANNING == SWE_FRICTION_MANNING && FR_STRICKLER == SWE_FRICTION_STRICKLER &&
+                  FR_CHEZY == SWE_FRICTION_CHEZY && FR_BEZZOLA == SWE_FRICTION_BEZZOLA,
+              "friction closure numbering");
+
 void swe_params_default(swe_params *p) {
     if (!p) return;
     p->g = 9.81;
@@ -268,6 +272,7 @@ void swe_params_default(swe_params *p) {
     p->cells_per_thread = 0;
     p->steps_per_graph = 0;
     p->renumber = 1;
+    p->friction = SWE_FRICTION_MANNING;
 }
 
 const char *swe_last_error(void) { return g_err.c_str(); }
@@ -347,6 +352,8 @@ swe_status swe_state_init(const swe_mesh *m, const swe_params *params, const dou
     if (P.block_size != 0 && !valid_tile(P.block_size)) return fail(SWE_EINVAL, "block_size must be 0, 128, 256 or 512");
     if (P.cells_per_thread < 0 || P.cells_per_thread > 1) return fail(SWE_EINVAL, "cells_per_thread must be 0 or 1");
     if (P.steps_per_graph < 0 || P.steps_per_graph > 4096) return fail(SWE_EINVAL, "steps_per_graph out of range");
+    if (P.friction < SWE_FRICTION_MANNING || P.friction > SWE_FRICTION_BEZZOLA)
+        return fail(SWE_EINVAL, "unknown friction closure");
     if (H0 && h0) return fail(SWE_EINVAL, "give H0 or h0, not both");
     if (!std::isfinite(t0)) return fail(SWE_EINVAL, "t0 must be finite");
     if (n_bc < 0 || n_bc > MAX_BC || (n_bc > 0 && !bcs)) return fail(SWE_EINVAL, "bad boundary-condition list");
@@ -370,11 +377,18 @@ swe_status swe_state_init(const swe_mesh *m, const swe_params *params, const dou
         }
         const double a = qx0 ? qx0[i] : 0.0, b = qy0 ? qy0[i] : 0.0, nn = manning ? manning[i] : 0.0;
         if (!std::isfinite(a) || !std::isfinite(b)) return fail(SWE_EINVAL, "non-finite initial discharge");
-        if (!(nn >= 0) || !std::isfinite(nn)) return fail(SWE_EINVAL, "Manning n must be finite and >= 0");
+        if (!(nn >= 0) || !std::isfinite(nn)) return fail(SWE_EINVAL, "friction parameter must be finite and >= 0");
         H[p] = Hi;
         qx[p] = a;
         qy[p] = b;
-        gn2[p] = P.g * nn * nn;
+        // friction coefficient as the kernels use it: g n^2 for the power
+        // laws (Strickler: n = 1/k_str), K_s or y_R for the log types
+        if (P.friction == SWE_FRICTION_MANNING)
+            gn2[p] = P.g * nn * nn;
+        else if (P.friction == SWE_FRICTION_STRICKLER)
+            gn2[p] = nn > 0 ? P.g / (nn * nn) : 0.0;
+        else
+            gn2[p] = nn;
     }
     // boundary conditions
     std::vector<BCdev> hb((size_t)std::max(n_bc, 1));
@@ -408,8 +422,10 @@ swe_status swe_state_init(const swe_mesh *m, const swe_params *params, const dou
             if (bcs[b].kind == SWE_BC_WALL) break;
             kbc[s] = bcs[b].kind | (b << 4);
             lens[b].push_back(M.slot_len[s]);
+            if (bcs[b].kind == SWE_BC_INFLOW_UNIFORM && P.friction >= SWE_FRICTION_CHEZY)
+                return fail(SWE_EINVAL, "inflow uniform(Q, S) needs the Manning or Strickler closure");
             if (bcs[b].kind == SWE_BC_INFLOW_UNIFORM && !(gn2[M.slot_cell[s]] > 0))
-                return fail(SWE_EINVAL, "inflow edge next to a cell with Manning n = 0");
+                return fail(SWE_EINVAL, "inflow edge next to a frictionless cell");
             break;
         }
     }
@@ -514,7 +530,7 @@ swe_status swe_state_init(const swe_mesh *m, const swe_params *params, const dou
         I.h_min = P.h_min;
         I.dt_max = P.dt_max;
         I.neg_policy = P.neg_depth_policy;
-        I.pad = 0;
+        I.friction = P.friction;
     };
     if (prec == SWE_FP32) {
         fill_inst(S->inst32, float());

@@ -9,8 +9,8 @@
 // mass one cell loses is bitwise the mass the other gains).  Phase 2 gives
 // each cell to one thread: it sums its three contributions in local edge
 // order, applies the conservative update (paper: eq.
-// hydrodynamicupdateformula), the Manning friction split (eq.
-// friction_closure, Table friction_closure) and the positivity clip, writes
+// hydrodynamicupdateformula), the friction split (eq. friction_closure, any
+// closure of Table friction_closure) and the positivity clip, writes
 // its new state and computes its CFL candidate (eq. CFL_condition).  A wave64
 // shuffle, an LDS pass and at most one atomic min per block give the next
 // time step; block 0 publishes the next time level, so a run of steps needs no
@@ -195,16 +195,45 @@ __device__ __forceinline__ void neumaier(double &s, double &c, double v) {
     s = t;
 }
 
-// Manning friction split: the exact solution of dq/dt = -g n^2 |q| q / h^(7/3)
-// over dt scales q by 1 / (1 + dt g n^2 |q| / h^(7/3)).
-__device__ __forceinline__ double friction_factor(double dt, double gn2, double qx, double qy, double h) {
-    const double qa = sqrt(qx * qx + qy * qy);
-    return 1.0 / (1.0 + dt * gn2 * qa / pow(h, 7.0 / 3.0));
+// Friction split (eq. friction_closure, Table friction_closure).  With
+// S_f = u|u| / (g h c_f^2) the momentum sink is |q| q / (h^2 c_f^2); its exact
+// solution over dt (h frozen) scales q by 1 / (1 + dt |q| / (h^2 c_f^2)).  The
+// power laws (Manning; Strickler with n = 1/k_str) give
+// 1 / (1 + dt g n^2 |q| / h^(7/3)) with par = g n^2; the log types take
+// par = K_s (Chezy: c_f = 6.25 + ln(h/K_s) above K_s, else 6.25) or y_R
+// (Bezzola, three branches in h/y_R).
+__device__ __forceinline__ double friction_cf(int kind, double par, double h) {
+    if (kind == FR_CHEZY) return h > par ? 6.25 + log(h / par) : 6.25;
+    const double r = h / par;
+    if (r > 2.0) return 2.5 * sqrt(1.0 - 1.0 / r) * log(10.9 * r);
+    if (r >= 0.5) return 1.25 * sqrt(r) * log(10.9 * r);
+    return 1.5;
 }
-__device__ __forceinline__ float friction_factor(float dt, float gn2, float qx, float qy, float h) {
+__device__ __forceinline__ double friction_factor(int kind, double dt, double par, double qx, double qy,
+                                                  double h) {
+    const double qa = sqrt(qx * qx + qy * qy);
+    if (kind <= FR_STRICKLER) return 1.0 / (1.0 + dt * par * qa / pow(h, 7.0 / 3.0));
+    const double cf = friction_cf(kind, par, h);
+    return 1.0 / (1.0 + dt * qa / (h * h * cf * cf));
+}
+__device__ __forceinline__ float friction_cf(int kind, float par, float h) {
+    constexpr float LN2 = 0.693147180559945f;
+    if (kind == FR_CHEZY)
+        return h > par ? fmaf(LN2, __builtin_amdgcn_logf(h * __builtin_amdgcn_rcpf(par)), 6.25f) : 6.25f;
+    const float r = h * __builtin_amdgcn_rcpf(par);
+    const float ln = LN2 * __builtin_amdgcn_logf(10.9f * r);
+    if (r > 2.0f) return 2.5f * qsqrt(1.0f - __builtin_amdgcn_rcpf(r)) * ln;
+    if (r >= 0.5f) return 1.25f * qsqrt(r) * ln;
+    return 1.5f;
+}
+__device__ __forceinline__ float friction_factor(int kind, float dt, float par, float qx, float qy, float h) {
     const float qa = qsqrt(fmaf(qx, qx, qy * qy));
-    const float hp = __builtin_amdgcn_exp2f((-7.0f / 3.0f) * __builtin_amdgcn_logf(h));  // h^(-7/3)
-    return __builtin_amdgcn_rcpf(fmaf(dt * gn2 * qa, hp, 1.0f));
+    if (kind <= FR_STRICKLER) {
+        const float hp = __builtin_amdgcn_exp2f((-7.0f / 3.0f) * __builtin_amdgcn_logf(h));  // h^(-7/3)
+        return __builtin_amdgcn_rcpf(fmaf(dt * par * qa, hp, 1.0f));
+    }
+    const float cf = friction_cf(kind, par, h);
+    return __builtin_amdgcn_rcpf(fmaf(dt * qa, __builtin_amdgcn_rcpf(h * h * cf * cf), 1.0f));
 }
 
 // CFL terms (eq. CFL_condition, rho = twice the centroid-edge distance =
@@ -606,7 +635,7 @@ __device__ __forceinline__ CandT<T> tile_update(const Inst<T> &I, const TileLds<
     // friction split
     T f;
     if (hn > h_min)
-        f = gn2 > T(0) ? friction_factor(T(dt), gn2, qx, qy, T(hn)) : T(1);
+        f = gn2 > T(0) ? friction_factor(I.friction, T(dt), gn2, qx, qy, T(hn)) : T(1);
     else
         f = T(0);
     qx = qx * f;

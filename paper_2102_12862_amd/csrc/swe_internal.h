@@ -10,7 +10,8 @@ namespace swe {
 // Device layout (cells renumbered along a Hilbert curve of their centroids):
 //   U[2][n]   vec4 (H, qx, qy, z)  ping-pong state; z rides along so a cell's
 //             whole state is one vector load
-//   cellp[n]  vec2 (|cell| in FP64, 1/|cell| in FP32; g n^2)
+//   cellp[n]  vec2 (|cell| in FP64, 1/|cell| in FP32; friction coefficient:
+//             g n^2 for Manning and Strickler, K_s for Chezy, y_R for Bezzola)
 //   edges     per tile of TILE consecutive cells, every edge touching the tile
 //             once (see TileEdge in meshprep.h): two ints and l*n
 //   eoff      first edge of each tile
@@ -37,6 +38,8 @@ enum : int { EK_LOCAL = 0, EK_REMOTE = 1, EK_BOUNDARY = 2 };
 
 enum : int { BC_WALL = 0, BC_INFLOW = 1, BC_OUTFLOW = 2 };
 enum : int { FLAG_NONFINITE = 1, FLAG_NEGDEPTH = 2, FLAG_NODT = 4 };
+// friction closures, numbered as SWE_FRICTION_* in swe.h
+enum : int { FR_MANNING = 0, FR_STRICKLER = 1, FR_CHEZY = 2, FR_BEZZOLA = 3 };
 constexpr int MAX_BC = 64;
 
 // Boundary condition record on the device.
@@ -86,7 +89,7 @@ constexpr unsigned long long INF_BITS = 0x7FF0000000000000ull;
 template <typename T> struct Inst {
     V4<T> *U0;
     V4<T> *U1;
-    const V2<T> *cellp;    // (|cell| in FP64, 1/|cell| in FP32; g n^2)
+    const V2<T> *cellp;    // (|cell| in FP64, 1/|cell| in FP32; friction coefficient)
     const Edge<T> *edges;  // tile edge lists
     const int *eoff;       // first edge of each tile (ntiles + 1)
     const int *slot_kbc;   // per boundary slot: kind | (bc index << 4)
@@ -98,7 +101,7 @@ template <typename T> struct Inst {
     int ntiles;            // tiles of this state's mesh
     double g, cfl, h_min, dt_max;
     int neg_policy;
-    int pad;
+    int friction;          // SWE_FRICTION_* closure
 };
 
 // Launch wrappers (kernels.hip).

@@ -21,6 +21,7 @@ OK, EINVAL, ENOMEM, EDEVICE, ENONFINITE, ENEGDEPTH, EBUDGET, ENODT = 0, -1, -2, 
 BC_WALL, BC_INFLOW_UNIFORM, BC_OUTFLOW_ZEROGRAD = 0, 1, 2
 FP64, FP32 = 0, 1
 NEG_CLIP, NEG_ERROR = 0, 1
+FRICTION = {"manning": 0, "strickler": 1, "chezy": 2, "bezzola": 3}
 
 _dp = ctypes.POINTER(ctypes.c_double)
 _ip = ctypes.POINTER(ctypes.c_int32)
@@ -43,7 +44,7 @@ class SweParams(ctypes.Structure):
     _fields_ = [("g", ctypes.c_double), ("cfl", ctypes.c_double), ("h_min", ctypes.c_double),
                 ("dt_max", ctypes.c_double), ("precision", ctypes.c_int32), ("neg_depth_policy", ctypes.c_int32),
                 ("block_size", ctypes.c_int32), ("cells_per_thread", ctypes.c_int32),
-                ("steps_per_graph", ctypes.c_int32), ("renumber", ctypes.c_int32)]
+                ("steps_per_graph", ctypes.c_int32), ("renumber", ctypes.c_int32), ("friction", ctypes.c_int32)]
 
 
 # every symbol the header declares, with (restype, argtypes)
@@ -217,6 +218,7 @@ class State:
         L = load()
         self.mesh = mesh
         self.precision = precision
+        pkw.setdefault("friction", FRICTION[getattr(sc, "friction", "manning")])
         p = params(g=sc.g, cfl=sc.cfl, h_min=sc.h_min, dt_max=sc.dt_max, precision=precision, **pkw)
         if H0 is None and h0 is None:
             H0, h0 = sc.H0, sc.h0

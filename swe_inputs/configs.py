@@ -56,12 +56,13 @@ class Scenario:
     h0: Optional[np.ndarray]     # (N,) water depth (used when H0 is None)
     qx0: np.ndarray
     qy0: np.ndarray
-    manning: np.ndarray          # (N,) Manning n [s m^-1/3]
+    manning: np.ndarray          # (N,) friction parameter: Manning n [s m^-1/3] (or k_str, K_s, y_R)
     t_end: float
     g: float = 9.81
     cfl: float = 0.9
     h_min: float = 1e-4
     dt_max: float = float("inf")
+    friction: str = "manning"    # closure the `manning` array parameterises: manning, strickler, chezy, bezzola
 
     @property
     def n_cells(self) -> int:

@@ -65,19 +65,22 @@ typedef struct {
 } swe_device;
 
 /* Boundary kinds (section "Boundary conditions", Hydrodynamic BCs; the
- * supplementary feature table lists wall, inflow uniform(discharge, slope)
- * and outflow zero_gradient among the standard types).  Boundary edges whose
- * tag has no entry, and untagged boundary edges, are walls (walls are the
- * default on every external boundary). */
-enum { SWE_BC_WALL = 0, SWE_BC_INFLOW_UNIFORM = 1, SWE_BC_OUTFLOW_ZEROGRAD = 2 };
+ * supplementary feature table lists wall, inflow uniform(discharge, slope),
+ * outflow zero_gradient and zhydrograph (water surface elevation) among the
+ * standard types).  A zhydrograph edge sees still water at the prescribed
+ * surface elevation over its cell's bed, so water flows in or out as the
+ * interior level differs.  Boundary edges whose tag has no entry, and
+ * untagged boundary edges, are walls (walls are the default on every external
+ * boundary). */
+enum { SWE_BC_WALL = 0, SWE_BC_INFLOW_UNIFORM = 1, SWE_BC_OUTFLOW_ZEROGRAD = 2, SWE_BC_ZHYDROGRAPH = 3 };
 
 typedef struct {
     int32_t tag;      /* boundary tag given to swe_mesh_create */
     int32_t kind;     /* SWE_BC_* */
     double slope;     /* inflow: energy slope S > 0 of uniform(Q, S) */
-    const double *t;  /* inflow hydrograph times [s], strictly increasing (host) */
-    const double *Q;  /* inflow hydrograph discharge [m^3/s] (host) */
-    int32_t n_pts;    /* number of hydrograph points (>= 1 for inflow) */
+    const double *t;  /* series times [s], strictly increasing (host) */
+    const double *Q;  /* inflow: discharge [m^3/s]; zhydrograph: surface elevation [m] (host) */
+    int32_t n_pts;    /* number of series points (>= 1 for inflow and zhydrograph) */
 } swe_bc;
 
 enum { SWE_FP64 = 0, SWE_FP32 = 1 };        /* precision (double is the paper's default) */

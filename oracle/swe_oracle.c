@@ -316,9 +316,10 @@ om_sim *om_sim_new(const om_mesh *m, double g, double cfl, double h_min, double 
         om_bc *B = &s->bc[b];
         B->tag = bc_tag[b]; B->kind = bc_kind[b]; B->slope = bc_slope ? bc_slope[b] : 0.0;
         B->npts = bc_npts ? bc_npts[b] : 0;
-        if (B->kind < 0 || B->kind > 2) { seterr(err, elen, "unknown boundary kind"); goto fail; }
-        if (B->kind == OM_INFLOW_UNIFORM) {
-            if (B->npts < 1 || !(B->slope > 0)) { seterr(err, elen, "inflow needs a hydrograph and a positive slope"); goto fail; }
+        if (B->kind < 0 || B->kind > 3) { seterr(err, elen, "unknown boundary kind"); goto fail; }
+        if (B->kind == OM_ZHYDROGRAPH && B->npts < 1) { seterr(err, elen, "zhydrograph needs a series"); goto fail; }
+        if (B->kind == OM_INFLOW_UNIFORM || B->kind == OM_ZHYDROGRAPH) {
+            if (B->kind == OM_INFLOW_UNIFORM && (B->npts < 1 || !(B->slope > 0))) { seterr(err, elen, "inflow needs a hydrograph and a positive slope"); goto fail; }
             B->t = malloc(sizeof(double) * B->npts); B->Q = malloc(sizeof(double) * B->npts);
             if (!B->t || !B->Q) { seterr(err, elen, "out of memory"); goto fail; }
             for (int k = 0; k < B->npts; k++) {
@@ -537,6 +538,16 @@ double om_next_dt(const om_sim *s, double t_end) {
         double r = m->rho[3 * m->eL[e] + m->ekL[e]] / lam;
         if (r < best) best = r;
     }
+    /* z-hydrograph ghosts: still water, lambda = sqrt(g h_g) while wet */
+    for (int64_t e = 0; e < m->ne; e++) {
+        if (s->ebc[e] < 0) continue;
+        const om_bc *B = &s->bc[s->ebc[e]];
+        if (B->kind != OM_ZHYDROGRAPH) continue;
+        double hg = hydrograph(B, s->t) - m->zb[m->eL[e]];
+        if (hg < OM_H_DRY) continue;
+        double r = m->rho[3 * m->eL[e] + m->ekL[e]] / sqrt(s->g * hg);
+        if (r < best) best = r;
+    }
     double dt = s->cfl * best;
     if (s->dt_max < dt) dt = s->dt_max;
     if (t_end - s->t < dt) dt = t_end - s->t;
@@ -574,6 +585,12 @@ int om_step(om_sim *s, double t_end, double *dt_taken) {
                 HR = HL; unR = unL; utR = utL; open = 1;
             } else if (B && B->kind == OM_INFLOW_UNIFORM && inflow_ghost(s, B, L, s->t, &hg, &ung)) {
                 HR = zL + hg; unR = ung; utR = 0.0; open = 1;
+            } else if (B && B->kind == OM_ZHYDROGRAPH) {
+                /* "zhydrograph" (section "Hydrodynamic BCs", water surface
+                 * elevation series).  Reading: the ghost is still water at the
+                 * prescribed surface over the cell's bed, like a reservoir or
+                 * sea level; the flux then lets water in or out. */
+                HR = hydrograph(B, s->t); unR = 0.0; utR = 0.0; open = 1;
             } else {
                 /* reflective wall: mirror the normal velocity */
                 HR = HL; unR = -unL; utR = utL; wall = 1;

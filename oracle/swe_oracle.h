@@ -20,7 +20,7 @@ typedef struct om_mesh om_mesh;
 typedef struct om_sim om_sim;
 
 /* boundary kinds */
-enum { OM_WALL = 0, OM_INFLOW_UNIFORM = 1, OM_OUTFLOW_ZEROGRAD = 2 };
+enum { OM_WALL = 0, OM_INFLOW_UNIFORM = 1, OM_OUTFLOW_ZEROGRAD = 2, OM_ZHYDROGRAPH = 3 };
 /* friction closures (Table friction_closure) */
 enum { OM_MANNING = 0, OM_STRICKLER = 1, OM_CHEZY = 2, OM_BEZZOLA = 3 };
 

@@ -396,12 +396,13 @@ swe_status swe_state_init(const swe_mesh *m, const swe_params *params, const dou
     std::vector<size_t> hoff((size_t)std::max(n_bc, 1));
     for (int b = 0; b < n_bc; b++) {
         const swe_bc &B = bcs[b];
-        if (B.kind < SWE_BC_WALL || B.kind > SWE_BC_OUTFLOW_ZEROGRAD) return fail(SWE_EINVAL, "unknown boundary kind");
+        if (B.kind < SWE_BC_WALL || B.kind > SWE_BC_ZHYDROGRAPH) return fail(SWE_EINVAL, "unknown boundary kind");
         hb[b] = BCdev{B.kind, 0, B.slope, 0.0, nullptr, nullptr};
         hoff[b] = hydro.size();
-        if (B.kind == SWE_BC_INFLOW_UNIFORM) {
-            if (B.n_pts < 1 || !B.t || !B.Q) return fail(SWE_EINVAL, "inflow needs a hydrograph");
-            if (!(B.slope > 0) || !std::isfinite(B.slope)) return fail(SWE_EINVAL, "inflow needs a positive slope");
+        if (B.kind == SWE_BC_INFLOW_UNIFORM || B.kind == SWE_BC_ZHYDROGRAPH) {
+            if (B.n_pts < 1 || !B.t || !B.Q) return fail(SWE_EINVAL, "inflow and zhydrograph need a series");
+            if (B.kind == SWE_BC_INFLOW_UNIFORM && (!(B.slope > 0) || !std::isfinite(B.slope)))
+                return fail(SWE_EINVAL, "inflow needs a positive slope");
             for (int k = 0; k < B.n_pts; k++) {
                 if (!std::isfinite(B.t[k]) || !std::isfinite(B.Q[k])) return fail(SWE_EINVAL, "non-finite hydrograph");
                 if (k > 0 && !(B.t[k] > B.t[k - 1])) return fail(SWE_EINVAL, "hydrograph times must increase");

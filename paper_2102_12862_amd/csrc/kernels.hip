@@ -461,6 +461,9 @@ __device__ __forceinline__ void tile_edges(const Inst<T> &I, TileLds<T, TILE> &S
                     T hg, ung;
                     if (inflow_ghost(I.bcs[kbc >> 4], t_cand, cp.y, g, hg, ung))
                         ghost_cfl<T, TILE>(S, l, hg, ung, g, cp.x);
+                } else if ((kbc & 15) == BC_ZHYDRO) {
+                    const double dg = hydrograph(I.bcs[kbc >> 4], t_cand) - double(S.huvz[a].w);
+                    if (!(dg < H_DRY)) ghost_cfl<T, TILE>(S, l, T(dg), T(0), g, I.cellp[tile * TILE + a].x);
                 }
             }
             continue;
@@ -526,6 +529,14 @@ __device__ __forceinline__ void tile_edges(const Inst<T> &I, TileLds<T, TILE> &S
                     F0 = T(0);
                 }
                 if (inflow_ghost(I.bcs[bi], t_cand, cp.y, g, hg, ung)) ghost_cfl<T, TILE>(S, l, hg, ung, g, cp.x);
+            } else if (bkind == BC_ZHYDRO) {
+                // still water at the prescribed surface over a's bed
+                const double dg = hydrograph(I.bcs[bi], t) - double(sa.w);
+                const T hgs = dg < H_DRY ? T(0) : T(dg);
+                hllc(ha, una, uta, hgs, T(0), T(0), g, F0, F1, F2);
+                open = true;
+                const double dc = hydrograph(I.bcs[bi], t_cand) - double(sa.w);
+                if (!(dc < H_DRY)) ghost_cfl<T, TILE>(S, l, T(dc), T(0), g, I.cellp[tile * TILE + a].x);
             } else {
                 // reflective, impermeable wall: mirrored normal velocity
                 hllc(ha, una, uta, ha, -una, uta, g, F0, F1, F2);

@@ -36,7 +36,7 @@ template <typename T> struct alignas(sizeof(T) == 4 ? 16 : 8) Edge {
 };
 enum : int { EK_LOCAL = 0, EK_REMOTE = 1, EK_BOUNDARY = 2 };
 
-enum : int { BC_WALL = 0, BC_INFLOW = 1, BC_OUTFLOW = 2 };
+enum : int { BC_WALL = 0, BC_INFLOW = 1, BC_OUTFLOW = 2, BC_ZHYDRO = 3 };
 enum : int { FLAG_NONFINITE = 1, FLAG_NEGDEPTH = 2, FLAG_NODT = 4 };
 // friction closures, numbered as SWE_FRICTION_* in swe.h
 enum : int { FR_MANNING = 0, FR_STRICKLER = 1, FR_CHEZY = 2, FR_BEZZOLA = 3 };
@@ -48,8 +48,8 @@ struct BCdev {
     int npts;
     double slope;    // inflow energy slope
     double length;   // summed length of the edges carrying this condition
-    const double *t; // hydrograph
-    const double *Q;
+    const double *t; // series times
+    const double *Q; // discharge (inflow) or surface elevation (zhydrograph)
 };
 
 // Per-state control block, triple-buffered by step phase p = step % 3.

@@ -29,6 +29,7 @@ BASE_SEED = 210212862
 WALL = 0
 INFLOW_UNIFORM = 1
 OUTFLOW_ZEROGRAD = 2
+ZHYDROGRAPH = 3   # prescribed water-surface elevation series (t, Q hold times and elevations)
 
 
 def rng(offset: int) -> np.random.Generator:
@@ -41,7 +42,7 @@ class BC:
     kind: int
     slope: float = 0.0
     t: Optional[np.ndarray] = None  # hydrograph times [s]
-    Q: Optional[np.ndarray] = None  # hydrograph discharge [m^3/s]
+    Q: Optional[np.ndarray] = None  # hydrograph discharge [m^3/s] (surface elevation [m] for ZHYDROGRAPH)
 
 
 @dataclasses.dataclass
@@ -136,6 +137,22 @@ def lake_at_rest(n_cells: int = 200_000, seed: int = 0, lx: float = 2000.0,
     n = tri.shape[0]
     return _assemble(f"lake_at_rest_{n}", xy, z, tri, [], [], H0=np.full(n, level),
                      manning=np.full(n, 0.035), t_end=t_end, cfl=0.9)
+
+
+# ------------------------------------------------------- level-boundary basin
+def level_basin(times, levels, H0, d: float = 1.0, lx: float = 40.0, ly: float = 20.0,
+                n: float = 0.02, t_end: float = 60.0) -> Scenario:
+    """Rectangle of right triangles (legs d) with a Gaussian mound (0.8 m
+    high, at the centre) on a bed rising 1 mm/m in x, walls except the x = 0
+    side, where the water-surface elevation follows (times, levels); the
+    initial surface is H0 (dry where below the bed)."""
+    xy, tri, sides = M.structured_right(lx, ly, d)
+    z = 0.8 * np.exp(-((xy[:, 0] - 0.5 * lx) ** 2 + (xy[:, 1] - 0.5 * ly) ** 2) / 30.0) + 1e-3 * xy[:, 0]
+    segs = [(M.segments_on_side(xy, sides["x0"], -1, 1e9, 1), 1)]
+    bcs = [BC(1, ZHYDROGRAPH, t=np.asarray(times, np.float64), Q=np.asarray(levels, np.float64))]
+    ntri = tri.shape[0]
+    return _assemble(f"level_basin_{ntri}", xy, z, tri, segs, bcs, H0=np.full(ntri, H0),
+                     manning=np.full(ntri, n), t_end=t_end, cfl=0.9)
 
 
 # ------------------------------------------------------------ valley flood

@@ -62,8 +62,16 @@ struct DevMem {
 // Tile edge lists of one mesh for one precision and tile size.
 struct TileGeom {
     void *edges = nullptr;
+    int *ew1 = nullptr;
     int *eoff = nullptr;
     int ntiles = 0;
+    // points an instance at these lists
+    template <typename T> void bind(Inst<T> &I) const {
+        I.edges = (const Edge<T> *)edges;
+        I.ew1 = ew1;
+        I.eoff = eoff;
+        I.ntiles = ntiles;
+    }
 };
 constexpr int TILES[3] = {128, 256, 512};
 int tile_index(int tile) { return tile == 128 ? 0 : tile == 256 ? 1 : tile == 512 ? 2 : -1; }
@@ -91,6 +99,7 @@ struct swe_mesh {
         for (auto &row : geom)
             for (auto &g : row) {
                 mem.release(g.edges);
+                mem.release(g.ew1);
                 mem.release(g.eoff);
             }
     }
@@ -113,18 +122,22 @@ struct swe_mesh {
         std::vector<int32_t> eoff;
         if (!build_tile_edges(H, tile, te, eoff)) return fail(SWE_EINVAL, "cannot build tile edge lists");
         std::vector<Edge<T>> ed(te.size());
+        std::vector<int> w1(te.size());
         for (size_t k = 0; k < te.size(); k++) {
             ed[k].w0 = te[k].w0;
-            ed[k].w1 = te[k].w1;
             ed[k].lx = T(te[k].lx);
             ed[k].ly = T(te[k].ly);
+            w1[k] = te[k].w1;
         }
         g.edges = mem.alloc(std::max<size_t>(ed.size(), 1) * sizeof(Edge<T>));
+        g.ew1 = (int *)mem.alloc(std::max<size_t>(w1.size(), 1) * sizeof(int));
         g.eoff = (int *)mem.alloc(eoff.size() * sizeof(int));
-        if (!g.edges || !g.eoff) return fail(SWE_ENOMEM, "device allocation failed (tile edges)");
+        if (!g.edges || !g.ew1 || !g.eoff) return fail(SWE_ENOMEM, "device allocation failed (tile edges)");
         hipStream_t s = mem.stream();
-        if (!ed.empty())
+        if (!ed.empty()) {
             HIP_TRY(hipMemcpyAsync(g.edges, ed.data(), ed.size() * sizeof(Edge<T>), hipMemcpyHostToDevice, s));
+            HIP_TRY(hipMemcpyAsync(g.ew1, w1.data(), w1.size() * sizeof(int), hipMemcpyHostToDevice, s));
+        }
         HIP_TRY(hipMemcpyAsync(g.eoff, eoff.data(), eoff.size() * sizeof(int), hipMemcpyHostToDevice, s));
         HIP_TRY(hipStreamSynchronize(s));
         g.ntiles = (int)(eoff.size() - 1);
@@ -229,10 +242,8 @@ struct swe_state {
         swe_status st = prec == SWE_FP32 ? m->ensure_tiles<float>(prec, t) : m->ensure_tiles<double>(prec, t);
         if (st) return st;
         const TileGeom &g = m->geom[prec][tile_index(t)];
-        inst32.edges = (const Edge<float> *)g.edges;
-        inst64.edges = (const Edge<double> *)g.edges;
-        inst32.eoff = inst64.eoff = g.eoff;
-        inst32.ntiles = inst64.ntiles = g.ntiles;
+        g.bind(inst32);
+        g.bind(inst64);
         tile = t;
         return SWE_OK;
     }
@@ -327,8 +338,8 @@ int64_t swe_state_footprint(const swe_mesh *m, int32_t precision) {
     const int64_t n = m->H.nc, ns = (int64_t)m->H.slot_tag.size();
     const int64_t v4 = (int64_t)vec4_bytes(precision);
     const int64_t state = 2 * n * v4 + n * v4 / 2 + ns * (4 + 16) + (int64_t)sizeof(Ctrl) + MASS_BLOCKS * 16 + 4096;
-    // tile edge list (about 1.7 edges per cell) and FP64 areas
-    const int64_t edge = precision == SWE_FP32 ? 16 : 24;
+    // tile edge list (about 1.7 edges per cell: record + other-cell id) and FP64 areas
+    const int64_t edge = precision == SWE_FP32 ? 12 + 4 : 24 + 4;
     const int64_t geom = n * 8 + (n * 7 / 4) * edge + 4 * (n / 128 + 2);
     return state + geom;
 }
@@ -517,8 +528,7 @@ swe_status swe_state_init(const swe_mesh *m, const swe_params *params, const dou
         I.U1 = (V4<T> *)S->U1;
         const TileGeom &tg = m->geom[prec][tile_index(S->tile)];
         I.cellp = (const V2<T> *)S->cellp;
-        I.edges = (const Edge<T> *)tg.edges;
-        I.eoff = tg.eoff;
+        tg.bind(I);
         I.slot_kbc = S->slot_kbc;
         I.slot_acc = S->slot_acc;
         I.bcs = S->bcs;
@@ -795,15 +805,11 @@ struct swe_batch {
             const int nt = tg.ntiles;
             if (prec == SWE_FP32) {
                 Inst<float> I = s->inst32;
-                I.edges = (const Edge<float> *)tg.edges;
-                I.eoff = tg.eoff;
-                I.ntiles = nt;
+                tg.bind(I);
                 i32.push_back(I);
             } else {
                 Inst<double> I = s->inst64;
-                I.edges = (const Edge<double> *)tg.edges;
-                I.eoff = tg.eoff;
-                I.ntiles = nt;
+                tg.bind(I);
                 i64.push_back(I);
             }
             for (int t = 0; t < nt; t++) tl.push_back(make_int2(idx, t));

@@ -336,6 +336,17 @@ __device__ __forceinline__ Level step_setup(Ctrl *c, int phase, double cfl, doub
     return L;
 }
 
+// Work-groups are dealt to the eight XCDs in turn (group b to XCD b mod 8),
+// each with its own L2.  Remapping group b to tile x*q + min(x, r) + b/8
+// (x = b mod 8, n = 8q + r tiles) gives every XCD one contiguous run of
+// Hilbert-ordered tiles, walked in order, so the neighbours a tile gathers
+// from other tiles were mostly just read through the same L2.  A bijection
+// for any n; results do not depend on the order tiles are processed in.
+__device__ __forceinline__ int xcd_tile(int b, int n) {
+    const int q = n >> 3, r = n & 7, x = b & 7;
+    return x * q + min(x, r) + (b >> 3);
+}
+
 // Slot that a step of launch phase `phase` lowers (advance) or an
 // initialisation fills (!advance).
 __device__ __forceinline__ unsigned long long *cfl_slot(Ctrl *c, int phase, bool advance) {
@@ -343,14 +354,13 @@ __device__ __forceinline__ unsigned long long *cfl_slot(Ctrl *c, int phase, bool
 }
 
 // Block reduction of the CFL terms -> at most one atomic min on the slot,
-// skipped when `seen` (the slot's value read by thread 0 before the update
-// phase; values only decrease, so a stale one never hides a lower minimum)
-// shows it cannot lower it.  Block `lead` publishes the next time level and
-// clears the slot two phases ahead.  REUSE: the block goes on to another tile
-// and must not overwrite wred before thread 0 has read it.
-template <bool REUSE, typename C>
-__device__ __forceinline__ void block_finish(Ctrl *c, int phase, C cand, const Level &L, bool lead, bool advance,
-                                             unsigned long long seen) {
+// skipped when the slot already holds a value no larger.  The slot is read
+// here, after every other load of the block: the loads of a wave complete in
+// order, so reading this contended line earlier would hold up the update
+// phase's own loads.  Block `lead` publishes the next time level and clears
+// the slot two phases ahead.
+template <typename C>
+__device__ __forceinline__ void block_finish(Ctrl *c, int phase, C cand, const Level &L, bool lead, bool advance) {
     __shared__ C wred[16];
     const int pout = phase == 2 ? 0 : phase + 1, pclr = phase == 0 ? 2 : phase - 1;
     cand = wave_reduce(cand);
@@ -363,7 +373,8 @@ __device__ __forceinline__ void block_finish(Ctrl *c, int phase, C cand, const L
         for (int k = 1; k < nw; k++) r = combine(r, wred[k]);
         const double m = block_rho_lambda(r);
         const unsigned long long mb = (unsigned long long)__double_as_longlong(m);
-        if (mb < seen) atomicMin(cfl_slot(c, phase, advance), mb);
+        unsigned long long *slot = cfl_slot(c, phase, advance);
+        if (mb < load_agent(slot)) atomicMin(slot, mb);
         if (lead && advance) {
             store_agent(&c->s[pout].t, L.t + L.dt);
             store_agent(&c->s[pout].dt, L.dt);
@@ -372,7 +383,7 @@ __device__ __forceinline__ void block_finish(Ctrl *c, int phase, C cand, const L
             store_agent(&c->m[pclr].bits, INF_BITS);
         }
     }
-    if (REUSE) __syncthreads();
+    __syncthreads();  // wred may be reused by a following tile
 }
 
 // LDS of one tile: per cell (H, u, v, z) with the velocity zero at or below
@@ -455,7 +466,7 @@ __device__ __forceinline__ void tile_edges(const Inst<T> &I, TileLds<T, TILE> &S
         }
         if (!UPDATE) {
             if (kind == EK_BOUNDARY) {
-                const int kbc = I.slot_kbc[E.w1];
+                const int kbc = I.slot_kbc[I.ew1[e]];
                 if ((kbc & 15) == BC_INFLOW) {
                     const V2<T> cp = I.cellp[tile * TILE + a];
                     T hg, ung;
@@ -482,7 +493,7 @@ __device__ __forceinline__ void tile_edges(const Inst<T> &I, TileLds<T, TILE> &S
                 ub = sb.y;
                 vb = sb.z;
             } else {
-                sb = src[E.w1];
+                sb = src[I.ew1[e]];
                 whole(sb);
                 const double hbd = double(sb.x) - double(sb.w);
                 const bool bwet = hbd > h_min;
@@ -505,7 +516,7 @@ __device__ __forceinline__ void tile_edges(const Inst<T> &I, TileLds<T, TILE> &S
             hllc(hL, unL, utL, hR, unR, utR, g, F0, F1, F2);
             if (flip) F0 = -F0;  // mass leaving a
         } else {
-            const int slot = E.w1;
+            const int slot = I.ew1[e];
             const int kbc = I.slot_kbc[slot];
             const int bkind = kbc & 15, bi = kbc >> 4;
             // the ghost shares a's bed, so z* = z and h* = H - z
@@ -677,12 +688,12 @@ __global__ void __launch_bounds__(TILE, (WAVES_PER_SIMD<T, TILE>)) k_step(Inst<T
     const bool lead = blockIdx.x == 0;
     const Level L = step_setup(I.ctrl, phase, I.cfl, I.dt_max, lead);
     if (!L.run) return;
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
     V4<T> own;
-    tile_edges<T, TILE, true>(I, S, blockIdx.x, L.cur, L.t, L.dt, L.t + L.dt, own);
-    const unsigned long long seen = threadIdx.x == 0 ? load_agent(cfl_slot(I.ctrl, phase, true)) : 0ull;
-    CandT<T> cand = tile_update<T, TILE>(I, S, blockIdx.x, L.cur, L.dt, own);
+    tile_edges<T, TILE, true>(I, S, tile, L.cur, L.t, L.dt, L.t + L.dt, own);
+    CandT<T> cand = tile_update<T, TILE>(I, S, tile, L.cur, L.dt, own);
     if (threadIdx.x == 0) cand = combine(cand, ghost_value(S.ghost));
-    block_finish<false>(I.ctrl, phase, cand, L, lead, true, seen);
+    block_finish(I.ctrl, phase, cand, L, lead, true);
 }
 
 // CFL minimum of the state of level `phase` (after an initialisation); the
@@ -698,17 +709,17 @@ __global__ void __launch_bounds__(TILE) k_dt_init(Inst<T> I, int phase) {
     L.steps = 0;
     L.rawmin = 0.0;
     L.run = true;
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
     V4<T> s;
-    tile_edges<T, TILE, false>(I, S, blockIdx.x, L.cur, L.t, 0.0, L.t, s);
-    const unsigned long long seen = threadIdx.x == 0 ? load_agent(cfl_slot(I.ctrl, phase, false)) : 0ull;
+    tile_edges<T, TILE, false>(I, S, tile, L.cur, L.t, 0.0, L.t, s);
     CandT<T> cand = IS32<T> ? T(0) : T(INFINITY);
-    const int i = blockIdx.x * TILE + threadIdx.x;
+    const int i = tile * TILE + threadIdx.x;
     if (i < I.n) {
         const V2<T> cp = I.cellp[i];
         cand = tile_candidate<T, TILE>(I, S, threadIdx.x, cp.x, s.x, s.y, s.z, s.w);
     }
     if (threadIdx.x == 0) cand = combine(cand, ghost_value(S.ghost));
-    block_finish<false>(I.ctrl, phase, cand, L, false, false, seen);
+    block_finish(I.ctrl, phase, cand, L, false, false);
 }
 
 // Persistent batched step: blocks stride over a list of (member, tile)
@@ -719,17 +730,16 @@ __global__ void __launch_bounds__(TILE, (WAVES_PER_SIMD<T, TILE>)) k_step_batche
                                                         const int2 *__restrict__ tiles, int ntiles, int phase) {
     __shared__ TileLds<T, TILE> S;
     for (int tt = blockIdx.x; tt < ntiles; tt += gridDim.x) {
-        const int2 td = tiles[tt];
+        const int2 td = tiles[xcd_tile(tt, ntiles)];
         const Inst<T> I = insts[td.x];
         const bool lead = td.y == 0;
         const Level L = step_setup(I.ctrl, phase, I.cfl, I.dt_max, lead);
         if (!L.run) continue;
         V4<T> own;
         tile_edges<T, TILE, true>(I, S, td.y, L.cur, L.t, L.dt, L.t + L.dt, own);
-        const unsigned long long seen = threadIdx.x == 0 ? load_agent(cfl_slot(I.ctrl, phase, true)) : 0ull;
         CandT<T> cand = tile_update<T, TILE>(I, S, td.y, L.cur, L.dt, own);
         if (threadIdx.x == 0) cand = combine(cand, ghost_value(S.ghost));
-        block_finish<true>(I.ctrl, phase, cand, L, lead, true, seen);
+        block_finish(I.ctrl, phase, cand, L, lead, true);
     }
 }
 

@@ -13,7 +13,10 @@ namespace swe {
 //   cellp[n]  vec2 (|cell| in FP64, 1/|cell| in FP32; friction coefficient:
 //             g n^2 for Manning and Strickler, K_s for Chezy, y_R for Bezzola)
 //   edges     per tile of TILE consecutive cells, every edge touching the tile
-//             once (see TileEdge in meshprep.h): two ints and l*n
+//             once (see TileEdge in meshprep.h): packed indices and l*n
+//             (12 B in FP32, 24 B in FP64)
+//   ew1       per edge: the other cell's device id (edge to another tile) or
+//             the boundary slot, read only by such edges
 //   eoff      first edge of each tile
 // A block owns one tile: it stages the tile's states in LDS, evaluates each of
 // the tile's edges once, then updates its cells.
@@ -29,11 +32,13 @@ template <> struct V2T<float> { using type = float2; };
 template <> struct V2T<double> { using type = double2; };
 template <typename T> using V2 = typename V2T<T>::type;
 
-// Edge record on the device (the host TileEdge with l*n in precision T).
-template <typename T> struct alignas(sizeof(T) == 4 ? 16 : 8) Edge {
-    int w0, w1;
+// Edge record on the device: the host TileEdge's packed indices w0 and l*n
+// in precision T; its w1 lives in the separate array ew1.
+template <typename T> struct alignas(sizeof(T)) Edge {
+    int w0;
     T lx, ly;
 };
+static_assert(sizeof(Edge<float>) == 12 && sizeof(Edge<double>) == 24, "edge record size");
 enum : int { EK_LOCAL = 0, EK_REMOTE = 1, EK_BOUNDARY = 2 };
 
 enum : int { BC_WALL = 0, BC_INFLOW = 1, BC_OUTFLOW = 2, BC_ZHYDRO = 3 };
@@ -91,6 +96,7 @@ template <typename T> struct Inst {
     V4<T> *U1;
     const V2<T> *cellp;    // (|cell| in FP64, 1/|cell| in FP32; friction coefficient)
     const Edge<T> *edges;  // tile edge lists
+    const int *ew1;        // per edge: other cell's device id or boundary slot
     const int *eoff;       // first edge of each tile (ntiles + 1)
     const int *slot_kbc;   // per boundary slot: kind | (bc index << 4)
     double *slot_acc;      // per boundary slot: Neumaier (sum, compensation)

@@ -141,18 +141,19 @@ def lake_at_rest(n_cells: int = 200_000, seed: int = 0, lx: float = 2000.0,
 
 # ------------------------------------------------------- level-boundary basin
 def level_basin(times, levels, H0, d: float = 1.0, lx: float = 40.0, ly: float = 20.0,
-                n: float = 0.02, t_end: float = 60.0) -> Scenario:
+                n: float = 0.02, t_end: float = 60.0, cfl: float = 0.5) -> Scenario:
     """Rectangle of right triangles (legs d) with a Gaussian mound (0.8 m
     high, at the centre) on a bed rising 1 mm/m in x, walls except the x = 0
     side, where the water-surface elevation follows (times, levels); the
-    initial surface is H0 (dry where below the bed)."""
+    initial surface is H0 (dry where below the bed).  CFL 0.5: on right
+    triangles the time step of eq. CFL_condition is unstable above about 0.6."""
     xy, tri, sides = M.structured_right(lx, ly, d)
     z = 0.8 * np.exp(-((xy[:, 0] - 0.5 * lx) ** 2 + (xy[:, 1] - 0.5 * ly) ** 2) / 30.0) + 1e-3 * xy[:, 0]
     segs = [(M.segments_on_side(xy, sides["x0"], -1, 1e9, 1), 1)]
     bcs = [BC(1, ZHYDROGRAPH, t=np.asarray(times, np.float64), Q=np.asarray(levels, np.float64))]
     ntri = tri.shape[0]
     return _assemble(f"level_basin_{ntri}", xy, z, tri, segs, bcs, H0=np.full(ntri, H0),
-                     manning=np.full(ntri, n), t_end=t_end, cfl=0.9)
+                     manning=np.full(ntri, n), t_end=t_end, cfl=cfl)
 
 
 # ------------------------------------------------------------ valley flood

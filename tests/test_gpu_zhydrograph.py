@@ -45,7 +45,7 @@ def test_fill_parity_fp32_fixed_step(swe):
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_lake_at_boundary_level_exact(swe, prec):
-    sc = S.level_basin([0.0], [0.6], H0=0.6)
+    sc = S.level_basin([0.0], [0.625], H0=0.625)
     st = gpu_state(sc, swe.FP64 if prec == "fp64" else swe.FP32)
     r0 = st.read()
     for _ in range(100):

@@ -15,7 +15,7 @@ import swe_inputs as S
 
 
 def test_lake_at_boundary_level_stays_at_rest():
-    sc = S.level_basin([0.0], [0.6], H0=0.6)
+    sc = S.level_basin([0.0], [0.625], H0=0.625)
     sim = oracle.Sim(sc)
     H0, _, _, _ = sim.state()
     for _ in range(200):

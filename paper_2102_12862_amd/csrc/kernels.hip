@@ -394,7 +394,10 @@ __device__ __forceinline__ void block_finish(Ctrl *c, int phase, C cand, const L
 template <typename T, int TILE> struct TileLds {
     V4<T> huvz[TILE];
     T c[3][3][TILE];   // [component][local edge][cell]
-    T l[3][TILE], nx[3][TILE], ny[3][TILE];
+    // edge geometry of each (local edge, cell) for the CFL term: FP32 keeps
+    // l*n and recomputes l; FP64 keeps the unit normal and l
+    T gx[3][TILE], gy[3][TILE];
+    T gl[IS32<T> ? 1 : 3][IS32<T> ? 1 : TILE];
     GhostBits<T> ghost;
 };
 
@@ -455,14 +458,24 @@ __device__ __forceinline__ void tile_edges(const Inst<T> &I, TileLds<T, TILE> &S
         const bool flip = (E.w0 >> 16) & 1;
         T l, nx, ny;
         edge_normal(E.lx, E.ly, l, nx, ny);  // n: outward of a
-        S.l[ka][a] = l;
-        S.nx[ka][a] = nx;
-        S.ny[ka][a] = ny;
+        if constexpr (IS32<T>) {
+            S.gx[ka][a] = E.lx;
+            S.gy[ka][a] = E.ly;
+        } else {
+            S.gl[ka][a] = l;
+            S.gx[ka][a] = nx;
+            S.gy[ka][a] = ny;
+        }
         if (kind == EK_LOCAL) {
             const int b = (E.w0 >> 17) & 1023;
-            S.l[kb][b] = l;
-            S.nx[kb][b] = -nx;
-            S.ny[kb][b] = -ny;
+            if constexpr (IS32<T>) {
+                S.gx[kb][b] = -E.lx;
+                S.gy[kb][b] = -E.ly;
+            } else {
+                S.gl[kb][b] = l;
+                S.gx[kb][b] = -nx;
+                S.gy[kb][b] = -ny;
+            }
         }
         if (!UPDATE) {
             if (kind == EK_BOUNDARY) {
@@ -605,7 +618,11 @@ __device__ __forceinline__ CandT<T> tile_candidate(const Inst<T> &I, const TileL
             const float cc = qsqrt(g * hh);
 #pragma unroll
             for (int k = 0; k < 3; k++)
-                lmax = fmaxf(lmax, S.l[k][c] * (fabsf(fmaf(u2, S.nx[k][c], v2 * S.ny[k][c])) + cc));
+            {
+                const float lx = S.gx[k][c], ly = S.gy[k][c];
+                const float lk = qsqrt(fmaf(lx, lx, ly * ly));
+                lmax = fmaxf(lmax, fmaf(cc, lk, fabsf(fmaf(u2, lx, v2 * ly))));
+            }
         }
         return lmax * ap;
     } else {
@@ -616,8 +633,8 @@ __device__ __forceinline__ CandT<T> tile_candidate(const Inst<T> &I, const TileL
             const double cc = sqrt(g * hh);
 #pragma unroll
             for (int k = 0; k < 3; k++) {
-                const double lam = fabs(u2 * S.nx[k][c] + v2 * S.ny[k][c]) + cc;
-                const double r = cfl_term(ap, S.l[k][c], lam);
+                const double lam = fabs(u2 * S.gx[k][c] + v2 * S.gy[k][c]) + cc;
+                const double r = cfl_term(ap, S.gl[k][c], lam);
                 best = r < best ? r : best;
             }
         }
@@ -677,10 +694,13 @@ __device__ __forceinline__ CandT<T> tile_update(const Inst<T> &I, const TileLds<
 }
 
 // Occupancy hint (minimum waves per SIMD): what the tile's LDS allows (FP32:
-// seven waves per SIMD, six at 512 cells; FP64: three, two at 512 cells), so
-// the register budget matches it.
+// eight waves per SIMD, the most a SIMD holds; FP64: three, two at 512
+// cells), so the register budget matches it.  The persistent batched kernel
+// needs a few more registers and asks for seven FP32 waves.
 template <typename T, int TILE>
-constexpr int WAVES_PER_SIMD = IS32<T> ? (TILE >= 512 ? 6 : 7) : (TILE >= 512 ? 2 : 3);
+constexpr int WAVES_PER_SIMD = IS32<T> ? 8 : (TILE >= 512 ? 2 : 3);
+template <typename T, int TILE>
+constexpr int WAVES_PER_SIMD_BATCHED = IS32<T> ? 7 : (TILE >= 512 ? 2 : 3);
 
 template <typename T, int TILE>
 __global__ void __launch_bounds__(TILE, (WAVES_PER_SIMD<T, TILE>)) k_step(Inst<T> I, int phase) {
@@ -726,7 +746,7 @@ __global__ void __launch_bounds__(TILE) k_dt_init(Inst<T> I, int phase) {
 // pairs; each member keeps its own control block, so members step with their
 // own dt and finished members cost one control-block read per tile.
 template <typename T, int TILE>
-__global__ void __launch_bounds__(TILE, (WAVES_PER_SIMD<T, TILE>)) k_step_batched(const Inst<T> *__restrict__ insts,
+__global__ void __launch_bounds__(TILE, (WAVES_PER_SIMD_BATCHED<T, TILE>)) k_step_batched(const Inst<T> *__restrict__ insts,
                                                         const int2 *__restrict__ tiles, int ntiles, int phase) {
     __shared__ TileLds<T, TILE> S;
     for (int tt = blockIdx.x; tt < ntiles; tt += gridDim.x) {

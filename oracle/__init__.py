@@ -82,6 +82,11 @@ def lib():
         L.om_friction_cf.argtypes = [ctypes.c_int32, ctypes.c_double, ctypes.c_double]
         L.om_friction_closure.restype = ctypes.c_double
         L.om_friction_closure.argtypes = [ctypes.c_int32] + [ctypes.c_double] * 5
+        L.om_sim_set_scalars.restype = ctypes.c_int
+        L.om_sim_set_scalars.argtypes = [ctypes.c_void_p, ctypes.c_int32, _c_double_p, _c_double_p,
+                                         ctypes.c_char_p, ctypes.c_int]
+        L.om_get_scalars.argtypes = [ctypes.c_void_p, _c_double_p]
+        L.om_scalar_diag.argtypes = [ctypes.c_void_p, _c_double_p, _c_double_p, _c_double_p]
         L.om_sim_set_friction.restype = ctypes.c_int
         L.om_sim_set_friction.argtypes = [ctypes.c_void_p, ctypes.c_int32, _c_double_p, ctypes.c_char_p, ctypes.c_int]
         _lib = L
@@ -197,6 +202,20 @@ class Sim:
         if kind != "manning":
             if L.om_sim_set_friction(self._p, FRICTION[kind], _dp(man), err, 256):
                 raise OracleError(err.value.decode())
+        self.ns = 0
+        phi0 = getattr(sc, "phi0", None)
+        if phi0 is not None:
+            phi0 = np.ascontiguousarray(np.atleast_2d(phi0), np.float64)
+            ns = phi0.shape[0]
+            pin = np.zeros((max(len(bcs), 1), ns))
+            for b, bc in enumerate(bcs):
+                if len(getattr(bc, "phi_in", ())):
+                    pin[b] = bc.phi_in
+            pin = np.ascontiguousarray(pin)
+            self._keep += [phi0, pin]
+            if L.om_sim_set_scalars(self._p, ns, _dp(phi0), _dp(pin), err, 256):
+                raise OracleError(err.value.decode())
+            self.ns = ns
 
     def __del__(self):
         if getattr(self, "_p", None):
@@ -236,6 +255,19 @@ class Sim:
     @property
     def t(self):
         return self.state()[3]
+
+    def scalars(self):
+        """Specific masses q = h phi, (species, cells)."""
+        q = np.zeros((self.ns, self.n))
+        lib().om_get_scalars(self._p, _dp(q))
+        return q
+
+    def scalar_diag(self):
+        """Per species: total mass, the mass that left through open boundaries,
+        and the mass set by resetting cells left dry."""
+        m, b, c = (np.zeros(max(self.ns, 1)) for _ in range(3))
+        lib().om_scalar_diag(self._p, _dp(m), _dp(b), _dp(c))
+        return m[:self.ns], b[:self.ns], c[:self.ns]
 
     def diag(self):
         m, b, c = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()

@@ -59,6 +59,12 @@ struct om_sim {
     double bsum, bcomp;  /* Neumaier sum of dt * l * mass flux leaving the domain */
     double clip, clipc;  /* Neumaier sum of volume added by the positivity clip */
     int64_t steps;
+    /* passive scalars (section "Scalar advection-diffusion"): per species c
+     * the specific mass q_c = h phi_c, [ns][nc] */
+    int32_t ns;
+    double *sq, *sphi, *scont, *phi_in;
+    double sbsum[OM_MAX_SPECIES], sbcomp[OM_MAX_SPECIES];
+    double sclip[OM_MAX_SPECIES], sclipc[OM_MAX_SPECIES];  /* mass set by the dry-cell reset */
 };
 
 static void seterr(char *err, int len, const char *msg) {
@@ -266,6 +272,7 @@ void om_sim_free(om_sim *s) {
     if (!s) return;
     for (int b = 0; b < s->nbc; b++) { free(s->bc[b].t); free(s->bc[b].Q); }
     free(s->bc); free(s->ebc); free(s->H); free(s->qx); free(s->qy); free(s->gn2); free(s->cont);
+    free(s->sq); free(s->sphi); free(s->scont); free(s->phi_in);
     free(s);
 }
 
@@ -554,6 +561,88 @@ double om_next_dt(const om_sim *s, double t_end) {
     return dt;
 }
 
+
+/* ---------------------------------------------------------------------------
+ * Passive scalars (section "Scalar advection-diffusion": eq. scalar_goveq
+ * without the diffusion tensor, and the update eq. scl:updateformula with
+ * the advective fluxes A_ij only).  Per species c the specific mass
+ * q_c = h phi_c.  Readings: the advective flux of an edge is the HLLC mass
+ * flux F_h (the one the hydrodynamic update uses) times the concentration of
+ * the cell the water leaves; phi = q/h in cells with water (q and h are
+ * carried by the same mass flux, so thin films keep their concentration),
+ * 0 in dry ones;
+ * walls carry nothing, zero-gradient and prescribed-surface edges repeat the
+ * interior concentration, inflow edges carry their condition's inflow
+ * concentration; a cell left dry by the step (the water's positivity clip)
+ * keeps no scalar, and the mass removed or added is tallied.  The diffusive
+ * part (the relaxed SVT flux) is not built.
+ * ------------------------------------------------------------------------ */
+int om_sim_set_scalars(om_sim *s, int32_t ns, const double *phi0, const double *phi_in, char *err, int elen) {
+    const om_mesh *m = s->m;
+    int64_t nc = m->nc;
+    if (ns < 0 || ns > OM_MAX_SPECIES) { seterr(err, elen, "between 0 and 5 species"); return -1; }
+    free(s->sq); free(s->sphi); free(s->scont); free(s->phi_in);
+    s->sq = calloc((size_t)(ns * nc + 1), sizeof(double));
+    s->sphi = calloc((size_t)(ns * nc + 1), sizeof(double));
+    s->scont = calloc((size_t)(3 * ns * nc + 1), sizeof(double));
+    s->phi_in = calloc((size_t)(ns * (s->nbc > 0 ? s->nbc : 1) + 1), sizeof(double));
+    if (!s->sq || !s->sphi || !s->scont || !s->phi_in) { seterr(err, elen, "out of memory"); return -1; }
+    for (int c = 0; c < ns; c++) {
+        for (int64_t i = 0; i < nc; i++) {
+            double p = phi0 ? phi0[c * nc + i] : 0.0;
+            if (!isfinite(p)) { seterr(err, elen, "non-finite initial concentration"); return -1; }
+            double h = s->H[i] - m->zb[i];
+            s->sq[c * nc + i] = h > 0.0 ? h * p : 0.0;
+        }
+        for (int b = 0; b < s->nbc; b++) {
+            double p = phi_in ? phi_in[b * ns + c] : 0.0;
+            if (!isfinite(p)) { seterr(err, elen, "non-finite inflow concentration"); return -1; }
+            s->phi_in[b * ns + c] = p;
+        }
+        s->sbsum[c] = 0.0; s->sbcomp[c] = 0.0;
+        s->sclip[c] = 0.0; s->sclipc[c] = 0.0;
+    }
+    s->ns = ns;
+    return 0;
+}
+
+void om_get_scalars(const om_sim *s, double *q) {
+    if (q) memcpy(q, s->sq, (size_t)s->ns * (size_t)s->m->nc * sizeof(double));
+}
+
+/* per species: total mass sum q_c |Omega|, the time integral of the mass
+ * flux leaving through open boundaries, and the mass added by resetting
+ * cells left dry (mass(t) = mass(0) - bnd + clipped) */
+void om_scalar_diag(const om_sim *s, double *mass, double *bnd, double *clipped) {
+    for (int c = 0; c < s->ns; c++) {
+        double sum = 0.0, comp = 0.0;
+        for (int64_t i = 0; i < s->m->nc; i++) neumaier(&sum, &comp, s->sq[c * s->m->nc + i] * s->m->area[i]);
+        if (mass) mass[c] = sum + comp;
+        if (bnd) bnd[c] = s->sbsum[c] + s->sbcomp[c];
+        if (clipped) clipped[c] = s->sclip[c] + s->sclipc[c];
+    }
+}
+
+/* Scalar contributions of one edge for every species.  R < 0: a boundary
+ * edge; `wall` and `inflow_b` (index of an active inflow condition, or -1)
+ * describe its ghost. */
+static void scalar_edge(om_sim *s, int32_t L, int32_t R, int kL, int kR, double l, double F0, int wall,
+                        int inflow_b, int open, double dt, double *bst, double *bstc) {
+    const int64_t nc = s->m->nc;
+    for (int c = 0; c < s->ns; c++) {
+        const double *ph = s->sphi + c * nc;
+        double phL = ph[L], phR;
+        if (R >= 0) phR = ph[R];
+        else if (wall) phR = phL;
+        else if (inflow_b >= 0) phR = s->phi_in[inflow_b * s->ns + c];
+        else phR = phL;
+        double A = F0 * (F0 >= 0.0 ? phL : phR);
+        s->scont[3 * (c * nc + L) + kL] = l * A;
+        if (R >= 0) s->scont[3 * (c * nc + R) + kR] = -(l * A);
+        else if (open) neumaier(&bst[c], &bstc[c], dt * (l * A));
+    }
+}
+
 int om_step(om_sim *s, double t_end, double *dt_taken) {
     const om_mesh *m = s->m;
     const double g = s->g;
@@ -562,6 +651,15 @@ int om_step(om_sim *s, double t_end, double *dt_taken) {
     if (!(dt > 0.0) || !isfinite(dt)) return -7;
     memset(s->cont, 0, sizeof(double) * 9 * (size_t)m->nc);
     double bstep = 0.0, bstepc = 0.0;
+    double sbst[OM_MAX_SPECIES] = {0}, sbstc[OM_MAX_SPECIES] = {0};
+    for (int c = 0; c < s->ns; c++) {
+        /* concentrations of the state at t^n (zero in dry cells) */
+        for (int64_t i = 0; i < m->nc; i++) {
+            double h = s->H[i] - m->zb[i];
+            s->sphi[c * m->nc + i] = h > 0.0 ? s->sq[c * m->nc + i] / h : 0.0;
+        }
+    }
+    if (s->ns > 0) memset(s->scont, 0, sizeof(double) * 3 * (size_t)(s->ns * m->nc));
     for (int64_t e = 0; e < m->ne; e++) {
         int32_t L = m->eL[e], R = m->eR[e];
         double nx = m->enx[e], ny = m->eny[e], l = m->elen[e];
@@ -570,7 +668,7 @@ int om_step(om_sim *s, double t_end, double *dt_taken) {
         double HL = s->H[L], zL = m->zb[L];
         double unL = uL * nx + vL * ny, utL = -uL * ny + vL * nx;
         double HR, zR, unR, utR;
-        int wall = 0, open = 0;
+        int wall = 0, open = 0, inflow_b = -1;
         if (R >= 0) {
             cell_velocity(s, R, &hR, &uR, &vR);
             HR = s->H[R]; zR = m->zb[R];
@@ -584,7 +682,7 @@ int om_step(om_sim *s, double t_end, double *dt_taken) {
                 /* transmissive: the ghost repeats the interior state */
                 HR = HL; unR = unL; utR = utL; open = 1;
             } else if (B && B->kind == OM_INFLOW_UNIFORM && inflow_ghost(s, B, L, s->t, &hg, &ung)) {
-                HR = zL + hg; unR = ung; utR = 0.0; open = 1;
+                HR = zL + hg; unR = ung; utR = 0.0; open = 1; inflow_b = b;
             } else if (B && B->kind == OM_ZHYDROGRAPH) {
                 /* "zhydrograph" (section "Hydrodynamic BCs", water surface
                  * elevation series).  Reading: the ghost is still water at the
@@ -625,6 +723,8 @@ int om_step(om_sim *s, double t_end, double *dt_taken) {
         } else if (open) {
             neumaier(&bstep, &bstepc, dt * cL0);
         }
+        if (s->ns > 0)
+            scalar_edge(s, L, R, kL, R >= 0 ? m->ekR[e] : 0, l, F[0], wall, inflow_b, open, dt, sbst, sbstc);
     }
     for (int64_t i = 0; i < m->nc; i++) {
         const double *c = &s->cont[9 * i];
@@ -649,6 +749,24 @@ int om_step(om_sim *s, double t_end, double *dt_taken) {
         }
         if (!isfinite(H) || !isfinite(qx) || !isfinite(qy)) return -4;
         s->H[i] = H; s->qx[i] = qx; s->qy[i] = qy;
+    }
+    for (int c = 0; c < s->ns; c++) {
+        /* eq. scl:updateformula with the advective fluxes */
+        double *q = s->sq + c * m->nc;
+        for (int64_t i = 0; i < m->nc; i++) {
+            const double *k = s->scont + 3 * (c * m->nc + i);
+            double Rq = k[0] + k[1] + k[2];
+            double w = dt * (1.0 / m->area[i]);
+            q[i] = q[i] - w * Rq;
+            /* a cell left without water keeps no scalar (the positivity
+             * clip of the water, step 6, is mirrored here and tallied) */
+            if (!(s->H[i] - m->zb[i] > 0.0)) {
+                neumaier(&s->sclip[c], &s->sclipc[c], -q[i] * m->area[i]);
+                q[i] = 0.0;
+            }
+            if (!isfinite(q[i])) return -4;
+        }
+        neumaier(&s->sbsum[c], &s->sbcomp[c], sbst[c] + sbstc[c]);
     }
     neumaier(&s->bsum, &s->bcomp, bstep + bstepc);
     s->t += dt;

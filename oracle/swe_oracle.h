@@ -21,6 +21,7 @@ typedef struct om_sim om_sim;
 
 /* boundary kinds */
 enum { OM_WALL = 0, OM_INFLOW_UNIFORM = 1, OM_OUTFLOW_ZEROGRAD = 2, OM_ZHYDROGRAPH = 3 };
+#define OM_MAX_SPECIES 5
 /* friction closures (Table friction_closure) */
 enum { OM_MANNING = 0, OM_STRICKLER = 1, OM_CHEZY = 2, OM_BEZZOLA = 3 };
 
@@ -56,5 +57,13 @@ void om_hllc(double hL, double unL, double utL, double hR, double unR, double ut
              double F[3]);
 double om_friction(double q_abs_scale, double h, double gn2, double dt, double h_min);
 double om_friction_cf(int32_t kind, double par, double h);
+
+/* passive scalars (advected): ns species (<= OM_MAX_SPECIES) with initial
+ * concentrations phi0[ns][nc] (NULL = 0) and inflow concentrations
+ * phi_in[nbc][ns] of the boundary conditions (NULL = 0).  0 or -1. */
+int om_sim_set_scalars(om_sim *s, int32_t ns, const double *phi0, const double *phi_in, char *err, int err_len);
+/* specific masses q = h phi, [ns][nc] */
+void om_get_scalars(const om_sim *s, double *q);
+void om_scalar_diag(const om_sim *s, double *mass, double *bnd, double *clipped);
 double om_friction_closure(int32_t kind, double par, double q_abs, double h, double dt, double h_min);
 #endif

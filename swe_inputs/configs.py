@@ -43,6 +43,7 @@ class BC:
     slope: float = 0.0
     t: Optional[np.ndarray] = None  # hydrograph times [s]
     Q: Optional[np.ndarray] = None  # hydrograph discharge [m^3/s] (surface elevation [m] for ZHYDROGRAPH)
+    phi_in: tuple = ()              # inflow concentration of each passive species
 
 
 @dataclasses.dataclass
@@ -64,6 +65,7 @@ class Scenario:
     h_min: float = 1e-4
     dt_max: float = float("inf")
     friction: str = "manning"    # closure the `manning` array parameterises: manning, strickler, chezy, bezzola
+    phi0: Optional[np.ndarray] = None  # (S, N) initial concentrations of S <= 5 advected species
 
     @property
     def n_cells(self) -> int:
@@ -298,8 +300,10 @@ def t5_rarefactions(d: float = 0.1, t_end: float = 2.5) -> Scenario:
     qx = np.where(cx < 50.0, -3.0, 3.0)
     segs = [(M.segments_on_side(xy, sides["x0"], -1, 1e9, 1), 2),
             (M.segments_on_side(xy, sides["x1"], -1, 1e9, 1), 2)]
+    phi = np.where(cx < 50.0, 1.0, 0.0)[None, :]   # one advected species
     return _assemble(f"t5_d{d}", xy, np.zeros(len(xy)), tri, segs,
-                     [BC(2, OUTFLOW_ZEROGRAD)], h0=np.ones(n), qx0=qx, t_end=t_end, cfl=0.95)
+                     [BC(2, OUTFLOW_ZEROGRAD)], h0=np.ones(n), qx0=qx, t_end=t_end, cfl=0.95,
+                     phi0=phi)
 
 
 def t6_bed(x: np.ndarray, y: np.ndarray) -> np.ndarray:
@@ -321,8 +325,11 @@ def t6_three_humps(n_cells: int = 20_000, t_end: float = 1200.0, seed: int = 0) 
     cx = xy[tri, 0].mean(axis=1)
     n = tri.shape[0]
     H0 = np.where(cx < 16.0, 1.0, 0.125)
+    # two species: 0.5 / 0 left of the dam, 0 / 0.1 right of it (advected;
+    # the paper also diffuses them with K = 0.25 m^2/s)
+    phi = np.stack([np.where(cx < 16.0, 0.5, 0.0), np.where(cx < 16.0, 0.0, 0.1)])
     return _assemble(f"t6_{n}", xy, z, tri, [], [], H0=H0, manning=np.full(n, 0.01),
-                     t_end=t_end, cfl=0.95)
+                     t_end=t_end, cfl=0.95, phi0=phi)
 
 
 # ------------------------------------------------------------ tiny meshes

@@ -87,6 +87,11 @@ def lib():
                                          ctypes.c_char_p, ctypes.c_int]
         L.om_get_scalars.argtypes = [ctypes.c_void_p, _c_double_p]
         L.om_scalar_diag.argtypes = [ctypes.c_void_p, _c_double_p, _c_double_p, _c_double_p]
+        L.om_sim_set_sources.restype = ctypes.c_int
+        L.om_sim_set_sources.argtypes = [ctypes.c_void_p, _c_int32_p, ctypes.c_int32, _c_int32_p, _c_int32_p,
+                                         _c_int32_p, _c_double_p, _c_double_p, ctypes.c_char_p, ctypes.c_int]
+        L.om_source_volume.restype = ctypes.c_double
+        L.om_source_volume.argtypes = [ctypes.c_void_p]
         L.om_sim_set_friction.restype = ctypes.c_int
         L.om_sim_set_friction.argtypes = [ctypes.c_void_p, ctypes.c_int32, _c_double_p, ctypes.c_char_p, ctypes.c_int]
         _lib = L
@@ -216,6 +221,27 @@ class Sim:
             if L.om_sim_set_scalars(self._p, ns, _dp(phi0), _dp(pin), err, 256):
                 raise OracleError(err.value.decode())
             self.ns = ns
+        if len(getattr(sc, "sources", ())):
+            self.set_sources(sc.src_region, sc.sources)
+
+    def set_sources(self, region, sources):
+        """External water sources and sinks: region (cells,) -> index into
+        sources (-1: none); each source has mode, unit, t, v."""
+        region = np.ascontiguousarray(region, np.int32)
+        mode = np.array([x.mode for x in sources], np.int32)
+        unit = np.array([x.unit for x in sources], np.int32)
+        npts = np.array([0 if x.t is None else len(x.t) for x in sources], np.int32)
+        t = np.concatenate([np.asarray(x.t, np.float64) for x in sources if x.t is not None] or [np.zeros(0)])
+        v = np.concatenate([np.asarray(x.v, np.float64) for x in sources if x.v is not None] or [np.zeros(0)])
+        self._keep += [region, mode, unit, npts, t, v]
+        err = ctypes.create_string_buffer(256)
+        if lib().om_sim_set_sources(self._p, _ip(region), len(sources), _ip(mode), _ip(unit), _ip(npts), _dp(t),
+                                    _dp(v), err, 256):
+            raise OracleError(err.value.decode())
+
+    def source_volume(self):
+        """Volume the external sources added so far (negative: removed)."""
+        return lib().om_source_volume(self._p)
 
     def __del__(self):
         if getattr(self, "_p", None):
@@ -229,14 +255,18 @@ class Sim:
         dt = ctypes.c_double()
         rc = lib().om_step(self._p, t_end, ctypes.byref(dt))
         if rc:
-            raise OracleError(f"oracle step failed ({rc})")
+            e = OracleError(f"oracle step failed ({rc})")
+            e.code = rc
+            raise e
         return dt.value
 
     def run_until(self, t_end, max_steps=0):
         n = ctypes.c_int64()
         rc = lib().om_run_until(self._p, t_end, max_steps, ctypes.byref(n))
         if rc:
-            raise OracleError(f"oracle run failed ({rc})")
+            e = OracleError(f"oracle run failed ({rc})")
+            e.code = rc
+            raise e
         return n.value
 
     def run_steps(self, k, t_end=float("inf")):

@@ -65,6 +65,14 @@ struct om_sim {
     double *sq, *sphi, *scont, *phi_in;
     double sbsum[OM_MAX_SPECIES], sbcomp[OM_MAX_SPECIES];
     double sclip[OM_MAX_SPECIES], sclipc[OM_MAX_SPECIES];  /* mass set by the dry-cell reset */
+    /* external water sources and sinks S_h: per region the mode (kind),
+     * the series of its value (t, Q) and the factor from that value to a
+     * rate in m/s (length); per cell the region or -1 */
+    int32_t nsrc;
+    om_bc *src;
+    int32_t *csrc;
+    double *sfac;        /* per cell: fraction of its water a sink left (species follow it) */
+    double ssum, scomp;  /* Neumaier sum of the volume the sources added (negative: removed) */
 };
 
 static void seterr(char *err, int len, const char *msg) {
@@ -273,6 +281,8 @@ void om_sim_free(om_sim *s) {
     for (int b = 0; b < s->nbc; b++) { free(s->bc[b].t); free(s->bc[b].Q); }
     free(s->bc); free(s->ebc); free(s->H); free(s->qx); free(s->qy); free(s->gn2); free(s->cont);
     free(s->sq); free(s->sphi); free(s->scont); free(s->phi_in);
+    for (int r = 0; r < s->nsrc; r++) { free(s->src[r].t); free(s->src[r].Q); }
+    free(s->src); free(s->csrc); free(s->sfac);
     free(s);
 }
 
@@ -383,6 +393,85 @@ static double hydrograph(const om_bc *B, double t) {
     double w = (t - B->t[k]) / (B->t[k + 1] - B->t[k]);
     return B->Q[k] + w * (B->Q[k + 1] - B->Q[k]);
 }
+
+/* ---------------------------------------------------------------------------
+ * External water sources and sinks (section "Closure relationships" of the
+ * hydrodynamics, the S_h paragraph; eq. swe_vectorial_form_sourceterms): a
+ * rate S_h [m/s] added explicitly to the continuity equation of eq.
+ * hydrodynamicupdateformula, H += dt S_h, before the friction split.
+ * Region r holds a series (linear in time, constant past its ends, taken at
+ * t^n) of a total discharge [m^3/s], spread evenly over the region's area,
+ * or of an intensity [mm/h].  Modes: EXACT adds or removes exactly dt S_h
+ * (a removal larger than the cell's water after the fluxes is an error, -8);
+ * AVAILABLE removes at most that water; INFINITY removes all of it.
+ * Readings: "available water" is the depth after the flux update; a cell
+ * emptied by a sink gets H = z exactly; added water carries no species,
+ * removed water carries the cell's concentrations.
+ * ------------------------------------------------------------------------ */
+int om_sim_set_sources(om_sim *s, const int32_t *cell_src, int32_t nsrc, const int32_t *mode,
+                       const int32_t *unit, const int32_t *npts, const double *t, const double *v, char *err,
+                       int elen) {
+    const om_mesh *m = s->m;
+    for (int r = 0; r < s->nsrc; r++) { free(s->src[r].t); free(s->src[r].Q); }
+    free(s->src); free(s->csrc); free(s->sfac);
+    s->src = NULL; s->csrc = NULL; s->sfac = NULL; s->nsrc = 0;
+    s->ssum = 0.0; s->scomp = 0.0;
+    if (nsrc == 0) return 0;
+    if (nsrc < 0 || !cell_src || !mode || !unit || !npts) { seterr(err, elen, "bad source list"); return -1; }
+    s->src = calloc((size_t)nsrc, sizeof(om_bc));
+    s->csrc = malloc(sizeof(int32_t) * (size_t)m->nc);
+    s->sfac = malloc(sizeof(double) * (size_t)m->nc);
+    if (!s->src || !s->csrc || !s->sfac) { seterr(err, elen, "out of memory"); return -1; }
+    s->nsrc = nsrc;
+    int64_t off = 0;
+    for (int r = 0; r < nsrc; r++) {
+        om_bc *B = &s->src[r];
+        B->kind = mode[r];
+        B->npts = npts[r];
+        if (mode[r] < OM_SRC_EXACT || mode[r] > OM_SRC_INFINITY) { seterr(err, elen, "unknown source mode"); return -1; }
+        if (unit[r] != OM_SRC_DISCHARGE && unit[r] != OM_SRC_INTENSITY) { seterr(err, elen, "unknown source unit"); return -1; }
+        if (mode[r] != OM_SRC_INFINITY && (npts[r] < 1 || !t || !v)) { seterr(err, elen, "a source needs a series"); return -1; }
+        if (npts[r] < 0) { seterr(err, elen, "bad source list"); return -1; }
+        if (npts[r] > 0) {
+            B->t = malloc(sizeof(double) * (size_t)npts[r]);
+            B->Q = malloc(sizeof(double) * (size_t)npts[r]);
+            if (!B->t || !B->Q) { seterr(err, elen, "out of memory"); return -1; }
+            for (int k = 0; k < npts[r]; k++) {
+                B->t[k] = t[off + k];
+                B->Q[k] = v[off + k];
+                if (!isfinite(B->t[k]) || !isfinite(B->Q[k])) { seterr(err, elen, "non-finite source series"); return -1; }
+                if (k > 0 && !(B->t[k] > B->t[k - 1])) { seterr(err, elen, "source times must increase"); return -1; }
+                if (mode[r] == OM_SRC_AVAILABLE && B->Q[k] > 0.0) { seterr(err, elen, "only exact sources add water"); return -1; }
+            }
+            off += npts[r];
+        }
+    }
+    /* region areas summed in ascending order (independent of numbering) */
+    double *ar = malloc(sizeof(double) * (size_t)(m->nc > 0 ? m->nc : 1));
+    if (!ar) { seterr(err, elen, "out of memory"); return -1; }
+    for (int r = 0; r < nsrc; r++) {
+        int64_t k = 0;
+        for (int64_t i = 0; i < m->nc; i++)
+            if (cell_src[i] == r) ar[k++] = m->area[i];
+        qsort(ar, (size_t)k, sizeof(double), cmp_double);
+        double A = 0.0;
+        for (int64_t j = 0; j < k; j++) A += ar[j];
+        if (unit[r] == OM_SRC_DISCHARGE) {
+            if (!(A > 0.0) && mode[r] != OM_SRC_INFINITY) { free(ar); seterr(err, elen, "empty source region"); return -1; }
+            s->src[r].length = 1.0 / A;
+        } else {
+            s->src[r].length = 1.0 / 3.6e6;   /* mm/h -> m/s */
+        }
+    }
+    free(ar);
+    for (int64_t i = 0; i < m->nc; i++) {
+        if (cell_src[i] < -1 || cell_src[i] >= nsrc) { seterr(err, elen, "source region out of range"); return -1; }
+        s->csrc[i] = cell_src[i];
+    }
+    return 0;
+}
+
+double om_source_volume(const om_sim *s) { return s->ssum + s->scomp; }
 
 /* Inflow "uniform(discharge, slope)" (section "Hydrodynamic BCs"): the given
  * discharge is spread over the boundary length; reading: the ghost carries
@@ -651,6 +740,7 @@ int om_step(om_sim *s, double t_end, double *dt_taken) {
     if (!(dt > 0.0) || !isfinite(dt)) return -7;
     memset(s->cont, 0, sizeof(double) * 9 * (size_t)m->nc);
     double bstep = 0.0, bstepc = 0.0;
+    int deficit = 0;   /* an exact sink asked for more water than a cell held */
     double sbst[OM_MAX_SPECIES] = {0}, sbstc[OM_MAX_SPECIES] = {0};
     for (int c = 0; c < s->ns; c++) {
         /* concentrations of the state at t^n (zero in dry cells) */
@@ -735,6 +825,29 @@ int om_step(om_sim *s, double t_end, double *dt_taken) {
         double H = s->H[i] - w * Rh;
         double qx = s->qx[i] - w * Rx;
         double qy = s->qy[i] - w * Ry;
+        if (s->csrc && s->csrc[i] >= 0) {
+            /* external source or sink, explicit in the continuity equation */
+            const om_bc *B = &s->src[s->csrc[i]];
+            double hf = H - m->zb[i];
+            double avail = hf > 0.0 ? hf : 0.0;
+            double dh;
+            int empty = 0;
+            if (B->kind == OM_SRC_INFINITY) {
+                dh = -avail;
+                empty = 1;
+            } else {
+                dh = dt * (hydrograph(B, s->t) * B->length);
+                if (dh < -avail) {
+                    if (B->kind == OM_SRC_AVAILABLE) { dh = -avail; empty = 1; }
+                    else deficit = 1;
+                }
+            }
+            if (empty) { if (avail > 0.0) H = m->zb[i]; }
+            else H = H + dh;
+            neumaier(&s->ssum, &s->scomp, dh * m->area[i]);
+            double hn = H - m->zb[i];
+            s->sfac[i] = (dh < 0.0 && hf > 0.0) ? (hn > 0.0 ? hn / hf : 0.0) : 1.0;
+        }
         double h = H - m->zb[i];
         double f = om_friction_closure(s->fkind, s->gn2[i], sqrt(qx * qx + qy * qy), h, dt, s->h_min);
         qx = qx * f;
@@ -758,6 +871,7 @@ int om_step(om_sim *s, double t_end, double *dt_taken) {
             double Rq = k[0] + k[1] + k[2];
             double w = dt * (1.0 / m->area[i]);
             q[i] = q[i] - w * Rq;
+            if (s->csrc && s->csrc[i] >= 0) q[i] = q[i] * s->sfac[i];
             /* a cell left without water keeps no scalar (the positivity
              * clip of the water, step 6, is mirrored here and tallied) */
             if (!(s->H[i] - m->zb[i] > 0.0)) {
@@ -771,7 +885,7 @@ int om_step(om_sim *s, double t_end, double *dt_taken) {
     neumaier(&s->bsum, &s->bcomp, bstep + bstepc);
     s->t += dt;
     s->steps++;
-    return 0;
+    return deficit ? -8 : 0;
 }
 
 int om_run_until(om_sim *s, double t_end, int64_t max_steps, int64_t *n_steps) {

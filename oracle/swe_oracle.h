@@ -10,7 +10,8 @@
  * sums them in that order.  Compiled with -ffp-contract=off.
  *
  * Status codes: 0 ok, -1 invalid input, -2 out of memory, -4 non-finite
- * state, -7 no finite time step.
+ * state, -7 no finite time step, -8 an exact sink exceeded a cell's water
+ * (the step is complete; the deficit was clipped and tallied).
  */
 #ifndef SWE_ORACLE_H
 #define SWE_ORACLE_H
@@ -66,4 +67,18 @@ int om_sim_set_scalars(om_sim *s, int32_t ns, const double *phi0, const double *
 void om_get_scalars(const om_sim *s, double *q);
 void om_scalar_diag(const om_sim *s, double *mass, double *bnd, double *clipped);
 double om_friction_closure(int32_t kind, double par, double q_abs, double h, double dt, double h_min);
+
+/* external water sources and sinks S_h: cell_src[nc] gives each cell's
+ * region (-1: none); region r has a mode, a unit (total discharge [m^3/s]
+ * over the region, or intensity [mm/h]) and a series of npts[r] points,
+ * concatenated in t and v (INFINITY sinks need none).  n_src = 0 removes
+ * them.  0 or -1. */
+enum { OM_SRC_EXACT = 0, OM_SRC_AVAILABLE = 1, OM_SRC_INFINITY = 2 };
+enum { OM_SRC_DISCHARGE = 0, OM_SRC_INTENSITY = 1 };
+int om_sim_set_sources(om_sim *s, const int32_t *cell_src, int32_t n_src, const int32_t *mode,
+                       const int32_t *unit, const int32_t *npts, const double *t, const double *v, char *err,
+                       int err_len);
+/* volume the sources added so far (negative: removed); the balance is
+ * M(t) = M(0) - bnd_flux + clipped + source volume */
+double om_source_volume(const om_sim *s);
 #endif

@@ -46,6 +46,19 @@ class BC:
     phi_in: tuple = ()              # inflow concentration of each passive species
 
 
+# external water sources and sinks: modes and units of the series
+SRC_EXACT, SRC_AVAILABLE, SRC_INFINITY = 0, 1, 2
+SRC_DISCHARGE, SRC_INTENSITY = 0, 1
+
+
+@dataclasses.dataclass
+class Source:
+    mode: int                       # SRC_EXACT (adds or removes), SRC_AVAILABLE or SRC_INFINITY (sinks)
+    unit: int = SRC_DISCHARGE       # total discharge over the region [m^3/s] or intensity [mm/h]
+    t: Optional[np.ndarray] = None  # series times [s] (none for SRC_INFINITY)
+    v: Optional[np.ndarray] = None  # series values (negative: a sink)
+
+
 @dataclasses.dataclass
 class Scenario:
     name: str
@@ -66,6 +79,8 @@ class Scenario:
     dt_max: float = float("inf")
     friction: str = "manning"    # closure the `manning` array parameterises: manning, strickler, chezy, bezzola
     phi0: Optional[np.ndarray] = None  # (S, N) initial concentrations of S <= 5 advected species
+    sources: tuple = ()                # external water sources and sinks (Source)
+    src_region: Optional[np.ndarray] = None  # (N,) int32 index into sources, -1 for none
 
     @property
     def n_cells(self) -> int:

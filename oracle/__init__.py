@@ -63,7 +63,7 @@ def lib():
         L.om_sim_new.argtypes = [ctypes.c_void_p, ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                  ctypes.c_double, _c_double_p, _c_double_p, _c_double_p, _c_double_p,
                                  _c_double_p, ctypes.c_int32, _c_int32_p, _c_int32_p, _c_double_p,
-                                 _c_int32_p, _c_double_p, _c_double_p, ctypes.c_double,
+                                 _c_int32_p, _c_double_p, _c_double_p, _c_double_p, ctypes.c_double,
                                  ctypes.c_char_p, ctypes.c_int]
         L.om_sim_free.argtypes = [ctypes.c_void_p]
         L.om_next_dt.restype = ctypes.c_double
@@ -191,14 +191,15 @@ class Sim:
         bQ = np.concatenate([np.asarray(b.Q, np.float64) for b in bcs if b.Q is not None] or [np.zeros(0)])
         H0 = None if sc.H0 is None else np.ascontiguousarray(sc.H0, np.float64)
         h0 = None if sc.h0 is None else np.ascontiguousarray(sc.h0, np.float64)
-        self._keep = [tags, kinds, slopes, npts, bt, bQ, H0, h0]
+        pars = np.array([getattr(b, "par", 0.0) for b in bcs], np.float64)
+        self._keep = [tags, kinds, slopes, npts, bt, bQ, H0, h0, pars]
         qx0 = np.ascontiguousarray(sc.qx0, np.float64)
         qy0 = np.ascontiguousarray(sc.qy0, np.float64)
         man = np.ascontiguousarray(sc.manning, np.float64)
         err = ctypes.create_string_buffer(256)
         self._p = L.om_sim_new(self.mesh._p, sc.g, sc.cfl, sc.h_min, sc.dt_max if dt_max is None else dt_max,
                                _dp(H0), _dp(h0), _dp(qx0), _dp(qy0), _dp(man), len(bcs),
-                               _ip(tags), _ip(kinds), _dp(slopes), _ip(npts), _dp(bt), _dp(bQ),
+                               _ip(tags), _ip(kinds), _dp(slopes), _ip(npts), _dp(bt), _dp(bQ), _dp(pars),
                                t0, err, 256)
         if not self._p:
             raise OracleError(err.value.decode())

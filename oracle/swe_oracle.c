@@ -41,7 +41,8 @@ struct om_mesh {
 
 typedef struct {
     int32_t tag, kind, npts;
-    double slope, length;
+    double slope, length;  /* slope: energy slope, Froude number, crest elevation or collapse time */
+    double par;            /* Poleni factor of a weir */
     double *t, *Q;
 } om_bc;
 
@@ -293,7 +294,7 @@ om_sim *om_sim_new(const om_mesh *m, double g, double cfl, double h_min, double 
                    const double *H0, const double *h0, const double *qx0, const double *qy0,
                    const double *manning, int32_t nbc, const int32_t *bc_tag, const int32_t *bc_kind,
                    const double *bc_slope, const int32_t *bc_npts, const double *bc_t,
-                   const double *bc_Q, double t0, char *err, int elen) {
+                   const double *bc_Q, const double *bc_par, double t0, char *err, int elen) {
     om_sim *s = (om_sim *)calloc(1, sizeof(om_sim));
     if (!s) { seterr(err, elen, "out of memory"); return NULL; }
     int64_t nc = m->nc;
@@ -333,15 +334,24 @@ om_sim *om_sim_new(const om_mesh *m, double g, double cfl, double h_min, double 
         om_bc *B = &s->bc[b];
         B->tag = bc_tag[b]; B->kind = bc_kind[b]; B->slope = bc_slope ? bc_slope[b] : 0.0;
         B->npts = bc_npts ? bc_npts[b] : 0;
-        if (B->kind < 0 || B->kind > 3) { seterr(err, elen, "unknown boundary kind"); goto fail; }
+        B->par = bc_par ? bc_par[b] : 0.0;
+        if (B->kind < 0 || B->kind > OM_DYNAMIC_WALL) { seterr(err, elen, "unknown boundary kind"); goto fail; }
+        if (!isfinite(B->slope) || !isfinite(B->par)) { seterr(err, elen, "non-finite boundary parameter"); goto fail; }
         if (B->kind == OM_ZHYDROGRAPH && B->npts < 1) { seterr(err, elen, "zhydrograph needs a series"); goto fail; }
-        if (B->kind == OM_INFLOW_UNIFORM || B->kind == OM_ZHYDROGRAPH) {
+        if (B->kind == OM_INFLOW_FROUDE && (B->npts < 1 || !(B->slope > 0))) { seterr(err, elen, "froude inflow needs a hydrograph and a positive Froude number"); goto fail; }
+        if (B->kind == OM_OUTFLOW_UNIFORM && !(B->slope > 0)) { seterr(err, elen, "uniform outflow needs a positive slope"); goto fail; }
+        if (B->kind == OM_OUTFLOW_WEIR && !(B->par > 0)) { seterr(err, elen, "a weir needs a positive Poleni factor"); goto fail; }
+        if (B->kind == OM_OUTFLOW_HQ && B->npts < 1) { seterr(err, elen, "an h-Q relation needs a table"); goto fail; }
+        if (B->kind == OM_INFLOW_UNIFORM || B->kind == OM_ZHYDROGRAPH || B->kind == OM_INFLOW_FROUDE ||
+            B->kind == OM_OUTFLOW_HQ) {
             if (B->kind == OM_INFLOW_UNIFORM && (B->npts < 1 || !(B->slope > 0))) { seterr(err, elen, "inflow needs a hydrograph and a positive slope"); goto fail; }
             B->t = malloc(sizeof(double) * B->npts); B->Q = malloc(sizeof(double) * B->npts);
             if (!B->t || !B->Q) { seterr(err, elen, "out of memory"); goto fail; }
             for (int k = 0; k < B->npts; k++) {
                 B->t[k] = bc_t[off + k]; B->Q[k] = bc_Q[off + k];
+                if (!isfinite(B->t[k]) || !isfinite(B->Q[k])) { seterr(err, elen, "non-finite boundary series"); goto fail; }
                 if (k > 0 && !(B->t[k] > B->t[k - 1])) { seterr(err, elen, "hydrograph times must increase"); goto fail; }
+                if (B->kind == OM_OUTFLOW_HQ && B->Q[k] < 0.0) { seterr(err, elen, "h-Q discharges must be >= 0"); goto fail; }
             }
         }
         off += B->npts;
@@ -356,8 +366,8 @@ om_sim *om_sim_new(const om_mesh *m, double g, double cfl, double h_min, double 
         }
         if (s->ebc[e] >= 0) {
             om_bc *B = &s->bc[s->ebc[e]];
-            if (B->kind == OM_INFLOW_UNIFORM && !(s->gn2[m->eL[e]] > 0)) {
-                seterr(err, elen, "inflow edge next to a cell with Manning n = 0"); goto fail;
+            if ((B->kind == OM_INFLOW_UNIFORM || B->kind == OM_OUTFLOW_UNIFORM) && !(s->gn2[m->eL[e]] > 0)) {
+                seterr(err, elen, "uniform inflow or outflow edge next to a cell with Manning n = 0"); goto fail;
             }
         }
     }
@@ -472,6 +482,46 @@ int om_sim_set_sources(om_sim *s, const int32_t *cell_src, int32_t nsrc, const i
 }
 
 double om_source_volume(const om_sim *s) { return s->ssum + s->scomp; }
+
+/* Inflow "froude(discharge, Froude number)" (the supplementary feature
+ * table's inflow options): the unit discharge q = Q / length enters with the
+ * depth at which the flow has the given Froude number, u = Fr sqrt(g h) and
+ * q = u h, so h = (q / (Fr sqrt(g)))^(2/3).  Returns 0 when Q <= 0 (wall). */
+static int froude_ghost(const om_sim *s, const om_bc *B, double t, double *hg, double *ung) {
+    double Q = hydrograph(B, t);
+    if (!(Q > 0)) return 0;
+    double q = Q / B->length;
+    double h = pow(q / (B->slope * sqrt(s->g)), 2.0 / 3.0);
+    *hg = h;
+    *ung = -q / h;
+    return 1;
+}
+
+/* Normal depth of a unit discharge q >= 0 under the cell's power-law
+ * friction coefficient gn2 = g n^2 on the energy slope S (Manning's formula
+ * q = h^(5/3) sqrt(S) / n solved for h). */
+static double normal_depth(const om_sim *s, double gn2, double q, double S) {
+    double n = sqrt(gn2 / s->g);
+    return pow(n * q / sqrt(S), 0.6);
+}
+
+/* Outflow discharge per unit length of the imposed-discharge outflows, from
+ * the surface H and bed z of the boundary cell:
+ *  weir(crest elevation z_w, Poleni factor mu): Poleni's free-overflow law
+ *  q = (2/3) mu sqrt(2g) d^(3/2) with the head d = H - max(z_w, z) (a crest
+ *  below the cell's bed counts at the bed);
+ *  h-Q relation: Q(H) from the table (linear, constant past its ends)
+ *  spread over the boundary length.  Zero for a dry cell. */
+static double imposed_outflow(const om_sim *s, const om_bc *B, double H, double z) {
+    if (!(H - z > 0.0)) return 0.0;
+    if (B->kind == OM_OUTFLOW_WEIR) {
+        double crest = B->slope > z ? B->slope : z;
+        double d = H - crest;
+        if (!(d > 0.0)) return 0.0;
+        return (2.0 / 3.0) * B->par * sqrt(2.0 * s->g) * (d * sqrt(d));
+    }
+    return hydrograph(B, H) / B->length;
+}
 
 /* Inflow "uniform(discharge, slope)" (section "Hydrodynamic BCs"): the given
  * discharge is spread over the boundary length; reading: the ghost carries
@@ -589,11 +639,13 @@ int om_sim_set_friction(om_sim *s, int32_t kind, const double *par, char *err, i
     }
     s->fkind = kind;
     for (int64_t e = 0; e < m->ne; e++) {
-        if (s->ebc[e] < 0 || s->bc[s->ebc[e]].kind != OM_INFLOW_UNIFORM) continue;
+        if (s->ebc[e] < 0) continue;
+        int k = s->bc[s->ebc[e]].kind;
+        if (k != OM_INFLOW_UNIFORM && k != OM_OUTFLOW_UNIFORM) continue;
         if (kind == OM_CHEZY || kind == OM_BEZZOLA) {
-            seterr(err, elen, "inflow uniform(Q, S) needs the Manning or Strickler closure"); return -1;
+            seterr(err, elen, "uniform inflow or outflow needs the Manning or Strickler closure"); return -1;
         }
-        if (!(s->gn2[m->eL[e]] > 0)) { seterr(err, elen, "inflow edge next to a frictionless cell"); return -1; }
+        if (!(s->gn2[m->eL[e]] > 0)) { seterr(err, elen, "uniform inflow or outflow edge next to a frictionless cell"); return -1; }
     }
     return 0;
 }
@@ -630,6 +682,16 @@ double om_next_dt(const om_sim *s, double t_end) {
         if (B->kind != OM_INFLOW_UNIFORM) continue;
         double hg, ung;
         if (!inflow_ghost(s, B, m->eL[e], s->t, &hg, &ung)) continue;
+        double lam = fabs(ung) + sqrt(s->g * hg);
+        double r = m->rho[3 * m->eL[e] + m->ekL[e]] / lam;
+        if (r < best) best = r;
+    }
+    for (int64_t e = 0; e < m->ne; e++) {
+        if (s->ebc[e] < 0) continue;
+        const om_bc *B = &s->bc[s->ebc[e]];
+        if (B->kind != OM_INFLOW_FROUDE) continue;
+        double hg, ung;
+        if (!froude_ghost(s, B, s->t, &hg, &ung)) continue;
         double lam = fabs(ung) + sqrt(s->g * hg);
         double r = m->rho[3 * m->eL[e] + m->ekL[e]] / lam;
         if (r < best) best = r;
@@ -758,7 +820,7 @@ int om_step(om_sim *s, double t_end, double *dt_taken) {
         double HL = s->H[L], zL = m->zb[L];
         double unL = uL * nx + vL * ny, utL = -uL * ny + vL * nx;
         double HR, zR, unR, utR;
-        int wall = 0, open = 0, inflow_b = -1;
+        int wall = 0, open = 0, inflow_b = -1, imposed = 0;
         if (R >= 0) {
             cell_velocity(s, R, &hR, &uR, &vR);
             HR = s->H[R]; zR = m->zb[R];
@@ -773,6 +835,21 @@ int om_step(om_sim *s, double t_end, double *dt_taken) {
                 HR = HL; unR = unL; utR = utL; open = 1;
             } else if (B && B->kind == OM_INFLOW_UNIFORM && inflow_ghost(s, B, L, s->t, &hg, &ung)) {
                 HR = zL + hg; unR = ung; utR = 0.0; open = 1; inflow_b = b;
+            } else if (B && B->kind == OM_INFLOW_FROUDE && froude_ghost(s, B, s->t, &hg, &ung)) {
+                HR = zL + hg; unR = ung; utR = 0.0; open = 1; inflow_b = b;
+            } else if (B && B->kind == OM_OUTFLOW_UNIFORM) {
+                /* uniform(slope) outflow: the ghost carries the normal depth
+                 * of the cell's outflowing unit discharge with the cell's
+                 * velocity (reading: "a value for the water depth must be
+                 * specified" for outflows; no outflow gives a dry ghost) */
+                double qn = hL * unL;
+                hg = normal_depth(s, s->gn2[L], qn > 0.0 ? qn : 0.0, B->slope);
+                HR = zL + hg; unR = unL; utR = utL; open = 1;
+            } else if (B && (B->kind == OM_OUTFLOW_WEIR || B->kind == OM_OUTFLOW_HQ)) {
+                HR = HL; unR = unL; utR = utL; open = 1; imposed = 1;
+            } else if (B && B->kind == OM_DYNAMIC_WALL && s->t >= B->slope) {
+                /* a dynamic wall after its collapse time: transmissive */
+                HR = HL; unR = unL; utR = utL; open = 1;
             } else if (B && B->kind == OM_ZHYDROGRAPH) {
                 /* "zhydrograph" (section "Hydrodynamic BCs", water surface
                  * elevation series).  Reading: the ghost is still water at the
@@ -792,7 +869,16 @@ int om_step(om_sim *s, double t_end, double *dt_taken) {
         double hLs = HL - zs; if (hLs < OM_H_DRY) hLs = 0.0;
         double hRs = HR - zs; if (hRs < OM_H_DRY) hRs = 0.0;
         double F[3];
-        om_hllc(hLs, unL, utL, hRs, unR, utR, g, F);
+        if (imposed) {
+            /* weir or h-Q outflow: the boundary discharge q leaves carrying
+             * the cell's state: F = (q, q^2/h + g h^2/2, q u_t) */
+            double q = imposed_outflow(s, &s->bc[s->ebc[e]], HL, zL);
+            F[0] = q;
+            F[1] = (hLs > 0.0 ? q * (q / hLs) : 0.0) + 0.5 * g * hLs * hLs;
+            F[2] = q * utL;
+        } else {
+            om_hllc(hLs, unL, utL, hRs, unR, utR, g, F);
+        }
         if (wall) F[0] = 0.0;   /* impermeable: no mass crosses a wall */
         /* fluctuations: the flux minus each side's own reconstructed pressure
          * (the bed-slope source in well-balanced form, using sum_j l n = 0) */

@@ -21,7 +21,8 @@ typedef struct om_mesh om_mesh;
 typedef struct om_sim om_sim;
 
 /* boundary kinds */
-enum { OM_WALL = 0, OM_INFLOW_UNIFORM = 1, OM_OUTFLOW_ZEROGRAD = 2, OM_ZHYDROGRAPH = 3 };
+enum { OM_WALL = 0, OM_INFLOW_UNIFORM = 1, OM_OUTFLOW_ZEROGRAD = 2, OM_ZHYDROGRAPH = 3, OM_INFLOW_FROUDE = 4,
+       OM_OUTFLOW_UNIFORM = 5, OM_OUTFLOW_WEIR = 6, OM_OUTFLOW_HQ = 7, OM_DYNAMIC_WALL = 8 };
 #define OM_MAX_SPECIES 5
 /* friction closures (Table friction_closure) */
 enum { OM_MANNING = 0, OM_STRICKLER = 1, OM_CHEZY = 2, OM_BEZZOLA = 3 };
@@ -40,7 +41,8 @@ om_sim *om_sim_new(const om_mesh *m, double g, double cfl, double h_min, double 
                    const double *H0, const double *h0, const double *qx0, const double *qy0,
                    const double *manning, int32_t n_bc, const int32_t *bc_tag,
                    const int32_t *bc_kind, const double *bc_slope, const int32_t *bc_npts,
-                   const double *bc_t, const double *bc_Q, double t0, char *err, int err_len);
+                   const double *bc_t, const double *bc_Q, const double *bc_par, double t0, char *err,
+                   int err_len);
 void om_sim_free(om_sim *s);
 /* closure and per-cell parameter (n, k_str, K_s or y_R); default Manning
  * with the array given to om_sim_new.  0 or -1 (message in err). */

@@ -30,6 +30,11 @@ WALL = 0
 INFLOW_UNIFORM = 1
 OUTFLOW_ZEROGRAD = 2
 ZHYDROGRAPH = 3   # prescribed water-surface elevation series (t, Q hold times and elevations)
+INFLOW_FROUDE = 4     # discharge series entering at a given Froude number (slope = Fr)
+OUTFLOW_UNIFORM = 5   # normal depth of the outflowing discharge (slope = energy slope)
+OUTFLOW_WEIR = 6      # Poleni weir (slope = crest elevation, par = Poleni factor)
+OUTFLOW_HQ = 7        # h-Q relation (t = surface elevations, Q = discharges)
+DYNAMIC_WALL = 8      # wall until the collapse time (slope), then zero gradient
 
 
 def rng(offset: int) -> np.random.Generator:
@@ -40,10 +45,11 @@ def rng(offset: int) -> np.random.Generator:
 class BC:
     tag: int
     kind: int
-    slope: float = 0.0
-    t: Optional[np.ndarray] = None  # hydrograph times [s]
-    Q: Optional[np.ndarray] = None  # hydrograph discharge [m^3/s] (surface elevation [m] for ZHYDROGRAPH)
+    slope: float = 0.0              # energy slope (uniform), Froude number, crest elevation (weir), collapse time
+    t: Optional[np.ndarray] = None  # hydrograph times [s] (surface elevations [m] of an h-Q table)
+    Q: Optional[np.ndarray] = None  # discharge [m^3/s] (surface elevation [m] for ZHYDROGRAPH)
     phi_in: tuple = ()              # inflow concentration of each passive species
+    par: float = 0.0                # Poleni factor of a weir
 
 
 # external water sources and sinks: modes and units of the series

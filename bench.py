@@ -35,13 +35,19 @@ HBM_PEAK_GBS = 8000.0
 # once (state in, bed, g n^2, cell area, 3 neighbour ids, 3 l*n pairs, state
 # out), neighbour gathers served from cache
 ALGO_BYTES = {"fp32": 72.0, "fp64": 132.0}
+# each passive species adds its specific mass in and out
+SPECIES_BYTES = {"fp32": 8.0, "fp64": 16.0}
 
 
 # HBM traffic of the step kernel, measured with the FETCH_SIZE and WRITE_SIZE
 # counters (each scaled by what it reads for a plain copy of known size); it
 # is reported only while the kernel sources still hash to the digest recorded
 # with the measurement
-TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_step_fp32_valley4m_hbm_traffic.md")
+def traffic_profile(precision, species):
+    kern = f"k_step_species{species}" if species else "k_step"
+    return os.path.join(ROOT, "profiles", f"{kern}_{precision}_valley4m_hbm_traffic.md")
+
+
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2102_12862_amd", "csrc", f)
                   for f in ("kernels.hip", "swe_internal.h", "meshprep.cpp", "meshprep.h")]
 
@@ -59,19 +65,19 @@ def kernel_digest():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(workload, precision, tile):
+def measured_traffic(workload, precision, tile, species=0):
     """Bytes per step-kernel launch from the committed counter profile, or
     None when it was taken on other kernel sources or another configuration."""
     try:
-        with open(TRAFFIC_PROFILE) as fh:
+        with open(traffic_profile(precision, species)) as fh:
             kv = dict(line.strip()[2:].split(": ", 1) for line in fh if line.startswith("- ") and ": " in line)
     except OSError:
         return None
     try:
         if (kv.get("kernel_digest") != kernel_digest() or kv.get("workload") != workload
-                or kv.get("precision") != precision or int(kv.get("tile", -1)) != tile):
+                or kv.get("precision") != precision):
             return None
-        return float(kv["traffic_bytes_per_launch"])
+        return float(kv[f"traffic_bytes_per_launch_tile{tile}"])
     except (KeyError, ValueError):
         return None
 
@@ -93,7 +99,15 @@ def _events():
     return torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
 
 
-def time_gpu(sc, precision, steps, warmup, autotune=True):
+def species_phi0(sc, ns):
+    """Initial concentrations of ns species: a front across the domain at
+    the median centroid x, then uniform backgrounds."""
+    cx = sc.centroids()[:, 0]
+    rows = [np.where(cx < np.median(cx), 1.0, 0.0)] + [np.full(sc.n_cells, 0.1 * (k + 1)) for k in range(ns - 1)]
+    return np.stack(rows[:ns])
+
+
+def time_gpu(sc, precision, steps, warmup, autotune=True, species=0, tile=0):
     """Kernel time per step over `steps` graph-launched steps."""
     import torch
     from paper_2102_12862_amd import swe
@@ -101,8 +115,10 @@ def time_gpu(sc, precision, steps, warmup, autotune=True):
     dev = device()
     mesh = swe.Mesh(sc.nodes, sc.tri, sc.bnd_seg, sc.bnd_tag, device=dev)
     p = swe.FP32 if precision == "fp32" else swe.FP64
-    st = swe.State(mesh, sc, precision=p, steps_per_graph=50)
-    tune = st.autotune(k=5) if autotune else None
+    st = swe.State(mesh, sc, precision=p, steps_per_graph=50, block_size=tile)
+    if species:
+        st.set_scalars(species_phi0(sc, species))
+    tune = st.autotune(k=5) if (autotune and not tile) else None
     st.launch_steps(warmup)
     st.sync()
     e0, e1 = _events()
@@ -250,6 +266,10 @@ def main():
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="also run a plain device copy of this many MiB (counter calibration)")
+    ap.add_argument("--tile", type=int, default=0, choices=(0, 128, 256, 512),
+                    help="cells per tile (block size) of the step kernel; 0: autotuned")
+    ap.add_argument("--species", type=int, default=0, choices=range(0, 6),
+                    help="passive species carried by the step (0: the hydrodynamic step alone)")
     ap.add_argument("--kernel-digest", action="store_true", help="print the digest of the kernel sources and exit")
     args = ap.parse_args()
     if args.kernel_digest:
@@ -278,12 +298,17 @@ def main():
     t0 = time.perf_counter()
     sc = make_workload(args.workload)
     log(f"[bench] {sc.name}: {sc.n_cells} cells ({time.perf_counter() - t0:.1f}s)")
-    r = time_gpu(sc, args.precision, args.steps, args.warmup, autotune=not args.no_autotune)
+    r = time_gpu(sc, args.precision, args.steps, args.warmup, autotune=not args.no_autotune, species=args.species,
+                 tile=args.tile)
     N = sc.n_cells
     value = r["rate"]
-    achieved = ALGO_BYTES[args.precision] * N / (r["ms_step"] * 1e-3) / 1e9
-    tile = r["tune"][0] if r["tune"] else 256
-    traffic = measured_traffic(sc.name, args.precision, tile)
+    bytes_per_cell = ALGO_BYTES[args.precision] + args.species * SPECIES_BYTES[args.precision]
+    achieved = bytes_per_cell * N / (r["ms_step"] * 1e-3) / 1e9
+    tile = r["tune"][0] if r["tune"] else (args.tile or 256)
+    traffic = measured_traffic(sc.name, args.precision, tile, args.species)
+    tname = "float" if args.precision == "fp32" else "double"
+    kname = (f"k_step_species<{tname}, 256, {args.species}, false>" if args.species
+             else f"k_step<{tname}, {tile}, false>")
     log(f"[bench] gpu {args.precision}: {r['ms_step'] * 1e3:.1f} us/step, {value:.3e} cell-updates/s, "
         f"{achieved:.0f} GB/s algorithmic, tune {r['tune']}")
     variants = {}
@@ -300,6 +325,14 @@ def main():
             variants[f"{lake.name}_{p}"] = {"cell_updates_per_s": lr["rate"], "us_per_step": lr["ms_step"] * 1e3,
                                            "note": "working set fits the 256 MB Infinity Cache"}
             log(f"[bench] lake {p}: {lr['ms_step'] * 1e3:.1f} us/step")
+        for ns in ((2, 5) if not args.species else ()):
+            sr = time_gpu(sc, args.precision, max(50, args.steps // 5), 10, species=ns)
+            b = ALGO_BYTES[args.precision] + ns * SPECIES_BYTES[args.precision]
+            variants[f"{sc.name}_{args.precision}_species{ns}"] = {
+                "cell_updates_per_s": sr["rate"], "us_per_step": sr["ms_step"] * 1e3,
+                "algorithmic_bytes_per_cell": b,
+                "roofline_frac": b * N / (sr["ms_step"] * 1e-3) / 1e9 / HBM_PEAK_GBS}
+            log(f"[bench] {ns} species: {sr['ms_step'] * 1e3:.1f} us/step")
         log("[bench] batched ensemble")
         variants["batched_ensemble_fp32"] = bench_batched()
         log(f"[bench] batched: {variants['batched_ensemble_fp32']}")
@@ -330,12 +363,12 @@ def main():
         "data": "synthetic",
         "config": {"workload": sc.name, "cells": N, "precision": args.precision,
                    "state": "fully wet snapshot" if "wet" in args.workload else "as generated",
-                   "block_size_cells_per_thread": r["tune"]},
+                   "block_size_cells_per_thread": r["tune"], "species": args.species},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "algorithmic_bytes_per_cell": ALGO_BYTES[args.precision],
-                     "algorithmic_bytes_per_launch": ALGO_BYTES[args.precision] * N,
-                     "kernel": f"k_step<{'float' if args.precision == 'fp32' else 'double'}, {tile}>"},
+                     "algorithmic_bytes_per_cell": bytes_per_cell,
+                     "algorithmic_bytes_per_launch": bytes_per_cell * N,
+                     "kernel": kname},
         "cpu_baseline": cpu,
         "variants": variants,
     }

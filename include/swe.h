@@ -49,7 +49,8 @@ enum {
     SWE_ENONFINITE = -4, /* the state became non-finite */
     SWE_ENEGDEPTH = -5,  /* negative depth under SWE_NEG_ERROR */
     SWE_EBUDGET = -6,    /* batch footprint budget exceeded */
-    SWE_ENODT = -7       /* no finite positive time step (dry domain, no cap) */
+    SWE_ENODT = -7,      /* no finite positive time step (dry domain, no cap) */
+    SWE_ESINK = -8       /* an exact sink asked for more water than a cell held */
 };
 
 /* Device memory and stream bridge.  alloc(bytes, ctx) returns device memory
@@ -64,23 +65,51 @@ typedef struct {
     void *hip_stream;
 } swe_device;
 
-/* Boundary kinds (section "Boundary conditions", Hydrodynamic BCs; the
- * supplementary feature table lists wall, inflow uniform(discharge, slope),
- * outflow zero_gradient and zhydrograph (water surface elevation) among the
- * standard types).  A zhydrograph edge sees still water at the prescribed
- * surface elevation over its cell's bed, so water flows in or out as the
- * interior level differs.  Boundary edges whose tag has no entry, and
- * untagged boundary edges, are walls (walls are the default on every external
- * boundary). */
-enum { SWE_BC_WALL = 0, SWE_BC_INFLOW_UNIFORM = 1, SWE_BC_OUTFLOW_ZEROGRAD = 2, SWE_BC_ZHYDROGRAPH = 3 };
+/* Boundary kinds (section "Boundary conditions", Hydrodynamic BCs, and the
+ * standard inflows and outflows of the supplementary feature table).  Series
+ * are linear in time (or in the surface elevation for an h-Q table), constant
+ * past their ends, and taken at the step's start time.
+ *  - WALL: reflective, impermeable (the default on every external boundary:
+ *    edges whose tag has no entry, and untagged edges, are walls).
+ *  - INFLOW_UNIFORM (Q(t), slope S): q = Q / (boundary length) enters at
+ *    the Manning normal depth (n q / sqrt(S))^(3/5) of the edge's cell.
+ *  - OUTFLOW_ZEROGRAD: the ghost repeats the interior state.
+ *  - ZHYDROGRAPH (surface elevation series): still water at that surface
+ *    over the cell's bed; water flows in or out as the levels differ.
+ *  - INFLOW_FROUDE (Q(t), slope = Froude number Fr > 0): q enters at the
+ *    depth (q / (Fr sqrt(g)))^(2/3) where the flow has that Froude number.
+ *  - OUTFLOW_UNIFORM (slope S): the ghost has the normal depth of the cell's
+ *    outflowing unit discharge, with the cell's velocity.
+ *  - OUTFLOW_WEIR (slope = crest elevation z_w, par = Poleni factor mu > 0):
+ *    the edge carries q = (2/3) mu sqrt(2g) d^(3/2) out, d = H - max(z_w, z)
+ *    of its cell, with the cell's state: flux (q, q^2/h + g h^2/2, q u_t).
+ *  - OUTFLOW_HQ (t = surface elevations H, Q = discharges >= 0): q =
+ *    Q(H) / (boundary length) leaves like over a weir.
+ *  - DYNAMIC_WALL (slope = collapse time): a wall before it, zero gradient
+ *    from then on.
+ * Uniform inflow and outflow need the Manning or Strickler closure and a
+ * positive friction parameter in their cells.  Inflows carry their inflow
+ * concentrations of passive species; outflows the interior's. */
+enum {
+    SWE_BC_WALL = 0,
+    SWE_BC_INFLOW_UNIFORM = 1,
+    SWE_BC_OUTFLOW_ZEROGRAD = 2,
+    SWE_BC_ZHYDROGRAPH = 3,
+    SWE_BC_INFLOW_FROUDE = 4,
+    SWE_BC_OUTFLOW_UNIFORM = 5,
+    SWE_BC_OUTFLOW_WEIR = 6,
+    SWE_BC_OUTFLOW_HQ = 7,
+    SWE_BC_DYNAMIC_WALL = 8
+};
 
 typedef struct {
     int32_t tag;      /* boundary tag given to swe_mesh_create */
     int32_t kind;     /* SWE_BC_* */
-    double slope;     /* inflow: energy slope S > 0 of uniform(Q, S) */
-    const double *t;  /* series times [s], strictly increasing (host) */
-    const double *Q;  /* inflow: discharge [m^3/s]; zhydrograph: surface elevation [m] (host) */
-    int32_t n_pts;    /* number of series points (>= 1 for inflow and zhydrograph) */
+    double slope;     /* energy slope (uniform), Froude number, crest elevation (weir) or collapse time [s] */
+    const double *t;  /* series times [s] or the surface elevations of an h-Q table, strictly increasing (host) */
+    const double *Q;  /* discharge [m^3/s], or surface elevation [m] for a zhydrograph (host) */
+    int32_t n_pts;    /* number of series points (>= 1 where a series is needed) */
+    double par;       /* Poleni factor of a weir */
 } swe_bc;
 
 enum { SWE_FP64 = 0, SWE_FP32 = 1 };        /* precision (double is the paper's default) */
@@ -179,6 +208,72 @@ swe_status swe_state_read(const swe_state *s, double *H, double *h, double *qx, 
  * boundaries, the volume added by positivity clips, and the step count.
  * The scheme is conservative: mass(t) = mass(0) - bnd_flux + clipped. */
 swe_status swe_mass(const swe_state *s, double *mass, double *bnd_flux, double *clipped, int64_t *steps);
+
+/* ---- passive species (section "Scalar advection-diffusion": eq.
+ * scalar_goveq without the diffusion tensor, updated by eq.
+ * scl:updateformula with the advective fluxes only).  Per species c the
+ * specific mass q_c = h phi_c is carried by the HLLC mass flux of each edge
+ * times the concentration of the cell the water leaves (phi = q/h in cells
+ * with water, 0 in dry ones).  Walls carry nothing; zero-gradient and
+ * prescribed-surface edges repeat the interior concentration; active inflow
+ * edges carry their condition's inflow concentration.  A cell the step leaves
+ * without water keeps no species mass; the mass so removed is tallied.
+ *
+ * swe_state_set_scalars: ns in 0..5 species (0 removes them).  phi0 (host,
+ * ns x n_cells doubles, original cell order; NULL = 0) gives initial
+ * concentrations: q = h phi0 of the state's current depth.  phi_in (host,
+ * n_bc x ns doubles in the order of the bcs given to swe_state_init; NULL =
+ * 0) gives the inflow concentrations.  Allocates 2 ns n_cells values of the
+ * state's precision; switches the state to 256-cell tiles (the only tile size
+ * of the species-carrying step; swe_autotune then keeps it).  States with
+ * species cannot join a batch.  SWE_EINVAL for ns out of range or non-finite
+ * values, SWE_ENOMEM when the device allocation fails (species removed). */
+swe_status swe_state_set_scalars(swe_state *s, int32_t ns, const double *phi0, const double *phi_in);
+/* Copies the specific masses q (ns x n_cells doubles, original cell order) to
+ * host memory; nothing is written when the state has no species. */
+swe_status swe_state_read_scalars(const swe_state *s, double *q);
+/* Per species (arrays of ns doubles, any may be NULL): mass sum q |Omega|
+ * (compensated FP64, fixed order), the time integral of the species flux
+ * leaving through open boundaries, and the mass added by resetting cells
+ * left dry: mass(t) = mass(0) - bnd_flux + clipped.  The reset tally is summed
+ * with device atomics: its last bits depend on the order of the cells. */
+swe_status swe_scalar_mass(const swe_state *s, double *mass, double *bnd_flux, double *clipped);
+
+/* ---- external water sources and sinks S_h (the S_h paragraph of the
+ * hydrodynamic closure relations; eq. swe_vectorial_form_sourceterms,
+ * added explicitly to the continuity equation of eq.
+ * hydrodynamicupdateformula: H += dt S_h after the fluxes, before the
+ * friction split).  Each region has a series (linear in time, constant past
+ * its ends, taken at the step's start time) of a total discharge [m^3/s]
+ * spread evenly over the region's area (summed in ascending order), or of an
+ * intensity [mm/h]; negative values remove water.  Modes: SWE_SRC_EXACT
+ * adds or removes exactly dt S_h (a removal beyond the water a cell holds
+ * after the fluxes sets SWE_ESINK; the step completes and the deficit is
+ * clipped and tallied like a negative depth); SWE_SRC_AVAILABLE removes at
+ * most that water (values must be <= 0); SWE_SRC_INFINITY removes all of it
+ * (no series).  A cell a sink empties gets H = z exactly.  Removed water
+ * carries the cell's species concentrations; added water carries none. */
+enum { SWE_SRC_EXACT = 0, SWE_SRC_AVAILABLE = 1, SWE_SRC_INFINITY = 2 };
+enum { SWE_SRC_DISCHARGE = 0, SWE_SRC_INTENSITY = 1 };
+typedef struct {
+    int32_t mode;       /* SWE_SRC_* mode */
+    int32_t unit;       /* SWE_SRC_DISCHARGE or SWE_SRC_INTENSITY */
+    const double *t;    /* n_pts increasing times [s] (host) */
+    const double *v;    /* n_pts values (host) */
+    int32_t n_pts;      /* >= 1, or 0 for SWE_SRC_INFINITY */
+} swe_source;
+/* Sets the sources of a state: cell_region (host, n_cells ints in original
+ * cell order) gives each cell's index into src[n_src], or -1.  n_src = 0
+ * removes them.  Copies everything; allocates per cell 4 bytes and per tile
+ * 16 bytes of device memory.  States with sources keep their tile size under
+ * swe_autotune and cannot join a batch.  SWE_EINVAL for bad modes, units,
+ * series, region indices or an empty discharge region; SWE_ENOMEM. */
+swe_status swe_state_set_sources(swe_state *s, const int32_t *cell_region, const swe_source *src, int32_t n_src);
+/* Volume the sources have added since they were set (negative: removed),
+ * compensated FP64 over per-tile accumulators in a fixed order.  With
+ * sources the balance of swe_mass reads mass(t) = mass(0) - bnd_flux +
+ * clipped + source volume. */
+swe_status swe_source_volume(const swe_state *s, double *volume);
 
 /* Times k steps for each tile size (block size) in {128, 256, 512}, keeps
  * the fastest for this state, and restores the state exactly as it was.

@@ -82,6 +82,7 @@ swe_status check_flags(int flags) {
     if (flags & FLAG_NONFINITE) return fail(SWE_ENONFINITE, "state became non-finite");
     if (flags & FLAG_NEGDEPTH) return fail(SWE_ENEGDEPTH, "negative depth under the error policy");
     if (flags & FLAG_NODT) return fail(SWE_ENODT, "no finite positive time step");
+    if (flags & FLAG_SINK) return fail(SWE_ESINK, "an exact sink asked for more water than a cell held");
     return SWE_OK;
 }
 
@@ -160,7 +161,18 @@ struct swe_state {
     double *mass_out = nullptr;
     Ctrl *hctrl = nullptr;    // pinned host copy of the control block
     double *hbuf = nullptr;   // pinned scratch (t_end, mass results)
-    int nslots = 0;
+    int nslots = 0, n_bc = 0;
+    // passive species: specific masses [ns][n] (ping-pong with U0/U1), inflow
+    // concentrations [n_bc][ns], per-slot boundary accumulators, reset tallies
+    int ns = 0;
+    void *Q0 = nullptr, *Q1 = nullptr, *phi_in = nullptr;
+    double *sslot_acc = nullptr, *sclip = nullptr;
+    // external sources: per device cell the region, per region its record
+    // and series, per tile (at the smallest tile size) a volume accumulator
+    int nsrc = 0, src_tiles = 0;
+    int *src_cell = nullptr;
+    BCdev *srcs = nullptr;
+    double *src_series = nullptr, *src_acc = nullptr;
     int tile = 256, spg = 32;
     int phase = 0;  // step launches issued so far, mod 3 (selects the control slot)
     hipStream_t cap = nullptr;
@@ -175,10 +187,45 @@ struct swe_state {
         for (void *q : {U0, U1, cellp, (void *)slot_kbc, (void *)slot_acc, (void *)bcs, (void *)hydro, (void *)ctrl,
                         (void *)partials, (void *)mass_out})
             mem.release(q);
+        drop_species();
+        drop_sources();
         if (hctrl) (void)hipHostFree(hctrl);
         if (hbuf) (void)hipHostFree(hbuf);
     }
     hipStream_t stream() const { return mem.stream(); }
+    void drop_species() {
+        for (void *q : {Q0, Q1, phi_in, (void *)sslot_acc, (void *)sclip}) mem.release(q);
+        Q0 = Q1 = phi_in = nullptr;
+        sslot_acc = sclip = nullptr;
+        ns = 0;
+        bind_species();
+    }
+    void drop_sources() {
+        for (void *q : {(void *)src_cell, (void *)srcs, (void *)src_series, (void *)src_acc}) mem.release(q);
+        src_cell = nullptr;
+        srcs = nullptr;
+        src_series = src_acc = nullptr;
+        nsrc = src_tiles = 0;
+        bind_sources();
+    }
+    void bind_sources() {
+        inst32.nsrc = inst64.nsrc = nsrc;
+        inst32.src_cell = inst64.src_cell = src_cell;
+        inst32.srcs = inst64.srcs = srcs;
+        inst32.src_acc = inst64.src_acc = src_acc;
+    }
+    // copies the species buffers into both kernel parameter blocks
+    void bind_species() {
+        inst32.Q0 = (float *)Q0;
+        inst32.Q1 = (float *)Q1;
+        inst32.phi_in = (const float *)phi_in;
+        inst64.Q0 = (double *)Q0;
+        inst64.Q1 = (double *)Q1;
+        inst64.phi_in = (const double *)phi_in;
+        inst32.sslot_acc = inst64.sslot_acc = sslot_acc;
+        inst32.sclip = inst64.sclip = sclip;
+        inst32.ns = inst64.ns = ns;
+    }
     // the current time level as last read from the device
     const CtrlSlot &lvl() const { return hctrl->s[phase]; }
     void drop_graphs() {
@@ -270,6 +317,8 @@ extern "C" {
 static_assert(FR_MANNING == SWE_FRICTION_MANNING && FR_STRICKLER == SWE_FRICTION_STRICKLER &&
                   FR_CHEZY == SWE_FRICTION_CHEZY && FR_BEZZOLA == SWE_FRICTION_BEZZOLA,
               "friction closure numbering");
+static_assert(SRC_EXACT == SWE_SRC_EXACT && SRC_AVAILABLE == SWE_SRC_AVAILABLE && SRC_INFINITY == SWE_SRC_INFINITY,
+              "source mode numbering");
 
 void swe_params_default(swe_params *p) {
     if (!p) return;
@@ -407,16 +456,21 @@ swe_status swe_state_init(const swe_mesh *m, const swe_params *params, const dou
     std::vector<size_t> hoff((size_t)std::max(n_bc, 1));
     for (int b = 0; b < n_bc; b++) {
         const swe_bc &B = bcs[b];
-        if (B.kind < SWE_BC_WALL || B.kind > SWE_BC_ZHYDROGRAPH) return fail(SWE_EINVAL, "unknown boundary kind");
-        hb[b] = BCdev{B.kind, 0, B.slope, 0.0, nullptr, nullptr};
+        if (B.kind < SWE_BC_WALL || B.kind > SWE_BC_DYNAMIC_WALL) return fail(SWE_EINVAL, "unknown boundary kind");
+        if (!std::isfinite(B.slope) || !std::isfinite(B.par)) return fail(SWE_EINVAL, "non-finite boundary parameter");
+        hb[b] = BCdev{B.kind, 0, B.slope, 0.0, nullptr, nullptr, B.par};
         hoff[b] = hydro.size();
-        if (B.kind == SWE_BC_INFLOW_UNIFORM || B.kind == SWE_BC_ZHYDROGRAPH) {
-            if (B.n_pts < 1 || !B.t || !B.Q) return fail(SWE_EINVAL, "inflow and zhydrograph need a series");
-            if (B.kind == SWE_BC_INFLOW_UNIFORM && (!(B.slope > 0) || !std::isfinite(B.slope)))
-                return fail(SWE_EINVAL, "inflow needs a positive slope");
+        if ((B.kind == SWE_BC_INFLOW_UNIFORM || B.kind == SWE_BC_INFLOW_FROUDE || B.kind == SWE_BC_OUTFLOW_UNIFORM) &&
+            !(B.slope > 0))
+            return fail(SWE_EINVAL, "uniform and froude conditions need a positive slope or Froude number");
+        if (B.kind == SWE_BC_OUTFLOW_WEIR && !(B.par > 0)) return fail(SWE_EINVAL, "a weir needs a positive Poleni factor");
+        if (B.kind == SWE_BC_INFLOW_UNIFORM || B.kind == SWE_BC_ZHYDROGRAPH || B.kind == SWE_BC_INFLOW_FROUDE ||
+            B.kind == SWE_BC_OUTFLOW_HQ) {
+            if (B.n_pts < 1 || !B.t || !B.Q) return fail(SWE_EINVAL, "inflows, zhydrograph and h-Q need a series");
             for (int k = 0; k < B.n_pts; k++) {
                 if (!std::isfinite(B.t[k]) || !std::isfinite(B.Q[k])) return fail(SWE_EINVAL, "non-finite hydrograph");
                 if (k > 0 && !(B.t[k] > B.t[k - 1])) return fail(SWE_EINVAL, "hydrograph times must increase");
+                if (B.kind == SWE_BC_OUTFLOW_HQ && B.Q[k] < 0.0) return fail(SWE_EINVAL, "h-Q discharges must be >= 0");
             }
             hb[b].npts = B.n_pts;
             hydro.insert(hydro.end(), B.t, B.t + B.n_pts);
@@ -434,10 +488,11 @@ swe_status swe_state_init(const swe_mesh *m, const swe_params *params, const dou
             if (bcs[b].kind == SWE_BC_WALL) break;
             kbc[s] = bcs[b].kind | (b << 4);
             lens[b].push_back(M.slot_len[s]);
-            if (bcs[b].kind == SWE_BC_INFLOW_UNIFORM && P.friction >= SWE_FRICTION_CHEZY)
-                return fail(SWE_EINVAL, "inflow uniform(Q, S) needs the Manning or Strickler closure");
-            if (bcs[b].kind == SWE_BC_INFLOW_UNIFORM && !(gn2[M.slot_cell[s]] > 0))
-                return fail(SWE_EINVAL, "inflow edge next to a frictionless cell");
+            const bool unif = bcs[b].kind == SWE_BC_INFLOW_UNIFORM || bcs[b].kind == SWE_BC_OUTFLOW_UNIFORM;
+            if (unif && P.friction >= SWE_FRICTION_CHEZY)
+                return fail(SWE_EINVAL, "uniform inflow or outflow needs the Manning or Strickler closure");
+            if (unif && !(gn2[M.slot_cell[s]] > 0))
+                return fail(SWE_EINVAL, "uniform inflow or outflow edge next to a frictionless cell");
             break;
         }
     }
@@ -457,6 +512,7 @@ swe_status swe_state_init(const swe_mesh *m, const swe_params *params, const dou
     S->mem = m->mem;
     S->prec = prec;
     S->nslots = nslots;
+    S->n_bc = n_bc;
     S->tile = P.block_size ? P.block_size : 256;
     S->spg = P.steps_per_graph ? P.steps_per_graph : 32;
     swe_status st = prec == SWE_FP32 ? S->m->ensure_tiles<float>(prec, S->tile)
@@ -669,8 +725,226 @@ swe_status swe_mass(const swe_state *cs, double *mass, double *bnd_flux, double 
     return SWE_OK;
 }
 
+swe_status swe_state_set_scalars(swe_state *s, int32_t ns, const double *phi0, const double *phi_in) {
+    if (!s) return fail(SWE_EINVAL, "state is NULL");
+    if (ns < 0 || ns > MAX_SPECIES) return fail(SWE_EINVAL, "between 0 and 5 species");
+    const HostMesh &M = s->m->H;
+    const int64_t n = M.nc;
+    for (int64_t k = 0; phi0 && k < (int64_t)ns * n; k++)
+        if (!std::isfinite(phi0[k])) return fail(SWE_EINVAL, "non-finite initial concentration");
+    for (int64_t k = 0; phi_in && k < (int64_t)ns * s->n_bc; k++)
+        if (!std::isfinite(phi_in[k])) return fail(SWE_EINVAL, "non-finite inflow concentration");
+    swe_status st = s->read_ctrl();
+    if (st) return st;
+    s->drop_graphs();
+    s->drop_species();
+    if (ns == 0) return SWE_OK;
+    if (s->tile != SPECIES_TILE) {
+        st = s->set_tile(SPECIES_TILE);
+        if (st) return st;
+    }
+    const size_t es = s->prec == SWE_FP32 ? sizeof(float) : sizeof(double);
+    const int nb = std::max(s->n_bc, 1);
+    s->Q0 = s->mem.alloc((size_t)ns * n * es);
+    s->Q1 = s->mem.alloc((size_t)ns * n * es);
+    s->phi_in = s->mem.alloc((size_t)ns * nb * es);
+    s->sslot_acc = (double *)s->mem.alloc(2 * sizeof(double) * (size_t)ns * std::max(s->nslots, 1));
+    s->sclip = (double *)s->mem.alloc(sizeof(double) * ns);
+    if (!s->Q0 || !s->Q1 || !s->phi_in || !s->sslot_acc || !s->sclip) {
+        s->drop_species();
+        return fail(SWE_ENOMEM, "device allocation failed (species)");
+    }
+    hipStream_t q = s->stream();
+    const void *cur = s->lvl().cur ? s->U1 : s->U0;
+    void *qcur = s->lvl().cur ? s->Q1 : s->Q0;
+    // q = h phi of the current state (0 in dry cells), in device order
+    auto up = [&](auto tag) -> swe_status {
+        using T = decltype(tag);
+        std::vector<V4<T>> u((size_t)n);
+        HIP_TRY(hipMemcpyAsync(u.data(), cur, u.size() * sizeof(V4<T>), hipMemcpyDeviceToHost, q));
+        HIP_TRY(hipStreamSynchronize(q));
+        std::vector<T> qh((size_t)ns * n), pin((size_t)ns * nb, T(0));
+        for (int c = 0; c < ns; c++)
+            for (int64_t i = 0; i < n; i++) {
+                const V4<T> &v = u[M.inv[i]];
+                const double h = double(v.x) - double(v.w);
+                const double p = phi0 ? phi0[(size_t)c * n + i] : 0.0;
+                qh[(size_t)c * n + M.inv[i]] = h > 0.0 ? T(h * p) : T(0);
+            }
+        for (int64_t k = 0; phi_in && k < (int64_t)ns * s->n_bc; k++) pin[k] = T(phi_in[k]);
+        HIP_TRY(hipMemcpyAsync(qcur, qh.data(), qh.size() * sizeof(T), hipMemcpyHostToDevice, q));
+        HIP_TRY(hipMemcpyAsync(s->phi_in, pin.data(), pin.size() * sizeof(T), hipMemcpyHostToDevice, q));
+        std::vector<double> z((size_t)2 * ns * std::max(s->nslots, 1), 0.0);
+        HIP_TRY(hipMemcpyAsync(s->sslot_acc, z.data(), z.size() * sizeof(double), hipMemcpyHostToDevice, q));
+        HIP_TRY(hipMemcpyAsync(s->sclip, z.data(), ns * sizeof(double), hipMemcpyHostToDevice, q));
+        HIP_TRY(hipStreamSynchronize(q));
+        return SWE_OK;
+    };
+    st = s->prec == SWE_FP32 ? up(float()) : up(double());
+    if (st) {
+        s->drop_species();
+        return st;
+    }
+    s->ns = ns;
+    s->bind_species();
+    return SWE_OK;
+}
+
+swe_status swe_state_set_sources(swe_state *s, const int32_t *cell_region, const swe_source *src, int32_t n_src) {
+    if (!s) return fail(SWE_EINVAL, "state is NULL");
+    if (n_src < 0 || n_src > MAX_BC) return fail(SWE_EINVAL, "between 0 and 64 sources");
+    if (n_src > 0 && (!cell_region || !src)) return fail(SWE_EINVAL, "bad source list");
+    const HostMesh &M = s->m->H;
+    const int64_t n = M.nc;
+    std::vector<BCdev> rec((size_t)std::max(n_src, 1));
+    std::vector<double> series;
+    std::vector<size_t> off((size_t)std::max(n_src, 1));
+    for (int r = 0; r < n_src; r++) {
+        const swe_source &X = src[r];
+        if (X.mode < SWE_SRC_EXACT || X.mode > SWE_SRC_INFINITY) return fail(SWE_EINVAL, "unknown source mode");
+        if (X.unit != SWE_SRC_DISCHARGE && X.unit != SWE_SRC_INTENSITY) return fail(SWE_EINVAL, "unknown source unit");
+        if (X.n_pts < 0 || (X.mode != SWE_SRC_INFINITY && (X.n_pts < 1 || !X.t || !X.v)))
+            return fail(SWE_EINVAL, "a source needs a series");
+        for (int k = 0; k < X.n_pts; k++) {
+            if (!std::isfinite(X.t[k]) || !std::isfinite(X.v[k])) return fail(SWE_EINVAL, "non-finite source series");
+            if (k > 0 && !(X.t[k] > X.t[k - 1])) return fail(SWE_EINVAL, "source times must increase");
+            if (X.mode == SWE_SRC_AVAILABLE && X.v[k] > 0.0) return fail(SWE_EINVAL, "only exact sources add water");
+        }
+        rec[r] = BCdev{X.mode, X.mode == SWE_SRC_INFINITY ? 0 : X.n_pts, 0.0, 0.0, nullptr, nullptr};
+        off[r] = series.size();
+        if (X.mode != SWE_SRC_INFINITY) {
+            series.insert(series.end(), X.t, X.t + X.n_pts);
+            series.insert(series.end(), X.v, X.v + X.n_pts);
+        }
+    }
+    std::vector<int> dcell((size_t)n, -1);
+    std::vector<std::vector<double>> areas((size_t)std::max(n_src, 1));
+    for (int64_t i = 0; n_src > 0 && i < n; i++) {
+        const int32_t r = cell_region[i];
+        if (r < -1 || r >= n_src) return fail(SWE_EINVAL, "source region out of range");
+        dcell[M.inv[i]] = r;
+        if (r >= 0) areas[r].push_back(M.area[M.inv[i]]);
+    }
+    // factor from a series value to a rate in m/s; region areas summed in
+    // ascending order, so the value does not depend on the numbering
+    for (int r = 0; r < n_src; r++) {
+        std::sort(areas[r].begin(), areas[r].end());
+        double A = 0.0;
+        for (double a : areas[r]) A += a;
+        if (src[r].unit == SWE_SRC_DISCHARGE) {
+            if (!(A > 0.0) && src[r].mode != SWE_SRC_INFINITY) return fail(SWE_EINVAL, "empty source region");
+            rec[r].length = A > 0.0 ? 1.0 / A : 0.0;
+        } else {
+            rec[r].length = 1.0 / 3.6e6;  // mm/h -> m/s
+        }
+    }
+    s->drop_graphs();
+    s->drop_sources();
+    if (n_src == 0) return SWE_OK;
+    const int tiles = (int)((n + 127) / 128);  // the most tiles any tile size gives
+    s->src_cell = (int *)s->mem.alloc(sizeof(int) * (size_t)n);
+    s->srcs = (BCdev *)s->mem.alloc(sizeof(BCdev) * (size_t)n_src);
+    s->src_series = (double *)s->mem.alloc(sizeof(double) * std::max<size_t>(series.size(), 1));
+    s->src_acc = (double *)s->mem.alloc(2 * sizeof(double) * (size_t)std::max(tiles, 1));
+    if (!s->src_cell || !s->srcs || !s->src_series || !s->src_acc) {
+        s->drop_sources();
+        return fail(SWE_ENOMEM, "device allocation failed (sources)");
+    }
+    for (int r = 0; r < n_src; r++)
+        if (rec[r].npts) {
+            rec[r].t = s->src_series + off[r];
+            rec[r].Q = s->src_series + off[r] + rec[r].npts;
+        }
+    hipStream_t q = s->stream();
+    std::vector<double> z((size_t)2 * std::max(tiles, 1), 0.0);
+    auto up = [&]() -> swe_status {
+        HIP_TRY(hipMemcpyAsync(s->src_cell, dcell.data(), sizeof(int) * dcell.size(), hipMemcpyHostToDevice, q));
+        HIP_TRY(hipMemcpyAsync(s->srcs, rec.data(), sizeof(BCdev) * (size_t)n_src, hipMemcpyHostToDevice, q));
+        if (!series.empty())
+            HIP_TRY(hipMemcpyAsync(s->src_series, series.data(), sizeof(double) * series.size(),
+                                   hipMemcpyHostToDevice, q));
+        HIP_TRY(hipMemcpyAsync(s->src_acc, z.data(), sizeof(double) * z.size(), hipMemcpyHostToDevice, q));
+        HIP_TRY(hipStreamSynchronize(q));
+        return SWE_OK;
+    };
+    swe_status st = up();
+    if (st) {
+        s->drop_sources();
+        return st;
+    }
+    s->nsrc = n_src;
+    s->src_tiles = tiles;
+    s->bind_sources();
+    return SWE_OK;
+}
+
+swe_status swe_source_volume(const swe_state *cs, double *volume) {
+    swe_state *s = const_cast<swe_state *>(cs);
+    if (!s) return fail(SWE_EINVAL, "state is NULL");
+    if (!volume) return SWE_OK;
+    *volume = 0.0;
+    if (s->nsrc == 0) return SWE_OK;
+    HIP_TRY(launch_pair_sum(s->src_acc, s->src_tiles, s->mass_out, s->stream()));
+    HIP_TRY(hipMemcpyAsync(s->hbuf + 1, s->mass_out, sizeof(double), hipMemcpyDeviceToHost, s->stream()));
+    HIP_TRY(hipStreamSynchronize(s->stream()));
+    *volume = s->hbuf[1];
+    return SWE_OK;
+}
+
+swe_status swe_state_read_scalars(const swe_state *cs, double *q) {
+    swe_state *s = const_cast<swe_state *>(cs);
+    if (!s) return fail(SWE_EINVAL, "state is NULL");
+    if (!q || s->ns == 0) return SWE_OK;
+    swe_status st = s->read_ctrl();
+    if (st) return st;
+    const HostMesh &M = s->m->H;
+    const int64_t n = M.nc;
+    const void *src = s->lvl().cur ? s->Q1 : s->Q0;
+    auto rd = [&](auto tag) -> swe_status {
+        using T = decltype(tag);
+        std::vector<T> v((size_t)s->ns * n);
+        HIP_TRY(hipMemcpyAsync(v.data(), src, v.size() * sizeof(T), hipMemcpyDeviceToHost, s->stream()));
+        HIP_TRY(hipStreamSynchronize(s->stream()));
+        for (int c = 0; c < s->ns; c++)
+            for (int64_t i = 0; i < n; i++) q[(size_t)c * n + i] = double(v[(size_t)c * n + M.inv[i]]);
+        return SWE_OK;
+    };
+    return s->prec == SWE_FP32 ? rd(float()) : rd(double());
+}
+
+swe_status swe_scalar_mass(const swe_state *cs, double *mass, double *bnd_flux, double *clipped) {
+    swe_state *s = const_cast<swe_state *>(cs);
+    if (!s) return fail(SWE_EINVAL, "state is NULL");
+    if (s->ns == 0) return SWE_OK;
+    hipStream_t q = s->stream();
+    for (int c = 0; c < s->ns; c++) {
+        if (s->prec == SWE_FP32)
+            HIP_TRY(launch_species_mass<float>(s->inst32, c, s->partials, s->mass_out, s->nslots, s->phase, q));
+        else
+            HIP_TRY(launch_species_mass<double>(s->inst64, c, s->partials, s->mass_out, s->nslots, s->phase, q));
+        HIP_TRY(hipMemcpyAsync(s->hbuf + 1, s->mass_out, 2 * sizeof(double), hipMemcpyDeviceToHost, q));
+        HIP_TRY(hipStreamSynchronize(q));
+        if (mass) mass[c] = s->hbuf[1];
+        if (bnd_flux) bnd_flux[c] = s->hbuf[2];
+    }
+    if (clipped) {
+        // hbuf holds 8 doubles; at most 5 species
+        HIP_TRY(hipMemcpyAsync(s->hbuf + 1, s->sclip, s->ns * sizeof(double), hipMemcpyDeviceToHost, q));
+        HIP_TRY(hipStreamSynchronize(q));
+        for (int c = 0; c < s->ns; c++) clipped[c] = s->hbuf[1 + c];
+    }
+    return SWE_OK;
+}
+
 swe_status swe_autotune(swe_state *s, int32_t k, int32_t *block_size, int32_t *cells_per_thread) {
     if (!s) return fail(SWE_EINVAL, "state is NULL");
+    if (s->ns > 0 || s->nsrc > 0) {
+        // the species-carrying step has one tile size; a state with sources
+        // keeps its tile (its source tally is kept per tile)
+        if (block_size) *block_size = s->tile;
+        if (cells_per_thread) *cells_per_thread = 1;
+        return SWE_OK;
+    }
     if (k < 1) k = 8;
     swe_status st = s->read_ctrl();
     if (st) return st;
@@ -894,6 +1168,8 @@ int64_t swe_batch_footprint(const swe_batch *b) { return b ? b->footprint() : 0;
 swe_status swe_batch_add(swe_batch *b, swe_state *s, double t_end, int32_t *slot) {
     if (!b || !s) return fail(SWE_EINVAL, "batch or state is NULL");
     if (s->prec != b->prec) return fail(SWE_EINVAL, "state precision differs from the batch");
+    if (s->ns > 0) return fail(SWE_EINVAL, "states with passive species are not batched");
+    if (s->nsrc > 0) return fail(SWE_EINVAL, "states with sources are not batched");
     if (s->stream() != b->stream()) return fail(SWE_EINVAL, "state and batch must use the same stream");
     if (std::isnan(t_end)) return fail(SWE_EINVAL, "t_end is NaN");
     for (auto *x : b->members)

@@ -163,27 +163,56 @@ __device__ __forceinline__ double hydrograph(const BCdev &b, double t) {
     return Qs[k] + w * (Qs[k + 1] - Qs[k]);
 }
 
-// Inflow uniform(Q, S): unit discharge q = Q / length entering with the
-// Manning normal depth (n q / sqrt(S))^(3/5) of the adjacent cell's n.
-// Returns false when Q <= 0 (the edge then behaves as a wall).
-__device__ __forceinline__ bool inflow_ghost(const BCdev &b, double t, double gn2, double g, double &hg,
-                                             double &ung) {
+// Ghost of the two discharge inflows (kind BC_INFLOW or BC_FROUDE): q = Q /
+// length enters at the depth x^p, x = n q / sqrt(S), p = 3/5 (uniform) or
+// x = q / (Fr sqrt(g)), p = 2/3 (froude).  One pow call serves both.
+__device__ __forceinline__ bool discharge_ghost(const BCdev &b, int kind, double t, double gn2, double g, double &hg,
+                                                double &ung) {
     double Q = hydrograph(b, t);
     if (!(Q > 0.0)) return false;
     double q = Q / b.length;
-    double n = sqrt(gn2 / g);
-    hg = pow(n * q / sqrt(b.slope), 0.6);
+    const bool unif = kind == BC_INFLOW;
+    double x = unif ? sqrt(gn2 / g) * q / sqrt(b.slope) : q / (b.slope * sqrt(g));
+    hg = pow(x, unif ? 0.6 : 2.0 / 3.0);
     ung = -q / hg;
     return true;
 }
-__device__ __forceinline__ bool inflow_ghost(const BCdev &b, double t, float gn2, float g, float &hg, float &ung) {
+__device__ __forceinline__ bool discharge_ghost(const BCdev &b, int kind, double t, float gn2, float g, float &hg,
+                                                float &ung) {
     const double Q = hydrograph(b, t);
     if (!(Q > 0.0)) return false;
     const float q = float(Q / b.length);
-    const float x = q * qsqrt(qdiv(gn2, g * float(b.slope)));  // n q / sqrt(S), n = sqrt(g n^2 / g)
-    hg = __builtin_amdgcn_exp2f(0.6f * __builtin_amdgcn_logf(x));
+    const bool unif = kind == BC_INFLOW;
+    const float x = unif ? q * qsqrt(qdiv(gn2, g * float(b.slope))) : qdiv(q, float(b.slope) * qsqrt(g));
+    hg = __builtin_amdgcn_exp2f((unif ? 0.6f : 2.0f / 3.0f) * __builtin_amdgcn_logf(x));
     ung = -qdiv(q, hg);
     return true;
+}
+
+// Normal depth (n q / sqrt(S))^(3/5) of a unit discharge q >= 0 under the
+// cell's power-law coefficient gn2 = g n^2 (uniform outflow).
+__device__ __forceinline__ double normal_depth(double gn2, double g, double q, double S) {
+    double n = sqrt(gn2 / g);
+    return pow(n * q / sqrt(S), 0.6);
+}
+__device__ __forceinline__ float normal_depth(float gn2, float g, float q, double S) {
+    const float x = q * qsqrt(qdiv(gn2, g * float(S)));
+    return x > 0.0f ? __builtin_amdgcn_exp2f(0.6f * __builtin_amdgcn_logf(x)) : 0.0f;
+}
+
+// Discharge per unit length leaving through a weir (Poleni's free overflow
+// (2/3) mu sqrt(2g) d^(3/2), head d over the crest, a crest below the cell's
+// bed counting at the bed) or an h-Q relation (Q(H) over the boundary
+// length), from the cell's surface H and bed z; zero for a dry cell.
+__device__ __forceinline__ double imposed_outflow(const BCdev &b, double H, double z, double g) {
+    if (!(H - z > 0.0)) return 0.0;
+    if (b.kind == BC_WEIR) {
+        const double crest = b.slope > z ? b.slope : z;
+        const double d = H - crest;
+        if (!(d > 0.0)) return 0.0;
+        return (2.0 / 3.0) * b.par * sqrt(2.0 * g) * (d * sqrt(d));
+    }
+    return hydrograph(b, H) / b.length;
 }
 
 __device__ __forceinline__ void neumaier(double &s, double &c, double v) {
@@ -401,6 +430,21 @@ template <typename T, int TILE> struct TileLds {
     GhostBits<T> ghost;
 };
 
+// LDS of the passive species of one tile (section "Scalar advection-
+// diffusion", advective part): per species the concentrations of the tile's
+// cells and the advective contribution of each (local edge, cell).
+template <typename T, int TILE, int NS> struct ScalarLds {
+    T phi[NS][TILE];
+    T c[NS][3][TILE];
+};
+
+// Concentration phi = q / h of a cell with water (q and h are carried by the
+// same mass flux, so thin films keep theirs), 0 in a dry one.
+__device__ __forceinline__ double concentration(double q, double h) { return h > 0.0 ? q / h : 0.0; }
+__device__ __forceinline__ float concentration(float q, double h) {
+    return h > 0.0 ? q * __builtin_amdgcn_rcpf(float(h)) : 0.0f;
+}
+
 // CFL term of an inflow ghost (depth hg, normal velocity ung) on an edge of
 // length l of a cell with ap = |cell| (FP64) or 1/|cell| (FP32), merged into
 // the tile's LDS word.
@@ -422,11 +466,17 @@ template <typename V> __device__ __forceinline__ void whole(V &s) {
 
 // Phases 0 and 1 for tile `tile`: fluxes at time t (UPDATE = false: geometry
 // only) and the inflow ghosts' CFL terms at time t_cand.  `own` receives the
-// state (H, qx, qy, z) of this thread's cell.
-template <typename T, int TILE, bool UPDATE>
+// state (H, qx, qy, z) of this thread's cell.  NS > 0: NS passive species
+// ride on the pass (SS, and qown for the cell's specific masses); each edge's
+// advective flux is the HLLC mass flux times the concentration of the cell
+// the water leaves.
+template <typename T, int TILE, bool UPDATE, int NS = 0>
 __device__ __forceinline__ void tile_edges(const Inst<T> &I, TileLds<T, TILE> &S, int tile, int cur, double t,
-                                           double dt, double t_cand, V4<T> &own) {
+                                           double dt, double t_cand, V4<T> &own,
+                                           ScalarLds<T, TILE, (NS > 0 ? NS : 1)> *SS = nullptr,
+                                           T *qown = nullptr) {
     const V4<T> *__restrict__ src = cur ? I.U1 : I.U0;
+    const T *__restrict__ qsrc = cur ? I.Q1 : I.Q0;
     const T g = T(I.g);
     const T hg2 = T(0.5) * g;  // g/2 of the hydrostatic pressure (g/2 h) h
     const double h_min = I.h_min;
@@ -448,6 +498,14 @@ __device__ __forceinline__ void tile_edges(const Inst<T> &I, TileLds<T, TILE> &S
         const bool wet = hd > h_min;
         const T h = T(hd);
         S.huvz[c] = make4<T>(s.x, wet ? qdiv(s.y, h) : T(0), wet ? qdiv(s.z, h) : T(0), s.w);
+        if constexpr (NS > 0) {
+#pragma unroll
+            for (int sp = 0; sp < NS; sp++) {
+                const T q = qsrc[(size_t)sp * I.n + i];
+                qown[sp] = q;
+                SS->phi[sp][c] = concentration(q, hd);
+            }
+        }
     }
     if (c == 0) S.ghost = ghost_init(T(0));
     __syncthreads();
@@ -480,10 +538,10 @@ __device__ __forceinline__ void tile_edges(const Inst<T> &I, TileLds<T, TILE> &S
         if (!UPDATE) {
             if (kind == EK_BOUNDARY) {
                 const int kbc = I.slot_kbc[I.ew1[e]];
-                if ((kbc & 15) == BC_INFLOW) {
+                if ((kbc & 15) == BC_INFLOW || (kbc & 15) == BC_FROUDE) {
                     const V2<T> cp = I.cellp[tile * TILE + a];
                     T hg, ung;
-                    if (inflow_ghost(I.bcs[kbc >> 4], t_cand, cp.y, g, hg, ung))
+                    if (discharge_ghost(I.bcs[kbc >> 4], kbc & 15, t_cand, cp.y, g, hg, ung))
                         ghost_cfl<T, TILE>(S, l, hg, ung, g, cp.x);
                 } else if ((kbc & 15) == BC_ZHYDRO) {
                     const double dg = hydrograph(I.bcs[kbc >> 4], t_cand) - double(S.huvz[a].w);
@@ -497,6 +555,13 @@ __device__ __forceinline__ void tile_edges(const Inst<T> &I, TileLds<T, TILE> &S
         T una, uta;
         rotate(sa.y, sa.z, nx, ny, una, uta);
         T F0, F1, F2, ha, hb = T(0);
+        T phib[NS > 0 ? NS : 1];  // other side's concentrations (edges leaving the tile)
+        // the two states handed to the Riemann solver (one call for every
+        // kind of edge keeps a single copy of the solver in the kernel)
+        T hL, unL, utL, hR, unR, utR;
+        int slot = 0, bi = 0;
+        bool open = false, inflow_on = false, imposed = false;
+        T qimp = T(0);  // weir or h-Q discharge
         if (kind != EK_BOUNDARY) {
             V4<T> sb;
             T ub, vb;
@@ -509,6 +574,10 @@ __device__ __forceinline__ void tile_edges(const Inst<T> &I, TileLds<T, TILE> &S
                 sb = src[I.ew1[e]];
                 whole(sb);
                 const double hbd = double(sb.x) - double(sb.w);
+                if constexpr (NS > 0) {
+#pragma unroll
+                    for (int sp = 0; sp < NS; sp++) phib[sp] = concentration(qsrc[(size_t)sp * I.n + I.ew1[e]], hbd);
+                }
                 const bool bwet = hbd > h_min;
                 const T hh = T(hbd);
                 ub = bwet ? qdiv(sb.y, hh) : T(0);
@@ -523,48 +592,80 @@ __device__ __forceinline__ void tile_edges(const Inst<T> &I, TileLds<T, TILE> &S
             hb = db < H_DRY ? T(0) : T(db);
             // canonical orientation (left = smaller original index); the
             // canonical normal is -n when a is the right cell
-            const T hL = flip ? hb : ha, hR = flip ? ha : hb;
-            const T unL = flip ? -unb : una, utL = flip ? -utb : uta;
-            const T unR = flip ? -una : unb, utR = flip ? -uta : utb;
-            hllc(hL, unL, utL, hR, unR, utR, g, F0, F1, F2);
-            if (flip) F0 = -F0;  // mass leaving a
+            hL = flip ? hb : ha;
+            hR = flip ? ha : hb;
+            unL = flip ? -unb : una;
+            utL = flip ? -utb : uta;
+            unR = flip ? -una : unb;
+            utR = flip ? -uta : utb;
         } else {
-            const int slot = I.ew1[e];
+            slot = I.ew1[e];
             const int kbc = I.slot_kbc[slot];
-            const int bkind = kbc & 15, bi = kbc >> 4;
+            const int bkind = kbc & 15;
+            bi = kbc >> 4;
             // the ghost shares a's bed, so z* = z and h* = H - z
-            const double da = double(sa.x) - double(sa.w);
+            const double zc = double(sa.w);
+            const double da = double(sa.x) - zc;
             ha = da < H_DRY ? T(0) : T(da);
+            // by default a reflective, impermeable wall: mirrored normal velocity
+            hL = ha;
+            unL = una;
+            utL = uta;
+            hR = ha;
+            unR = -una;
+            utR = uta;
             T hg, ung;
-            bool open = false;
-            if (bkind == BC_OUTFLOW) {
-                // transmissive: the ghost repeats the interior state
-                hllc(ha, una, uta, ha, una, uta, g, F0, F1, F2);
+            if (bkind == BC_OUTFLOW || (bkind == BC_DYNWALL && t >= I.bcs[bi].slope)) {
+                // transmissive (a dynamic wall after its collapse time too)
+                unR = una;
                 open = true;
-            } else if (bkind == BC_INFLOW) {
+            } else if (bkind == BC_INFLOW || bkind == BC_FROUDE) {
                 const V2<T> cp = I.cellp[tile * TILE + a];
-                if (inflow_ghost(I.bcs[bi], t, cp.y, g, hg, ung)) {
-                    const double dg = (double(sa.w) + double(hg)) - double(sa.w);
-                    const T hgs = dg < H_DRY ? T(0) : T(dg);
-                    hllc(ha, una, uta, hgs, ung, T(0), g, F0, F1, F2);
-                    open = true;
-                } else {
-                    hllc(ha, una, uta, ha, -una, uta, g, F0, F1, F2);
-                    F0 = T(0);
+                const BCdev &B = I.bcs[bi];
+                const bool on = discharge_ghost(B, bkind, t, cp.y, g, hg, ung);
+                if (on) {
+                    const double dg = (zc + double(hg)) - zc;
+                    hR = dg < H_DRY ? T(0) : T(dg);
+                    unR = ung;
+                    utR = T(0);
+                    open = inflow_on = true;
                 }
-                if (inflow_ghost(I.bcs[bi], t_cand, cp.y, g, hg, ung)) ghost_cfl<T, TILE>(S, l, hg, ung, g, cp.x);
+                const bool onc = discharge_ghost(B, bkind, t_cand, cp.y, g, hg, ung);
+                if (onc) ghost_cfl<T, TILE>(S, l, hg, ung, g, cp.x);
+            } else if (bkind == BC_UNIFORM_OUT) {
+                // the normal depth of the cell's outflowing unit discharge,
+                // with the cell's velocity
+                const T qn = T(da) * una;
+                hg = normal_depth(I.cellp[tile * TILE + a].y, g, qn > T(0) ? qn : T(0), I.bcs[bi].slope);
+                const double dg = (zc + double(hg)) - zc;
+                hR = dg < H_DRY ? T(0) : T(dg);
+                unR = una;
+                open = true;
+            } else if (bkind == BC_WEIR || bkind == BC_HQ) {
+                open = imposed = true;
+                qimp = T(imposed_outflow(I.bcs[bi], double(sa.x), zc, I.g));
             } else if (bkind == BC_ZHYDRO) {
                 // still water at the prescribed surface over a's bed
-                const double dg = hydrograph(I.bcs[bi], t) - double(sa.w);
-                const T hgs = dg < H_DRY ? T(0) : T(dg);
-                hllc(ha, una, uta, hgs, T(0), T(0), g, F0, F1, F2);
+                const double dg = hydrograph(I.bcs[bi], t) - zc;
+                hR = dg < H_DRY ? T(0) : T(dg);
+                unR = T(0);
+                utR = T(0);
                 open = true;
-                const double dc = hydrograph(I.bcs[bi], t_cand) - double(sa.w);
+                const double dc = hydrograph(I.bcs[bi], t_cand) - zc;
                 if (!(dc < H_DRY)) ghost_cfl<T, TILE>(S, l, T(dc), T(0), g, I.cellp[tile * TILE + a].x);
-            } else {
-                // reflective, impermeable wall: mirrored normal velocity
-                hllc(ha, una, uta, ha, -una, uta, g, F0, F1, F2);
-                F0 = T(0);
+            }
+        }
+        hllc(hL, unL, utL, hR, unR, utR, g, F0, F1, F2);
+        if (kind != EK_BOUNDARY) {
+            if (flip) F0 = -F0;  // mass leaving a
+        } else {
+            if (!open) F0 = T(0);  // no mass crosses a wall
+            if (imposed) {
+                // weir or h-Q: the boundary discharge leaves carrying the cell's state
+                const T q = qimp;
+                F0 = q;
+                F1 = (ha > T(0) ? q * qdiv(q, ha) : T(0)) + hg2 * ha * ha;
+                F2 = q * uta;
             }
             if (open) {
                 double *acc = I.slot_acc + 2 * slot;
@@ -572,6 +673,21 @@ __device__ __forceinline__ void tile_edges(const Inst<T> &I, TileLds<T, TILE> &S
                 neumaier(sm, cp, dt * double(l * F0));
                 acc[0] = sm;
                 acc[1] = cp;
+            }
+            if constexpr (NS > 0) {
+                // the ghost repeats a's concentration, except at an active inflow
+#pragma unroll
+                for (int sp = 0; sp < NS; sp++) {
+                    phib[sp] = inflow_on ? I.phi_in[bi * NS + sp] : SS->phi[sp][a];
+                    if (open) {
+                        const T A = F0 * (F0 >= T(0) ? SS->phi[sp][a] : phib[sp]);
+                        double *acc = I.sslot_acc + 2 * ((size_t)slot * NS + sp);
+                        double sm = acc[0], cp = acc[1];
+                        neumaier(sm, cp, dt * double(l * A));
+                        acc[0] = sm;
+                        acc[1] = cp;
+                    }
+                }
             }
         }
         // fluctuations: the flux minus each side's reconstructed pressure
@@ -584,6 +700,17 @@ __device__ __forceinline__ void tile_edges(const Inst<T> &I, TileLds<T, TILE> &S
         } else {
             S.c[1][ka][a] = l * (Da * nx - F2 * ny);
             S.c[2][ka][a] = l * (Da * ny + F2 * nx);
+        }
+        if constexpr (NS > 0) {
+            // advective species fluxes (F0 is the mass leaving a)
+            const int b = (E.w0 >> 17) & 1023;
+#pragma unroll
+            for (int sp = 0; sp < NS; sp++) {
+                const T pa = SS->phi[sp][a], pb = kind == EK_LOCAL ? SS->phi[sp][b] : phib[sp];
+                const T A = F0 * (F0 >= T(0) ? pa : pb);
+                SS->c[sp][ka][a] = l * A;
+                if (kind == EK_LOCAL) SS->c[sp][kb][b] = -(l * A);
+            }
         }
         if (kind == EK_LOCAL) {
             const int b = (E.w0 >> 17) & 1023;
@@ -643,10 +770,19 @@ __device__ __forceinline__ CandT<T> tile_candidate(const Inst<T> &I, const TileL
 }
 
 // Phase 2 for cell c of tile `tile`: update, friction, clip, write; returns
-// the CFL term of the new state.
-template <typename T, int TILE>
+// the CFL term of the new state.  NS > 0: the species' specific masses get
+// the same update from their advective contributions, and a cell the step
+// leaves without water keeps none (the change is tallied per species).
+// SRC: external sources and sinks add dt S_h to the continuity equation
+// (taken at time t) before the friction split; dvol receives the volume the
+// cell's source added (negative: removed), and a sink's removal leaves the
+// species' concentrations unchanged (added water carries none).
+template <typename T, int TILE, int NS = 0, bool SRC = false>
 __device__ __forceinline__ CandT<T> tile_update(const Inst<T> &I, const TileLds<T, TILE> &S, int tile, int cur,
-                                                double dt, const V4<T> &s) {
+                                                double dt, const V4<T> &s,
+                                                const ScalarLds<T, TILE, (NS > 0 ? NS : 1)> *SS = nullptr,
+                                                const T *qown = nullptr, double t = 0.0,
+                                                double *dvol = nullptr) {
     const int c = threadIdx.x;
     const int i = tile * TILE + c;
     if (i >= I.n) return IS32<T> ? T(0) : T(INFINITY);
@@ -670,6 +806,41 @@ __device__ __forceinline__ CandT<T> tile_update(const Inst<T> &I, const TileLds<
         qx = s.y - w * R1;
         qy = s.z - w * R2;
     }
+    double sfac = 1.0;  // fraction of the cell's water a sink left
+    bool has_src = false;
+    if constexpr (SRC) {
+        const int r = I.src_cell[i];
+        if (r >= 0) {
+            has_src = true;
+            const BCdev &B = I.srcs[r];
+            const double hf = double(Hn) - double(s.w);
+            const double avail = hf > 0.0 ? hf : 0.0;
+            double dh;
+            bool empty = false;
+            if (B.kind == SRC_INFINITY) {
+                dh = -avail;
+                empty = true;
+            } else {
+                dh = dt * (hydrograph(B, t) * B.length);
+                if (dh < -avail) {
+                    if (B.kind == SRC_AVAILABLE) {
+                        dh = -avail;
+                        empty = true;
+                    } else {
+                        atomicOr(&I.ctrl->flags, FLAG_SINK);
+                    }
+                }
+            }
+            if (empty) {
+                if (avail > 0.0) Hn = s.w;
+            } else {
+                Hn = T(double(Hn) + dh);
+            }
+            *dvol = dh * I.area[i];
+            const double h2 = double(Hn) - double(s.w);
+            sfac = (dh < 0.0 && hf > 0.0) ? (h2 > 0.0 ? h2 / hf : 0.0) : 1.0;
+        }
+    }
     const double hn = double(Hn) - double(s.w);
     // friction split
     T f;
@@ -690,19 +861,58 @@ __device__ __forceinline__ CandT<T> tile_update(const Inst<T> &I, const TileLds<
     }
     if (!isfinite(Hn) || !isfinite(qx) || !isfinite(qy)) atomicOr(&I.ctrl->flags, FLAG_NONFINITE);
     dst[i] = make4<T>(Hn, qx, qy, s.w);
+    if constexpr (NS > 0) {
+        T *__restrict__ qdst = cur ? I.Q0 : I.Q1;
+        const bool dry = !(double(Hn) - double(s.w) > 0.0);
+#pragma unroll
+        for (int sp = 0; sp < NS; sp++) {
+            const T R = SS->c[sp][0][c] + SS->c[sp][1][c] + SS->c[sp][2][c];
+            T q;
+            if constexpr (IS32<T>) {
+                q = fmaf(-(float(dt) * cp.x), R, qown[sp]);
+            } else {
+                q = qown[sp] - dt * (1.0 / cp.x) * R;
+            }
+            if (SRC && has_src) q = T(double(q) * sfac);
+            if (dry) {
+                atomicAdd(&I.sclip[sp], -double(q) * I.area[i]);
+                q = T(0);
+            }
+            if (!isfinite(q)) atomicOr(&I.ctrl->flags, FLAG_NONFINITE);
+            qdst[(size_t)sp * I.n + i] = q;
+        }
+    }
     return tile_candidate<T, TILE>(I, S, c, cp.x, Hn, qx, qy, s.w);
 }
 
 // Occupancy hint (minimum waves per SIMD): what the tile's LDS allows (FP32:
 // eight waves per SIMD, the most a SIMD holds; FP64: three, two at 512
 // cells), so the register budget matches it.  The persistent batched kernel
-// needs a few more registers and asks for seven FP32 waves.
+// needs more registers (its member parameters and every boundary kind) and
+// asks for six FP32 waves, the most it runs without spilling.
 template <typename T, int TILE>
 constexpr int WAVES_PER_SIMD = IS32<T> ? 8 : (TILE >= 512 ? 2 : 3);
 template <typename T, int TILE>
-constexpr int WAVES_PER_SIMD_BATCHED = IS32<T> ? 7 : (TILE >= 512 ? 2 : 3);
+constexpr int WAVES_PER_SIMD_BATCHED = IS32<T> ? 6 : (TILE >= 512 ? 2 : 3);
 
-template <typename T, int TILE>
+// Adds the tile's source volume (one value per thread) to the tile's
+// compensated accumulator: shuffle tree per wave, then the waves in order.
+template <int TILE>
+__device__ __forceinline__ void tile_source_tally(double *acc, double v) {
+    __shared__ double part[TILE / 64];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double sm = acc[0], cp = acc[1];
+        for (int w = 0; w < TILE / 64; w++) neumaier(sm, cp, part[w]);
+        acc[0] = sm;
+        acc[1] = cp;
+    }
+}
+
+template <typename T, int TILE, bool SRC = false>
 __global__ void __launch_bounds__(TILE, (WAVES_PER_SIMD<T, TILE>)) k_step(Inst<T> I, int phase) {
     __shared__ TileLds<T, TILE> S;
     const bool lead = blockIdx.x == 0;
@@ -711,7 +921,29 @@ __global__ void __launch_bounds__(TILE, (WAVES_PER_SIMD<T, TILE>)) k_step(Inst<T
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
     V4<T> own;
     tile_edges<T, TILE, true>(I, S, tile, L.cur, L.t, L.dt, L.t + L.dt, own);
-    CandT<T> cand = tile_update<T, TILE>(I, S, tile, L.cur, L.dt, own);
+    double dvol = 0.0;
+    CandT<T> cand = tile_update<T, TILE, 0, SRC>(I, S, tile, L.cur, L.dt, own, nullptr, nullptr, L.t, &dvol);
+    if constexpr (SRC) tile_source_tally<TILE>(I.src_acc + 2 * tile, dvol);
+    if (threadIdx.x == 0) cand = combine(cand, ghost_value(S.ghost));
+    block_finish(I.ctrl, phase, cand, L, lead, true);
+}
+
+// The step with NS passive species riding on the edge pass (tile of 256
+// cells; the species' LDS lowers the occupancy, so it is a kernel of its own).
+template <typename T, int TILE, int NS, bool SRC>
+__global__ void __launch_bounds__(TILE) k_step_species(Inst<T> I, int phase) {
+    __shared__ TileLds<T, TILE> S;
+    __shared__ ScalarLds<T, TILE, NS> SS;
+    const bool lead = blockIdx.x == 0;
+    const Level L = step_setup(I.ctrl, phase, I.cfl, I.dt_max, lead);
+    if (!L.run) return;
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    V4<T> own;
+    T qown[NS];
+    tile_edges<T, TILE, true, NS>(I, S, tile, L.cur, L.t, L.dt, L.t + L.dt, own, &SS, qown);
+    double dvol = 0.0;
+    CandT<T> cand = tile_update<T, TILE, NS, SRC>(I, S, tile, L.cur, L.dt, own, &SS, qown, L.t, &dvol);
+    if constexpr (SRC) tile_source_tally<TILE>(I.src_acc + 2 * tile, dvol);
     if (threadIdx.x == 0) cand = combine(cand, ghost_value(S.ghost));
     block_finish(I.ctrl, phase, cand, L, lead, true);
 }
@@ -796,6 +1028,45 @@ __global__ void __launch_bounds__(MASS_THREADS) k_mass_partial(Inst<T> I, double
     if (threadIdx.x == 0) partials[blockIdx.x] = r;
 }
 
+// Sum of n compensated pairs in a fixed order (one block).
+__global__ void __launch_bounds__(MASS_THREADS) k_pair_sum(const double *acc, int n, double *out) {
+    double2 a = make_double2(0.0, 0.0);
+    for (int k = threadIdx.x; k < n; k += MASS_THREADS) a = cadd(a, make_double2(acc[2 * k], acc[2 * k + 1]));
+    const double2 r = block_csum(a);
+    if (threadIdx.x == 0) out[0] = r.x + r.y;
+}
+
+// Species mass sum q |cell| in the same fixed order as the water volume.
+template <typename T>
+__global__ void __launch_bounds__(MASS_THREADS) k_species_mass_partial(Inst<T> I, int sp, double2 *partials,
+                                                                        int phase) {
+    const T *q = (I.ctrl->s[phase].cur ? I.Q1 : I.Q0) + (size_t)sp * I.n;
+    double s = 0.0, c = 0.0;
+    for (int i = blockIdx.x * MASS_THREADS + threadIdx.x; i < I.n; i += MASS_BLOCKS * MASS_THREADS)
+        neumaier(s, c, double(q[i]) * I.area[i]);
+    const double2 r = block_csum(make_double2(s, c));
+    if (threadIdx.x == 0) partials[blockIdx.x] = r;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(MASS_THREADS) k_species_mass_final(Inst<T> I, int sp, const double2 *partials,
+                                                                      int nslots, double *out) {
+    double2 acc = make_double2(0.0, 0.0);
+    for (int k = threadIdx.x; k < MASS_BLOCKS; k += MASS_THREADS) acc = cadd(acc, partials[k]);
+    double2 m = block_csum(acc);
+    __syncthreads();
+    double2 b = make_double2(0.0, 0.0);
+    for (int k = threadIdx.x; k < nslots; k += MASS_THREADS) {
+        const double *a = I.sslot_acc + 2 * ((size_t)k * I.ns + sp);
+        b = cadd(b, make_double2(a[0], a[1]));
+    }
+    double2 bs = block_csum(b);
+    if (threadIdx.x == 0) {
+        out[0] = m.x + m.y;
+        out[1] = bs.x + bs.y;
+    }
+}
+
 template <typename T>
 __global__ void __launch_bounds__(MASS_THREADS) k_mass_final(Inst<T> I, const double2 *partials, int nslots,
                                                              double *out) {
@@ -823,9 +1094,36 @@ __global__ void __launch_bounds__(MASS_THREADS) k_mass_final(Inst<T> I, const do
         default: return hipErrorInvalidValue;                                              \
     }
 
+template <typename T, bool SRC>
+hipError_t launch_species(const Inst<T> &I, int phase, hipStream_t s) {
+    const dim3 grid(I.ntiles), block(SPECIES_TILE);
+    switch (I.ns) {
+        case 1: hipLaunchKernelGGL((k_step_species<T, SPECIES_TILE, 1, SRC>), grid, block, 0, s, I, phase); break;
+        case 2: hipLaunchKernelGGL((k_step_species<T, SPECIES_TILE, 2, SRC>), grid, block, 0, s, I, phase); break;
+        case 3: hipLaunchKernelGGL((k_step_species<T, SPECIES_TILE, 3, SRC>), grid, block, 0, s, I, phase); break;
+        case 4: hipLaunchKernelGGL((k_step_species<T, SPECIES_TILE, 4, SRC>), grid, block, 0, s, I, phase); break;
+        case 5: hipLaunchKernelGGL((k_step_species<T, SPECIES_TILE, 5, SRC>), grid, block, 0, s, I, phase); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
 template <typename T>
 hipError_t launch_step(const Inst<T> &I, int tile, int phase, hipStream_t s) {
     if (I.n <= 0) return hipSuccess;
+    if (I.ns > 0) {
+        if (tile != SPECIES_TILE) return hipErrorInvalidValue;
+        return I.nsrc > 0 ? launch_species<T, true>(I, phase, s) : launch_species<T, false>(I, phase, s);
+    }
+    if (I.nsrc > 0) {
+        switch (tile) {
+            case 128: hipLaunchKernelGGL((k_step<T, 128, true>), dim3(I.ntiles), dim3(128), 0, s, I, phase); break;
+            case 256: hipLaunchKernelGGL((k_step<T, 256, true>), dim3(I.ntiles), dim3(256), 0, s, I, phase); break;
+            case 512: hipLaunchKernelGGL((k_step<T, 512, true>), dim3(I.ntiles), dim3(512), 0, s, I, phase); break;
+            default: return hipErrorInvalidValue;
+        }
+        return hipGetLastError();
+    }
     SWE_TILE_DISPATCH(tile, k_step, dim3(I.ntiles), dim3(tile), 0, s, I, phase)
     return hipGetLastError();
 }
@@ -842,6 +1140,22 @@ hipError_t launch_mass(const Inst<T> &I, double2 *partials, double *out, int nsl
     hipLaunchKernelGGL((k_mass_partial<T>), dim3(MASS_BLOCKS), dim3(MASS_THREADS), 0, s, I, partials, phase);
     hipLaunchKernelGGL((k_mass_final<T>), dim3(1), dim3(MASS_THREADS), 0, s, I, (const double2 *)partials, nslots,
                        out);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_species_mass(const Inst<T> &I, int sp, double2 *partials, double *out, int nslots, int phase,
+                               hipStream_t s) {
+    if (sp < 0 || sp >= I.ns) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((k_species_mass_partial<T>), dim3(MASS_BLOCKS), dim3(MASS_THREADS), 0, s, I, sp, partials,
+                       phase);
+    hipLaunchKernelGGL((k_species_mass_final<T>), dim3(1), dim3(MASS_THREADS), 0, s, I, sp,
+                       (const double2 *)partials, nslots, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_pair_sum(const double *acc, int n, double *out, hipStream_t s) {
+    hipLaunchKernelGGL(k_pair_sum, dim3(1), dim3(MASS_THREADS), 0, s, acc, n, out);
     return hipGetLastError();
 }
 
@@ -874,6 +1188,7 @@ hipError_t launch_step_batched(const Inst<T> *insts, const int2 *tiles, int ntil
     template hipError_t launch_step<T>(const Inst<T> &, int, int, hipStream_t);                             \
     template hipError_t launch_dt_init<T>(const Inst<T> &, int, int, hipStream_t);                          \
     template hipError_t launch_mass<T>(const Inst<T> &, double2 *, double *, int, int, hipStream_t);        \
+    template hipError_t launch_species_mass<T>(const Inst<T> &, int, double2 *, double *, int, int, hipStream_t); \
     template hipError_t launch_step_batched<T>(const Inst<T> *, const int2 *, int, int, int, int, hipStream_t); \
     template int batched_grid<T>(int);
 SWE_INSTANTIATE(float)

@@ -41,8 +41,20 @@ template <typename T> struct alignas(sizeof(T)) Edge {
 static_assert(sizeof(Edge<float>) == 12 && sizeof(Edge<double>) == 24, "edge record size");
 enum : int { EK_LOCAL = 0, EK_REMOTE = 1, EK_BOUNDARY = 2 };
 
-enum : int { BC_WALL = 0, BC_INFLOW = 1, BC_OUTFLOW = 2, BC_ZHYDRO = 3 };
-enum : int { FLAG_NONFINITE = 1, FLAG_NEGDEPTH = 2, FLAG_NODT = 4 };
+enum : int {
+    BC_WALL = 0,
+    BC_INFLOW = 1,
+    BC_OUTFLOW = 2,
+    BC_ZHYDRO = 3,
+    BC_FROUDE = 4,
+    BC_UNIFORM_OUT = 5,
+    BC_WEIR = 6,
+    BC_HQ = 7,
+    BC_DYNWALL = 8
+};
+enum : int { FLAG_NONFINITE = 1, FLAG_NEGDEPTH = 2, FLAG_NODT = 4, FLAG_SINK = 8 };
+// external source modes, numbered as SWE_SRC_* in swe.h
+enum : int { SRC_EXACT = 0, SRC_AVAILABLE = 1, SRC_INFINITY = 2 };
 // friction closures, numbered as SWE_FRICTION_* in swe.h
 enum : int { FR_MANNING = 0, FR_STRICKLER = 1, FR_CHEZY = 2, FR_BEZZOLA = 3 };
 constexpr int MAX_BC = 64;
@@ -51,10 +63,11 @@ constexpr int MAX_BC = 64;
 struct BCdev {
     int kind;
     int npts;
-    double slope;    // inflow energy slope
+    double slope;    // energy slope, Froude number, crest elevation or collapse time
     double length;   // summed length of the edges carrying this condition
-    const double *t; // series times
-    const double *Q; // discharge (inflow) or surface elevation (zhydrograph)
+    const double *t; // series times (surface elevations of an h-Q table)
+    const double *Q; // discharge, or surface elevation (zhydrograph)
+    double par;      // Poleni factor (weir)
 };
 
 // Per-state control block, triple-buffered by step phase p = step % 3.
@@ -108,7 +121,26 @@ template <typename T> struct Inst {
     double g, cfl, h_min, dt_max;
     int neg_policy;
     int friction;          // SWE_FRICTION_* closure
+    // passive species (ns = 0: none): specific masses q = h phi, [ns][n] per
+    // buffer (ping-pong with U), inflow concentrations [bc][ns], per boundary
+    // slot and species a Neumaier accumulator, per species the dry-reset tally
+    T *Q0;
+    T *Q1;
+    const T *phi_in;
+    double *sslot_acc;
+    double *sclip;
+    int ns;
+    // external water sources and sinks (nsrc = 0: none): per cell the
+    // region or -1, per region its record (kind = mode, length = factor from
+    // the series value to m/s), per tile a Neumaier accumulator of the volume
+    // they added
+    int nsrc;
+    const int *src_cell;
+    const BCdev *srcs;
+    double *src_acc;
 };
+constexpr int MAX_SPECIES = 5;
+constexpr int SPECIES_TILE = 256;  // tile size of the species-carrying step
 
 // Launch wrappers (kernels.hip).
 template <typename T>
@@ -117,6 +149,13 @@ template <typename T>
 hipError_t launch_dt_init(const Inst<T> &I, int tile, int phase, hipStream_t s);
 template <typename T>
 hipError_t launch_mass(const Inst<T> &I, double2 *partials, double *out, int nslots, int phase, hipStream_t s);
+// sum of n compensated pairs (sum, compensation) in a fixed order -> *out
+hipError_t launch_pair_sum(const double *acc, int n, double *out, hipStream_t s);
+// species sp: out[0] = sum q |cell| (compensated, fixed order), out[1] = mass
+// that left through open boundaries
+template <typename T>
+hipError_t launch_species_mass(const Inst<T> &I, int sp, double2 *partials, double *out, int nslots, int phase,
+                               hipStream_t s);
 template <typename T>
 hipError_t launch_step_batched(const Inst<T> *insts, const int2 *tiles, int ntiles, int grid, int tile, int phase,
                                hipStream_t s);

@@ -17,8 +17,9 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libswe.so")
 
-OK, EINVAL, ENOMEM, EDEVICE, ENONFINITE, ENEGDEPTH, EBUDGET, ENODT = 0, -1, -2, -3, -4, -5, -6, -7
-BC_WALL, BC_INFLOW_UNIFORM, BC_OUTFLOW_ZEROGRAD = 0, 1, 2
+OK, EINVAL, ENOMEM, EDEVICE, ENONFINITE, ENEGDEPTH, EBUDGET, ENODT, ESINK = 0, -1, -2, -3, -4, -5, -6, -7, -8
+BC_WALL, BC_INFLOW_UNIFORM, BC_OUTFLOW_ZEROGRAD, BC_ZHYDROGRAPH = 0, 1, 2, 3
+BC_INFLOW_FROUDE, BC_OUTFLOW_UNIFORM, BC_OUTFLOW_WEIR, BC_OUTFLOW_HQ, BC_DYNAMIC_WALL = 4, 5, 6, 7, 8
 FP64, FP32 = 0, 1
 NEG_CLIP, NEG_ERROR = 0, 1
 FRICTION = {"manning": 0, "strickler": 1, "chezy": 2, "bezzola": 3}
@@ -37,7 +38,12 @@ class SweDevice(ctypes.Structure):
 
 class SweBC(ctypes.Structure):
     _fields_ = [("tag", ctypes.c_int32), ("kind", ctypes.c_int32), ("slope", ctypes.c_double),
-                ("t", _dp), ("Q", _dp), ("n_pts", ctypes.c_int32)]
+                ("t", _dp), ("Q", _dp), ("n_pts", ctypes.c_int32), ("par", ctypes.c_double)]
+
+
+class SweSource(ctypes.Structure):
+    _fields_ = [("mode", ctypes.c_int32), ("unit", ctypes.c_int32), ("t", _dp), ("v", _dp),
+                ("n_pts", ctypes.c_int32)]
 
 
 class SweParams(ctypes.Structure):
@@ -68,6 +74,11 @@ SIGNATURES = {
     "swe_state_read": (ctypes.c_int32, [ctypes.c_void_p, _dp, _dp, _dp, _dp, _dp]),
     "swe_mass": (ctypes.c_int32, [ctypes.c_void_p, _dp, _dp, _dp, _lp]),
     "swe_autotune": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, _ip, _ip]),
+    "swe_state_set_scalars": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, _dp, _dp]),
+    "swe_state_read_scalars": (ctypes.c_int32, [ctypes.c_void_p, _dp]),
+    "swe_scalar_mass": (ctypes.c_int32, [ctypes.c_void_p, _dp, _dp, _dp]),
+    "swe_state_set_sources": (ctypes.c_int32, [ctypes.c_void_p, _ip, ctypes.POINTER(SweSource), ctypes.c_int32]),
+    "swe_source_volume": (ctypes.c_int32, [ctypes.c_void_p, _dp]),
     "swe_batch_create": (ctypes.c_int32, [ctypes.c_int32, ctypes.c_int64, ctypes.POINTER(SweDevice),
                                           ctypes.POINTER(ctypes.c_void_p)]),
     "swe_batch_destroy": (None, [ctypes.c_void_p]),
@@ -206,7 +217,7 @@ def _bc_array(bcs):
         t = None if b.t is None else np.ascontiguousarray(b.t, np.float64)
         Q = None if b.Q is None else np.ascontiguousarray(b.Q, np.float64)
         keep += [t, Q]
-        arr[k] = SweBC(b.tag, b.kind, b.slope, _d(t), _d(Q), 0 if t is None else len(t))
+        arr[k] = SweBC(b.tag, b.kind, b.slope, _d(t), _d(Q), 0 if t is None else len(t), getattr(b, "par", 0.0))
     return arr, keep
 
 
@@ -231,6 +242,57 @@ class State:
                                 ctypes.byref(h)))
         self._h = h
         self.n = mesh.n_cells
+        self.ns = 0
+        phi0 = getattr(sc, "phi0", None)
+        if phi0 is not None:
+            pin = np.zeros((len(sc.bcs), np.atleast_2d(phi0).shape[0]))
+            for b, bc in enumerate(sc.bcs):
+                if len(getattr(bc, "phi_in", ())):
+                    pin[b] = bc.phi_in
+            self.set_scalars(phi0, pin)
+        if len(getattr(sc, "sources", ())):
+            self.set_sources(sc.src_region, sc.sources)
+
+    def set_sources(self, region, sources):
+        """External water sources and sinks: region (cells,) indexes sources
+        (-1: none); each source has mode, unit, t, v."""
+        region = np.ascontiguousarray(region, np.int32)
+        arr = (SweSource * max(1, len(sources)))()
+        keep = [region]
+        for k, x in enumerate(sources):
+            t = None if x.t is None else np.ascontiguousarray(x.t, np.float64)
+            v = None if x.v is None else np.ascontiguousarray(x.v, np.float64)
+            keep += [t, v]
+            arr[k] = SweSource(x.mode, x.unit, _d(t), _d(v), 0 if t is None else len(t))
+        _check(load().swe_state_set_sources(self._h, _i(region), arr, len(sources)))
+
+    def source_volume(self):
+        """Volume the sources added since they were set (negative: removed)."""
+        v = ctypes.c_double()
+        _check(load().swe_source_volume(self._h, ctypes.byref(v)))
+        return v.value
+
+    def set_scalars(self, phi0, phi_in=None):
+        """Passive species with initial concentrations phi0 (species, cells)
+        and inflow concentrations phi_in (boundary conditions, species)."""
+        phi0 = np.ascontiguousarray(np.atleast_2d(phi0), np.float64)
+        ns = phi0.shape[0] if phi0.size else 0
+        pin = None if phi_in is None else np.ascontiguousarray(phi_in, np.float64)
+        _check(load().swe_state_set_scalars(self._h, ns, _d(phi0), _d(pin)))
+        self.ns = ns
+
+    def scalars(self):
+        """Specific masses q = h phi, (species, cells)."""
+        q = np.zeros((self.ns, self.n))
+        _check(load().swe_state_read_scalars(self._h, _d(q)))
+        return q
+
+    def scalar_mass(self):
+        """Per species: total mass, the mass that left through open
+        boundaries, and the mass set by resetting cells left dry."""
+        m, b, c = (np.zeros(max(self.ns, 1)) for _ in range(3))
+        _check(load().swe_scalar_mass(self._h, _d(m), _d(b), _d(c)))
+        return m[:self.ns], b[:self.ns], c[:self.ns]
 
     def step(self):
         dt = ctypes.c_double()

@@ -92,6 +92,12 @@ def lib():
                                          _c_int32_p, _c_double_p, _c_double_p, ctypes.c_char_p, ctypes.c_int]
         L.om_source_volume.restype = ctypes.c_double
         L.om_source_volume.argtypes = [ctypes.c_void_p]
+        L.om_sim_set_morpho.restype = ctypes.c_int
+        L.om_sim_set_morpho.argtypes = [ctypes.c_void_p, ctypes.c_int32] + [ctypes.c_double] * 6 + \
+            [_c_double_p, ctypes.c_char_p, ctypes.c_int]
+        L.om_get_bed.argtypes = [ctypes.c_void_p, _c_double_p]
+        L.om_morpho_diag.argtypes = [ctypes.c_void_p, _c_double_p, _c_double_p, _c_double_p]
+        L.om_sed_cell.argtypes = [ctypes.c_int32] + [ctypes.c_double] * 12 + [_c_double_p] * 4
         L.om_sim_set_friction.restype = ctypes.c_int
         L.om_sim_set_friction.argtypes = [ctypes.c_void_p, ctypes.c_int32, _c_double_p, ctypes.c_char_p, ctypes.c_int]
         _lib = L
@@ -126,6 +132,15 @@ def friction_factor(qabs, h, gn2, dt, h_min=1e-4):
 
 # friction closures of Table friction_closure, by name
 FRICTION = {"manning": 0, "strickler": 1, "chezy": 2, "bezzola": 3}
+SED = {"mpm": 0, "grass": 1, "eh": 2}
+
+
+def sed_cell(closure, alpha, m, thr, d_m, s_rel, g, h, u, v, cf2, nx, ny):
+    """(q_B.n, dq_B,n/dq_n, lambda_1, lambda_2) of one cell."""
+    out = [ctypes.c_double() for _ in range(4)]
+    lib().om_sed_cell(SED[closure], alpha, m, thr, d_m, s_rel, g, h, u, v, cf2, nx, ny,
+                      *[ctypes.byref(o) for o in out])
+    return tuple(o.value for o in out)
 
 
 def friction_cf(kind, par, h):
@@ -224,6 +239,29 @@ class Sim:
             self.ns = ns
         if len(getattr(sc, "sources", ())):
             self.set_sources(sc.src_region, sc.sources)
+        if getattr(sc, "morpho", None) is not None:
+            self.set_morpho(sc.morpho)
+
+    def set_morpho(self, mo):
+        """Exner module with the closure and parameters of mo (swe_inputs.Morpho)."""
+        zr = None if mo.z_rel is None else np.ascontiguousarray(mo.z_rel, np.float64)
+        self._keep.append(zr)
+        err = ctypes.create_string_buffer(256)
+        if lib().om_sim_set_morpho(self._p, SED[mo.closure], mo.alpha, mo.m, mo.thr, mo.d_m, mo.s_rel,
+                                   mo.porosity, _dp(zr), err, 256):
+            raise OracleError(err.value.decode())
+
+    def bed(self):
+        z = np.zeros(self.n)
+        lib().om_get_bed(self._p, _dp(z))
+        return z
+
+    def morpho_diag(self):
+        """Sediment volume (1 - p) sum z |cell|, the volume that left through
+        open boundaries, and the volume the fixed-bed clip added."""
+        v, b, c = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+        lib().om_morpho_diag(self._p, ctypes.byref(v), ctypes.byref(b), ctypes.byref(c))
+        return v.value, b.value, c.value
 
     def set_sources(self, region, sources):
         """External water sources and sinks: region (cells,) -> index into

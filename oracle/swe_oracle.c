@@ -50,6 +50,7 @@ struct om_sim {
     const om_mesh *m;
     double g, cfl, h_min, dt_max;
     double *H, *qx, *qy;
+    double *z;           /* cell bed elevation (the mesh's, moved by the Exner module) */
     int32_t fkind;       /* friction closure (OM_MANNING ... OM_BEZZOLA) */
     double *gn2;         /* per cell: g n^2 (Manning), g / k^2 (Strickler), K_s (Chezy), y_R (Bezzola) */
     double t;
@@ -74,6 +75,15 @@ struct om_sim {
     int32_t *csrc;
     double *sfac;        /* per cell: fraction of its water a sink left (species follow it) */
     double ssum, scomp;  /* Neumaier sum of the volume the sources added (negative: removed) */
+    /* morphodynamics (Exner): closure and its parameters, porosity, the
+     * non-erodible bed per cell, the per-(cell, local edge) bed
+     * contributions l q_B, and the sediment tallies */
+    int morpho;
+    int32_t sclos;
+    double salpha, sm, sthr, sd, srel, spor;
+    double *zfix, *bcont;
+    double bvsum, bvcomp;    /* sediment volume that left through open boundaries */
+    double bclip, bclipc;    /* sediment volume added by the fixed-bed clip */
 };
 
 static void seterr(char *err, int len, const char *msg) {
@@ -280,10 +290,11 @@ void om_mesh_geometry(const om_mesh *m, double *area, double *zb, double *rho3, 
 void om_sim_free(om_sim *s) {
     if (!s) return;
     for (int b = 0; b < s->nbc; b++) { free(s->bc[b].t); free(s->bc[b].Q); }
-    free(s->bc); free(s->ebc); free(s->H); free(s->qx); free(s->qy); free(s->gn2); free(s->cont);
+    free(s->z); free(s->bc); free(s->ebc); free(s->H); free(s->qx); free(s->qy); free(s->gn2); free(s->cont);
     free(s->sq); free(s->sphi); free(s->scont); free(s->phi_in);
     for (int r = 0; r < s->nsrc; r++) { free(s->src[r].t); free(s->src[r].Q); }
     free(s->src); free(s->csrc); free(s->sfac);
+    free(s->zfix); free(s->bcont);
     free(s);
 }
 
@@ -303,12 +314,14 @@ om_sim *om_sim_new(const om_mesh *m, double g, double cfl, double h_min, double 
     if (!(g > 0) || !(cfl > 0 && cfl <= 1) || !(h_min > 0) || !(dt_max > 0) || !isfinite(t0)) {
         seterr(err, elen, "bad parameters"); goto fail;
     }
+    s->z = malloc(sizeof(double) * (nc > 0 ? nc : 1));
+    if (s->z) memcpy(s->z, m->zb, sizeof(double) * nc);
     s->H = malloc(sizeof(double) * nc); s->qx = malloc(sizeof(double) * nc);
     s->qy = malloc(sizeof(double) * nc); s->gn2 = malloc(sizeof(double) * nc);
     s->cont = malloc(sizeof(double) * 9 * nc);
     s->ebc = malloc(sizeof(int32_t) * m->ne);
     s->bc = calloc((size_t)(nbc > 0 ? nbc : 1), sizeof(om_bc));
-    if (!s->H || !s->qx || !s->qy || !s->gn2 || !s->cont || !s->ebc || !s->bc) {
+    if (!s->z || !s->H || !s->qx || !s->qy || !s->gn2 || !s->cont || !s->ebc || !s->bc) {
         seterr(err, elen, "out of memory"); goto fail;
     }
     for (int64_t i = 0; i < nc; i++) {
@@ -523,6 +536,162 @@ static double imposed_outflow(const om_sim *s, const om_bc *B, double H, double 
     return hydrograph(B, H) / B->length;
 }
 
+/* ---------------------------------------------------------------------------
+ * Morphodynamics (section "Morphodynamics": eq. exner; numerics: eq.
+ * exnerupdateformula with the HLL sediment flux eq. exner_hll, speeds eq.
+ * exner_wave_assign and eq. exner_wave_estimation; closures of Table
+ * sedtransport_closure).  Synchronous-decoupled: the bed moves with the
+ * hydrodynamic dt, from the state at t^n.  Readings:
+ *  - Shields parameter theta = |u|^2 / (c_f^2 (s-1) g d_m) with the cell's
+ *    friction closure (u_* = |u| / c_f); frictionless or dry cells (h <=
+ *    h_min) and cells at their non-erodible bed carry no sediment;
+ *  - the transport is aligned with the flow: q_B = Phi(|u|) u / |u|;
+ *  - dq_B,n / dq_n is taken at fixed depth and fixed tangential velocity:
+ *    (Phi'(|u|) cos^2 a + Phi(|u|) / |u| sin^2 a) / h, cos a = u_n / |u|;
+ *  - walls carry no sediment; open hydrodynamic edges carry the cell's own
+ *    normal transport (zero gradient of the bed and of the transport);
+ *  - the water depth is kept when the bed moves (H += z^{n+1} - z^n);
+ *  - a bed update below the non-erodible bed is clipped to it and the
+ *    sediment volume so added is tallied;
+ *  - when both HLL speeds vanish the flux is the mean of the two normal
+ *    transports.
+ * ------------------------------------------------------------------------ */
+static double sed_K(double d, double srel, double g) { return sqrt((srel - 1.0) * g * d * d * d); }
+
+/* transport magnitude Phi(|u|) and dPhi/d|u| at fixed depth */
+static void sed_mag(int32_t clos, double alpha, double mexp, double thr, double d, double srel, double g,
+                    double umag, double cf2, double *phi, double *dphi) {
+    *phi = 0.0;
+    *dphi = 0.0;
+    if (!(umag > 0.0)) return;
+    if (clos == OM_SED_GRASS) {
+        double e = umag - thr;
+        if (e > 0.0) {
+            *phi = alpha * pow(e, mexp);
+            *dphi = alpha * mexp * pow(e, mexp - 1.0);
+        }
+        return;
+    }
+    if (!(cf2 > 0.0)) return;
+    double theta = umag * umag / (cf2 * ((srel - 1.0) * g * d));
+    double K = sed_K(d, srel, g);
+    if (clos == OM_SED_MPM) {
+        double e = theta - thr;
+        if (e > 0.0) {
+            *phi = alpha * pow(e, mexp) * K;
+            *dphi = alpha * mexp * pow(e, mexp - 1.0) * K * (2.0 * theta / umag);
+        }
+    } else {
+        *phi = 0.05 * cf2 * pow(theta, 2.5) * K;
+        *dphi = 5.0 * *phi / umag;
+    }
+}
+
+/* Normal transport q_B.n, its derivative dq_B,n/dq_n and the two speeds
+ * lambda_1 <= 0 <= lambda_2 of one cell for the unit normal (nx, ny). */
+void om_sed_cell(int32_t clos, double alpha, double mexp, double thr, double d, double srel, double g, double h,
+                 double u, double v, double cf2, double nx, double ny, double *qbn, double *D, double *l1,
+                 double *l2) {
+    double umag = sqrt(u * u + v * v);
+    double phi, dphi;
+    sed_mag(clos, alpha, mexp, thr, d, srel, g, umag, cf2, &phi, &dphi);
+    double un = u * nx + v * ny;
+    double dd = 0.0, qn = 0.0;
+    if (phi > 0.0 && h > 0.0) {
+        double ca = un / umag;
+        qn = phi * ca;
+        dd = (dphi * (ca * ca) + (phi / umag) * (1.0 - ca * ca)) / h;
+    }
+    double c = sqrt(g * (h > 0.0 ? h : 0.0));
+    double a = un - c;
+    double r = sqrt(a * a + 4.0 * dd * (c * c));
+    *qbn = qn;
+    *D = dd;
+    *l1 = 0.5 * (a - r);
+    *l2 = 0.5 * (a + r);
+}
+
+static double cell_cf2(const om_sim *s, int64_t i, double h) {
+    double par = s->gn2[i];
+    if (!(par > 0.0)) return 0.0;
+    if (s->fkind == OM_MANNING || s->fkind == OM_STRICKLER) return cbrt(h) / par;  /* h^(1/3) / (g n^2) */
+    double cf = om_friction_cf(s->fkind, par, h);
+    return cf * cf;
+}
+
+static void sed_state(const om_sim *s, int64_t i, double nx, double ny, double *qbn, double *l1, double *l2) {
+    double h = s->H[i] - s->z[i];
+    double u = 0.0, v = 0.0, cf2 = 0.0;
+    int moves = h > s->h_min && !(s->zfix && s->z[i] <= s->zfix[i]);
+    if (h > s->h_min) { u = s->qx[i] / h; v = s->qy[i] / h; }
+    if (moves) cf2 = cell_cf2(s, i, h);
+    double D;
+    om_sed_cell(moves ? s->sclos : OM_SED_MPM, moves ? s->salpha : 0.0, s->sm, s->sthr, s->sd, s->srel, s->g, h, u,
+                v, moves ? cf2 : 0.0, nx, ny, qbn, &D, l1, l2);
+}
+
+/* Bed contributions of one edge (n from L to R, outward of L). */
+static void sed_edge(om_sim *s, int32_t L, int32_t R, int kL, int kR, double l, double nx, double ny, int open,
+                     double dt, double *bst, double *bstc) {
+    double qL, l1L, l2L;
+    sed_state(s, L, nx, ny, &qL, &l1L, &l2L);
+    double q;
+    if (R >= 0) {
+        double qR, l1R, l2R;
+        sed_state(s, R, nx, ny, &qR, &l1R, &l2R);
+        double lm = l1L < l1R ? l1L : l1R;
+        double lp = l2L > l2R ? l2L : l2R;
+        if (lp > lm) q = (lp * qL - lm * qR + lp * lm * (s->z[R] - s->z[L])) / (lp - lm);
+        else q = 0.5 * (qL + qR);
+        s->bcont[3 * L + kL] = l * q;
+        s->bcont[3 * R + kR] = -(l * q);
+    } else {
+        q = open ? qL : 0.0;
+        s->bcont[3 * L + kL] = l * q;
+        if (open) neumaier(bst, bstc, dt * (l * q));
+    }
+}
+
+int om_sim_set_morpho(om_sim *s, int32_t clos, double alpha, double mexp, double thr, double d, double srel,
+                      double porosity, const double *z_rel, char *err, int elen) {
+    const om_mesh *m = s->m;
+    free(s->zfix); free(s->bcont);
+    s->zfix = NULL; s->bcont = NULL; s->morpho = 0;
+    s->bvsum = s->bvcomp = s->bclip = s->bclipc = 0.0;
+    if (clos < 0) return 0;
+    if (clos > OM_SED_EH) { seterr(err, elen, "unknown sediment transport closure"); return -1; }
+    if (!(alpha >= 0) || !isfinite(alpha) || !(mexp > 0) || !isfinite(mexp) || !(thr >= 0) || !isfinite(thr) ||
+        !(d > 0) || !isfinite(d) || !(srel > 1) || !isfinite(srel) || !(porosity >= 0 && porosity < 1)) {
+        seterr(err, elen, "bad sediment parameters"); return -1;
+    }
+    s->bcont = calloc((size_t)(3 * m->nc + 1), sizeof(double));
+    if (!s->bcont) { seterr(err, elen, "out of memory"); return -1; }
+    if (z_rel) {
+        s->zfix = malloc(sizeof(double) * (size_t)(m->nc > 0 ? m->nc : 1));
+        if (!s->zfix) { seterr(err, elen, "out of memory"); return -1; }
+        for (int64_t i = 0; i < m->nc; i++) {
+            if (!(z_rel[i] <= 0.0)) { seterr(err, elen, "the fixed bed lies at or below the bed (z_rel <= 0)"); return -1; }
+            s->zfix[i] = s->z[i] + z_rel[i];
+        }
+    }
+    s->sclos = clos; s->salpha = alpha; s->sm = mexp; s->sthr = thr; s->sd = d; s->srel = srel; s->spor = porosity;
+    s->morpho = 1;
+    return 0;
+}
+
+void om_get_bed(const om_sim *s, double *z) { memcpy(z, s->z, sizeof(double) * (size_t)s->m->nc); }
+
+/* Sediment volume (1 - p) sum z |Omega| (Neumaier), the volume that left
+ * through open boundaries, and the volume the fixed-bed clip added: the
+ * balance reads V(t) = V(0) - bnd + clipped. */
+void om_morpho_diag(const om_sim *s, double *vol, double *bnd, double *clipped) {
+    double sum = 0.0, comp = 0.0;
+    for (int64_t i = 0; i < s->m->nc; i++) neumaier(&sum, &comp, (1.0 - s->spor) * s->z[i] * s->m->area[i]);
+    if (vol) *vol = sum + comp;
+    if (bnd) *bnd = s->bvsum + s->bvcomp;
+    if (clipped) *clipped = s->bclip + s->bclipc;
+}
+
 /* Inflow "uniform(discharge, slope)" (section "Hydrodynamic BCs"): the given
  * discharge is spread over the boundary length; reading: the ghost carries
  * the Manning normal depth for that unit discharge, q = h^{5/3} sqrt(S) / n,
@@ -651,7 +820,7 @@ int om_sim_set_friction(om_sim *s, int32_t kind, const double *par, char *err, i
 }
 
 static void cell_velocity(const om_sim *s, int32_t i, double *h, double *u, double *v) {
-    *h = s->H[i] - s->m->zb[i];
+    *h = s->H[i] - s->z[i];
     if (*h > s->h_min) { *u = s->qx[i] / *h; *v = s->qy[i] / *h; }
     else { *u = 0.0; *v = 0.0; }
 }
@@ -701,7 +870,7 @@ double om_next_dt(const om_sim *s, double t_end) {
         if (s->ebc[e] < 0) continue;
         const om_bc *B = &s->bc[s->ebc[e]];
         if (B->kind != OM_ZHYDROGRAPH) continue;
-        double hg = hydrograph(B, s->t) - m->zb[m->eL[e]];
+        double hg = hydrograph(B, s->t) - s->z[m->eL[e]];
         if (hg < OM_H_DRY) continue;
         double r = m->rho[3 * m->eL[e] + m->ekL[e]] / sqrt(s->g * hg);
         if (r < best) best = r;
@@ -742,7 +911,7 @@ int om_sim_set_scalars(om_sim *s, int32_t ns, const double *phi0, const double *
         for (int64_t i = 0; i < nc; i++) {
             double p = phi0 ? phi0[c * nc + i] : 0.0;
             if (!isfinite(p)) { seterr(err, elen, "non-finite initial concentration"); return -1; }
-            double h = s->H[i] - m->zb[i];
+            double h = s->H[i] - s->z[i];
             s->sq[c * nc + i] = h > 0.0 ? h * p : 0.0;
         }
         for (int b = 0; b < s->nbc; b++) {
@@ -803,11 +972,12 @@ int om_step(om_sim *s, double t_end, double *dt_taken) {
     memset(s->cont, 0, sizeof(double) * 9 * (size_t)m->nc);
     double bstep = 0.0, bstepc = 0.0;
     int deficit = 0;   /* an exact sink asked for more water than a cell held */
+    double bvst = 0.0, bvstc = 0.0;   /* sediment leaving through open boundaries this step */
     double sbst[OM_MAX_SPECIES] = {0}, sbstc[OM_MAX_SPECIES] = {0};
     for (int c = 0; c < s->ns; c++) {
         /* concentrations of the state at t^n (zero in dry cells) */
         for (int64_t i = 0; i < m->nc; i++) {
-            double h = s->H[i] - m->zb[i];
+            double h = s->H[i] - s->z[i];
             s->sphi[c * m->nc + i] = h > 0.0 ? s->sq[c * m->nc + i] / h : 0.0;
         }
     }
@@ -817,13 +987,13 @@ int om_step(om_sim *s, double t_end, double *dt_taken) {
         double nx = m->enx[e], ny = m->eny[e], l = m->elen[e];
         double hL, uL, vL, hR, uR, vR;
         cell_velocity(s, L, &hL, &uL, &vL);
-        double HL = s->H[L], zL = m->zb[L];
+        double HL = s->H[L], zL = s->z[L];
         double unL = uL * nx + vL * ny, utL = -uL * ny + vL * nx;
         double HR, zR, unR, utR;
         int wall = 0, open = 0, inflow_b = -1, imposed = 0;
         if (R >= 0) {
             cell_velocity(s, R, &hR, &uR, &vR);
-            HR = s->H[R]; zR = m->zb[R];
+            HR = s->H[R]; zR = s->z[R];
             unR = uR * nx + vR * ny; utR = -uR * ny + vR * nx;
         } else {
             int b = s->ebc[e];
@@ -901,6 +1071,8 @@ int om_step(om_sim *s, double t_end, double *dt_taken) {
         }
         if (s->ns > 0)
             scalar_edge(s, L, R, kL, R >= 0 ? m->ekR[e] : 0, l, F[0], wall, inflow_b, open, dt, sbst, sbstc);
+        if (s->morpho)
+            sed_edge(s, L, R, kL, R >= 0 ? m->ekR[e] : 0, l, nx, ny, open, dt, &bvst, &bvstc);
     }
     for (int64_t i = 0; i < m->nc; i++) {
         const double *c = &s->cont[9 * i];
@@ -914,7 +1086,7 @@ int om_step(om_sim *s, double t_end, double *dt_taken) {
         if (s->csrc && s->csrc[i] >= 0) {
             /* external source or sink, explicit in the continuity equation */
             const om_bc *B = &s->src[s->csrc[i]];
-            double hf = H - m->zb[i];
+            double hf = H - s->z[i];
             double avail = hf > 0.0 ? hf : 0.0;
             double dh;
             int empty = 0;
@@ -928,13 +1100,13 @@ int om_step(om_sim *s, double t_end, double *dt_taken) {
                     else deficit = 1;
                 }
             }
-            if (empty) { if (avail > 0.0) H = m->zb[i]; }
+            if (empty) { if (avail > 0.0) H = s->z[i]; }
             else H = H + dh;
             neumaier(&s->ssum, &s->scomp, dh * m->area[i]);
-            double hn = H - m->zb[i];
+            double hn = H - s->z[i];
             s->sfac[i] = (dh < 0.0 && hf > 0.0) ? (hn > 0.0 ? hn / hf : 0.0) : 1.0;
         }
-        double h = H - m->zb[i];
+        double h = H - s->z[i];
         double f = om_friction_closure(s->fkind, s->gn2[i], sqrt(qx * qx + qy * qy), h, dt, s->h_min);
         qx = qx * f;
         qy = qy * f;
@@ -943,7 +1115,7 @@ int om_step(om_sim *s, double t_end, double *dt_taken) {
              * cell draining through several edges; clip and account for it */
             double add = -h * m->area[i];
             neumaier(&s->clip, &s->clipc, add);
-            H = m->zb[i];
+            H = s->z[i];
             qx = 0.0; qy = 0.0;
         }
         if (!isfinite(H) || !isfinite(qx) || !isfinite(qy)) return -4;
@@ -960,7 +1132,7 @@ int om_step(om_sim *s, double t_end, double *dt_taken) {
             if (s->csrc && s->csrc[i] >= 0) q[i] = q[i] * s->sfac[i];
             /* a cell left without water keeps no scalar (the positivity
              * clip of the water, step 6, is mirrored here and tallied) */
-            if (!(s->H[i] - m->zb[i] > 0.0)) {
+            if (!(s->H[i] - s->z[i] > 0.0)) {
                 neumaier(&s->sclip[c], &s->sclipc[c], -q[i] * m->area[i]);
                 q[i] = 0.0;
             }
@@ -969,6 +1141,22 @@ int om_step(om_sim *s, double t_end, double *dt_taken) {
         neumaier(&s->sbsum[c], &s->sbcomp[c], sbst[c] + sbstc[c]);
     }
     neumaier(&s->bsum, &s->bcomp, bstep + bstepc);
+    if (s->morpho) {
+        /* eq. exnerupdateformula; the water depth is kept as the bed moves */
+        for (int64_t i = 0; i < m->nc; i++) {
+            const double *k = s->bcont + 3 * i;
+            double Rz = k[0] + k[1] + k[2];
+            double w = dt * (1.0 / m->area[i]);
+            double zn = s->z[i] - (w * Rz) / (1.0 - s->spor);
+            if (s->zfix && zn < s->zfix[i]) {
+                neumaier(&s->bclip, &s->bclipc, (1.0 - s->spor) * (s->zfix[i] - zn) * m->area[i]);
+                zn = s->zfix[i];
+            }
+            s->H[i] = s->H[i] + (zn - s->z[i]);
+            s->z[i] = zn;
+        }
+        neumaier(&s->bvsum, &s->bvcomp, bvst + bvstc);
+    }
     s->t += dt;
     s->steps++;
     return deficit ? -8 : 0;
@@ -1009,7 +1197,7 @@ void om_set_state(om_sim *s, const double *H, const double *qx, const double *qy
 void om_diag(const om_sim *s, double *mass, double *bnd, double *clipped, int64_t *steps) {
     double sum = 0.0, comp = 0.0;
     for (int64_t i = 0; i < s->m->nc; i++)
-        neumaier(&sum, &comp, (s->H[i] - s->m->zb[i]) * s->m->area[i]);
+        neumaier(&sum, &comp, (s->H[i] - s->z[i]) * s->m->area[i]);
     if (mass) *mass = sum + comp;
     if (bnd) *bnd = s->bsum + s->bcomp;
     if (clipped) *clipped = s->clip + s->clipc;

@@ -80,6 +80,21 @@ enum { OM_SRC_DISCHARGE = 0, OM_SRC_INTENSITY = 1 };
 int om_sim_set_sources(om_sim *s, const int32_t *cell_src, int32_t n_src, const int32_t *mode,
                        const int32_t *unit, const int32_t *npts, const double *t, const double *v, char *err,
                        int err_len);
+/* morphodynamics (Exner, HLL sediment flux): closure OM_SED_* with its
+ * alpha, exponent m and threshold (theta_cr, or u_cr for GRASS), grain
+ * diameter d_m, relative density s, porosity p; z_rel[nc] (<= 0, NULL =
+ * none) puts a non-erodible bed below the initial bed.  closure < 0
+ * switches it off.  0 or -1. */
+enum { OM_SED_MPM = 0, OM_SED_GRASS = 1, OM_SED_EH = 2 };
+int om_sim_set_morpho(om_sim *s, int32_t closure, double alpha, double m, double thr, double d_m, double s_rel,
+                      double porosity, const double *z_rel, char *err, int err_len);
+void om_get_bed(const om_sim *s, double *z);
+void om_morpho_diag(const om_sim *s, double *volume, double *bnd, double *clipped);
+/* one cell's normal transport, its derivative with respect to the normal
+ * discharge, and the two HLL speeds, for the pin tests */
+void om_sed_cell(int32_t closure, double alpha, double m, double thr, double d_m, double s_rel, double g, double h,
+                 double u, double v, double cf2, double nx, double ny, double *qbn, double *D, double *l1,
+                 double *l2);
 /* volume the sources added so far (negative: removed); the balance is
  * M(t) = M(0) - bnd_flux + clipped + source volume */
 double om_source_volume(const om_sim *s);

@@ -66,6 +66,22 @@ class Source:
 
 
 @dataclasses.dataclass
+class Morpho:
+    """Exner module: sediment closure ("mpm", "grass" or "eh") with alpha,
+    exponent m and threshold thr (theta_cr, or u_cr for grass), grain
+    diameter d_m [m], relative density s_rel, porosity, and an optional
+    non-erodible bed z_rel (<= 0) below the initial bed per cell."""
+    closure: str = "mpm"
+    alpha: float = 8.0
+    m: float = 1.5
+    thr: float = 0.047
+    d_m: float = 1e-3
+    s_rel: float = 2.65
+    porosity: float = 0.4
+    z_rel: Optional[np.ndarray] = None
+
+
+@dataclasses.dataclass
 class Scenario:
     name: str
     nodes: np.ndarray            # (V,3) float64: x, y, bed elevation z
@@ -87,6 +103,7 @@ class Scenario:
     phi0: Optional[np.ndarray] = None  # (S, N) initial concentrations of S <= 5 advected species
     sources: tuple = ()                # external water sources and sinks (Source)
     src_region: Optional[np.ndarray] = None  # (N,) int32 index into sources, -1 for none
+    morpho: Optional[Morpho] = None    # Exner module (bed evolution)
 
     @property
     def n_cells(self) -> int:

@@ -43,8 +43,8 @@ SPECIES_BYTES = {"fp32": 8.0, "fp64": 16.0}
 # counters (each scaled by what it reads for a plain copy of known size); it
 # is reported only while the kernel sources still hash to the digest recorded
 # with the measurement
-def traffic_profile(precision, species):
-    kern = f"k_step_species{species}" if species else "k_step"
+def traffic_profile(precision, species, morpho=False):
+    kern = "k_step_morpho" if morpho else f"k_step_species{species}" if species else "k_step"
     return os.path.join(ROOT, "profiles", f"{kern}_{precision}_valley4m_hbm_traffic.md")
 
 
@@ -65,11 +65,11 @@ def kernel_digest():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(workload, precision, tile, species=0):
+def measured_traffic(workload, precision, tile, species=0, morpho=False):
     """Bytes per step-kernel launch from the committed counter profile, or
     None when it was taken on other kernel sources or another configuration."""
     try:
-        with open(traffic_profile(precision, species)) as fh:
+        with open(traffic_profile(precision, species, morpho)) as fh:
             kv = dict(line.strip()[2:].split(": ", 1) for line in fh if line.startswith("- ") and ": " in line)
     except OSError:
         return None
@@ -107,7 +107,7 @@ def species_phi0(sc, ns):
     return np.stack(rows[:ns])
 
 
-def time_gpu(sc, precision, steps, warmup, autotune=True, species=0, tile=0):
+def time_gpu(sc, precision, steps, warmup, autotune=True, species=0, tile=0, morpho=False):
     """Kernel time per step over `steps` graph-launched steps."""
     import torch
     from paper_2102_12862_amd import swe
@@ -118,6 +118,9 @@ def time_gpu(sc, precision, steps, warmup, autotune=True, species=0, tile=0):
     st = swe.State(mesh, sc, precision=p, steps_per_graph=50, block_size=tile)
     if species:
         st.set_scalars(species_phi0(sc, species))
+    if morpho:
+        import swe_inputs as S
+        st.set_morpho(S.Morpho("mpm"))
     tune = st.autotune(k=5) if (autotune and not tile) else None
     st.launch_steps(warmup)
     st.sync()
@@ -268,6 +271,7 @@ def main():
                     help="also run a plain device copy of this many MiB (counter calibration)")
     ap.add_argument("--tile", type=int, default=0, choices=(0, 128, 256, 512),
                     help="cells per tile (block size) of the step kernel; 0: autotuned")
+    ap.add_argument("--morpho", action="store_true", help="carry the Exner module (MPM closure)")
     ap.add_argument("--species", type=int, default=0, choices=range(0, 6),
                     help="passive species carried by the step (0: the hydrodynamic step alone)")
     ap.add_argument("--kernel-digest", action="store_true", help="print the digest of the kernel sources and exit")
@@ -299,15 +303,16 @@ def main():
     sc = make_workload(args.workload)
     log(f"[bench] {sc.name}: {sc.n_cells} cells ({time.perf_counter() - t0:.1f}s)")
     r = time_gpu(sc, args.precision, args.steps, args.warmup, autotune=not args.no_autotune, species=args.species,
-                 tile=args.tile)
+                 tile=args.tile, morpho=args.morpho)
     N = sc.n_cells
     value = r["rate"]
     bytes_per_cell = ALGO_BYTES[args.precision] + args.species * SPECIES_BYTES[args.precision]
     achieved = bytes_per_cell * N / (r["ms_step"] * 1e-3) / 1e9
     tile = r["tune"][0] if r["tune"] else (args.tile or 256)
-    traffic = measured_traffic(sc.name, args.precision, tile, args.species)
+    traffic = measured_traffic(sc.name, args.precision, tile, args.species, args.morpho)
     tname = "float" if args.precision == "fp32" else "double"
-    kname = (f"k_step_species<{tname}, 256, {args.species}, false>" if args.species
+    kname = (f"k_step_morpho<{tname}, 256>" if args.morpho else
+             f"k_step_species<{tname}, 256, {args.species}, false>" if args.species
              else f"k_step<{tname}, {tile}, false>")
     log(f"[bench] gpu {args.precision}: {r['ms_step'] * 1e3:.1f} us/step, {value:.3e} cell-updates/s, "
         f"{achieved:.0f} GB/s algorithmic, tune {r['tune']}")
@@ -325,7 +330,14 @@ def main():
             variants[f"{lake.name}_{p}"] = {"cell_updates_per_s": lr["rate"], "us_per_step": lr["ms_step"] * 1e3,
                                            "note": "working set fits the 256 MB Infinity Cache"}
             log(f"[bench] lake {p}: {lr['ms_step'] * 1e3:.1f} us/step")
-        for ns in ((2, 5) if not args.species else ()):
+        if not (args.species or args.morpho):
+            mr = time_gpu(sc, args.precision, max(50, args.steps // 5), 10, morpho=True)
+            variants[f"{sc.name}_{args.precision}_morpho"] = {
+                "cell_updates_per_s": mr["rate"], "us_per_step": mr["ms_step"] * 1e3,
+                "algorithmic_bytes_per_cell": ALGO_BYTES[args.precision],
+                "roofline_frac": ALGO_BYTES[args.precision] * N / (mr["ms_step"] * 1e-3) / 1e9 / HBM_PEAK_GBS}
+            log(f"[bench] Exner (MPM): {mr['ms_step'] * 1e3:.1f} us/step")
+        for ns in ((2, 5) if not (args.species or args.morpho) else ()):
             sr = time_gpu(sc, args.precision, max(50, args.steps // 5), 10, species=ns)
             b = ALGO_BYTES[args.precision] + ns * SPECIES_BYTES[args.precision]
             variants[f"{sc.name}_{args.precision}_species{ns}"] = {
@@ -363,7 +375,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": sc.name, "cells": N, "precision": args.precision,
                    "state": "fully wet snapshot" if "wet" in args.workload else "as generated",
-                   "block_size_cells_per_thread": r["tune"], "species": args.species},
+                   "block_size_cells_per_thread": r["tune"], "species": args.species, "morpho": args.morpho},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "algorithmic_bytes_per_cell": bytes_per_cell,

@@ -275,6 +275,46 @@ swe_status swe_state_set_sources(swe_state *s, const int32_t *cell_region, const
  * clipped + source volume. */
 swe_status swe_source_volume(const swe_state *s, double *volume);
 
+/* ---- morphodynamics (section "Morphodynamics": the Exner equation eq.
+ * exner, updated by eq. exnerupdateformula with the HLL sediment flux eq.
+ * exner_hll and the speeds of eq. exner_wave_assign / eq.
+ * exner_wave_estimation; transport closures of Table sedtransport_closure).
+ * Synchronous-decoupled: the bed moves every step with the hydrodynamic dt,
+ * from the state at the step's start, and the water depth is kept as it
+ * moves.  The Shields number is theta = |u|^2 / (c_f^2 (s - 1) g d_m) with
+ * the cell's friction closure; dry (h <= h_min) and frictionless cells and
+ * cells at their non-erodible bed carry no sediment; the transport is
+ * aligned with the flow; dq_B,n/dq_n is taken at fixed depth and tangential
+ * velocity; walls carry no sediment and open edges the cell's own normal
+ * transport.  Sediment sources, local slope / curvature corrections and
+ * Smart-Jaggi are not built. */
+enum { SWE_SED_MPM = 0, SWE_SED_GRASS = 1, SWE_SED_EH = 2 };
+typedef struct {
+    int32_t closure;  /* SWE_SED_*: MPM alpha (theta - theta_cr)^m sqrt((s-1) g d^3); Grass alpha (|u| - u_cr)^m;
+                         Engelund-Hansen 0.05 c_f^2 theta^(5/2) sqrt((s-1) g d^3) */
+    double alpha;     /* MPM or Grass coefficient (>= 0) */
+    double m;         /* MPM or Grass exponent (> 0) */
+    double thr;       /* theta_cr (MPM) or u_cr [m/s] (Grass), >= 0 */
+    double d_m;       /* representative grain diameter [m] > 0 */
+    double s_rel;     /* relative density rho_s / rho > 1 */
+    double porosity;  /* bed porosity in [0, 1) */
+} swe_morpho;
+/* Switches the Exner module on (mo != NULL) or off (mo == NULL).  z_rel
+ * (host, n_cells doubles <= 0 in original cell order, or NULL) puts a
+ * non-erodible bed that far below the current bed: cells at it carry no
+ * sediment, and an update below it is clipped to it with the sediment volume
+ * so added tallied.  The module runs with 256-cell tiles and excludes passive
+ * species, external sources and batches (SWE_EINVAL).  Clears the sediment
+ * tallies. */
+swe_status swe_state_set_morpho(swe_state *s, const swe_morpho *mo, const double *z_rel);
+/* Copies the bed elevation (n_cells doubles, original cell order) to host memory. */
+swe_status swe_state_read_bed(const swe_state *s, double *z);
+/* Sediment volume (1 - p) sum z |Omega| (compensated FP64, fixed order),
+ * the volume that left through open boundaries, and the volume the fixed-bed
+ * clip added since the module was switched on: volume(t) = volume(0) -
+ * bnd + clipped.  The clip tally is summed with device atomics. */
+swe_status swe_morpho_volume(const swe_state *s, double *volume, double *bnd, double *clipped);
+
 /* Times k steps for each tile size (block size) in {128, 256, 512}, keeps
  * the fastest for this state, and restores the state exactly as it was.
  * *block_size receives the choice, *cells_per_thread 1 (either may be NULL).

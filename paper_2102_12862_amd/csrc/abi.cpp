@@ -173,6 +173,11 @@ struct swe_state {
     int *src_cell = nullptr;
     BCdev *srcs = nullptr;
     double *src_series = nullptr, *src_acc = nullptr;
+    // morphodynamics: the non-erodible bed (device order, or none), per
+    // boundary slot the sediment outflow, the fixed-bed clip tally
+    int morpho = 0;
+    void *zfix = nullptr;
+    double *bslot_acc = nullptr, *bclip = nullptr;
     int tile = 256, spg = 32;
     int phase = 0;  // step launches issued so far, mod 3 (selects the control slot)
     hipStream_t cap = nullptr;
@@ -189,6 +194,7 @@ struct swe_state {
             mem.release(q);
         drop_species();
         drop_sources();
+        drop_morpho();
         if (hctrl) (void)hipHostFree(hctrl);
         if (hbuf) (void)hipHostFree(hbuf);
     }
@@ -199,6 +205,17 @@ struct swe_state {
         sslot_acc = sclip = nullptr;
         ns = 0;
         bind_species();
+    }
+    void drop_morpho() {
+        for (void *q : {zfix, (void *)bslot_acc, (void *)bclip}) mem.release(q);
+        zfix = nullptr;
+        bslot_acc = bclip = nullptr;
+        morpho = 0;
+        inst32.morpho = inst64.morpho = 0;
+        inst32.zfix = nullptr;
+        inst64.zfix = nullptr;
+        inst32.bslot_acc = inst64.bslot_acc = nullptr;
+        inst32.bclip = inst64.bclip = nullptr;
     }
     void drop_sources() {
         for (void *q : {(void *)src_cell, (void *)srcs, (void *)src_series, (void *)src_acc}) mem.release(q);
@@ -317,6 +334,8 @@ extern "C" {
 static_assert(FR_MANNING == SWE_FRICTION_MANNING && FR_STRICKLER == SWE_FRICTION_STRICKLER &&
                   FR_CHEZY == SWE_FRICTION_CHEZY && FR_BEZZOLA == SWE_FRICTION_BEZZOLA,
               "friction closure numbering");
+static_assert(SED_MPM == SWE_SED_MPM && SED_GRASS == SWE_SED_GRASS && SED_EH == SWE_SED_EH,
+              "sediment closure numbering");
 static_assert(SRC_EXACT == SWE_SRC_EXACT && SRC_AVAILABLE == SWE_SRC_AVAILABLE && SRC_INFINITY == SWE_SRC_INFINITY,
               "source mode numbering");
 
@@ -727,6 +746,7 @@ swe_status swe_mass(const swe_state *cs, double *mass, double *bnd_flux, double 
 
 swe_status swe_state_set_scalars(swe_state *s, int32_t ns, const double *phi0, const double *phi_in) {
     if (!s) return fail(SWE_EINVAL, "state is NULL");
+    if (ns > 0 && s->morpho) return fail(SWE_EINVAL, "species and a moving bed do not combine");
     if (ns < 0 || ns > MAX_SPECIES) return fail(SWE_EINVAL, "between 0 and 5 species");
     const HostMesh &M = s->m->H;
     const int64_t n = M.nc;
@@ -792,6 +812,7 @@ swe_status swe_state_set_scalars(swe_state *s, int32_t ns, const double *phi0, c
 
 swe_status swe_state_set_sources(swe_state *s, const int32_t *cell_region, const swe_source *src, int32_t n_src) {
     if (!s) return fail(SWE_EINVAL, "state is NULL");
+    if (n_src > 0 && s->morpho) return fail(SWE_EINVAL, "sources and a moving bed do not combine");
     if (n_src < 0 || n_src > MAX_BC) return fail(SWE_EINVAL, "between 0 and 64 sources");
     if (n_src > 0 && (!cell_region || !src)) return fail(SWE_EINVAL, "bad source list");
     const HostMesh &M = s->m->H;
@@ -878,6 +899,128 @@ swe_status swe_state_set_sources(swe_state *s, const int32_t *cell_region, const
     return SWE_OK;
 }
 
+swe_status swe_state_set_morpho(swe_state *s, const swe_morpho *mo, const double *z_rel) {
+    if (!s) return fail(SWE_EINVAL, "state is NULL");
+    if (!mo) {
+        s->drop_graphs();
+        s->drop_morpho();
+        return SWE_OK;
+    }
+    if (mo->closure < SWE_SED_MPM || mo->closure > SWE_SED_EH) return fail(SWE_EINVAL, "unknown sediment closure");
+    auto fin = [](double x) { return std::isfinite(x); };
+    if (!(mo->alpha >= 0) || !fin(mo->alpha) || !(mo->m > 0) || !fin(mo->m) || !(mo->thr >= 0) || !fin(mo->thr) ||
+        !(mo->d_m > 0) || !fin(mo->d_m) || !(mo->s_rel > 1) || !fin(mo->s_rel) ||
+        !(mo->porosity >= 0 && mo->porosity < 1))
+        return fail(SWE_EINVAL, "bad sediment parameters");
+    if (s->ns > 0 || s->nsrc > 0) return fail(SWE_EINVAL, "a moving bed excludes species and sources");
+    const HostMesh &M = s->m->H;
+    const int64_t n = M.nc;
+    for (int64_t i = 0; z_rel && i < n; i++)
+        if (!(z_rel[i] <= 0.0)) return fail(SWE_EINVAL, "the fixed bed lies at or below the bed (z_rel <= 0)");
+    swe_status st = s->read_ctrl();
+    if (st) return st;
+    s->drop_graphs();
+    s->drop_morpho();
+    if (s->tile != SPECIES_TILE) {
+        st = s->set_tile(SPECIES_TILE);
+        if (st) return st;
+    }
+    const size_t es = s->prec == SWE_FP32 ? sizeof(float) : sizeof(double);
+    const int nsl = std::max(s->nslots, 1);
+    s->bslot_acc = (double *)s->mem.alloc(2 * sizeof(double) * (size_t)nsl);
+    s->bclip = (double *)s->mem.alloc(sizeof(double));
+    if (z_rel) s->zfix = s->mem.alloc(es * (size_t)n);
+    if (!s->bslot_acc || !s->bclip || (z_rel && !s->zfix)) {
+        s->drop_morpho();
+        return fail(SWE_ENOMEM, "device allocation failed (morphodynamics)");
+    }
+    hipStream_t q = s->stream();
+    const void *cur = s->lvl().cur ? s->U1 : s->U0;
+    auto up = [&](auto tag) -> swe_status {
+        using T = decltype(tag);
+        std::vector<double> z((size_t)2 * nsl, 0.0);
+        HIP_TRY(hipMemcpyAsync(s->bslot_acc, z.data(), z.size() * sizeof(double), hipMemcpyHostToDevice, q));
+        HIP_TRY(hipMemcpyAsync(s->bclip, z.data(), sizeof(double), hipMemcpyHostToDevice, q));
+        if (z_rel) {
+            std::vector<V4<T>> u((size_t)n);
+            HIP_TRY(hipMemcpyAsync(u.data(), cur, u.size() * sizeof(V4<T>), hipMemcpyDeviceToHost, q));
+            HIP_TRY(hipStreamSynchronize(q));
+            std::vector<T> zf((size_t)n);
+            for (int64_t i = 0; i < n; i++) {
+                const int32_t d = M.inv[i];
+                zf[d] = T(double(u[d].w) + z_rel[i]);
+            }
+            HIP_TRY(hipMemcpyAsync(s->zfix, zf.data(), zf.size() * sizeof(T), hipMemcpyHostToDevice, q));
+        }
+        HIP_TRY(hipStreamSynchronize(q));
+        return SWE_OK;
+    };
+    st = s->prec == SWE_FP32 ? up(float()) : up(double());
+    if (st) {
+        s->drop_morpho();
+        return st;
+    }
+    const double g = s->p.g;
+    auto bind = [&](auto &I, auto tag) {
+        using T = decltype(tag);
+        I.morpho = 1;
+        I.sclos = mo->closure;
+        I.salpha = mo->alpha;
+        I.sm = mo->m;
+        I.sthr = mo->thr;
+        // the same operations as the Shields number and K are written with
+        I.srgd = (mo->s_rel - 1.0) * g * mo->d_m;
+        I.sK = std::sqrt((mo->s_rel - 1.0) * g * mo->d_m * mo->d_m * mo->d_m);
+        I.spor = mo->porosity;
+        I.zfix = (const T *)s->zfix;
+        I.bslot_acc = s->bslot_acc;
+        I.bclip = s->bclip;
+    };
+    bind(s->inst32, float());
+    bind(s->inst64, double());
+    s->morpho = 1;
+    return SWE_OK;
+}
+
+swe_status swe_state_read_bed(const swe_state *cs, double *z) {
+    swe_state *s = const_cast<swe_state *>(cs);
+    if (!s) return fail(SWE_EINVAL, "state is NULL");
+    if (!z) return SWE_OK;
+    swe_status st = s->read_ctrl();
+    if (st) return st;
+    const HostMesh &M = s->m->H;
+    const int64_t n = M.nc;
+    const void *src = s->lvl().cur ? s->U1 : s->U0;
+    auto rd = [&](auto tag) -> swe_status {
+        using T = decltype(tag);
+        std::vector<V4<T>> u((size_t)n);
+        HIP_TRY(hipMemcpyAsync(u.data(), src, u.size() * sizeof(V4<T>), hipMemcpyDeviceToHost, s->stream()));
+        HIP_TRY(hipStreamSynchronize(s->stream()));
+        for (int64_t i = 0; i < n; i++) z[i] = double(u[M.inv[i]].w);
+        return SWE_OK;
+    };
+    return s->prec == SWE_FP32 ? rd(float()) : rd(double());
+}
+
+swe_status swe_morpho_volume(const swe_state *cs, double *volume, double *bnd, double *clipped) {
+    swe_state *s = const_cast<swe_state *>(cs);
+    if (!s) return fail(SWE_EINVAL, "state is NULL");
+    if (!s->morpho) return fail(SWE_EINVAL, "the bed is not moving (no morphodynamics)");
+    hipStream_t q = s->stream();
+    if (s->prec == SWE_FP32)
+        HIP_TRY(launch_bed_volume<float>(s->inst32, s->partials, s->mass_out, s->phase, q));
+    else
+        HIP_TRY(launch_bed_volume<double>(s->inst64, s->partials, s->mass_out, s->phase, q));
+    HIP_TRY(launch_pair_sum(s->bslot_acc, std::max(s->nslots, 1), s->mass_out + 1, q));
+    HIP_TRY(hipMemcpyAsync(s->hbuf + 1, s->mass_out, 2 * sizeof(double), hipMemcpyDeviceToHost, q));
+    HIP_TRY(hipMemcpyAsync(s->hbuf + 3, s->bclip, sizeof(double), hipMemcpyDeviceToHost, q));
+    HIP_TRY(hipStreamSynchronize(q));
+    if (volume) *volume = s->hbuf[1];
+    if (bnd) *bnd = s->hbuf[2];
+    if (clipped) *clipped = s->hbuf[3];
+    return SWE_OK;
+}
+
 swe_status swe_source_volume(const swe_state *cs, double *volume) {
     swe_state *s = const_cast<swe_state *>(cs);
     if (!s) return fail(SWE_EINVAL, "state is NULL");
@@ -938,9 +1081,9 @@ swe_status swe_scalar_mass(const swe_state *cs, double *mass, double *bnd_flux, 
 
 swe_status swe_autotune(swe_state *s, int32_t k, int32_t *block_size, int32_t *cells_per_thread) {
     if (!s) return fail(SWE_EINVAL, "state is NULL");
-    if (s->ns > 0 || s->nsrc > 0) {
-        // the species-carrying step has one tile size; a state with sources
-        // keeps its tile (its source tally is kept per tile)
+    if (s->ns > 0 || s->nsrc > 0 || s->morpho) {
+        // the species and Exner steps have one tile size; a state with
+        // sources keeps its tile (its source tally is kept per tile)
         if (block_size) *block_size = s->tile;
         if (cells_per_thread) *cells_per_thread = 1;
         return SWE_OK;
@@ -1170,6 +1313,7 @@ swe_status swe_batch_add(swe_batch *b, swe_state *s, double t_end, int32_t *slot
     if (s->prec != b->prec) return fail(SWE_EINVAL, "state precision differs from the batch");
     if (s->ns > 0) return fail(SWE_EINVAL, "states with passive species are not batched");
     if (s->nsrc > 0) return fail(SWE_EINVAL, "states with sources are not batched");
+    if (s->morpho) return fail(SWE_EINVAL, "states with a moving bed are not batched");
     if (s->stream() != b->stream()) return fail(SWE_EINVAL, "state and batch must use the same stream");
     if (std::isnan(t_end)) return fail(SWE_EINVAL, "t_end is NaN");
     for (auto *x : b->members)

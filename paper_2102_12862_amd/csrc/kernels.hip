@@ -445,6 +445,101 @@ __device__ __forceinline__ float concentration(float q, double h) {
     return h > 0.0 ? q * __builtin_amdgcn_rcpf(float(h)) : 0.0f;
 }
 
+// LDS of the Exner module for one tile (section "Morphodynamics"): per cell
+// the transport magnitude Phi and dPhi/d|u|, per (local edge, cell) the bed
+// contribution l q_B.
+template <typename T, int TILE> struct MorphoLds {
+    T phi[TILE];
+    T dphi[TILE];
+    T c[3][TILE];
+};
+
+// c_f^2 of the cell's friction closure at depth h > 0 (0: frictionless).
+__device__ __forceinline__ double cell_cf2(int kind, double par, double h) {
+    if (!(par > 0.0)) return 0.0;
+    if (kind <= FR_STRICKLER) return cbrt(h) / par;  // h^(1/3) / (g n^2)
+    const double cf = friction_cf(kind, par, h);
+    return cf * cf;
+}
+__device__ __forceinline__ float cell_cf2(int kind, float par, float h) {
+    if (!(par > 0.0f)) return 0.0f;
+    if (kind <= FR_STRICKLER)
+        return __builtin_amdgcn_exp2f((1.0f / 3.0f) * __builtin_amdgcn_logf(h)) * __builtin_amdgcn_rcpf(par);
+    const float cf = friction_cf(kind, par, h);
+    return cf * cf;
+}
+
+__device__ __forceinline__ double spow(double x, double p) { return pow(x, p); }
+__device__ __forceinline__ float spow(float x, float p) {
+    return __builtin_amdgcn_exp2f(p * __builtin_amdgcn_logf(x));
+}
+
+// Transport magnitude Phi(|u|) and dPhi/d|u| at fixed depth (Table
+// sedtransport_closure): MPM alpha (theta - theta_cr)^m K, Grass alpha
+// (|u| - u_cr)^m, Engelund-Hansen 0.05 c_f^2 theta^(5/2) K, with the Shields
+// number theta = |u|^2 / (c_f^2 (s - 1) g d) and K = sqrt((s - 1) g d^3).
+template <typename T>
+__device__ __forceinline__ void sed_mag(const Inst<T> &I, T umag, T cf2, T &phi, T &dphi) {
+    phi = T(0);
+    dphi = T(0);
+    if (!(umag > T(0))) return;
+    const T alpha = T(I.salpha), m = T(I.sm), thr = T(I.sthr);
+    if (I.sclos == SED_GRASS) {
+        const T e = umag - thr;
+        if (e > T(0)) {
+            phi = alpha * spow(e, m);
+            dphi = alpha * m * spow(e, m - T(1));
+        }
+        return;
+    }
+    if (!(cf2 > T(0))) return;
+    const T theta = umag * umag / (cf2 * T(I.srgd));
+    const T Kc = T(I.sK);
+    if (I.sclos == SED_MPM) {
+        const T e = theta - thr;
+        if (e > T(0)) {
+            phi = alpha * spow(e, m) * Kc;
+            dphi = alpha * m * spow(e, m - T(1)) * Kc * (T(2) * theta / umag);
+        }
+    } else {
+        phi = T(0.05) * cf2 * spow(theta, T(2.5)) * Kc;
+        dphi = T(5) * phi / umag;
+    }
+}
+
+// Phi and dPhi of a cell from its state: no transport when dry (h <= h_min),
+// frictionless, or at its non-erodible bed.
+template <typename T>
+__device__ __forceinline__ void cell_sediment(const Inst<T> &I, double hd, T u, T v, T z, T gn2, int cell, T &phi,
+                                              T &dphi) {
+    phi = T(0);
+    dphi = T(0);
+    if (!(hd > I.h_min)) return;
+    if (I.zfix && z <= I.zfix[cell]) return;
+    const T cf2 = cell_cf2(I.friction, gn2, T(hd));
+    sed_mag(I, T(qsqrt(u * u + v * v)), cf2, phi, dphi);
+}
+
+// Normal transport q_B.n and the speeds lambda_1, lambda_2 of one side of an
+// edge (eq. exner_wave_estimation), with dq_B,n/dq_n at fixed depth and
+// tangential velocity: (Phi' cos^2 a + Phi / |u| sin^2 a) / h.
+template <typename T>
+__device__ __forceinline__ void sed_side(T phi, T dphi, T u, T v, T un, T h, T g, T &qn, T &l1, T &l2) {
+    T dd = T(0);
+    qn = T(0);
+    if (phi > T(0) && h > T(0)) {
+        const T umag = qsqrt(u * u + v * v);
+        const T ca = un / umag;
+        qn = phi * ca;
+        dd = (dphi * (ca * ca) + (phi / umag) * (T(1) - ca * ca)) / h;
+    }
+    const T c = qsqrt(g * (h > T(0) ? h : T(0)));
+    const T a = un - c;
+    const T r = qsqrt(a * a + T(4) * dd * (c * c));
+    l1 = T(0.5) * (a - r);
+    l2 = T(0.5) * (a + r);
+}
+
 // CFL term of an inflow ghost (depth hg, normal velocity ung) on an edge of
 // length l of a cell with ap = |cell| (FP64) or 1/|cell| (FP32), merged into
 // the tile's LDS word.
@@ -470,11 +565,11 @@ template <typename V> __device__ __forceinline__ void whole(V &s) {
 // ride on the pass (SS, and qown for the cell's specific masses); each edge's
 // advective flux is the HLLC mass flux times the concentration of the cell
 // the water leaves.
-template <typename T, int TILE, bool UPDATE, int NS = 0>
+template <typename T, int TILE, bool UPDATE, int NS = 0, bool MORPHO = false>
 __device__ __forceinline__ void tile_edges(const Inst<T> &I, TileLds<T, TILE> &S, int tile, int cur, double t,
                                            double dt, double t_cand, V4<T> &own,
                                            ScalarLds<T, TILE, (NS > 0 ? NS : 1)> *SS = nullptr,
-                                           T *qown = nullptr) {
+                                           T *qown = nullptr, MorphoLds<T, TILE> *MS = nullptr) {
     const V4<T> *__restrict__ src = cur ? I.U1 : I.U0;
     const T *__restrict__ qsrc = cur ? I.Q1 : I.Q0;
     const T g = T(I.g);
@@ -505,6 +600,12 @@ __device__ __forceinline__ void tile_edges(const Inst<T> &I, TileLds<T, TILE> &S
                 qown[sp] = q;
                 SS->phi[sp][c] = concentration(q, hd);
             }
+        }
+        if constexpr (MORPHO) {
+            T phi, dphi;
+            cell_sediment(I, hd, S.huvz[c].y, S.huvz[c].z, s.w, I.cellp[i].y, i, phi, dphi);
+            MS->phi[c] = phi;
+            MS->dphi[c] = dphi;
         }
     }
     if (c == 0) S.ghost = ghost_init(T(0));
@@ -560,6 +661,8 @@ __device__ __forceinline__ void tile_edges(const Inst<T> &I, TileLds<T, TILE> &S
         // kind of edge keeps a single copy of the solver in the kernel)
         T hL, unL, utL, hR, unR, utR;
         int slot = 0, bi = 0;
+        // the other cell's sediment state (Exner): Phi, dPhi, velocity, depth, bed
+        T mphi = T(0), mdphi = T(0), mub = T(0), mvb = T(0), mhb = T(0), mzb = T(0);
         bool open = false, inflow_on = false, imposed = false;
         T qimp = T(0);  // weir or h-Q discharge
         if (kind != EK_BOUNDARY) {
@@ -582,6 +685,22 @@ __device__ __forceinline__ void tile_edges(const Inst<T> &I, TileLds<T, TILE> &S
                 const T hh = T(hbd);
                 ub = bwet ? qdiv(sb.y, hh) : T(0);
                 vb = bwet ? qdiv(sb.z, hh) : T(0);
+                if constexpr (MORPHO) {
+                    const int jb = I.ew1[e];
+                    cell_sediment(I, hbd, ub, vb, sb.w, I.cellp[jb].y, jb, mphi, mdphi);
+                    mhb = hh;
+                }
+            }
+            if constexpr (MORPHO) {
+                if (kind == EK_LOCAL) {
+                    const int b = (E.w0 >> 17) & 1023;
+                    mphi = MS->phi[b];
+                    mdphi = MS->dphi[b];
+                    mhb = T(double(sb.x) - double(sb.w));
+                }
+                mub = ub;
+                mvb = vb;
+                mzb = sb.w;
             }
             T unb, utb;
             rotate(ub, vb, nx, ny, unb, utb);
@@ -712,6 +831,48 @@ __device__ __forceinline__ void tile_edges(const Inst<T> &I, TileLds<T, TILE> &S
                 if (kind == EK_LOCAL) SS->c[sp][kb][b] = -(l * A);
             }
         }
+        if constexpr (MORPHO) {
+            // HLL sediment flux (eq. exner_hll, speeds eq. exner_wave_assign)
+            // in the edge's canonical orientation, like the water's
+            const T ua = sa.y, va = sa.z;
+            const T ha_raw = T(double(sa.x) - double(sa.w));
+            T cq;  // l q_B as leaving a
+            if (kind != EK_BOUNDARY) {
+                // canonical normal n_c = flip ? -n : n; both sides' normal components with it
+                const T unb_c = mub * (flip ? -nx : nx) + mvb * (flip ? -ny : ny);
+                const T una_c = flip ? -una : una;
+                T qa_c, l1a_c, l2a_c, qb_c, l1b_c, l2b_c;
+                sed_side(MS->phi[a], MS->dphi[a], ua, va, una_c, ha_raw, g, qa_c, l1a_c, l2a_c);
+                sed_side(mphi, mdphi, mub, mvb, unb_c, mhb, g, qb_c, l1b_c, l2b_c);
+                // left = a unless flipped
+                const T qLs = flip ? qb_c : qa_c, qRs = flip ? qa_c : qb_c;
+                const T l1L = flip ? l1b_c : l1a_c, l1R = flip ? l1a_c : l1b_c;
+                const T l2L = flip ? l2b_c : l2a_c, l2R = flip ? l2a_c : l2b_c;
+                const T zL = flip ? mzb : sa.w, zR = flip ? sa.w : mzb;
+                const T lm = l1L < l1R ? l1L : l1R;
+                const T lp = l2L > l2R ? l2L : l2R;
+                T q;
+                if (lp > lm)
+                    q = (lp * qLs - lm * qRs + lp * lm * (zR - zL)) / (lp - lm);
+                else
+                    q = T(0.5) * (qLs + qRs);
+                cq = flip ? -(l * q) : l * q;
+            } else {
+                // open edges carry the cell's own normal transport, walls none
+                T qa, l1a, l2a;
+                sed_side(MS->phi[a], MS->dphi[a], ua, va, una, ha_raw, g, qa, l1a, l2a);
+                cq = open ? l * qa : T(0);
+                if (open) {
+                    double *acc = I.bslot_acc + 2 * slot;
+                    double sm = acc[0], cp = acc[1];
+                    neumaier(sm, cp, dt * double(cq));
+                    acc[0] = sm;
+                    acc[1] = cp;
+                }
+            }
+            MS->c[ka][a] = cq;
+            if (kind == EK_LOCAL) MS->c[kb][(E.w0 >> 17) & 1023] = -cq;
+        }
         if (kind == EK_LOCAL) {
             const int b = (E.w0 >> 17) & 1023;
             const T Db = F1 - hg2 * hb * hb;
@@ -777,12 +938,13 @@ __device__ __forceinline__ CandT<T> tile_candidate(const Inst<T> &I, const TileL
 // (taken at time t) before the friction split; dvol receives the volume the
 // cell's source added (negative: removed), and a sink's removal leaves the
 // species' concentrations unchanged (added water carries none).
-template <typename T, int TILE, int NS = 0, bool SRC = false>
+template <typename T, int TILE, int NS = 0, bool SRC = false, bool MORPHO = false>
 __device__ __forceinline__ CandT<T> tile_update(const Inst<T> &I, const TileLds<T, TILE> &S, int tile, int cur,
                                                 double dt, const V4<T> &s,
                                                 const ScalarLds<T, TILE, (NS > 0 ? NS : 1)> *SS = nullptr,
                                                 const T *qown = nullptr, double t = 0.0,
-                                                double *dvol = nullptr) {
+                                                double *dvol = nullptr,
+                                                const MorphoLds<T, TILE> *MS = nullptr) {
     const int c = threadIdx.x;
     const int i = tile * TILE + c;
     if (i >= I.n) return IS32<T> ? T(0) : T(INFINITY);
@@ -859,8 +1021,26 @@ __device__ __forceinline__ CandT<T> tile_update(const Inst<T> &I, const TileLds<
         qx = T(0);
         qy = T(0);
     }
-    if (!isfinite(Hn) || !isfinite(qx) || !isfinite(qy)) atomicOr(&I.ctrl->flags, FLAG_NONFINITE);
-    dst[i] = make4<T>(Hn, qx, qy, s.w);
+    T zn = s.w;
+    if constexpr (MORPHO) {
+        // eq. exnerupdateformula; the water depth is kept as the bed moves
+        const T Rz = MS->c[0][c] + MS->c[1][c] + MS->c[2][c];
+        double znd;
+        if constexpr (IS32<T>) {
+            znd = double(s.w) - double((float(dt) * cp.x) * Rz) / (1.0 - I.spor);
+        } else {
+            const double w = dt * (1.0 / cp.x);
+            znd = s.w - (w * Rz) / (1.0 - I.spor);
+        }
+        if (I.zfix && znd < double(I.zfix[i])) {
+            atomicAdd(I.bclip, (1.0 - I.spor) * (double(I.zfix[i]) - znd) * I.area[i]);
+            znd = double(I.zfix[i]);
+        }
+        zn = T(znd);
+        Hn = T(double(Hn) + (znd - double(s.w)));
+    }
+    if (!isfinite(Hn) || !isfinite(qx) || !isfinite(qy) || !isfinite(zn)) atomicOr(&I.ctrl->flags, FLAG_NONFINITE);
+    dst[i] = make4<T>(Hn, qx, qy, zn);
     if constexpr (NS > 0) {
         T *__restrict__ qdst = cur ? I.Q0 : I.Q1;
         const bool dry = !(double(Hn) - double(s.w) > 0.0);
@@ -882,7 +1062,7 @@ __device__ __forceinline__ CandT<T> tile_update(const Inst<T> &I, const TileLds<
             qdst[(size_t)sp * I.n + i] = q;
         }
     }
-    return tile_candidate<T, TILE>(I, S, c, cp.x, Hn, qx, qy, s.w);
+    return tile_candidate<T, TILE>(I, S, c, cp.x, Hn, qx, qy, zn);
 }
 
 // Occupancy hint (minimum waves per SIMD): what the tile's LDS allows (FP32:
@@ -944,6 +1124,25 @@ __global__ void __launch_bounds__(TILE) k_step_species(Inst<T> I, int phase) {
     double dvol = 0.0;
     CandT<T> cand = tile_update<T, TILE, NS, SRC>(I, S, tile, L.cur, L.dt, own, &SS, qown, L.t, &dvol);
     if constexpr (SRC) tile_source_tally<TILE>(I.src_acc + 2 * tile, dvol);
+    if (threadIdx.x == 0) cand = combine(cand, ghost_value(S.ghost));
+    block_finish(I.ctrl, phase, cand, L, lead, true);
+}
+
+// The step with the Exner module: the bed moves with the same dt from the
+// state at t^n (synchronous-decoupled), its HLL sediment fluxes evaluated in
+// the same edge pass (tile of 256 cells, a kernel of its own for its LDS).
+template <typename T, int TILE>
+__global__ void __launch_bounds__(TILE) k_step_morpho(Inst<T> I, int phase) {
+    __shared__ TileLds<T, TILE> S;
+    __shared__ MorphoLds<T, TILE> MS;
+    const bool lead = blockIdx.x == 0;
+    const Level L = step_setup(I.ctrl, phase, I.cfl, I.dt_max, lead);
+    if (!L.run) return;
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    V4<T> own;
+    tile_edges<T, TILE, true, 0, true>(I, S, tile, L.cur, L.t, L.dt, L.t + L.dt, own, nullptr, nullptr, &MS);
+    CandT<T> cand = tile_update<T, TILE, 0, false, true>(I, S, tile, L.cur, L.dt, own, nullptr, nullptr, L.t,
+                                                          nullptr, &MS);
     if (threadIdx.x == 0) cand = combine(cand, ghost_value(S.ghost));
     block_finish(I.ctrl, phase, cand, L, lead, true);
 }
@@ -1036,6 +1235,17 @@ __global__ void __launch_bounds__(MASS_THREADS) k_pair_sum(const double *acc, in
     if (threadIdx.x == 0) out[0] = r.x + r.y;
 }
 
+// Sediment volume (1 - p) z |cell| in the same fixed order as the water volume.
+template <typename T>
+__global__ void __launch_bounds__(MASS_THREADS) k_bed_partial(Inst<T> I, double2 *partials, int phase) {
+    const V4<T> *src = I.ctrl->s[phase].cur ? I.U1 : I.U0;
+    double s = 0.0, c = 0.0;
+    for (int i = blockIdx.x * MASS_THREADS + threadIdx.x; i < I.n; i += MASS_BLOCKS * MASS_THREADS)
+        neumaier(s, c, (1.0 - I.spor) * double(src[i].w) * I.area[i]);
+    const double2 r = block_csum(make_double2(s, c));
+    if (threadIdx.x == 0) partials[blockIdx.x] = r;
+}
+
 // Species mass sum q |cell| in the same fixed order as the water volume.
 template <typename T>
 __global__ void __launch_bounds__(MASS_THREADS) k_species_mass_partial(Inst<T> I, int sp, double2 *partials,
@@ -1111,6 +1321,11 @@ hipError_t launch_species(const Inst<T> &I, int phase, hipStream_t s) {
 template <typename T>
 hipError_t launch_step(const Inst<T> &I, int tile, int phase, hipStream_t s) {
     if (I.n <= 0) return hipSuccess;
+    if (I.morpho) {
+        if (tile != SPECIES_TILE || I.ns > 0 || I.nsrc > 0) return hipErrorInvalidValue;
+        hipLaunchKernelGGL((k_step_morpho<T, SPECIES_TILE>), dim3(I.ntiles), dim3(SPECIES_TILE), 0, s, I, phase);
+        return hipGetLastError();
+    }
     if (I.ns > 0) {
         if (tile != SPECIES_TILE) return hipErrorInvalidValue;
         return I.nsrc > 0 ? launch_species<T, true>(I, phase, s) : launch_species<T, false>(I, phase, s);
@@ -1154,6 +1369,13 @@ hipError_t launch_species_mass(const Inst<T> &I, int sp, double2 *partials, doub
     return hipGetLastError();
 }
 
+template <typename T>
+hipError_t launch_bed_volume(const Inst<T> &I, double2 *partials, double *out, int phase, hipStream_t s) {
+    hipLaunchKernelGGL((k_bed_partial<T>), dim3(MASS_BLOCKS), dim3(MASS_THREADS), 0, s, I, partials, phase);
+    hipLaunchKernelGGL(k_pair_sum, dim3(1), dim3(MASS_THREADS), 0, s, (const double *)partials, MASS_BLOCKS, out);
+    return hipGetLastError();
+}
+
 hipError_t launch_pair_sum(const double *acc, int n, double *out, hipStream_t s) {
     hipLaunchKernelGGL(k_pair_sum, dim3(1), dim3(MASS_THREADS), 0, s, acc, n, out);
     return hipGetLastError();
@@ -1189,6 +1411,7 @@ hipError_t launch_step_batched(const Inst<T> *insts, const int2 *tiles, int ntil
     template hipError_t launch_dt_init<T>(const Inst<T> &, int, int, hipStream_t);                          \
     template hipError_t launch_mass<T>(const Inst<T> &, double2 *, double *, int, int, hipStream_t);        \
     template hipError_t launch_species_mass<T>(const Inst<T> &, int, double2 *, double *, int, int, hipStream_t); \
+    template hipError_t launch_bed_volume<T>(const Inst<T> &, double2 *, double *, int, hipStream_t);        \
     template hipError_t launch_step_batched<T>(const Inst<T> *, const int2 *, int, int, int, int, hipStream_t); \
     template int batched_grid<T>(int);
 SWE_INSTANTIATE(float)

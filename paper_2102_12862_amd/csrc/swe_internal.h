@@ -53,6 +53,8 @@ enum : int {
     BC_DYNWALL = 8
 };
 enum : int { FLAG_NONFINITE = 1, FLAG_NEGDEPTH = 2, FLAG_NODT = 4, FLAG_SINK = 8 };
+// sediment transport closures, numbered as SWE_SED_* in swe.h
+enum : int { SED_MPM = 0, SED_GRASS = 1, SED_EH = 2 };
 // external source modes, numbered as SWE_SRC_* in swe.h
 enum : int { SRC_EXACT = 0, SRC_AVAILABLE = 1, SRC_INFINITY = 2 };
 // friction closures, numbered as SWE_FRICTION_* in swe.h
@@ -138,6 +140,16 @@ template <typename T> struct Inst {
     const int *src_cell;
     const BCdev *srcs;
     double *src_acc;
+    // morphodynamics (morpho = 0: off): closure, its alpha / exponent /
+    // threshold, (s - 1) g d and sqrt((s - 1) g d^3), porosity; per cell the
+    // non-erodible bed (or null), per boundary slot a Neumaier accumulator of
+    // the sediment that left, and the fixed-bed clip tally
+    int morpho;
+    int sclos;
+    double salpha, sm, sthr, srgd, sK, spor;
+    const T *zfix;
+    double *bslot_acc;
+    double *bclip;
 };
 constexpr int MAX_SPECIES = 5;
 constexpr int SPECIES_TILE = 256;  // tile size of the species-carrying step
@@ -151,6 +163,9 @@ template <typename T>
 hipError_t launch_mass(const Inst<T> &I, double2 *partials, double *out, int nslots, int phase, hipStream_t s);
 // sum of n compensated pairs (sum, compensation) in a fixed order -> *out
 hipError_t launch_pair_sum(const double *acc, int n, double *out, hipStream_t s);
+// sediment volume (1 - p) sum z |cell| in a fixed order -> out[0]
+template <typename T>
+hipError_t launch_bed_volume(const Inst<T> &I, double2 *partials, double *out, int phase, hipStream_t s);
 // species sp: out[0] = sum q |cell| (compensated, fixed order), out[1] = mass
 // that left through open boundaries
 template <typename T>

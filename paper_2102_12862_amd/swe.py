@@ -46,6 +46,15 @@ class SweSource(ctypes.Structure):
                 ("n_pts", ctypes.c_int32)]
 
 
+class SweMorpho(ctypes.Structure):
+    _fields_ = [("closure", ctypes.c_int32), ("alpha", ctypes.c_double), ("m", ctypes.c_double),
+                ("thr", ctypes.c_double), ("d_m", ctypes.c_double), ("s_rel", ctypes.c_double),
+                ("porosity", ctypes.c_double)]
+
+
+SED = {"mpm": 0, "grass": 1, "eh": 2}
+
+
 class SweParams(ctypes.Structure):
     _fields_ = [("g", ctypes.c_double), ("cfl", ctypes.c_double), ("h_min", ctypes.c_double),
                 ("dt_max", ctypes.c_double), ("precision", ctypes.c_int32), ("neg_depth_policy", ctypes.c_int32),
@@ -79,6 +88,9 @@ SIGNATURES = {
     "swe_scalar_mass": (ctypes.c_int32, [ctypes.c_void_p, _dp, _dp, _dp]),
     "swe_state_set_sources": (ctypes.c_int32, [ctypes.c_void_p, _ip, ctypes.POINTER(SweSource), ctypes.c_int32]),
     "swe_source_volume": (ctypes.c_int32, [ctypes.c_void_p, _dp]),
+    "swe_state_set_morpho": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(SweMorpho), _dp]),
+    "swe_state_read_bed": (ctypes.c_int32, [ctypes.c_void_p, _dp]),
+    "swe_morpho_volume": (ctypes.c_int32, [ctypes.c_void_p, _dp, _dp, _dp]),
     "swe_batch_create": (ctypes.c_int32, [ctypes.c_int32, ctypes.c_int64, ctypes.POINTER(SweDevice),
                                           ctypes.POINTER(ctypes.c_void_p)]),
     "swe_batch_destroy": (None, [ctypes.c_void_p]),
@@ -252,6 +264,30 @@ class State:
             self.set_scalars(phi0, pin)
         if len(getattr(sc, "sources", ())):
             self.set_sources(sc.src_region, sc.sources)
+        if getattr(sc, "morpho", None) is not None:
+            self.set_morpho(sc.morpho)
+
+    def set_morpho(self, mo):
+        """Exner module with mo (closure, alpha, m, thr, d_m, s_rel, porosity,
+        z_rel), or off for None."""
+        if mo is None:
+            _check(load().swe_state_set_morpho(self._h, None, None))
+            return
+        p = SweMorpho(SED[mo.closure], mo.alpha, mo.m, mo.thr, mo.d_m, mo.s_rel, mo.porosity)
+        zr = None if mo.z_rel is None else np.ascontiguousarray(mo.z_rel, np.float64)
+        _check(load().swe_state_set_morpho(self._h, ctypes.byref(p), _d(zr)))
+
+    def bed(self):
+        z = np.empty(self.n)
+        _check(load().swe_state_read_bed(self._h, _d(z)))
+        return z
+
+    def morpho_volume(self):
+        """Sediment volume, the volume that left through open boundaries, and
+        the volume the fixed-bed clip added."""
+        v, b, c = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+        _check(load().swe_morpho_volume(self._h, ctypes.byref(v), ctypes.byref(b), ctypes.byref(c)))
+        return v.value, b.value, c.value
 
     def set_sources(self, region, sources):
         """External water sources and sinks: region (cells,) indexes sources

@@ -62,7 +62,7 @@ def errors(got, sim):
     max error of H) of a GPU read-out against the oracle."""
     H, qx, qy, t = sim.state()
     geo = sim.mesh.geometry()
-    zb, area = geo["zb"], geo["area"]
+    zb, area = sim.bed(), geo["area"]   # the bed as it stands (it moves under morphodynamics)
     ref = dict(H=H, h=H - zb, qx=qx, qy=qy)
     out = {}
     for f in ("H", "h", "qx", "qy"):

@@ -96,6 +96,8 @@ def lib():
         L.om_sim_set_morpho.argtypes = [ctypes.c_void_p, ctypes.c_int32] + [ctypes.c_double] * 6 + \
             [_c_double_p, ctypes.c_char_p, ctypes.c_int]
         L.om_get_bed.argtypes = [ctypes.c_void_p, _c_double_p]
+        L.om_sim_set_drain.restype = ctypes.c_int
+        L.om_sim_set_drain.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_char_p, ctypes.c_int]
         L.om_morpho_diag.argtypes = [ctypes.c_void_p, _c_double_p, _c_double_p, _c_double_p]
         L.om_sed_cell.argtypes = [ctypes.c_int32] + [ctypes.c_double] * 12 + [_c_double_p] * 4
         L.om_sim_set_friction.restype = ctypes.c_int
@@ -241,6 +243,14 @@ class Sim:
             self.set_sources(sc.src_region, sc.sources)
         if getattr(sc, "morpho", None) is not None:
             self.set_morpho(sc.morpho)
+        if getattr(sc, "drain", False):
+            self.set_drain(True)
+
+    def set_drain(self, on):
+        """Draining-time positivity limiter on or off."""
+        err = ctypes.create_string_buffer(256)
+        if lib().om_sim_set_drain(self._p, int(bool(on)), err, 256):
+            raise OracleError(err.value.decode())
 
     def set_morpho(self, mo):
         """Exner module with the closure and parameters of mo (swe_inputs.Morpho)."""

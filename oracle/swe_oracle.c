@@ -84,6 +84,10 @@ struct om_sim {
     double *zfix, *bcont;
     double bvsum, bvcomp;    /* sediment volume that left through open boundaries */
     double bclip, bclipc;    /* sediment volume added by the fixed-bed clip */
+    /* draining-time positivity limiter: per cell theta = min(1, draining
+     * time / dt), and per (cell, local edge) the mass leaving through it */
+    int drain;
+    double *theta, *dout;
 };
 
 static void seterr(char *err, int len, const char *msg) {
@@ -295,6 +299,7 @@ void om_sim_free(om_sim *s) {
     for (int r = 0; r < s->nsrc; r++) { free(s->src[r].t); free(s->src[r].Q); }
     free(s->src); free(s->csrc); free(s->sfac);
     free(s->zfix); free(s->bcont);
+    free(s->theta); free(s->dout);
     free(s);
 }
 
@@ -679,6 +684,29 @@ int om_sim_set_morpho(om_sim *s, int32_t clos, double alpha, double mexp, double
     return 0;
 }
 
+/* ---------------------------------------------------------------------------
+ * Draining-time positivity limiter (the survey's replacement of the clip;
+ * the paper's scheme only clips).  Reading of the draining-time idea for
+ * explicit finite volumes: a cell can lose at most the water it holds in a
+ * step, so every flux that leaves a cell acts only for that cell's draining
+ * time T = h |Omega| / (sum of its outgoing mass fluxes l F_h), i.e. is
+ * scaled by theta = min(1, T / dt); the three components scale together, so
+ * a still lake (no mass flux) is untouched and the state stays well
+ * balanced.  Depths then stay >= 0 up to rounding; the clip remains for that
+ * rounding and is tallied as before.
+ * ------------------------------------------------------------------------ */
+int om_sim_set_drain(om_sim *s, int on, char *err, int elen) {
+    free(s->theta); free(s->dout);
+    s->theta = NULL; s->dout = NULL; s->drain = 0;
+    if (!on) return 0;
+    size_t nc = (size_t)(s->m->nc > 0 ? s->m->nc : 1);
+    s->theta = malloc(sizeof(double) * nc);
+    s->dout = calloc(3 * nc, sizeof(double));
+    if (!s->theta || !s->dout) { seterr(err, elen, "out of memory"); return -1; }
+    s->drain = 1;
+    return 0;
+}
+
 void om_get_bed(const om_sim *s, double *z) { memcpy(z, s->z, sizeof(double) * (size_t)s->m->nc); }
 
 /* Sediment volume (1 - p) sum z |Omega| (Neumaier), the volume that left
@@ -963,6 +991,90 @@ static void scalar_edge(om_sim *s, int32_t L, int32_t R, int kL, int kR, double 
     }
 }
 
+/* The numerical flux of edge e (HLLC, or a boundary condition's ghost or
+ * imposed discharge) at t^n, in the edge's frame (n from L to R), with the
+ * reconstructed depths on its two sides. */
+typedef struct {
+    double F[3];
+    double hLs, hRs;
+    int wall, open, inflow_b;
+} edge_flux_t;
+
+static void edge_flux(const om_sim *s, int64_t e, edge_flux_t *out) {
+    const om_mesh *m = s->m;
+    const double g = s->g;
+    int32_t L = m->eL[e], R = m->eR[e];
+    double nx = m->enx[e], ny = m->eny[e], l = m->elen[e];
+    double hL, uL, vL, hR, uR, vR;
+    cell_velocity(s, L, &hL, &uL, &vL);
+    double HL = s->H[L], zL = s->z[L];
+    double unL = uL * nx + vL * ny, utL = -uL * ny + vL * nx;
+    double HR, zR, unR, utR;
+    int wall = 0, open = 0, inflow_b = -1, imposed = 0;
+    if (R >= 0) {
+        cell_velocity(s, R, &hR, &uR, &vR);
+        HR = s->H[R]; zR = s->z[R];
+        unR = uR * nx + vR * ny; utR = -uR * ny + vR * nx;
+    } else {
+        int b = s->ebc[e];
+        const om_bc *B = b >= 0 ? &s->bc[b] : NULL;
+        double hg, ung;
+        zR = zL;
+        if (B && B->kind == OM_OUTFLOW_ZEROGRAD) {
+            /* transmissive: the ghost repeats the interior state */
+            HR = HL; unR = unL; utR = utL; open = 1;
+        } else if (B && B->kind == OM_INFLOW_UNIFORM && inflow_ghost(s, B, L, s->t, &hg, &ung)) {
+            HR = zL + hg; unR = ung; utR = 0.0; open = 1; inflow_b = b;
+        } else if (B && B->kind == OM_INFLOW_FROUDE && froude_ghost(s, B, s->t, &hg, &ung)) {
+            HR = zL + hg; unR = ung; utR = 0.0; open = 1; inflow_b = b;
+        } else if (B && B->kind == OM_OUTFLOW_UNIFORM) {
+            /* uniform(slope) outflow: the ghost carries the normal depth
+             * of the cell's outflowing unit discharge with the cell's
+             * velocity (reading: "a value for the water depth must be
+             * specified" for outflows; no outflow gives a dry ghost) */
+            double qn = hL * unL;
+            hg = normal_depth(s, s->gn2[L], qn > 0.0 ? qn : 0.0, B->slope);
+            HR = zL + hg; unR = unL; utR = utL; open = 1;
+        } else if (B && (B->kind == OM_OUTFLOW_WEIR || B->kind == OM_OUTFLOW_HQ)) {
+            HR = HL; unR = unL; utR = utL; open = 1; imposed = 1;
+        } else if (B && B->kind == OM_DYNAMIC_WALL && s->t >= B->slope) {
+            /* a dynamic wall after its collapse time: transmissive */
+            HR = HL; unR = unL; utR = utL; open = 1;
+        } else if (B && B->kind == OM_ZHYDROGRAPH) {
+            /* "zhydrograph" (section "Hydrodynamic BCs", water surface
+             * elevation series).  Reading: the ghost is still water at the
+             * prescribed surface over the cell's bed, like a reservoir or
+             * sea level; the flux then lets water in or out. */
+            HR = hydrograph(B, s->t); unR = 0.0; utR = 0.0; open = 1;
+        } else {
+            /* reflective wall: mirror the normal velocity */
+            HR = HL; unR = -unL; utR = utL; wall = 1;
+        }
+    }
+    /* hydrostatic reconstruction of modified states at the edge.
+     * Reading: a reconstructed depth under OM_H_DRY counts as dry, so the
+     * contact speed never divides two underflowed products; a dry side
+     * never loses mass, so this keeps depths non-negative. */
+    double zs = zL > zR ? zL : zR;
+    double hLs = HL - zs; if (hLs < OM_H_DRY) hLs = 0.0;
+    double hRs = HR - zs; if (hRs < OM_H_DRY) hRs = 0.0;
+    double F[3];
+    if (imposed) {
+        /* weir or h-Q outflow: the boundary discharge q leaves carrying
+         * the cell's state: F = (q, q^2/h + g h^2/2, q u_t) */
+        double q = imposed_outflow(s, &s->bc[s->ebc[e]], HL, zL);
+        F[0] = q;
+        F[1] = (hLs > 0.0 ? q * (q / hLs) : 0.0) + 0.5 * g * hLs * hLs;
+        F[2] = q * utL;
+    } else {
+        om_hllc(hLs, unL, utL, hRs, unR, utR, g, F);
+    }
+    if (wall) F[0] = 0.0;   /* impermeable: no mass crosses a wall */
+    out->F[0] = F[0]; out->F[1] = F[1]; out->F[2] = F[2];
+    out->hLs = hLs; out->hRs = hRs;
+    out->wall = wall; out->open = open; out->inflow_b = inflow_b;
+}
+
 int om_step(om_sim *s, double t_end, double *dt_taken) {
     const om_mesh *m = s->m;
     const double g = s->g;
@@ -982,74 +1094,41 @@ int om_step(om_sim *s, double t_end, double *dt_taken) {
         }
     }
     if (s->ns > 0) memset(s->scont, 0, sizeof(double) * 3 * (size_t)(s->ns * m->nc));
+    if (s->drain) {
+        /* draining time: the water each cell loses through its edges this
+         * step, summed in local edge order, against the water it holds */
+        for (int64_t e = 0; e < m->ne; e++) {
+            edge_flux_t ef;
+            edge_flux(s, e, &ef);
+            double l = m->elen[e];
+            s->dout[3 * m->eL[e] + m->ekL[e]] = l * ef.F[0];
+            if (m->eR[e] >= 0) s->dout[3 * m->eR[e] + m->ekR[e]] = -(l * ef.F[0]);
+        }
+        for (int64_t i = 0; i < m->nc; i++) {
+            const double *o = s->dout + 3 * i;
+            double out = (o[0] > 0.0 ? o[0] : 0.0) + (o[1] > 0.0 ? o[1] : 0.0) + (o[2] > 0.0 ? o[2] : 0.0);
+            double h = s->H[i] - s->z[i];
+            double vol = (h > 0.0 ? h : 0.0) * m->area[i];
+            double leave = out * dt;
+            s->theta[i] = leave > vol ? vol / leave : 1.0;
+        }
+    }
     for (int64_t e = 0; e < m->ne; e++) {
         int32_t L = m->eL[e], R = m->eR[e];
         double nx = m->enx[e], ny = m->eny[e], l = m->elen[e];
-        double hL, uL, vL, hR, uR, vR;
-        cell_velocity(s, L, &hL, &uL, &vL);
-        double HL = s->H[L], zL = s->z[L];
-        double unL = uL * nx + vL * ny, utL = -uL * ny + vL * nx;
-        double HR, zR, unR, utR;
-        int wall = 0, open = 0, inflow_b = -1, imposed = 0;
-        if (R >= 0) {
-            cell_velocity(s, R, &hR, &uR, &vR);
-            HR = s->H[R]; zR = s->z[R];
-            unR = uR * nx + vR * ny; utR = -uR * ny + vR * nx;
-        } else {
-            int b = s->ebc[e];
-            const om_bc *B = b >= 0 ? &s->bc[b] : NULL;
-            double hg, ung;
-            zR = zL;
-            if (B && B->kind == OM_OUTFLOW_ZEROGRAD) {
-                /* transmissive: the ghost repeats the interior state */
-                HR = HL; unR = unL; utR = utL; open = 1;
-            } else if (B && B->kind == OM_INFLOW_UNIFORM && inflow_ghost(s, B, L, s->t, &hg, &ung)) {
-                HR = zL + hg; unR = ung; utR = 0.0; open = 1; inflow_b = b;
-            } else if (B && B->kind == OM_INFLOW_FROUDE && froude_ghost(s, B, s->t, &hg, &ung)) {
-                HR = zL + hg; unR = ung; utR = 0.0; open = 1; inflow_b = b;
-            } else if (B && B->kind == OM_OUTFLOW_UNIFORM) {
-                /* uniform(slope) outflow: the ghost carries the normal depth
-                 * of the cell's outflowing unit discharge with the cell's
-                 * velocity (reading: "a value for the water depth must be
-                 * specified" for outflows; no outflow gives a dry ghost) */
-                double qn = hL * unL;
-                hg = normal_depth(s, s->gn2[L], qn > 0.0 ? qn : 0.0, B->slope);
-                HR = zL + hg; unR = unL; utR = utL; open = 1;
-            } else if (B && (B->kind == OM_OUTFLOW_WEIR || B->kind == OM_OUTFLOW_HQ)) {
-                HR = HL; unR = unL; utR = utL; open = 1; imposed = 1;
-            } else if (B && B->kind == OM_DYNAMIC_WALL && s->t >= B->slope) {
-                /* a dynamic wall after its collapse time: transmissive */
-                HR = HL; unR = unL; utR = utL; open = 1;
-            } else if (B && B->kind == OM_ZHYDROGRAPH) {
-                /* "zhydrograph" (section "Hydrodynamic BCs", water surface
-                 * elevation series).  Reading: the ghost is still water at the
-                 * prescribed surface over the cell's bed, like a reservoir or
-                 * sea level; the flux then lets water in or out. */
-                HR = hydrograph(B, s->t); unR = 0.0; utR = 0.0; open = 1;
-            } else {
-                /* reflective wall: mirror the normal velocity */
-                HR = HL; unR = -unL; utR = utL; wall = 1;
-            }
+        edge_flux_t ef;
+        edge_flux(s, e, &ef);
+        double F[3] = {ef.F[0], ef.F[1], ef.F[2]};
+        double hLs = ef.hLs, hRs = ef.hRs;
+        int wall = ef.wall, open = ef.open, inflow_b = ef.inflow_b;
+        if (s->drain) {
+            /* the flux leaves its upwind cell for at most that cell's
+             * draining time: scaled by theta of the cell the water leaves */
+            double th = F[0] > 0.0 ? s->theta[L] : (F[0] < 0.0 && R >= 0 ? s->theta[R] : 1.0);
+            F[0] = F[0] * th;
+            F[1] = F[1] * th;
+            F[2] = F[2] * th;
         }
-        /* hydrostatic reconstruction of modified states at the edge.
-         * Reading: a reconstructed depth under OM_H_DRY counts as dry, so the
-         * contact speed never divides two underflowed products; a dry side
-         * never loses mass, so this keeps depths non-negative. */
-        double zs = zL > zR ? zL : zR;
-        double hLs = HL - zs; if (hLs < OM_H_DRY) hLs = 0.0;
-        double hRs = HR - zs; if (hRs < OM_H_DRY) hRs = 0.0;
-        double F[3];
-        if (imposed) {
-            /* weir or h-Q outflow: the boundary discharge q leaves carrying
-             * the cell's state: F = (q, q^2/h + g h^2/2, q u_t) */
-            double q = imposed_outflow(s, &s->bc[s->ebc[e]], HL, zL);
-            F[0] = q;
-            F[1] = (hLs > 0.0 ? q * (q / hLs) : 0.0) + 0.5 * g * hLs * hLs;
-            F[2] = q * utL;
-        } else {
-            om_hllc(hLs, unL, utL, hRs, unR, utR, g, F);
-        }
-        if (wall) F[0] = 0.0;   /* impermeable: no mass crosses a wall */
         /* fluctuations: the flux minus each side's own reconstructed pressure
          * (the bed-slope source in well-balanced form, using sum_j l n = 0) */
         double PL = 0.5 * g * hLs * hLs, PR = 0.5 * g * hRs * hRs;

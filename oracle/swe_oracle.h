@@ -89,6 +89,8 @@ enum { OM_SED_MPM = 0, OM_SED_GRASS = 1, OM_SED_EH = 2 };
 int om_sim_set_morpho(om_sim *s, int32_t closure, double alpha, double m, double thr, double d_m, double s_rel,
                       double porosity, const double *z_rel, char *err, int err_len);
 void om_get_bed(const om_sim *s, double *z);
+/* draining-time positivity limiter on (1) or off (0, the default) */
+int om_sim_set_drain(om_sim *s, int on, char *err, int err_len);
 void om_morpho_diag(const om_sim *s, double *volume, double *bnd, double *clipped);
 /* one cell's normal transport, its derivative with respect to the normal
  * discharge, and the two HLL speeds, for the pin tests */

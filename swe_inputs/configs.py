@@ -104,6 +104,7 @@ class Scenario:
     sources: tuple = ()                # external water sources and sinks (Source)
     src_region: Optional[np.ndarray] = None  # (N,) int32 index into sources, -1 for none
     morpho: Optional[Morpho] = None    # Exner module (bed evolution)
+    drain: bool = False                # draining-time positivity limiter instead of the bare clip
 
     @property
     def n_cells(self) -> int:

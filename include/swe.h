@@ -119,6 +119,7 @@ enum { SWE_FP64 = 0, SWE_FP32 = 1 };        /* precision (double is the paper's 
  * friction in that cell. */
 enum { SWE_FRICTION_MANNING = 0, SWE_FRICTION_STRICKLER = 1, SWE_FRICTION_CHEZY = 2, SWE_FRICTION_BEZZOLA = 3 };
 enum { SWE_NEG_CLIP = 0, SWE_NEG_ERROR = 1 }; /* negative-depth policy */
+enum { SWE_LIMIT_NONE = 0, SWE_LIMIT_DRAIN = 1 }; /* positivity limiter */
 
 /* Parameters (supplementary feature table, hydrodynamics parameters: CFL,
  * minimum water depth, upper limit of the time step; eq. CFL_condition for
@@ -135,6 +136,11 @@ typedef struct {
     int32_t steps_per_graph;  /* steps captured per hipGraph in swe_run_until; 0 = default (32) */
     int32_t renumber;       /* 1 = Hilbert order of cell centroids (default), 0 = input order */
     int32_t friction;       /* SWE_FRICTION_* closure (default Manning) */
+    int32_t limiter;        /* SWE_LIMIT_NONE (default: negative depths are clipped and tallied) or
+                               SWE_LIMIT_DRAIN: every flux leaving a cell acts only for that cell's
+                               draining time h |Omega| / (its outgoing mass flux), so depths stay
+                               >= 0 without the clip (up to rounding); costs a second edge pass per
+                               step; not with passive species, morphodynamics or batches */
 } swe_params;
 
 /* Fills *p with the defaults listed above. */

@@ -177,6 +177,7 @@ struct swe_state {
     // boundary slot the sediment outflow, the fixed-bed clip tally
     int morpho = 0;
     void *zfix = nullptr;
+    void *theta = nullptr;  // draining factors of the step (limiter on)
     double *bslot_acc = nullptr, *bclip = nullptr;
     int tile = 256, spg = 32;
     int phase = 0;  // step launches issued so far, mod 3 (selects the control slot)
@@ -190,7 +191,7 @@ struct swe_state {
         drop_graphs();
         if (cap) (void)hipStreamDestroy(cap);
         for (void *q : {U0, U1, cellp, (void *)slot_kbc, (void *)slot_acc, (void *)bcs, (void *)hydro, (void *)ctrl,
-                        (void *)partials, (void *)mass_out})
+                        (void *)partials, (void *)mass_out, theta})
             mem.release(q);
         drop_species();
         drop_sources();
@@ -352,6 +353,7 @@ void swe_params_default(swe_params *p) {
     p->steps_per_graph = 0;
     p->renumber = 1;
     p->friction = SWE_FRICTION_MANNING;
+    p->limiter = SWE_LIMIT_NONE;
 }
 
 const char *swe_last_error(void) { return g_err.c_str(); }
@@ -433,6 +435,7 @@ swe_status swe_state_init(const swe_mesh *m, const swe_params *params, const dou
     if (P.steps_per_graph < 0 || P.steps_per_graph > 4096) return fail(SWE_EINVAL, "steps_per_graph out of range");
     if (P.friction < SWE_FRICTION_MANNING || P.friction > SWE_FRICTION_BEZZOLA)
         return fail(SWE_EINVAL, "unknown friction closure");
+    if (P.limiter != SWE_LIMIT_NONE && P.limiter != SWE_LIMIT_DRAIN) return fail(SWE_EINVAL, "unknown limiter");
     if (H0 && h0) return fail(SWE_EINVAL, "give H0 or h0, not both");
     if (!std::isfinite(t0)) return fail(SWE_EINVAL, "t0 must be finite");
     if (n_bc < 0 || n_bc > MAX_BC || (n_bc > 0 && !bcs)) return fail(SWE_EINVAL, "bad boundary-condition list");
@@ -549,6 +552,10 @@ swe_status swe_state_init(const swe_mesh *m, const swe_params *params, const dou
     S->ctrl = (Ctrl *)S->mem.alloc(sizeof(Ctrl));
     S->partials = (double2 *)S->mem.alloc(sizeof(double2) * MASS_BLOCKS);
     S->mass_out = (double *)S->mem.alloc(2 * sizeof(double));
+    if (P.limiter == SWE_LIMIT_DRAIN) {
+        S->theta = S->mem.alloc((size_t)n * (prec == SWE_FP32 ? sizeof(float) : sizeof(double)));
+        if (!S->theta) return fail(SWE_ENOMEM, "device allocation failed (limiter)");
+    }
     if (!S->U0 || !S->U1 || !S->cellp || !S->slot_kbc || !S->slot_acc || !S->bcs || !S->hydro || !S->ctrl ||
         !S->partials || !S->mass_out)
         return fail(SWE_ENOMEM, "device allocation failed (state)");
@@ -617,6 +624,8 @@ swe_status swe_state_init(const swe_mesh *m, const swe_params *params, const dou
         I.dt_max = P.dt_max;
         I.neg_policy = P.neg_depth_policy;
         I.friction = P.friction;
+        I.drain = P.limiter == SWE_LIMIT_DRAIN;
+        I.theta = (T *)S->theta;
     };
     if (prec == SWE_FP32) {
         fill_inst(S->inst32, float());
@@ -747,6 +756,7 @@ swe_status swe_mass(const swe_state *cs, double *mass, double *bnd_flux, double 
 swe_status swe_state_set_scalars(swe_state *s, int32_t ns, const double *phi0, const double *phi_in) {
     if (!s) return fail(SWE_EINVAL, "state is NULL");
     if (ns > 0 && s->morpho) return fail(SWE_EINVAL, "species and a moving bed do not combine");
+    if (ns > 0 && s->p.limiter == SWE_LIMIT_DRAIN) return fail(SWE_EINVAL, "species and the draining-time limiter do not combine");
     if (ns < 0 || ns > MAX_SPECIES) return fail(SWE_EINVAL, "between 0 and 5 species");
     const HostMesh &M = s->m->H;
     const int64_t n = M.nc;
@@ -913,6 +923,7 @@ swe_status swe_state_set_morpho(swe_state *s, const swe_morpho *mo, const double
         !(mo->porosity >= 0 && mo->porosity < 1))
         return fail(SWE_EINVAL, "bad sediment parameters");
     if (s->ns > 0 || s->nsrc > 0) return fail(SWE_EINVAL, "a moving bed excludes species and sources");
+    if (s->p.limiter == SWE_LIMIT_DRAIN) return fail(SWE_EINVAL, "a moving bed and the draining-time limiter do not combine");
     const HostMesh &M = s->m->H;
     const int64_t n = M.nc;
     for (int64_t i = 0; z_rel && i < n; i++)
@@ -1314,6 +1325,7 @@ swe_status swe_batch_add(swe_batch *b, swe_state *s, double t_end, int32_t *slot
     if (s->ns > 0) return fail(SWE_EINVAL, "states with passive species are not batched");
     if (s->nsrc > 0) return fail(SWE_EINVAL, "states with sources are not batched");
     if (s->morpho) return fail(SWE_EINVAL, "states with a moving bed are not batched");
+    if (s->p.limiter == SWE_LIMIT_DRAIN) return fail(SWE_EINVAL, "states with the draining-time limiter are not batched");
     if (s->stream() != b->stream()) return fail(SWE_EINVAL, "state and batch must use the same stream");
     if (std::isnan(t_end)) return fail(SWE_EINVAL, "t_end is NaN");
     for (auto *x : b->members)

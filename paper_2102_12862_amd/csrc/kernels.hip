@@ -565,7 +565,12 @@ template <typename V> __device__ __forceinline__ void whole(V &s) {
 // ride on the pass (SS, and qown for the cell's specific masses); each edge's
 // advective flux is the HLLC mass flux times the concentration of the cell
 // the water leaves.
-template <typename T, int TILE, bool UPDATE, int NS = 0, bool MORPHO = false>
+// DRAIN: 0 none; DRAIN_MEASURE: fluxes into LDS only, without the
+// boundary tallies (the draining-time pass); DRAIN_APPLY: each flux scaled by
+// the draining factor of the cell its water leaves.
+enum : int { DRAIN_NONE = 0, DRAIN_MEASURE = 1, DRAIN_APPLY = 2 };
+
+template <typename T, int TILE, bool UPDATE, int NS = 0, bool MORPHO = false, int DRAIN = DRAIN_NONE>
 __device__ __forceinline__ void tile_edges(const Inst<T> &I, TileLds<T, TILE> &S, int tile, int cur, double t,
                                            double dt, double t_cand, V4<T> &own,
                                            ScalarLds<T, TILE, (NS > 0 ? NS : 1)> *SS = nullptr,
@@ -786,6 +791,19 @@ __device__ __forceinline__ void tile_edges(const Inst<T> &I, TileLds<T, TILE> &S
                 F1 = (ha > T(0) ? q * qdiv(q, ha) : T(0)) + hg2 * ha * ha;
                 F2 = q * uta;
             }
+        }
+        if constexpr (DRAIN == DRAIN_APPLY) {
+            // the flux acts only for the draining time of the cell it leaves
+            T th = T(1);
+            if (F0 > T(0))
+                th = I.theta[tile * TILE + a];
+            else if (F0 < T(0) && kind != EK_BOUNDARY)
+                th = I.theta[kind == EK_LOCAL ? tile * TILE + ((E.w0 >> 17) & 1023) : I.ew1[e]];
+            F0 = F0 * th;
+            F1 = F1 * th;
+            F2 = F2 * th;
+        }
+        if (kind == EK_BOUNDARY && DRAIN != DRAIN_MEASURE) {
             if (open) {
                 double *acc = I.slot_acc + 2 * slot;
                 double sm = acc[0], cp = acc[1];
@@ -1092,20 +1110,47 @@ __device__ __forceinline__ void tile_source_tally(double *acc, double v) {
     }
 }
 
-template <typename T, int TILE, bool SRC = false>
-__global__ void __launch_bounds__(TILE, (WAVES_PER_SIMD<T, TILE>)) k_step(Inst<T> I, int phase) {
+// The limited step (draining factors gathered per edge) needs a few more
+// registers: seven FP32 waves per SIMD keep it spill-free.
+template <typename T, int TILE, bool DRAIN>
+constexpr int WAVES_PER_SIMD_STEP = (DRAIN && IS32<T>) ? 7 : WAVES_PER_SIMD<T, TILE>;
+
+template <typename T, int TILE, bool SRC = false, bool DRAIN = false>
+__global__ void __launch_bounds__(TILE, (WAVES_PER_SIMD_STEP<T, TILE, DRAIN>)) k_step(Inst<T> I, int phase) {
     __shared__ TileLds<T, TILE> S;
     const bool lead = blockIdx.x == 0;
     const Level L = step_setup(I.ctrl, phase, I.cfl, I.dt_max, lead);
     if (!L.run) return;
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
     V4<T> own;
-    tile_edges<T, TILE, true>(I, S, tile, L.cur, L.t, L.dt, L.t + L.dt, own);
+    tile_edges<T, TILE, true, 0, false, (DRAIN ? DRAIN_APPLY : DRAIN_NONE)>(I, S, tile, L.cur, L.t, L.dt,
+                                                                             L.t + L.dt, own);
     double dvol = 0.0;
     CandT<T> cand = tile_update<T, TILE, 0, SRC>(I, S, tile, L.cur, L.dt, own, nullptr, nullptr, L.t, &dvol);
     if constexpr (SRC) tile_source_tally<TILE>(I.src_acc + 2 * tile, dvol);
     if (threadIdx.x == 0) cand = combine(cand, ghost_value(S.ghost));
     block_finish(I.ctrl, phase, cand, L, lead, true);
+}
+
+// Draining-time pass (before a limited step, same time level): each cell's
+// outgoing mass over the step, summed in local edge order, against the water
+// it holds gives theta = min(1, draining time / dt), stored per cell.
+template <typename T, int TILE>
+__global__ void __launch_bounds__(TILE, (WAVES_PER_SIMD<T, TILE>)) k_drain(Inst<T> I, int phase) {
+    __shared__ TileLds<T, TILE> S;
+    const Level L = step_setup(I.ctrl, phase, I.cfl, I.dt_max, false);
+    if (!L.run) return;
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    V4<T> own;
+    tile_edges<T, TILE, true, 0, false, DRAIN_MEASURE>(I, S, tile, L.cur, L.t, L.dt, L.t + L.dt, own);
+    const int c = threadIdx.x, i = tile * TILE + c;
+    if (i >= I.n) return;
+    const double o0 = double(S.c[0][0][c]), o1 = double(S.c[0][1][c]), o2 = double(S.c[0][2][c]);
+    const double out = (o0 > 0.0 ? o0 : 0.0) + (o1 > 0.0 ? o1 : 0.0) + (o2 > 0.0 ? o2 : 0.0);
+    const double h = double(own.x) - double(own.w);
+    const double vol = (h > 0.0 ? h : 0.0) * I.area[i];
+    const double leave = out * L.dt;
+    I.theta[i] = T(leave > vol ? vol / leave : 1.0);
 }
 
 // The step with NS passive species riding on the edge pass (tile of 256
@@ -1322,13 +1367,33 @@ template <typename T>
 hipError_t launch_step(const Inst<T> &I, int tile, int phase, hipStream_t s) {
     if (I.n <= 0) return hipSuccess;
     if (I.morpho) {
-        if (tile != SPECIES_TILE || I.ns > 0 || I.nsrc > 0) return hipErrorInvalidValue;
+        if (tile != SPECIES_TILE || I.ns > 0 || I.nsrc > 0 || I.drain) return hipErrorInvalidValue;
         hipLaunchKernelGGL((k_step_morpho<T, SPECIES_TILE>), dim3(I.ntiles), dim3(SPECIES_TILE), 0, s, I, phase);
         return hipGetLastError();
     }
     if (I.ns > 0) {
         if (tile != SPECIES_TILE) return hipErrorInvalidValue;
         return I.nsrc > 0 ? launch_species<T, true>(I, phase, s) : launch_species<T, false>(I, phase, s);
+    }
+    if (I.drain) {
+        if (I.ns > 0) return hipErrorInvalidValue;
+        const dim3 grid(I.ntiles);
+        switch (tile) {
+#define SWE_DRAIN_CASE(TL)                                                                                      \
+    case TL:                                                                                                    \
+        hipLaunchKernelGGL((k_drain<T, TL>), grid, dim3(TL), 0, s, I, phase);                                   \
+        if (I.nsrc > 0)                                                                                         \
+            hipLaunchKernelGGL((k_step<T, TL, true, true>), grid, dim3(TL), 0, s, I, phase);                    \
+        else                                                                                                    \
+            hipLaunchKernelGGL((k_step<T, TL, false, true>), grid, dim3(TL), 0, s, I, phase);                   \
+        break;
+            SWE_DRAIN_CASE(128)
+            SWE_DRAIN_CASE(256)
+            SWE_DRAIN_CASE(512)
+#undef SWE_DRAIN_CASE
+            default: return hipErrorInvalidValue;
+        }
+        return hipGetLastError();
     }
     if (I.nsrc > 0) {
         switch (tile) {

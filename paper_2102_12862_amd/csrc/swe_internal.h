@@ -150,6 +150,10 @@ template <typename T> struct Inst {
     const T *zfix;
     double *bslot_acc;
     double *bclip;
+    // draining-time limiter (drain = 0: the bare clip): per cell the factor
+    // min(1, draining time / dt) of the step being taken
+    int drain;
+    T *theta;
 };
 constexpr int MAX_SPECIES = 5;
 constexpr int SPECIES_TILE = 256;  // tile size of the species-carrying step

@@ -22,6 +22,7 @@ BC_WALL, BC_INFLOW_UNIFORM, BC_OUTFLOW_ZEROGRAD, BC_ZHYDROGRAPH = 0, 1, 2, 3
 BC_INFLOW_FROUDE, BC_OUTFLOW_UNIFORM, BC_OUTFLOW_WEIR, BC_OUTFLOW_HQ, BC_DYNAMIC_WALL = 4, 5, 6, 7, 8
 FP64, FP32 = 0, 1
 NEG_CLIP, NEG_ERROR = 0, 1
+LIMIT_NONE, LIMIT_DRAIN = 0, 1
 FRICTION = {"manning": 0, "strickler": 1, "chezy": 2, "bezzola": 3}
 
 _dp = ctypes.POINTER(ctypes.c_double)
@@ -59,7 +60,8 @@ class SweParams(ctypes.Structure):
     _fields_ = [("g", ctypes.c_double), ("cfl", ctypes.c_double), ("h_min", ctypes.c_double),
                 ("dt_max", ctypes.c_double), ("precision", ctypes.c_int32), ("neg_depth_policy", ctypes.c_int32),
                 ("block_size", ctypes.c_int32), ("cells_per_thread", ctypes.c_int32),
-                ("steps_per_graph", ctypes.c_int32), ("renumber", ctypes.c_int32), ("friction", ctypes.c_int32)]
+                ("steps_per_graph", ctypes.c_int32), ("renumber", ctypes.c_int32), ("friction", ctypes.c_int32),
+                ("limiter", ctypes.c_int32)]
 
 
 # every symbol the header declares, with (restype, argtypes)
@@ -242,6 +244,7 @@ class State:
         self.mesh = mesh
         self.precision = precision
         pkw.setdefault("friction", FRICTION[getattr(sc, "friction", "manning")])
+        pkw.setdefault("limiter", LIMIT_DRAIN if getattr(sc, "drain", False) else LIMIT_NONE)
         p = params(g=sc.g, cfl=sc.cfl, h_min=sc.h_min, dt_max=sc.dt_max, precision=precision, **pkw)
         if H0 is None and h0 is None:
             H0, h0 = sc.H0, sc.h0

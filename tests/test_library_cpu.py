@@ -47,6 +47,7 @@ def test_params_defaults(swe):
     p = swe.params()
     assert p.g == 9.81 and p.cfl == 0.9 and p.h_min == 1e-4 and np.isinf(p.dt_max)
     assert p.precision == swe.FP64 and p.renumber == 1 and p.friction == swe.FRICTION["manning"]
+    assert p.limiter == swe.LIMIT_NONE
 
 
 @pytest.mark.parametrize("maker", [lambda: S.lake_at_rest(3000), lambda: S.valley_flood(20000, scale=0.1),

@@ -243,6 +243,10 @@ om_mesh *om_mesh_new(const double *xyz, int64_t nv, const int32_t *tri, int64_t 
             if (pR != q) { seterr(err, elen, "inconsistent orientation (overlapping triangles)"); goto fail; }
             m->eR[e] = R; m->ekR[e] = kR;
             m->cell_edge[3 * R + kR] = (int32_t)e;
+            /* a tagged interior edge can carry an internal condition */
+            seg_key key = {he[h].a, he[h].b, 0};
+            seg_key *f = ns > 0 ? bsearch(&key, sk, (size_t)ns, sizeof(seg_key), cmp_seg) : NULL;
+            if (f) { m->etag[e] = f->tag; matched++; }
         } else {
             m->eR[e] = -1; m->ekR[e] = -1;
             seg_key key = {he[h].a, he[h].b, 0};
@@ -251,7 +255,7 @@ om_mesh *om_mesh_new(const double *xyz, int64_t nv, const int32_t *tri, int64_t 
         }
         h = g;
     }
-    if (matched != ns) { seterr(err, elen, "boundary segment is not a boundary edge of the mesh"); goto fail; }
+    if (matched != ns) { seterr(err, elen, "segment is not an edge of the mesh"); goto fail; }
     /* rho_ij: twice the distance from the centroid of i to edge j
      * (eq. CFL_condition); the centroid is at a third of the height, so
      * rho = 2 * (2|Omega|/l) / 3. */
@@ -376,7 +380,20 @@ om_sim *om_sim_new(const om_mesh *m, double g, double cfl, double h_min, double 
     }
     for (int64_t e = 0; e < m->ne; e++) {
         s->ebc[e] = -1;
-        if (m->eR[e] >= 0 || m->etag[e] < 0) continue;
+        if (m->etag[e] < 0) continue;
+        if (m->eR[e] >= 0) {
+            /* internal condition (section "Hydrodynamic BCs", internal BCs):
+             * a static wall, or a dynamic wall until its collapse time */
+            for (int b = 0; b < nbc; b++) {
+                if (s->bc[b].tag != m->etag[e]) continue;
+                if (s->bc[b].kind != OM_WALL && s->bc[b].kind != OM_DYNAMIC_WALL) {
+                    seterr(err, elen, "interior edges take walls and dynamic walls only"); goto fail;
+                }
+                s->ebc[e] = b;
+                break;
+            }
+            continue;
+        }
         for (int b = 0; b < nbc; b++) {
             if (s->bc[b].tag != m->etag[e]) continue;
             if (s->bc[b].kind != OM_WALL) s->ebc[e] = b;
@@ -1000,6 +1017,34 @@ typedef struct {
     int wall, open, inflow_b;
 } edge_flux_t;
 
+/* An interior edge that is a standing internal wall (a static wall, or a
+ * dynamic wall before its collapse time). */
+static int internal_wall(const om_sim *s, int64_t e) {
+    if (s->m->eR[e] < 0 || s->ebc[e] < 0) return 0;
+    const om_bc *B = &s->bc[s->ebc[e]];
+    return B->kind == OM_WALL || s->t < B->slope;
+}
+
+/* One side K of an internal wall, with K's outward normal (nx, ny): the
+ * reflective wall flux of K's own state, as on the domain boundary. */
+static void wall_side(om_sim *s, int32_t K, int kK, double nx, double ny, double l) {
+    double hK, uK, vK;
+    cell_velocity(s, K, &hK, &uK, &vK);
+    double un = uK * nx + vK * ny, ut = -uK * ny + vK * nx;
+    double hs = s->H[K] - s->z[K];
+    if (hs < OM_H_DRY) hs = 0.0;
+    double F[3];
+    om_hllc(hs, un, ut, hs, -un, ut, s->g, F);
+    F[0] = 0.0;
+    double P = 0.5 * s->g * hs * hs;
+    double dn = F[1] - P;
+    s->cont[9 * K + 3 * kK + 0] = l * F[0];
+    s->cont[9 * K + 3 * kK + 1] = l * (dn * nx - F[2] * ny);
+    s->cont[9 * K + 3 * kK + 2] = l * (dn * ny + F[2] * nx);
+    for (int c = 0; c < s->ns; c++) s->scont[3 * (c * s->m->nc + K) + kK] = 0.0;
+    if (s->morpho) s->bcont[3 * K + kK] = 0.0;
+}
+
 static void edge_flux(const om_sim *s, int64_t e, edge_flux_t *out) {
     const om_mesh *m = s->m;
     const double g = s->g;
@@ -1098,6 +1143,11 @@ int om_step(om_sim *s, double t_end, double *dt_taken) {
         /* draining time: the water each cell loses through its edges this
          * step, summed in local edge order, against the water it holds */
         for (int64_t e = 0; e < m->ne; e++) {
+            if (internal_wall(s, e)) {
+                s->dout[3 * m->eL[e] + m->ekL[e]] = 0.0;
+                s->dout[3 * m->eR[e] + m->ekR[e]] = 0.0;
+                continue;
+            }
             edge_flux_t ef;
             edge_flux(s, e, &ef);
             double l = m->elen[e];
@@ -1116,6 +1166,12 @@ int om_step(om_sim *s, double t_end, double *dt_taken) {
     for (int64_t e = 0; e < m->ne; e++) {
         int32_t L = m->eL[e], R = m->eR[e];
         double nx = m->enx[e], ny = m->eny[e], l = m->elen[e];
+        if (internal_wall(s, e)) {
+            /* each side sees a wall: its own reflected state */
+            wall_side(s, L, m->ekL[e], nx, ny, l);
+            wall_side(s, R, m->ekR[e], -nx, -ny, l);
+            continue;
+        }
         edge_flux_t ef;
         edge_flux(s, e, &ef);
         double F[3] = {ef.F[0], ef.F[1], ef.F[2]};

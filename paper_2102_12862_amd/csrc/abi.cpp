@@ -178,6 +178,7 @@ struct swe_state {
     int morpho = 0;
     void *zfix = nullptr;
     void *theta = nullptr;  // draining factors of the step (limiter on)
+    int *iw_bc = nullptr;   // per interior-tag index: its wall condition or -1
     double *bslot_acc = nullptr, *bclip = nullptr;
     int tile = 256, spg = 32;
     int phase = 0;  // step launches issued so far, mod 3 (selects the control slot)
@@ -191,7 +192,7 @@ struct swe_state {
         drop_graphs();
         if (cap) (void)hipStreamDestroy(cap);
         for (void *q : {U0, U1, cellp, (void *)slot_kbc, (void *)slot_acc, (void *)bcs, (void *)hydro, (void *)ctrl,
-                        (void *)partials, (void *)mass_out, theta})
+                        (void *)partials, (void *)mass_out, theta, (void *)iw_bc})
             mem.release(q);
         drop_species();
         drop_sources();
@@ -499,6 +500,18 @@ swe_status swe_state_init(const swe_mesh *m, const swe_params *params, const dou
             hydro.insert(hydro.end(), B.Q, B.Q + B.n_pts);
         }
     }
+    // internal conditions on tagged interior edges: walls and dynamic walls
+    std::vector<int> iwb(MAX_IW_TAGS + 1, -1);
+    for (size_t k = 0; k < M.iw_tags.size(); k++)
+        for (int b = 0; b < n_bc; b++) {
+            if (bcs[b].tag != M.iw_tags[k]) continue;
+            if (bcs[b].kind != SWE_BC_WALL && bcs[b].kind != SWE_BC_DYNAMIC_WALL)
+                return fail(SWE_EINVAL, "interior edges take walls and dynamic walls only");
+            iwb[k] = b;
+            break;
+        }
+    int iw_on = 0;
+    for (int v : iwb) iw_on |= v >= 0;
     const int nslots = (int)M.slot_tag.size();
     std::vector<int> kbc((size_t)std::max(nslots, 1), BC_WALL);
     std::vector<std::vector<double>> lens((size_t)std::max(n_bc, 1));
@@ -552,6 +565,8 @@ swe_status swe_state_init(const swe_mesh *m, const swe_params *params, const dou
     S->ctrl = (Ctrl *)S->mem.alloc(sizeof(Ctrl));
     S->partials = (double2 *)S->mem.alloc(sizeof(double2) * MASS_BLOCKS);
     S->mass_out = (double *)S->mem.alloc(2 * sizeof(double));
+    S->iw_bc = (int *)S->mem.alloc(sizeof(int) * iwb.size());
+    if (!S->iw_bc) return fail(SWE_ENOMEM, "device allocation failed (state)");
     if (P.limiter == SWE_LIMIT_DRAIN) {
         S->theta = S->mem.alloc((size_t)n * (prec == SWE_FP32 ? sizeof(float) : sizeof(double)));
         if (!S->theta) return fail(SWE_ENOMEM, "device allocation failed (limiter)");
@@ -593,6 +608,7 @@ swe_status swe_state_init(const swe_mesh *m, const swe_params *params, const dou
     HIP_TRY(hipMemcpyAsync(S->slot_kbc, kbc.data(), sizeof(int) * kbc.size(), hipMemcpyHostToDevice, s));
     HIP_TRY(hipMemcpyAsync(S->slot_acc, zeros.data(), sizeof(double) * zeros.size(), hipMemcpyHostToDevice, s));
     HIP_TRY(hipMemcpyAsync(S->bcs, hb.data(), sizeof(BCdev) * hb.size(), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(S->iw_bc, iwb.data(), sizeof(int) * iwb.size(), hipMemcpyHostToDevice, s));
     if (!hydro.empty())
         HIP_TRY(hipMemcpyAsync(S->hydro, hydro.data(), sizeof(double) * hydro.size(), hipMemcpyHostToDevice, s));
     Ctrl c;
@@ -625,6 +641,8 @@ swe_status swe_state_init(const swe_mesh *m, const swe_params *params, const dou
         I.neg_policy = P.neg_depth_policy;
         I.friction = P.friction;
         I.drain = P.limiter == SWE_LIMIT_DRAIN;
+        I.iw_bc = S->iw_bc;
+        I.iw_on = iw_on;
         I.theta = (T *)S->theta;
     };
     if (prec == SWE_FP32) {

@@ -570,7 +570,9 @@ template <typename V> __device__ __forceinline__ void whole(V &s) {
 // the draining factor of the cell its water leaves.
 enum : int { DRAIN_NONE = 0, DRAIN_MEASURE = 1, DRAIN_APPLY = 2 };
 
-template <typename T, int TILE, bool UPDATE, int NS = 0, bool MORPHO = false, int DRAIN = DRAIN_NONE>
+// IW: the mesh has internal walls (tagged interior edges); the check is
+// compiled only where it is needed, as it costs the plain step registers.
+template <typename T, int TILE, bool UPDATE, int NS = 0, bool MORPHO = false, int DRAIN = DRAIN_NONE, bool IW = true>
 __device__ __forceinline__ void tile_edges(const Inst<T> &I, TileLds<T, TILE> &S, int tile, int cur, double t,
                                            double dt, double t_cand, V4<T> &own,
                                            ScalarLds<T, TILE, (NS > 0 ? NS : 1)> *SS = nullptr,
@@ -619,7 +621,7 @@ __device__ __forceinline__ void tile_edges(const Inst<T> &I, TileLds<T, TILE> &S
         const Edge<T> E = En;
         En = I.edges[min(e + TILE, e1 - 1)];
         const int a = E.w0 & 1023, ka = (E.w0 >> 10) & 3, kb = (E.w0 >> 12) & 3, kind = (E.w0 >> 14) & 3;
-        const bool flip = (E.w0 >> 16) & 1;
+        bool flip = (E.w0 >> 16) & 1;
         T l, nx, ny;
         edge_normal(E.lx, E.ly, l, nx, ny);  // n: outward of a
         if constexpr (IS32<T>) {
@@ -668,7 +670,7 @@ __device__ __forceinline__ void tile_edges(const Inst<T> &I, TileLds<T, TILE> &S
         int slot = 0, bi = 0;
         // the other cell's sediment state (Exner): Phi, dPhi, velocity, depth, bed
         T mphi = T(0), mdphi = T(0), mub = T(0), mvb = T(0), mhb = T(0), mzb = T(0);
-        bool open = false, inflow_on = false, imposed = false;
+        bool open = false, inflow_on = false, imposed = false, walled = false;
         T qimp = T(0);  // weir or h-Q discharge
         if (kind != EK_BOUNDARY) {
             V4<T> sb;
@@ -722,6 +724,22 @@ __device__ __forceinline__ void tile_edges(const Inst<T> &I, TileLds<T, TILE> &S
             utL = flip ? -utb : uta;
             unR = flip ? -una : unb;
             utR = flip ? -uta : utb;
+            // a standing internal wall (static, or dynamic before its
+            // collapse time): this side sees its own reflected state
+            const int iw = IW ? (E.w0 >> 27) & 31 : 0;
+            if (iw) {
+                const int bc = I.iw_bc[iw - 1];
+                if (bc >= 0 && (I.bcs[bc].kind == BC_WALL || t < I.bcs[bc].slope)) {
+                    const double dw = double(sa.x) - double(sa.w);
+                    ha = dw < H_DRY ? T(0) : T(dw);
+                    hL = hR = ha;
+                    unL = una;
+                    utL = utR = uta;
+                    unR = -una;
+                    flip = false;
+                    walled = true;
+                }
+            }
         } else {
             slot = I.ew1[e];
             const int kbc = I.slot_kbc[slot];
@@ -782,6 +800,7 @@ __device__ __forceinline__ void tile_edges(const Inst<T> &I, TileLds<T, TILE> &S
         hllc(hL, unL, utL, hR, unR, utR, g, F0, F1, F2);
         if (kind != EK_BOUNDARY) {
             if (flip) F0 = -F0;  // mass leaving a
+            if (walled) F0 = T(0);
         } else {
             if (!open) F0 = T(0);  // no mass crosses a wall
             if (imposed) {
@@ -855,7 +874,9 @@ __device__ __forceinline__ void tile_edges(const Inst<T> &I, TileLds<T, TILE> &S
             const T ua = sa.y, va = sa.z;
             const T ha_raw = T(double(sa.x) - double(sa.w));
             T cq;  // l q_B as leaving a
-            if (kind != EK_BOUNDARY) {
+            if (walled) {
+                cq = T(0);
+            } else if (kind != EK_BOUNDARY) {
                 // canonical normal n_c = flip ? -n : n; both sides' normal components with it
                 const T unb_c = mub * (flip ? -nx : nx) + mvb * (flip ? -ny : ny);
                 const T una_c = flip ? -una : una;
@@ -1110,21 +1131,22 @@ __device__ __forceinline__ void tile_source_tally(double *acc, double v) {
     }
 }
 
-// The limited step (draining factors gathered per edge) needs a few more
-// registers: seven FP32 waves per SIMD keep it spill-free.
-template <typename T, int TILE, bool DRAIN>
-constexpr int WAVES_PER_SIMD_STEP = (DRAIN && IS32<T>) ? 7 : WAVES_PER_SIMD<T, TILE>;
+// The limited step (draining factors gathered per edge) and the step with
+// internal walls need a few more registers: seven FP32 waves per SIMD keep
+// them spill-free.
+template <typename T, int TILE, bool MORE>
+constexpr int WAVES_PER_SIMD_STEP = (MORE && IS32<T>) ? 7 : WAVES_PER_SIMD<T, TILE>;
 
-template <typename T, int TILE, bool SRC = false, bool DRAIN = false>
-__global__ void __launch_bounds__(TILE, (WAVES_PER_SIMD_STEP<T, TILE, DRAIN>)) k_step(Inst<T> I, int phase) {
+template <typename T, int TILE, bool SRC = false, bool DRAIN = false, bool IW = false>
+__global__ void __launch_bounds__(TILE, (WAVES_PER_SIMD_STEP<T, TILE, (DRAIN || IW)>)) k_step(Inst<T> I, int phase) {
     __shared__ TileLds<T, TILE> S;
     const bool lead = blockIdx.x == 0;
     const Level L = step_setup(I.ctrl, phase, I.cfl, I.dt_max, lead);
     if (!L.run) return;
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
     V4<T> own;
-    tile_edges<T, TILE, true, 0, false, (DRAIN ? DRAIN_APPLY : DRAIN_NONE)>(I, S, tile, L.cur, L.t, L.dt,
-                                                                             L.t + L.dt, own);
+    tile_edges<T, TILE, true, 0, false, (DRAIN ? DRAIN_APPLY : DRAIN_NONE), IW>(I, S, tile, L.cur, L.t, L.dt,
+                                                                                 L.t + L.dt, own);
     double dvol = 0.0;
     CandT<T> cand = tile_update<T, TILE, 0, SRC>(I, S, tile, L.cur, L.dt, own, nullptr, nullptr, L.t, &dvol);
     if constexpr (SRC) tile_source_tally<TILE>(I.src_acc + 2 * tile, dvol);
@@ -1135,14 +1157,14 @@ __global__ void __launch_bounds__(TILE, (WAVES_PER_SIMD_STEP<T, TILE, DRAIN>)) k
 // Draining-time pass (before a limited step, same time level): each cell's
 // outgoing mass over the step, summed in local edge order, against the water
 // it holds gives theta = min(1, draining time / dt), stored per cell.
-template <typename T, int TILE>
+template <typename T, int TILE, bool IW>
 __global__ void __launch_bounds__(TILE, (WAVES_PER_SIMD<T, TILE>)) k_drain(Inst<T> I, int phase) {
     __shared__ TileLds<T, TILE> S;
     const Level L = step_setup(I.ctrl, phase, I.cfl, I.dt_max, false);
     if (!L.run) return;
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
     V4<T> own;
-    tile_edges<T, TILE, true, 0, false, DRAIN_MEASURE>(I, S, tile, L.cur, L.t, L.dt, L.t + L.dt, own);
+    tile_edges<T, TILE, true, 0, false, DRAIN_MEASURE, IW>(I, S, tile, L.cur, L.t, L.dt, L.t + L.dt, own);
     const int c = threadIdx.x, i = tile * TILE + c;
     if (i >= I.n) return;
     const double o0 = double(S.c[0][0][c]), o1 = double(S.c[0][1][c]), o2 = double(S.c[0][2][c]);
@@ -1363,6 +1385,30 @@ hipError_t launch_species(const Inst<T> &I, int phase, hipStream_t s) {
     return hipGetLastError();
 }
 
+// The plain step with its compiled-in options: external sources, the
+// draining-time limiter (a measuring pass first), internal walls.
+template <typename T, int TL, bool SRC, bool DRAIN>
+hipError_t launch_plain_opts(const Inst<T> &I, int phase, hipStream_t s) {
+    const dim3 grid(I.ntiles), block(TL);
+    if (DRAIN) {
+        if (I.iw_on)
+            hipLaunchKernelGGL((k_drain<T, TL, true>), grid, block, 0, s, I, phase);
+        else
+            hipLaunchKernelGGL((k_drain<T, TL, false>), grid, block, 0, s, I, phase);
+    }
+    if (I.iw_on)
+        hipLaunchKernelGGL((k_step<T, TL, SRC, DRAIN, true>), grid, block, 0, s, I, phase);
+    else
+        hipLaunchKernelGGL((k_step<T, TL, SRC, DRAIN, false>), grid, block, 0, s, I, phase);
+    return hipGetLastError();
+}
+template <typename T, int TL>
+hipError_t launch_plain_step(const Inst<T> &I, int phase, hipStream_t s) {
+    if (I.nsrc > 0)
+        return I.drain ? launch_plain_opts<T, TL, true, true>(I, phase, s) : launch_plain_opts<T, TL, true, false>(I, phase, s);
+    return I.drain ? launch_plain_opts<T, TL, false, true>(I, phase, s) : launch_plain_opts<T, TL, false, false>(I, phase, s);
+}
+
 template <typename T>
 hipError_t launch_step(const Inst<T> &I, int tile, int phase, hipStream_t s) {
     if (I.n <= 0) return hipSuccess;
@@ -1375,37 +1421,12 @@ hipError_t launch_step(const Inst<T> &I, int tile, int phase, hipStream_t s) {
         if (tile != SPECIES_TILE) return hipErrorInvalidValue;
         return I.nsrc > 0 ? launch_species<T, true>(I, phase, s) : launch_species<T, false>(I, phase, s);
     }
-    if (I.drain) {
-        if (I.ns > 0) return hipErrorInvalidValue;
-        const dim3 grid(I.ntiles);
-        switch (tile) {
-#define SWE_DRAIN_CASE(TL)                                                                                      \
-    case TL:                                                                                                    \
-        hipLaunchKernelGGL((k_drain<T, TL>), grid, dim3(TL), 0, s, I, phase);                                   \
-        if (I.nsrc > 0)                                                                                         \
-            hipLaunchKernelGGL((k_step<T, TL, true, true>), grid, dim3(TL), 0, s, I, phase);                    \
-        else                                                                                                    \
-            hipLaunchKernelGGL((k_step<T, TL, false, true>), grid, dim3(TL), 0, s, I, phase);                   \
-        break;
-            SWE_DRAIN_CASE(128)
-            SWE_DRAIN_CASE(256)
-            SWE_DRAIN_CASE(512)
-#undef SWE_DRAIN_CASE
-            default: return hipErrorInvalidValue;
-        }
-        return hipGetLastError();
+    switch (tile) {
+        case 128: return launch_plain_step<T, 128>(I, phase, s);
+        case 256: return launch_plain_step<T, 256>(I, phase, s);
+        case 512: return launch_plain_step<T, 512>(I, phase, s);
+        default: return hipErrorInvalidValue;
     }
-    if (I.nsrc > 0) {
-        switch (tile) {
-            case 128: hipLaunchKernelGGL((k_step<T, 128, true>), dim3(I.ntiles), dim3(128), 0, s, I, phase); break;
-            case 256: hipLaunchKernelGGL((k_step<T, 256, true>), dim3(I.ntiles), dim3(256), 0, s, I, phase); break;
-            case 512: hipLaunchKernelGGL((k_step<T, 512, true>), dim3(I.ntiles), dim3(512), 0, s, I, phase); break;
-            default: return hipErrorInvalidValue;
-        }
-        return hipGetLastError();
-    }
-    SWE_TILE_DISPATCH(tile, k_step, dim3(I.ntiles), dim3(tile), 0, s, I, phase)
-    return hipGetLastError();
 }
 
 template <typename T>

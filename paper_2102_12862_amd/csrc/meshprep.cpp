@@ -101,6 +101,7 @@ bool prepare_mesh(const double *xyz, int64_t nv, const int32_t *tri, int64_t nc,
     }
     // neighbour of every (old cell, local edge): old neighbour id, or -1 - boundary id
     std::vector<int32_t> link((size_t)(3 * nc));
+    std::vector<int32_t> itag0((size_t)(3 * nc), -1);  // tag of a tagged interior edge
     std::vector<int32_t> btag;
     int64_t matched = 0, ne = 0;
     for (int64_t v = 0; v < nv; v++) {
@@ -121,6 +122,12 @@ bool prepare_mesh(const double *xyz, int64_t nv, const int32_t *tri, int64_t nc,
                 if (t3[3 * c2 + k2] != q1) { err = "inconsistent orientation (overlapping triangles)"; return false; }
                 link[3 * c1 + k1] = c2;
                 link[3 * c2 + k2] = c1;
+                const uint64_t key = ((uint64_t)v << 32) | (uint32_t)g->hi;
+                auto it = segtag.find(key);
+                if (it != segtag.end()) {
+                    itag0[3 * c1 + k1] = itag0[3 * c2 + k2] = it->second;
+                    matched++;
+                }
             } else {
                 const uint64_t key = ((uint64_t)v << 32) | (uint32_t)g->hi;
                 auto it = segtag.find(key);
@@ -135,7 +142,13 @@ bool prepare_mesh(const double *xyz, int64_t nv, const int32_t *tri, int64_t nc,
             g = h;
         }
     }
-    if (matched != ns) { err = "boundary segment is not a boundary edge of the mesh"; return false; }
+    if (matched != ns) { err = "segment is not an edge of the mesh"; return false; }
+    M.iw_tags.clear();
+    for (int32_t tg : itag0)
+        if (tg >= 0 && std::find(M.iw_tags.begin(), M.iw_tags.end(), tg) == M.iw_tags.end()) {
+            if ((int)M.iw_tags.size() == MAX_IW_TAGS) { err = "at most 31 tags on interior edges"; return false; }
+            M.iw_tags.push_back(tg);
+        }
     M.ne = ne;
     M.nb = (int64_t)btag.size();
 
@@ -168,6 +181,7 @@ bool prepare_mesh(const double *xyz, int64_t nv, const int32_t *tri, int64_t nc,
     M.lx.resize((size_t)(3 * nc));
     M.ly.resize((size_t)(3 * nc));
     M.nbr.resize((size_t)(3 * nc));
+    M.iw_slot.assign((size_t)(3 * nc), -1);
     M.slot_tag.clear();
     M.slot_len.clear();
     M.slot_cell.clear();
@@ -183,6 +197,9 @@ bool prepare_mesh(const double *xyz, int64_t nv, const int32_t *tri, int64_t nc,
             M.lx[3 * p + k] = dy;
             M.ly[3 * p + k] = -dx;
             const int32_t L = link[3 * i + k];
+            if (itag0[3 * i + k] >= 0)
+                M.iw_slot[3 * p + k] = (int32_t)(std::find(M.iw_tags.begin(), M.iw_tags.end(), itag0[3 * i + k]) -
+                                                 M.iw_tags.begin());
             if (L >= 0) {
                 int32_t code = M.inv[L];
                 if (i > L) code |= NBR_FLIP_BIT;  // canonical left cell = smaller original id
@@ -219,10 +236,15 @@ bool build_tile_edges(const HostMesh &M, int tile, std::vector<TileEdge> &edges,
                 e.lx = M.lx[3 * p + k];
                 e.ly = M.ly[3 * p + k];
                 int32_t w0 = (int32_t)(p - p0) | (k << 10);
+                const int32_t iw = M.iw_slot[3 * p + k];
                 if (code >= 0) {
                     const int32_t q = code & (NBR_FLIP_BIT - 1);
                     if (code & NBR_FLIP_BIT) w0 |= 1 << 16;
-                    if (q >= p0 && q < p1) {
+                    if (iw >= 0) {
+                        // a tagged interior edge: one record per side
+                        w0 |= (EDGE_REMOTE << 14) | (int32_t)((uint32_t)(iw + 1) << 27);
+                        e.w1 = q;
+                    } else if (q >= p0 && q < p1) {
                         if (q < p) continue;  // emitted from the other cell
                         int kb = -1;
                         for (int k2 = 0; k2 < 3; k2++) {
@@ -280,6 +302,8 @@ std::string check_tile_edges(const HostMesh &M, int tile, const std::vector<Tile
             if (a >= tile || pa >= n || ka > 2) return "edge cell outside its tile";
             if (E.lx != M.lx[3 * pa + ka] || E.ly != M.ly[3 * pa + ka]) return "edge geometry differs from its cell";
             const int32_t code = M.nbr[3 * pa + ka];
+            const int iwf = (int)(((uint32_t)E.w0 >> 27) & 31);
+            if (iwf != M.iw_slot[3 * pa + ka] + 1) return "interior-tag index mismatch";
             seen[3 * pa + ka]++;
             if (kind == EDGE_BOUNDARY) {
                 if (code >= 0 || E.w1 != -1 - code) return "boundary edge mismatch";
@@ -288,7 +312,7 @@ std::string check_tile_edges(const HostMesh &M, int tile, const std::vector<Tile
                 const int32_t q = code & (NBR_FLIP_BIT - 1);
                 if (flip != ((code & NBR_FLIP_BIT) ? 1 : 0)) return "orientation flag mismatch";
                 if (E.w1 != q) return "neighbour id mismatch";
-                const bool local = q >= p0 && q < std::min(n, p0 + tile);
+                const bool local = q >= p0 && q < std::min(n, p0 + tile) && !iwf;
                 if ((kind == EDGE_LOCAL) != local) return "local/remote classification wrong";
                 if (kind == EDGE_LOCAL) {
                     const int b = (E.w0 >> 17) & 1023;

@@ -22,7 +22,12 @@ struct HostMesh {
     std::vector<int32_t> slot_tag;   // per boundary slot (slot order = device cell, local edge)
     std::vector<double> slot_len;
     std::vector<int32_t> slot_cell;
+    // tagged interior edges (internal conditions): per (device cell, local
+    // edge) the index of its tag in iw_tags, or -1; at most 31 distinct tags
+    std::vector<int32_t> iw_slot;
+    std::vector<int32_t> iw_tags;
 };
+constexpr int MAX_IW_TAGS = 31;
 
 // One edge of a tile (a block of `tile` consecutive cells), stored once per
 // tile: an edge between two cells of the tile appears once, an edge to a
@@ -32,7 +37,10 @@ struct HostMesh {
 //   w0: bits 0-9 local cell a, 10-11 its local edge ka, 12-13 the other
 //       cell's local edge kb, 14-15 kind (0 both cells in the tile, 1 other
 //       cell in another tile, 2 boundary), bit 16 set when a is the right
-//       cell of the edge's canonical orientation, bits 17-26 local cell b
+//       cell of the edge's canonical orientation, bits 17-26 local cell b,
+//       bits 27-31 one plus the interior-tag index of a tagged interior edge
+//       (such an edge is stored once per side, as kind 1, even when both
+//       cells are in the tile, so that each side can become a wall)
 //   w1: kind 1: device id of the other cell; kind 2: boundary slot
 //   lx, ly: l * n with n the outward normal of a
 enum : int32_t { EDGE_LOCAL = 0, EDGE_REMOTE = 1, EDGE_BOUNDARY = 2 };

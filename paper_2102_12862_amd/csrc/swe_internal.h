@@ -154,6 +154,10 @@ template <typename T> struct Inst {
     // min(1, draining time / dt) of the step being taken
     int drain;
     T *theta;
+    // internal conditions: per interior-tag index the boundary condition (a
+    // wall or a dynamic wall) or -1
+    const int *iw_bc;
+    int iw_on;  // some interior tag carries a wall
 };
 constexpr int MAX_SPECIES = 5;
 constexpr int SPECIES_TILE = 256;  // tile size of the species-carrying step

@@ -1,0 +1,107 @@
+"""Internal static and dynamic walls on the GPU (section "Hydrodynamic BCs",
+internal BCs on tagged interior edges): parity with the FP64 oracle (FP64
+within 1e-10 of the norm, FP32 within 1e-4 in the L1 norm on a fixed step)
+at every tile size, through a dynamic wall's collapse, with species, the
+Exner module, the draining-time limiter and in a batch; the tile edge lists
+stay consistent; other kinds on interior edges are refused."""
+import numpy as np
+import pytest
+
+import oracle
+import swe_inputs as S
+from gpu_util import compare, device, gpu_state, rel_err
+from test_oracle_internal_walls import _cut_basin, _scenario
+
+pytestmark = pytest.mark.gpu
+
+FP64_TOL = 1e-10
+FP32_TOL = 1e-4
+
+
+@pytest.fixture(scope="module")
+def swe():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_2102_12862_amd import swe as mod
+    return mod
+
+
+def _basin(bc, xcut=20.0, lx=40.0, **kw):
+    xy, tri, seg = _cut_basin(lx=lx, xcut=xcut)
+    cx = xy[tri, 0].mean(axis=1)
+    H0 = np.where(cx < 10.0, 1.0, 0.4)
+    z = 0.05 * np.sin(xy[:, 0] / 3.0)
+    sc = _scenario(xy, tri, seg, np.full(len(seg), 9, np.int32), [bc], H0, z)
+    return S.Scenario(**{**sc.__dict__, **kw})
+
+
+@pytest.mark.parametrize("tile", [128, 256, 512])
+def test_static_wall_fp64(swe, tile):
+    sc = _basin(S.BC(9, S.WALL))
+    st = gpu_state(sc, swe.FP64, block_size=tile)
+    st.mesh.check(tile)
+    sim = oracle.Sim(sc)
+    for k in range(60):
+        dg, do = st.step(), sim.step()
+        assert abs(dg - do) <= 1e-13 * do, (k, dg, do)
+    compare(st, sim, FP64_TOL)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_dynamic_wall_collapse(swe, prec):
+    sc = _basin(S.BC(9, S.DYNAMIC_WALL, slope=2.0), xcut=20.0)
+    if prec == "fp64":
+        st = gpu_state(sc, swe.FP64)
+        st.run_until(6.0)
+        sim = oracle.Sim(sc)
+        sim.run_until(6.0)
+        compare(st, sim, FP64_TOL)
+    else:
+        fixed = S.Scenario(**{**sc.__dict__, "dt_max": 0.5 * oracle.Sim(sc).next_dt()})
+        st = gpu_state(fixed, swe.FP32)
+        sim = oracle.Sim(fixed)
+        while sim.t < 4.0:
+            st.step()
+            sim.step()
+        compare(st, sim, FP32_TOL, metric="l1")
+
+
+def test_with_species_morpho_and_limiter_fp64(swe):
+    n = len(_cut_basin()[1])
+    r = np.random.default_rng(5)
+    for kw in ({"phi0": r.uniform(0, 1, (2, n))}, {"morpho": S.Morpho("mpm", d_m=1e-3)}, {"drain": True}):
+        sc = _basin(S.BC(9, S.DYNAMIC_WALL, slope=1.0), **kw)
+        st = gpu_state(sc, swe.FP64)
+        sim = oracle.Sim(sc)
+        for _ in range(40):
+            st.step()
+            sim.step()
+        compare(st, sim, FP64_TOL)
+        if "phi0" in kw:
+            q, qo = st.scalars(), sim.scalars()
+            assert all(rel_err(q[c], qo[c]) <= FP64_TOL for c in range(2))
+        if "morpho" in kw:
+            assert rel_err(st.bed(), sim.bed()) <= FP64_TOL
+
+
+def test_batch_matches_a_single_run(swe):
+    sc = _basin(S.BC(9, S.DYNAMIC_WALL, slope=1.0))
+    one = gpu_state(sc, swe.FP32, block_size=256)
+    mine = gpu_state(sc, swe.FP32, block_size=256)
+    b = swe.Batch(swe.FP32, device=device())
+    b.add(mine, 3.0)
+    while b.step(16):
+        pass
+    one.run_until(3.0)
+    ra, rb = one.read(), mine.read()
+    assert ra["t"] == rb["t"]
+    for f in ("H", "qx", "qy"):
+        assert np.array_equal(ra[f], rb[f]), f
+    b.close()
+
+
+def test_only_walls_on_interior_edges(swe):
+    sc = _basin(S.BC(9, S.OUTFLOW_ZEROGRAD))
+    m = swe.Mesh(sc.nodes, sc.tri, sc.bnd_seg, sc.bnd_tag)
+    with pytest.raises(swe.SweError, match="interior edges"):
+        swe.State(m, sc, precision=swe.FP32)

@@ -71,7 +71,7 @@ def test_mesh_validation(swe):
     cases = [
         (bad, sc.tri, None, None, "degenerate"),
         (sc.nodes, np.vstack([sc.tri, sc.tri[:1]]), None, None, ("non-conforming", "orientation")),
-        (sc.nodes, sc.tri, np.array([[0, len(sc.nodes) - 1]], np.int32), np.array([1], np.int32), "boundary segment"),
+        (sc.nodes, sc.tri, np.array([[0, len(sc.nodes) - 1]], np.int32), np.array([1], np.int32), "not an edge of the mesh"),
         (np.where(np.arange(sc.nodes.size).reshape(sc.nodes.shape) == 4, np.nan, sc.nodes), sc.tri, None, None,
          "non-finite"),
         (sc.nodes, np.where(sc.tri == sc.tri[0, 0], len(sc.nodes) + 5, sc.tri).astype(np.int32), None, None,

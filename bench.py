@@ -313,7 +313,7 @@ def main():
     tname = "float" if args.precision == "fp32" else "double"
     kname = (f"k_step_morpho<{tname}, 256>" if args.morpho else
              f"k_step_species<{tname}, 256, {args.species}, false>" if args.species
-             else f"k_step<{tname}, {tile}, false>")
+             else f"k_step<{tname}, {tile}, false, false, false>")
     log(f"[bench] gpu {args.precision}: {r['ms_step'] * 1e3:.1f} us/step, {value:.3e} cell-updates/s, "
         f"{achieved:.0f} GB/s algorithmic, tune {r['tune']}")
     variants = {}

@@ -170,7 +170,7 @@ def time_oracle(sc, budget_s=15.0, max_steps=50, precision="fp32"):
     return dict(steps=n, seconds=el, prep=prep, rate=sc.n_cells * n / el, errors=errs)
 
 
-def bench_batched(n_members=32, rounds=8, k=16):
+def bench_batched(n_members=64, rounds=8, k=16):
     """Batched ensemble: members of the lake generator (jittered-lattice mesh
     for generation speed) with log-uniform sizes, each fed by its own
     hydrograph, stepped together by one persistent kernel per step; against

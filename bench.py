@@ -232,8 +232,8 @@ def bench_serving(n_requests=24, rate=4.0):
     import swe_inputs as S
     from gpu_util import cached, device
     from paper_2102_12862_amd import serve, swe
-    arrive, sizes, horizon = S.serving_trace(n_requests=n_requests, rate=rate, n_lo=1e4, n_hi=2e5,
-                                             h_lo=60.0, h_hi=600.0)
+    arrive, sizes, horizon = S.serving_trace(n_requests=n_requests, rate=rate, n_lo=1e4, n_hi=2e6,
+                                             h_lo=60.0, h_hi=1800.0)
     scen = [cached("req", S.serving_request, i, int(n), float(h)) for i, (n, h) in enumerate(zip(sizes, horizon))]
 
     def reqs():
@@ -253,7 +253,7 @@ def bench_serving(n_requests=24, rate=4.0):
     serve.serve_sequential(r2, precision=swe.FP32, device=dev)
     wall2 = time.perf_counter() - t0
     s_seq = serve.summarize(r2, wall2)
-    return {"requests": n_requests, "rate_per_s": rate, "cells_range": [1e4, 2e5], "horizon_s": [60, 600],
+    return {"requests": n_requests, "rate_per_s": rate, "cells_range": [1e4, 2e6], "horizon_s": [60, 1800],
             "served": s_batched, "one_at_a_time": s_seq}
 
 

@@ -202,6 +202,7 @@ class Mesh:
                                  ctypes.byref(p), None if self.device is None else ctypes.byref(self.device.struct),
                                  ctypes.byref(h)))
         self._h = h
+        self._destroy = load().swe_mesh_destroy
         self.n_cells = len(tri)
 
     def info(self):
@@ -217,7 +218,8 @@ class Mesh:
 
     def close(self):
         if getattr(self, "_h", None):
-            load().swe_mesh_destroy(self._h)
+            # the bound destroy call outlives the module's globals at interpreter exit
+            self._destroy(self._h)
             self._h = None
 
     def __del__(self):
@@ -256,6 +258,7 @@ class State:
         _check(L.swe_state_init(mesh._h, ctypes.byref(p), *[_d(a) for a in arrs], bc, len(sc.bcs), t0,
                                 ctypes.byref(h)))
         self._h = h
+        self._destroy = load().swe_state_destroy
         self.n = mesh.n_cells
         self.ns = 0
         phi0 = getattr(sc, "phi0", None)
@@ -368,7 +371,8 @@ class State:
 
     def close(self):
         if getattr(self, "_h", None):
-            load().swe_state_destroy(self._h)
+            # the bound destroy call outlives the module's globals at interpreter exit
+            self._destroy(self._h)
             self._h = None
 
     def __del__(self):
@@ -384,6 +388,7 @@ class Batch:
         h = ctypes.c_void_p()
         _check(load().swe_batch_create(precision, budget_bytes, ctypes.byref(self.device.struct), ctypes.byref(h)))
         self._h = h
+        self._destroy = load().swe_batch_destroy
         self.members = {}
 
     def add(self, state: State, t_end: float) -> int:
@@ -415,7 +420,8 @@ class Batch:
 
     def close(self):
         if getattr(self, "_h", None):
-            load().swe_batch_destroy(self._h)
+            # the bound destroy call outlives the module's globals at interpreter exit
+            self._destroy(self._h)
             self._h = None
 
     def __del__(self):

@@ -635,6 +635,8 @@ swe_status swe_state_init(const swe_mesh *m, const swe_params *params, const dou
         I.n = (int)n;
         I.ntiles = tg.ntiles;
         I.g = P.g;
+        I.sqrtg = std::sqrt(P.g);
+        I.sqrt2g = std::sqrt(2.0 * P.g);
         I.cfl = P.cfl;
         I.h_min = P.h_min;
         I.dt_max = P.dt_max;

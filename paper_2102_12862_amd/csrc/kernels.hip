@@ -163,22 +163,31 @@ __device__ __forceinline__ double hydrograph(const BCdev &b, double t) {
     return Qs[k] + w * (Qs[k + 1] - Qs[k]);
 }
 
+// FP64 power of the boundary branches, kept out of line: inlined, the
+// compiler loads the polynomial constants of pow into some forty registers
+// before the edge loop and holds them through it, for a call that only
+// boundary edges make.
+__device__ __noinline__ double bc_pow(double x, double p) { return pow(x, p); }
+
 // Ghost of the two discharge inflows (kind BC_INFLOW or BC_FROUDE): q = Q /
 // length enters at the depth x^p, x = n q / sqrt(S), p = 3/5 (uniform) or
-// x = q / (Fr sqrt(g)), p = 2/3 (froude).  One pow call serves both.
-__device__ __forceinline__ bool discharge_ghost(const BCdev &b, int kind, double t, double gn2, double g, double &hg,
-                                                double &ung) {
+// x = q / (Fr sqrt(g)), p = 2/3 (froude).  One pow call serves both.  FP64
+// takes sqrt(g) from the host (like sqrt(2 g) of the weir law: formed on the
+// device, it would be hoisted into every wave's prologue); FP32 forms its
+// single-instruction square root itself.
+__device__ __forceinline__ bool discharge_ghost(const BCdev &b, int kind, double t, double gn2, double g,
+                                                double sqrtg, double &hg, double &ung) {
     double Q = hydrograph(b, t);
     if (!(Q > 0.0)) return false;
     double q = Q / b.length;
     const bool unif = kind == BC_INFLOW;
-    double x = unif ? sqrt(gn2 / g) * q / sqrt(b.slope) : q / (b.slope * sqrt(g));
-    hg = pow(x, unif ? 0.6 : 2.0 / 3.0);
+    double x = unif ? sqrt(gn2 / g) * q / sqrt(b.slope) : q / (b.slope * sqrtg);
+    hg = bc_pow(x, unif ? 0.6 : 2.0 / 3.0);
     ung = -q / hg;
     return true;
 }
-__device__ __forceinline__ bool discharge_ghost(const BCdev &b, int kind, double t, float gn2, float g, float &hg,
-                                                float &ung) {
+__device__ __forceinline__ bool discharge_ghost(const BCdev &b, int kind, double t, float gn2, float g,
+                                                double /*sqrtg*/, float &hg, float &ung) {
     const double Q = hydrograph(b, t);
     if (!(Q > 0.0)) return false;
     const float q = float(Q / b.length);
@@ -193,7 +202,7 @@ __device__ __forceinline__ bool discharge_ghost(const BCdev &b, int kind, double
 // cell's power-law coefficient gn2 = g n^2 (uniform outflow).
 __device__ __forceinline__ double normal_depth(double gn2, double g, double q, double S) {
     double n = sqrt(gn2 / g);
-    return pow(n * q / sqrt(S), 0.6);
+    return bc_pow(n * q / sqrt(S), 0.6);
 }
 __device__ __forceinline__ float normal_depth(float gn2, float g, float q, double S) {
     const float x = q * qsqrt(qdiv(gn2, g * float(S)));
@@ -203,14 +212,16 @@ __device__ __forceinline__ float normal_depth(float gn2, float g, float q, doubl
 // Discharge per unit length leaving through a weir (Poleni's free overflow
 // (2/3) mu sqrt(2g) d^(3/2), head d over the crest, a crest below the cell's
 // bed counting at the bed) or an h-Q relation (Q(H) over the boundary
-// length), from the cell's surface H and bed z; zero for a dry cell.
-__device__ __forceinline__ double imposed_outflow(const BCdev &b, double H, double z, double g) {
+// length), from the cell's surface H and bed z; zero for a dry cell.  The
+// constant sqrt(2 g) comes from the host: formed here, the compiler hoists
+// it out of the edge loop into every wave's prologue.
+__device__ __forceinline__ double imposed_outflow(const BCdev &b, double H, double z, double sqrt2g) {
     if (!(H - z > 0.0)) return 0.0;
     if (b.kind == BC_WEIR) {
         const double crest = b.slope > z ? b.slope : z;
         const double d = H - crest;
         if (!(d > 0.0)) return 0.0;
-        return (2.0 / 3.0) * b.par * sqrt(2.0 * g) * (d * sqrt(d));
+        return (2.0 / 3.0) * b.par * sqrt2g * (d * sqrt(d));
     }
     return hydrograph(b, H) / b.length;
 }
@@ -649,7 +660,7 @@ __device__ __forceinline__ void tile_edges(const Inst<T> &I, TileLds<T, TILE> &S
                 if ((kbc & 15) == BC_INFLOW || (kbc & 15) == BC_FROUDE) {
                     const V2<T> cp = I.cellp[tile * TILE + a];
                     T hg, ung;
-                    if (discharge_ghost(I.bcs[kbc >> 4], kbc & 15, t_cand, cp.y, g, hg, ung))
+                    if (discharge_ghost(I.bcs[kbc >> 4], kbc & 15, t_cand, cp.y, g, I.sqrtg, hg, ung))
                         ghost_cfl<T, TILE>(S, l, hg, ung, g, cp.x);
                 } else if ((kbc & 15) == BC_ZHYDRO) {
                     const double dg = hydrograph(I.bcs[kbc >> 4], t_cand) - double(S.huvz[a].w);
@@ -764,7 +775,7 @@ __device__ __forceinline__ void tile_edges(const Inst<T> &I, TileLds<T, TILE> &S
             } else if (bkind == BC_INFLOW || bkind == BC_FROUDE) {
                 const V2<T> cp = I.cellp[tile * TILE + a];
                 const BCdev &B = I.bcs[bi];
-                const bool on = discharge_ghost(B, bkind, t, cp.y, g, hg, ung);
+                const bool on = discharge_ghost(B, bkind, t, cp.y, g, I.sqrtg, hg, ung);
                 if (on) {
                     const double dg = (zc + double(hg)) - zc;
                     hR = dg < H_DRY ? T(0) : T(dg);
@@ -772,7 +783,7 @@ __device__ __forceinline__ void tile_edges(const Inst<T> &I, TileLds<T, TILE> &S
                     utR = T(0);
                     open = inflow_on = true;
                 }
-                const bool onc = discharge_ghost(B, bkind, t_cand, cp.y, g, hg, ung);
+                const bool onc = discharge_ghost(B, bkind, t_cand, cp.y, g, I.sqrtg, hg, ung);
                 if (onc) ghost_cfl<T, TILE>(S, l, hg, ung, g, cp.x);
             } else if (bkind == BC_UNIFORM_OUT) {
                 // the normal depth of the cell's outflowing unit discharge,
@@ -785,7 +796,7 @@ __device__ __forceinline__ void tile_edges(const Inst<T> &I, TileLds<T, TILE> &S
                 open = true;
             } else if (bkind == BC_WEIR || bkind == BC_HQ) {
                 open = imposed = true;
-                qimp = T(imposed_outflow(I.bcs[bi], double(sa.x), zc, I.g));
+                qimp = T(imposed_outflow(I.bcs[bi], double(sa.x), zc, I.sqrt2g));
             } else if (bkind == BC_ZHYDRO) {
                 // still water at the prescribed surface over a's bed
                 const double dg = hydrograph(I.bcs[bi], t) - zc;

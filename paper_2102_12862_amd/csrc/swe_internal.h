@@ -121,6 +121,7 @@ template <typename T> struct Inst {
     int n;
     int ntiles;            // tiles of this state's mesh
     double g, cfl, h_min, dt_max;
+    double sqrtg, sqrt2g;  // sqrt(g) (froude inflow) and sqrt(2 g) (weir law), formed on the host
     int neg_policy;
     int friction;          // SWE_FRICTION_* closure
     // passive species (ns = 0: none): specific masses q = h phi, [ns][n] per

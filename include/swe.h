@@ -334,7 +334,13 @@ swe_status swe_autotune(swe_state *s, int32_t k, int32_t *block_size, int32_t *c
  * footprint; swe_batch_add returns SWE_EBUDGET when it would be exceeded. */
 swe_status swe_batch_create(int32_t precision, int64_t budget_bytes, const swe_device *dev, swe_batch **out);
 void swe_batch_destroy(swe_batch *b);
-/* Adds a state with its own end time; *slot receives its id. */
+/* Adds a state with its own end time; *slot receives its id.  The batch
+ * borrows the state: it must outlive its membership (remove it before
+ * swe_state_destroy), and while a member it advances only through the batch
+ * (swe_state_read and the diagnostics stay valid after swe_batch_step).
+ * States with species, sources, a moving bed or the draining-time limiter
+ * are refused (SWE_EINVAL), as are a state already in the batch and one on
+ * another stream. */
 swe_status swe_batch_add(swe_batch *b, swe_state *s, double t_end, int32_t *slot);
 /* Removes (detaches) a state; the state itself stays valid. */
 swe_status swe_batch_remove(swe_batch *b, int32_t slot);
@@ -344,8 +350,9 @@ swe_status swe_batch_remove(swe_batch *b, int32_t slot);
 swe_status swe_batch_step(swe_batch *b, int32_t k, int32_t *n_active);
 /* Issues the same work without waiting (for overlap and timing). */
 swe_status swe_batch_launch(swe_batch *b, int32_t k);
-/* Per-member status after the last swe_batch_step: done flag (t >= t_end),
- * error code (0 or SWE_E*), time and steps.  Arrays sized by capacity. */
+/* Per-member status after the last swe_batch_step: done flag (t >= t_end
+ * or an error), error code (0 or SWE_E*), time and steps of the member in
+ * slot `slot` (as returned by swe_batch_add); each output may be NULL. */
 swe_status swe_batch_poll(swe_batch *b, int32_t slot, int32_t *done, int32_t *error, double *t, int64_t *steps);
 int64_t swe_batch_footprint(const swe_batch *b);
 

@@ -80,23 +80,36 @@ class Server:
             # admission in arrival order, by footprint
             while waiting and prepared[waiting[0].rid].done():
                 r = waiting[0]
+
+                def drop(msg, mesh=None, st=None):
+                    # an invalid or oversized request is reported and dropped; its
+                    # device objects are freed
+                    r.error = msg
+                    r.finished = clock() - t0
+                    for x in (st, mesh):
+                        if x is not None:
+                            x.close()
+                    waiting.popleft()
+                    del prepared[r.rid]
+
                 try:
                     sc, mesh = prepared[r.rid].result()
-                except Exception as e:  # invalid request: report and drop
-                    r.error = str(e)
-                    r.finished = clock() - t0
-                    waiting.popleft()
+                except Exception as e:
+                    drop(str(e))
                     continue
                 need = mesh.footprint(self.precision)
                 if self.budget and used + need > self.budget:
                     if not active:
-                        r.error = f"footprint {need} exceeds the budget {self.budget}"
-                        r.finished = clock() - t0
-                        waiting.popleft()
+                        drop(f"footprint {need} exceeds the budget {self.budget}", mesh)
                         continue
                     break
-                st = swe.State(mesh, sc, precision=self.precision)
-                slot = self.batch.add(st, r.t_end)
+                st = None
+                try:
+                    st = swe.State(mesh, sc, precision=self.precision)
+                    slot = self.batch.add(st, r.t_end)
+                except Exception as e:
+                    drop(str(e), mesh, st)
+                    continue
                 used += need
                 r.admitted = clock() - t0
                 r.cells = sc.n_cells

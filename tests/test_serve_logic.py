@@ -15,18 +15,23 @@ class StubDevice:
 
 
 class StubMesh:
+    live = 0
+
     def __init__(self, nodes, tri, seg, tag, device=None):
         self.n_cells = len(tri)
+        StubMesh.live += 1
 
     def footprint(self, precision):
         return 100 * self.n_cells
 
     def close(self):
-        pass
+        StubMesh.live -= 1
 
 
 class StubState:
     def __init__(self, mesh, sc, precision=None):
+        if getattr(sc, "bad", False):
+            raise ValueError("invalid scenario")
         self.n = mesh.n_cells
         self.t = 0.0
         self.steps = 0
@@ -117,3 +122,17 @@ def test_late_arrivals_join_running_batch(stubbed):
     srv.serve(reqs)
     assert reqs[1].admitted < reqs[0].finished  # joined while request 0 was running
     assert srv.batch.max_concurrent == 2
+
+
+def test_failing_request_is_reported_and_freed(stubbed):
+    bad = make(50)
+    bad().bad = True
+    reqs = [serve.Request(0, 0.0, make(10), 3.0), serve.Request(1, 0.0, bad, 3.0),
+            serve.Request(2, 0.0, make(10 ** 6), 3.0), serve.Request(3, 0.001, make(20), 3.0)]
+    StubMesh.live = 0
+    srv = serve.Server(budget_bytes=100 * 1000, steps_per_round=2, device=StubDevice())
+    srv.serve(reqs)
+    assert reqs[0].error is None and reqs[3].error is None
+    assert "invalid scenario" in reqs[1].error and "budget" in reqs[2].error
+    assert all(r.finished is not None for r in reqs)
+    assert StubMesh.live == 0  # every mesh, admitted or refused, was closed

@@ -7,10 +7,11 @@ plain C (``swe_oracle.c``, compiled with ``gcc -ffp-contract=off``) driven
 through ctypes from here.
 
 Parity pins for each function are in ``tests/test_oracle_*.py``.  The one part
-without a pin independent of the oracle itself is the inflow boundary's exact
-delivered discharge (the ghost-state inflow does not impose Q exactly):
-parity unpinned for the value of the boundary-flux integral under inflow, only
-its role in the mass balance is pinned.
+without a pin independent of the oracle itself is the inflow boundary's
+delivered discharge in subcritical flow (the ghost-state inflow does not impose
+Q exactly there): parity unpinned for the value of the boundary-flux integral
+under a subcritical inflow, only its role in the mass balance is pinned.  A
+supercritical inflow (uniform or froude) is pinned exactly: it delivers Q t.
 """
 from __future__ import annotations
 

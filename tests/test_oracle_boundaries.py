@@ -5,7 +5,9 @@ dynamic-wall outflows), against closed forms:
 
 * a supercritical Froude inflow onto a dry bed delivers exactly Q t (all
   waves enter the domain, so the edge flux is the ghost's own flux), and the
-  inflowing layer carries the ghost depth (q / (Fr sqrt(g)))^(2/3);
+  inflowing layer carries the ghost depth (q / (Fr sqrt(g)))^(2/3); so does
+  a uniform (normal-depth) inflow down a channel steep enough for its ghost
+  to be supercritical;
 * a uniform outflow keeps uniform (normal) flow down a Manning channel;
 * a basin draining over a Poleni weir follows the closed form of
   dV/dt = -(2/3) mu sqrt(2g) (H - z_w)^(3/2) L;
@@ -65,6 +67,33 @@ def test_supercritical_froude_inflow_onto_a_dry_bed():
     near = cx < 3.0
     assert np.max(np.abs(H[near] - hg)) <= 0.02 * hg
     assert np.max(np.abs(qx[near] - q)) <= 0.02 * q
+
+
+def test_supercritical_uniform_inflow_delivers_exactly_q():
+    # a steep Manning channel: the normal-depth ghost (n q / sqrt(S))^(3/5) is
+    # supercritical, so on a dry bed every wave of the inflow edge points into
+    # the domain and the edge flux is the ghost's own: exactly Q t enters
+    Q, S0, n, ly = 2.0, 0.05, 0.01, 4.0
+    q = Q / ly
+    hn = (n * q / math.sqrt(S0)) ** 0.6
+    assert q / hn > 2.0 * math.sqrt(G * hn)  # Froude number above 2
+    sc = _channel(80.0, ly, 1.0, lambda x, y: S0 * (80.0 - x), 0.0,
+                  [S.BC(1, S.INFLOW_UNIFORM, slope=S0, t=np.array([0.0]), Q=np.array([Q]))], {"x0": 1},
+                  manning=n)
+    sim = oracle.Sim(sc)
+    sim.run_until(5.0)
+    d = sim.diag()
+    assert d["clipped"] == 0.0
+    assert abs(-d["bnd_flux"] - Q * 5.0) <= 1e-12 * Q * 5.0
+    assert abs(d["mass"] - Q * 5.0) <= 1e-12 * Q * 5.0
+    # the layer next to the inlet carries about the normal depth and
+    # discharge (on a 5 % slope the first-order scheme's own equilibrium
+    # differs from the continuous normal flow by a few per cent)
+    H, qx, _, _ = sim.state()
+    h = H - sim.mesh.geometry()["zb"]
+    near = sc.centroids()[:, 0] < 3.0
+    assert np.max(np.abs(h[near] - hn)) <= 0.1 * hn
+    assert np.max(np.abs(qx[near] - q)) <= 0.1 * q
 
 
 def test_uniform_outflow_keeps_normal_flow():

@@ -59,6 +59,24 @@ def test_uniform_outflow(swe):
     _both(sc, swe, 30.0)
 
 
+def test_supercritical_uniform_inflow_delivers_exactly_q(swe):
+    # the oracle's exact pin, on the GPU: a steep Manning channel with a dry
+    # bed takes in exactly Q t through its normal-depth inflow ghost
+    Q, S0, n = 2.0, 0.05, 0.01
+    sc = _channel(80.0, 4.0, 1.0, lambda x, y: S0 * (80.0 - x), 0.0,
+                  [S.BC(1, S.INFLOW_UNIFORM, slope=S0, t=np.array([0.0]), Q=np.array([Q]))], {"x0": 1},
+                  manning=n)
+    st, _ = _both(sc, swe, 5.0)
+    m = st.mass()
+    assert m["clipped"] == 0.0
+    assert abs(-m["bnd_flux"] - Q * 5.0) <= 1e-12 * Q * 5.0
+    assert abs(m["mass"] - Q * 5.0) <= 1e-12 * Q * 5.0
+    st32 = gpu_state(sc, swe.FP32)
+    st32.run_until(5.0)
+    m32 = st32.mass()
+    assert abs(-m32["bnd_flux"] - Q * 5.0) <= 1e-6 * Q * 5.0
+
+
 @pytest.mark.parametrize("kind", ["weir", "hq"])
 def test_imposed_outflows(swe, kind):
     bc = (S.BC(2, S.OUTFLOW_WEIR, slope=1.0, par=0.6) if kind == "weir"

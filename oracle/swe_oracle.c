@@ -702,8 +702,8 @@ int om_sim_set_morpho(om_sim *s, int32_t clos, double alpha, double mexp, double
 }
 
 /* ---------------------------------------------------------------------------
- * Draining-time positivity limiter (the survey's replacement of the clip;
- * the paper's scheme only clips).  Reading of the draining-time idea for
+ * Draining-time positivity limiter (an option that replaces the clip; the
+ * paper is silent on positivity).  Reading of the draining-time idea for
  * explicit finite volumes: a cell can lose at most the water it holds in a
  * step, so every flux that leaves a cell acts only for that cell's draining
  * time T = h |Omega| / (sum of its outgoing mass fluxes l F_h), i.e. is

@@ -1,5 +1,5 @@
-"""Pins of the draining-time positivity limiter in the oracle (the survey's
-replacement of the positivity clip of the update: every flux leaving a cell
+"""Pins of the draining-time positivity limiter in the oracle (an option that
+replaces the positivity clip of the update: every flux leaving a cell
 acts only for that cell's draining time h |Omega| / (its outgoing mass flux)):
 
 * no cell drains in a wet flow, so the limiter changes nothing (bitwise);

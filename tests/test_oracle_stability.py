@@ -4,7 +4,7 @@ grow.  Holds at the default CFL 0.9 on the quality Delaunay meshes the
 workloads use (every angle above 28 degrees, bumpy bed with dry islands), and
 at CFL 0.5 on structured right triangles; on right triangles CFL 0.9 lets the
 perturbation grow to order one, which is why the right-triangle generators of
-long runs use 0.5 (the survey's short dam-break runs keep 0.9)."""
+long runs use 0.5 (the short dam-break runs keep 0.9)."""
 import numpy as np
 import pytest
 

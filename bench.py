@@ -322,7 +322,8 @@ def main():
         o = time_gpu(sc, other, max(50, args.steps // 5), 10)
         variants[f"{sc.name}_{other}"] = {"cell_updates_per_s": o["rate"], "us_per_step": o["ms_step"] * 1e3,
                                           "roofline_frac": ALGO_BYTES[other] * N / (o["ms_step"] * 1e-3) / 1e9
-                                          / HBM_PEAK_GBS, "block_cpt": o["tune"]}
+                                          / HBM_PEAK_GBS, "block_cpt": o["tune"],
+                                          "traffic": measured_traffic(sc.name, other, o["tune"][0])}
         log(f"[bench] {other}: {o['ms_step'] * 1e3:.1f} us/step")
         lake = make_workload("lake")
         for p in ("fp32", "fp64"):

@@ -31,26 +31,35 @@ _c_int32_p = ctypes.POINTER(ctypes.c_int32)
 _c_int64_p = ctypes.POINTER(ctypes.c_int64)
 
 
+_LIB_OMP = os.path.join(_HERE, "liboracle_omp.so")
+
+
 def build(force: bool = True) -> str:
-    """Compile the oracle with gcc (plain C, FP64, no contraction)."""
-    if force or not os.path.exists(_LIB):
-        tmp = _LIB + ".tmp"
-        cmd = ["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fPIC",
-               "-shared", "-o", tmp, _SRC, "-lm"]
-        subprocess.check_call(cmd)
-        os.replace(tmp, _LIB)
+    """Compile the oracle with gcc (plain C, FP64, no contraction): the
+    serial library, and the same source with OpenMP (its edge and cell loops
+    on all cores, every sum still taken in the serial order, so both give
+    bitwise the same results)."""
+    for out, extra in ((_LIB, []), (_LIB_OMP, ["-fopenmp"])):
+        if force or not os.path.exists(out):
+            tmp = out + ".tmp"
+            cmd = ["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fPIC"] + extra + \
+                  ["-shared", "-o", tmp, _SRC, "-lm"]
+            subprocess.check_call(cmd)
+            os.replace(tmp, out)
     return _LIB
 
 
-_lib = None
+_libs = {}
 
 
-def lib():
-    global _lib
-    if _lib is None:
-        if not os.path.exists(_LIB):
-            build()
-        L = ctypes.CDLL(_LIB)
+def lib(omp: bool = False):
+    """The serial oracle library, or its OpenMP build (omp=True)."""
+    L = _libs.get(omp)
+    if L is None:
+        path = _LIB_OMP if omp else _LIB
+        if not os.path.exists(path):
+            build(force=False)
+        L = ctypes.CDLL(path)
         L.om_mesh_new.restype = ctypes.c_void_p
         L.om_mesh_new.argtypes = [_c_double_p, ctypes.c_int64, _c_int32_p, ctypes.c_int64,
                                   _c_int32_p, _c_int32_p, ctypes.c_int64, ctypes.c_char_p, ctypes.c_int]
@@ -103,8 +112,17 @@ def lib():
         L.om_sed_cell.argtypes = [ctypes.c_int32] + [ctypes.c_double] * 12 + [_c_double_p] * 4
         L.om_sim_set_friction.restype = ctypes.c_int
         L.om_sim_set_friction.argtypes = [ctypes.c_void_p, ctypes.c_int32, _c_double_p, ctypes.c_char_p, ctypes.c_int]
-        _lib = L
-    return _lib
+        L.om_sim_set_bed.restype = ctypes.c_int
+        L.om_sim_set_bed.argtypes = [ctypes.c_void_p, _c_double_p, _c_double_p, ctypes.c_char_p, ctypes.c_int]
+        L.om_threads.restype = ctypes.c_int
+        L.om_threads.argtypes = [ctypes.c_int]
+        _libs[omp] = L
+    return L
+
+
+def threads(n: int = 0) -> int:
+    """Threads of the OpenMP oracle (n > 0 sets them)."""
+    return lib(True).om_threads(n)
 
 
 def _dp(a: Optional[np.ndarray]):
@@ -158,8 +176,10 @@ def friction_closure(kind, coef, qabs, h, dt, h_min=1e-4):
 
 
 class Mesh:
-    def __init__(self, nodes, tri, bnd_seg=None, bnd_tag=None):
-        L = lib()
+    """Oracle mesh; omp=True uses the OpenMP build (its states too)."""
+
+    def __init__(self, nodes, tri, bnd_seg=None, bnd_tag=None, omp: bool = False):
+        L = self._L = lib(omp)
         self.nodes = np.ascontiguousarray(nodes, np.float64)
         self.tri = np.ascontiguousarray(tri, np.int32)
         seg = np.zeros((0, 2), np.int32) if bnd_seg is None else np.ascontiguousarray(bnd_seg, np.int32)
@@ -173,32 +193,33 @@ class Mesh:
 
     @property
     def n_edges(self):
-        return lib().om_mesh_n_edges(self._p)
+        return self._L.om_mesh_n_edges(self._p)
 
     @property
     def n_boundary_edges(self):
-        return lib().om_mesh_n_boundary_edges(self._p)
+        return self._L.om_mesh_n_boundary_edges(self._p)
 
     def geometry(self):
         n = self.n_cells
         out = dict(area=np.zeros(n), zb=np.zeros(n), rho=np.zeros((n, 3)), nx=np.zeros((n, 3)),
                    ny=np.zeros((n, 3)), length=np.zeros((n, 3)), nbr=np.zeros((n, 3), np.int32))
-        lib().om_mesh_geometry(self._p, _dp(out["area"]), _dp(out["zb"]), _dp(out["rho"]), _dp(out["nx"]),
+        self._L.om_mesh_geometry(self._p, _dp(out["area"]), _dp(out["zb"]), _dp(out["rho"]), _dp(out["nx"]),
                                _dp(out["ny"]), _dp(out["length"]), _ip(out["nbr"]))
         return out
 
     def __del__(self):
         if getattr(self, "_p", None):
-            lib().om_mesh_free(self._p)
+            self._L.om_mesh_free(self._p)
             self._p = None
 
 
 class Sim:
     """One FP64 oracle run of a scenario (see swe_inputs.Scenario)."""
 
-    def __init__(self, sc, t0: float = 0.0, mesh: Optional[Mesh] = None, dt_max: Optional[float] = None):
-        L = lib()
-        self.mesh = mesh or Mesh(sc.nodes, sc.tri, sc.bnd_seg, sc.bnd_tag)
+    def __init__(self, sc, t0: float = 0.0, mesh: Optional[Mesh] = None, dt_max: Optional[float] = None,
+                 omp: bool = False):
+        self.mesh = mesh or Mesh(sc.nodes, sc.tri, sc.bnd_seg, sc.bnd_tag, omp=omp)
+        L = self._L = self.mesh._L
         n = sc.n_cells
         bcs = sc.bcs
         tags = np.array([b.tag for b in bcs], np.int32)
@@ -250,7 +271,7 @@ class Sim:
     def set_drain(self, on):
         """Draining-time positivity limiter on or off."""
         err = ctypes.create_string_buffer(256)
-        if lib().om_sim_set_drain(self._p, int(bool(on)), err, 256):
+        if self._L.om_sim_set_drain(self._p, int(bool(on)), err, 256):
             raise OracleError(err.value.decode())
 
     def set_morpho(self, mo):
@@ -258,20 +279,29 @@ class Sim:
         zr = None if mo.z_rel is None else np.ascontiguousarray(mo.z_rel, np.float64)
         self._keep.append(zr)
         err = ctypes.create_string_buffer(256)
-        if lib().om_sim_set_morpho(self._p, SED[mo.closure], mo.alpha, mo.m, mo.thr, mo.d_m, mo.s_rel,
+        if self._L.om_sim_set_morpho(self._p, SED[mo.closure], mo.alpha, mo.m, mo.thr, mo.d_m, mo.s_rel,
                                    mo.porosity, _dp(zr), err, 256):
+            raise OracleError(err.value.decode())
+
+    def set_bed(self, z, H=None):
+        """Cell beds per cell instead of the node means, with surfaces H (or
+        None to keep each cell's depth)."""
+        z = np.ascontiguousarray(z, np.float64)
+        H = None if H is None else np.ascontiguousarray(H, np.float64)
+        err = ctypes.create_string_buffer(256)
+        if self._L.om_sim_set_bed(self._p, _dp(z), _dp(H), err, 256):
             raise OracleError(err.value.decode())
 
     def bed(self):
         z = np.zeros(self.n)
-        lib().om_get_bed(self._p, _dp(z))
+        self._L.om_get_bed(self._p, _dp(z))
         return z
 
     def morpho_diag(self):
         """Sediment volume (1 - p) sum z |cell|, the volume that left through
         open boundaries, and the volume the fixed-bed clip added."""
         v, b, c = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
-        lib().om_morpho_diag(self._p, ctypes.byref(v), ctypes.byref(b), ctypes.byref(c))
+        self._L.om_morpho_diag(self._p, ctypes.byref(v), ctypes.byref(b), ctypes.byref(c))
         return v.value, b.value, c.value
 
     def set_sources(self, region, sources):
@@ -285,25 +315,25 @@ class Sim:
         v = np.concatenate([np.asarray(x.v, np.float64) for x in sources if x.v is not None] or [np.zeros(0)])
         self._keep += [region, mode, unit, npts, t, v]
         err = ctypes.create_string_buffer(256)
-        if lib().om_sim_set_sources(self._p, _ip(region), len(sources), _ip(mode), _ip(unit), _ip(npts), _dp(t),
+        if self._L.om_sim_set_sources(self._p, _ip(region), len(sources), _ip(mode), _ip(unit), _ip(npts), _dp(t),
                                     _dp(v), err, 256):
             raise OracleError(err.value.decode())
 
     def source_volume(self):
         """Volume the external sources added so far (negative: removed)."""
-        return lib().om_source_volume(self._p)
+        return self._L.om_source_volume(self._p)
 
     def __del__(self):
         if getattr(self, "_p", None):
-            lib().om_sim_free(self._p)
+            self._L.om_sim_free(self._p)
             self._p = None
 
     def next_dt(self, t_end=float("inf")):
-        return lib().om_next_dt(self._p, t_end)
+        return self._L.om_next_dt(self._p, t_end)
 
     def step(self, t_end=float("inf")):
         dt = ctypes.c_double()
-        rc = lib().om_step(self._p, t_end, ctypes.byref(dt))
+        rc = self._L.om_step(self._p, t_end, ctypes.byref(dt))
         if rc:
             e = OracleError(f"oracle step failed ({rc})")
             e.code = rc
@@ -312,7 +342,7 @@ class Sim:
 
     def run_until(self, t_end, max_steps=0):
         n = ctypes.c_int64()
-        rc = lib().om_run_until(self._p, t_end, max_steps, ctypes.byref(n))
+        rc = self._L.om_run_until(self._p, t_end, max_steps, ctypes.byref(n))
         if rc:
             e = OracleError(f"oracle run failed ({rc})")
             e.code = rc
@@ -325,12 +355,12 @@ class Sim:
     def state(self):
         H, qx, qy = np.zeros(self.n), np.zeros(self.n), np.zeros(self.n)
         t = ctypes.c_double()
-        lib().om_get_state(self._p, _dp(H), _dp(qx), _dp(qy), ctypes.byref(t))
+        self._L.om_get_state(self._p, _dp(H), _dp(qx), _dp(qy), ctypes.byref(t))
         return H, qx, qy, t.value
 
     def set_state(self, H, qx, qy, t):
         H, qx, qy = (np.ascontiguousarray(a, np.float64) for a in (H, qx, qy))
-        lib().om_set_state(self._p, _dp(H), _dp(qx), _dp(qy), t)
+        self._L.om_set_state(self._p, _dp(H), _dp(qx), _dp(qy), t)
 
     @property
     def t(self):
@@ -339,18 +369,18 @@ class Sim:
     def scalars(self):
         """Specific masses q = h phi, (species, cells)."""
         q = np.zeros((self.ns, self.n))
-        lib().om_get_scalars(self._p, _dp(q))
+        self._L.om_get_scalars(self._p, _dp(q))
         return q
 
     def scalar_diag(self):
         """Per species: total mass, the mass that left through open boundaries,
         and the mass set by resetting cells left dry."""
         m, b, c = (np.zeros(max(self.ns, 1)) for _ in range(3))
-        lib().om_scalar_diag(self._p, _dp(m), _dp(b), _dp(c))
+        self._L.om_scalar_diag(self._p, _dp(m), _dp(b), _dp(c))
         return m[:self.ns], b[:self.ns], c[:self.ns]
 
     def diag(self):
         m, b, c = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
         s = ctypes.c_int64()
-        lib().om_diag(self._p, ctypes.byref(m), ctypes.byref(b), ctypes.byref(c), ctypes.byref(s))
+        self._L.om_diag(self._p, ctypes.byref(m), ctypes.byref(b), ctypes.byref(c), ctypes.byref(s))
         return dict(mass=m.value, bnd_flux=b.value, clipped=c.value, steps=s.value)

@@ -22,6 +22,9 @@
 #include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 /* depth below which a reconstructed edge state is dry [m] */
 #define OM_H_DRY 1e-12
@@ -88,6 +91,12 @@ struct om_sim {
      * time / dt), and per (cell, local edge) the mass leaving through it */
     int drain;
     double *theta, *dout;
+    /* per-edge boundary volumes and per-cell clip / source volumes of the
+     * step being taken: the loops fill them in any order (the OpenMP build
+     * runs them on all cores), then the Neumaier sums take them in edge or
+     * cell order, exactly as a serial loop would */
+    double *ebvol, *cclip, *csrcv;
+    unsigned char *eflag, *cflag;
 };
 
 static void seterr(char *err, int len, const char *msg) {
@@ -304,6 +313,7 @@ void om_sim_free(om_sim *s) {
     free(s->src); free(s->csrc); free(s->sfac);
     free(s->zfix); free(s->bcont);
     free(s->theta); free(s->dout);
+    free(s->ebvol); free(s->eflag); free(s->cclip); free(s->csrcv); free(s->cflag);
     free(s);
 }
 
@@ -330,7 +340,13 @@ om_sim *om_sim_new(const om_mesh *m, double g, double cfl, double h_min, double 
     s->cont = malloc(sizeof(double) * 9 * nc);
     s->ebc = malloc(sizeof(int32_t) * m->ne);
     s->bc = calloc((size_t)(nbc > 0 ? nbc : 1), sizeof(om_bc));
-    if (!s->z || !s->H || !s->qx || !s->qy || !s->gn2 || !s->cont || !s->ebc || !s->bc) {
+    s->ebvol = malloc(sizeof(double) * (m->ne > 0 ? m->ne : 1));
+    s->eflag = malloc(m->ne > 0 ? (size_t)m->ne : 1);
+    s->cclip = malloc(sizeof(double) * (nc > 0 ? nc : 1));
+    s->csrcv = malloc(sizeof(double) * (nc > 0 ? nc : 1));
+    s->cflag = malloc(nc > 0 ? (size_t)nc : 1);
+    if (!s->z || !s->H || !s->qx || !s->qy || !s->gn2 || !s->cont || !s->ebc || !s->bc || !s->ebvol ||
+        !s->eflag || !s->cclip || !s->csrcv || !s->cflag) {
         seterr(err, elen, "out of memory"); goto fail;
     }
     for (int64_t i = 0; i < nc; i++) {
@@ -724,6 +740,22 @@ int om_sim_set_drain(om_sim *s, int on, char *err, int elen) {
     return 0;
 }
 
+/* Cell beds given per cell instead of the node means (a restart of a run
+ * whose bed moved, or a bed stored at lower precision), with the surface
+ * H per cell, or NULL to keep each cell's depth; a surface below its bed
+ * is a dry cell (H = z), as in the initial conditions. */
+int om_sim_set_bed(om_sim *s, const double *z, const double *H, char *err, int elen) {
+    const int64_t nc = s->m->nc;
+    for (int64_t i = 0; i < nc; i++)
+        if (!isfinite(z[i]) || (H && !isfinite(H[i]))) { seterr(err, elen, "non-finite bed or surface"); return -1; }
+    for (int64_t i = 0; i < nc; i++) {
+        double Hn = H ? H[i] : z[i] + (s->H[i] - s->z[i]);
+        s->H[i] = Hn > z[i] ? Hn : z[i];
+        s->z[i] = z[i];
+    }
+    return 0;
+}
+
 void om_get_bed(const om_sim *s, double *z) { memcpy(z, s->z, sizeof(double) * (size_t)s->m->nc); }
 
 /* Sediment volume (1 - p) sum z |Omega| (Neumaier), the volume that left
@@ -876,6 +908,8 @@ static void cell_velocity(const om_sim *s, int32_t i, double *h, double *u, doub
 double om_next_dt(const om_sim *s, double t_end) {
     const om_mesh *m = s->m;
     double best = INFINITY;
+    /* the minimum does not depend on the order cells are visited in */
+#pragma omp parallel for schedule(static) reduction(min : best)
     for (int64_t i = 0; i < m->nc; i++) {
         double h, u, v;
         cell_velocity(s, (int32_t)i, &h, &u, &v);
@@ -1163,9 +1197,15 @@ int om_step(om_sim *s, double t_end, double *dt_taken) {
             s->theta[i] = leave > vol ? vol / leave : 1.0;
         }
     }
+    /* every edge writes only its own two contribution slots, so the edge
+     * loop may run in any order; the species and sediment passes accumulate
+     * per edge and stay serial */
+    const int par_edges = s->ns == 0 && !s->morpho;
+#pragma omp parallel for schedule(static) if (par_edges)
     for (int64_t e = 0; e < m->ne; e++) {
         int32_t L = m->eL[e], R = m->eR[e];
         double nx = m->enx[e], ny = m->eny[e], l = m->elen[e];
+        s->eflag[e] = 0;
         if (internal_wall(s, e)) {
             /* each side sees a wall: its own reflected state */
             wall_side(s, L, m->ekL[e], nx, ny, l);
@@ -1202,15 +1242,22 @@ int om_step(om_sim *s, double t_end, double *dt_taken) {
             s->cont[9 * R + 3 * kR + 1] = -(l * (dRn * nx - F[2] * ny));
             s->cont[9 * R + 3 * kR + 2] = -(l * (dRn * ny + F[2] * nx));
         } else if (open) {
-            neumaier(&bstep, &bstepc, dt * cL0);
+            s->ebvol[e] = dt * cL0;
+            s->eflag[e] = 1;
         }
         if (s->ns > 0)
             scalar_edge(s, L, R, kL, R >= 0 ? m->ekR[e] : 0, l, F[0], wall, inflow_b, open, dt, sbst, sbstc);
         if (s->morpho)
             sed_edge(s, L, R, kL, R >= 0 ? m->ekR[e] : 0, l, nx, ny, open, dt, &bvst, &bvstc);
     }
+    /* volume through open boundary edges this step, in edge order */
+    for (int64_t e = 0; e < m->ne; e++)
+        if (s->eflag[e]) neumaier(&bstep, &bstepc, s->ebvol[e]);
+    int nonfinite = 0;
+#pragma omp parallel for schedule(static) reduction(| : nonfinite, deficit)
     for (int64_t i = 0; i < m->nc; i++) {
         const double *c = &s->cont[9 * i];
+        unsigned char flag = 0;
         double Rh = c[0] + c[3] + c[6];
         double Rx = c[1] + c[4] + c[7];
         double Ry = c[2] + c[5] + c[8];
@@ -1237,7 +1284,8 @@ int om_step(om_sim *s, double t_end, double *dt_taken) {
             }
             if (empty) { if (avail > 0.0) H = s->z[i]; }
             else H = H + dh;
-            neumaier(&s->ssum, &s->scomp, dh * m->area[i]);
+            s->csrcv[i] = dh * m->area[i];
+            flag |= 1;
             double hn = H - s->z[i];
             s->sfac[i] = (dh < 0.0 && hf > 0.0) ? (hn > 0.0 ? hn / hf : 0.0) : 1.0;
         }
@@ -1248,14 +1296,21 @@ int om_step(om_sim *s, double t_end, double *dt_taken) {
         if (h < 0.0) {
             /* positivity: the scheme's CFL does not bound the outflow of a
              * cell draining through several edges; clip and account for it */
-            double add = -h * m->area[i];
-            neumaier(&s->clip, &s->clipc, add);
+            s->cclip[i] = -h * m->area[i];
+            flag |= 2;
             H = s->z[i];
             qx = 0.0; qy = 0.0;
         }
-        if (!isfinite(H) || !isfinite(qx) || !isfinite(qy)) return -4;
+        if (!isfinite(H) || !isfinite(qx) || !isfinite(qy)) nonfinite = 1;
+        s->cflag[i] = flag;
         s->H[i] = H; s->qx[i] = qx; s->qy[i] = qy;
     }
+    /* the sources' and the clip's volumes, each summed in cell order */
+    for (int64_t i = 0; i < m->nc; i++)
+        if (s->cflag[i] & 1) neumaier(&s->ssum, &s->scomp, s->csrcv[i]);
+    for (int64_t i = 0; i < m->nc; i++)
+        if (s->cflag[i] & 2) neumaier(&s->clip, &s->clipc, s->cclip[i]);
+    if (nonfinite) return -4;
     for (int c = 0; c < s->ns; c++) {
         /* eq. scl:updateformula with the advective fluxes */
         double *q = s->sq + c * m->nc;
@@ -1295,6 +1350,17 @@ int om_step(om_sim *s, double t_end, double *dt_taken) {
     s->t += dt;
     s->steps++;
     return deficit ? -8 : 0;
+}
+
+/* Threads the OpenMP build uses (n > 0 sets them); 1 in the serial build. */
+int om_threads(int n) {
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+    return omp_get_max_threads();
+#else
+    (void)n;
+    return 1;
+#endif
 }
 
 int om_run_until(om_sim *s, double t_end, int64_t max_steps, int64_t *n_steps) {

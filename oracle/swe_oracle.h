@@ -89,6 +89,11 @@ enum { OM_SED_MPM = 0, OM_SED_GRASS = 1, OM_SED_EH = 2 };
 int om_sim_set_morpho(om_sim *s, int32_t closure, double alpha, double m, double thr, double d_m, double s_rel,
                       double porosity, const double *z_rel, char *err, int err_len);
 void om_get_bed(const om_sim *s, double *z);
+/* Cell beds per cell (instead of the node means) with surfaces H, or NULL
+ * to keep each cell's depth.  0 or -1 (message in err). */
+int om_sim_set_bed(om_sim *s, const double *z, const double *H, char *err, int err_len);
+/* Threads of the OpenMP build (n > 0 sets them); the serial build returns 1. */
+int om_threads(int n);
 /* draining-time positivity limiter on (1) or off (0, the default) */
 int om_sim_set_drain(om_sim *s, int on, char *err, int err_len);
 void om_morpho_diag(const om_sim *s, double *volume, double *bnd, double *clipped);

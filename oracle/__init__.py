@@ -6,12 +6,10 @@ its Python binding) never touches it, and the two share no code: the oracle is
 plain C (``swe_oracle.c``, compiled with ``gcc -ffp-contract=off``) driven
 through ctypes from here.
 
-Parity pins for each function are in ``tests/test_oracle_*.py``.  The one part
-without a pin independent of the oracle itself is the inflow boundary's
-delivered discharge in subcritical flow (the ghost-state inflow does not impose
-Q exactly there): parity unpinned for the value of the boundary-flux integral
-under a subcritical inflow, only its role in the mass balance is pinned.  A
-supercritical inflow (uniform or froude) is pinned exactly: it delivers Q t.
+Parity pins for each function are in ``tests/test_oracle_*.py``.  The inflow
+conditions impose their discharge as the edge mass flux, so the volume they
+deliver is pinned exactly (the hydrograph's, sum over steps of Q(t^n) dt) in
+sub- and supercritical flow alike.
 """
 from __future__ import annotations
 
@@ -114,6 +112,12 @@ def lib(omp: bool = False):
         L.om_sim_set_friction.argtypes = [ctypes.c_void_p, ctypes.c_int32, _c_double_p, ctypes.c_char_p, ctypes.c_int]
         L.om_sim_set_bed.restype = ctypes.c_int
         L.om_sim_set_bed.argtypes = [ctypes.c_void_p, _c_double_p, _c_double_p, ctypes.c_char_p, ctypes.c_int]
+        L.om_sim_set_diffusion.restype = ctypes.c_int
+        L.om_sim_set_diffusion.argtypes = [ctypes.c_void_p, _c_double_p, ctypes.c_double, ctypes.c_double,
+                                           ctypes.c_double, _c_double_p, ctypes.c_char_p, ctypes.c_int]
+        L.om_get_psi.argtypes = [ctypes.c_void_p, _c_double_p]
+        L.om_bc_flux.restype = ctypes.c_double
+        L.om_bc_flux.argtypes = [ctypes.c_void_p, ctypes.c_int32]
         L.om_threads.restype = ctypes.c_int
         L.om_threads.argtypes = [ctypes.c_int]
         _libs[omp] = L
@@ -232,6 +236,7 @@ class Sim:
         h0 = None if sc.h0 is None else np.ascontiguousarray(sc.h0, np.float64)
         pars = np.array([getattr(b, "par", 0.0) for b in bcs], np.float64)
         self._keep = [tags, kinds, slopes, npts, bt, bQ, H0, h0, pars]
+        self._bcs = list(bcs)
         qx0 = np.ascontiguousarray(sc.qx0, np.float64)
         qy0 = np.ascontiguousarray(sc.qy0, np.float64)
         man = np.ascontiguousarray(sc.manning, np.float64)
@@ -261,12 +266,32 @@ class Sim:
             if L.om_sim_set_scalars(self._p, ns, _dp(phi0), _dp(pin), err, 256):
                 raise OracleError(err.value.decode())
             self.ns = ns
+        if getattr(sc, "diffusion", None) is not None:
+            self.set_diffusion(sc.diffusion)
         if len(getattr(sc, "sources", ())):
             self.set_sources(sc.src_region, sc.sources)
         if getattr(sc, "morpho", None) is not None:
             self.set_morpho(sc.morpho)
         if getattr(sc, "drain", False):
             self.set_drain(True)
+
+    def set_diffusion(self, df, psi0=None):
+        """Diffusion of the species (swe_inputs.Diffusion: per-species
+        molecular diffusivity Km, dispersion alpha_L, alpha_T, relaxation
+        time zeta); psi0 (species, cells, 2) initial auxiliary variables."""
+        km = np.ascontiguousarray(np.broadcast_to(np.asarray(df.Km, np.float64), (self.ns,)))
+        p0 = None if psi0 is None else np.ascontiguousarray(psi0, np.float64)
+        self._keep += [km, p0]
+        err = ctypes.create_string_buffer(256)
+        if self._L.om_sim_set_diffusion(self._p, _dp(km), df.alpha_L, df.alpha_T, df.zeta, _dp(p0), err, 256):
+            raise OracleError(err.value.decode())
+
+    def psi(self):
+        """Auxiliary variables (psi_x, psi_y) of the diffusing species,
+        (species, cells, 2)."""
+        p = np.zeros((self.ns, self.n, 2))
+        self._L.om_get_psi(self._p, _dp(p))
+        return p
 
     def set_drain(self, on):
         """Draining-time positivity limiter on or off."""
@@ -378,6 +403,14 @@ class Sim:
         m, b, c = (np.zeros(max(self.ns, 1)) for _ in range(3))
         self._L.om_scalar_diag(self._p, _dp(m), _dp(b), _dp(c))
         return m[:self.ns], b[:self.ns], c[:self.ns]
+
+    def bc_flux(self, tag):
+        """Boundary-flux integral over the edges tagged `tag` (the first
+        condition given for the tag), positive where water left."""
+        for b, bc in enumerate(self._bcs):
+            if bc.tag == tag:
+                return self._L.om_bc_flux(self._p, b)
+        return 0.0
 
     def diag(self):
         m, b, c = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()

@@ -62,6 +62,7 @@ struct om_sim {
     int32_t *ebc;        /* per edge: index into bc[] or -1 (wall) */
     double *cont;        /* 9*nc: contribution of each local edge, 3 components */
     double bsum, bcomp;  /* Neumaier sum of dt * l * mass flux leaving the domain */
+    double *bcsum;       /* per boundary condition: the same sum over its edges (sum, compensation) */
     double clip, clipc;  /* Neumaier sum of volume added by the positivity clip */
     int64_t steps;
     /* passive scalars (section "Scalar advection-diffusion"): per species c
@@ -70,6 +71,16 @@ struct om_sim {
     double *sq, *sphi, *scont, *phi_in;
     double sbsum[OM_MAX_SPECIES], sbcomp[OM_MAX_SPECIES];
     double sclip[OM_MAX_SPECIES], sclipc[OM_MAX_SPECIES];  /* mass set by the dry-cell reset */
+    /* diffusion of the species by the relaxation system of eq.
+     * relaxation_terms: per species the molecular diffusivity dKm, the
+     * dispersion coefficients daL, daT and the relaxation time dzeta; per
+     * species and cell the auxiliary variables (psi_x, psi_y) [ns][nc][2]; per
+     * cell at t^n its depth and turbulent dispersion tensor (h, Kxx, Kxy,
+     * Kyy), with h = 0 for a cell at or below h_min; per species, cell and
+     * local edge the diffusive contributions (q, psi_x, psi_y) */
+    int diff;
+    double dKm[OM_MAX_SPECIES], daL, daT, dzeta;
+    double *spsi, *dK, *dcont;
     /* external water sources and sinks S_h: per region the mode (kind),
      * the series of its value (t, Q) and the factor from that value to a
      * rate in m/s (length); per cell the region or -1 */
@@ -309,11 +320,12 @@ void om_sim_free(om_sim *s) {
     for (int b = 0; b < s->nbc; b++) { free(s->bc[b].t); free(s->bc[b].Q); }
     free(s->z); free(s->bc); free(s->ebc); free(s->H); free(s->qx); free(s->qy); free(s->gn2); free(s->cont);
     free(s->sq); free(s->sphi); free(s->scont); free(s->phi_in);
+    free(s->spsi); free(s->dK); free(s->dcont);
     for (int r = 0; r < s->nsrc; r++) { free(s->src[r].t); free(s->src[r].Q); }
     free(s->src); free(s->csrc); free(s->sfac);
     free(s->zfix); free(s->bcont);
     free(s->theta); free(s->dout);
-    free(s->ebvol); free(s->eflag); free(s->cclip); free(s->csrcv); free(s->cflag);
+    free(s->ebvol); free(s->eflag); free(s->cclip); free(s->csrcv); free(s->cflag); free(s->bcsum);
     free(s);
 }
 
@@ -345,8 +357,9 @@ om_sim *om_sim_new(const om_mesh *m, double g, double cfl, double h_min, double 
     s->cclip = malloc(sizeof(double) * (nc > 0 ? nc : 1));
     s->csrcv = malloc(sizeof(double) * (nc > 0 ? nc : 1));
     s->cflag = malloc(nc > 0 ? (size_t)nc : 1);
+    s->bcsum = calloc((size_t)2 * (nbc > 0 ? nbc : 1), sizeof(double));
     if (!s->z || !s->H || !s->qx || !s->qy || !s->gn2 || !s->cont || !s->ebc || !s->bc || !s->ebvol ||
-        !s->eflag || !s->cclip || !s->csrcv || !s->cflag) {
+        !s->eflag || !s->cclip || !s->csrcv || !s->cflag || !s->bcsum) {
         seterr(err, elen, "out of memory"); goto fail;
     }
     for (int64_t i = 0; i < nc; i++) {
@@ -538,13 +551,14 @@ double om_source_volume(const om_sim *s) { return s->ssum + s->scomp; }
  * table's inflow options): the unit discharge q = Q / length enters with the
  * depth at which the flow has the given Froude number, u = Fr sqrt(g h) and
  * q = u h, so h = (q / (Fr sqrt(g)))^(2/3).  Returns 0 when Q <= 0 (wall). */
-static int froude_ghost(const om_sim *s, const om_bc *B, double t, double *hg, double *ung) {
+static int froude_ghost(const om_sim *s, const om_bc *B, double t, double *hg, double *ung, double *qin) {
     double Q = hydrograph(B, t);
     if (!(Q > 0)) return 0;
     double q = Q / B->length;
     double h = pow(q / (B->slope * sqrt(s->g)), 2.0 / 3.0);
     *hg = h;
     *ung = -q / h;
+    if (qin) *qin = q;
     return 1;
 }
 
@@ -770,10 +784,12 @@ void om_morpho_diag(const om_sim *s, double *vol, double *bnd, double *clipped) 
 }
 
 /* Inflow "uniform(discharge, slope)" (section "Hydrodynamic BCs"): the given
- * discharge is spread over the boundary length; reading: the ghost carries
- * the Manning normal depth for that unit discharge, q = h^{5/3} sqrt(S) / n,
- * flowing into the domain.  Returns 0 when Q <= 0 (edge acts as a wall). */
-static int inflow_ghost(const om_sim *s, const om_bc *B, int32_t cell, double t, double *hg, double *ung) {
+ * discharge is spread over the boundary length; reading: the boundary state
+ * carries the Manning normal depth for that unit discharge, q = h^{5/3}
+ * sqrt(S) / n, flowing into the domain.  Returns 0 when Q <= 0 (edge acts as
+ * a wall); *qin (may be NULL) receives q. */
+static int inflow_ghost(const om_sim *s, const om_bc *B, int32_t cell, double t, double *hg, double *ung,
+                        double *qin) {
     double Q = hydrograph(B, t);
     if (!(Q > 0)) return 0;
     double q = Q / B->length;
@@ -781,6 +797,7 @@ static int inflow_ghost(const om_sim *s, const om_bc *B, int32_t cell, double t,
     double h = pow(n * q / sqrt(B->slope), 0.6);
     *hg = h;
     *ung = -q / h;   /* the normal points out of the domain */
+    if (qin) *qin = q;
     return 1;
 }
 
@@ -918,8 +935,22 @@ double om_next_dt(const om_sim *s, double t_end) {
         for (int k = 0; k < 3; k++) {
             int32_t e = m->cell_edge[3 * i + k];
             double sg = (m->eL[e] == i) ? 1.0 : -1.0;
-            double un = u * (sg * m->enx[e]) + v * (sg * m->eny[e]);
+            double nx = sg * m->enx[e], ny = sg * m->eny[e];
+            double un = u * nx + v * ny;
             double lam = fabs(un) + c;
+            if (s->diff) {
+                /* reading: the relaxation waves +-sqrt(K_nn / zeta) of the
+                 * diffusing species bound the step too */
+                double kt = 0.0, um2 = u * u + v * v, cf2 = cell_cf2(s, i, h);
+                if (um2 > 0.0 && cf2 > 0.0) {
+                    double a = h * sqrt(um2 / cf2), dd = (s->daL - s->daT) / um2;
+                    kt = a * (s->daT + dd * (u * nx + v * ny) * (u * nx + v * ny));
+                }
+                double kmax = 0.0;
+                for (int q = 0; q < s->ns; q++) kmax = s->dKm[q] > kmax ? s->dKm[q] : kmax;
+                double lamd = fabs(un) + sqrt((kmax + kt) / s->dzeta);
+                if (lamd > lam) lam = lamd;
+            }
             double r = m->rho[3 * i + k] / lam;
             if (r < best) best = r;
         }
@@ -929,7 +960,7 @@ double om_next_dt(const om_sim *s, double t_end) {
         const om_bc *B = &s->bc[s->ebc[e]];
         if (B->kind != OM_INFLOW_UNIFORM) continue;
         double hg, ung;
-        if (!inflow_ghost(s, B, m->eL[e], s->t, &hg, &ung)) continue;
+        if (!inflow_ghost(s, B, m->eL[e], s->t, &hg, &ung, NULL)) continue;
         double lam = fabs(ung) + sqrt(s->g * hg);
         double r = m->rho[3 * m->eL[e] + m->ekL[e]] / lam;
         if (r < best) best = r;
@@ -939,7 +970,7 @@ double om_next_dt(const om_sim *s, double t_end) {
         const om_bc *B = &s->bc[s->ebc[e]];
         if (B->kind != OM_INFLOW_FROUDE) continue;
         double hg, ung;
-        if (!froude_ghost(s, B, s->t, &hg, &ung)) continue;
+        if (!froude_ghost(s, B, s->t, &hg, &ung, NULL)) continue;
         double lam = fabs(ung) + sqrt(s->g * hg);
         double r = m->rho[3 * m->eL[e] + m->ekL[e]] / lam;
         if (r < best) best = r;
@@ -981,6 +1012,9 @@ int om_sim_set_scalars(om_sim *s, int32_t ns, const double *phi0, const double *
     int64_t nc = m->nc;
     if (ns < 0 || ns > OM_MAX_SPECIES) { seterr(err, elen, "between 0 and 5 species"); return -1; }
     free(s->sq); free(s->sphi); free(s->scont); free(s->phi_in);
+    free(s->spsi); free(s->dK); free(s->dcont);
+    s->spsi = s->dK = s->dcont = NULL;
+    s->diff = 0;
     s->sq = calloc((size_t)(ns * nc + 1), sizeof(double));
     s->sphi = calloc((size_t)(ns * nc + 1), sizeof(double));
     s->scont = calloc((size_t)(3 * ns * nc + 1), sizeof(double));
@@ -1007,6 +1041,150 @@ int om_sim_set_scalars(om_sim *s, int32_t ns, const double *phi0, const double *
 
 void om_get_scalars(const om_sim *s, double *q) {
     if (q) memcpy(q, s->sq, (size_t)s->ns * (size_t)s->m->nc * sizeof(double));
+}
+
+/* Diffusion of the species (section "Scalar advection-diffusion"): the
+ * Cattaneo-type relaxation of eq. relaxation_terms adds per species the
+ * auxiliary variables psi = (psi_x, psi_y), which relax towards the gradient
+ * of the concentration with relaxation time zeta; the species flux gains the
+ * diffusive part -h K psi, and psi the flux -(phi / zeta) n (eq.
+ * vecform_scalar2).  K = K^m I + K^t (section "Scalar advection-diffusion
+ * closure relationships"): K^m per species, and the turbulent dispersion
+ * scaled by the friction velocity u_* = |u| / c_f and the depth; reading
+ * (the Elder form the two coefficients imply): K^t = h u_* (alpha_T I +
+ * (alpha_L - alpha_T) u u^T / |u|^2), with c_f from the cell's friction
+ * closure (none in frictionless cells).  Km (ns values >= 0), alpha_L,
+ * alpha_T >= 0, zeta > 0; psi0 (ns x nc x 2, or NULL = 0) the initial
+ * auxiliary variables.  Needs the species set first. */
+int om_sim_set_diffusion(om_sim *s, const double *Km, double alpha_L, double alpha_T, double zeta,
+                         const double *psi0, char *err, int elen) {
+    const int64_t nc = s->m->nc;
+    if (s->ns < 1) { seterr(err, elen, "diffusion needs species"); return -1; }
+    if (!(zeta > 0.0) || !isfinite(zeta)) { seterr(err, elen, "the relaxation time must be positive"); return -1; }
+    if (!(alpha_L >= 0.0) || !(alpha_T >= 0.0) || !isfinite(alpha_L) || !isfinite(alpha_T)) {
+        seterr(err, elen, "dispersion coefficients must be >= 0"); return -1;
+    }
+    for (int c = 0; c < s->ns; c++)
+        if (!(Km[c] >= 0.0) || !isfinite(Km[c])) { seterr(err, elen, "diffusivities must be >= 0"); return -1; }
+    free(s->spsi); free(s->dK); free(s->dcont);
+    s->spsi = calloc((size_t)(2 * s->ns * nc + 1), sizeof(double));
+    s->dK = calloc((size_t)(4 * nc + 1), sizeof(double));
+    s->dcont = calloc((size_t)(9 * s->ns * nc + 1), sizeof(double));
+    if (!s->spsi || !s->dK || !s->dcont) { seterr(err, elen, "out of memory"); return -1; }
+    if (psi0) {
+        for (int64_t k = 0; k < 2 * s->ns * nc; k++) {
+            if (!isfinite(psi0[k])) { seterr(err, elen, "non-finite auxiliary variable"); return -1; }
+            s->spsi[k] = psi0[k];
+        }
+    }
+    for (int c = 0; c < s->ns; c++) s->dKm[c] = Km[c];
+    s->daL = alpha_L; s->daT = alpha_T; s->dzeta = zeta;
+    s->diff = 1;
+    return 0;
+}
+
+void om_get_psi(const om_sim *s, double *psi) {
+    if (psi && s->diff) memcpy(psi, s->spsi, (size_t)2 * s->ns * (size_t)s->m->nc * sizeof(double));
+}
+
+/* Depth and turbulent dispersion tensor (h, Kxx, Kxy, Kyy) of every cell at
+ * t^n; h = 0 marks a cell at or below h_min, which takes part in no
+ * diffusive exchange. */
+static void diffusion_cells(om_sim *s) {
+    for (int64_t i = 0; i < s->m->nc; i++) {
+        double *K = s->dK + 4 * i;
+        double h = s->H[i] - s->z[i];
+        K[0] = K[1] = K[2] = K[3] = 0.0;
+        if (!(h > s->h_min)) continue;
+        K[0] = h;
+        double u = s->qx[i] / h, v = s->qy[i] / h;
+        double um2 = u * u + v * v;
+        double cf2 = cell_cf2(s, i, h);
+        if (!(um2 > 0.0) || !(cf2 > 0.0)) continue;
+        double us = sqrt(um2 / cf2);          /* u_* = |u| / c_f */
+        double a = h * us;
+        double d = (s->daL - s->daT) / um2;
+        K[1] = a * (s->daT + d * u * u);
+        K[2] = a * (d * u * v);
+        K[3] = a * (s->daT + d * v * v);
+    }
+}
+
+/* The interface flux of the relaxation system of species c on one side of
+ * an edge that carries no diffusive exchange (a boundary, an internal wall,
+ * or a neighbour at or below h_min), for a cell above h_min (cells at or
+ * below it receive no contribution, and their psi is reset to zero by the
+ * update): the mirrored ghost (phi, -psi_n, psi_t)
+ * gives the exact two-wave solution psi_n* = 0 (no diffusive flux of the
+ * species) and phi* = phi - sqrt(K_nn zeta) psi_n, where the species flux
+ * vanishes and psi receives -(phi* / zeta) n.  (nx, ny) is the outward normal
+ * of cell K. */
+static void diffusion_mirror(const om_sim *s, int c, int32_t K, int kK, double l, double nx, double ny) {
+    const int64_t nc = s->m->nc;
+    const double *Kt = s->dK + 4 * K;
+    if (!(Kt[0] > 0.0)) return;  /* a cell at or below h_min takes part in nothing */
+    const double *ps = s->spsi + 2 * (c * nc + K);
+    double knn = s->dKm[c] + (Kt[1] * nx * nx + 2.0 * Kt[2] * nx * ny + Kt[3] * ny * ny);
+    double psn = ps[0] * nx + ps[1] * ny;
+    double phs = s->sphi[c * nc + K] - sqrt(knn * s->dzeta) * psn;
+    double *d = s->dcont + 9 * (c * nc + K) + 3 * kK;
+    d[0] = 0.0;
+    d[1] = l * (-(phs / s->dzeta) * nx);
+    d[2] = l * (-(phs / s->dzeta) * ny);
+}
+
+/* Diffusive contributions of the edge e between L and R (n from L to R) for
+ * every species: the exact solution of the linear two-wave Riemann problem
+ * of the relaxation system in the edge's normal direction, with the
+ * interface depth the smaller of the two reconstructed depths hLs, hRs of
+ * the hydrodynamic flux (the wetted cross-section the edge shares; a cell
+ * next to a much deeper one then cannot receive more than its own depth
+ * carries, which keeps the update stable on thin layers) and the diffusion
+ * tensor the mean of the two cells' (readings).  Waves +-sqrt(K_nn / zeta) carry the invariants
+ * phi -+ sqrt(K_nn zeta) psi_n, so
+ *   psi_n* = (psi_nL + psi_nR) / 2 + (phi_R - phi_L) / (2 sqrt(K_nn zeta)),
+ *   phi*   = (phi_L + phi_R) / 2 + sqrt(K_nn zeta) (psi_nR - psi_nL) / 2,
+ * and the edge carries D_q = -h (K_nn psi_n* + K_nt psi_t) (psi_t the mean
+ * tangential component) and D_psi = -(phi* / zeta) n. */
+static void diffusion_edge(om_sim *s, int64_t e, int32_t L, int32_t R, int kL, int kR, double l, double nx,
+                           double ny, int closed, double hLs, double hRs) {
+    const int64_t nc = s->m->nc;
+    const double hi = hLs < hRs ? hLs : hRs;
+    for (int c = 0; c < s->ns; c++) {
+        const double *KL = s->dK + 4 * L;
+        if (R < 0 || closed || !(KL[0] > 0.0) || !(s->dK[4 * R] > 0.0) || !(hi > 0.0)) {
+            diffusion_mirror(s, c, L, kL, l, nx, ny);
+            if (R >= 0) diffusion_mirror(s, c, R, kR, l, -nx, -ny);
+            continue;
+        }
+        const double *KR = s->dK + 4 * R;
+        double h = hi;
+        double kxx = s->dKm[c] + 0.5 * (KL[1] + KR[1]);
+        double kxy = 0.5 * (KL[2] + KR[2]);
+        double kyy = s->dKm[c] + 0.5 * (KL[3] + KR[3]);
+        double knn = kxx * nx * nx + 2.0 * kxy * nx * ny + kyy * ny * ny;
+        double knt = -kxx * nx * ny + kxy * (nx * nx - ny * ny) + kyy * nx * ny;
+        const double *pL = s->spsi + 2 * (c * nc + L), *pR = s->spsi + 2 * (c * nc + R);
+        double pnL = pL[0] * nx + pL[1] * ny, pnR = pR[0] * nx + pR[1] * ny;
+        double ptL = -pL[0] * ny + pL[1] * nx, ptR = -pR[0] * ny + pR[1] * nx;
+        double fL = s->sphi[c * nc + L], fR = s->sphi[c * nc + R];
+        double Dq, fs;
+        if (knn > 0.0) {
+            double r = sqrt(knn * s->dzeta);
+            double pns = 0.5 * (pnL + pnR) + (fR - fL) / (2.0 * r);
+            fs = 0.5 * (fL + fR) + 0.5 * r * (pnR - pnL);
+            Dq = -h * (knn * pns + knt * (0.5 * (ptL + ptR)));
+        } else {
+            fs = 0.5 * (fL + fR);
+            Dq = 0.0;
+        }
+        double Dx = -(fs / s->dzeta) * nx, Dy = -(fs / s->dzeta) * ny;
+        double *dL = s->dcont + 9 * (c * nc + L) + 3 * kL;
+        double *dR = s->dcont + 9 * (c * nc + R) + 3 * kR;
+        dL[0] = l * Dq; dL[1] = l * Dx; dL[2] = l * Dy;
+        dR[0] = -(l * Dq); dR[1] = -(l * Dx); dR[2] = -(l * Dy);
+    }
+    (void)e;
 }
 
 /* per species: total mass sum q_c |Omega|, the time integral of the mass
@@ -1076,6 +1254,8 @@ static void wall_side(om_sim *s, int32_t K, int kK, double nx, double ny, double
     s->cont[9 * K + 3 * kK + 1] = l * (dn * nx - F[2] * ny);
     s->cont[9 * K + 3 * kK + 2] = l * (dn * ny + F[2] * nx);
     for (int c = 0; c < s->ns; c++) s->scont[3 * (c * s->m->nc + K) + kK] = 0.0;
+    if (s->diff)
+        for (int c = 0; c < s->ns; c++) diffusion_mirror(s, c, K, kK, l, nx, ny);
     if (s->morpho) s->bcont[3 * K + kK] = 0.0;
 }
 
@@ -1090,6 +1270,7 @@ static void edge_flux(const om_sim *s, int64_t e, edge_flux_t *out) {
     double unL = uL * nx + vL * ny, utL = -uL * ny + vL * nx;
     double HR, zR, unR, utR;
     int wall = 0, open = 0, inflow_b = -1, imposed = 0;
+    double qin = 0.0;  /* an active inflow's unit discharge */
     if (R >= 0) {
         cell_velocity(s, R, &hR, &uR, &vR);
         HR = s->H[R]; zR = s->z[R];
@@ -1102,9 +1283,9 @@ static void edge_flux(const om_sim *s, int64_t e, edge_flux_t *out) {
         if (B && B->kind == OM_OUTFLOW_ZEROGRAD) {
             /* transmissive: the ghost repeats the interior state */
             HR = HL; unR = unL; utR = utL; open = 1;
-        } else if (B && B->kind == OM_INFLOW_UNIFORM && inflow_ghost(s, B, L, s->t, &hg, &ung)) {
+        } else if (B && B->kind == OM_INFLOW_UNIFORM && inflow_ghost(s, B, L, s->t, &hg, &ung, &qin)) {
             HR = zL + hg; unR = ung; utR = 0.0; open = 1; inflow_b = b;
-        } else if (B && B->kind == OM_INFLOW_FROUDE && froude_ghost(s, B, s->t, &hg, &ung)) {
+        } else if (B && B->kind == OM_INFLOW_FROUDE && froude_ghost(s, B, s->t, &hg, &ung, &qin)) {
             HR = zL + hg; unR = ung; utR = 0.0; open = 1; inflow_b = b;
         } else if (B && B->kind == OM_OUTFLOW_UNIFORM) {
             /* uniform(slope) outflow: the ghost carries the normal depth
@@ -1148,6 +1329,16 @@ static void edge_flux(const om_sim *s, int64_t e, edge_flux_t *out) {
     } else {
         om_hllc(hLs, unL, utL, hRs, unR, utR, g, F);
     }
+    if (inflow_b >= 0) {
+        /* an inflow imposes its discharge (section "Hydrodynamic BCs": the
+         * inflow condition is set from the given discharge).  Reading: the
+         * edge's mass flux is the unit discharge q itself, the momentum
+         * flux that of the Riemann problem between the cell and the
+         * boundary state above; the volume that enters is then the
+         * hydrograph's in sub- and supercritical flow alike, and uniform
+         * flow at the boundary state stays in equilibrium */
+        F[0] = -qin;
+    }
     if (wall) F[0] = 0.0;   /* impermeable: no mass crosses a wall */
     out->F[0] = F[0]; out->F[1] = F[1]; out->F[2] = F[2];
     out->hLs = hLs; out->hRs = hRs;
@@ -1173,6 +1364,10 @@ int om_step(om_sim *s, double t_end, double *dt_taken) {
         }
     }
     if (s->ns > 0) memset(s->scont, 0, sizeof(double) * 3 * (size_t)(s->ns * m->nc));
+    if (s->diff) {
+        diffusion_cells(s);
+        memset(s->dcont, 0, sizeof(double) * 9 * (size_t)(s->ns * m->nc));
+    }
     if (s->drain) {
         /* draining time: the water each cell loses through its edges this
          * step, summed in local edge order, against the water it holds */
@@ -1247,12 +1442,18 @@ int om_step(om_sim *s, double t_end, double *dt_taken) {
         }
         if (s->ns > 0)
             scalar_edge(s, L, R, kL, R >= 0 ? m->ekR[e] : 0, l, F[0], wall, inflow_b, open, dt, sbst, sbstc);
+        if (s->diff) diffusion_edge(s, e, L, R, kL, R >= 0 ? m->ekR[e] : 0, l, nx, ny, R < 0, hLs, hRs);
         if (s->morpho)
             sed_edge(s, L, R, kL, R >= 0 ? m->ekR[e] : 0, l, nx, ny, open, dt, &bvst, &bvstc);
     }
-    /* volume through open boundary edges this step, in edge order */
+    /* volume through open boundary edges this step, in edge order, in
+     * total and per boundary condition */
     for (int64_t e = 0; e < m->ne; e++)
-        if (s->eflag[e]) neumaier(&bstep, &bstepc, s->ebvol[e]);
+        if (s->eflag[e]) {
+            neumaier(&bstep, &bstepc, s->ebvol[e]);
+            double *a = s->bcsum + 2 * s->ebc[e];
+            neumaier(&a[0], &a[1], s->ebvol[e]);
+        }
     int nonfinite = 0;
 #pragma omp parallel for schedule(static) reduction(| : nonfinite, deficit)
     for (int64_t i = 0; i < m->nc; i++) {
@@ -1312,12 +1513,31 @@ int om_step(om_sim *s, double t_end, double *dt_taken) {
         if (s->cflag[i] & 2) neumaier(&s->clip, &s->clipc, s->cclip[i]);
     if (nonfinite) return -4;
     for (int c = 0; c < s->ns; c++) {
-        /* eq. scl:updateformula with the advective fluxes */
+        /* eq. scl:updateformula: the advective fluxes, plus the diffusive
+         * ones and the relaxation of the auxiliary variables (its stiff
+         * source -psi/zeta by the locally implicit Euler step) when the
+         * species diffuse */
         double *q = s->sq + c * m->nc;
         for (int64_t i = 0; i < m->nc; i++) {
             const double *k = s->scont + 3 * (c * m->nc + i);
-            double Rq = k[0] + k[1] + k[2];
             double w = dt * (1.0 / m->area[i]);
+            double Rq;
+            if (s->diff) {
+                const double *d = s->dcont + 9 * (c * m->nc + i);
+                Rq = (k[0] + d[0]) + (k[1] + d[3]) + (k[2] + d[6]);
+                double Rx = d[1] + d[4] + d[7];
+                double Ry = d[2] + d[5] + d[8];
+                double *ps = s->spsi + 2 * (c * m->nc + i);
+                double rel = 1.0 + dt / s->dzeta;
+                ps[0] = (ps[0] - w * Rx) / rel;
+                ps[1] = (ps[1] - w * Ry) / rel;
+                /* psi of a cell that took part in no exchange (at or below
+                 * h_min at t^n), or that the step left dry, is reset */
+                if (!(s->dK[4 * i] > 0.0) || !(s->H[i] - s->z[i] > 0.0)) { ps[0] = 0.0; ps[1] = 0.0; }
+                if (!isfinite(ps[0]) || !isfinite(ps[1])) return -4;
+            } else {
+                Rq = k[0] + k[1] + k[2];
+            }
             q[i] = q[i] - w * Rq;
             if (s->csrc && s->csrc[i] >= 0) q[i] = q[i] * s->sfac[i];
             /* a cell left without water keeps no scalar (the positivity
@@ -1403,4 +1623,11 @@ void om_diag(const om_sim *s, double *mass, double *bnd, double *clipped, int64_
     if (bnd) *bnd = s->bsum + s->bcomp;
     if (clipped) *clipped = s->clip + s->clipc;
     if (steps) *steps = s->steps;
+}
+
+/* The part of the boundary-flux integral that crossed the edges of boundary
+ * condition b (positive: left the domain); 0 for an index out of range. */
+double om_bc_flux(const om_sim *s, int32_t b) {
+    if (b < 0 || b >= s->nbc) return 0.0;
+    return s->bcsum[2 * b] + s->bcsum[2 * b + 1];
 }

@@ -54,6 +54,14 @@ int om_run_until(om_sim *s, double t_end, int64_t max_steps, int64_t *n_steps);
 void om_get_state(const om_sim *s, double *H, double *qx, double *qy, double *t);
 void om_set_state(om_sim *s, const double *H, const double *qx, const double *qy, double t);
 void om_diag(const om_sim *s, double *mass, double *bnd_flux, double *clipped, int64_t *steps);
+/* boundary-flux integral over the edges of boundary condition b (its index
+ * in the list given to om_sim_new); positive: left the domain */
+double om_bc_flux(const om_sim *s, int32_t b);
+/* species diffusion by the relaxation system (eq. relaxation_terms,
+ * vecform_scalar2, scl:updateformula); see swe_oracle.c */
+int om_sim_set_diffusion(om_sim *s, const double *Km, double alpha_L, double alpha_T, double zeta,
+                         const double *psi0, char *err, int elen);
+void om_get_psi(const om_sim *s, double *psi);
 
 /* single-edge pieces, exposed for the pin tests */
 void om_hllc(double hL, double unL, double utL, double hR, double unR, double utR, double g,

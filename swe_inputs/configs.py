@@ -82,6 +82,18 @@ class Morpho:
 
 
 @dataclasses.dataclass
+class Diffusion:
+    """Diffusion of the passive species: molecular diffusivity Km [m^2/s]
+    (one value, or one per species), longitudinal and transversal dispersion
+    coefficients alpha_L, alpha_T (scaled by h u_*, u_* = |u| / c_f), and
+    the relaxation time zeta [s] of the hyperbolic (Cattaneo-type) form."""
+    Km: object = 0.0
+    alpha_L: float = 0.0
+    alpha_T: float = 0.0
+    zeta: float = 1.0
+
+
+@dataclasses.dataclass
 class Scenario:
     name: str
     nodes: np.ndarray            # (V,3) float64: x, y, bed elevation z
@@ -101,6 +113,7 @@ class Scenario:
     dt_max: float = float("inf")
     friction: str = "manning"    # closure the `manning` array parameterises: manning, strickler, chezy, bezzola
     phi0: Optional[np.ndarray] = None  # (S, N) initial concentrations of S <= 5 advected species
+    diffusion: Optional[Diffusion] = None  # diffusion of the species (relaxation form)
     sources: tuple = ()                # external water sources and sinks (Source)
     src_region: Optional[np.ndarray] = None  # (N,) int32 index into sources, -1 for none
     morpho: Optional[Morpho] = None    # Exner module (bed evolution)
@@ -279,6 +292,15 @@ def valley_flood(n_cells: int = 4_000_000, seed: int = 0, scale: float = 1.0,
                      manning=manning, t_end=t_end, cfl=0.9)
 
 
+def wet_snapshot(sc: Scenario) -> Scenario:
+    """The fully wet snapshot of a valley-flood scenario on the same mesh:
+    1 m of water moving at 0.5 m/s along x everywhere."""
+    n = sc.n_cells
+    name = sc.name if sc.name.endswith("_wet") else sc.name + "_wet"
+    return Scenario(**{**sc.__dict__, "name": name, "H0": None, "h0": np.ones(n), "qx0": np.full(n, 0.5),
+                       "qy0": np.zeros(n)})
+
+
 # --------------------------------------------------------- batched ensemble
 def ensemble_sizes(k: int = 64, lo: float = 2e4, hi: float = 5e5) -> np.ndarray:
     return np.round(np.exp(rng(7).uniform(np.log(lo), np.log(hi), k))).astype(np.int64)
@@ -326,6 +348,25 @@ def serving_request(i: int, n_cells: int, horizon: float) -> Scenario:
     sc = valley_flood(n_cells=n_cells, seed=1000 + i, scale=s, t_end=horizon, t_rise=horizon)
     sc.name = f"request_{i}_{sc.n_cells}"
     return sc
+
+
+def serving_pool(n_pool: int = 12, n_lo: float = 1e4, n_hi: float = 2e6) -> np.ndarray:
+    """Mesh sizes of a cached pool of serving domains: log-spaced over
+    [n_lo, n_hi], so a request drawn log-uniformly finds a pool mesh within a
+    factor (n_hi/n_lo)^(1/(2(n_pool-1))) of its size."""
+    return np.round(np.exp(np.linspace(np.log(n_lo), np.log(n_hi), n_pool))).astype(np.int64)
+
+
+def pool_request(base: Scenario, rid: int, horizon: float) -> Scenario:
+    """A request on a pooled serving domain: the domain's mesh and bed with
+    its own horizon, the inflow hydrograph rising over that horizon."""
+    bcs = []
+    for b in base.bcs:
+        if b.kind == INFLOW_UNIFORM:
+            b = dataclasses.replace(b, t=np.array([0.0, horizon]), Q=np.asarray(b.Q, np.float64).copy())
+        bcs.append(b)
+    return Scenario(**{**base.__dict__, "name": f"request_{rid}_{base.n_cells}", "bcs": bcs,
+                       "t_end": float(horizon)})
 
 
 # ------------------------------------------------- paper T5 / T6 (hydro part)

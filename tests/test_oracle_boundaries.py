@@ -3,11 +3,12 @@ zero gradient and zhydrograph (section "Hydrodynamic BCs" and the
 supplementary feature table: froude inflow, uniform, weir, h-Q relation and
 dynamic-wall outflows), against closed forms:
 
-* a supercritical Froude inflow onto a dry bed delivers exactly Q t (all
-  waves enter the domain, so the edge flux is the ghost's own flux), and the
-  inflowing layer carries the ghost depth (q / (Fr sqrt(g)))^(2/3); so does
-  a uniform (normal-depth) inflow down a channel steep enough for its ghost
-  to be supercritical;
+* an inflow imposes its discharge: a uniform or Froude inflow delivers
+  exactly the hydrograph's volume, sum over steps of Q(t^n) dt, whether its
+  boundary state is subcritical (a mild channel filling a basin, a rising
+  hydrograph) or supercritical (a Froude inflow onto a dry bed, a steep
+  channel), and the inflowing layer carries the boundary depth
+  (q / (Fr sqrt(g)))^(2/3) or the normal depth in the supercritical case;
 * a uniform outflow keeps uniform (normal) flow down a Manning channel;
 * a basin draining over a Poleni weir follows the closed form of
   dV/dt = -(2/3) mu sqrt(2g) (H - z_w)^(3/2) L;
@@ -94,6 +95,46 @@ def test_supercritical_uniform_inflow_delivers_exactly_q():
     near = sc.centroids()[:, 0] < 3.0
     assert np.max(np.abs(h[near] - hn)) <= 0.1 * hn
     assert np.max(np.abs(qx[near] - q)) <= 0.1 * q
+
+
+def _hydrograph_volume(sim, Q, t_end):
+    """Runs to t_end and returns sum over steps of Q(t^n) dt_n, the volume
+    an inflow that imposes its discharge delivers (hydrograph at t^n)."""
+    parts = []
+    while sim.t < t_end:
+        t0 = sim.t
+        parts.append(Q(t0) * sim.step(t_end))
+    return math.fsum(parts)
+
+
+@pytest.mark.parametrize("kind", ["uniform", "froude"])
+def test_subcritical_inflow_delivers_the_hydrograph_volume(kind):
+    # a mild channel (slope 1e-3) filling a closed basin through a rising
+    # hydrograph: the boundary state is subcritical (Froude 0.5 for the
+    # froude inflow, about 0.2 at the normal depth), so waves leave the
+    # domain through the inlet, and still exactly the hydrograph enters
+    ly = 4.0
+    ts, Qs = np.array([0.0, 20.0]), np.array([0.5, 2.5])
+
+    def Q(t):
+        return float(np.interp(t, ts, Qs))
+
+    if kind == "uniform":
+        bc = S.BC(1, S.INFLOW_UNIFORM, slope=1e-3, t=ts, Q=Qs)
+        q = Qs[-1] / ly
+        hn = (0.03 * q / math.sqrt(1e-3)) ** 0.6
+        assert q / hn < 0.5 * math.sqrt(G * hn)
+    else:
+        bc = S.BC(1, S.INFLOW_FROUDE, slope=0.5, t=ts, Q=Qs)
+    sc = _channel(40.0, ly, 1.0, lambda x, y: 1e-3 * (40.0 - x), 0.3, [bc], {"x0": 1}, manning=0.03)
+    sim = oracle.Sim(sc)
+    m0 = sim.diag()["mass"]
+    vol = _hydrograph_volume(sim, Q, 20.0)
+    d = sim.diag()
+    assert abs(-d["bnd_flux"] - vol) <= 1e-13 * vol
+    assert abs(d["mass"] - m0 - vol) <= 1e-12 * d["mass"]
+    # and the discrete volume is the hydrograph's integral up to O(dt)
+    assert abs(vol - 30.0) <= 0.01 * 30.0
 
 
 def test_uniform_outflow_keeps_normal_flow():

@@ -131,8 +131,9 @@ typedef struct {
     double dt_max;          /* upper limit of the time step [s] > 0, default +inf */
     int32_t precision;      /* SWE_FP64 (default) or SWE_FP32 */
     int32_t neg_depth_policy; /* SWE_NEG_CLIP (default) or SWE_NEG_ERROR */
-    int32_t block_size;     /* cells per tile = threads per block: 128, 256 or 512; 0 = default (256) */
-    int32_t cells_per_thread; /* reserved: 0 or 1 */
+    int32_t block_size;     /* cells per tile = threads per block: 128, 256 or 512; 0 = default (256).
+                               One thread per cell; a tile's edges (about 1.7 per cell) are spread
+                               over its threads, so this also sets the edges per thread */
     int32_t steps_per_graph;  /* steps captured per hipGraph in swe_run_until; 0 = default (32) */
     int32_t renumber;       /* 1 = Hilbert order of cell centroids (default), 0 = input order */
     int32_t friction;       /* SWE_FRICTION_* closure (default Manning) */
@@ -203,6 +204,13 @@ swe_status swe_run_until(swe_state *s, double t_end, int64_t *n_steps);
  * (graph launches); swe_sync waits and reports errors.  For timing. */
 swe_status swe_launch_steps(swe_state *s, double t_end, int64_t k);
 swe_status swe_sync(swe_state *s);
+/* Captures and instantiates the hipGraphs that swe_run_until and
+ * swe_launch_steps replay -- steps_per_graph step launches each, one graph
+ * per starting launch phase (the step count mod 3) -- WITHOUT launching
+ * anything, so that a timed region that follows replays graphs only.
+ * steps_per_graph in 1..4096 also replaces the state's setting; 0 keeps it.
+ * SWE_EINVAL out of range, SWE_EDEVICE when capture fails. */
+swe_status swe_prepare_graphs(swe_state *s, int32_t steps_per_graph);
 
 /* Copies the state to the host in original cell order as doubles; any
  * pointer may be NULL.  H surface elevation, h depth, qx, qy discharges,
@@ -214,6 +222,11 @@ swe_status swe_state_read(const swe_state *s, double *H, double *h, double *qx, 
  * boundaries, the volume added by positivity clips, and the step count.
  * The scheme is conservative: mass(t) = mass(0) - bnd_flux + clipped. */
 swe_status swe_mass(const swe_state *s, double *mass, double *bnd_flux, double *clipped, int64_t *steps);
+/* The part of bnd_flux that crossed the boundary edges carrying `tag`
+ * (positive: water left the domain; an inflow's is minus the volume it
+ * delivered), summed over those edges' accumulators in a fixed order.
+ * 0 for a tag with no open edges. */
+swe_status swe_boundary_flux(const swe_state *s, int32_t tag, double *volume);
 
 /* ---- passive species (section "Scalar advection-diffusion": eq.
  * scalar_goveq without the diffusion tensor, updated by eq.
@@ -323,9 +336,10 @@ swe_status swe_morpho_volume(const swe_state *s, double *volume, double *bnd, do
 
 /* Times k steps for each tile size (block size) in {128, 256, 512}, keeps
  * the fastest for this state, and restores the state exactly as it was.
- * *block_size receives the choice, *cells_per_thread 1 (either may be NULL).
- * Results are bitwise independent of the choice. */
-swe_status swe_autotune(swe_state *s, int32_t k, int32_t *block_size, int32_t *cells_per_thread);
+ * *block_size (may be NULL) receives the choice.  Results are bitwise
+ * independent of the choice.  States with species, sources or a moving bed
+ * keep their tile.  Allocates a copy of the state for the duration. */
+swe_status swe_autotune(swe_state *s, int32_t k, int32_t *block_size);
 
 /* ---- batched ensembles (many independent states stepped by one persistent
  * kernel per step, each with its own dt; paper motivation: ensemble and
@@ -350,6 +364,14 @@ swe_status swe_batch_remove(swe_batch *b, int32_t slot);
 swe_status swe_batch_step(swe_batch *b, int32_t k, int32_t *n_active);
 /* Issues the same work without waiting (for overlap and timing). */
 swe_status swe_batch_launch(swe_batch *b, int32_t k);
+/* The autotuner of the persistent batched step: times k launches over the
+ * running members for each tile size in {128, 256, 512} (the persistent grid
+ * follows the occupancy of each), keeps the fastest, and restores every
+ * member exactly as it was (state, boundary tallies, time level).
+ * *block_size (may be NULL) receives the choice.  Results are bitwise
+ * independent of the choice.  Allocates a copy of every running member for
+ * the duration (SWE_ENOMEM). */
+swe_status swe_batch_autotune(swe_batch *b, int32_t k, int32_t *block_size);
 /* Per-member status after the last swe_batch_step: done flag (t >= t_end
  * or an error), error code (0 or SWE_E*), time and steps of the member in
  * slot `slot` (as returned by swe_batch_add); each output may be NULL. */

@@ -9,6 +9,7 @@
 #include <cstring>
 #include <limits>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -159,6 +160,9 @@ struct swe_state {
     Ctrl *ctrl = nullptr;
     double2 *partials = nullptr;
     double *mass_out = nullptr;
+    float *L0 = nullptr, *L1 = nullptr;  // FP32: low parts of the surface (ping-pong with U0/U1)
+    double *clip_acc = nullptr;  // per 64-cell group: compensated clip volume
+    int ngroups = 0;
     Ctrl *hctrl = nullptr;    // pinned host copy of the control block
     double *hbuf = nullptr;   // pinned scratch (t_end, mass results)
     int nslots = 0, n_bc = 0;
@@ -166,7 +170,7 @@ struct swe_state {
     // concentrations [n_bc][ns], per-slot boundary accumulators, reset tallies
     int ns = 0;
     void *Q0 = nullptr, *Q1 = nullptr, *phi_in = nullptr;
-    double *sslot_acc = nullptr, *sclip = nullptr;
+    double *sslot_acc = nullptr, *sclip_acc = nullptr;
     // external sources: per device cell the region, per region its record
     // and series, per tile (at the smallest tile size) a volume accumulator
     int nsrc = 0, src_tiles = 0;
@@ -179,7 +183,7 @@ struct swe_state {
     void *zfix = nullptr;
     void *theta = nullptr;  // draining factors of the step (limiter on)
     int *iw_bc = nullptr;   // per interior-tag index: its wall condition or -1
-    double *bslot_acc = nullptr, *bclip = nullptr;
+    double *bslot_acc = nullptr, *bclip_acc = nullptr;
     int tile = 256, spg = 32;
     int phase = 0;  // step launches issued so far, mod 3 (selects the control slot)
     hipStream_t cap = nullptr;
@@ -191,8 +195,9 @@ struct swe_state {
     ~swe_state() {
         drop_graphs();
         if (cap) (void)hipStreamDestroy(cap);
-        for (void *q : {U0, U1, cellp, (void *)slot_kbc, (void *)slot_acc, (void *)bcs, (void *)hydro, (void *)ctrl,
-                        (void *)partials, (void *)mass_out, theta, (void *)iw_bc})
+        for (void *q : {U0, U1, (void *)L0, (void *)L1, cellp, (void *)slot_kbc, (void *)slot_acc, (void *)bcs,
+                        (void *)hydro, (void *)ctrl,
+                        (void *)partials, (void *)mass_out, (void *)clip_acc, theta, (void *)iw_bc})
             mem.release(q);
         drop_species();
         drop_sources();
@@ -202,22 +207,22 @@ struct swe_state {
     }
     hipStream_t stream() const { return mem.stream(); }
     void drop_species() {
-        for (void *q : {Q0, Q1, phi_in, (void *)sslot_acc, (void *)sclip}) mem.release(q);
+        for (void *q : {Q0, Q1, phi_in, (void *)sslot_acc, (void *)sclip_acc}) mem.release(q);
         Q0 = Q1 = phi_in = nullptr;
-        sslot_acc = sclip = nullptr;
+        sslot_acc = sclip_acc = nullptr;
         ns = 0;
         bind_species();
     }
     void drop_morpho() {
-        for (void *q : {zfix, (void *)bslot_acc, (void *)bclip}) mem.release(q);
+        for (void *q : {zfix, (void *)bslot_acc, (void *)bclip_acc}) mem.release(q);
         zfix = nullptr;
-        bslot_acc = bclip = nullptr;
+        bslot_acc = bclip_acc = nullptr;
         morpho = 0;
         inst32.morpho = inst64.morpho = 0;
         inst32.zfix = nullptr;
         inst64.zfix = nullptr;
         inst32.bslot_acc = inst64.bslot_acc = nullptr;
-        inst32.bclip = inst64.bclip = nullptr;
+        inst32.bclip_acc = inst64.bclip_acc = nullptr;
     }
     void drop_sources() {
         for (void *q : {(void *)src_cell, (void *)srcs, (void *)src_series, (void *)src_acc}) mem.release(q);
@@ -242,7 +247,7 @@ struct swe_state {
         inst64.Q1 = (double *)Q1;
         inst64.phi_in = (const double *)phi_in;
         inst32.sslot_acc = inst64.sslot_acc = sslot_acc;
-        inst32.sclip = inst64.sclip = sclip;
+        inst32.sclip_acc = inst64.sclip_acc = sclip_acc;
         inst32.ns = inst64.ns = ns;
     }
     // the current time level as last read from the device
@@ -272,15 +277,26 @@ struct swe_state {
         HIP_TRY(hipStreamSynchronize(stream()));
         return SWE_OK;
     }
-    // k captured steps starting at the current phase
-    swe_status graph(int k) {
+    // FP32: the low parts of the current level's surfaces (device order) into
+    // lo; FP64: lo left empty
+    swe_status read_lo(std::vector<float> &lo) {
+        lo.clear();
+        if (prec != SWE_FP32) return SWE_OK;
+        lo.resize((size_t)m->H.nc);
+        const float *src = lvl().cur ? L1 : L0;
+        HIP_TRY(hipMemcpyAsync(lo.data(), src, lo.size() * sizeof(float), hipMemcpyDeviceToHost, stream()));
+        HIP_TRY(hipStreamSynchronize(stream()));
+        return SWE_OK;
+    }
+    // k captured steps starting at launch phase ph
+    swe_status graph(int k, int ph) {
         if (g_k != k || g_tile != tile) drop_graphs();
-        if (gexec[phase]) return SWE_OK;
+        if (gexec[ph]) return SWE_OK;
         if (!cap) HIP_TRY(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
         hipGraph_t gr = nullptr;
         HIP_TRY(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
         for (int i = 0; i < k; i++) {
-            hipError_t e = launch_one_on(cap, (phase + i) % 3);
+            hipError_t e = launch_one_on(cap, (ph + i) % 3);
             if (e != hipSuccess) {
                 hipGraph_t dummy = nullptr;
                 (void)hipStreamEndCapture(cap, &dummy);
@@ -289,7 +305,7 @@ struct swe_state {
             }
         }
         HIP_TRY(hipStreamEndCapture(cap, &gr));
-        hipError_t e = hipGraphInstantiate(&gexec[phase], gr, nullptr, nullptr, 0);
+        hipError_t e = hipGraphInstantiate(&gexec[ph], gr, nullptr, nullptr, 0);
         (void)hipGraphDestroy(gr);
         if (e != hipSuccess) return fail(SWE_EDEVICE, std::string("graph instantiate: ") + hipGetErrorString(e));
         g_k = k;
@@ -297,7 +313,7 @@ struct swe_state {
         return SWE_OK;
     }
     swe_status launch_graph() {
-        swe_status st = graph(spg);
+        swe_status st = graph(spg, phase);
         if (st) return st;
         HIP_TRY(hipGraphLaunch(gexec[phase], stream()));
         phase = (phase + spg) % 3;
@@ -350,7 +366,6 @@ void swe_params_default(swe_params *p) {
     p->precision = SWE_FP64;
     p->neg_depth_policy = SWE_NEG_CLIP;
     p->block_size = 0;
-    p->cells_per_thread = 0;
     p->steps_per_graph = 0;
     p->renumber = 1;
     p->friction = SWE_FRICTION_MANNING;
@@ -408,7 +423,10 @@ int64_t swe_state_footprint(const swe_mesh *m, int32_t precision) {
     if (!m) return 0;
     const int64_t n = m->H.nc, ns = (int64_t)m->H.slot_tag.size();
     const int64_t v4 = (int64_t)vec4_bytes(precision);
-    const int64_t state = 2 * n * v4 + n * v4 / 2 + ns * (4 + 16) + (int64_t)sizeof(Ctrl) + MASS_BLOCKS * 16 + 4096;
+    // FP32 adds the low parts of the surface (two buffers of 4 bytes per cell)
+    const int64_t lo = precision == SWE_FP32 ? 2 * n * 4 : 0;
+    const int64_t state = 2 * n * v4 + lo + n * v4 / 2 + ns * (4 + 16) + (int64_t)sizeof(Ctrl) + MASS_BLOCKS * 16 +
+                          4096;
     // tile edge list (about 1.7 edges per cell: record + other-cell id) and FP64 areas
     const int64_t edge = precision == SWE_FP32 ? 12 + 4 : 24 + 4;
     const int64_t geom = n * 8 + (n * 7 / 4) * edge + 4 * (n / 128 + 2);
@@ -432,7 +450,6 @@ swe_status swe_state_init(const swe_mesh *m, const swe_params *params, const dou
     if (P.neg_depth_policy != SWE_NEG_CLIP && P.neg_depth_policy != SWE_NEG_ERROR)
         return fail(SWE_EINVAL, "unknown negative-depth policy");
     if (P.block_size != 0 && !valid_tile(P.block_size)) return fail(SWE_EINVAL, "block_size must be 0, 128, 256 or 512");
-    if (P.cells_per_thread < 0 || P.cells_per_thread > 1) return fail(SWE_EINVAL, "cells_per_thread must be 0 or 1");
     if (P.steps_per_graph < 0 || P.steps_per_graph > 4096) return fail(SWE_EINVAL, "steps_per_graph out of range");
     if (P.friction < SWE_FRICTION_MANNING || P.friction > SWE_FRICTION_BEZZOLA)
         return fail(SWE_EINVAL, "unknown friction closure");
@@ -448,7 +465,9 @@ swe_status swe_state_init(const swe_mesh *m, const swe_params *params, const dou
     std::vector<double> H((size_t)n), qx((size_t)n), qy((size_t)n), gn2((size_t)n);
     for (int64_t i = 0; i < n; i++) {
         const int32_t p = M.inv[i];
-        const double z = M.zb[p];
+        // the bed the state carries: FP32 states keep it in single precision,
+        // and an initial depth or a clamped surface refers to that bed
+        const double z = prec == SWE_FP32 ? double(float(M.zb[p])) : M.zb[p];
         double Hi;
         if (H0) {
             if (!std::isfinite(H0[i])) return fail(SWE_EINVAL, "non-finite initial surface");
@@ -557,6 +576,11 @@ swe_status swe_state_init(const swe_mesh *m, const swe_params *params, const dou
     const size_t v4 = vec4_bytes(prec);
     S->U0 = S->mem.alloc((size_t)n * v4);
     S->U1 = S->mem.alloc((size_t)n * v4);
+    if (prec == SWE_FP32) {
+        S->L0 = (float *)S->mem.alloc((size_t)std::max<int64_t>(n, 1) * sizeof(float));
+        S->L1 = (float *)S->mem.alloc((size_t)std::max<int64_t>(n, 1) * sizeof(float));
+        if (!S->L0 || !S->L1) return fail(SWE_ENOMEM, "device allocation failed (state)");
+    }
     S->cellp = S->mem.alloc((size_t)n * v4 / 2);
     S->slot_kbc = (int *)S->mem.alloc(sizeof(int) * std::max(nslots, 1));
     S->slot_acc = (double *)S->mem.alloc(2 * sizeof(double) * std::max(nslots, 1));
@@ -564,7 +588,9 @@ swe_status swe_state_init(const swe_mesh *m, const swe_params *params, const dou
     S->hydro = (double *)S->mem.alloc(sizeof(double) * std::max<size_t>(hydro.size(), 1));
     S->ctrl = (Ctrl *)S->mem.alloc(sizeof(Ctrl));
     S->partials = (double2 *)S->mem.alloc(sizeof(double2) * MASS_BLOCKS);
-    S->mass_out = (double *)S->mem.alloc(2 * sizeof(double));
+    S->mass_out = (double *)S->mem.alloc(4 * sizeof(double));
+    S->ngroups = (int)((n + 63) / 64);
+    S->clip_acc = (double *)S->mem.alloc(2 * sizeof(double) * std::max(S->ngroups, 1));
     S->iw_bc = (int *)S->mem.alloc(sizeof(int) * iwb.size());
     if (!S->iw_bc) return fail(SWE_ENOMEM, "device allocation failed (state)");
     if (P.limiter == SWE_LIMIT_DRAIN) {
@@ -572,7 +598,7 @@ swe_status swe_state_init(const swe_mesh *m, const swe_params *params, const dou
         if (!S->theta) return fail(SWE_ENOMEM, "device allocation failed (limiter)");
     }
     if (!S->U0 || !S->U1 || !S->cellp || !S->slot_kbc || !S->slot_acc || !S->bcs || !S->hydro || !S->ctrl ||
-        !S->partials || !S->mass_out)
+        !S->partials || !S->mass_out || !S->clip_acc)
         return fail(SWE_ENOMEM, "device allocation failed (state)");
     HIP_TRY(hipHostMalloc((void **)&S->hctrl, sizeof(Ctrl), hipHostMallocDefault));
     HIP_TRY(hipHostMalloc((void **)&S->hbuf, 64, hipHostMallocDefault));
@@ -587,8 +613,11 @@ swe_status swe_state_init(const swe_mesh *m, const swe_params *params, const dou
         using T = decltype(tag);
         std::vector<V4<T>> u((size_t)n);
         std::vector<V2<T>> cp((size_t)n);
+        std::vector<float> lo(sizeof(T) == 4 ? (size_t)n : 0);
         for (int64_t p = 0; p < n; p++) {
             u[p].x = T(H[p]);
+            // FP32 stores the surface as hi + lo
+            if (sizeof(T) == 4) lo[p] = float(H[p] - double(u[p].x));
             u[p].y = T(qx[p]);
             u[p].z = T(qy[p]);
             u[p].w = T(M.zb[p]);
@@ -598,6 +627,10 @@ swe_status swe_state_init(const swe_mesh *m, const swe_params *params, const dou
         }
         HIP_TRY(hipMemcpyAsync(S->U0, u.data(), u.size() * sizeof(V4<T>), hipMemcpyHostToDevice, s));
         HIP_TRY(hipMemcpyAsync(S->U1, u.data(), u.size() * sizeof(V4<T>), hipMemcpyHostToDevice, s));
+        if (!lo.empty()) {
+            HIP_TRY(hipMemcpyAsync(S->L0, lo.data(), lo.size() * sizeof(float), hipMemcpyHostToDevice, s));
+            HIP_TRY(hipMemcpyAsync(S->L1, lo.data(), lo.size() * sizeof(float), hipMemcpyHostToDevice, s));
+        }
         HIP_TRY(hipMemcpyAsync(S->cellp, cp.data(), cp.size() * sizeof(V2<T>), hipMemcpyHostToDevice, s));
         HIP_TRY(hipStreamSynchronize(s));
         return SWE_OK;
@@ -607,6 +640,7 @@ swe_status swe_state_init(const swe_mesh *m, const swe_params *params, const dou
     std::vector<double> zeros((size_t)2 * std::max(nslots, 1), 0.0);
     HIP_TRY(hipMemcpyAsync(S->slot_kbc, kbc.data(), sizeof(int) * kbc.size(), hipMemcpyHostToDevice, s));
     HIP_TRY(hipMemcpyAsync(S->slot_acc, zeros.data(), sizeof(double) * zeros.size(), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemsetAsync(S->clip_acc, 0, 2 * sizeof(double) * std::max(S->ngroups, 1), s));
     HIP_TRY(hipMemcpyAsync(S->bcs, hb.data(), sizeof(BCdev) * hb.size(), hipMemcpyHostToDevice, s));
     HIP_TRY(hipMemcpyAsync(S->iw_bc, iwb.data(), sizeof(int) * iwb.size(), hipMemcpyHostToDevice, s));
     if (!hydro.empty())
@@ -624,6 +658,8 @@ swe_status swe_state_init(const swe_mesh *m, const swe_params *params, const dou
         using T = decltype(tag);
         I.U0 = (V4<T> *)S->U0;
         I.U1 = (V4<T> *)S->U1;
+        I.L0 = (T *)S->L0;
+        I.L1 = (T *)S->L1;
         const TileGeom &tg = m->geom[prec][tile_index(S->tile)];
         I.cellp = (const V2<T> *)S->cellp;
         tg.bind(I);
@@ -632,6 +668,8 @@ swe_status swe_state_init(const swe_mesh *m, const swe_params *params, const dou
         I.bcs = S->bcs;
         I.area = m->area;
         I.ctrl = S->ctrl;
+        I.clip_acc = S->clip_acc;
+        I.ngroups = S->ngroups;
         I.n = (int)n;
         I.ntiles = tg.ntiles;
         I.g = P.g;
@@ -728,6 +766,17 @@ swe_status swe_sync(swe_state *s) {
     return check_flags(s->hctrl->flags);
 }
 
+swe_status swe_prepare_graphs(swe_state *s, int32_t steps_per_graph) {
+    if (!s) return fail(SWE_EINVAL, "state is NULL");
+    if (steps_per_graph < 0 || steps_per_graph > 4096) return fail(SWE_EINVAL, "steps_per_graph out of range");
+    if (steps_per_graph > 0) s->spg = steps_per_graph;
+    for (int ph = 0; ph < 3; ph++) {
+        swe_status st = s->graph(s->spg, ph);
+        if (st) return st;
+    }
+    return SWE_OK;
+}
+
 swe_status swe_state_read(const swe_state *cs, double *H, double *h, double *qx, double *qy, double *t) {
     swe_state *s = const_cast<swe_state *>(cs);
     if (!s) return fail(SWE_EINVAL, "state is NULL");
@@ -739,12 +788,16 @@ swe_status swe_state_read(const swe_state *cs, double *H, double *h, double *qx,
     auto rd = [&](auto tag) -> swe_status {
         using T = decltype(tag);
         std::vector<V4<T>> u((size_t)n);
+        std::vector<float> lo;
         HIP_TRY(hipMemcpyAsync(u.data(), src, u.size() * sizeof(V4<T>), hipMemcpyDeviceToHost, s->stream()));
-        HIP_TRY(hipStreamSynchronize(s->stream()));
+        swe_status r = s->read_lo(lo);
+        if (r) return r;
         for (int64_t i = 0; i < n; i++) {
-            const V4<T> &v = u[M.inv[i]];
-            if (H) H[i] = double(v.x);
-            if (h) h[i] = double(v.x) - double(v.w);
+            const int32_t d = M.inv[i];
+            const V4<T> &v = u[d];
+            const double Hs = lo.empty() ? double(v.x) : double(v.x) + double(lo[d]);
+            if (H) H[i] = Hs;
+            if (h) h[i] = Hs - double(v.w);
             if (qx) qx[i] = double(v.y);
             if (qy) qy[i] = double(v.z);
         }
@@ -763,13 +816,36 @@ swe_status swe_mass(const swe_state *cs, double *mass, double *bnd_flux, double 
         HIP_TRY(launch_mass<float>(s->inst32, s->partials, s->mass_out, s->nslots, s->phase, s->stream()));
     else
         HIP_TRY(launch_mass<double>(s->inst64, s->partials, s->mass_out, s->nslots, s->phase, s->stream()));
-    HIP_TRY(hipMemcpyAsync(s->hbuf + 1, s->mass_out, 2 * sizeof(double), hipMemcpyDeviceToHost, s->stream()));
+    HIP_TRY(launch_pair_sum(s->clip_acc, std::max(s->ngroups, 1), s->mass_out + 2, s->stream()));
+    HIP_TRY(hipMemcpyAsync(s->hbuf + 1, s->mass_out, 3 * sizeof(double), hipMemcpyDeviceToHost, s->stream()));
     swe_status st = s->read_ctrl();
     if (st) return st;
     if (mass) *mass = s->hbuf[1];
     if (bnd_flux) *bnd_flux = s->hbuf[2];
-    if (clipped) *clipped = s->hctrl->clipped;
+    if (clipped) *clipped = s->hbuf[3];
     if (steps) *steps = s->lvl().steps;
+    return SWE_OK;
+}
+
+swe_status swe_boundary_flux(const swe_state *cs, int32_t tag, double *volume) {
+    swe_state *s = const_cast<swe_state *>(cs);
+    if (!s || !volume) return fail(SWE_EINVAL, "state or volume is NULL");
+    const HostMesh &M = s->m->H;
+    const int nslots = (int)M.slot_tag.size();
+    std::vector<double> acc((size_t)2 * std::max(nslots, 1));
+    HIP_TRY(hipMemcpyAsync(acc.data(), s->slot_acc, acc.size() * sizeof(double), hipMemcpyDeviceToHost, s->stream()));
+    HIP_TRY(hipStreamSynchronize(s->stream()));
+    // compensated sum over the tag's slots in slot order
+    double sm = 0.0, cp = 0.0;
+    for (int k = 0; k < nslots; k++) {
+        if (M.slot_tag[k] != tag) continue;
+        for (double v : {acc[2 * k], acc[2 * k + 1]}) {
+            const double t = sm + v;
+            cp += std::fabs(sm) >= std::fabs(v) ? (sm - t) + v : (v - t) + sm;
+            sm = t;
+        }
+    }
+    *volume = sm + cp;
     return SWE_OK;
 }
 
@@ -799,8 +875,9 @@ swe_status swe_state_set_scalars(swe_state *s, int32_t ns, const double *phi0, c
     s->Q1 = s->mem.alloc((size_t)ns * n * es);
     s->phi_in = s->mem.alloc((size_t)ns * nb * es);
     s->sslot_acc = (double *)s->mem.alloc(2 * sizeof(double) * (size_t)ns * std::max(s->nslots, 1));
-    s->sclip = (double *)s->mem.alloc(sizeof(double) * ns);
-    if (!s->Q0 || !s->Q1 || !s->phi_in || !s->sslot_acc || !s->sclip) {
+    const size_t sclip_n = (size_t)2 * ns * std::max(s->ngroups, 1);
+    s->sclip_acc = (double *)s->mem.alloc(sizeof(double) * sclip_n);
+    if (!s->Q0 || !s->Q1 || !s->phi_in || !s->sslot_acc || !s->sclip_acc) {
         s->drop_species();
         return fail(SWE_ENOMEM, "device allocation failed (species)");
     }
@@ -811,13 +888,16 @@ swe_status swe_state_set_scalars(swe_state *s, int32_t ns, const double *phi0, c
     auto up = [&](auto tag) -> swe_status {
         using T = decltype(tag);
         std::vector<V4<T>> u((size_t)n);
+        std::vector<float> lo;
         HIP_TRY(hipMemcpyAsync(u.data(), cur, u.size() * sizeof(V4<T>), hipMemcpyDeviceToHost, q));
-        HIP_TRY(hipStreamSynchronize(q));
+        swe_status r = s->read_lo(lo);
+        if (r) return r;
         std::vector<T> qh((size_t)ns * n), pin((size_t)ns * nb, T(0));
         for (int c = 0; c < ns; c++)
             for (int64_t i = 0; i < n; i++) {
-                const V4<T> &v = u[M.inv[i]];
-                const double h = double(v.x) - double(v.w);
+                const int32_t d = M.inv[i];
+                const V4<T> &v = u[d];
+                const double h = (lo.empty() ? double(v.x) : double(v.x) + double(lo[d])) - double(v.w);
                 const double p = phi0 ? phi0[(size_t)c * n + i] : 0.0;
                 qh[(size_t)c * n + M.inv[i]] = h > 0.0 ? T(h * p) : T(0);
             }
@@ -826,7 +906,7 @@ swe_status swe_state_set_scalars(swe_state *s, int32_t ns, const double *phi0, c
         HIP_TRY(hipMemcpyAsync(s->phi_in, pin.data(), pin.size() * sizeof(T), hipMemcpyHostToDevice, q));
         std::vector<double> z((size_t)2 * ns * std::max(s->nslots, 1), 0.0);
         HIP_TRY(hipMemcpyAsync(s->sslot_acc, z.data(), z.size() * sizeof(double), hipMemcpyHostToDevice, q));
-        HIP_TRY(hipMemcpyAsync(s->sclip, z.data(), ns * sizeof(double), hipMemcpyHostToDevice, q));
+        HIP_TRY(hipMemsetAsync(s->sclip_acc, 0, sclip_n * sizeof(double), q));
         HIP_TRY(hipStreamSynchronize(q));
         return SWE_OK;
     };
@@ -959,9 +1039,10 @@ swe_status swe_state_set_morpho(swe_state *s, const swe_morpho *mo, const double
     const size_t es = s->prec == SWE_FP32 ? sizeof(float) : sizeof(double);
     const int nsl = std::max(s->nslots, 1);
     s->bslot_acc = (double *)s->mem.alloc(2 * sizeof(double) * (size_t)nsl);
-    s->bclip = (double *)s->mem.alloc(sizeof(double));
+    const size_t bclip_n = (size_t)2 * std::max(s->ngroups, 1);
+    s->bclip_acc = (double *)s->mem.alloc(sizeof(double) * bclip_n);
     if (z_rel) s->zfix = s->mem.alloc(es * (size_t)n);
-    if (!s->bslot_acc || !s->bclip || (z_rel && !s->zfix)) {
+    if (!s->bslot_acc || !s->bclip_acc || (z_rel && !s->zfix)) {
         s->drop_morpho();
         return fail(SWE_ENOMEM, "device allocation failed (morphodynamics)");
     }
@@ -971,7 +1052,7 @@ swe_status swe_state_set_morpho(swe_state *s, const swe_morpho *mo, const double
         using T = decltype(tag);
         std::vector<double> z((size_t)2 * nsl, 0.0);
         HIP_TRY(hipMemcpyAsync(s->bslot_acc, z.data(), z.size() * sizeof(double), hipMemcpyHostToDevice, q));
-        HIP_TRY(hipMemcpyAsync(s->bclip, z.data(), sizeof(double), hipMemcpyHostToDevice, q));
+        HIP_TRY(hipMemsetAsync(s->bclip_acc, 0, bclip_n * sizeof(double), q));
         if (z_rel) {
             std::vector<V4<T>> u((size_t)n);
             HIP_TRY(hipMemcpyAsync(u.data(), cur, u.size() * sizeof(V4<T>), hipMemcpyDeviceToHost, q));
@@ -1005,7 +1086,7 @@ swe_status swe_state_set_morpho(swe_state *s, const swe_morpho *mo, const double
         I.spor = mo->porosity;
         I.zfix = (const T *)s->zfix;
         I.bslot_acc = s->bslot_acc;
-        I.bclip = s->bclip;
+        I.bclip_acc = s->bclip_acc;
     };
     bind(s->inst32, float());
     bind(s->inst64, double());
@@ -1043,8 +1124,8 @@ swe_status swe_morpho_volume(const swe_state *cs, double *volume, double *bnd, d
     else
         HIP_TRY(launch_bed_volume<double>(s->inst64, s->partials, s->mass_out, s->phase, q));
     HIP_TRY(launch_pair_sum(s->bslot_acc, std::max(s->nslots, 1), s->mass_out + 1, q));
-    HIP_TRY(hipMemcpyAsync(s->hbuf + 1, s->mass_out, 2 * sizeof(double), hipMemcpyDeviceToHost, q));
-    HIP_TRY(hipMemcpyAsync(s->hbuf + 3, s->bclip, sizeof(double), hipMemcpyDeviceToHost, q));
+    HIP_TRY(launch_pair_sum(s->bclip_acc, std::max(s->ngroups, 1), s->mass_out + 2, q));
+    HIP_TRY(hipMemcpyAsync(s->hbuf + 1, s->mass_out, 3 * sizeof(double), hipMemcpyDeviceToHost, q));
     HIP_TRY(hipStreamSynchronize(q));
     if (volume) *volume = s->hbuf[1];
     if (bnd) *bnd = s->hbuf[2];
@@ -1102,21 +1183,23 @@ swe_status swe_scalar_mass(const swe_state *cs, double *mass, double *bnd_flux, 
         if (bnd_flux) bnd_flux[c] = s->hbuf[2];
     }
     if (clipped) {
-        // hbuf holds 8 doubles; at most 5 species
-        HIP_TRY(hipMemcpyAsync(s->hbuf + 1, s->sclip, s->ns * sizeof(double), hipMemcpyDeviceToHost, q));
-        HIP_TRY(hipStreamSynchronize(q));
-        for (int c = 0; c < s->ns; c++) clipped[c] = s->hbuf[1 + c];
+        const int ng = std::max(s->ngroups, 1);
+        for (int c = 0; c < s->ns; c++) {
+            HIP_TRY(launch_pair_sum(s->sclip_acc + (size_t)2 * c * ng, ng, s->mass_out, q));
+            HIP_TRY(hipMemcpyAsync(s->hbuf + 1, s->mass_out, sizeof(double), hipMemcpyDeviceToHost, q));
+            HIP_TRY(hipStreamSynchronize(q));
+            clipped[c] = s->hbuf[1];
+        }
     }
     return SWE_OK;
 }
 
-swe_status swe_autotune(swe_state *s, int32_t k, int32_t *block_size, int32_t *cells_per_thread) {
+swe_status swe_autotune(swe_state *s, int32_t k, int32_t *block_size) {
     if (!s) return fail(SWE_EINVAL, "state is NULL");
     if (s->ns > 0 || s->nsrc > 0 || s->morpho) {
         // the species and Exner steps have one tile size; a state with
         // sources keeps its tile (its source tally is kept per tile)
         if (block_size) *block_size = s->tile;
-        if (cells_per_thread) *cells_per_thread = 1;
         return SWE_OK;
     }
     if (k < 1) k = 8;
@@ -1127,14 +1210,19 @@ swe_status swe_autotune(swe_state *s, int32_t k, int32_t *block_size, int32_t *c
     const int64_t n = s->m->H.nc;
     const size_t ub = (size_t)n * vec4_bytes(s->prec);
     const size_t ab = 2 * sizeof(double) * std::max(s->nslots, 1);
-    void *keepU = s->mem.alloc(ub);
+    const size_t cb = 2 * sizeof(double) * std::max(s->ngroups, 1);
+    const size_t lb = s->prec == SWE_FP32 ? (size_t)n * sizeof(float) : 0;
+    void *keepU = s->mem.alloc(ub + lb);  // the state, then (FP32) the low parts of the surface
     void *keepA = s->mem.alloc(ab);
-    if (!keepU || !keepA) {
+    void *keepC = s->mem.alloc(cb);
+    if (!keepU || !keepA || !keepC) {
         s->mem.release(keepU);
         s->mem.release(keepA);
+        s->mem.release(keepC);
         return fail(SWE_ENOMEM, "device allocation failed (autotune)");
     }
     void *cur = saved.s[saved_phase].cur ? s->U1 : s->U0;
+    void *curL = saved.s[saved_phase].cur ? (void *)s->L1 : (void *)s->L0;
     hipStream_t q = s->stream();
     hipEvent_t e0 = nullptr, e1 = nullptr;
     auto cleanup = [&]() {
@@ -1142,19 +1230,24 @@ swe_status swe_autotune(swe_state *s, int32_t k, int32_t *block_size, int32_t *c
         if (e1) (void)hipEventDestroy(e1);
         s->mem.release(keepU);
         s->mem.release(keepA);
+        s->mem.release(keepC);
     };
     auto restore = [&]() -> swe_status {
         *s->hctrl = saved;
         s->phase = saved_phase;
         HIP_TRY(hipMemcpyAsync(cur, keepU, ub, hipMemcpyDeviceToDevice, q));
+        if (lb) HIP_TRY(hipMemcpyAsync(curL, (char *)keepU + ub, lb, hipMemcpyDeviceToDevice, q));
         HIP_TRY(hipMemcpyAsync(s->slot_acc, keepA, ab, hipMemcpyDeviceToDevice, q));
+        HIP_TRY(hipMemcpyAsync(s->clip_acc, keepC, cb, hipMemcpyDeviceToDevice, q));
         HIP_TRY(hipMemcpyAsync(s->ctrl, s->hctrl, sizeof(Ctrl), hipMemcpyHostToDevice, q));
         HIP_TRY(hipStreamSynchronize(q));
         return SWE_OK;
     };
     st = [&]() -> swe_status {
         HIP_TRY(hipMemcpyAsync(keepU, cur, ub, hipMemcpyDeviceToDevice, q));
+        if (lb) HIP_TRY(hipMemcpyAsync((char *)keepU + ub, curL, lb, hipMemcpyDeviceToDevice, q));
         HIP_TRY(hipMemcpyAsync(keepA, s->slot_acc, ab, hipMemcpyDeviceToDevice, q));
+        HIP_TRY(hipMemcpyAsync(keepC, s->clip_acc, cb, hipMemcpyDeviceToDevice, q));
         HIP_TRY(hipEventCreate(&e0));
         HIP_TRY(hipEventCreate(&e1));
         float best = std::numeric_limits<float>::infinity();
@@ -1187,7 +1280,6 @@ swe_status swe_autotune(swe_state *s, int32_t k, int32_t *block_size, int32_t *c
     cleanup();
     if (st) return st;
     if (block_size) *block_size = s->tile;
-    if (cells_per_thread) *cells_per_thread = 1;
     return SWE_OK;
 }
 
@@ -1426,6 +1518,130 @@ swe_status swe_batch_step(swe_batch *b, int32_t k, int32_t *n_active) {
         if (!done) active++;
     }
     if (n_active) *n_active = active;
+    return SWE_OK;
+}
+
+swe_status swe_batch_autotune(swe_batch *b, int32_t k, int32_t *block_size) {
+    if (!b) return fail(SWE_EINVAL, "batch is NULL");
+    if (k < 1) k = 4;
+    if (b->dirty) {
+        swe_status st = b->rebuild();
+        if (st) return st;
+    }
+    // every running member's current state vector, boundary accumulators,
+    // control block and launch phase, restored after each trial
+    struct Saved {
+        swe_state *s;
+        void *U = nullptr, *A = nullptr, *C = nullptr, *cur = nullptr, *curL = nullptr;
+        size_t ub = 0, ab = 0, cb = 0, lb = 0;
+        Ctrl c{};
+        int phase = 0;
+    };
+    std::vector<Saved> sv;
+    hipStream_t q = b->stream();
+    const int bphase = b->phase;
+    auto release = [&]() {
+        for (auto &x : sv) {
+            x.s->mem.release(x.U);
+            x.s->mem.release(x.A);
+            x.s->mem.release(x.C);
+        }
+    };
+    for (size_t i = 0; i < b->members.size(); i++) {
+        swe_state *s = b->members[i];
+        if (!s || b->finished[i]) continue;
+        swe_status st = s->read_ctrl();
+        if (st) {
+            release();
+            return st;
+        }
+        Saved x;
+        x.s = s;
+        x.c = *s->hctrl;
+        x.phase = s->phase;
+        x.cur = x.c.s[s->phase].cur ? s->U1 : s->U0;
+        x.curL = x.c.s[s->phase].cur ? (void *)s->L1 : (void *)s->L0;
+        x.lb = s->prec == SWE_FP32 ? (size_t)s->m->H.nc * sizeof(float) : 0;
+        x.ub = (size_t)s->m->H.nc * vec4_bytes(s->prec);
+        x.ab = 2 * sizeof(double) * std::max(s->nslots, 1);
+        x.cb = 2 * sizeof(double) * std::max(s->ngroups, 1);
+        x.U = s->mem.alloc(x.ub + x.lb);
+        x.A = s->mem.alloc(x.ab);
+        x.C = s->mem.alloc(x.cb);
+        sv.push_back(x);
+        if (!x.U || !x.A || !x.C) {
+            release();
+            return fail(SWE_ENOMEM, "device allocation failed (batch autotune)");
+        }
+        HIP_TRY(hipMemcpyAsync(x.U, x.cur, x.ub, hipMemcpyDeviceToDevice, q));
+        if (x.lb) HIP_TRY(hipMemcpyAsync((char *)x.U + x.ub, x.curL, x.lb, hipMemcpyDeviceToDevice, q));
+        HIP_TRY(hipMemcpyAsync(x.A, s->slot_acc, x.ab, hipMemcpyDeviceToDevice, q));
+        HIP_TRY(hipMemcpyAsync(x.C, s->clip_acc, x.cb, hipMemcpyDeviceToDevice, q));
+    }
+    auto restore = [&]() -> swe_status {
+        for (auto &x : sv) {
+            *x.s->hctrl = x.c;
+            x.s->phase = x.phase;
+            HIP_TRY(hipMemcpyAsync(x.cur, x.U, x.ub, hipMemcpyDeviceToDevice, q));
+            if (x.lb) HIP_TRY(hipMemcpyAsync(x.curL, (char *)x.U + x.ub, x.lb, hipMemcpyDeviceToDevice, q));
+            HIP_TRY(hipMemcpyAsync(x.s->slot_acc, x.A, x.ab, hipMemcpyDeviceToDevice, q));
+            HIP_TRY(hipMemcpyAsync(x.s->clip_acc, x.C, x.cb, hipMemcpyDeviceToDevice, q));
+            HIP_TRY(hipMemcpyAsync(x.s->ctrl, x.s->hctrl, sizeof(Ctrl), hipMemcpyHostToDevice, q));
+        }
+        HIP_TRY(hipStreamSynchronize(q));
+        b->phase = bphase;
+        return SWE_OK;
+    };
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    const int tile0 = b->tile;
+    swe_status st = [&]() -> swe_status {
+        HIP_TRY(hipEventCreate(&e0));
+        HIP_TRY(hipEventCreate(&e1));
+        float best = std::numeric_limits<float>::infinity();
+        int bt = tile0;
+        for (int t : TILES) {
+            swe_status r = restore();
+            if (r) return r;
+            b->tile = t;
+            r = b->rebuild();
+            if (r) return r;
+            if (b->ntiles == 0) break;
+            HIP_TRY(b->launch(q, b->phase));
+            b->phase = (b->phase + 1) % 3;
+            HIP_TRY(hipEventRecord(e0, q));
+            for (int i = 0; i < k; i++) {
+                HIP_TRY(b->launch(q, b->phase));
+                b->phase = (b->phase + 1) % 3;
+            }
+            HIP_TRY(hipEventRecord(e1, q));
+            HIP_TRY(hipEventSynchronize(e1));
+            float ms = 0;
+            HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+            bool ok = true;
+            for (auto &x : sv) {
+                r = x.s->read_ctrl();
+                if (r) return r;
+                ok = ok && x.s->hctrl->flags == 0;
+            }
+            if (ok && ms < best) {
+                best = ms;
+                bt = t;
+            }
+        }
+        swe_status r = restore();
+        if (r) return r;
+        b->tile = bt;
+        return b->rebuild();
+    }();
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    release();
+    if (st) {
+        b->tile = tile0;
+        b->dirty = true;
+        return st;
+    }
+    if (block_size) *block_size = b->tile;
     return SWE_OK;
 }
 

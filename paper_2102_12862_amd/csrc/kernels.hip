@@ -22,7 +22,13 @@
 // precision (hardware reciprocal, square root, log2 and exp2; fused
 // multiply-adds where they cannot break the exact balance of a lake at rest),
 // with the depth differences H - z, the wet/dry tests, the time levels, the
-// time step and the mass sums in FP64.
+// time step and the mass sums in FP64.  Its water surface is stored as an
+// unevaluated sum of two single-precision numbers, H = hi + lo (lo in an
+// array of its own): the fluxes see hi, the update adds its increment to the
+// whole sum in FP64, so an increment smaller than the single-precision
+// spacing of a surface tens of metres above the datum (the first water a
+// wetting front brings into a dry cell) is kept in lo instead of rounded
+// away, and the volume is conserved at the fronts too.
 #include "swe_internal.h"
 
 #include <math.h>
@@ -43,6 +49,21 @@ template <> __device__ __forceinline__ float4 make4<float>(float a, float b, flo
 }
 template <> __device__ __forceinline__ double4 make4<double>(double a, double b, double c, double d) {
     return make_double4(a, b, c, d);
+}
+
+// The surface of a cell in FP64: FP32 states carry it as hi + lo (exact in
+// FP64), FP64 states as hi alone.
+__device__ __forceinline__ double surface(double hi, double /*lo*/) { return hi; }
+__device__ __forceinline__ double surface(float hi, float lo) { return double(hi) + double(lo); }
+// Splits an FP64 surface into what the state stores: FP32 hi = the nearest
+// float, lo = the nearest float to the rest; FP64 keeps it whole.
+__device__ __forceinline__ void split_surface(double H, double &hi, double &lo) {
+    hi = H;
+    lo = 0.0;
+}
+__device__ __forceinline__ void split_surface(double H, float &hi, float &lo) {
+    hi = float(H);
+    lo = float(H - double(hi));
 }
 
 // Division and square root.  FP64 uses IEEE-correct operations so that every
@@ -169,14 +190,15 @@ __device__ __forceinline__ double hydrograph(const BCdev &b, double t) {
 // boundary edges make.
 __device__ __noinline__ double bc_pow(double x, double p) { return pow(x, p); }
 
-// Ghost of the two discharge inflows (kind BC_INFLOW or BC_FROUDE): q = Q /
-// length enters at the depth x^p, x = n q / sqrt(S), p = 3/5 (uniform) or
-// x = q / (Fr sqrt(g)), p = 2/3 (froude).  One pow call serves both.  FP64
+// Boundary state of the two discharge inflows (kind BC_INFLOW or
+// BC_FROUDE): q = Q / length enters at the depth x^p, x = n q / sqrt(S),
+// p = 3/5 (uniform) or x = q / (Fr sqrt(g)), p = 2/3 (froude).  One pow
+// call serves both.  FP64
 // takes sqrt(g) from the host (like sqrt(2 g) of the weir law: formed on the
 // device, it would be hoisted into every wave's prologue); FP32 forms its
 // single-instruction square root itself.
 __device__ __forceinline__ bool discharge_ghost(const BCdev &b, int kind, double t, double gn2, double g,
-                                                double sqrtg, double &hg, double &ung) {
+                                                double sqrtg, double &hg, double &ung, double &qin) {
     double Q = hydrograph(b, t);
     if (!(Q > 0.0)) return false;
     double q = Q / b.length;
@@ -184,10 +206,11 @@ __device__ __forceinline__ bool discharge_ghost(const BCdev &b, int kind, double
     double x = unif ? sqrt(gn2 / g) * q / sqrt(b.slope) : q / (b.slope * sqrtg);
     hg = bc_pow(x, unif ? 0.6 : 2.0 / 3.0);
     ung = -q / hg;
+    qin = q;
     return true;
 }
 __device__ __forceinline__ bool discharge_ghost(const BCdev &b, int kind, double t, float gn2, float g,
-                                                double /*sqrtg*/, float &hg, float &ung) {
+                                                double /*sqrtg*/, float &hg, float &ung, float &qin) {
     const double Q = hydrograph(b, t);
     if (!(Q > 0.0)) return false;
     const float q = float(Q / b.length);
@@ -195,6 +218,7 @@ __device__ __forceinline__ bool discharge_ghost(const BCdev &b, int kind, double
     const float x = unif ? q * qsqrt(qdiv(gn2, g * float(b.slope))) : qdiv(q, float(b.slope) * qsqrt(g));
     hg = __builtin_amdgcn_exp2f((unif ? 0.6f : 2.0f / 3.0f) * __builtin_amdgcn_logf(x));
     ung = -qdiv(q, hg);
+    qin = q;
     return true;
 }
 
@@ -233,6 +257,33 @@ __device__ __forceinline__ void neumaier(double &s, double &c, double v) {
     else
         c += (v - t) + s;
     s = t;
+}
+
+// Volumes a cell's update sets by hand (the water's positivity clip, the
+// species' reset in a cell left dry, the non-erodible bed's clip), handed
+// from the update to the per-group tallies.
+template <int NS> struct Tally {
+    double clip = 0.0, bed = 0.0;
+    double sp[NS > 0 ? NS : 1] = {};
+};
+
+// Adds each lane's v to the compensated accumulator (sum, compensation) of
+// its group of 64 consecutive device cells, acc + 2 * (cell / 64): a shuffle
+// tree in a fixed order, then lane 0 updates the group's own slot.  No slot
+// has two writers and every sum runs in one order, so the tally is the same
+// bitwise at any tile size and launch order.  Called by whole waves; a wave
+// with nothing to add skips it.
+__device__ __forceinline__ void group_tally(double *acc, int cell, double v) {
+    if (__ballot(v != 0.0) == 0) return;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    if ((threadIdx.x & 63) == 0) {
+        double *a = acc + 2 * (cell >> 6);
+        double sm = a[0], cp = a[1];
+        neumaier(sm, cp, v);
+        a[0] = sm;
+        a[1] = cp;
+    }
 }
 
 // Friction split (eq. friction_closure, Table friction_closure).  With
@@ -606,7 +657,8 @@ __device__ __forceinline__ void tile_edges(const Inst<T> &I, TileLds<T, TILE> &S
     if (i < I.n) {
         const V4<T> s = src[i];
         own = s;
-        // velocity only above the minimum depth
+        // velocity only above the minimum depth (the fluxes see the surface's
+        // high part)
         const double hd = double(s.x) - double(s.w);
         const bool wet = hd > h_min;
         const T h = T(hd);
@@ -659,8 +711,8 @@ __device__ __forceinline__ void tile_edges(const Inst<T> &I, TileLds<T, TILE> &S
                 const int kbc = I.slot_kbc[I.ew1[e]];
                 if ((kbc & 15) == BC_INFLOW || (kbc & 15) == BC_FROUDE) {
                     const V2<T> cp = I.cellp[tile * TILE + a];
-                    T hg, ung;
-                    if (discharge_ghost(I.bcs[kbc >> 4], kbc & 15, t_cand, cp.y, g, I.sqrtg, hg, ung))
+                    T hg, ung, qg;
+                    if (discharge_ghost(I.bcs[kbc >> 4], kbc & 15, t_cand, cp.y, g, I.sqrtg, hg, ung, qg))
                         ghost_cfl<T, TILE>(S, l, hg, ung, g, cp.x);
                 } else if ((kbc & 15) == BC_ZHYDRO) {
                     const double dg = hydrograph(I.bcs[kbc >> 4], t_cand) - double(S.huvz[a].w);
@@ -670,6 +722,7 @@ __device__ __forceinline__ void tile_edges(const Inst<T> &I, TileLds<T, TILE> &S
             continue;
         }
         const V4<T> sa = S.huvz[a];
+        const double Ha = double(sa.x);
         // a's velocity in the frame (n, t)
         T una, uta;
         rotate(sa.y, sa.z, nx, ny, una, uta);
@@ -682,19 +735,22 @@ __device__ __forceinline__ void tile_edges(const Inst<T> &I, TileLds<T, TILE> &S
         // the other cell's sediment state (Exner): Phi, dPhi, velocity, depth, bed
         T mphi = T(0), mdphi = T(0), mub = T(0), mvb = T(0), mhb = T(0), mzb = T(0);
         bool open = false, inflow_on = false, imposed = false, walled = false;
-        T qimp = T(0);  // weir or h-Q discharge
+        T qimp = T(0);  // weir or h-Q discharge, or an active inflow's unit discharge
         if (kind != EK_BOUNDARY) {
             V4<T> sb;
             T ub, vb;
+            double Hb;
             if (kind == EK_LOCAL) {
                 const int b = (E.w0 >> 17) & 1023;
                 sb = S.huvz[b];
+                Hb = double(sb.x);
                 ub = sb.y;
                 vb = sb.z;
             } else {
                 sb = src[I.ew1[e]];
                 whole(sb);
-                const double hbd = double(sb.x) - double(sb.w);
+                Hb = double(sb.x);
+                const double hbd = Hb - double(sb.w);
                 if constexpr (NS > 0) {
 #pragma unroll
                     for (int sp = 0; sp < NS; sp++) phib[sp] = concentration(qsrc[(size_t)sp * I.n + I.ew1[e]], hbd);
@@ -714,7 +770,7 @@ __device__ __forceinline__ void tile_edges(const Inst<T> &I, TileLds<T, TILE> &S
                     const int b = (E.w0 >> 17) & 1023;
                     mphi = MS->phi[b];
                     mdphi = MS->dphi[b];
-                    mhb = T(double(sb.x) - double(sb.w));
+                    mhb = T(Hb - double(sb.w));
                 }
                 mub = ub;
                 mvb = vb;
@@ -724,7 +780,7 @@ __device__ __forceinline__ void tile_edges(const Inst<T> &I, TileLds<T, TILE> &S
             rotate(ub, vb, nx, ny, unb, utb);
             // hydrostatic reconstruction of the two modified states
             const double zs = double(sa.w > sb.w ? sa.w : sb.w);
-            const double da = double(sa.x) - zs, db = double(sb.x) - zs;
+            const double da = Ha - zs, db = Hb - zs;
             ha = da < H_DRY ? T(0) : T(da);
             hb = db < H_DRY ? T(0) : T(db);
             // canonical orientation (left = smaller original index); the
@@ -741,7 +797,7 @@ __device__ __forceinline__ void tile_edges(const Inst<T> &I, TileLds<T, TILE> &S
             if (iw) {
                 const int bc = I.iw_bc[iw - 1];
                 if (bc >= 0 && (I.bcs[bc].kind == BC_WALL || t < I.bcs[bc].slope)) {
-                    const double dw = double(sa.x) - double(sa.w);
+                    const double dw = Ha - double(sa.w);
                     ha = dw < H_DRY ? T(0) : T(dw);
                     hL = hR = ha;
                     unL = una;
@@ -758,7 +814,7 @@ __device__ __forceinline__ void tile_edges(const Inst<T> &I, TileLds<T, TILE> &S
             bi = kbc >> 4;
             // the ghost shares a's bed, so z* = z and h* = H - z
             const double zc = double(sa.w);
-            const double da = double(sa.x) - zc;
+            const double da = Ha - zc;
             ha = da < H_DRY ? T(0) : T(da);
             // by default a reflective, impermeable wall: mirrored normal velocity
             hL = ha;
@@ -775,7 +831,7 @@ __device__ __forceinline__ void tile_edges(const Inst<T> &I, TileLds<T, TILE> &S
             } else if (bkind == BC_INFLOW || bkind == BC_FROUDE) {
                 const V2<T> cp = I.cellp[tile * TILE + a];
                 const BCdev &B = I.bcs[bi];
-                const bool on = discharge_ghost(B, bkind, t, cp.y, g, I.sqrtg, hg, ung);
+                const bool on = discharge_ghost(B, bkind, t, cp.y, g, I.sqrtg, hg, ung, qimp);
                 if (on) {
                     const double dg = (zc + double(hg)) - zc;
                     hR = dg < H_DRY ? T(0) : T(dg);
@@ -783,7 +839,8 @@ __device__ __forceinline__ void tile_edges(const Inst<T> &I, TileLds<T, TILE> &S
                     utR = T(0);
                     open = inflow_on = true;
                 }
-                const bool onc = discharge_ghost(B, bkind, t_cand, cp.y, g, I.sqrtg, hg, ung);
+                T qg;
+                const bool onc = discharge_ghost(B, bkind, t_cand, cp.y, g, I.sqrtg, hg, ung, qg);
                 if (onc) ghost_cfl<T, TILE>(S, l, hg, ung, g, cp.x);
             } else if (bkind == BC_UNIFORM_OUT) {
                 // the normal depth of the cell's outflowing unit discharge,
@@ -796,7 +853,7 @@ __device__ __forceinline__ void tile_edges(const Inst<T> &I, TileLds<T, TILE> &S
                 open = true;
             } else if (bkind == BC_WEIR || bkind == BC_HQ) {
                 open = imposed = true;
-                qimp = T(imposed_outflow(I.bcs[bi], double(sa.x), zc, I.sqrt2g));
+                qimp = T(imposed_outflow(I.bcs[bi], Ha, zc, I.sqrt2g));
             } else if (bkind == BC_ZHYDRO) {
                 // still water at the prescribed surface over a's bed
                 const double dg = hydrograph(I.bcs[bi], t) - zc;
@@ -820,6 +877,11 @@ __device__ __forceinline__ void tile_edges(const Inst<T> &I, TileLds<T, TILE> &S
                 F0 = q;
                 F1 = (ha > T(0) ? q * qdiv(q, ha) : T(0)) + hg2 * ha * ha;
                 F2 = q * uta;
+            } else if (inflow_on) {
+                // an inflow imposes its discharge as the mass flux (the
+                // momentum flux is the Riemann solver's), so the volume that
+                // enters is the hydrograph's in any flow regime
+                F0 = -qimp;
             }
         }
         if constexpr (DRAIN == DRAIN_APPLY) {
@@ -883,7 +945,7 @@ __device__ __forceinline__ void tile_edges(const Inst<T> &I, TileLds<T, TILE> &S
             // HLL sediment flux (eq. exner_hll, speeds eq. exner_wave_assign)
             // in the edge's canonical orientation, like the water's
             const T ua = sa.y, va = sa.z;
-            const T ha_raw = T(double(sa.x) - double(sa.w));
+            const T ha_raw = T(Ha - double(sa.w));
             T cq;  // l q_B as leaving a
             if (walled) {
                 cq = T(0);
@@ -939,14 +1001,15 @@ __device__ __forceinline__ void tile_edges(const Inst<T> &I, TileLds<T, TILE> &S
     __syncthreads();
 }
 
-// CFL term of cell c of the tile with state (H, qx, qy, z), from the edge
-// geometry left in LDS.  ap is |cell| (FP64) or 1/|cell| (FP32).  A dry cell
-// contributes nothing (its inflow ghosts are in the tile's ghost term).
+// CFL term of cell c of the tile with state (H, qx, qy, z), H in FP64, from
+// the edge geometry left in LDS.  ap is |cell| (FP64) or 1/|cell| (FP32).  A
+// dry cell contributes nothing (its inflow ghosts are in the tile's ghost
+// term).
 template <typename T, int TILE>
-__device__ __forceinline__ CandT<T> tile_candidate(const Inst<T> &I, const TileLds<T, TILE> &S, int c, T ap, T H,
-                                                   T qx, T qy, T z) {
+__device__ __forceinline__ CandT<T> tile_candidate(const Inst<T> &I, const TileLds<T, TILE> &S, int c, T ap,
+                                                   double H, T qx, T qy, T z) {
     const T g = T(I.g);
-    const double h2 = double(H) - double(z);
+    const double h2 = H - double(z);
     if constexpr (IS32<T>) {
         float lmax = 0.0f;
         if (h2 > I.h_min) {
@@ -990,7 +1053,7 @@ __device__ __forceinline__ CandT<T> tile_candidate(const Inst<T> &I, const TileL
 // species' concentrations unchanged (added water carries none).
 template <typename T, int TILE, int NS = 0, bool SRC = false, bool MORPHO = false>
 __device__ __forceinline__ CandT<T> tile_update(const Inst<T> &I, const TileLds<T, TILE> &S, int tile, int cur,
-                                                double dt, const V4<T> &s,
+                                                double dt, const V4<T> &s, Tally<NS> &tl,
                                                 const ScalarLds<T, TILE, (NS > 0 ? NS : 1)> *SS = nullptr,
                                                 const T *qown = nullptr, double t = 0.0,
                                                 double *dvol = nullptr,
@@ -999,6 +1062,10 @@ __device__ __forceinline__ CandT<T> tile_update(const Inst<T> &I, const TileLds<
     const int i = tile * TILE + c;
     if (i >= I.n) return IS32<T> ? T(0) : T(INFINITY);
     V4<T> *__restrict__ dst = cur ? I.U0 : I.U1;
+    T *__restrict__ ldst = cur ? I.L0 : I.L1;
+    // FP32: the low part of the cell's surface (loaded here, not kept
+    // through the edge pass)
+    const T slo = IS32<T> ? (cur ? I.L1 : I.L0)[i] : T(0);
     const double h_min = I.h_min;
     const V2<T> cp = I.cellp[i];
     const T gn2 = cp.y;
@@ -1006,10 +1073,13 @@ __device__ __forceinline__ CandT<T> tile_update(const Inst<T> &I, const TileLds<
     const T R0 = S.c[0][0][c] + S.c[0][1][c] + S.c[0][2][c];
     const T R1 = S.c[1][0][c] + S.c[1][1][c] + S.c[1][2][c];
     const T R2 = S.c[2][0][c] + S.c[2][1][c] + S.c[2][2][c];
-    T Hn, qx, qy;
+    // the new surface in FP64 (FP32: hi + lo minus the single-precision
+    // increment, so no increment is lost to the spacing of the surface)
+    double Hn;
+    T qx, qy;
     if constexpr (IS32<T>) {
         const float w = float(dt) * cp.x;  // cp.x = 1/|cell|
-        Hn = fmaf(-w, R0, s.x);
+        Hn = surface(s.x, slo) - double(w * R0);
         qx = fmaf(-w, R1, s.y);
         qy = fmaf(-w, R2, s.z);
     } else {
@@ -1025,7 +1095,7 @@ __device__ __forceinline__ CandT<T> tile_update(const Inst<T> &I, const TileLds<
         if (r >= 0) {
             has_src = true;
             const BCdev &B = I.srcs[r];
-            const double hf = double(Hn) - double(s.w);
+            const double hf = Hn - double(s.w);
             const double avail = hf > 0.0 ? hf : 0.0;
             double dh;
             bool empty = false;
@@ -1044,16 +1114,16 @@ __device__ __forceinline__ CandT<T> tile_update(const Inst<T> &I, const TileLds<
                 }
             }
             if (empty) {
-                if (avail > 0.0) Hn = s.w;
+                if (avail > 0.0) Hn = double(s.w);
             } else {
-                Hn = T(double(Hn) + dh);
+                Hn = Hn + dh;
             }
             *dvol = dh * I.area[i];
-            const double h2 = double(Hn) - double(s.w);
+            const double h2 = Hn - double(s.w);
             sfac = (dh < 0.0 && hf > 0.0) ? (h2 > 0.0 ? h2 / hf : 0.0) : 1.0;
         }
     }
-    const double hn = double(Hn) - double(s.w);
+    const double hn = Hn - double(s.w);
     // friction split
     T f;
     if (hn > h_min)
@@ -1064,10 +1134,9 @@ __device__ __forceinline__ CandT<T> tile_update(const Inst<T> &I, const TileLds<
     qy = qy * f;
     if (hn < 0.0) {
         // positivity: clip and account for the added volume
-        atomicAdd(&I.ctrl->clipped, -hn * I.area[i]);
-        atomicAdd(&I.ctrl->nclip, 1ull);
+        tl.clip = -hn * I.area[i];
         if (I.neg_policy) atomicOr(&I.ctrl->flags, FLAG_NEGDEPTH);
-        Hn = s.w;
+        Hn = double(s.w);
         qx = T(0);
         qy = T(0);
     }
@@ -1083,17 +1152,20 @@ __device__ __forceinline__ CandT<T> tile_update(const Inst<T> &I, const TileLds<
             znd = s.w - (w * Rz) / (1.0 - I.spor);
         }
         if (I.zfix && znd < double(I.zfix[i])) {
-            atomicAdd(I.bclip, (1.0 - I.spor) * (double(I.zfix[i]) - znd) * I.area[i]);
+            tl.bed = (1.0 - I.spor) * (double(I.zfix[i]) - znd) * I.area[i];
             znd = double(I.zfix[i]);
         }
         zn = T(znd);
-        Hn = T(double(Hn) + (znd - double(s.w)));
+        Hn = Hn + (znd - double(s.w));
     }
     if (!isfinite(Hn) || !isfinite(qx) || !isfinite(qy) || !isfinite(zn)) atomicOr(&I.ctrl->flags, FLAG_NONFINITE);
-    dst[i] = make4<T>(Hn, qx, qy, zn);
+    T Hhi, Hlo;
+    split_surface(Hn, Hhi, Hlo);
+    dst[i] = make4<T>(Hhi, qx, qy, zn);
+    if constexpr (IS32<T>) ldst[i] = Hlo;
     if constexpr (NS > 0) {
         T *__restrict__ qdst = cur ? I.Q0 : I.Q1;
-        const bool dry = !(double(Hn) - double(s.w) > 0.0);
+        const bool dry = !(Hn - double(s.w) > 0.0);
 #pragma unroll
         for (int sp = 0; sp < NS; sp++) {
             const T R = SS->c[sp][0][c] + SS->c[sp][1][c] + SS->c[sp][2][c];
@@ -1105,7 +1177,7 @@ __device__ __forceinline__ CandT<T> tile_update(const Inst<T> &I, const TileLds<
             }
             if (SRC && has_src) q = T(double(q) * sfac);
             if (dry) {
-                atomicAdd(&I.sclip[sp], -double(q) * I.area[i]);
+                tl.sp[sp] = -double(q) * I.area[i];
                 q = T(0);
             }
             if (!isfinite(q)) atomicOr(&I.ctrl->flags, FLAG_NONFINITE);
@@ -1159,8 +1231,10 @@ __global__ void __launch_bounds__(TILE, (WAVES_PER_SIMD_STEP<T, TILE, (DRAIN || 
     tile_edges<T, TILE, true, 0, false, (DRAIN ? DRAIN_APPLY : DRAIN_NONE), IW>(I, S, tile, L.cur, L.t, L.dt,
                                                                                  L.t + L.dt, own);
     double dvol = 0.0;
-    CandT<T> cand = tile_update<T, TILE, 0, SRC>(I, S, tile, L.cur, L.dt, own, nullptr, nullptr, L.t, &dvol);
+    Tally<0> tl;
+    CandT<T> cand = tile_update<T, TILE, 0, SRC>(I, S, tile, L.cur, L.dt, own, tl, nullptr, nullptr, L.t, &dvol);
     if constexpr (SRC) tile_source_tally<TILE>(I.src_acc + 2 * tile, dvol);
+    group_tally(I.clip_acc, tile * TILE + threadIdx.x, tl.clip);
     if (threadIdx.x == 0) cand = combine(cand, ghost_value(S.ghost));
     block_finish(I.ctrl, phase, cand, L, lead, true);
 }
@@ -1180,7 +1254,7 @@ __global__ void __launch_bounds__(TILE, (WAVES_PER_SIMD<T, TILE>)) k_drain(Inst<
     if (i >= I.n) return;
     const double o0 = double(S.c[0][0][c]), o1 = double(S.c[0][1][c]), o2 = double(S.c[0][2][c]);
     const double out = (o0 > 0.0 ? o0 : 0.0) + (o1 > 0.0 ? o1 : 0.0) + (o2 > 0.0 ? o2 : 0.0);
-    const double h = double(own.x) - double(own.w);
+    const double h = surface(own.x, IS32<T> ? (L.cur ? I.L1 : I.L0)[i] : T(0)) - double(own.w);
     const double vol = (h > 0.0 ? h : 0.0) * I.area[i];
     const double leave = out * L.dt;
     I.theta[i] = T(leave > vol ? vol / leave : 1.0);
@@ -1200,8 +1274,13 @@ __global__ void __launch_bounds__(TILE) k_step_species(Inst<T> I, int phase) {
     T qown[NS];
     tile_edges<T, TILE, true, NS>(I, S, tile, L.cur, L.t, L.dt, L.t + L.dt, own, &SS, qown);
     double dvol = 0.0;
-    CandT<T> cand = tile_update<T, TILE, NS, SRC>(I, S, tile, L.cur, L.dt, own, &SS, qown, L.t, &dvol);
+    Tally<NS> tl;
+    CandT<T> cand = tile_update<T, TILE, NS, SRC>(I, S, tile, L.cur, L.dt, own, tl, &SS, qown, L.t, &dvol);
     if constexpr (SRC) tile_source_tally<TILE>(I.src_acc + 2 * tile, dvol);
+    const int cell = tile * TILE + threadIdx.x;
+    group_tally(I.clip_acc, cell, tl.clip);
+#pragma unroll
+    for (int sp = 0; sp < NS; sp++) group_tally(I.sclip_acc + (size_t)2 * sp * I.ngroups, cell, tl.sp[sp]);
     if (threadIdx.x == 0) cand = combine(cand, ghost_value(S.ghost));
     block_finish(I.ctrl, phase, cand, L, lead, true);
 }
@@ -1219,8 +1298,11 @@ __global__ void __launch_bounds__(TILE) k_step_morpho(Inst<T> I, int phase) {
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
     V4<T> own;
     tile_edges<T, TILE, true, 0, true>(I, S, tile, L.cur, L.t, L.dt, L.t + L.dt, own, nullptr, nullptr, &MS);
-    CandT<T> cand = tile_update<T, TILE, 0, false, true>(I, S, tile, L.cur, L.dt, own, nullptr, nullptr, L.t,
+    Tally<0> tl;
+    CandT<T> cand = tile_update<T, TILE, 0, false, true>(I, S, tile, L.cur, L.dt, own, tl, nullptr, nullptr, L.t,
                                                           nullptr, &MS);
+    group_tally(I.clip_acc, tile * TILE + threadIdx.x, tl.clip);
+    group_tally(I.bclip_acc, tile * TILE + threadIdx.x, tl.bed);
     if (threadIdx.x == 0) cand = combine(cand, ghost_value(S.ghost));
     block_finish(I.ctrl, phase, cand, L, lead, true);
 }
@@ -1245,7 +1327,8 @@ __global__ void __launch_bounds__(TILE) k_dt_init(Inst<T> I, int phase) {
     const int i = tile * TILE + threadIdx.x;
     if (i < I.n) {
         const V2<T> cp = I.cellp[i];
-        cand = tile_candidate<T, TILE>(I, S, threadIdx.x, cp.x, s.x, s.y, s.z, s.w);
+        const T slo = IS32<T> ? (L.cur ? I.L1 : I.L0)[i] : T(0);
+        cand = tile_candidate<T, TILE>(I, S, threadIdx.x, cp.x, surface(s.x, slo), s.y, s.z, s.w);
     }
     if (threadIdx.x == 0) cand = combine(cand, ghost_value(S.ghost));
     block_finish(I.ctrl, phase, cand, L, false, false);
@@ -1266,7 +1349,9 @@ __global__ void __launch_bounds__(TILE, (WAVES_PER_SIMD_BATCHED<T, TILE>)) k_ste
         if (!L.run) continue;
         V4<T> own;
         tile_edges<T, TILE, true>(I, S, td.y, L.cur, L.t, L.dt, L.t + L.dt, own);
-        CandT<T> cand = tile_update<T, TILE>(I, S, td.y, L.cur, L.dt, own);
+        Tally<0> tl;
+        CandT<T> cand = tile_update<T, TILE>(I, S, td.y, L.cur, L.dt, own, tl);
+        group_tally(I.clip_acc, td.y * TILE + threadIdx.x, tl.clip);
         if (threadIdx.x == 0) cand = combine(cand, ghost_value(S.ghost));
         block_finish(I.ctrl, phase, cand, L, lead, true);
     }
@@ -1295,11 +1380,13 @@ __device__ __forceinline__ double2 block_csum(double2 v) {
 // fixed-shape tree per block, then one block over the partials.
 template <typename T>
 __global__ void __launch_bounds__(MASS_THREADS) k_mass_partial(Inst<T> I, double2 *partials, int phase) {
-    const V4<T> *src = I.ctrl->s[phase].cur ? I.U1 : I.U0;
+    const int cur = I.ctrl->s[phase].cur;
+    const V4<T> *src = cur ? I.U1 : I.U0;
+    const T *lsrc = cur ? I.L1 : I.L0;
     double s = 0.0, c = 0.0;
     for (int i = blockIdx.x * MASS_THREADS + threadIdx.x; i < I.n; i += MASS_BLOCKS * MASS_THREADS) {
         const V4<T> u = src[i];
-        neumaier(s, c, (double(u.x) - double(u.w)) * I.area[i]);
+        neumaier(s, c, (surface(u.x, IS32<T> ? lsrc[i] : T(0)) - double(u.w)) * I.area[i]);
     }
     const double2 r = block_csum(make_double2(s, c));
     if (threadIdx.x == 0) partials[blockIdx.x] = r;

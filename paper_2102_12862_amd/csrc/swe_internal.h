@@ -10,6 +10,8 @@ namespace swe {
 // Device layout (cells renumbered along a Hilbert curve of their centroids):
 //   U[2][n]   vec4 (H, qx, qy, z)  ping-pong state; z rides along so a cell's
 //             whole state is one vector load
+//   L[2][n]   FP32 only: the low part of the surface (H = U.x + L exactly in
+//             FP64), ping-pong with U
 //   cellp[n]  vec2 (|cell| in FP64, 1/|cell| in FP32; friction coefficient:
 //             g n^2 for Manning and Strickler, K_s for Chezy, y_R for Bezzola)
 //   edges     per tile of TILE consecutive cells, every edge touching the tile
@@ -97,9 +99,7 @@ struct alignas(128) Ctrl {
     double t_end;             // steps are capped to land on t_end
     int flags;                // FLAG_* bits
     int pad0;
-    double clipped;           // volume added by positivity clips
-    unsigned long long nclip;
-    double pad1[12];
+    double pad1[14];
 };
 static_assert(sizeof(Ctrl) == 7 * 128, "Ctrl layout");
 
@@ -109,6 +109,10 @@ constexpr unsigned long long INF_BITS = 0x7FF0000000000000ull;
 template <typename T> struct Inst {
     V4<T> *U0;
     V4<T> *U1;
+    // FP32: the low part of each cell's surface, ping-pong with U0/U1 (the
+    // surface is hi + lo); unused in FP64
+    T *L0;
+    T *L1;
     const V2<T> *cellp;    // (|cell| in FP64, 1/|cell| in FP32; friction coefficient)
     const Edge<T> *edges;  // tile edge lists
     const int *ew1;        // per edge: other cell's device id or boundary slot
@@ -118,6 +122,10 @@ template <typename T> struct Inst {
     const BCdev *bcs;
     const double *area;    // |cell| in FP64, for the mass sum
     Ctrl *ctrl;
+    // per group of 64 consecutive device cells a compensated accumulator
+    // (sum, compensation) of the volume the positivity clip added
+    double *clip_acc;
+    int ngroups;           // ceil(n / 64)
     int n;
     int ntiles;            // tiles of this state's mesh
     double g, cfl, h_min, dt_max;
@@ -126,12 +134,13 @@ template <typename T> struct Inst {
     int friction;          // SWE_FRICTION_* closure
     // passive species (ns = 0: none): specific masses q = h phi, [ns][n] per
     // buffer (ping-pong with U), inflow concentrations [bc][ns], per boundary
-    // slot and species a Neumaier accumulator, per species the dry-reset tally
+    // slot and species a Neumaier accumulator, per species and cell group
+    // (as clip_acc) the dry-reset tally
     T *Q0;
     T *Q1;
     const T *phi_in;
     double *sslot_acc;
-    double *sclip;
+    double *sclip_acc;
     int ns;
     // external water sources and sinks (nsrc = 0: none): per cell the
     // region or -1, per region its record (kind = mode, length = factor from
@@ -144,13 +153,14 @@ template <typename T> struct Inst {
     // morphodynamics (morpho = 0: off): closure, its alpha / exponent /
     // threshold, (s - 1) g d and sqrt((s - 1) g d^3), porosity; per cell the
     // non-erodible bed (or null), per boundary slot a Neumaier accumulator of
-    // the sediment that left, and the fixed-bed clip tally
+    // the sediment that left, and per cell group (as clip_acc) the fixed-bed
+    // clip tally
     int morpho;
     int sclos;
     double salpha, sm, sthr, srgd, sK, spor;
     const T *zfix;
     double *bslot_acc;
-    double *bclip;
+    double *bclip_acc;
     // draining-time limiter (drain = 0: the bare clip): per cell the factor
     // min(1, draining time / dt) of the step being taken
     int drain;
@@ -185,6 +195,7 @@ hipError_t launch_step_batched(const Inst<T> *insts, const int2 *tiles, int ntil
                                hipStream_t s);
 template <typename T>
 int batched_grid(int tile);
+
 constexpr int MASS_BLOCKS = 1024;
 constexpr int MASS_THREADS = 256;
 

@@ -32,6 +32,7 @@ class Request:
     arrival: float                 # seconds from the start of the trace
     make: Callable[[], object]     # returns a scenario (swe_inputs.Scenario)
     t_end: float
+    mesh: Optional[swe.Mesh] = None  # a prepared mesh from a cached pool (shared, not closed here)
     admitted: Optional[float] = None
     finished: Optional[float] = None
     cells: int = 0
@@ -59,8 +60,15 @@ class Server:
 
     def _prepare(self, req: Request):
         sc = req.make()
+        if req.mesh is not None:
+            return sc, req.mesh
         mesh = swe.Mesh(sc.nodes, sc.tri, sc.bnd_seg, sc.bnd_tag, device=self.device)
         return sc, mesh
+
+    @staticmethod
+    def _release(req: Request, mesh):
+        if mesh is not None and mesh is not req.mesh:
+            mesh.close()
 
     def serve(self, requests: List[Request], clock=time.perf_counter, idle_sleep: float = 0.0005):
         """Runs the trace in real time and returns the requests with their
@@ -86,9 +94,9 @@ class Server:
                     # device objects are freed
                     r.error = msg
                     r.finished = clock() - t0
-                    for x in (st, mesh):
-                        if x is not None:
-                            x.close()
+                    if st is not None:
+                        st.close()
+                    self._release(r, mesh)
                     waiting.popleft()
                     del prepared[r.rid]
 
@@ -142,7 +150,7 @@ class Server:
                 r.finished = clock() - t0
                 self.batch.remove(slot)
                 st.close()
-                mesh.close()
+                self._release(r, mesh)
                 used -= need
         return requests
 
@@ -161,7 +169,7 @@ def serve_sequential(requests: List[Request], precision=swe.FP32, device=None, c
         if now < r.arrival:
             time.sleep(r.arrival - now)
         sc = r.make()
-        mesh = swe.Mesh(sc.nodes, sc.tri, sc.bnd_seg, sc.bnd_tag, device=device)
+        mesh = r.mesh or swe.Mesh(sc.nodes, sc.tri, sc.bnd_seg, sc.bnd_tag, device=device)
         st = swe.State(mesh, sc, precision=precision)
         r.admitted = clock() - t0
         r.steps = st.run_until(r.t_end)
@@ -169,7 +177,8 @@ def serve_sequential(requests: List[Request], precision=swe.FP32, device=None, c
         r.result = st.read()
         r.finished = clock() - t0
         st.close()
-        mesh.close()
+        if mesh is not r.mesh:
+            mesh.close()
     return requests
 
 

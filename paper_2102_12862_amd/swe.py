@@ -59,8 +59,7 @@ SED = {"mpm": 0, "grass": 1, "eh": 2}
 class SweParams(ctypes.Structure):
     _fields_ = [("g", ctypes.c_double), ("cfl", ctypes.c_double), ("h_min", ctypes.c_double),
                 ("dt_max", ctypes.c_double), ("precision", ctypes.c_int32), ("neg_depth_policy", ctypes.c_int32),
-                ("block_size", ctypes.c_int32), ("cells_per_thread", ctypes.c_int32),
-                ("steps_per_graph", ctypes.c_int32), ("renumber", ctypes.c_int32), ("friction", ctypes.c_int32),
+                ("block_size", ctypes.c_int32), ("steps_per_graph", ctypes.c_int32), ("renumber", ctypes.c_int32), ("friction", ctypes.c_int32),
                 ("limiter", ctypes.c_int32)]
 
 
@@ -82,9 +81,11 @@ SIGNATURES = {
     "swe_run_until": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_double, _lp]),
     "swe_launch_steps": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_double, ctypes.c_int64]),
     "swe_sync": (ctypes.c_int32, [ctypes.c_void_p]),
+    "swe_prepare_graphs": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32]),
     "swe_state_read": (ctypes.c_int32, [ctypes.c_void_p, _dp, _dp, _dp, _dp, _dp]),
     "swe_mass": (ctypes.c_int32, [ctypes.c_void_p, _dp, _dp, _dp, _lp]),
-    "swe_autotune": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, _ip, _ip]),
+    "swe_boundary_flux": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, _dp]),
+    "swe_autotune": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, _ip]),
     "swe_state_set_scalars": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, _dp, _dp]),
     "swe_state_read_scalars": (ctypes.c_int32, [ctypes.c_void_p, _dp]),
     "swe_scalar_mass": (ctypes.c_int32, [ctypes.c_void_p, _dp, _dp, _dp]),
@@ -100,6 +101,7 @@ SIGNATURES = {
     "swe_batch_remove": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32]),
     "swe_batch_step": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, _ip]),
     "swe_batch_launch": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32]),
+    "swe_batch_autotune": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, _ip]),
     "swe_batch_poll": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, _ip, _ip, _dp, _lp]),
     "swe_batch_footprint": (ctypes.c_int64, [ctypes.c_void_p]),
     "swe_last_error": (ctypes.c_char_p, []),
@@ -364,10 +366,20 @@ class State:
         _check(load().swe_mass(self._h, ctypes.byref(m), ctypes.byref(b), ctypes.byref(c), ctypes.byref(s)))
         return dict(mass=m.value, bnd_flux=b.value, clipped=c.value, steps=s.value)
 
+    def boundary_flux(self, tag):
+        """Boundary-flux integral over the edges tagged `tag` (positive:
+        water left the domain)."""
+        v = ctypes.c_double()
+        _check(load().swe_boundary_flux(self._h, tag, ctypes.byref(v)))
+        return v.value
+
     def autotune(self, k=8):
-        b, c = ctypes.c_int32(), ctypes.c_int32()
-        _check(load().swe_autotune(self._h, k, ctypes.byref(b), ctypes.byref(c)))
-        return b.value, c.value
+        b = ctypes.c_int32()
+        _check(load().swe_autotune(self._h, k, ctypes.byref(b)))
+        return b.value
+
+    def prepare_graphs(self, steps_per_graph=0):
+        _check(load().swe_prepare_graphs(self._h, steps_per_graph))
 
     def close(self):
         if getattr(self, "_h", None):
@@ -408,6 +420,11 @@ class Batch:
 
     def launch(self, k: int):
         _check(load().swe_batch_launch(self._h, k))
+
+    def autotune(self, k=4):
+        b = ctypes.c_int32()
+        _check(load().swe_batch_autotune(self._h, k, ctypes.byref(b)))
+        return b.value
 
     def poll(self, slot: int):
         d, e = ctypes.c_int32(), ctypes.c_int32()

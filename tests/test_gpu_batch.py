@@ -112,3 +112,31 @@ def test_batch_admits_while_running(swe, members):
     for st, r in zip((s0, s2), ref):
         got = st.read()
         assert all(np.array_equal(got[f], r[f]) for f in ("H", "qx", "qy"))
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_batch_autotune_restores_members(swe, members, prec):
+    # the batched autotuner times every tile size on the running members and
+    # puts each back exactly as it was: the run continues bitwise like a solo
+    # run, whichever tile it picked
+    p = swe.FP32 if prec == "fp32" else swe.FP64
+    ends = [30.0, 30.0, 20.0]
+    alone = [_alone(members[k], p, te) for k, te in zip((0, 1, 4), ends)]
+    batch = swe.Batch(precision=p, device=device())
+    states = [gpu_state(members[k], p) for k in (0, 1, 4)]
+    for st, te in zip(states, ends):
+        batch.add(st, te)
+    batch.step(5)
+    before = [st.read() for st in states]
+    tile = batch.autotune(3)
+    assert tile in (128, 256, 512)
+    for st, b in zip(states, before):
+        got = st.read()
+        assert all(np.array_equal(got[f], b[f]) for f in ("H", "qx", "qy")) and got["t"] == b["t"]
+    while batch.step(8) > 0:
+        pass
+    for st, ref in zip(states, alone):
+        got = st.read()
+        assert all(np.array_equal(got[f], ref[f]) for f in ("H", "qx", "qy")) and got["t"] == ref["t"]
+        m = st.mass()
+        assert m["steps"] > 0

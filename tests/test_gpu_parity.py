@@ -199,22 +199,39 @@ def test_lake_at_rest_moving_water_parity_fp32(swe):
     compare(st, sim, FP32_TOL, metric="l1")
 
 
-def test_determinism_block_sizes_and_renumbering(swe):
-    sc = S.valley_flood(n_cells=20000, scale=0.1, snapshot="wet")
+@pytest.mark.parametrize("start", ["wet", "dry"])
+def test_determinism_block_sizes_and_renumbering(swe, start):
+    # the dam break onto a dry bed clips negative depths at its front: the
+    # clip tally is kept per group of 64 device cells (a fixed shuffle tree,
+    # one writer per group) and summed in a fixed order, so it is bitwise
+    # the same at every tile size; renumbering regroups the cells, and the
+    # compensated sums then agree to the last bit or within one ulp
+    if start == "wet":
+        sc = S.valley_flood(n_cells=20000, scale=0.1, snapshot="wet")
+        t_end = 20.0
+    else:
+        sc = S.dam_break(0.5, h_right=0.0)
+        t_end = 5.0
     ref = None
     for kw in (dict(block_size=256), dict(block_size=128), dict(block_size=512),
                dict(block_size=256, renumber=False), dict(block_size=256)):
         st = gpu_state(sc, swe.FP32, **kw)
-        st.run_until(20.0)
+        st.run_until(t_end)
         r = st.read()
         m = st.mass()
         if ref is None:
             ref = (r, m)
+            if start == "dry":
+                assert m["clipped"] > 0.0
             continue
         for f in ("H", "qx", "qy"):
             assert np.array_equal(r[f], ref[0][f]), (kw, f)
         assert r["t"] == ref[0]["t"]
         assert m["mass"] == ref[1]["mass"] and m["bnd_flux"] == ref[1]["bnd_flux"]
+        if kw.get("renumber", True):
+            assert m["clipped"] == ref[1]["clipped"], kw
+        else:
+            assert abs(m["clipped"] - ref[1]["clipped"]) <= 2.3e-16 * abs(ref[1]["clipped"]), kw
 
 
 def test_restart_is_bitwise(swe):
@@ -294,8 +311,8 @@ def test_autotune_keeps_state(swe):
     sc = S.valley_flood(n_cells=20000, scale=0.1, snapshot="wet")
     a = gpu_state(sc, swe.FP32)
     b = gpu_state(sc, swe.FP32)
-    bs, cpt = b.autotune(k=3)
-    assert bs in (128, 256, 512) and cpt == 1
+    bs = b.autotune(k=3)
+    assert bs in (128, 256, 512)
     a.run_until(10.0)
     b.run_until(10.0)
     ra, rb = a.read(), b.read()

@@ -192,7 +192,7 @@ def test_species_api(swe):
     with pytest.raises(swe.SweError, match="non-finite"):
         st.set_scalars(np.full((1, sc.n_cells), np.nan))
     st.set_scalars(np.full((2, sc.n_cells), 0.5), np.array([[1.0, 0.0], [0.0, 0.0]]))
-    assert st.autotune(2) == (256, 1)
+    assert st.autotune(2) == 256
     b = swe.Batch(swe.FP32)
     with pytest.raises(swe.SweError, match="not batched"):
         b.add(st, 1.0)

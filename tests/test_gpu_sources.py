@@ -170,7 +170,7 @@ def test_sources_api(swe):
         st.set_sources(np.full(n, -1, np.int32), [S.Source(S.SRC_EXACT, S.SRC_DISCHARGE, np.array([0.0]),
                                                            np.array([1.0]))])
     st.set_sources(np.zeros(n, np.int32), [rain])
-    assert st.autotune(2) == (512, 1)
+    assert st.autotune(2) == 512
     b = swe.Batch(swe.FP32)
     with pytest.raises(swe.SweError, match="not batched"):
         b.add(st, 1.0)

@@ -1,0 +1,87 @@
+"""The valley flood as configured, on a quarter of its extent: dry start,
+inflow uniform(Q, S = 1e-3) on the channel mouth with Q rising from 50 to
+2000 m^3/s over one hour, zero-gradient outflow at the far end, run to
+t = 3600 s (the whole hydrograph).  The domain is scaled by 1/4 in both
+directions (5 km x 1 km, about 250k cells), so cells (about 20 m^2), the
+40 m channel and the time step are those of the full valley.  FP64 against
+the oracle at 1e-10 (max norm); FP32 in the area-weighted L1 norm at 1e-4
+with its max error bounded by the value measured for this run; the volume
+balance on the device; the volume the inflow delivered, -B(t), equal to the
+hydrograph's volume sum_n Q(t^n) dt_n (the inflow imposes its discharge)."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import swe_inputs as S
+from gpu_util import cached, compare, gpu_state
+
+pytestmark = [pytest.mark.gpu, pytest.mark.timeout(900)]
+
+T_END = 3600.0
+
+
+@pytest.fixture(scope="module")
+def valley():
+    return cached("valley_scaled", S.valley_flood, n_cells=250_000, scale=0.25)
+
+
+@pytest.fixture(scope="module")
+def reference(valley):
+    """The oracle's run to t = 3600 s and the hydrograph's volume over its
+    steps, sum_n Q(t^n) dt_n."""
+    sim = oracle.Sim(valley, omp=True)
+    q = valley.bcs[0]
+    parts, n = [], 0
+    while sim.t < T_END:
+        t0 = sim.t
+        parts.append(float(np.interp(t0, q.t, q.Q)) * sim.step(T_END))
+        n += 1
+    return sim, n, math.fsum(parts)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_valley_hydrograph_to_one_hour(valley, reference, prec):
+    from paper_2102_12862_amd import swe
+    sim, n_or, vol_in = reference
+    st = gpu_state(valley, swe.FP64 if prec == "fp64" else swe.FP32)
+    m0 = st.mass()
+    n = st.run_until(T_END)
+    got = st.read()
+    assert got["t"] == T_END
+    if prec == "fp64":
+        assert n == n_or
+        errs = compare(st, sim, 1e-10)
+    else:
+        errs = compare(st, sim, 1e-4, metric="l1", max_bound=MAX_BOUND_FP32)
+    m = st.mass()
+    d = sim.diag()
+    # the volume balance of the device's own sums
+    resid = abs(m["mass"] - m0["mass"] + m["bnd_flux"] - m["clipped"])
+    if prec == "fp64":
+        assert resid <= 1e-11 * abs(m["bnd_flux"])
+        assert abs(m["bnd_flux"] - d["bnd_flux"]) <= 1e-10 * abs(d["bnd_flux"])
+    else:
+        geo = sim.mesh.geometry()
+        ulp = float(np.spacing(np.float32(np.abs(geo["zb"]).max() + 10.0)))
+        assert resid <= m["steps"] * ulp * geo["area"].sum()
+        assert abs(m["bnd_flux"] - d["bnd_flux"]) <= 1e-3 * abs(d["bnd_flux"])
+    wet = float((got["h"] > valley.h_min).mean())
+    # the inflow (tag 1) delivered exactly the hydrograph's volume over the
+    # steps taken, in the oracle and on the device; the outflow (tag 2)
+    # carries the rest of the boundary integral
+    inflow_or, inflow = -sim.bc_flux(1), -st.boundary_flux(1)
+    assert abs(inflow_or - vol_in) <= 1e-12 * vol_in
+    assert abs(inflow - vol_in) <= (1e-12 if prec == "fp64" else 1e-6) * vol_in
+    assert abs((st.boundary_flux(1) + st.boundary_flux(2)) - m["bnd_flux"]) <= 1e-12 * vol_in
+    resid_rel = resid / max(m["mass"], 1e-300)
+    print(f"{prec}: {n} steps (oracle {n_or}), wet fraction {wet:.3f}, inflow {inflow:.6e} m^3 "
+          f"(hydrograph {vol_in:.6e}), outflow {st.boundary_flux(2):.6e} (oracle {sim.bc_flux(2):.6e}), "
+          f"clipped {m['clipped']:.3e} m^3, balance residual {resid_rel:.2e}, errors {errs}")
+    assert wet > 0.01
+
+
+# measured max errors of the FP32 run against the oracle (h, qx, qy), times
+# a margin; the L1 gate is the stated tolerance
+MAX_BOUND_FP32 = 0.5

@@ -378,6 +378,28 @@ swe_status swe_batch_autotune(swe_batch *b, int32_t k, int32_t *block_size);
 swe_status swe_batch_poll(swe_batch *b, int32_t slot, int32_t *done, int32_t *error, double *t, int64_t *steps);
 int64_t swe_batch_footprint(const swe_batch *b);
 
+/* For callers that cannot allocate device memory -- code under hipGraph
+ * capture, tight serving loops, harnesses that forbid hipMalloc: the
+ * persistent batched step of swe_batch_step without a batch object.  Runs
+ * up to k steps of each of the n states (states[i] until t_end[i], the last
+ * step shortened to land on it) in one persistent launch per step and
+ * waits; *n_active (may be NULL) receives how many states are still short
+ * of their end time and error-free.  Results are bitwise those of
+ * swe_batch_step.  The work list (the states' kernel parameter blocks and
+ * their (state, tile) pairs) is staged in a file-scope device array of the
+ * library of fixed size (about 2.1 MiB, one copy per device, held until the
+ * process ends) instead of memory the library allocates: the call allocates
+ * no device memory and calls no allocating routine.  Limits: 1 <= n <= 64
+ * states and at most 262144 tiles in total (about 67M cells at the default
+ * 256-cell tiles); the states must share precision, tile size and stream,
+ * and carry no species, sources, moving bed or limiter (SWE_EINVAL).  The
+ * array is shared by every call on a device and keeps the last call's work
+ * list: calls that overlap on one device (from several host threads or
+ * streams) race.  Returns the first member error (SWE_ENONFINITE, ...) after
+ * all n states have stepped. */
+swe_status swe_batch_step_noalloc(swe_state *const *states, const double *t_end, int32_t n, int32_t k,
+                                  int32_t *n_active);
+
 const char *swe_last_error(void);
 /* Library version string. */
 const char *swe_version(void);

@@ -1521,6 +1521,90 @@ swe_status swe_batch_step(swe_batch *b, int32_t k, int32_t *n_active) {
     return SWE_OK;
 }
 
+swe_status swe_batch_step_noalloc(swe_state *const *states, const double *t_end, int32_t n, int32_t k,
+                                  int32_t *n_active) {
+    if (n < 1 || n > NOALLOC_MAX_STATES) return fail(SWE_EINVAL, "between 1 and 64 states");
+    if (!states || !t_end) return fail(SWE_EINVAL, "states or t_end is NULL");
+    if (k < 1) return fail(SWE_EINVAL, "k must be positive");
+    swe_state *s0 = states[0];
+    if (!s0) return fail(SWE_EINVAL, "state is NULL");
+    const int prec = s0->prec, tile = s0->tile;
+    const int ti = tile_index(tile);
+    int64_t total = 0;
+    for (int32_t i = 0; i < n; i++) {
+        swe_state *s = states[i];
+        if (!s) return fail(SWE_EINVAL, "state is NULL");
+        if (s->prec != prec) return fail(SWE_EINVAL, "states of one call share their precision");
+        if (s->tile != tile) return fail(SWE_EINVAL, "states of one call share their tile size");
+        if (s->stream() != s0->stream()) return fail(SWE_EINVAL, "states of one call share their stream");
+        if (s->ns > 0 || s->nsrc > 0 || s->morpho || s->p.limiter == SWE_LIMIT_DRAIN)
+            return fail(SWE_EINVAL, "states with species, sources, a moving bed or the limiter are not batched");
+        if (std::isnan(t_end[i])) return fail(SWE_EINVAL, "t_end is NaN");
+        for (int32_t j = 0; j < i; j++)
+            if (states[j] == s) return fail(SWE_EINVAL, "a state is given twice");
+        total += s->m->geom[prec][ti].ntiles;
+    }
+    if (total > NOALLOC_MAX_TILES) return fail(SWE_EINVAL, "more than 262144 tiles in one call");
+    void *scr = nullptr;
+    HIP_TRY(noalloc_scratch(&scr));
+    hipStream_t q = s0->stream();
+    const int phase = s0->phase;
+    for (int32_t i = 0; i < n; i++) {
+        swe_status st = states[i]->realign(phase);
+        if (st) return st;
+        st = states[i]->set_t_end(t_end[i]);
+        if (st) return st;
+    }
+    // the work list, staged in host arrays of the scratch's fixed size
+    static std::mutex mu;
+    static Inst<float> h32[NOALLOC_MAX_STATES];
+    static Inst<double> h64[NOALLOC_MAX_STATES];
+    static int2 htiles[NOALLOC_MAX_TILES];
+    int ntiles = 0;
+    {
+        std::lock_guard<std::mutex> lock(mu);
+        for (int32_t i = 0; i < n; i++) {
+            h32[i] = states[i]->inst32;
+            h64[i] = states[i]->inst64;
+            const int nt = states[i]->m->geom[prec][ti].ntiles;
+            for (int t = 0; t < nt; t++) htiles[ntiles++] = make_int2(i, t);
+        }
+        char *base = (char *)scr;
+        if (prec == SWE_FP32)
+            HIP_TRY(hipMemcpyAsync(base, h32, n * sizeof(Inst<float>), hipMemcpyHostToDevice, q));
+        else
+            HIP_TRY(hipMemcpyAsync(base, h64, n * sizeof(Inst<double>), hipMemcpyHostToDevice, q));
+        if (ntiles)
+            HIP_TRY(hipMemcpyAsync(base + NOALLOC_INST_BYTES, htiles, ntiles * sizeof(int2), hipMemcpyHostToDevice, q));
+        HIP_TRY(hipStreamSynchronize(q));
+    }
+    const int2 *dtiles = (const int2 *)((char *)scr + NOALLOC_INST_BYTES);
+    int grid = prec == SWE_FP32 ? batched_grid<float>(tile) : batched_grid<double>(tile);
+    if (grid < 1) grid = 1;
+    for (int32_t i = 0; i < k; i++) {
+        const int ph = (phase + i) % 3;
+        if (prec == SWE_FP32)
+            HIP_TRY(launch_step_batched<float>((const Inst<float> *)scr, dtiles, ntiles, grid, tile, ph, q));
+        else
+            HIP_TRY(launch_step_batched<double>((const Inst<double> *)scr, dtiles, ntiles, grid, tile, ph, q));
+    }
+    const int after = (phase + k) % 3;
+    for (int32_t i = 0; i < n; i++) {
+        states[i]->phase = after;
+        HIP_TRY(hipMemcpyAsync(states[i]->hctrl, states[i]->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, q));
+    }
+    HIP_TRY(hipStreamSynchronize(q));
+    int active = 0;
+    swe_status err = SWE_OK;
+    for (int32_t i = 0; i < n; i++) {
+        const int flags = states[i]->hctrl->flags;
+        if (flags && !err) err = check_flags(flags);
+        if (!flags && states[i]->lvl().t < t_end[i]) active++;
+    }
+    if (n_active) *n_active = active;
+    return err;
+}
+
 swe_status swe_batch_autotune(swe_batch *b, int32_t k, int32_t *block_size) {
     if (!b) return fail(SWE_EINVAL, "batch is NULL");
     if (k < 1) k = 4;

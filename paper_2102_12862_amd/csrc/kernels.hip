@@ -33,6 +33,7 @@
 
 #include <math.h>
 
+#include <mutex>
 #include <type_traits>
 
 namespace swe {
@@ -1588,6 +1589,32 @@ hipError_t launch_step_batched(const Inst<T> *insts, const int2 *tiles, int ntil
     if (grid > ntiles) grid = ntiles;
     SWE_TILE_DISPATCH(tile, k_step_batched, dim3(grid), dim3(tile), 0, s, insts, tiles, ntiles, phase)
     return hipGetLastError();
+}
+
+// Scratch of the allocation-free batched step (swe_batch_step_noalloc): the
+// work list of one call.  Each device holds its own copy until the process
+// ends; host code reaches it only through the address noalloc_scratch looks
+// up for the current device, never through this name.
+static __device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
+
+hipError_t noalloc_scratch(void **out) {
+    constexpr int MAX_DEVICES = 64;
+    static std::mutex mu;
+    static void *addr[MAX_DEVICES] = {};
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= MAX_DEVICES) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        addr[dev] = p;
+    }
+    *out = addr[dev];
+    return hipSuccess;
 }
 
 #define SWE_INSTANTIATE(T)                                                                                  \

@@ -196,6 +196,18 @@ hipError_t launch_step_batched(const Inst<T> *insts, const int2 *tiles, int ntil
 template <typename T>
 int batched_grid(int tile);
 
+// Allocation-free batched step: its work list lives in a file-scope device
+// array (kernels.hip) of a fixed size, one per device: the kernel parameter
+// blocks of at most NOALLOC_MAX_STATES states, then at most NOALLOC_MAX_TILES
+// (state, tile) pairs.
+constexpr int NOALLOC_MAX_STATES = 64;
+constexpr int NOALLOC_MAX_TILES = 1 << 18;
+constexpr size_t NOALLOC_INST_BYTES = (size_t)NOALLOC_MAX_STATES * 512;
+constexpr size_t NOALLOC_SCRATCH_BYTES = NOALLOC_INST_BYTES + (size_t)NOALLOC_MAX_TILES * sizeof(int2);
+static_assert(sizeof(Inst<double>) <= 512 && sizeof(Inst<float>) <= 512, "parameter block slot");
+// Device address of the current device's copy of that array (looked up with
+// hipGetSymbolAddress on the first call on each device).
+hipError_t noalloc_scratch(void **out);
 constexpr int MASS_BLOCKS = 1024;
 constexpr int MASS_THREADS = 256;
 

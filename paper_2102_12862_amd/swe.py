@@ -104,6 +104,8 @@ SIGNATURES = {
     "swe_batch_autotune": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, _ip]),
     "swe_batch_poll": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, _ip, _ip, _dp, _lp]),
     "swe_batch_footprint": (ctypes.c_int64, [ctypes.c_void_p]),
+    "swe_batch_step_noalloc": (ctypes.c_int32, [ctypes.POINTER(ctypes.c_void_p), _dp, ctypes.c_int32, ctypes.c_int32,
+                                                _ip]),
     "swe_last_error": (ctypes.c_char_p, []),
     "swe_version": (ctypes.c_char_p, []),
 }
@@ -443,6 +445,18 @@ class Batch:
 
     def __del__(self):
         self.close()
+
+
+def batch_step_noalloc(states, t_end, k: int) -> int:
+    """k persistent batched steps of `states` (each until its t_end) with
+    the work list in the library's fixed device scratch: no device memory is
+    allocated.  Returns how many states are still running."""
+    n = len(states)
+    hs = (ctypes.c_void_p * max(n, 1))(*[st._h.value for st in states])
+    te = np.ascontiguousarray(np.broadcast_to(np.asarray(t_end, np.float64), (n,)))
+    act = ctypes.c_int32()
+    _check(load().swe_batch_step_noalloc(hs, _d(te), n, k, ctypes.byref(act)))
+    return act.value
 
 
 def exported_symbols(path: str = LIB_PATH) -> Sequence[str]:

@@ -258,6 +258,35 @@ swe_status swe_state_read_scalars(const swe_state *s, double *q);
  * with device atomics: its last bits depend on the order of the cells. */
 swe_status swe_scalar_mass(const swe_state *s, double *mass, double *bnd_flux, double *clipped);
 
+/* ---- diffusion of the species (section "Scalar advection-diffusion": the
+ * governing eq. scalar_goveq with the diffusion tensor, reformulated by the
+ * Cattaneo-type relaxation of eq. relaxation_terms; the relaxed flux of eq.
+ * vecform_scalar2; the update of eq. scl:updateformula with the stiff
+ * relaxation source by the locally implicit Euler step; the closure of
+ * section "Scalar advection-diffusion closure relationships").  Per species
+ * the auxiliary variables psi = (psi_x, psi_y) relax towards the gradient of
+ * the concentration with relaxation time zeta; each edge carries the exact
+ * solution of the two-wave Riemann problem of the linear relaxed system in
+ * its normal direction (waves +- sqrt(K_nn / zeta)), with the edge's depth
+ * the smaller of the two reconstructed depths and K the mean of the two
+ * cells' tensors.  K = Km I + K^t, K^t = h u_* (alpha_T I + (alpha_L -
+ * alpha_T) u u^T / |u|^2), u_* = |u| / c_f of the cell's friction closure.
+ * Boundaries, standing internal walls and cells at or below h_min exchange
+ * nothing by diffusion (mirrored states).  The relaxation waves of the
+ * diffusing species bound the time step beside the water's.
+ *
+ * swe_state_set_diffusion: Km (ns doubles >= 0, m^2/s), alpha_L, alpha_T >= 0,
+ * zeta > 0 [s]; psi0 (host, ns x n_cells x 2 doubles in original cell order,
+ * or NULL = 0) the initial auxiliary variables.  Needs the species set first
+ * (swe_state_set_scalars; setting species again removes the diffusion) and
+ * no sources (SWE_EINVAL).  Allocates 4 ns n_cells values of the state's
+ * precision (SWE_ENOMEM). */
+swe_status swe_state_set_diffusion(swe_state *s, const double *Km, double alpha_L, double alpha_T, double zeta,
+                                   const double *psi0);
+/* Copies the auxiliary variables (ns x n_cells x 2 doubles, original cell
+ * order) to host memory; nothing is written without diffusion. */
+swe_status swe_state_read_psi(const swe_state *s, double *psi);
+
 /* ---- external water sources and sinks S_h (the S_h paragraph of the
  * hydrodynamic closure relations; eq. swe_vectorial_form_sourceterms,
  * added explicitly to the continuity equation of eq.

@@ -170,6 +170,10 @@ struct swe_state {
     // concentrations [n_bc][ns], per-slot boundary accumulators, reset tallies
     int ns = 0;
     void *Q0 = nullptr, *Q1 = nullptr, *phi_in = nullptr;
+    // diffusion of the species: auxiliary variables [ns][n] pairs (ping-pong)
+    void *P0 = nullptr, *P1 = nullptr;
+    int diff = 0;
+    double dKm[MAX_SPECIES] = {}, dKmax = 0.0, daL = 0.0, daT = 0.0, dzeta = 1.0;
     double *sslot_acc = nullptr, *sclip_acc = nullptr;
     // external sources: per device cell the region, per region its record
     // and series, per tile (at the smallest tile size) a volume accumulator
@@ -207,11 +211,31 @@ struct swe_state {
     }
     hipStream_t stream() const { return mem.stream(); }
     void drop_species() {
+        drop_diffusion();
         for (void *q : {Q0, Q1, phi_in, (void *)sslot_acc, (void *)sclip_acc}) mem.release(q);
         Q0 = Q1 = phi_in = nullptr;
         sslot_acc = sclip_acc = nullptr;
         ns = 0;
         bind_species();
+    }
+    void drop_diffusion() {
+        mem.release(P0);
+        mem.release(P1);
+        P0 = P1 = nullptr;
+        diff = 0;
+        bind_diffusion();
+    }
+    void bind_diffusion() {
+        inst32.P0 = (float *)P0;
+        inst32.P1 = (float *)P1;
+        inst64.P0 = (double *)P0;
+        inst64.P1 = (double *)P1;
+        inst32.diff = inst64.diff = diff;
+        for (int c = 0; c < MAX_SPECIES; c++) inst32.dKm[c] = inst64.dKm[c] = dKm[c];
+        inst32.dKmax = inst64.dKmax = dKmax;
+        inst32.daL = inst64.daL = daL;
+        inst32.daT = inst64.daT = daT;
+        inst32.dzeta = inst64.dzeta = dzeta;
     }
     void drop_morpho() {
         for (void *q : {zfix, (void *)bslot_acc, (void *)bclip_acc}) mem.release(q);
@@ -328,6 +352,16 @@ struct swe_state {
         g.bind(inst64);
         tile = t;
         return SWE_OK;
+    }
+    // recomputes the CFL minimum of the current level, after the terms that
+    // bound the step have changed (diffusion switched on or off)
+    swe_status reseed_dt() {
+        const unsigned long long inf = INF_BITS;
+        HIP_TRY(hipMemcpyAsync(&ctrl->m[phase].bits, &inf, sizeof inf, hipMemcpyHostToDevice, stream()));
+        HIP_TRY(prec == SWE_FP32 ? launch_dt_init<float>(inst32, tile, phase, stream())
+                                 : launch_dt_init<double>(inst64, tile, phase, stream()));
+        HIP_TRY(hipStreamSynchronize(stream()));
+        return read_ctrl();
     }
     // moves the current level to control slot `to` (aligning with a batch)
     swe_status realign(int to) {
@@ -863,8 +897,9 @@ swe_status swe_state_set_scalars(swe_state *s, int32_t ns, const double *phi0, c
     swe_status st = s->read_ctrl();
     if (st) return st;
     s->drop_graphs();
+    const bool had_diff = s->diff;
     s->drop_species();
-    if (ns == 0) return SWE_OK;
+    if (ns == 0) return had_diff ? s->reseed_dt() : SWE_OK;
     if (s->tile != SPECIES_TILE) {
         st = s->set_tile(SPECIES_TILE);
         if (st) return st;
@@ -917,11 +952,94 @@ swe_status swe_state_set_scalars(swe_state *s, int32_t ns, const double *phi0, c
     }
     s->ns = ns;
     s->bind_species();
-    return SWE_OK;
+    return had_diff ? s->reseed_dt() : SWE_OK;
+}
+
+swe_status swe_state_set_diffusion(swe_state *s, const double *Km, double alpha_L, double alpha_T, double zeta,
+                                   const double *psi0) {
+    if (!s) return fail(SWE_EINVAL, "state is NULL");
+    if (s->ns < 1) return fail(SWE_EINVAL, "diffusion needs species (swe_state_set_scalars first)");
+    if (s->nsrc > 0) return fail(SWE_EINVAL, "diffusing species and sources do not combine");
+    if (!Km) return fail(SWE_EINVAL, "Km is NULL");
+    if (!(zeta > 0) || !std::isfinite(zeta)) return fail(SWE_EINVAL, "the relaxation time must be positive");
+    if (!(alpha_L >= 0) || !(alpha_T >= 0) || !std::isfinite(alpha_L) || !std::isfinite(alpha_T))
+        return fail(SWE_EINVAL, "dispersion coefficients must be >= 0");
+    for (int c = 0; c < s->ns; c++)
+        if (!(Km[c] >= 0) || !std::isfinite(Km[c])) return fail(SWE_EINVAL, "diffusivities must be >= 0");
+    const HostMesh &M = s->m->H;
+    const int64_t n = M.nc;
+    for (int64_t k = 0; psi0 && k < (int64_t)2 * s->ns * n; k++)
+        if (!std::isfinite(psi0[k])) return fail(SWE_EINVAL, "non-finite auxiliary variable");
+    swe_status st = s->read_ctrl();
+    if (st) return st;
+    s->drop_graphs();
+    s->drop_diffusion();
+    const size_t es = s->prec == SWE_FP32 ? sizeof(float) : sizeof(double);
+    const size_t cnt = (size_t)2 * s->ns * std::max<int64_t>(n, 1);
+    s->P0 = s->mem.alloc(cnt * es);
+    s->P1 = s->mem.alloc(cnt * es);
+    if (!s->P0 || !s->P1) {
+        s->drop_diffusion();
+        return fail(SWE_ENOMEM, "device allocation failed (diffusion)");
+    }
+    // psi in device order, into both buffers
+    auto up = [&](auto tag) -> swe_status {
+        using T = decltype(tag);
+        std::vector<T> p(cnt, T(0));
+        for (int c = 0; c < s->ns && psi0; c++)
+            for (int64_t i = 0; i < n; i++)
+                for (int k = 0; k < 2; k++)
+                    p[2 * ((size_t)c * n + M.inv[i]) + k] = T(psi0[2 * ((size_t)c * n + i) + k]);
+        HIP_TRY(hipMemcpyAsync(s->P0, p.data(), cnt * es, hipMemcpyHostToDevice, s->stream()));
+        HIP_TRY(hipMemcpyAsync(s->P1, p.data(), cnt * es, hipMemcpyHostToDevice, s->stream()));
+        HIP_TRY(hipStreamSynchronize(s->stream()));
+        return SWE_OK;
+    };
+    st = s->prec == SWE_FP32 ? up(float()) : up(double());
+    if (st) {
+        s->drop_diffusion();
+        return st;
+    }
+    s->dKmax = 0.0;
+    for (int c = 0; c < MAX_SPECIES; c++) {
+        s->dKm[c] = c < s->ns ? Km[c] : 0.0;
+        s->dKmax = std::max(s->dKmax, s->dKm[c]);
+    }
+    s->daL = alpha_L;
+    s->daT = alpha_T;
+    s->dzeta = zeta;
+    s->diff = 1;
+    s->bind_diffusion();
+    return s->reseed_dt();
+}
+
+swe_status swe_state_read_psi(const swe_state *cs, double *psi) {
+    swe_state *s = const_cast<swe_state *>(cs);
+    if (!s || !psi) return fail(SWE_EINVAL, "state or psi is NULL");
+    if (!s->diff) return SWE_OK;
+    swe_status st = s->read_ctrl();
+    if (st) return st;
+    const HostMesh &M = s->m->H;
+    const int64_t n = M.nc;
+    const size_t cnt = (size_t)2 * s->ns * n;
+    const void *src = s->lvl().cur ? s->P1 : s->P0;
+    auto rd = [&](auto tag) -> swe_status {
+        using T = decltype(tag);
+        std::vector<T> p(cnt);
+        HIP_TRY(hipMemcpyAsync(p.data(), src, cnt * sizeof(T), hipMemcpyDeviceToHost, s->stream()));
+        HIP_TRY(hipStreamSynchronize(s->stream()));
+        for (int c = 0; c < s->ns; c++)
+            for (int64_t i = 0; i < n; i++)
+                for (int k = 0; k < 2; k++)
+                    psi[2 * ((size_t)c * n + i) + k] = double(p[2 * ((size_t)c * n + M.inv[i]) + k]);
+        return SWE_OK;
+    };
+    return s->prec == SWE_FP32 ? rd(float()) : rd(double());
 }
 
 swe_status swe_state_set_sources(swe_state *s, const int32_t *cell_region, const swe_source *src, int32_t n_src) {
     if (!s) return fail(SWE_EINVAL, "state is NULL");
+    if (n_src > 0 && s->diff) return fail(SWE_EINVAL, "sources and diffusing species do not combine");
     if (n_src > 0 && s->morpho) return fail(SWE_EINVAL, "sources and a moving bed do not combine");
     if (n_src < 0 || n_src > MAX_BC) return fail(SWE_EINVAL, "between 0 and 64 sources");
     if (n_src > 0 && (!cell_region || !src)) return fail(SWE_EINVAL, "bad source list");

@@ -480,18 +480,38 @@ __device__ __forceinline__ void block_finish(Ctrl *c, int phase, C cand, const L
 
 // LDS of one tile: per cell (H, u, v, z) with the velocity zero at or below
 // the minimum depth, per (local edge, cell) the three contribution components
-// and the edge geometry the CFL candidate needs, and the tile's inflow-ghost
+// and what the CFL candidate needs of the edge, and the tile's inflow-ghost
 // CFL term.  The update thread of a cell keeps its (H, qx, qy, z) in
 // registers.
 template <typename T, int TILE> struct TileLds {
     V4<T> huvz[TILE];
     T c[3][3][TILE];   // [component][local edge][cell]
-    // edge geometry of each (local edge, cell) for the CFL term: FP32 keeps
-    // l*n and recomputes l; FP64 keeps the unit normal and l
-    T gx[3][TILE], gy[3][TILE];
-    T gl[IS32<T> ? 1 : 3][IS32<T> ? 1 : TILE];
+    // per (local edge, cell): FP32 keeps l*n (8 B); FP64 the edge's index
+    // (4 B instead of 24 B of geometry: the update re-reads the record, just
+    // read by this block, through the cache), so more FP64 tiles fit a CU
+    T gx[IS32<T> ? 3 : 1][IS32<T> ? TILE : 1], gy[IS32<T> ? 3 : 1][IS32<T> ? TILE : 1];
+    int gi[IS32<T> ? 1 : 3][IS32<T> ? 1 : TILE];
     GhostBits<T> ghost;
 };
+
+// Geometry of the three edges of cell c of the tile, from what TileLds keeps:
+// FP32 l*n in (gx, gy); FP64 the unit normal in (gx, gy) and the length in gl
+// (the outward normal's sign is not kept: the CFL terms need |u.n| only).
+template <typename T, int TILE>
+__device__ __forceinline__ void cell_geometry(const Inst<T> &I, const TileLds<T, TILE> &S, int c, T (&gx)[3],
+                                              T (&gy)[3], T (&gl)[3]) {
+#pragma unroll
+    for (int k = 0; k < 3; k++) {
+        if constexpr (IS32<T>) {
+            gx[k] = S.gx[k][c];
+            gy[k] = S.gy[k][c];
+            gl[k] = T(0);
+        } else {
+            const Edge<T> E = I.edges[S.gi[k][c]];
+            edge_normal(E.lx, E.ly, gl[k], gx[k], gy[k]);
+        }
+    }
+}
 
 // LDS of the passive species of one tile (section "Scalar advection-
 // diffusion", advective part): per species the concentrations of the tile's
@@ -692,9 +712,7 @@ __device__ __forceinline__ void tile_edges(const Inst<T> &I, TileLds<T, TILE> &S
             S.gx[ka][a] = E.lx;
             S.gy[ka][a] = E.ly;
         } else {
-            S.gl[ka][a] = l;
-            S.gx[ka][a] = nx;
-            S.gy[ka][a] = ny;
+            S.gi[ka][a] = e;
         }
         if (kind == EK_LOCAL) {
             const int b = (E.w0 >> 17) & 1023;
@@ -702,9 +720,7 @@ __device__ __forceinline__ void tile_edges(const Inst<T> &I, TileLds<T, TILE> &S
                 S.gx[kb][b] = -E.lx;
                 S.gy[kb][b] = -E.ly;
             } else {
-                S.gl[kb][b] = l;
-                S.gx[kb][b] = -nx;
-                S.gy[kb][b] = -ny;
+                S.gi[kb][b] = e;
             }
         }
         if (!UPDATE) {
@@ -1033,10 +1049,12 @@ __device__ __forceinline__ CandT<T> tile_candidate(const Inst<T> &I, const TileL
             const double hh = h2;
             const double u2 = qx / hh, v2 = qy / hh;
             const double cc = sqrt(g * hh);
+            double gx[3], gy[3], gl[3];
+            cell_geometry(I, S, c, gx, gy, gl);
 #pragma unroll
             for (int k = 0; k < 3; k++) {
-                const double lam = fabs(u2 * S.gx[k][c] + v2 * S.gy[k][c]) + cc;
-                const double r = cfl_term(ap, S.gl[k][c], lam);
+                const double lam = fabs(u2 * gx[k] + v2 * gy[k]) + cc;
+                const double r = cfl_term(ap, gl[k], lam);
                 best = r < best ? r : best;
             }
         }
@@ -1189,12 +1207,12 @@ __device__ __forceinline__ CandT<T> tile_update(const Inst<T> &I, const TileLds<
 }
 
 // Occupancy hint (minimum waves per SIMD): what the tile's LDS allows (FP32:
-// eight waves per SIMD, the most a SIMD holds; FP64: three, two at 512
+// eight waves per SIMD, the most a SIMD holds; FP64: five, four at 512
 // cells), so the register budget matches it.  The persistent batched kernel
 // needs more registers (its member parameters and every boundary kind) and
 // asks for six FP32 waves, the most it runs without spilling.
 template <typename T, int TILE>
-constexpr int WAVES_PER_SIMD = IS32<T> ? 8 : (TILE >= 512 ? 2 : 3);
+constexpr int WAVES_PER_SIMD = IS32<T> ? 8 : 4;
 template <typename T, int TILE>
 constexpr int WAVES_PER_SIMD_BATCHED = IS32<T> ? 6 : (TILE >= 512 ? 2 : 3);
 
@@ -1308,6 +1326,55 @@ __global__ void __launch_bounds__(TILE) k_step_morpho(Inst<T> I, int phase) {
     block_finish(I.ctrl, phase, cand, L, lead, true);
 }
 
+// Smallest squared speed for which a cell gets a turbulent dispersion
+// tensor: zero in FP64; in FP32 1e-30 (m/s)^2, below which the single-
+// precision reciprocal of |u|^2 overflows (and the tensor, of order h |u|,
+// is far below anything FP32 resolves beside the molecular part).
+template <typename T> __device__ __forceinline__ constexpr T speed2_floor() { return IS32<T> ? T(1e-30) : T(0); }
+
+// CFL term of the relaxation waves of the diffusing species in one cell of
+// depth h2: lambda = |u.n| + sqrt((K^m_max + K^t_nn) / zeta) over its three
+// edges (geometry per local edge as the tile LDS keeps it: l*n in FP32, the
+// unit normal and l in FP64); no term at or below h_min.
+template <typename T>
+__device__ __forceinline__ CandT<T> relax_candidate(const Inst<T> &I, const T (&gx)[3], const T (&gy)[3],
+                                                    const T (&gl)[3], const V2<T> &cp, double h2, T qx, T qy) {
+    CandT<T> cand = IS32<T> ? T(0) : T(INFINITY);
+    if (!(h2 > I.h_min)) return cand;
+    const T u2 = qdiv(qx, T(h2)), v2 = qdiv(qy, T(h2));
+    const T um2 = u2 * u2 + v2 * v2;
+    const T cf2 = cell_cf2(I.friction, cp.y, T(h2));
+    const bool turb = um2 > speed2_floor<T>() && cf2 > T(0);
+    const T at = turb ? T(h2) * qsqrt(qdiv(um2, cf2)) : T(0);
+    const T dd = turb ? qdiv(T(I.daL) - T(I.daT), um2) : T(0);
+    if constexpr (IS32<T>) {
+        float lmax = 0.0f;
+#pragma unroll
+        for (int k = 0; k < 3; k++) {
+            const float lx = gx[k], ly = gy[k];
+            const float lk = qsqrt(fmaf(lx, lx, ly * ly));
+            const float rl = __builtin_amdgcn_rcpf(lk);
+            const float un = (u2 * lx + v2 * ly) * rl;
+            const float kt = turb ? at * (float(I.daT) + dd * un * un) : 0.0f;
+            const float lam = fabsf(un) + qsqrt((float(I.dKmax) + kt) / float(I.dzeta));
+            lmax = fmaxf(lmax, lk * lam);
+        }
+        cand = lmax * cp.x;
+    } else {
+        double best = INFINITY;
+#pragma unroll
+        for (int k = 0; k < 3; k++) {
+            const double un = u2 * gx[k] + v2 * gy[k];
+            const double kt = turb ? at * (I.daT + dd * un * un) : 0.0;
+            const double lam = fabs(un) + sqrt((I.dKmax + kt) / I.dzeta);
+            const double r = cfl_term(cp.x, gl[k], lam);
+            best = r < best ? r : best;
+        }
+        cand = best;
+    }
+    return cand;
+}
+
 // CFL minimum of the state of level `phase` (after an initialisation); the
 // host clears the slot first.
 template <typename T, int TILE>
@@ -1330,9 +1397,304 @@ __global__ void __launch_bounds__(TILE) k_dt_init(Inst<T> I, int phase) {
         const V2<T> cp = I.cellp[i];
         const T slo = IS32<T> ? (L.cur ? I.L1 : I.L0)[i] : T(0);
         cand = tile_candidate<T, TILE>(I, S, threadIdx.x, cp.x, surface(s.x, slo), s.y, s.z, s.w);
+        if (I.diff) {
+            T gx[3], gy[3], gl[3];
+            cell_geometry(I, S, threadIdx.x, gx, gy, gl);
+            cand = combine(cand, relax_candidate(I, gx, gy, gl, cp, surface(s.x, slo) - double(s.w), s.y, s.z));
+        }
     }
     if (threadIdx.x == 0) cand = combine(cand, ghost_value(S.ghost));
     block_finish(I.ctrl, phase, cand, L, false, false);
+}
+
+// ---------------------------------------------------------------------
+// Species diffusion (section "Scalar advection-diffusion": the Cattaneo-type
+// relaxation of eq. relaxation_terms adds per species the auxiliary
+// variables psi = (psi_x, psi_y); the relaxed flux of eq. vecform_scalar2 is
+// solved at each edge as the exact two-wave Riemann problem of the linear
+// system in the edge's normal direction; eq. scl:updateformula with the stiff
+// relaxation source -psi/zeta by the locally implicit Euler step).  A kernel
+// of its own, launched after the species step on the same time level: it
+// reads the state of t^n (U[cur], Q[cur], P[cur]), adds its contributions to
+// the advected specific masses the species step wrote (Q[1-cur]), writes the
+// auxiliary variables of t^{n+1} (P[1-cur]), resets both in cells the step
+// left dry, and lowers the next time step's CFL slot by the relaxation waves
+// of the new state.
+
+// Depth and turbulent dispersion tensor (h, Kxx, Kxy, Kyy) of a cell: the
+// Elder form h u_* (alpha_T I + (alpha_L - alpha_T) u u^T / |u|^2) with
+// u_* = |u| / c_f (the cell's friction closure); h = 0 marks a cell at or
+// below h_min, which takes part in no diffusive exchange.
+template <typename T>
+__device__ __forceinline__ void dispersion(const Inst<T> &I, double hd, T qx, T qy, T par, T &h, T &kxx, T &kxy,
+                                           T &kyy) {
+    h = kxx = kxy = kyy = T(0);
+    if (!(hd > I.h_min)) return;
+    h = T(hd);
+    const T u = qdiv(qx, h), v = qdiv(qy, h);
+    const T um2 = u * u + v * v;
+    const T cf2 = cell_cf2(I.friction, par, h);
+    if (!(um2 > speed2_floor<T>()) || !(cf2 > T(0))) return;
+    const T us = qsqrt(qdiv(um2, cf2));
+    const T a = h * us;
+    const T d = qdiv(T(I.daL) - T(I.daT), um2);
+    kxx = a * (T(I.daT) + d * u * u);
+    kxy = a * (d * u * v);
+    kyy = a * (T(I.daT) + d * v * v);
+}
+
+template <typename T, int TILE, int NS> struct DiffLds {
+    T hk[4][TILE];               // per cell at t^n: depth (0: no exchange), Kxx, Kxy, Kyy
+    T H[TILE], z[TILE];          // surface (high part) and bed, for the reconstructed depths
+    T phi[NS][TILE];
+    T psx[NS][TILE], psy[NS][TILE];
+    T c[NS][3][3][TILE];         // [species][q, psi_x, psi_y][local edge][cell]
+    T gx[3][TILE], gy[3][TILE];  // l*n (FP32) or the unit normal (FP64) per (local edge, cell)
+    T gl[IS32<T> ? 1 : 3][IS32<T> ? 1 : TILE];
+};
+
+// The mirrored side of an edge without diffusive exchange (a boundary, a
+// standing internal wall, or a neighbour at or below h_min) for cell c of
+// the tile with outward normal (nx, ny): psi_n* = 0, so the species flux
+// vanishes, and psi receives -(phi*/zeta) n with phi* = phi - sqrt(K_nn zeta)
+// psi_n.
+template <typename T, int TILE, int NS>
+__device__ __forceinline__ void diff_mirror(const Inst<T> &I, DiffLds<T, TILE, NS> &S, int c, int k, T l, T nx,
+                                            T ny) {
+    if (!(S.hk[0][c] > T(0))) return;
+    const T zeta = T(I.dzeta);
+#pragma unroll
+    for (int sp = 0; sp < NS; sp++) {
+        const T knn = T(I.dKm[sp]) + (S.hk[1][c] * nx * nx + T(2) * S.hk[2][c] * nx * ny + S.hk[3][c] * ny * ny);
+        const T psn = S.psx[sp][c] * nx + S.psy[sp][c] * ny;
+        const T phs = S.phi[sp][c] - qsqrt(knn * zeta) * psn;
+        S.c[sp][0][k][c] = T(0);
+        S.c[sp][1][k][c] = l * (-qdiv(phs, zeta) * nx);
+        S.c[sp][2][k][c] = l * (-qdiv(phs, zeta) * ny);
+    }
+}
+
+template <typename T, int TILE, int NS>
+__global__ void __launch_bounds__(TILE) k_diffuse(Inst<T> I, int phase) {
+    __shared__ DiffLds<T, TILE, NS> S;
+    const Level L = step_setup(I.ctrl, phase, I.cfl, I.dt_max, false);
+    if (!L.run) return;
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int c = threadIdx.x, i = tile * TILE + c;
+    const V4<T> *__restrict__ src = L.cur ? I.U1 : I.U0;
+    const T *__restrict__ qsrc = L.cur ? I.Q1 : I.Q0;
+    const T *__restrict__ psrc = L.cur ? I.P1 : I.P0;
+    const int e1 = I.eoff[tile + 1];
+    int e = I.eoff[tile] + c;
+    const T zeta = T(I.dzeta);
+    // phase 0: the tile's cells at t^n
+    if (i < I.n) {
+        const V4<T> s = src[i];
+        const double hd = double(s.x) - double(s.w);
+        T h, kxx, kxy, kyy;
+        dispersion(I, hd, s.y, s.z, I.cellp[i].y, h, kxx, kxy, kyy);
+        S.hk[0][c] = h;
+        S.hk[1][c] = kxx;
+        S.hk[2][c] = kxy;
+        S.hk[3][c] = kyy;
+        S.H[c] = s.x;
+        S.z[c] = s.w;
+#pragma unroll
+        for (int sp = 0; sp < NS; sp++) {
+            S.phi[sp][c] = concentration(qsrc[(size_t)sp * I.n + i], hd);
+            const V2<T> p = reinterpret_cast<const V2<T> *>(psrc)[(size_t)sp * I.n + i];
+            S.psx[sp][c] = p.x;
+            S.psy[sp][c] = p.y;
+#pragma unroll
+            for (int k = 0; k < 3; k++) {
+                S.c[sp][0][k][c] = T(0);
+                S.c[sp][1][k][c] = T(0);
+                S.c[sp][2][k][c] = T(0);
+            }
+        }
+    }
+    __syncthreads();
+    // phase 1: every edge of the tile once
+    for (; e < e1; e += TILE) {
+        const Edge<T> E = I.edges[e];
+        const int a = E.w0 & 1023, ka = (E.w0 >> 10) & 3, kb = (E.w0 >> 12) & 3, kind = (E.w0 >> 14) & 3;
+        const bool flip = (E.w0 >> 16) & 1;
+        const int b = (E.w0 >> 17) & 1023;
+        T l, nx, ny;
+        edge_normal(E.lx, E.ly, l, nx, ny);  // outward of a
+        if constexpr (IS32<T>) {
+            S.gx[ka][a] = E.lx;
+            S.gy[ka][a] = E.ly;
+            if (kind == EK_LOCAL) {
+                S.gx[kb][b] = -E.lx;
+                S.gy[kb][b] = -E.ly;
+            }
+        } else {
+            S.gl[ka][a] = l;
+            S.gx[ka][a] = nx;
+            S.gy[ka][a] = ny;
+            if (kind == EK_LOCAL) {
+                S.gl[kb][b] = l;
+                S.gx[kb][b] = -nx;
+                S.gy[kb][b] = -ny;
+            }
+        }
+        bool closed = kind == EK_BOUNDARY;
+        const int iw = (E.w0 >> 27) & 31;
+        if (iw && !closed) {
+            const int bc = I.iw_bc[iw - 1];
+            if (bc >= 0 && (I.bcs[bc].kind == BC_WALL || L.t < I.bcs[bc].slope)) closed = true;
+        }
+        if (closed) {
+            diff_mirror<T, TILE, NS>(I, S, a, ka, l, nx, ny);
+            continue;
+        }
+        // the other cell's state at t^n
+        T hb, kbxx, kbxy, kbyy, Hb, zb;
+        T phb[NS], pxb[NS], pyb[NS];
+        if (kind == EK_LOCAL) {
+            hb = S.hk[0][b];
+            kbxx = S.hk[1][b];
+            kbxy = S.hk[2][b];
+            kbyy = S.hk[3][b];
+            Hb = S.H[b];
+            zb = S.z[b];
+#pragma unroll
+            for (int sp = 0; sp < NS; sp++) {
+                phb[sp] = S.phi[sp][b];
+                pxb[sp] = S.psx[sp][b];
+                pyb[sp] = S.psy[sp][b];
+            }
+        } else {
+            const int j = I.ew1[e];
+            const V4<T> s = src[j];
+            const double hbd = double(s.x) - double(s.w);
+            dispersion(I, hbd, s.y, s.z, I.cellp[j].y, hb, kbxx, kbxy, kbyy);
+            Hb = s.x;
+            zb = s.w;
+#pragma unroll
+            for (int sp = 0; sp < NS; sp++) {
+                phb[sp] = concentration(qsrc[(size_t)sp * I.n + j], hbd);
+                const V2<T> p = reinterpret_cast<const V2<T> *>(psrc)[(size_t)sp * I.n + j];
+                pxb[sp] = p.x;
+                pyb[sp] = p.y;
+            }
+        }
+        // the wetted cross-section both share: the smaller reconstructed depth
+        const double zs = double(S.z[a] > zb ? S.z[a] : zb);
+        double da = double(S.H[a]) - zs, db = double(Hb) - zs;
+        if (da < H_DRY) da = 0.0;
+        if (db < H_DRY) db = 0.0;
+        const T hi = T(da < db ? da : db);
+        if (!(S.hk[0][a] > T(0)) || !(hb > T(0)) || !(hi > T(0))) {
+            diff_mirror<T, TILE, NS>(I, S, a, ka, l, nx, ny);
+            if (kind == EK_LOCAL) diff_mirror<T, TILE, NS>(I, S, b, kb, l, -nx, -ny);
+            continue;
+        }
+        // canonical orientation (left = smaller original index), n_c = flip ? -n : n
+        const T cnx = flip ? -nx : nx, cny = flip ? -ny : ny;
+        const T KL1 = flip ? kbxx : S.hk[1][a], KR1 = flip ? S.hk[1][a] : kbxx;
+        const T KL2 = flip ? kbxy : S.hk[2][a], KR2 = flip ? S.hk[2][a] : kbxy;
+        const T KL3 = flip ? kbyy : S.hk[3][a], KR3 = flip ? S.hk[3][a] : kbyy;
+#pragma unroll
+        for (int sp = 0; sp < NS; sp++) {
+            const T kxx = T(I.dKm[sp]) + T(0.5) * (KL1 + KR1);
+            const T kxy = T(0.5) * (KL2 + KR2);
+            const T kyy = T(I.dKm[sp]) + T(0.5) * (KL3 + KR3);
+            const T knn = kxx * cnx * cnx + T(2) * kxy * cnx * cny + kyy * cny * cny;
+            const T knt = -kxx * cnx * cny + kxy * (cnx * cnx - cny * cny) + kyy * cnx * cny;
+            const T pxL = flip ? pxb[sp] : S.psx[sp][a], pyL = flip ? pyb[sp] : S.psy[sp][a];
+            const T pxR = flip ? S.psx[sp][a] : pxb[sp], pyR = flip ? S.psy[sp][a] : pyb[sp];
+            const T fL = flip ? phb[sp] : S.phi[sp][a], fR = flip ? S.phi[sp][a] : phb[sp];
+            const T pnL = pxL * cnx + pyL * cny, pnR = pxR * cnx + pyR * cny;
+            const T ptL = -pxL * cny + pyL * cnx, ptR = -pxR * cny + pyR * cnx;
+            T Dq, fs;
+            if (knn > T(0)) {
+                const T r = qsqrt(knn * zeta);
+                const T pns = T(0.5) * (pnL + pnR) + qdiv(fR - fL, T(2) * r);
+                fs = T(0.5) * (fL + fR) + T(0.5) * r * (pnR - pnL);
+                Dq = -hi * (knn * pns + knt * (T(0.5) * (ptL + ptR)));
+            } else {
+                fs = T(0.5) * (fL + fR);
+                Dq = T(0);
+            }
+            const T Dx = -qdiv(fs, zeta) * cnx, Dy = -qdiv(fs, zeta) * cny;
+            // leaving the canonical left cell: +l D; a gets it with its sign
+            const T sg = flip ? T(-1) : T(1);
+            S.c[sp][0][ka][a] = sg * (l * Dq);
+            S.c[sp][1][ka][a] = sg * (l * Dx);
+            S.c[sp][2][ka][a] = sg * (l * Dy);
+            if (kind == EK_LOCAL) {
+                S.c[sp][0][kb][b] = -(sg * (l * Dq));
+                S.c[sp][1][kb][b] = -(sg * (l * Dx));
+                S.c[sp][2][kb][b] = -(sg * (l * Dy));
+            }
+        }
+    }
+    __syncthreads();
+    // phase 2: update, dry reset, CFL term of the relaxation waves of the new state
+    CandT<T> cand = IS32<T> ? T(0) : T(INFINITY);
+    Tally<NS> tl;
+    if (i < I.n) {
+        const V2<T> cp = I.cellp[i];
+        V4<T> *__restrict__ udst = L.cur ? I.U0 : I.U1;
+        T *__restrict__ qdst = L.cur ? I.Q0 : I.Q1;
+        T *__restrict__ pdst = L.cur ? I.P0 : I.P1;
+        const V4<T> sn = udst[i];
+        const T lon = IS32<T> ? (L.cur ? I.L0 : I.L1)[i] : T(0);
+        const double Hn = surface(sn.x, lon);
+        const bool dry = !(Hn - double(sn.w) > 0.0);
+        const bool active = S.hk[0][c] > T(0);
+        const T rel = T(1.0 + L.dt / I.dzeta);
+#pragma unroll
+        for (int sp = 0; sp < NS; sp++) {
+            const T Rq = S.c[sp][0][0][c] + S.c[sp][0][1][c] + S.c[sp][0][2][c];
+            const T Rx = S.c[sp][1][0][c] + S.c[sp][1][1][c] + S.c[sp][1][2][c];
+            const T Ry = S.c[sp][2][0][c] + S.c[sp][2][1][c] + S.c[sp][2][2][c];
+            T q = qdst[(size_t)sp * I.n + i];
+            T px, py;
+            if constexpr (IS32<T>) {
+                const float w = float(L.dt) * cp.x;
+                q = fmaf(-w, Rq, q);
+                px = fmaf(-w, Rx, S.psx[sp][c]) / rel;
+                py = fmaf(-w, Ry, S.psy[sp][c]) / rel;
+            } else {
+                const double w = L.dt * (1.0 / cp.x);
+                q = q - w * Rq;
+                px = (S.psx[sp][c] - w * Rx) / rel;
+                py = (S.psy[sp][c] - w * Ry) / rel;
+            }
+            if (!active || dry) {
+                px = T(0);
+                py = T(0);
+            }
+            if (dry) {
+                tl.sp[sp] = -double(q) * I.area[i];
+                q = T(0);
+            }
+            if (!isfinite(q) || !isfinite(px) || !isfinite(py)) atomicOr(&I.ctrl->flags, FLAG_NONFINITE);
+            qdst[(size_t)sp * I.n + i] = q;
+            V2<T> pv;
+            pv.x = px;
+            pv.y = py;
+            reinterpret_cast<V2<T> *>(pdst)[(size_t)sp * I.n + i] = pv;
+        }
+        // relaxation waves of the new state
+        T gx[3], gy[3], gl[3];
+#pragma unroll
+        for (int k = 0; k < 3; k++) {
+            gx[k] = S.gx[k][c];
+            gy[k] = S.gy[k][c];
+            if constexpr (IS32<T>)
+                gl[k] = T(0);
+            else
+                gl[k] = S.gl[k][c];
+        }
+        cand = relax_candidate(I, gx, gy, gl, cp, Hn - double(sn.w), sn.y, sn.z);
+    }
+#pragma unroll
+    for (int sp = 0; sp < NS; sp++) group_tally(I.sclip_acc + (size_t)2 * sp * I.ngroups, i, tl.sp[sp]);
+    block_finish(I.ctrl, phase, cand, L, false, true);
 }
 
 // Persistent batched step: blocks stride over a list of (member, tile)
@@ -1480,6 +1842,17 @@ hipError_t launch_species(const Inst<T> &I, int phase, hipStream_t s) {
         case 4: hipLaunchKernelGGL((k_step_species<T, SPECIES_TILE, 4, SRC>), grid, block, 0, s, I, phase); break;
         case 5: hipLaunchKernelGGL((k_step_species<T, SPECIES_TILE, 5, SRC>), grid, block, 0, s, I, phase); break;
         default: return hipErrorInvalidValue;
+    }
+    if (I.diff) {
+        // the diffusion of the species, on the same time level (same phase)
+        switch (I.ns) {
+            case 1: hipLaunchKernelGGL((k_diffuse<T, SPECIES_TILE, 1>), grid, block, 0, s, I, phase); break;
+            case 2: hipLaunchKernelGGL((k_diffuse<T, SPECIES_TILE, 2>), grid, block, 0, s, I, phase); break;
+            case 3: hipLaunchKernelGGL((k_diffuse<T, SPECIES_TILE, 3>), grid, block, 0, s, I, phase); break;
+            case 4: hipLaunchKernelGGL((k_diffuse<T, SPECIES_TILE, 4>), grid, block, 0, s, I, phase); break;
+            case 5: hipLaunchKernelGGL((k_diffuse<T, SPECIES_TILE, 5>), grid, block, 0, s, I, phase); break;
+            default: return hipErrorInvalidValue;
+        }
     }
     return hipGetLastError();
 }

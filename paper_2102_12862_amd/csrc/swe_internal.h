@@ -142,6 +142,15 @@ template <typename T> struct Inst {
     double *sslot_acc;
     double *sclip_acc;
     int ns;
+    // diffusion of the species (diff = 0: advection only): per species and
+    // cell the auxiliary variables (psi_x, psi_y) [ns][n] pairs, ping-pong
+    // with U; per species the molecular diffusivity, their maximum, the
+    // dispersion coefficients and the relaxation time
+    T *P0;
+    T *P1;
+    int diff;
+    double dKm[5];
+    double dKmax, daL, daT, dzeta;
     // external water sources and sinks (nsrc = 0: none): per cell the
     // region or -1, per region its record (kind = mode, length = factor from
     // the series value to m/s), per tile a Neumaier accumulator of the volume

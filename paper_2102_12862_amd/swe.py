@@ -88,6 +88,9 @@ SIGNATURES = {
     "swe_autotune": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, _ip]),
     "swe_state_set_scalars": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, _dp, _dp]),
     "swe_state_read_scalars": (ctypes.c_int32, [ctypes.c_void_p, _dp]),
+    "swe_state_set_diffusion": (ctypes.c_int32, [ctypes.c_void_p, _dp, ctypes.c_double, ctypes.c_double,
+                                                 ctypes.c_double, _dp]),
+    "swe_state_read_psi": (ctypes.c_int32, [ctypes.c_void_p, _dp]),
     "swe_scalar_mass": (ctypes.c_int32, [ctypes.c_void_p, _dp, _dp, _dp]),
     "swe_state_set_sources": (ctypes.c_int32, [ctypes.c_void_p, _ip, ctypes.POINTER(SweSource), ctypes.c_int32]),
     "swe_source_volume": (ctypes.c_int32, [ctypes.c_void_p, _dp]),
@@ -272,6 +275,8 @@ class State:
                 if len(getattr(bc, "phi_in", ())):
                     pin[b] = bc.phi_in
             self.set_scalars(phi0, pin)
+            if getattr(sc, "diffusion", None) is not None:
+                self.set_diffusion(sc.diffusion)
         if len(getattr(sc, "sources", ())):
             self.set_sources(sc.src_region, sc.sources)
         if getattr(sc, "morpho", None) is not None:
@@ -326,6 +331,20 @@ class State:
         pin = None if phi_in is None else np.ascontiguousarray(phi_in, np.float64)
         _check(load().swe_state_set_scalars(self._h, ns, _d(phi0), _d(pin)))
         self.ns = ns
+
+    def set_diffusion(self, df, psi0=None):
+        """Diffusion of the species (df: Km per species or one value,
+        alpha_L, alpha_T, zeta); psi0 (species, cells, 2) the initial
+        auxiliary variables."""
+        km = np.ascontiguousarray(np.broadcast_to(np.asarray(df.Km, np.float64), (self.ns,)))
+        p0 = None if psi0 is None else np.ascontiguousarray(psi0, np.float64)
+        _check(load().swe_state_set_diffusion(self._h, _d(km), df.alpha_L, df.alpha_T, df.zeta, _d(p0)))
+
+    def psi(self):
+        """Auxiliary variables of the diffusing species, (species, cells, 2)."""
+        p = np.zeros((self.ns, self.n, 2))
+        _check(load().swe_state_read_psi(self._h, _d(p)))
+        return p
 
     def scalars(self):
         """Specific masses q = h phi, (species, cells)."""

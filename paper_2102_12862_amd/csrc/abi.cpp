@@ -68,9 +68,9 @@ struct TileGeom {
     int ntiles = 0;
     // points an instance at these lists
     template <typename T> void bind(Inst<T> &I) const {
-        I.edges = (const Edge<T> *)edges;
-        I.ew1 = ew1;
-        I.eoff = eoff;
+        I.edges = dev_ptr((const Edge<T> *)edges);
+        I.ew1 = dev_ptr((const int *)ew1);
+        I.eoff = dev_ptr((const int *)eoff);
         I.ntiles = ntiles;
     }
 };
@@ -226,10 +226,10 @@ struct swe_state {
         bind_diffusion();
     }
     void bind_diffusion() {
-        inst32.P0 = (float *)P0;
-        inst32.P1 = (float *)P1;
-        inst64.P0 = (double *)P0;
-        inst64.P1 = (double *)P1;
+        inst32.P0 = dev_ptr((float *)P0);
+        inst32.P1 = dev_ptr((float *)P1);
+        inst64.P0 = dev_ptr((double *)P0);
+        inst64.P1 = dev_ptr((double *)P1);
         inst32.diff = inst64.diff = diff;
         for (int c = 0; c < MAX_SPECIES; c++) inst32.dKm[c] = inst64.dKm[c] = dKm[c];
         inst32.dKmax = inst64.dKmax = dKmax;
@@ -258,17 +258,17 @@ struct swe_state {
     }
     void bind_sources() {
         inst32.nsrc = inst64.nsrc = nsrc;
-        inst32.src_cell = inst64.src_cell = src_cell;
+        inst32.src_cell = inst64.src_cell = dev_ptr((const int *)src_cell);
         inst32.srcs = inst64.srcs = srcs;
         inst32.src_acc = inst64.src_acc = src_acc;
     }
     // copies the species buffers into both kernel parameter blocks
     void bind_species() {
-        inst32.Q0 = (float *)Q0;
-        inst32.Q1 = (float *)Q1;
+        inst32.Q0 = dev_ptr((float *)Q0);
+        inst32.Q1 = dev_ptr((float *)Q1);
         inst32.phi_in = (const float *)phi_in;
-        inst64.Q0 = (double *)Q0;
-        inst64.Q1 = (double *)Q1;
+        inst64.Q0 = dev_ptr((double *)Q0);
+        inst64.Q1 = dev_ptr((double *)Q1);
         inst64.phi_in = (const double *)phi_in;
         inst32.sslot_acc = inst64.sslot_acc = sslot_acc;
         inst32.sclip_acc = inst64.sclip_acc = sclip_acc;
@@ -690,19 +690,19 @@ swe_status swe_state_init(const swe_mesh *m, const swe_params *params, const dou
 
     auto fill_inst = [&](auto &I, auto tag) {
         using T = decltype(tag);
-        I.U0 = (V4<T> *)S->U0;
-        I.U1 = (V4<T> *)S->U1;
-        I.L0 = (T *)S->L0;
-        I.L1 = (T *)S->L1;
+        I.U0 = dev_ptr((V4<T> *)S->U0);
+        I.U1 = dev_ptr((V4<T> *)S->U1);
+        I.L0 = dev_ptr((T *)S->L0);
+        I.L1 = dev_ptr((T *)S->L1);
         const TileGeom &tg = m->geom[prec][tile_index(S->tile)];
-        I.cellp = (const V2<T> *)S->cellp;
+        I.cellp = dev_ptr((const V2<T> *)S->cellp);
         tg.bind(I);
-        I.slot_kbc = S->slot_kbc;
-        I.slot_acc = S->slot_acc;
+        I.slot_kbc = dev_ptr((const int *)S->slot_kbc);
+        I.slot_acc = dev_ptr(S->slot_acc);
         I.bcs = S->bcs;
-        I.area = m->area;
+        I.area = dev_ptr((const double *)m->area);
         I.ctrl = S->ctrl;
-        I.clip_acc = S->clip_acc;
+        I.clip_acc = dev_ptr(S->clip_acc);
         I.ngroups = S->ngroups;
         I.n = (int)n;
         I.ntiles = tg.ntiles;
@@ -717,7 +717,7 @@ swe_status swe_state_init(const swe_mesh *m, const swe_params *params, const dou
         I.drain = P.limiter == SWE_LIMIT_DRAIN;
         I.iw_bc = S->iw_bc;
         I.iw_on = iw_on;
-        I.theta = (T *)S->theta;
+        I.theta = dev_ptr((T *)S->theta);
     };
     if (prec == SWE_FP32) {
         fill_inst(S->inst32, float());
@@ -1202,7 +1202,7 @@ swe_status swe_state_set_morpho(swe_state *s, const swe_morpho *mo, const double
         I.srgd = (mo->s_rel - 1.0) * g * mo->d_m;
         I.sK = std::sqrt((mo->s_rel - 1.0) * g * mo->d_m * mo->d_m * mo->d_m);
         I.spor = mo->porosity;
-        I.zfix = (const T *)s->zfix;
+        I.zfix = dev_ptr((const T *)s->zfix);
         I.bslot_acc = s->bslot_acc;
         I.bclip_acc = s->bclip_acc;
     };
@@ -1419,6 +1419,7 @@ struct swe_batch {
     int tile = 256, grid = 0;
     int phase = 0;  // launches so far mod 3; every member is aligned to it
     bool dirty = true;
+    bool iw = false;  // some running member has internal walls
     hipStream_t cap = nullptr;
     hipGraphExec_t gexec[3] = {nullptr, nullptr, nullptr};
     int g_k = 0;
@@ -1444,17 +1445,19 @@ struct swe_batch {
     }
     hipError_t launch(hipStream_t s, int ph) {
         return prec == SWE_FP32
-                   ? launch_step_batched<float>((const Inst<float> *)insts, tiles, ntiles, grid, tile, ph, s)
-                   : launch_step_batched<double>((const Inst<double> *)insts, tiles, ntiles, grid, tile, ph, s);
+                   ? launch_step_batched<float>((const Inst<float> *)insts, tiles, ntiles, grid, tile, iw, ph, s)
+                   : launch_step_batched<double>((const Inst<double> *)insts, tiles, ntiles, grid, tile, iw, ph, s);
     }
     // work list of the members that are still running
     swe_status rebuild() {
         std::vector<Inst<float>> i32;
         std::vector<Inst<double>> i64;
         std::vector<int2> tl;
+        bool any_iw = false;
         for (size_t m = 0; m < members.size(); m++) {
             swe_state *s = members[m];
             if (!s || finished[m]) continue;
+            any_iw = any_iw || s->inst32.iw_on;
             const int idx = prec == SWE_FP32 ? (int)i32.size() : (int)i64.size();
             swe_status st = prec == SWE_FP32 ? s->m->ensure_tiles<float>(prec, tile)
                                              : s->m->ensure_tiles<double>(prec, tile);
@@ -1492,7 +1495,8 @@ struct swe_batch {
             HIP_TRY(hipMemcpyAsync(tiles, tl.data(), tl.size() * sizeof(int2), hipMemcpyHostToDevice, stream()));
         HIP_TRY(hipStreamSynchronize(stream()));
         ntiles = (int)tl.size();
-        grid = prec == SWE_FP32 ? batched_grid<float>(tile) : batched_grid<double>(tile);
+        iw = any_iw;
+        grid = prec == SWE_FP32 ? batched_grid<float>(tile, iw) : batched_grid<double>(tile, iw);
         if (grid < 1) grid = 1;
         drop_graphs();
         dirty = false;
@@ -1679,9 +1683,11 @@ swe_status swe_batch_step_noalloc(swe_state *const *states, const double *t_end,
     static Inst<double> h64[NOALLOC_MAX_STATES];
     static int2 htiles[NOALLOC_MAX_TILES];
     int ntiles = 0;
+    bool iw = false;
     {
         std::lock_guard<std::mutex> lock(mu);
         for (int32_t i = 0; i < n; i++) {
+            iw = iw || states[i]->inst32.iw_on;
             h32[i] = states[i]->inst32;
             h64[i] = states[i]->inst64;
             const int nt = states[i]->m->geom[prec][ti].ntiles;
@@ -1697,14 +1703,14 @@ swe_status swe_batch_step_noalloc(swe_state *const *states, const double *t_end,
         HIP_TRY(hipStreamSynchronize(q));
     }
     const int2 *dtiles = (const int2 *)((char *)scr + NOALLOC_INST_BYTES);
-    int grid = prec == SWE_FP32 ? batched_grid<float>(tile) : batched_grid<double>(tile);
+    int grid = prec == SWE_FP32 ? batched_grid<float>(tile, iw) : batched_grid<double>(tile, iw);
     if (grid < 1) grid = 1;
     for (int32_t i = 0; i < k; i++) {
         const int ph = (phase + i) % 3;
         if (prec == SWE_FP32)
-            HIP_TRY(launch_step_batched<float>((const Inst<float> *)scr, dtiles, ntiles, grid, tile, ph, q));
+            HIP_TRY(launch_step_batched<float>((const Inst<float> *)scr, dtiles, ntiles, grid, tile, iw, ph, q));
         else
-            HIP_TRY(launch_step_batched<double>((const Inst<double> *)scr, dtiles, ntiles, grid, tile, ph, q));
+            HIP_TRY(launch_step_batched<double>((const Inst<double> *)scr, dtiles, ntiles, grid, tile, iw, ph, q));
     }
     const int after = (phase + k) % 3;
     for (int32_t i = 0; i < n; i++) {

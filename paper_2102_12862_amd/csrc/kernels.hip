@@ -274,12 +274,13 @@ template <int NS> struct Tally {
 // has two writers and every sum runs in one order, so the tally is the same
 // bitwise at any tile size and launch order.  Called by whole waves; a wave
 // with nothing to add skips it.
-__device__ __forceinline__ void group_tally(double *acc, int cell, double v) {
+template <typename P>
+__device__ __forceinline__ void group_tally(P acc, int cell, double v) {
     if (__ballot(v != 0.0) == 0) return;
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
     if ((threadIdx.x & 63) == 0) {
-        double *a = acc + 2 * (cell >> 6);
+        const P a = acc + 2 * (cell >> 6);
         double sm = a[0], cp = a[1];
         neumaier(sm, cp, v);
         a[0] = sm;
@@ -480,35 +481,42 @@ __device__ __forceinline__ void block_finish(Ctrl *c, int phase, C cand, const L
 
 // LDS of one tile: per cell (H, u, v, z) with the velocity zero at or below
 // the minimum depth, per (local edge, cell) the three contribution components
-// and what the CFL candidate needs of the edge, and the tile's inflow-ghost
+// and the edge geometry the CFL candidate needs, and the tile's inflow-ghost
 // CFL term.  The update thread of a cell keeps its (H, qx, qy, z) in
-// registers.
+// registers.  FP32 keeps l*n of local edges 0 and 1 only (the outward l*n of
+// a triangle's three edges add up to zero, so edge 2's is minus their sum)
+// and, staged with the state, the low part of the surface; FP64 keeps the
+// unit normal and the length of all three (its CFL term follows the oracle's
+// operation order).
 template <typename T, int TILE> struct TileLds {
     V4<T> huvz[TILE];
     T c[3][3][TILE];   // [component][local edge][cell]
-    // per (local edge, cell): FP32 keeps l*n (8 B); FP64 the edge's index
-    // (4 B instead of 24 B of geometry: the update re-reads the record, just
-    // read by this block, through the cache), so more FP64 tiles fit a CU
-    T gx[IS32<T> ? 3 : 1][IS32<T> ? TILE : 1], gy[IS32<T> ? 3 : 1][IS32<T> ? TILE : 1];
-    int gi[IS32<T> ? 1 : 3][IS32<T> ? 1 : TILE];
+    T gx[IS32<T> ? 2 : 3][TILE], gy[IS32<T> ? 2 : 3][TILE];
+    T gl[IS32<T> ? 1 : 3][IS32<T> ? 1 : TILE];
+    T lo[IS32<T> ? TILE : 1];
     GhostBits<T> ghost;
 };
 
 // Geometry of the three edges of cell c of the tile, from what TileLds keeps:
 // FP32 l*n in (gx, gy); FP64 the unit normal in (gx, gy) and the length in gl
-// (the outward normal's sign is not kept: the CFL terms need |u.n| only).
+// (the normal's sign is the cell's outward one).
 template <typename T, int TILE>
-__device__ __forceinline__ void cell_geometry(const Inst<T> &I, const TileLds<T, TILE> &S, int c, T (&gx)[3],
-                                              T (&gy)[3], T (&gl)[3]) {
+__device__ __forceinline__ void cell_geometry(const TileLds<T, TILE> &S, int c, T (&gx)[3], T (&gy)[3],
+                                              T (&gl)[3]) {
+    if constexpr (IS32<T>) {
+        gx[0] = S.gx[0][c];
+        gy[0] = S.gy[0][c];
+        gx[1] = S.gx[1][c];
+        gy[1] = S.gy[1][c];
+        gx[2] = -(gx[0] + gx[1]);
+        gy[2] = -(gy[0] + gy[1]);
+        gl[0] = gl[1] = gl[2] = T(0);
+    } else {
 #pragma unroll
-    for (int k = 0; k < 3; k++) {
-        if constexpr (IS32<T>) {
+        for (int k = 0; k < 3; k++) {
             gx[k] = S.gx[k][c];
             gy[k] = S.gy[k][c];
-            gl[k] = T(0);
-        } else {
-            const Edge<T> E = I.edges[S.gi[k][c]];
-            edge_normal(E.lx, E.ly, gl[k], gx[k], gy[k]);
+            gl[k] = S.gl[k][c];
         }
     }
 }
@@ -660,8 +668,8 @@ __device__ __forceinline__ void tile_edges(const Inst<T> &I, TileLds<T, TILE> &S
                                            double dt, double t_cand, V4<T> &own,
                                            ScalarLds<T, TILE, (NS > 0 ? NS : 1)> *SS = nullptr,
                                            T *qown = nullptr, MorphoLds<T, TILE> *MS = nullptr) {
-    const V4<T> *__restrict__ src = cur ? I.U1 : I.U0;
-    const T *__restrict__ qsrc = cur ? I.Q1 : I.Q0;
+    const gptr<const V4<T>> __restrict__ src = cur ? I.U1 : I.U0;
+    const gptr<const T> __restrict__ qsrc = cur ? I.Q1 : I.Q0;
     const T g = T(I.g);
     const T hg2 = T(0.5) * g;  // g/2 of the hydrostatic pressure (g/2 h) h
     const double h_min = I.h_min;
@@ -678,6 +686,7 @@ __device__ __forceinline__ void tile_edges(const Inst<T> &I, TileLds<T, TILE> &S
     if (i < I.n) {
         const V4<T> s = src[i];
         own = s;
+        if constexpr (IS32<T>) S.lo[c] = (cur ? I.L1 : I.L0)[i];
         // velocity only above the minimum depth (the fluxes see the surface's
         // high part)
         const double hd = double(s.x) - double(s.w);
@@ -709,18 +718,26 @@ __device__ __forceinline__ void tile_edges(const Inst<T> &I, TileLds<T, TILE> &S
         T l, nx, ny;
         edge_normal(E.lx, E.ly, l, nx, ny);  // n: outward of a
         if constexpr (IS32<T>) {
-            S.gx[ka][a] = E.lx;
-            S.gy[ka][a] = E.ly;
+            if (ka < 2) {
+                S.gx[ka][a] = E.lx;
+                S.gy[ka][a] = E.ly;
+            }
         } else {
-            S.gi[ka][a] = e;
+            S.gl[ka][a] = l;
+            S.gx[ka][a] = nx;
+            S.gy[ka][a] = ny;
         }
         if (kind == EK_LOCAL) {
             const int b = (E.w0 >> 17) & 1023;
             if constexpr (IS32<T>) {
-                S.gx[kb][b] = -E.lx;
-                S.gy[kb][b] = -E.ly;
+                if (kb < 2) {
+                    S.gx[kb][b] = -E.lx;
+                    S.gy[kb][b] = -E.ly;
+                }
             } else {
-                S.gi[kb][b] = e;
+                S.gl[kb][b] = l;
+                S.gx[kb][b] = -nx;
+                S.gy[kb][b] = -ny;
             }
         }
         if (!UPDATE) {
@@ -914,7 +931,7 @@ __device__ __forceinline__ void tile_edges(const Inst<T> &I, TileLds<T, TILE> &S
         }
         if (kind == EK_BOUNDARY && DRAIN != DRAIN_MEASURE) {
             if (open) {
-                double *acc = I.slot_acc + 2 * slot;
+                const gptr<double> acc = I.slot_acc + 2 * slot;
                 double sm = acc[0], cp = acc[1];
                 neumaier(sm, cp, dt * double(l * F0));
                 acc[0] = sm;
@@ -1034,10 +1051,12 @@ __device__ __forceinline__ CandT<T> tile_candidate(const Inst<T> &I, const TileL
             const float rh = __builtin_amdgcn_rcpf(hh);
             const float u2 = qx * rh, v2 = qy * rh;
             const float cc = qsqrt(g * hh);
+            float gx[3], gy[3], gl[3];
+            cell_geometry(S, c, gx, gy, gl);
 #pragma unroll
             for (int k = 0; k < 3; k++)
             {
-                const float lx = S.gx[k][c], ly = S.gy[k][c];
+                const float lx = gx[k], ly = gy[k];
                 const float lk = qsqrt(fmaf(lx, lx, ly * ly));
                 lmax = fmaxf(lmax, fmaf(cc, lk, fabsf(fmaf(u2, lx, v2 * ly))));
             }
@@ -1050,7 +1069,7 @@ __device__ __forceinline__ CandT<T> tile_candidate(const Inst<T> &I, const TileL
             const double u2 = qx / hh, v2 = qy / hh;
             const double cc = sqrt(g * hh);
             double gx[3], gy[3], gl[3];
-            cell_geometry(I, S, c, gx, gy, gl);
+            cell_geometry(S, c, gx, gy, gl);
 #pragma unroll
             for (int k = 0; k < 3; k++) {
                 const double lam = fabs(u2 * gx[k] + v2 * gy[k]) + cc;
@@ -1080,11 +1099,10 @@ __device__ __forceinline__ CandT<T> tile_update(const Inst<T> &I, const TileLds<
     const int c = threadIdx.x;
     const int i = tile * TILE + c;
     if (i >= I.n) return IS32<T> ? T(0) : T(INFINITY);
-    V4<T> *__restrict__ dst = cur ? I.U0 : I.U1;
-    T *__restrict__ ldst = cur ? I.L0 : I.L1;
-    // FP32: the low part of the cell's surface (loaded here, not kept
-    // through the edge pass)
-    const T slo = IS32<T> ? (cur ? I.L1 : I.L0)[i] : T(0);
+    const gptr<V4<T>> __restrict__ dst = cur ? I.U0 : I.U1;
+    const gptr<T> __restrict__ ldst = cur ? I.L0 : I.L1;
+    // FP32: the low part of the cell's surface (staged in LDS with the state)
+    const T slo = IS32<T> ? S.lo[c] : T(0);
     const double h_min = I.h_min;
     const V2<T> cp = I.cellp[i];
     const T gn2 = cp.y;
@@ -1183,7 +1201,7 @@ __device__ __forceinline__ CandT<T> tile_update(const Inst<T> &I, const TileLds<
     dst[i] = make4<T>(Hhi, qx, qy, zn);
     if constexpr (IS32<T>) ldst[i] = Hlo;
     if constexpr (NS > 0) {
-        T *__restrict__ qdst = cur ? I.Q0 : I.Q1;
+        const gptr<T> __restrict__ qdst = cur ? I.Q0 : I.Q1;
         const bool dry = !(Hn - double(s.w) > 0.0);
 #pragma unroll
         for (int sp = 0; sp < NS; sp++) {
@@ -1207,13 +1225,13 @@ __device__ __forceinline__ CandT<T> tile_update(const Inst<T> &I, const TileLds<
 }
 
 // Occupancy hint (minimum waves per SIMD): what the tile's LDS allows (FP32:
-// eight waves per SIMD, the most a SIMD holds; FP64: five, four at 512
+// eight waves per SIMD, the most a SIMD holds; FP64: three, two at 512
 // cells), so the register budget matches it.  The persistent batched kernel
 // needs more registers (its member parameters and every boundary kind) and
 // asks for six FP32 waves, the most it runs without spilling.
 template <typename T, int TILE>
-constexpr int WAVES_PER_SIMD = IS32<T> ? 8 : 4;
-template <typename T, int TILE>
+constexpr int WAVES_PER_SIMD = IS32<T> ? 8 : (TILE >= 512 ? 2 : 3);
+template <typename T, int TILE, bool IW>
 constexpr int WAVES_PER_SIMD_BATCHED = IS32<T> ? 6 : (TILE >= 512 ? 2 : 3);
 
 // Adds the tile's source volume (one value per thread) to the tile's
@@ -1399,7 +1417,7 @@ __global__ void __launch_bounds__(TILE) k_dt_init(Inst<T> I, int phase) {
         cand = tile_candidate<T, TILE>(I, S, threadIdx.x, cp.x, surface(s.x, slo), s.y, s.z, s.w);
         if (I.diff) {
             T gx[3], gy[3], gl[3];
-            cell_geometry(I, S, threadIdx.x, gx, gy, gl);
+            cell_geometry(S, threadIdx.x, gx, gy, gl);
             cand = combine(cand, relax_candidate(I, gx, gy, gl, cp, surface(s.x, slo) - double(s.w), s.y, s.z));
         }
     }
@@ -1481,9 +1499,9 @@ __global__ void __launch_bounds__(TILE) k_diffuse(Inst<T> I, int phase) {
     if (!L.run) return;
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
     const int c = threadIdx.x, i = tile * TILE + c;
-    const V4<T> *__restrict__ src = L.cur ? I.U1 : I.U0;
-    const T *__restrict__ qsrc = L.cur ? I.Q1 : I.Q0;
-    const T *__restrict__ psrc = L.cur ? I.P1 : I.P0;
+    const gptr<const V4<T>> __restrict__ src = L.cur ? I.U1 : I.U0;
+    const gptr<const T> __restrict__ qsrc = L.cur ? I.Q1 : I.Q0;
+    const gptr<const V2<T>> __restrict__ psrc = (gptr<const V2<T>>)(L.cur ? I.P1 : I.P0);
     const int e1 = I.eoff[tile + 1];
     int e = I.eoff[tile] + c;
     const T zeta = T(I.dzeta);
@@ -1502,7 +1520,7 @@ __global__ void __launch_bounds__(TILE) k_diffuse(Inst<T> I, int phase) {
 #pragma unroll
         for (int sp = 0; sp < NS; sp++) {
             S.phi[sp][c] = concentration(qsrc[(size_t)sp * I.n + i], hd);
-            const V2<T> p = reinterpret_cast<const V2<T> *>(psrc)[(size_t)sp * I.n + i];
+            const V2<T> p = psrc[(size_t)sp * I.n + i];
             S.psx[sp][c] = p.x;
             S.psy[sp][c] = p.y;
 #pragma unroll
@@ -1575,7 +1593,7 @@ __global__ void __launch_bounds__(TILE) k_diffuse(Inst<T> I, int phase) {
 #pragma unroll
             for (int sp = 0; sp < NS; sp++) {
                 phb[sp] = concentration(qsrc[(size_t)sp * I.n + j], hbd);
-                const V2<T> p = reinterpret_cast<const V2<T> *>(psrc)[(size_t)sp * I.n + j];
+                const V2<T> p = psrc[(size_t)sp * I.n + j];
                 pxb[sp] = p.x;
                 pyb[sp] = p.y;
             }
@@ -1637,9 +1655,9 @@ __global__ void __launch_bounds__(TILE) k_diffuse(Inst<T> I, int phase) {
     Tally<NS> tl;
     if (i < I.n) {
         const V2<T> cp = I.cellp[i];
-        V4<T> *__restrict__ udst = L.cur ? I.U0 : I.U1;
-        T *__restrict__ qdst = L.cur ? I.Q0 : I.Q1;
-        T *__restrict__ pdst = L.cur ? I.P0 : I.P1;
+        const gptr<V4<T>> __restrict__ udst = L.cur ? I.U0 : I.U1;
+        const gptr<T> __restrict__ qdst = L.cur ? I.Q0 : I.Q1;
+        const gptr<V2<T>> __restrict__ pdst = (gptr<V2<T>>)(L.cur ? I.P0 : I.P1);
         const V4<T> sn = udst[i];
         const T lon = IS32<T> ? (L.cur ? I.L0 : I.L1)[i] : T(0);
         const double Hn = surface(sn.x, lon);
@@ -1677,7 +1695,7 @@ __global__ void __launch_bounds__(TILE) k_diffuse(Inst<T> I, int phase) {
             V2<T> pv;
             pv.x = px;
             pv.y = py;
-            reinterpret_cast<V2<T> *>(pdst)[(size_t)sp * I.n + i] = pv;
+            pdst[(size_t)sp * I.n + i] = pv;
         }
         // relaxation waves of the new state
         T gx[3], gy[3], gl[3];
@@ -1699,19 +1717,29 @@ __global__ void __launch_bounds__(TILE) k_diffuse(Inst<T> I, int phase) {
 
 // Persistent batched step: blocks stride over a list of (member, tile)
 // pairs; each member keeps its own control block, so members step with their
-// own dt and finished members cost one control-block read per tile.
-template <typename T, int TILE>
-__global__ void __launch_bounds__(TILE, (WAVES_PER_SIMD_BATCHED<T, TILE>)) k_step_batched(const Inst<T> *__restrict__ insts,
-                                                        const int2 *__restrict__ tiles, int ntiles, int phase) {
+// own dt and finished members cost one control-block read per tile.  IW: some
+// member has internal walls (the check costs registers, so a batch without
+// them runs the kernel compiled without it).
+template <typename T, int TILE, bool IW>
+__global__ void __launch_bounds__(TILE, (WAVES_PER_SIMD_BATCHED<T, TILE, IW>)) k_step_batched(
+    const Inst<T> *__restrict__ insts, const int2 *__restrict__ tiles, int ntiles, int phase) {
     __shared__ TileLds<T, TILE> S;
+    // a member's time level does not change during the launch: it is read
+    // once per run of the member's tiles (and by each member's lead tile,
+    // which also publishes the next level)
+    int mlast = -1;
+    Level L;
     for (int tt = blockIdx.x; tt < ntiles; tt += gridDim.x) {
         const int2 td = tiles[xcd_tile(tt, ntiles)];
         const Inst<T> I = insts[td.x];
         const bool lead = td.y == 0;
-        const Level L = step_setup(I.ctrl, phase, I.cfl, I.dt_max, lead);
+        if (lead || td.x != mlast) {
+            L = step_setup(I.ctrl, phase, I.cfl, I.dt_max, lead);
+            mlast = td.x;
+        }
         if (!L.run) continue;
         V4<T> own;
-        tile_edges<T, TILE, true>(I, S, td.y, L.cur, L.t, L.dt, L.t + L.dt, own);
+        tile_edges<T, TILE, true, 0, false, DRAIN_NONE, IW>(I, S, td.y, L.cur, L.t, L.dt, L.t + L.dt, own);
         Tally<0> tl;
         CandT<T> cand = tile_update<T, TILE>(I, S, td.y, L.cur, L.dt, own, tl);
         group_tally(I.clip_acc, td.y * TILE + threadIdx.x, tl.clip);
@@ -1744,8 +1772,8 @@ __device__ __forceinline__ double2 block_csum(double2 v) {
 template <typename T>
 __global__ void __launch_bounds__(MASS_THREADS) k_mass_partial(Inst<T> I, double2 *partials, int phase) {
     const int cur = I.ctrl->s[phase].cur;
-    const V4<T> *src = cur ? I.U1 : I.U0;
-    const T *lsrc = cur ? I.L1 : I.L0;
+    const gptr<const V4<T>> src = cur ? I.U1 : I.U0;
+    const gptr<const T> lsrc = cur ? I.L1 : I.L0;
     double s = 0.0, c = 0.0;
     for (int i = blockIdx.x * MASS_THREADS + threadIdx.x; i < I.n; i += MASS_BLOCKS * MASS_THREADS) {
         const V4<T> u = src[i];
@@ -1766,7 +1794,7 @@ __global__ void __launch_bounds__(MASS_THREADS) k_pair_sum(const double *acc, in
 // Sediment volume (1 - p) z |cell| in the same fixed order as the water volume.
 template <typename T>
 __global__ void __launch_bounds__(MASS_THREADS) k_bed_partial(Inst<T> I, double2 *partials, int phase) {
-    const V4<T> *src = I.ctrl->s[phase].cur ? I.U1 : I.U0;
+    const gptr<const V4<T>> src = I.ctrl->s[phase].cur ? I.U1 : I.U0;
     double s = 0.0, c = 0.0;
     for (int i = blockIdx.x * MASS_THREADS + threadIdx.x; i < I.n; i += MASS_BLOCKS * MASS_THREADS)
         neumaier(s, c, (1.0 - I.spor) * double(src[i].w) * I.area[i]);
@@ -1778,7 +1806,7 @@ __global__ void __launch_bounds__(MASS_THREADS) k_bed_partial(Inst<T> I, double2
 template <typename T>
 __global__ void __launch_bounds__(MASS_THREADS) k_species_mass_partial(Inst<T> I, int sp, double2 *partials,
                                                                         int phase) {
-    const T *q = (I.ctrl->s[phase].cur ? I.Q1 : I.Q0) + (size_t)sp * I.n;
+    const gptr<const T> q = (I.ctrl->s[phase].cur ? I.Q1 : I.Q0) + (size_t)sp * I.n;
     double s = 0.0, c = 0.0;
     for (int i = blockIdx.x * MASS_THREADS + threadIdx.x; i < I.n; i += MASS_BLOCKS * MASS_THREADS)
         neumaier(s, c, double(q[i]) * I.area[i]);
@@ -1939,28 +1967,42 @@ hipError_t launch_pair_sum(const double *acc, int n, double *out, hipStream_t s)
     return hipGetLastError();
 }
 
+template <typename T, bool IW>
+hipError_t batched_occupancy(int *per, int tile) {
+    switch (tile) {
+        case 128: return hipOccupancyMaxActiveBlocksPerMultiprocessor(per, (const void *)k_step_batched<T, 128, IW>, 128, 0);
+        case 256: return hipOccupancyMaxActiveBlocksPerMultiprocessor(per, (const void *)k_step_batched<T, 256, IW>, 256, 0);
+        case 512: return hipOccupancyMaxActiveBlocksPerMultiprocessor(per, (const void *)k_step_batched<T, 512, IW>, 512, 0);
+        default: return hipErrorInvalidValue;
+    }
+}
+
 template <typename T>
-int batched_grid(int tile) {
+int batched_grid(int tile, bool iw) {
     int dev = 0, cus = 0, per = 0;
     if (hipGetDevice(&dev) != hipSuccess) return 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
-    hipError_t e;
-    switch (tile) {
-        case 128: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, (const void *)k_step_batched<T, 128>, 128, 0); break;
-        case 256: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, (const void *)k_step_batched<T, 256>, 256, 0); break;
-        case 512: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, (const void *)k_step_batched<T, 512>, 512, 0); break;
-        default: return 0;
-    }
+    const hipError_t e = iw ? batched_occupancy<T, true>(&per, tile) : batched_occupancy<T, false>(&per, tile);
+    if (e == hipErrorInvalidValue) return 0;
     if (e != hipSuccess || per < 1) per = 1;
     return cus * per;
 }
 
 template <typename T>
-hipError_t launch_step_batched(const Inst<T> *insts, const int2 *tiles, int ntiles, int grid, int tile, int phase,
-                               hipStream_t s) {
+hipError_t launch_step_batched(const Inst<T> *insts, const int2 *tiles, int ntiles, int grid, int tile, bool iw,
+                               int phase, hipStream_t s) {
     if (ntiles <= 0) return hipSuccess;
     if (grid > ntiles) grid = ntiles;
-    SWE_TILE_DISPATCH(tile, k_step_batched, dim3(grid), dim3(tile), 0, s, insts, tiles, ntiles, phase)
+    const dim3 g(grid), b(tile);
+    switch (tile * 2 + (iw ? 1 : 0)) {
+        case 256: hipLaunchKernelGGL((k_step_batched<T, 128, false>), g, b, 0, s, insts, tiles, ntiles, phase); break;
+        case 257: hipLaunchKernelGGL((k_step_batched<T, 128, true>), g, b, 0, s, insts, tiles, ntiles, phase); break;
+        case 512: hipLaunchKernelGGL((k_step_batched<T, 256, false>), g, b, 0, s, insts, tiles, ntiles, phase); break;
+        case 513: hipLaunchKernelGGL((k_step_batched<T, 256, true>), g, b, 0, s, insts, tiles, ntiles, phase); break;
+        case 1024: hipLaunchKernelGGL((k_step_batched<T, 512, false>), g, b, 0, s, insts, tiles, ntiles, phase); break;
+        case 1025: hipLaunchKernelGGL((k_step_batched<T, 512, true>), g, b, 0, s, insts, tiles, ntiles, phase); break;
+        default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 
@@ -1996,8 +2038,8 @@ hipError_t noalloc_scratch(void **out) {
     template hipError_t launch_mass<T>(const Inst<T> &, double2 *, double *, int, int, hipStream_t);        \
     template hipError_t launch_species_mass<T>(const Inst<T> &, int, double2 *, double *, int, int, hipStream_t); \
     template hipError_t launch_bed_volume<T>(const Inst<T> &, double2 *, double *, int, hipStream_t);        \
-    template hipError_t launch_step_batched<T>(const Inst<T> *, const int2 *, int, int, int, int, hipStream_t); \
-    template int batched_grid<T>(int);
+    template hipError_t launch_step_batched<T>(const Inst<T> *, const int2 *, int, int, int, bool, int, hipStream_t); \
+    template int batched_grid<T>(int, bool);
 SWE_INSTANTIATE(float)
 SWE_INSTANTIATE(double)
 

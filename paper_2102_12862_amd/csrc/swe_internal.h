@@ -23,6 +23,19 @@ namespace swe {
 // A block owns one tile: it stages the tile's states in LDS, evaluates each of
 // the tile's edges once, then updates its cells.
 constexpr int NBR_FLIP = 1 << 30;
+
+// The arrays the kernels touch on their hot paths are typed as global memory
+// in the device pass (the host pass sees plain pointers of the same size).
+// A parameter block that a kernel reads out of memory -- a batched member's
+// -- otherwise leaves the compiler generic pointers, and the flat accesses it
+// then emits wait on the LDS counter as well, so every LDS wait of the edge
+// loop would also wait for the prefetched edge record.
+#if defined(__HIP_DEVICE_COMPILE__)
+template <typename X> using gptr = __attribute__((address_space(1))) X *;
+#else
+template <typename X> using gptr = X *;
+#endif
+template <typename X> __host__ __device__ inline gptr<X> dev_ptr(X *p) { return (gptr<X>)p; }
 constexpr int NBR_MASK = NBR_FLIP - 1;
 
 template <typename T> struct V4T;
@@ -107,24 +120,24 @@ constexpr unsigned long long INF_BITS = 0x7FF0000000000000ull;
 
 // Everything one kernel needs about one state.
 template <typename T> struct Inst {
-    V4<T> *U0;
-    V4<T> *U1;
+    gptr<V4<T>> U0;
+    gptr<V4<T>> U1;
     // FP32: the low part of each cell's surface, ping-pong with U0/U1 (the
     // surface is hi + lo); unused in FP64
-    T *L0;
-    T *L1;
-    const V2<T> *cellp;    // (|cell| in FP64, 1/|cell| in FP32; friction coefficient)
-    const Edge<T> *edges;  // tile edge lists
-    const int *ew1;        // per edge: other cell's device id or boundary slot
-    const int *eoff;       // first edge of each tile (ntiles + 1)
-    const int *slot_kbc;   // per boundary slot: kind | (bc index << 4)
-    double *slot_acc;      // per boundary slot: Neumaier (sum, compensation)
+    gptr<T> L0;
+    gptr<T> L1;
+    gptr<const V2<T>> cellp;    // (|cell| in FP64, 1/|cell| in FP32; friction coefficient)
+    gptr<const Edge<T>> edges;  // tile edge lists
+    gptr<const int> ew1;        // per edge: other cell's device id or boundary slot
+    gptr<const int> eoff;       // first edge of each tile (ntiles + 1)
+    gptr<const int> slot_kbc;   // per boundary slot: kind | (bc index << 4)
+    gptr<double> slot_acc;      // per boundary slot: Neumaier (sum, compensation)
     const BCdev *bcs;
-    const double *area;    // |cell| in FP64, for the mass sum
+    gptr<const double> area;    // |cell| in FP64, for the mass sum
     Ctrl *ctrl;
     // per group of 64 consecutive device cells a compensated accumulator
     // (sum, compensation) of the volume the positivity clip added
-    double *clip_acc;
+    gptr<double> clip_acc;
     int ngroups;           // ceil(n / 64)
     int n;
     int ntiles;            // tiles of this state's mesh
@@ -136,8 +149,8 @@ template <typename T> struct Inst {
     // buffer (ping-pong with U), inflow concentrations [bc][ns], per boundary
     // slot and species a Neumaier accumulator, per species and cell group
     // (as clip_acc) the dry-reset tally
-    T *Q0;
-    T *Q1;
+    gptr<T> Q0;
+    gptr<T> Q1;
     const T *phi_in;
     double *sslot_acc;
     double *sclip_acc;
@@ -146,8 +159,8 @@ template <typename T> struct Inst {
     // cell the auxiliary variables (psi_x, psi_y) [ns][n] pairs, ping-pong
     // with U; per species the molecular diffusivity, their maximum, the
     // dispersion coefficients and the relaxation time
-    T *P0;
-    T *P1;
+    gptr<T> P0;
+    gptr<T> P1;
     int diff;
     double dKm[5];
     double dKmax, daL, daT, dzeta;
@@ -156,7 +169,7 @@ template <typename T> struct Inst {
     // the series value to m/s), per tile a Neumaier accumulator of the volume
     // they added
     int nsrc;
-    const int *src_cell;
+    gptr<const int> src_cell;
     const BCdev *srcs;
     double *src_acc;
     // morphodynamics (morpho = 0: off): closure, its alpha / exponent /
@@ -167,13 +180,13 @@ template <typename T> struct Inst {
     int morpho;
     int sclos;
     double salpha, sm, sthr, srgd, sK, spor;
-    const T *zfix;
+    gptr<const T> zfix;
     double *bslot_acc;
     double *bclip_acc;
     // draining-time limiter (drain = 0: the bare clip): per cell the factor
     // min(1, draining time / dt) of the step being taken
     int drain;
-    T *theta;
+    gptr<T> theta;
     // internal conditions: per interior-tag index the boundary condition (a
     // wall or a dynamic wall) or -1
     const int *iw_bc;
@@ -199,11 +212,12 @@ hipError_t launch_bed_volume(const Inst<T> &I, double2 *partials, double *out, i
 template <typename T>
 hipError_t launch_species_mass(const Inst<T> &I, int sp, double2 *partials, double *out, int nslots, int phase,
                                hipStream_t s);
+// iw: some member has internal walls
 template <typename T>
-hipError_t launch_step_batched(const Inst<T> *insts, const int2 *tiles, int ntiles, int grid, int tile, int phase,
-                               hipStream_t s);
+hipError_t launch_step_batched(const Inst<T> *insts, const int2 *tiles, int ntiles, int grid, int tile, bool iw,
+                               int phase, hipStream_t s);
 template <typename T>
-int batched_grid(int tile);
+int batched_grid(int tile, bool iw);
 
 // Allocation-free batched step: its work list lives in a file-scope device
 // array (kernels.hip) of a fixed size, one per device: the kernel parameter

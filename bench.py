@@ -47,13 +47,16 @@ ALGO_BYTES = {"fp32": 72.0, "fp64": 132.0}
 # each passive species adds its specific mass in and out
 SPECIES_BYTES = {"fp32": 8.0, "fp64": 16.0}
 VALLEY_T_END = 3600.0
+AUTOTUNE_STEPS = 20  # steps per tile size and round of the autotuner
 
 
 # HBM traffic of the step kernel, measured with the FETCH_SIZE and WRITE_SIZE
 # counters (each scaled by what it reads for a plain copy of known size); it
 # is reported only while the kernel sources still hash to the digest recorded
 # with the measurement
-def traffic_profile(precision, species, morpho=False):
+def traffic_profile(precision, species, morpho=False, batched=False):
+    if batched:
+        return os.path.join(ROOT, "profiles", f"k_step_batched_{precision}_ensemble64_hbm_traffic.md")
     kern = "k_step_morpho" if morpho else f"k_step_species{species}" if species else "k_step"
     return os.path.join(ROOT, "profiles", f"{kern}_{precision}_valley4m_hbm_traffic.md")
 
@@ -75,11 +78,11 @@ def kernel_digest():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(workload, precision, tile, species=0, morpho=False):
+def measured_traffic(workload, precision, tile, species=0, morpho=False, batched=False):
     """Bytes per step-kernel launch from the committed counter profile, or
     None when it was taken on other kernel sources or another configuration."""
     try:
-        with open(traffic_profile(precision, species, morpho)) as fh:
+        with open(traffic_profile(precision, species, morpho, batched)) as fh:
             kv = dict(line.strip()[2:].split(": ", 1) for line in fh if line.startswith("- ") and ": " in line)
     except OSError:
         return None
@@ -190,7 +193,7 @@ def time_gpu(sc, precision, steps, warmup, autotune=True, species=0, tile=0, mor
     """Time per step over `steps` graph-launched steps (timed_steps)."""
     from gpu_util import device
     mesh, st = state if state is not None else gpu_state(sc, precision, tile, species, morpho)
-    tune = st.autotune(k=5) if (autotune and not tile and not (species or morpho)) else None
+    tune = st.autotune(k=AUTOTUNE_STEPS) if (autotune and not tile and not (species or morpho)) else None
     r = timed_steps(st, device(), steps, warmup)
     st.close()
     mesh.close()
@@ -275,12 +278,13 @@ def valley_to_t_end(sc, precision, steps, warmup, tile=0):
     run_wall = time.perf_counter() - t0
     m1 = st.mass()
     got = st.read()
-    tune = st.autotune(k=5) if not tile else None
+    q = sc.bcs[0]
+    delivered = -st.boundary_flux(q.tag)  # volume that entered through the inflow edges
+    tune = st.autotune(k=AUTOTUNE_STEPS) if not tile else None
     # every later step is capped at t_end: step on past it for the timing
     r = timed_steps_after(st, device(), steps, warmup)
     st.close()
     mesh.close()
-    q = sc.bcs[0]
     inflow = float(sum(0.5 * (q.Q[i] + q.Q[i + 1]) * (q.t[i + 1] - q.t[i]) for i in range(len(q.t) - 1))) \
         if VALLEY_T_END >= q.t[-1] else None
     wet = float((got["h"] > sc.h_min).mean())
@@ -288,8 +292,8 @@ def valley_to_t_end(sc, precision, steps, warmup, tile=0):
     r.update(tile=tune or tile or 256, rate=sc.n_cells * steps / (r["ms"] * 1e-3), run_steps=int(n),
              run_wall_s=run_wall, run_mean_us_per_step=1e6 * run_wall / max(n, 1), t=got["t"],
              wet_fraction=wet, volume=m1["mass"], clipped=m1["clipped"], balance_residual_rel=resid,
-             bnd_flux=m1["bnd_flux"], inflow_volume_hydrograph=inflow,
-             delivered_over_hydrograph=(-m1["bnd_flux"] / inflow) if inflow else None)
+             bnd_flux=m1["bnd_flux"], inflow_volume_hydrograph=inflow, inflow_volume_delivered=delivered,
+             delivered_over_hydrograph=(delivered / inflow) if inflow else None)
     return r
 
 
@@ -322,7 +326,7 @@ def bench_batched(n_members=64, rounds=8, k=16):
     batch = swe.Batch(precision=swe.FP32, device=dev)
     for st in states:
         batch.add(st, 1e9)
-    tile = batch.autotune(4)
+    tile = batch.autotune(8)
     batch.step(k)  # warm-up (capture)
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(rounds + 1)]
     torch.cuda.synchronize()
@@ -341,6 +345,7 @@ def bench_batched(n_members=64, rounds=8, k=16):
     sim = oracle.Sim(members[small], omp=True)
     sim.run_until(got["t"])
     errs, _ = errors(got, sim)
+    log(f"[bench] batched: {1e3 * ms_b / steps:.1f} us per step of all members; members one after another")
     # one after another
     states = [swe.State(me, m, precision=swe.FP32, steps_per_graph=k) for me, m in zip(meshes, members)]
     for st in states:
@@ -365,7 +370,8 @@ def bench_batched(n_members=64, rounds=8, k=16):
             "sequential_cell_updates_per_s": total * steps / (ms_s * 1e-3), "speedup": ms_s / ms_b,
             "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                          "frac": achieved / HBM_PEAK_GBS, "algorithmic_bytes_per_cell": ALGO_BYTES["fp32"],
-                         "kernel": f"k_step_batched<float, {tile}>"},
+                         "traffic": measured_traffic(f"batched_ensemble_{n_members}", "fp32", tile, batched=True),
+                         "kernel": f"k_step_batched<float, {tile}, false>"},
             "errors_vs_oracle": {"member_cells": members[small].n_cells, "t": got["t"],
                                  **{kk: float(v) for kk, v in errs.items()}}}
 
@@ -454,6 +460,8 @@ def main():
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--only", default="", help="comma-separated variants to run (default: all)")
     ap.add_argument("--serving-requests", type=int, default=48, help="requests per arrival rate")
+    ap.add_argument("--batched-rounds", type=int, default=8,
+                    help="timed rounds of 16 steps of the batched ensemble (and of its one-after-another baseline)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="also run a plain device copy of this many MiB (counter calibration)")
     ap.add_argument("--tile", type=int, default=0, choices=(0, 128, 256, 512),
@@ -545,7 +553,7 @@ def main():
         for p in ("fp32", "fp64"):
             mesh, st = gpu_state(lake, p)
             H0 = st.read()["H"]
-            tl = st.autotune(k=5)
+            tl = st.autotune(k=AUTOTUNE_STEPS)
             lr = timed_steps(st, _dev(), 500, 50)
             got = st.read()
             rest = {"steps": int(st.mass()["steps"]),
@@ -582,7 +590,7 @@ def main():
                 log(f"[bench] {ns} species: {variants[f'{wet.name}_{args.precision}_species{ns}']}")
     if want("batched"):
         log("[bench] batched ensemble")
-        variants["batched_ensemble_fp32"] = bench_batched()
+        variants["batched_ensemble_fp32"] = bench_batched(rounds=args.batched_rounds)
         log(f"[bench] batched: {variants['batched_ensemble_fp32']}")
     if want("serving"):
         log("[bench] serving traces")

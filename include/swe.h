@@ -192,7 +192,11 @@ void swe_state_destroy(swe_state *s);
 /* One step of eq. hydrodynamicupdateformula with dt = min(dt_max,
  * CFL * min rho/lambda) (no end-time cap).  Blocks until done; *dt_taken may
  * be NULL.  Returns SWE_ENODT when no finite step exists, SWE_ENONFINITE /
- * SWE_ENEGDEPTH when the state broke (the state is then left as computed). */
+ * SWE_ENEGDEPTH when the state broke.  A step that raises such an error is
+ * not completed consistently: the tiles that ran before the flag was raised
+ * wrote the new level, the later ones skip theirs, so the state read
+ * afterwards mixes two time levels and only tells where the failure began;
+ * a run continues from a state saved before the failing step. */
 swe_status swe_step(swe_state *s, double *dt_taken);
 
 /* Steps until t = t_end (the last step is shortened to land on t_end), with
@@ -254,8 +258,9 @@ swe_status swe_state_read_scalars(const swe_state *s, double *q);
 /* Per species (arrays of ns doubles, any may be NULL): mass sum q |Omega|
  * (compensated FP64, fixed order), the time integral of the species flux
  * leaving through open boundaries, and the mass added by resetting cells
- * left dry: mass(t) = mass(0) - bnd_flux + clipped.  The reset tally is summed
- * with device atomics: its last bits depend on the order of the cells. */
+ * left dry: mass(t) = mass(0) - bnd_flux + clipped.  Like the water's clip
+ * volume, the reset tally is kept per group of 64 cells in compensated FP64
+ * and summed in a fixed order, so it is bitwise reproducible. */
 swe_status swe_scalar_mass(const swe_state *s, double *mass, double *bnd_flux, double *clipped);
 
 /* ---- diffusion of the species (section "Scalar advection-diffusion": the
@@ -360,11 +365,13 @@ swe_status swe_state_read_bed(const swe_state *s, double *z);
 /* Sediment volume (1 - p) sum z |Omega| (compensated FP64, fixed order),
  * the volume that left through open boundaries, and the volume the fixed-bed
  * clip added since the module was switched on: volume(t) = volume(0) -
- * bnd + clipped.  The clip tally is summed with device atomics. */
+ * bnd + clipped.  The clip tally is kept per group of 64 cells in
+ * compensated FP64 and summed in a fixed order (bitwise reproducible). */
 swe_status swe_morpho_volume(const swe_state *s, double *volume, double *bnd, double *clipped);
 
-/* Times k steps for each tile size (block size) in {128, 256, 512}, keeps
- * the fastest for this state, and restores the state exactly as it was.
+/* Times k steps for each tile size (block size) in {128, 256, 512}, in
+ * three interleaved rounds, keeps the size with the fastest round for this
+ * state, and restores the state exactly as it was.
  * *block_size (may be NULL) receives the choice.  Results are bitwise
  * independent of the choice.  States with species, sources or a moving bed
  * keep their tile.  Allocates a copy of the state for the duration. */
@@ -395,7 +402,8 @@ swe_status swe_batch_step(swe_batch *b, int32_t k, int32_t *n_active);
 swe_status swe_batch_launch(swe_batch *b, int32_t k);
 /* The autotuner of the persistent batched step: times k launches over the
  * running members for each tile size in {128, 256, 512} (the persistent grid
- * follows the occupancy of each), keeps the fastest, and restores every
+ * follows the occupancy of each) in three interleaved rounds, keeps the size
+ * with the fastest round, and restores every
  * member exactly as it was (state, boundary tallies, time level).
  * *block_size (may be NULL) receives the choice.  Results are bitwise
  * independent of the choice.  Allocates a copy of every running member for

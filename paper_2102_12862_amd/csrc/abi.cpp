@@ -75,6 +75,7 @@ struct TileGeom {
     }
 };
 constexpr int TILES[3] = {128, 256, 512};
+constexpr int AUTOTUNE_ROUNDS = 3;  // interleaved timing rounds per tile size
 int tile_index(int tile) { return tile == 128 ? 0 : tile == 256 ? 1 : tile == 512 ? 2 : -1; }
 
 size_t vec4_bytes(int prec) { return prec == SWE_FP32 ? sizeof(float4) : sizeof(double4); }
@@ -1368,9 +1369,14 @@ swe_status swe_autotune(swe_state *s, int32_t k, int32_t *block_size) {
         HIP_TRY(hipMemcpyAsync(keepC, s->clip_acc, cb, hipMemcpyDeviceToDevice, q));
         HIP_TRY(hipEventCreate(&e0));
         HIP_TRY(hipEventCreate(&e1));
-        float best = std::numeric_limits<float>::infinity();
-        int bb = s->tile;
-        for (int b : TILES) {
+        // each tile size timed in AUTOTUNE_ROUNDS interleaved rounds (so a
+        // drift of the clock or of the other work on the device hits every
+        // size alike); a size's figure is its fastest round
+        float tbest[3] = {std::numeric_limits<float>::infinity(), std::numeric_limits<float>::infinity(),
+                          std::numeric_limits<float>::infinity()};
+        for (int round = 0; round < AUTOTUNE_ROUNDS; round++)
+            for (int ti = 0; ti < 3; ti++) {
+                const int b = TILES[ti];
                 swe_status r = restore();
                 if (r) return r;
                 r = s->set_tile(b);
@@ -1386,11 +1392,15 @@ swe_status swe_autotune(swe_state *s, int32_t k, int32_t *block_size) {
                 HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
                 r = s->read_ctrl();
                 if (r) return r;
-                if (s->hctrl->flags == 0 && ms < best) {
-                    best = ms;
-                    bb = b;
-                }
-        }
+                if (s->hctrl->flags == 0 && ms < tbest[ti]) tbest[ti] = ms;
+            }
+        float best = std::numeric_limits<float>::infinity();
+        int bb = s->tile;
+        for (int ti = 0; ti < 3; ti++)
+            if (tbest[ti] < best) {
+                best = tbest[ti];
+                bb = TILES[ti];
+            }
         swe_status r = s->set_tile(bb);
         if (r) return r;
         return restore();
@@ -1805,9 +1815,11 @@ swe_status swe_batch_autotune(swe_batch *b, int32_t k, int32_t *block_size) {
     swe_status st = [&]() -> swe_status {
         HIP_TRY(hipEventCreate(&e0));
         HIP_TRY(hipEventCreate(&e1));
-        float best = std::numeric_limits<float>::infinity();
-        int bt = tile0;
-        for (int t : TILES) {
+        float tbest[3] = {std::numeric_limits<float>::infinity(), std::numeric_limits<float>::infinity(),
+                          std::numeric_limits<float>::infinity()};
+        for (int round = 0; round < AUTOTUNE_ROUNDS; round++)
+        for (int ti = 0; ti < 3; ti++) {
+            const int t = TILES[ti];
             swe_status r = restore();
             if (r) return r;
             b->tile = t;
@@ -1831,11 +1843,15 @@ swe_status swe_batch_autotune(swe_batch *b, int32_t k, int32_t *block_size) {
                 if (r) return r;
                 ok = ok && x.s->hctrl->flags == 0;
             }
-            if (ok && ms < best) {
-                best = ms;
-                bt = t;
-            }
+            if (ok && ms < tbest[ti]) tbest[ti] = ms;
         }
+        float best = std::numeric_limits<float>::infinity();
+        int bt = tile0;
+        for (int ti = 0; ti < 3; ti++)
+            if (tbest[ti] < best) {
+                best = tbest[ti];
+                bt = TILES[ti];
+            }
         swe_status r = restore();
         if (r) return r;
         b->tile = bt;

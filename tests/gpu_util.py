@@ -87,22 +87,23 @@ def compare(state, sim, tol, metric="max", max_bound=None):
     """FP64 (metric "max"): every field within tol in the max norm.
 
     FP32 trajectories (metric "l1"): the area-weighted L1 errors of h, qx
-    and qy within tol, and the max errors within max_bound, a bound set per
-    workload from measured values.  The max norm of a trajectory cannot be
-    held at tol: the HLLC wave speeds switch from the two-rarefaction
-    estimate to the dry-bed form when a reconstructed depth H - max(z_L, z_R)
-    reaches zero, and an edge whose reconstructed depth lies within the FP32
-    rounding of H and z (about 1e-6 m) takes the other branch than the FP64
-    oracle; that edge's flux then differs by O(h c) for a step, and the
-    difference spreads and decays over the following steps.  The arithmetic
-    of a step itself is held to tol in the max norm by local_step_errors."""
+    and qy within tol, and the max errors within max_bound, which is tol
+    itself unless a test gives a bound measured on its own workload.  Only
+    the 4M-cell comparison does: there, among millions of edges, a few have a
+    reconstructed depth H - max(z_L, z_R) within the FP32 rounding of H and z
+    (about 1e-6 m) of zero, where the HLLC wave speeds switch from the two-
+    rarefaction estimate to the dry-bed form; such an edge takes the other
+    branch than the FP64 oracle, its flux differs by O(h c) for a step, and
+    the difference spreads and decays over the following steps.  The
+    arithmetic of a step itself is held to tol in the max norm there by
+    local_step_errors."""
     got = state.read()
     errs, t = errors(got, sim)
     if metric == "max":
         bad = {k: v for k, v in errs.items() if k.startswith("max_") and not v <= tol}
     else:
         if max_bound is None:
-            max_bound = 500 * tol
+            max_bound = tol
         bad = {k: v for k, v in errs.items() if (k.startswith("l1_") and not v <= tol)
                or (k.startswith("max_") and k != "max_H" and not v <= max_bound)}
     _log_errors(metric, errs)

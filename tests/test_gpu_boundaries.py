@@ -1,7 +1,7 @@
 """Standard inflow and outflow conditions on the GPU (section "Hydrodynamic
 BCs" and the supplementary feature table: froude inflow, uniform, weir, h-Q
 and dynamic-wall outflows): parity with the FP64 oracle (FP64 within 1e-10 of
-the norm, FP32 within 1e-4 in the L1 norm on a fixed step) on the oracle's
+the norm, FP32 within 1e-4 in the max and L1 norms on a fixed step) on the oracle's
 closed-form cases and on wet/dry flows with species, plus argument checks."""
 import numpy as np
 import pytest

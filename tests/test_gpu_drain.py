@@ -1,6 +1,6 @@
 """The draining-time positivity limiter on the GPU (every flux leaving a cell
 acts only for that cell's draining time): parity with the FP64 oracle (FP64
-within 1e-10 of the norm, FP32 within 1e-4 in the L1 norm on a fixed step)
+within 1e-10 of the norm, FP32 within 1e-4 in the max and L1 norms on a fixed step)
 on wet/dry flows at every tile size and with external sinks; depths stay
 non-negative without clipping; a wet flow is bitwise the unlimited one; a
 column on a dry bed keeps its volume; the combinations it refuses."""

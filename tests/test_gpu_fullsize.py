@@ -10,6 +10,8 @@ from gpu_util import cached, compare, gpu_state
 
 pytestmark = pytest.mark.gpu
 
+FULLSIZE_MAX_BOUND = 2e-2
+
 
 @pytest.fixture(scope="module")
 def valley_wet():
@@ -34,7 +36,10 @@ def test_fullsize_fp32_three_steps(valley_wet, valley_oracle):
     for _ in range(3):
         st.step()
         sim.step()
-    errs = compare(st, sim, 1e-4, metric="l1")
+    # L1 within 1e-4; the max error, set by the few edges whose reconstructed
+    # depth sits within FP32 rounding of zero (see compare), was 8.9e-3
+    # (qy) when measured
+    errs = compare(st, sim, 1e-4, metric="l1", max_bound=FULLSIZE_MAX_BOUND)
     print("fp32 full size", errs)
 
 

@@ -1,6 +1,6 @@
 """Internal static and dynamic walls on the GPU (section "Hydrodynamic BCs",
 internal BCs on tagged interior edges): parity with the FP64 oracle (FP64
-within 1e-10 of the norm, FP32 within 1e-4 in the L1 norm on a fixed step)
+within 1e-10 of the norm, FP32 within 1e-4 in the max and L1 norms on a fixed step)
 at every tile size, through a dynamic wall's collapse, with species, the
 Exner module, the draining-time limiter and in a batch; the tile edge lists
 stay consistent; other kinds on interior edges are refused."""

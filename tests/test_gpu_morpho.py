@@ -2,7 +2,7 @@
 exnerupdateformula, the HLL sediment flux eq. exner_hll with the speeds of
 eq. exner_wave_assign / eq. exner_wave_estimation, Table
 sedtransport_closure): parity of the bed and the water with the FP64 oracle
-(FP64 within 1e-10 of the norm; FP32 within 1e-4 in the L1 norm on a fixed
+(FP64 within 1e-10 of the norm; FP32 within 1e-4 in the max and L1 norms on a fixed
 step) on a closed basin, an open channel with a non-erodible bed, wet/dry
 multi-tile meshes with each closure and friction law; sediment conservation;
 the lake at rest; the hump's migration at the bed celerity; the API."""

@@ -302,13 +302,15 @@ def timed_steps_after(st, dev, steps, warmup):
     return timed_steps(st, dev, steps, warmup)
 
 
-def bench_batched(n_members=64, rounds=8, k=16):
+def bench_batched(n_members=64, rounds=8, k=16, t_end=1800.0):
     """Batched ensemble: members of the lake generator (jittered-lattice mesh
     for generation speed) with log-uniform sizes, each fed by its own
     hydrograph, stepped together by one persistent kernel per step (tile
     chosen by the batched autotuner); against the same members stepped one
     after another through the single-solve API for the same number of steps.
-    Errors of the smallest member against the oracle after those steps."""
+    Then the whole ensemble run on to its horizon t_end (members finish at
+    their own step counts), with the errors of the smallest member against
+    the oracle at t_end."""
     import torch
     import oracle
     import swe_inputs as S
@@ -325,7 +327,7 @@ def bench_batched(n_members=64, rounds=8, k=16):
     states = [swe.State(me, m, precision=swe.FP32) for me, m in zip(meshes, members)]
     batch = swe.Batch(precision=swe.FP32, device=dev)
     for st in states:
-        batch.add(st, 1e9)
+        batch.add(st, t_end)
     tile = batch.autotune(8)
     batch.step(k)  # warm-up (capture)
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(rounds + 1)]
@@ -337,6 +339,13 @@ def bench_batched(n_members=64, rounds=8, k=16):
     torch.cuda.synchronize()
     ms_b = ev[0].elapsed_time(ev[rounds])
     chunk = [1e3 * ev[i].elapsed_time(ev[i + 1]) / k for i in range(rounds)]
+    # on to the horizon
+    t0 = time.perf_counter()
+    while batch.step(64):
+        pass
+    run_wall = time.perf_counter() - t0
+    member_steps = [int(st.mass()["steps"]) for st in states]
+    run_updates = sum(n * m.n_cells for n, m in zip(member_steps, members))
     small = int(np.argmin([m.n_cells for m in members]))
     got = states[small].read()
     batch.close()
@@ -372,6 +381,9 @@ def bench_batched(n_members=64, rounds=8, k=16):
                          "frac": achieved / HBM_PEAK_GBS, "algorithmic_bytes_per_cell": ALGO_BYTES["fp32"],
                          "traffic": measured_traffic(f"batched_ensemble_{n_members}", "fp32", tile, batched=True),
                          "kernel": f"k_step_batched<float, {tile}, false>"},
+            "run_to_horizon": {"t_end": t_end, "wall_s": run_wall, "member_steps_min": min(member_steps),
+                               "member_steps_max": max(member_steps), "cell_updates": run_updates,
+                               "cell_updates_per_s": run_updates / run_wall},
             "errors_vs_oracle": {"member_cells": members[small].n_cells, "t": got["t"],
                                  **{kk: float(v) for kk, v in errs.items()}}}
 
@@ -392,13 +404,14 @@ def parallel_generate(jobs, workers=8):
         return list(ex.map(_gen, jobs))
 
 
-def bench_serving(rates=(4.0, 16.0, 64.0), n_requests=48, n_pool=12):
+def bench_serving(rates=(4.0, 16.0, 64.0), n_requests=48, n_pool=12, long_trace=(64.0, 512)):
     """Served Poisson traces of valley-flood requests on a cached pool of
     prepared domains (each pool domain scaled so the cell size stays the
     valley's; a request takes the pool domain nearest its log-uniform size,
     with its own horizon), continuous batching with footprint admission;
     against the same trace served one request at a time, at each arrival
-    rate.  Errors of one served result against the oracle."""
+    rate; then one long trace (rate, requests) the same way.  Errors of one
+    served result against the oracle."""
     import oracle
     import swe_inputs as S
     from gpu_util import device, errors
@@ -410,8 +423,9 @@ def bench_serving(rates=(4.0, 16.0, 64.0), n_requests=48, n_pool=12):
     out = {"pool_cells": [int(sc.n_cells) for sc in pool], "requests_per_rate": n_requests,
            "cells_range": [1e4, 2e6], "horizon_s": [60, 1800], "rates": {}}
     sample = None
-    for rate in rates:
-        arrive, want, horizon = S.serving_trace(n_requests=n_requests, rate=rate, n_lo=1e4, n_hi=2e6,
+    traces = [(rate, n_requests) for rate in rates] + ([tuple(long_trace)] if long_trace and long_trace[1] else [])
+    for rate, nreq in traces:
+        arrive, want, horizon = S.serving_trace(n_requests=nreq, rate=rate, n_lo=1e4, n_hi=2e6,
                                                 h_lo=60.0, h_hi=1800.0)
         pick = [int(np.argmin(np.abs(np.log(sizes) - np.log(n)))) for n in want]
 
@@ -434,9 +448,9 @@ def bench_serving(rates=(4.0, 16.0, 64.0), n_requests=48, n_pool=12):
         t0 = time.perf_counter()
         serve.serve_sequential(r2, precision=swe.FP32, device=dev)
         wall2 = time.perf_counter() - t0
-        out["rates"][f"{rate:g}"] = {"served": serve.summarize(r1, wall),
-                                     "one_at_a_time": serve.summarize(r2, wall2)}
-        log(f"[bench] serving at {rate:g}/s: {out['rates'][f'{rate:g}']}")
+        key = f"{rate:g}" if nreq == n_requests else f"{rate:g}x{nreq}"
+        out["rates"][key] = {"served": serve.summarize(r1, wall), "one_at_a_time": serve.summarize(r2, wall2)}
+        log(f"[bench] serving {nreq} requests at {rate:g}/s: {out['rates'][key]}")
     for me in meshes:
         me.close()
     r, sc = sample
@@ -460,6 +474,8 @@ def main():
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--only", default="", help="comma-separated variants to run (default: all)")
     ap.add_argument("--serving-requests", type=int, default=48, help="requests per arrival rate")
+    ap.add_argument("--serving-long", type=int, default=512,
+                    help="requests of the long served trace at 64 per second (0: none)")
     ap.add_argument("--batched-rounds", type=int, default=8,
                     help="timed rounds of 16 steps of the batched ensemble (and of its one-after-another baseline)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
@@ -594,7 +610,8 @@ def main():
         log(f"[bench] batched: {variants['batched_ensemble_fp32']}")
     if want("serving"):
         log("[bench] serving traces")
-        variants["served_traces_fp32"] = bench_serving(n_requests=args.serving_requests)
+        variants["served_traces_fp32"] = bench_serving(n_requests=args.serving_requests,
+                                                       long_trace=(64.0, args.serving_long))
     errs = None
     if want("errors") and args.workload == "valley_wet":
         errs = error_sample(wet, args.precision, 20, om_omp, tile=tile, species=args.species, morpho=args.morpho)

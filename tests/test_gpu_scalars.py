@@ -114,9 +114,11 @@ def test_t5_contact_is_kept(swe, prec):
     else:
         # FP32: the two sides of the contact are mirror images only up to
         # rounding (the triangles are not), so the mass flux through the
-        # contact, zero in exact arithmetic, is a rounding residue there
+        # contact, zero in exact arithmetic, is a rounding residue there;
+        # measured 6.4e-5 next to the contact, 1.2e-6 beyond 0.25 m of it
         far = np.abs(cx - 50.0) > 0.25
-        assert err[far].max() <= 2e-5 and err.max() <= 1e-3, (err[far].max(), err.max())
+        _log_errors("t5_contact", {"max_far": float(err[far].max()), "max_all": float(err.max())})
+        assert err[far].max() <= 2e-5 and err.max() <= 1e-4, (err[far].max(), err.max())
     if prec == "fp64":
         sim = oracle.Sim(sc)
         sim.run_until(2.5)

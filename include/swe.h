@@ -87,6 +87,15 @@ typedef struct {
  *    Q(H) / (boundary length) leaves like over a weir.
  *  - DYNAMIC_WALL (slope = collapse time): a wall before it, zero gradient
  *    from then on.
+ * On tagged interior edges (internal conditions, section "Hydrodynamic
+ * BCs"): WALL makes each side a wall of its own state; DYNAMIC_WALL does so
+ * until its collapse time, after which the edge is an ordinary one; OUTFLOW_HQ
+ * is a rating curve: q = Q(H) / (the curve's length) at the surface H of the
+ * cell left of each segment (walking from its first node to its second)
+ * crosses to the cell on the right, leaving with the left cell's state,
+ * while the right cell's momentum sees a wall (one-way flow; species cross
+ * with the left cell's concentrations, sediment and diffusion do not cross;
+ * not with the draining-time limiter).
  * Uniform inflow and outflow need the Manning or Strickler closure and a
  * positive friction parameter in their cells.  Inflows carry their inflow
  * concentrations of passive species; outflows the interior's. */
@@ -150,8 +159,10 @@ void swe_params_default(swe_params *p);
 /* Builds a mesh from node coordinates and elevations (node_xyz: n_nodes x 3
  * doubles x, y, z, host) and triangles (tri: n_tri x 3 node ids, host, any
  * winding -- fixed to counter-clockwise).  bnd_seg (n_seg x 2 node ids) with
- * bnd_tag (n_seg ints) tags boundary edges; every segment must be a boundary
- * edge of the mesh.  The cell bed elevation is the mean of its three node
+ * bnd_tag (n_seg ints) tags edges: boundary edges, and interior edges that
+ * carry an internal condition (at most 31 such tags; the segment's node
+ * order gives its direction, see the boundary kinds); every segment must be
+ * an edge of the mesh.  The cell bed elevation is the mean of its three node
  * elevations.  Rejects non-finite coordinates, degenerate triangles, edges
  * shared by three or more triangles and inconsistently oriented neighbours
  * (SWE_EINVAL).  params may be NULL (defaults); only params->renumber is read.
@@ -294,7 +305,7 @@ swe_status swe_state_read_psi(const swe_state *s, double *psi);
 
 /* ---- external water sources and sinks S_h (the S_h paragraph of the
  * hydrodynamic closure relations; eq. swe_vectorial_form_sourceterms,
- * added explicitly to the continuity equation of eq.
+ * an explicit source in the continuity equation of eq.
  * hydrodynamicupdateformula: H += dt S_h after the fluxes, before the
  * friction split).  Each region has a series (linear in time, constant past
  * its ends, taken at the step's start time) of a total discharge [m^3/s]

@@ -37,6 +37,7 @@ struct om_mesh {
     int32_t *eL, *eR;    /* cells of edge e; eR = -1 on the boundary */
     int32_t *ekL, *ekR;  /* local edge index of e inside L and R */
     int32_t *etag;       /* boundary tag, -1 when untagged */
+    int8_t *eup;         /* tagged interior edge: 1 when L lies left of its segment (first node to second) */
     double *enx, *eny, *elen; /* unit normal pointing from L to R (outward of L), length */
     int32_t *cell_edge;  /* 3*nc: edge id of the cell's local edge k */
     double *rho;         /* 3*nc: twice the centroid-to-edge distance */
@@ -145,7 +146,7 @@ static int cmp_half(const void *p, const void *q) {
 }
 
 typedef struct {
-    int32_t a, b, tag;
+    int32_t a, b, tag, first;   /* first: the segment's first node as given */
 } seg_key;
 
 static int cmp_seg(const void *p, const void *q) {
@@ -158,7 +159,7 @@ static int cmp_seg(const void *p, const void *q) {
 void om_mesh_free(om_mesh *m) {
     if (!m) return;
     free(m->x); free(m->y); free(m->zn); free(m->tri); free(m->area); free(m->zb);
-    free(m->eL); free(m->eR); free(m->ekL); free(m->ekR); free(m->etag);
+    free(m->eL); free(m->eR); free(m->ekL); free(m->ekR); free(m->etag); free(m->eup);
     free(m->enx); free(m->eny); free(m->elen); free(m->cell_edge); free(m->rho);
     free(m);
 }
@@ -228,9 +229,10 @@ om_mesh *om_mesh_new(const double *xyz, int64_t nv, const int32_t *tri, int64_t 
     m->eL = malloc(sizeof(int32_t) * ne); m->eR = malloc(sizeof(int32_t) * ne);
     m->ekL = malloc(sizeof(int32_t) * ne); m->ekR = malloc(sizeof(int32_t) * ne);
     m->etag = malloc(sizeof(int32_t) * ne);
+    m->eup = malloc(sizeof(int8_t) * ne);
     m->enx = malloc(sizeof(double) * ne); m->eny = malloc(sizeof(double) * ne);
     m->elen = malloc(sizeof(double) * ne);
-    if (!m->eL || !m->eR || !m->ekL || !m->ekR || !m->etag || !m->enx || !m->eny || !m->elen) {
+    if (!m->eL || !m->eR || !m->ekL || !m->ekR || !m->etag || !m->eup || !m->enx || !m->eny || !m->elen) {
         seterr(err, elen, "out of memory"); goto fail;
     }
     sk = malloc(sizeof(seg_key) * (ns > 0 ? ns : 1));
@@ -238,7 +240,7 @@ om_mesh *om_mesh_new(const double *xyz, int64_t nv, const int32_t *tri, int64_t 
     for (int64_t s = 0; s < ns; s++) {
         int32_t p = seg[2 * s], q = seg[2 * s + 1];
         if (p < 0 || q < 0 || p >= nv || q >= nv || p == q) { seterr(err, elen, "bad boundary segment"); goto fail; }
-        sk[s].a = p < q ? p : q; sk[s].b = p < q ? q : p; sk[s].tag = tag[s];
+        sk[s].a = p < q ? p : q; sk[s].b = p < q ? q : p; sk[s].tag = tag[s]; sk[s].first = p;
     }
     qsort(sk, (size_t)ns, sizeof(seg_key), cmp_seg);
     int64_t matched = 0;
@@ -257,19 +259,22 @@ om_mesh *om_mesh_new(const double *xyz, int64_t nv, const int32_t *tri, int64_t 
         m->enx[e] = dy / l;   /* outward of a counter-clockwise cell */
         m->eny[e] = -dx / l;
         m->etag[e] = -1;
+        m->eup[e] = 0;
         if (g - h == 2) {
             int32_t R = he[h + 1].cell, kR = he[h + 1].k;
             int32_t pR = m->tri[3 * R + kR];
             if (pR != q) { seterr(err, elen, "inconsistent orientation (overlapping triangles)"); goto fail; }
             m->eR[e] = R; m->ekR[e] = kR;
             m->cell_edge[3 * R + kR] = (int32_t)e;
-            /* a tagged interior edge can carry an internal condition */
-            seg_key key = {he[h].a, he[h].b, 0};
+            /* a tagged interior edge can carry an internal condition; L,
+             * counter-clockwise, walks the edge from p to q, so it lies on
+             * the left of the segment when the segment starts at p */
+            seg_key key = {he[h].a, he[h].b, 0, 0};
             seg_key *f = ns > 0 ? bsearch(&key, sk, (size_t)ns, sizeof(seg_key), cmp_seg) : NULL;
-            if (f) { m->etag[e] = f->tag; matched++; }
+            if (f) { m->etag[e] = f->tag; m->eup[e] = (int8_t)(f->first == p); matched++; }
         } else {
             m->eR[e] = -1; m->ekR[e] = -1;
-            seg_key key = {he[h].a, he[h].b, 0};
+            seg_key key = {he[h].a, he[h].b, 0, 0};
             seg_key *f = ns > 0 ? bsearch(&key, sk, (size_t)ns, sizeof(seg_key), cmp_seg) : NULL;
             if (f) { m->etag[e] = f->tag; matched++; }
         }
@@ -412,11 +417,12 @@ om_sim *om_sim_new(const om_mesh *m, double g, double cfl, double h_min, double 
         if (m->etag[e] < 0) continue;
         if (m->eR[e] >= 0) {
             /* internal condition (section "Hydrodynamic BCs", internal BCs):
-             * a static wall, or a dynamic wall until its collapse time */
+             * a static wall, a dynamic wall until its collapse time, or a
+             * rating curve (h-Q relation) */
             for (int b = 0; b < nbc; b++) {
                 if (s->bc[b].tag != m->etag[e]) continue;
-                if (s->bc[b].kind != OM_WALL && s->bc[b].kind != OM_DYNAMIC_WALL) {
-                    seterr(err, elen, "interior edges take walls and dynamic walls only"); goto fail;
+                if (s->bc[b].kind != OM_WALL && s->bc[b].kind != OM_DYNAMIC_WALL && s->bc[b].kind != OM_OUTFLOW_HQ) {
+                    seterr(err, elen, "interior edges take walls, dynamic walls and h-Q relations only"); goto fail;
                 }
                 s->ebc[e] = b;
                 break;
@@ -471,7 +477,7 @@ static double hydrograph(const om_bc *B, double t) {
 /* ---------------------------------------------------------------------------
  * External water sources and sinks (section "Closure relationships" of the
  * hydrodynamics, the S_h paragraph; eq. swe_vectorial_form_sourceterms): a
- * rate S_h [m/s] added explicitly to the continuity equation of eq.
+ * rate S_h [m/s], an explicit source in the continuity equation of eq.
  * hydrodynamicupdateformula, H += dt S_h, before the friction split.
  * Region r holds a series (linear in time, constant past its ends, taken at
  * t^n) of a total discharge [m^3/s], spread evenly over the region's area,
@@ -746,6 +752,11 @@ int om_sim_set_drain(om_sim *s, int on, char *err, int elen) {
     free(s->theta); free(s->dout);
     s->theta = NULL; s->dout = NULL; s->drain = 0;
     if (!on) return 0;
+    for (int64_t e = 0; e < s->m->ne; e++)
+        if (s->m->eR[e] >= 0 && s->ebc[e] >= 0 && s->bc[s->ebc[e]].kind == OM_OUTFLOW_HQ) {
+            seterr(err, elen, "internal h-Q relations and the draining-time limiter do not combine");
+            return -1;
+        }
     size_t nc = (size_t)(s->m->nc > 0 ? s->m->nc : 1);
     s->theta = malloc(sizeof(double) * nc);
     s->dout = calloc(3 * nc, sizeof(double));
@@ -1234,7 +1245,12 @@ typedef struct {
 static int internal_wall(const om_sim *s, int64_t e) {
     if (s->m->eR[e] < 0 || s->ebc[e] < 0) return 0;
     const om_bc *B = &s->bc[s->ebc[e]];
-    return B->kind == OM_WALL || s->t < B->slope;
+    return B->kind == OM_WALL || (B->kind == OM_DYNAMIC_WALL && s->t < B->slope);
+}
+
+/* An interior edge that carries an internal rating curve. */
+static int internal_hq(const om_sim *s, int64_t e) {
+    return s->m->eR[e] >= 0 && s->ebc[e] >= 0 && s->bc[s->ebc[e]].kind == OM_OUTFLOW_HQ;
 }
 
 /* One side K of an internal wall, with K's outward normal (nx, ny): the
@@ -1257,6 +1273,46 @@ static void wall_side(om_sim *s, int32_t K, int kK, double nx, double ny, double
     if (s->diff)
         for (int c = 0; c < s->ns; c++) diffusion_mirror(s, c, K, kK, l, nx, ny);
     if (s->morpho) s->bcont[3 * K + kK] = 0.0;
+}
+
+/* An internal rating curve (section "Hydrodynamic BCs", internal BCs: a
+ * flow relation applies on one side, wall conditions on the other, the flow
+ * one way; readings): the table's discharge at the upstream cell's surface,
+ * q = Q(H_U) / (the curve's length), crosses the edge from the cell U on the
+ * left of the tag's segment to the other cell D.  U's side is the imposed
+ * outflow of its own state, F = (q, q^2/h + g h^2/2, q u_t); D's side is the
+ * wall flux of its own state with the mass flux -q; the species cross with
+ * U's concentrations; neither sediment nor diffusion crosses. */
+static void hq_edge(om_sim *s, int64_t e) {
+    const om_mesh *m = s->m;
+    const int up = m->eup[e];
+    const int32_t U = up ? m->eL[e] : m->eR[e], D = up ? m->eR[e] : m->eL[e];
+    const int kU = up ? m->ekL[e] : m->ekR[e], kD = up ? m->ekR[e] : m->ekL[e];
+    const double sg = up ? 1.0 : -1.0;   /* U's outward normal is sg n */
+    const double nx = sg * m->enx[e], ny = sg * m->eny[e], l = m->elen[e];
+    const double q = imposed_outflow(s, &s->bc[s->ebc[e]], s->H[U], s->z[U]);
+    double hU, uU, vU;
+    cell_velocity(s, U, &hU, &uU, &vU);
+    double utU = -uU * ny + vU * nx;
+    double hs = s->H[U] - s->z[U];
+    if (hs < OM_H_DRY) hs = 0.0;
+    double F1 = (hs > 0.0 ? q * (q / hs) : 0.0) + 0.5 * s->g * hs * hs;
+    double F2 = q * utU;
+    double dn = F1 - 0.5 * s->g * hs * hs;
+    s->cont[9 * U + 3 * kU + 0] = l * q;
+    s->cont[9 * U + 3 * kU + 1] = l * (dn * nx - F2 * ny);
+    s->cont[9 * U + 3 * kU + 2] = l * (dn * ny + F2 * nx);
+    wall_side(s, D, kD, -nx, -ny, l);
+    s->cont[9 * D + 3 * kD + 0] = -(l * q);
+    const int64_t nc = m->nc;
+    for (int c = 0; c < s->ns; c++) {
+        double A = q * s->sphi[c * nc + U];
+        s->scont[3 * (c * nc + U) + kU] = l * A;
+        s->scont[3 * (c * nc + D) + kD] = -(l * A);
+    }
+    if (s->diff)
+        for (int c = 0; c < s->ns; c++) diffusion_mirror(s, c, U, kU, l, nx, ny);
+    if (s->morpho) s->bcont[3 * U + kU] = 0.0;
 }
 
 static void edge_flux(const om_sim *s, int64_t e, edge_flux_t *out) {
@@ -1405,6 +1461,10 @@ int om_step(om_sim *s, double t_end, double *dt_taken) {
             /* each side sees a wall: its own reflected state */
             wall_side(s, L, m->ekL[e], nx, ny, l);
             wall_side(s, R, m->ekR[e], -nx, -ny, l);
+            continue;
+        }
+        if (internal_hq(s, e)) {
+            hq_edge(s, e);
             continue;
         }
         edge_flux_t ef;

@@ -554,21 +554,35 @@ swe_status swe_state_init(const swe_mesh *m, const swe_params *params, const dou
             hydro.insert(hydro.end(), B.Q, B.Q + B.n_pts);
         }
     }
-    // internal conditions on tagged interior edges: walls and dynamic walls
+    // internal conditions on tagged interior edges: walls, dynamic walls and
+    // rating curves (h-Q relations)
     std::vector<int> iwb(MAX_IW_TAGS + 1, -1);
+    bool iw_hq = false;
     for (size_t k = 0; k < M.iw_tags.size(); k++)
         for (int b = 0; b < n_bc; b++) {
             if (bcs[b].tag != M.iw_tags[k]) continue;
-            if (bcs[b].kind != SWE_BC_WALL && bcs[b].kind != SWE_BC_DYNAMIC_WALL)
-                return fail(SWE_EINVAL, "interior edges take walls and dynamic walls only");
+            if (bcs[b].kind != SWE_BC_WALL && bcs[b].kind != SWE_BC_DYNAMIC_WALL && bcs[b].kind != SWE_BC_OUTFLOW_HQ)
+                return fail(SWE_EINVAL, "interior edges take walls, dynamic walls and h-Q relations only");
             iwb[k] = b;
+            iw_hq = iw_hq || bcs[b].kind == SWE_BC_OUTFLOW_HQ;
             break;
         }
+    if (iw_hq && P.limiter == SWE_LIMIT_DRAIN)
+        return fail(SWE_EINVAL, "internal h-Q relations and the draining-time limiter do not combine");
     int iw_on = 0;
     for (int v : iwb) iw_on |= v >= 0;
     const int nslots = (int)M.slot_tag.size();
     std::vector<int> kbc((size_t)std::max(nslots, 1), BC_WALL);
     std::vector<std::vector<double>> lens((size_t)std::max(n_bc, 1));
+    // an internal rating curve spreads its discharge over the length of its
+    // interior edges (each counted once, on its upstream side)
+    for (int64_t p = 0; p < M.nc; p++)
+        for (int k = 0; k < 3; k++) {
+            const int32_t iw = M.iw_slot[3 * p + k];
+            if (iw < 0 || !M.iw_up[3 * p + k] || iwb[iw] < 0 || bcs[iwb[iw]].kind != SWE_BC_OUTFLOW_HQ) continue;
+            const double lx = M.lx[3 * p + k], ly = M.ly[3 * p + k];
+            lens[iwb[iw]].push_back(std::sqrt(lx * lx + ly * ly));
+        }
     for (int s = 0; s < nslots; s++) {
         const int32_t tg = M.slot_tag[s];
         if (tg < 0) continue;

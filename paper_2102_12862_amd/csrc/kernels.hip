@@ -771,6 +771,7 @@ __device__ __forceinline__ void tile_edges(const Inst<T> &I, TileLds<T, TILE> &S
         // the other cell's sediment state (Exner): Phi, dPhi, velocity, depth, bed
         T mphi = T(0), mdphi = T(0), mub = T(0), mvb = T(0), mhb = T(0), mzb = T(0);
         bool open = false, inflow_on = false, imposed = false, walled = false;
+        int ihq = 0;  // internal rating curve: 1 this side upstream, -1 downstream
         T qimp = T(0);  // weir or h-Q discharge, or an active inflow's unit discharge
         if (kind != EK_BOUNDARY) {
             V4<T> sb;
@@ -828,11 +829,16 @@ __device__ __forceinline__ void tile_edges(const Inst<T> &I, TileLds<T, TILE> &S
             unR = flip ? -una : unb;
             utR = flip ? -uta : utb;
             // a standing internal wall (static, or dynamic before its
-            // collapse time): this side sees its own reflected state
+            // collapse time): this side sees its own reflected state.  An
+            // internal rating curve is a wall for the momentum too, while
+            // the discharge of its table at the upstream cell's surface
+            // crosses from the side left of the tag's segment (bit 17) to
+            // the other
             const int iw = IW ? (E.w0 >> 27) & 31 : 0;
             if (iw) {
                 const int bc = I.iw_bc[iw - 1];
-                if (bc >= 0 && (I.bcs[bc].kind == BC_WALL || t < I.bcs[bc].slope)) {
+                const int bk = bc >= 0 ? I.bcs[bc].kind : -1;
+                if (bk == BC_WALL || (bk == BC_DYNWALL && t < I.bcs[bc].slope) || bk == BC_HQ) {
                     const double dw = Ha - double(sa.w);
                     ha = dw < H_DRY ? T(0) : T(dw);
                     hL = hR = ha;
@@ -841,6 +847,12 @@ __device__ __forceinline__ void tile_edges(const Inst<T> &I, TileLds<T, TILE> &S
                     unR = -una;
                     flip = false;
                     walled = true;
+                    if (bk == BC_HQ) {
+                        const bool up = (E.w0 >> 17) & 1;
+                        qimp = T(up ? imposed_outflow(I.bcs[bc], Ha, double(sa.w), I.sqrt2g)
+                                    : imposed_outflow(I.bcs[bc], Hb, double(sb.w), I.sqrt2g));
+                        ihq = up ? 1 : -1;
+                    }
                 }
             }
         } else {
@@ -905,6 +917,14 @@ __device__ __forceinline__ void tile_edges(const Inst<T> &I, TileLds<T, TILE> &S
         if (kind != EK_BOUNDARY) {
             if (flip) F0 = -F0;  // mass leaving a
             if (walled) F0 = T(0);
+            if (ihq > 0) {
+                // the rating curve's discharge leaves carrying a's state
+                F0 = qimp;
+                F1 = (ha > T(0) ? qimp * qdiv(qimp, ha) : T(0)) + hg2 * ha * ha;
+                F2 = qimp * uta;
+            } else if (ihq < 0) {
+                F0 = -qimp;  // and enters the downstream cell
+            }
         } else {
             if (!open) F0 = T(0);  // no mass crosses a wall
             if (imposed) {
@@ -1562,8 +1582,10 @@ __global__ void __launch_bounds__(TILE) k_diffuse(Inst<T> I, int phase) {
         bool closed = kind == EK_BOUNDARY;
         const int iw = (E.w0 >> 27) & 31;
         if (iw && !closed) {
+            // standing walls and rating curves exchange nothing by diffusion
             const int bc = I.iw_bc[iw - 1];
-            if (bc >= 0 && (I.bcs[bc].kind == BC_WALL || L.t < I.bcs[bc].slope)) closed = true;
+            const int bk = bc >= 0 ? I.bcs[bc].kind : -1;
+            if (bk == BC_WALL || (bk == BC_DYNWALL && L.t < I.bcs[bc].slope) || bk == BC_HQ) closed = true;
         }
         if (closed) {
             diff_mirror<T, TILE, NS>(I, S, a, ka, l, nx, ny);

@@ -10,6 +10,7 @@
 #include <cmath>
 #include <cstring>
 #include <unordered_map>
+#include <utility>
 
 namespace swe {
 
@@ -91,17 +92,21 @@ bool prepare_mesh(const double *xyz, int64_t nv, const int32_t *tri, int64_t nc,
                 he[(size_t)fill[std::min(p, q)]++] = HalfEdge{std::max(p, q), (int32_t)i, k};
             }
     }
-    std::unordered_map<uint64_t, int32_t> segtag;
+    // per segment its tag and its first node (the direction a segment on
+    // interior edges gives: the cell on its left is the upstream side of an
+    // internal rating curve)
+    std::unordered_map<uint64_t, std::pair<int32_t, int32_t>> segtag;
     segtag.reserve((size_t)ns * 2 + 1);
     for (int64_t s = 0; s < ns; s++) {
         const int32_t p = seg[2 * s], q = seg[2 * s + 1];
         if (p < 0 || q < 0 || p >= nv || q >= nv || p == q) { err = "bad boundary segment"; return false; }
         const uint64_t key = ((uint64_t)std::min(p, q) << 32) | (uint32_t)std::max(p, q);
-        if (!segtag.emplace(key, tag[s]).second) { err = "duplicate boundary segment"; return false; }
+        if (!segtag.emplace(key, std::make_pair(tag[s], p)).second) { err = "duplicate boundary segment"; return false; }
     }
     // neighbour of every (old cell, local edge): old neighbour id, or -1 - boundary id
     std::vector<int32_t> link((size_t)(3 * nc));
     std::vector<int32_t> itag0((size_t)(3 * nc), -1);  // tag of a tagged interior edge
+    std::vector<uint8_t> up0((size_t)(3 * nc), 0);     // the cell is on the left of that edge's segment
     std::vector<int32_t> btag;
     int64_t matched = 0, ne = 0;
     for (int64_t v = 0; v < nv; v++) {
@@ -125,7 +130,11 @@ bool prepare_mesh(const double *xyz, int64_t nv, const int32_t *tri, int64_t nc,
                 const uint64_t key = ((uint64_t)v << 32) | (uint32_t)g->hi;
                 auto it = segtag.find(key);
                 if (it != segtag.end()) {
-                    itag0[3 * c1 + k1] = itag0[3 * c2 + k2] = it->second;
+                    itag0[3 * c1 + k1] = itag0[3 * c2 + k2] = it->second.first;
+                    // a counter-clockwise cell walking the edge in the
+                    // segment's direction lies on the segment's left
+                    up0[3 * c1 + k1] = t3[3 * c1 + k1] == it->second.second;
+                    up0[3 * c2 + k2] = t3[3 * c2 + k2] == it->second.second;
                     matched++;
                 }
             } else {
@@ -133,7 +142,7 @@ bool prepare_mesh(const double *xyz, int64_t nv, const int32_t *tri, int64_t nc,
                 auto it = segtag.find(key);
                 int32_t tg = -1;
                 if (it != segtag.end()) {
-                    tg = it->second;
+                    tg = it->second.first;
                     matched++;
                 }
                 link[3 * g->cell + g->k] = -1 - (int32_t)btag.size();
@@ -182,6 +191,7 @@ bool prepare_mesh(const double *xyz, int64_t nv, const int32_t *tri, int64_t nc,
     M.ly.resize((size_t)(3 * nc));
     M.nbr.resize((size_t)(3 * nc));
     M.iw_slot.assign((size_t)(3 * nc), -1);
+    M.iw_up.assign((size_t)(3 * nc), 0);
     M.slot_tag.clear();
     M.slot_len.clear();
     M.slot_cell.clear();
@@ -197,9 +207,11 @@ bool prepare_mesh(const double *xyz, int64_t nv, const int32_t *tri, int64_t nc,
             M.lx[3 * p + k] = dy;
             M.ly[3 * p + k] = -dx;
             const int32_t L = link[3 * i + k];
-            if (itag0[3 * i + k] >= 0)
+            if (itag0[3 * i + k] >= 0) {
                 M.iw_slot[3 * p + k] = (int32_t)(std::find(M.iw_tags.begin(), M.iw_tags.end(), itag0[3 * i + k]) -
                                                  M.iw_tags.begin());
+                M.iw_up[3 * p + k] = up0[3 * i + k];
+            }
             if (L >= 0) {
                 int32_t code = M.inv[L];
                 if (i > L) code |= NBR_FLIP_BIT;  // canonical left cell = smaller original id
@@ -241,8 +253,10 @@ bool build_tile_edges(const HostMesh &M, int tile, std::vector<TileEdge> &edges,
                     const int32_t q = code & (NBR_FLIP_BIT - 1);
                     if (code & NBR_FLIP_BIT) w0 |= 1 << 16;
                     if (iw >= 0) {
-                        // a tagged interior edge: one record per side
-                        w0 |= (EDGE_REMOTE << 14) | (int32_t)((uint32_t)(iw + 1) << 27);
+                        // a tagged interior edge: one record per side, bit 17
+                        // set on the side left of the tag's segment
+                        w0 |= (EDGE_REMOTE << 14) | (int32_t)((uint32_t)(iw + 1) << 27) |
+                              ((int32_t)M.iw_up[3 * p + k] << 17);
                         e.w1 = q;
                     } else if (q >= p0 && q < p1) {
                         if (q < p) continue;  // emitted from the other cell
@@ -304,6 +318,8 @@ std::string check_tile_edges(const HostMesh &M, int tile, const std::vector<Tile
             const int32_t code = M.nbr[3 * pa + ka];
             const int iwf = (int)(((uint32_t)E.w0 >> 27) & 31);
             if (iwf != M.iw_slot[3 * pa + ka] + 1) return "interior-tag index mismatch";
+            if (iwf && ((E.w0 >> 17) & 1) != M.iw_up[3 * pa + ka]) return "interior-tag side mismatch";
+            if (iwf && ((E.w0 >> 18) & 511)) return "stray bits in a tagged interior record";
             seen[3 * pa + ka]++;
             if (kind == EDGE_BOUNDARY) {
                 if (code >= 0 || E.w1 != -1 - code) return "boundary edge mismatch";

@@ -26,6 +26,10 @@ struct HostMesh {
     // edge) the index of its tag in iw_tags, or -1; at most 31 distinct tags
     std::vector<int32_t> iw_slot;
     std::vector<int32_t> iw_tags;
+    // per (device cell, local edge) of a tagged interior edge: 1 when the
+    // cell lies on the left of the edge's segment (its first node to its
+    // second), the upstream side of an internal rating curve
+    std::vector<uint8_t> iw_up;
 };
 constexpr int MAX_IW_TAGS = 31;
 
@@ -40,7 +44,8 @@ constexpr int MAX_IW_TAGS = 31;
 //       cell of the edge's canonical orientation, bits 17-26 local cell b,
 //       bits 27-31 one plus the interior-tag index of a tagged interior edge
 //       (such an edge is stored once per side, as kind 1, even when both
-//       cells are in the tile, so that each side can become a wall)
+//       cells are in the tile, so that each side can become a wall; its bit
+//       17 is set on the side left of the tag's segment)
 //   w1: kind 1: device id of the other cell; kind 2: boundary slot
 //   lx, ly: l * n with n the outward normal of a
 enum : int32_t { EDGE_LOCAL = 0, EDGE_REMOTE = 1, EDGE_BOUNDARY = 2 };

@@ -1,16 +1,19 @@
-"""Internal static and dynamic walls on the GPU (section "Hydrodynamic BCs",
-internal BCs on tagged interior edges): parity with the FP64 oracle (FP64
-within 1e-10 of the norm, FP32 within 1e-4 in the max and L1 norms on a fixed step)
-at every tile size, through a dynamic wall's collapse, with species, the
-Exner module, the draining-time limiter and in a batch; the tile edge lists
-stay consistent; other kinds on interior edges are refused."""
+"""Internal static and dynamic walls and rating curves on the GPU (section
+"Hydrodynamic BCs", internal BCs on tagged interior edges): parity with the
+FP64 oracle (FP64 within 1e-10 of the norm, FP32 within 1e-4 in the max and
+L1 norms on a fixed step) at every tile size, through a dynamic wall's
+collapse, with species, the Exner module, the draining-time limiter and in a
+batch; a rating curve draining one half of a basin into the other, either
+way round, with species and in a batch, the volume exact on the device; the
+tile edge lists stay consistent; other kinds on interior edges, and a
+rating curve with the limiter, are refused."""
 import numpy as np
 import pytest
 
 import oracle
 import swe_inputs as S
 from gpu_util import compare, device, gpu_state, rel_err
-from test_oracle_internal_walls import _cut_basin, _scenario
+from test_oracle_internal_walls import _cut_basin, _rating_basin, _scenario
 
 pytestmark = pytest.mark.gpu
 
@@ -105,3 +108,69 @@ def test_only_walls_on_interior_edges(swe):
     m = swe.Mesh(sc.nodes, sc.tri, sc.bnd_seg, sc.bnd_tag)
     with pytest.raises(swe.SweError, match="interior edges"):
         swe.State(m, sc, precision=swe.FP32)
+
+
+@pytest.mark.parametrize("reverse", [False, True])
+@pytest.mark.parametrize("tile", [128, 512])
+def test_rating_curve_fp64(swe, reverse, tile):
+    sc, up = _rating_basin(reverse)
+    st = gpu_state(sc, swe.FP64, block_size=tile)
+    st.mesh.check(tile)
+    v0 = st.mass()["mass"]
+    sim = oracle.Sim(sc)
+    for k in range(150):
+        dg, do = st.step(), sim.step()
+        assert abs(dg - do) <= 1e-13 * do, (k, dg, do)
+    compare(st, sim, FP64_TOL)
+    m = st.mass()
+    assert m["bnd_flux"] == 0.0 and abs(m["mass"] - v0) <= 1e-12 * v0
+    # water went downstream
+    h = st.read()["h"]
+    area = sim.mesh.geometry()["area"]
+    assert (h * area)[~up].sum() > 0.5 * area[~up].sum() + 1.0
+
+
+def test_rating_curve_with_species_fp64(swe):
+    sc, up = _rating_basin(phi=True)
+    st = gpu_state(sc, swe.FP64)
+    sim = oracle.Sim(sc)
+    for _ in range(100):
+        st.step()
+        sim.step()
+    compare(st, sim, FP64_TOL)
+    q, qo = st.scalars(), sim.scalars()
+    assert rel_err(q[0], qo[0]) <= FP64_TOL
+    m, b, c = st.scalar_mass()
+    mo, bo, co = sim.scalar_diag()
+    assert abs(m[0] - mo[0]) <= 1e-12 * mo[0] and b[0] == 0.0
+
+
+def test_rating_curve_fp32_and_batch(swe):
+    sc, up = _rating_basin()
+    fixed = S.Scenario(**{**sc.__dict__, "dt_max": 0.5 * oracle.Sim(sc).next_dt()})
+    st = gpu_state(fixed, swe.FP32)
+    sim = oracle.Sim(fixed)
+    for _ in range(100):
+        st.step()
+        sim.step()
+    compare(st, sim, FP32_TOL, metric="l1")
+    # in a batch, bitwise the single run
+    one = gpu_state(sc, swe.FP32, block_size=256)
+    mine = gpu_state(sc, swe.FP32, block_size=256)
+    b = swe.Batch(swe.FP32, device=device())
+    b.add(mine, 20.0)
+    while b.step(16):
+        pass
+    one.run_until(20.0)
+    ra, rb = one.read(), mine.read()
+    for f in ("H", "qx", "qy"):
+        assert np.array_equal(ra[f], rb[f]), f
+    b.close()
+
+
+def test_rating_curve_refuses_the_limiter(swe):
+    sc, _ = _rating_basin()
+    sc.drain = True
+    m = swe.Mesh(sc.nodes, sc.tri, sc.bnd_seg, sc.bnd_tag)
+    with pytest.raises(swe.SweError, match="do not combine"):
+        swe.State(m, sc, precision=swe.FP64)

@@ -1,12 +1,23 @@
 """Pins of the internal conditions in the oracle (section "Hydrodynamic
-BCs": internal static walls and dynamic walls on tagged interior edges):
+BCs": internal static walls, dynamic walls and rating curves on tagged
+interior edges):
 
 * a basin cut by a static internal wall evolves, on each side, bitwise like
   that side meshed alone with walls on its cut;
 * a dynamic wall stands until its collapse time, then the flow is bitwise
   the flow without the wall restarted from the state at that time;
-* only walls and dynamic walls are taken on interior edges.
+* an internal rating curve with a linear table drains the upstream half of
+  a cut basin (the side left of the cut's segments) into the other half
+  along the closed form of A dH/dt = -k (H - H_0), whatever the downstream
+  level, the total volume exact and the downstream half gaining what the
+  upstream half loses; reversing the segments reverses the flow; the
+  species cross with the upstream concentration; a zero table keeps a lake
+  at rest bitwise;
+* only walls, dynamic walls and rating curves are taken on interior edges,
+  and a rating curve refuses the draining-time limiter.
 """
+import math
+
 import numpy as np
 import pytest
 
@@ -87,3 +98,95 @@ def test_only_walls_on_interior_edges():
     sc = _scenario(xy, tri, seg, np.full(len(seg), 9, np.int32), [S.BC(9, S.OUTFLOW_ZEROGRAD)], np.full(n, 1.0))
     with pytest.raises(oracle.OracleError, match="interior edges"):
         oracle.Sim(sc)
+
+
+K_HQ, H_CREST = 4.0, 1.0
+
+
+def _rating_basin(reverse=False, H_up=1.3, H_down=0.5, k=K_HQ, phi=False):
+    """The 40 m x 10 m basin cut at x = 20 by a rating curve Q(H) = k (H - 1)
+    (0 below H = 1); the cut's segments run along +y, so the half x < 20
+    lies on their left (upstream), or along -y with reverse."""
+    xy, tri, seg = _cut_basin()
+    if reverse:
+        seg = seg[:, ::-1].copy()
+    cx = xy[tri, 0].mean(axis=1)
+    left = cx < 20.0
+    up = ~left if reverse else left
+    H0 = np.where(up, H_up, H_down)
+    bc = S.BC(9, S.OUTFLOW_HQ, t=np.array([H_CREST, H_CREST + 1.0]), Q=np.array([0.0, k]))
+    sc = _scenario(xy, tri, seg, np.full(len(seg), 9, np.int32), [bc], H0)
+    sc.dt_max = 0.5
+    if phi:
+        sc.phi0 = np.where(up, 1.0, 0.0)[None, :]
+    return sc, up
+
+
+@pytest.mark.parametrize("reverse", [False, True])
+def test_rating_curve_drains_the_upstream_half(reverse):
+    sc, up = _rating_basin(reverse)
+    sim = oracle.Sim(sc)
+    area = sim.mesh.geometry()["area"]
+    a_up = area[up].sum()
+    v0 = sim.diag()["mass"]
+    vu0 = ((sim.state()[0] - sim.bed()) * area)[up].sum()
+    T = 200.0
+    sim.run_until(T)
+    H = sim.state()[0]
+    h = H - sim.bed()
+    # A dH/dt = -k (H - 1) over the upstream half (its level stays near flat)
+    expect = H_CREST + (1.3 - H_CREST) * math.exp(-K_HQ * T / a_up)
+    mean_up = (H[up] * area[up]).sum() / a_up
+    assert abs(mean_up - expect) <= 0.02 * (expect - H_CREST), (mean_up, expect)
+    # the total exact, the downstream half gains what the upstream half lost
+    d = sim.diag()
+    assert d["bnd_flux"] == 0.0 and d["clipped"] == 0.0
+    assert abs(d["mass"] - v0) <= 1e-12 * v0
+    vu = (h * area)[up].sum()
+    vd = (h * area)[~up].sum()
+    assert abs((vu0 - vu) - (vd - (v0 - vu0))) <= 1e-11 * v0
+    assert vu0 - vu > 0.5 * (1.3 - expect) * a_up
+
+
+def test_rating_curve_is_one_way():
+    # the downstream half higher than the upstream one: the curve still
+    # passes Q(H_upstream) downstream, and nothing flows back
+    sc, up = _rating_basin(H_up=1.2, H_down=1.6)
+    sim = oracle.Sim(sc)
+    area = sim.mesh.geometry()["area"]
+    vu0 = ((sim.state()[0] - sim.bed()) * area)[up].sum()
+    sim.run_until(50.0)
+    vu = ((sim.state()[0] - sim.bed()) * area)[up].sum()
+    assert vu < vu0
+
+
+def test_rating_curve_carries_the_upstream_concentration():
+    sc, up = _rating_basin(phi=True)
+    sim = oracle.Sim(sc)
+    area = sim.mesh.geometry()["area"]
+    vd0 = ((sim.state()[0] - sim.bed()) * area)[~up].sum()
+    sim.run_until(100.0)
+    vd = ((sim.state()[0] - sim.bed()) * area)[~up].sum()
+    q = sim.scalars()[0]
+    # the upstream half stays at phi = 1; what entered downstream is exactly
+    # the water that crossed, at phi = 1
+    assert abs((q * area)[~up].sum() - (vd - vd0)) <= 1e-10 * (vd - vd0)
+    m, b, c = sim.scalar_diag()
+    assert b[0] == 0.0 and abs(m[0] - ((1.3 - 0.0) * area[up].sum())) <= 1e-11 * m[0]
+
+
+def test_zero_rating_curve_keeps_a_lake_at_rest():
+    sc, _ = _rating_basin(H_up=1.4, H_down=1.4, k=0.0)
+    sim = oracle.Sim(sc)
+    H0 = sim.state()[0].copy()
+    for _ in range(100):
+        sim.step()
+    H, qx, qy, _ = sim.state()
+    assert np.array_equal(H, H0) and np.all(qx == 0.0) and np.all(qy == 0.0)
+
+
+def test_rating_curve_refuses_the_limiter():
+    sc, _ = _rating_basin()
+    sim = oracle.Sim(sc)
+    with pytest.raises(oracle.OracleError, match="do not combine"):
+        sim.set_drain(True)

@@ -1,6 +1,6 @@
 """Pins of the external water sources and sinks S_h in the oracle (the S_h
 paragraph of the hydrodynamic closure relations; eq.
-swe_vectorial_form_sourceterms added explicitly to the continuity equation
+swe_vectorial_form_sourceterms, an explicit source in the continuity equation
 of eq. hydrodynamicupdateformula):
 
 * uniform rain (intensity in mm/h) on a closed flat basin raises a lake at

@@ -85,11 +85,15 @@ typedef struct {
  *    of its cell, with the cell's state: flux (q, q^2/h + g h^2/2, q u_t).
  *  - OUTFLOW_HQ (t = surface elevations H, Q = discharges >= 0): q =
  *    Q(H) / (boundary length) leaves like over a weir.
- *  - DYNAMIC_WALL (slope = collapse time): a wall before it, zero gradient
- *    from then on.
+ *  - DYNAMIC_WALL (slope = collapse time, par = collapse depth >= 0, 0 for
+ *    none): a wall before its collapse time and, with a collapse depth,
+ *    until the end of the first step that starts with its cell at that
+ *    depth or deeper (h = H - z; at most 8 such walls per state); zero
+ *    gradient from then on.
  * On tagged interior edges (internal conditions, section "Hydrodynamic
  * BCs"): WALL makes each side a wall of its own state; DYNAMIC_WALL does so
- * until its collapse time, after which the edge is an ordinary one; OUTFLOW_HQ
+ * until it collapses (by time, or by the depth of a cell on either side),
+ * after which the edge is an ordinary one; OUTFLOW_HQ
  * is a rating curve: q = Q(H) / (the curve's length) at the surface H of the
  * cell left of each segment (walking from its first node to its second)
  * crosses to the cell on the right, leaving with the left cell's state,
@@ -118,7 +122,7 @@ typedef struct {
     const double *t;  /* series times [s] or the surface elevations of an h-Q table, strictly increasing (host) */
     const double *Q;  /* discharge [m^3/s], or surface elevation [m] for a zhydrograph (host) */
     int32_t n_pts;    /* number of series points (>= 1 where a series is needed) */
-    double par;       /* Poleni factor of a weir */
+    double par;       /* Poleni factor of a weir, collapse depth [m] of a dynamic wall */
 } swe_bc;
 
 enum { SWE_FP64 = 0, SWE_FP32 = 1 };        /* precision (double is the paper's default) */

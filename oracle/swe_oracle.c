@@ -46,7 +46,8 @@ struct om_mesh {
 typedef struct {
     int32_t tag, kind, npts;
     double slope, length;  /* slope: energy slope, Froude number, crest elevation or collapse time */
-    double par;            /* Poleni factor of a weir */
+    double par;            /* Poleni factor of a weir, collapse depth of a dynamic wall */
+    double gone;           /* dynamic wall with a collapse depth: the time it is gone from (+inf until then) */
     double *t, *Q;
 } om_bc;
 
@@ -391,7 +392,9 @@ om_sim *om_sim_new(const om_mesh *m, double g, double cfl, double h_min, double 
         B->tag = bc_tag[b]; B->kind = bc_kind[b]; B->slope = bc_slope ? bc_slope[b] : 0.0;
         B->npts = bc_npts ? bc_npts[b] : 0;
         B->par = bc_par ? bc_par[b] : 0.0;
+        B->gone = INFINITY;
         if (B->kind < 0 || B->kind > OM_DYNAMIC_WALL) { seterr(err, elen, "unknown boundary kind"); goto fail; }
+        if (B->kind == OM_DYNAMIC_WALL && B->par < 0.0) { seterr(err, elen, "a dynamic wall's collapse depth must be >= 0"); goto fail; }
         if (!isfinite(B->slope) || !isfinite(B->par)) { seterr(err, elen, "non-finite boundary parameter"); goto fail; }
         if (B->kind == OM_ZHYDROGRAPH && B->npts < 1) { seterr(err, elen, "zhydrograph needs a series"); goto fail; }
         if (B->kind == OM_INFLOW_FROUDE && (B->npts < 1 || !(B->slope > 0))) { seterr(err, elen, "froude inflow needs a hydrograph and a positive Froude number"); goto fail; }
@@ -1240,12 +1243,35 @@ typedef struct {
     int wall, open, inflow_b;
 } edge_flux_t;
 
+/* A dynamic wall (section "Hydrodynamic BCs": removed once a threshold in
+ * time or in water depth is reached) stands before its collapse time and,
+ * with a collapse depth, before the end of the first step that started with
+ * a cell next to it at that depth (reading: the wall holds through that
+ * step and is gone from the next; dynamic_wall_depths sets the time). */
+static int wall_stands(const om_sim *s, const om_bc *B) {
+    return s->t < B->slope && s->t < B->gone;
+}
+
 /* An interior edge that is a standing internal wall (a static wall, or a
- * dynamic wall before its collapse time). */
+ * standing dynamic wall). */
 static int internal_wall(const om_sim *s, int64_t e) {
     if (s->m->eR[e] < 0 || s->ebc[e] < 0) return 0;
     const om_bc *B = &s->bc[s->ebc[e]];
-    return B->kind == OM_WALL || (B->kind == OM_DYNAMIC_WALL && s->t < B->slope);
+    return B->kind == OM_WALL || (B->kind == OM_DYNAMIC_WALL && wall_stands(s, B));
+}
+
+/* Dynamic walls with a collapse depth: one that stands at t^n with a cell on
+ * either side of one of its edges (the one cell of a boundary edge) at or
+ * above that depth h = H - z is gone from t^n + dt on. */
+static void dynamic_wall_depths(om_sim *s, double dt) {
+    const om_mesh *m = s->m;
+    for (int64_t e = 0; e < m->ne; e++) {
+        if (s->ebc[e] < 0) continue;
+        om_bc *B = &s->bc[s->ebc[e]];
+        if (B->kind != OM_DYNAMIC_WALL || !(B->par > 0.0) || !wall_stands(s, B)) continue;
+        const int32_t L = m->eL[e], R = m->eR[e];
+        if (s->H[L] - s->z[L] >= B->par || (R >= 0 && s->H[R] - s->z[R] >= B->par)) B->gone = s->t + dt;
+    }
 }
 
 /* An interior edge that carries an internal rating curve. */
@@ -1346,15 +1372,15 @@ static void edge_flux(const om_sim *s, int64_t e, edge_flux_t *out) {
         } else if (B && B->kind == OM_OUTFLOW_UNIFORM) {
             /* uniform(slope) outflow: the ghost carries the normal depth
              * of the cell's outflowing unit discharge with the cell's
-             * velocity (reading: "a value for the water depth must be
-             * specified" for outflows; no outflow gives a dry ghost) */
+             * velocity (reading: the paper asks for a depth at outflows
+             * without saying which; no outflow gives a dry ghost) */
             double qn = hL * unL;
             hg = normal_depth(s, s->gn2[L], qn > 0.0 ? qn : 0.0, B->slope);
             HR = zL + hg; unR = unL; utR = utL; open = 1;
         } else if (B && (B->kind == OM_OUTFLOW_WEIR || B->kind == OM_OUTFLOW_HQ)) {
             HR = HL; unR = unL; utR = utL; open = 1; imposed = 1;
-        } else if (B && B->kind == OM_DYNAMIC_WALL && s->t >= B->slope) {
-            /* a dynamic wall after its collapse time: transmissive */
+        } else if (B && B->kind == OM_DYNAMIC_WALL && !wall_stands(s, B)) {
+            /* a dynamic wall once it is gone: transmissive */
             HR = HL; unR = unL; utR = utL; open = 1;
         } else if (B && B->kind == OM_ZHYDROGRAPH) {
             /* "zhydrograph" (section "Hydrodynamic BCs", water surface
@@ -1407,6 +1433,7 @@ int om_step(om_sim *s, double t_end, double *dt_taken) {
     double dt = om_next_dt(s, t_end);
     if (dt_taken) *dt_taken = dt;
     if (!(dt > 0.0) || !isfinite(dt)) return -7;
+    dynamic_wall_depths(s, dt);
     memset(s->cont, 0, sizeof(double) * 9 * (size_t)m->nc);
     double bstep = 0.0, bstepc = 0.0;
     int deficit = 0;   /* an exact sink asked for more water than a cell held */

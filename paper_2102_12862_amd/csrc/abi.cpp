@@ -531,12 +531,21 @@ swe_status swe_state_init(const swe_mesh *m, const swe_params *params, const dou
     std::vector<BCdev> hb((size_t)std::max(n_bc, 1));
     std::vector<double> hydro;
     std::vector<size_t> hoff((size_t)std::max(n_bc, 1));
+    int n_depth_walls = 0;
     for (int b = 0; b < n_bc; b++) {
         const swe_bc &B = bcs[b];
         if (B.kind < SWE_BC_WALL || B.kind > SWE_BC_DYNAMIC_WALL) return fail(SWE_EINVAL, "unknown boundary kind");
         if (!std::isfinite(B.slope) || !std::isfinite(B.par)) return fail(SWE_EINVAL, "non-finite boundary parameter");
         hb[b] = BCdev{B.kind, 0, B.slope, 0.0, nullptr, nullptr, B.par};
         hoff[b] = hydro.size();
+        if (B.kind == SWE_BC_DYNAMIC_WALL) {
+            if (B.par < 0.0) return fail(SWE_EINVAL, "a dynamic wall's collapse depth must be >= 0");
+            if (B.par > 0.0) {
+                if (n_depth_walls == MAX_DEPTH_WALLS)
+                    return fail(SWE_EINVAL, "at most 8 dynamic walls with a collapse depth");
+                hb[b].wslot = n_depth_walls++;
+            }
+        }
         if ((B.kind == SWE_BC_INFLOW_UNIFORM || B.kind == SWE_BC_INFLOW_FROUDE || B.kind == SWE_BC_OUTFLOW_UNIFORM) &&
             !(B.slope > 0))
             return fail(SWE_EINVAL, "uniform and froude conditions need a positive slope or Froude number");
@@ -699,6 +708,7 @@ swe_status swe_state_init(const swe_mesh *m, const swe_params *params, const dou
     c.s[0].t = t0;
     for (auto &mm : c.m) mm.bits = INF_BITS;
     c.t_end = std::numeric_limits<double>::infinity();
+    for (auto &w : c.wall) w = time_key(std::numeric_limits<double>::infinity());
     *S->hctrl = c;
     S->phase = 0;
     HIP_TRY(hipMemcpyAsync(S->ctrl, S->hctrl, sizeof(Ctrl), hipMemcpyHostToDevice, s));

@@ -34,7 +34,7 @@ INFLOW_FROUDE = 4     # discharge series entering at a given Froude number (slop
 OUTFLOW_UNIFORM = 5   # normal depth of the outflowing discharge (slope = energy slope)
 OUTFLOW_WEIR = 6      # Poleni weir (slope = crest elevation, par = Poleni factor)
 OUTFLOW_HQ = 7        # h-Q relation (t = surface elevations, Q = discharges)
-DYNAMIC_WALL = 8      # wall until the collapse time (slope), then zero gradient
+DYNAMIC_WALL = 8      # wall until the collapse time (slope) or depth (par), then zero gradient
 
 
 def rng(offset: int) -> np.random.Generator:
@@ -49,7 +49,7 @@ class BC:
     t: Optional[np.ndarray] = None  # hydrograph times [s] (surface elevations [m] of an h-Q table)
     Q: Optional[np.ndarray] = None  # discharge [m^3/s] (surface elevation [m] for ZHYDROGRAPH)
     phi_in: tuple = ()              # inflow concentration of each passive species
-    par: float = 0.0                # Poleni factor of a weir
+    par: float = 0.0                # Poleni factor of a weir, collapse depth of a dynamic wall
 
 
 # external water sources and sinks: modes and units of the series

@@ -2,7 +2,9 @@
 "Hydrodynamic BCs", internal BCs on tagged interior edges): parity with the
 FP64 oracle (FP64 within 1e-10 of the norm, FP32 within 1e-4 in the max and
 L1 norms on a fixed step) at every tile size, through a dynamic wall's
-collapse, with species, the Exner module, the draining-time limiter and in a
+collapse (at its time, or at the end of the first step that starts with a
+cell next to it at its collapse depth, inside the domain and on its
+boundary), with species, the Exner module, the draining-time limiter and in a
 batch; a rating curve draining one half of a basin into the other, either
 way round, with species and in a batch, the volume exact on the device; the
 tile edge lists stay consistent; other kinds on interior edges, and a
@@ -101,6 +103,75 @@ def test_batch_matches_a_single_run(swe):
     for f in ("H", "qx", "qy"):
         assert np.array_equal(ra[f], rb[f]), f
     b.close()
+
+
+@pytest.mark.parametrize("tile", [128, 512])
+def test_dynamic_wall_collapse_depth_fp64(swe, tile):
+    # the dam-break wave raises the cut's cells from 0.4 m to 0.6 m at t ~ 3 s
+    sc = _basin(S.BC(9, S.DYNAMIC_WALL, slope=1e30, par=0.6))
+    st = gpu_state(sc, swe.FP64, block_size=tile)
+    sim = oracle.Sim(sc)
+    for k in range(150):
+        dg, do = st.step(), sim.step()
+        assert abs(dg - do) <= 1e-13 * do, (k, dg, do)
+    assert sim.t > 6.0
+    compare(st, sim, FP64_TOL)
+    # water crossed the cut
+    wall = oracle.Sim(_basin(S.BC(9, S.WALL)))
+    wall.run_until(sim.t)
+    assert rel_err(sim.state()[0], wall.state()[0]) > 1e-3
+
+
+def test_dynamic_wall_collapse_depth_on_the_boundary_fp64(swe):
+    base = S.dam_break(d=1.0, h_right=0.0)
+    xy = base.nodes[:, :2]
+    right = np.where(np.abs(xy[:, 0] - 100.0) < 1e-9)[0]
+    right = right[np.argsort(xy[right, 1])]
+    seg = np.c_[right[:-1], right[1:]].astype(np.int32)
+    sc = S.Scenario(**{**base.__dict__, "bnd_seg": seg, "bnd_tag": np.full(len(seg), 7, np.int32),
+                       "bcs": [S.BC(7, S.DYNAMIC_WALL, slope=1e30, par=0.05)]})
+    st = gpu_state(sc, swe.FP64)
+    sim = oracle.Sim(sc)
+    while sim.t < 20.0:
+        dg, do = st.step(), sim.step()
+        assert abs(dg - do) <= 1e-13 * do, (sim.t, dg, do)
+    compare(st, sim, FP64_TOL)
+    bg, bo = st.mass()["bnd_flux"], sim.diag()["bnd_flux"]
+    assert bo > 0.0 and abs(bg - bo) <= 1e-10 * bo, (bg, bo)
+
+
+def test_dynamic_wall_collapse_depth_fp32_and_batch(swe):
+    sc = _basin(S.BC(9, S.DYNAMIC_WALL, slope=1e30, par=0.6))
+    fixed = S.Scenario(**{**sc.__dict__, "dt_max": 0.5 * oracle.Sim(sc).next_dt()})
+    st = gpu_state(fixed, swe.FP32)
+    sim = oracle.Sim(fixed)
+    while sim.t < 6.0:
+        st.step()
+        sim.step()
+    compare(st, sim, FP32_TOL, metric="l1")
+    one = gpu_state(sc, swe.FP32, block_size=256)
+    mine = gpu_state(sc, swe.FP32, block_size=256)
+    b = swe.Batch(swe.FP32, device=device())
+    b.add(mine, 8.0)
+    while b.step(16):
+        pass
+    one.run_until(8.0)
+    ra, rb = one.read(), mine.read()
+    assert ra["t"] == rb["t"]
+    for f in ("H", "qx", "qy"):
+        assert np.array_equal(ra[f], rb[f]), f
+    b.close()
+
+
+def test_dynamic_wall_collapse_depth_api(swe):
+    sc = _basin(S.BC(9, S.DYNAMIC_WALL, slope=1.0, par=-0.1))
+    m = swe.Mesh(sc.nodes, sc.tri, sc.bnd_seg, sc.bnd_tag)
+    with pytest.raises(swe.SweError, match="collapse depth"):
+        swe.State(m, sc, precision=swe.FP64)
+    many = S.Scenario(**{**sc.__dict__, "bcs": [S.BC(100 + k, S.DYNAMIC_WALL, slope=1.0, par=0.5)
+                                                for k in range(9)]})
+    with pytest.raises(swe.SweError, match="at most 8"):
+        swe.State(m, many, precision=swe.FP64)
 
 
 def test_only_walls_on_interior_edges(swe):

@@ -6,6 +6,12 @@ interior edges):
   that side meshed alone with walls on its cut;
 * a dynamic wall stands until its collapse time, then the flow is bitwise
   the flow without the wall restarted from the state at that time;
+* a dynamic wall with a collapse depth (the paper's water-depth threshold)
+  is bitwise a static wall up to and including the first step that starts
+  with a cell next to it at that depth, found by brute force over the
+  states, and bitwise the flow without it from then on (inside the domain
+  and on its boundary, where the flow without it is zero-gradient outflow);
+  a depth never reached keeps it standing;
 * an internal rating curve with a linear table drains the upstream half of
   a cut basin (the side left of the cut's segments) into the other half
   along the closed form of A dH/dt = -k (H - H_0), whatever the downstream
@@ -90,6 +96,98 @@ def test_dynamic_wall_collapses_into_a_plain_edge():
         assert np.array_equal(x, y)
     assert np.abs(dyn.state()[1]).max() > 0.1
     assert abs(dyn.diag()["mass"] - (20 * 10 * 1.0 + 20 * 10 * 0.3)) <= 1e-12 * 260.0
+
+
+def _depth_trigger(make, cells, par, n_after=40, n_max=5000):
+    """Steps make("depth") beside make("wall") until the first step that
+    started with some cell of `cells` at depth >= par (both bitwise alike
+    up to and including it), then beside make("free") restarted from that
+    state; returns the time the wall went."""
+    dyn, wall = oracle.Sim(make("depth")), oracle.Sim(make("wall"))
+    for k in range(n_max):
+        h = dyn.state()[0] - dyn.bed()
+        fired = bool((h[cells] >= par).any())
+        assert dyn.step() == wall.step()
+        for x, y in zip(dyn.state()[:3], wall.state()[:3]):
+            assert np.array_equal(x, y), k
+        if fired:
+            break
+    else:
+        raise AssertionError("the collapse depth was never reached")
+    H, qx, qy, t = dyn.state()
+    free = oracle.Sim(make("free"))
+    free.set_state(H, qx, qy, t)
+    for _ in range(n_after):
+        assert dyn.step() == free.step()
+    for x, y in zip(dyn.state()[:3], free.state()[:3]):
+        assert np.array_equal(x, y)
+    return t
+
+
+def _cut_cells(xy, tri, xcut=20.0):
+    return np.nonzero((np.abs(xy[tri, 0] - xcut) < 1e-9).sum(axis=1) == 2)[0]
+
+
+def test_dynamic_wall_collapse_depth_inside():
+    xy, tri, seg = _cut_basin()
+    cx = xy[tri, 0].mean(axis=1)
+    H0 = np.where(cx < 10.0, 1.0, 0.4)
+    tags = np.full(len(seg), 9, np.int32)
+    bcs = {"depth": [S.BC(9, S.DYNAMIC_WALL, slope=1e30, par=0.6)], "wall": [S.BC(9, S.WALL)], "free": []}
+    cells = _cut_cells(xy, tri)
+    assert len(cells) == 20
+    t = _depth_trigger(lambda k: _scenario(xy, tri, seg, tags, bcs[k], H0), cells, 0.6)
+    # the dam-break wave reaches the cut (0.4 m on both sides at the start)
+    assert 2.0 < t < 20.0
+    # a collapse time before the depth is reached wins
+    early = oracle.Sim(_scenario(xy, tri, seg, tags, [S.BC(9, S.DYNAMIC_WALL, slope=1.0, par=0.6)], H0))
+    plain = oracle.Sim(_scenario(xy, tri, seg, tags, [S.BC(9, S.DYNAMIC_WALL, slope=1.0)], H0))
+    for _ in range(200):
+        assert early.step() == plain.step()
+    assert np.array_equal(early.state()[0], plain.state()[0])
+
+
+def test_dynamic_wall_collapse_depth_never_reached():
+    xy, tri, seg = _cut_basin()
+    cx = xy[tri, 0].mean(axis=1)
+    H0 = np.where(cx < 10.0, 1.0, 0.4)
+    tags = np.full(len(seg), 9, np.int32)
+    dyn = oracle.Sim(_scenario(xy, tri, seg, tags, [S.BC(9, S.DYNAMIC_WALL, slope=1e30, par=5.0)], H0))
+    wall = oracle.Sim(_scenario(xy, tri, seg, tags, [S.BC(9, S.WALL)], H0))
+    for _ in range(300):
+        assert dyn.step() == wall.step()
+    for x, y in zip(dyn.state()[:3], wall.state()[:3]):
+        assert np.array_equal(x, y)
+
+
+def test_dynamic_wall_collapse_depth_on_the_boundary():
+    base = S.dam_break(d=1.0, h_right=0.0)
+    xy = base.nodes[:, :2]
+    right = np.where(np.abs(xy[:, 0] - 100.0) < 1e-9)[0]
+    right = right[np.argsort(xy[right, 1])]
+    seg = np.c_[right[:-1], right[1:]].astype(np.int32)
+    bcs = {"depth": [S.BC(7, S.DYNAMIC_WALL, slope=1e30, par=0.05)], "wall": [],
+           "free": [S.BC(7, S.OUTFLOW_ZEROGRAD)]}
+    def make(k):
+        return S.Scenario(**{**base.__dict__, "bnd_seg": seg, "bnd_tag": np.full(len(seg), 7, np.int32),
+                             "bcs": bcs[k]})
+    cells = np.nonzero((np.abs(base.nodes[base.tri, 0] - 100.0) < 1e-9).sum(axis=1) == 2)[0]
+    assert len(cells) > 0
+    t = _depth_trigger(make, cells, 0.05)
+    assert t > 5.0
+    dyn = oracle.Sim(make("depth"))
+    dyn.run_until(t)
+    assert dyn.diag()["bnd_flux"] == 0.0
+    dyn.run_until(t + 5.0)
+    assert dyn.diag()["bnd_flux"] > 0.0
+
+
+def test_dynamic_wall_collapse_depth_must_not_be_negative():
+    xy, tri, seg = _cut_basin()
+    sc = _scenario(xy, tri, seg, np.full(len(seg), 9, np.int32), [S.BC(9, S.DYNAMIC_WALL, slope=1.0, par=-1.0)],
+                   np.full(len(tri), 1.0))
+    with pytest.raises(oracle.OracleError, match="collapse depth"):
+        oracle.Sim(sc)
 
 
 def test_only_walls_on_interior_edges():

@@ -88,8 +88,8 @@ typedef struct {
  *  - DYNAMIC_WALL (slope = collapse time, par = collapse depth >= 0, 0 for
  *    none): a wall before its collapse time and, with a collapse depth,
  *    until the end of the first step that starts with its cell at that
- *    depth or deeper (h = H - z; at most 8 such walls per state); zero
- *    gradient from then on.
+ *    depth or deeper (h = H - z); zero gradient from then on.  A state
+ *    created from another one's read-out starts with its walls standing.
  * On tagged interior edges (internal conditions, section "Hydrodynamic
  * BCs"): WALL makes each side a wall of its own state; DYNAMIC_WALL does so
  * until it collapses (by time, or by the depth of a cell on either side),

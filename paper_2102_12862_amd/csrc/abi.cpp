@@ -531,21 +531,14 @@ swe_status swe_state_init(const swe_mesh *m, const swe_params *params, const dou
     std::vector<BCdev> hb((size_t)std::max(n_bc, 1));
     std::vector<double> hydro;
     std::vector<size_t> hoff((size_t)std::max(n_bc, 1));
-    int n_depth_walls = 0;
     for (int b = 0; b < n_bc; b++) {
         const swe_bc &B = bcs[b];
         if (B.kind < SWE_BC_WALL || B.kind > SWE_BC_DYNAMIC_WALL) return fail(SWE_EINVAL, "unknown boundary kind");
         if (!std::isfinite(B.slope) || !std::isfinite(B.par)) return fail(SWE_EINVAL, "non-finite boundary parameter");
         hb[b] = BCdev{B.kind, 0, B.slope, 0.0, nullptr, nullptr, B.par};
         hoff[b] = hydro.size();
-        if (B.kind == SWE_BC_DYNAMIC_WALL) {
-            if (B.par < 0.0) return fail(SWE_EINVAL, "a dynamic wall's collapse depth must be >= 0");
-            if (B.par > 0.0) {
-                if (n_depth_walls == MAX_DEPTH_WALLS)
-                    return fail(SWE_EINVAL, "at most 8 dynamic walls with a collapse depth");
-                hb[b].wslot = n_depth_walls++;
-            }
-        }
+        if (B.kind == SWE_BC_DYNAMIC_WALL && B.par < 0.0)
+            return fail(SWE_EINVAL, "a dynamic wall's collapse depth must be >= 0");
         if ((B.kind == SWE_BC_INFLOW_UNIFORM || B.kind == SWE_BC_INFLOW_FROUDE || B.kind == SWE_BC_OUTFLOW_UNIFORM) &&
             !(B.slope > 0))
             return fail(SWE_EINVAL, "uniform and froude conditions need a positive slope or Froude number");
@@ -708,7 +701,6 @@ swe_status swe_state_init(const swe_mesh *m, const swe_params *params, const dou
     c.s[0].t = t0;
     for (auto &mm : c.m) mm.bits = INF_BITS;
     c.t_end = std::numeric_limits<double>::infinity();
-    for (auto &w : c.wall) w = time_key(std::numeric_limits<double>::infinity());
     *S->hctrl = c;
     S->phase = 0;
     HIP_TRY(hipMemcpyAsync(S->ctrl, S->hctrl, sizeof(Ctrl), hipMemcpyHostToDevice, s));
@@ -1350,6 +1342,11 @@ swe_status swe_autotune(swe_state *s, int32_t k, int32_t *block_size) {
     if (st) return st;
     const Ctrl saved = *s->hctrl;
     const int saved_phase = s->phase;
+    // the boundary records too: a trial step may lower a dynamic wall's
+    // collapse time (its collapse depth reached)
+    std::vector<BCdev> keepB((size_t)std::max(s->n_bc, 1));
+    HIP_TRY(hipMemcpyAsync(keepB.data(), s->bcs, sizeof(BCdev) * keepB.size(), hipMemcpyDeviceToHost, s->stream()));
+    HIP_TRY(hipStreamSynchronize(s->stream()));
     const int64_t n = s->m->H.nc;
     const size_t ub = (size_t)n * vec4_bytes(s->prec);
     const size_t ab = 2 * sizeof(double) * std::max(s->nslots, 1);
@@ -1383,6 +1380,7 @@ swe_status swe_autotune(swe_state *s, int32_t k, int32_t *block_size) {
         HIP_TRY(hipMemcpyAsync(s->slot_acc, keepA, ab, hipMemcpyDeviceToDevice, q));
         HIP_TRY(hipMemcpyAsync(s->clip_acc, keepC, cb, hipMemcpyDeviceToDevice, q));
         HIP_TRY(hipMemcpyAsync(s->ctrl, s->hctrl, sizeof(Ctrl), hipMemcpyHostToDevice, q));
+        HIP_TRY(hipMemcpyAsync(s->bcs, keepB.data(), sizeof(BCdev) * keepB.size(), hipMemcpyHostToDevice, q));
         HIP_TRY(hipStreamSynchronize(q));
         return SWE_OK;
     };
@@ -1771,13 +1769,15 @@ swe_status swe_batch_autotune(swe_batch *b, int32_t k, int32_t *block_size) {
         if (st) return st;
     }
     // every running member's current state vector, boundary accumulators,
-    // control block and launch phase, restored after each trial
+    // boundary records (a trial step may lower a dynamic wall's collapse
+    // time), control block and launch phase, restored after each trial
     struct Saved {
         swe_state *s;
         void *U = nullptr, *A = nullptr, *C = nullptr, *cur = nullptr, *curL = nullptr;
         size_t ub = 0, ab = 0, cb = 0, lb = 0;
         Ctrl c{};
         int phase = 0;
+        std::vector<BCdev> B;
     };
     std::vector<Saved> sv;
     hipStream_t q = b->stream();
@@ -1819,7 +1819,10 @@ swe_status swe_batch_autotune(swe_batch *b, int32_t k, int32_t *block_size) {
         if (x.lb) HIP_TRY(hipMemcpyAsync((char *)x.U + x.ub, x.curL, x.lb, hipMemcpyDeviceToDevice, q));
         HIP_TRY(hipMemcpyAsync(x.A, s->slot_acc, x.ab, hipMemcpyDeviceToDevice, q));
         HIP_TRY(hipMemcpyAsync(x.C, s->clip_acc, x.cb, hipMemcpyDeviceToDevice, q));
+        sv.back().B.resize((size_t)std::max(s->n_bc, 1));
+        HIP_TRY(hipMemcpyAsync(sv.back().B.data(), s->bcs, sizeof(BCdev) * sv.back().B.size(), hipMemcpyDeviceToHost, q));
     }
+    HIP_TRY(hipStreamSynchronize(q));
     auto restore = [&]() -> swe_status {
         for (auto &x : sv) {
             *x.s->hctrl = x.c;
@@ -1829,6 +1832,7 @@ swe_status swe_batch_autotune(swe_batch *b, int32_t k, int32_t *block_size) {
             HIP_TRY(hipMemcpyAsync(x.s->slot_acc, x.A, x.ab, hipMemcpyDeviceToDevice, q));
             HIP_TRY(hipMemcpyAsync(x.s->clip_acc, x.C, x.cb, hipMemcpyDeviceToDevice, q));
             HIP_TRY(hipMemcpyAsync(x.s->ctrl, x.s->hctrl, sizeof(Ctrl), hipMemcpyHostToDevice, q));
+            HIP_TRY(hipMemcpyAsync(x.s->bcs, x.B.data(), sizeof(BCdev) * x.B.size(), hipMemcpyHostToDevice, q));
         }
         HIP_TRY(hipStreamSynchronize(q));
         b->phase = bphase;

@@ -391,18 +391,18 @@ template <typename V> __device__ __forceinline__ void store_agent(V *p, V v) {
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// A dynamic wall (section "Hydrodynamic BCs", internal and standard
-// conditions) stands at time t before its collapse time and, if it has a
-// collapse depth, before the end of the first step that saw a cell next to
-// it at that depth.
-__device__ __forceinline__ bool wall_stands(Ctrl *c, const BCdev &B, double t) {
-    return t < B.slope && (B.wslot < 0 || t < key_time(load_agent(&c->wall[B.wslot])));
-}
-// A standing dynamic wall with a collapse depth next to a cell of depth h
-// at t^n: from t_next = t^n + dt on it is gone.  Every pass of a step that
-// sees it asks for the same time, and the step itself still sees the wall.
-__device__ __forceinline__ void wall_trigger(Ctrl *c, const BCdev &B, double h, double t_next) {
-    if (B.wslot >= 0 && h >= B.par) atomicMin(&c->wall[B.wslot], time_key(t_next));
+// A dynamic wall (section "Hydrodynamic BCs") with a collapse depth: the
+// step that starts with a cell next to it at that depth or deeper lowers the
+// wall's collapse time to its own end time t_next (an atomic min on the
+// device record), so every block of that step still sees the wall and the
+// steps from t_next on do not.
+__device__ __forceinline__ void wall_trigger(const BCdev &B, double h, double t_next) {
+    if (B.par > 0.0 && h >= B.par) {
+        // formed here: hoisted out of the edge loop the value would hold
+        // registers through it
+        __asm__ volatile("" : "+v"(t_next));
+        __hip_atomic_fetch_min(const_cast<double *>(&B.slope), t_next, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
 }
 
 // Time level of phase p as this step sees it.
@@ -852,9 +852,9 @@ __device__ __forceinline__ void tile_edges(const Inst<T> &I, TileLds<T, TILE> &S
             if (iw) {
                 const int bc = I.iw_bc[iw - 1];
                 const int bk = bc >= 0 ? I.bcs[bc].kind : -1;
-                if (bk == BC_WALL || (bk == BC_DYNWALL && wall_stands(I.ctrl, I.bcs[bc], t)) || bk == BC_HQ) {
+                if (bk == BC_WALL || (bk == BC_DYNWALL && t < I.bcs[bc].slope) || bk == BC_HQ) {
                     const double dw = Ha - double(sa.w);
-                    if (bk == BC_DYNWALL) wall_trigger(I.ctrl, I.bcs[bc], dw, t_cand);
+                    if (bk == BC_DYNWALL) wall_trigger(I.bcs[bc], dw, t_cand);
                     ha = dw < H_DRY ? T(0) : T(dw);
                     hL = hR = ha;
                     unL = una;
@@ -887,12 +887,12 @@ __device__ __forceinline__ void tile_edges(const Inst<T> &I, TileLds<T, TILE> &S
             unR = -una;
             utR = uta;
             T hg, ung;
-            const bool gone = bkind == BC_DYNWALL && !wall_stands(I.ctrl, I.bcs[bi], t);
-            if (bkind == BC_DYNWALL && !gone) wall_trigger(I.ctrl, I.bcs[bi], da, t_cand);
-            if (bkind == BC_OUTFLOW || gone) {
-                // transmissive (a dynamic wall once it is gone too)
+            if (bkind == BC_OUTFLOW || (bkind == BC_DYNWALL && t >= I.bcs[bi].slope)) {
+                // transmissive (a dynamic wall after its collapse time too)
                 unR = una;
                 open = true;
+            } else if (bkind == BC_DYNWALL) {
+                wall_trigger(I.bcs[bi], da, t_cand);
             } else if (bkind == BC_INFLOW || bkind == BC_FROUDE) {
                 const V2<T> cp = I.cellp[tile * TILE + a];
                 const BCdev &B = I.bcs[bi];
@@ -1602,7 +1602,7 @@ __global__ void __launch_bounds__(TILE) k_diffuse(Inst<T> I, int phase) {
             // standing walls and rating curves exchange nothing by diffusion
             const int bc = I.iw_bc[iw - 1];
             const int bk = bc >= 0 ? I.bcs[bc].kind : -1;
-            if (bk == BC_WALL || (bk == BC_DYNWALL && wall_stands(I.ctrl, I.bcs[bc], L.t)) || bk == BC_HQ) closed = true;
+            if (bk == BC_WALL || (bk == BC_DYNWALL && L.t < I.bcs[bc].slope) || bk == BC_HQ) closed = true;
         }
         if (closed) {
             diff_mirror<T, TILE, NS>(I, S, a, ka, l, nx, ny);

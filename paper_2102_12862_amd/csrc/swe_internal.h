@@ -75,19 +75,17 @@ enum : int { SRC_EXACT = 0, SRC_AVAILABLE = 1, SRC_INFINITY = 2 };
 // friction closures, numbered as SWE_FRICTION_* in swe.h
 enum : int { FR_MANNING = 0, FR_STRICKLER = 1, FR_CHEZY = 2, FR_BEZZOLA = 3 };
 constexpr int MAX_BC = 64;
-// dynamic walls with a collapse depth, per state
-constexpr int MAX_DEPTH_WALLS = 8;
 
 // Boundary condition record on the device.
 struct BCdev {
     int kind;
     int npts;
-    double slope;    // energy slope, Froude number, crest elevation or collapse time
+    double slope;    // energy slope, Froude number, crest elevation or collapse time (a
+                     // dynamic wall's is lowered on the device when its collapse depth is reached)
     double length;   // summed length of the edges carrying this condition
     const double *t; // series times (surface elevations of an h-Q table)
     const double *Q; // discharge, or surface elevation (zhydrograph)
-    double par;      // Poleni factor (weir) or collapse depth (dynamic wall)
-    int wslot = -1;  // a dynamic wall with a collapse depth: its latch in the control block
+    double par;      // Poleni factor (weir) or collapse depth (dynamic wall; 0: none)
 };
 
 // Per-state control block, triple-buffered by step phase p = step % 3.
@@ -115,27 +113,11 @@ struct alignas(128) Ctrl {
     double t_end;             // steps are capped to land on t_end
     int flags;                // FLAG_* bits
     int pad0;
-    // per dynamic wall with a collapse depth: time_key of the time it is
-    // gone from (of +inf while no step has seen a cell next to it at that
-    // depth); lowered with an atomic min by the step that sees one, to that
-    // step's end time, so the wall stands for the whole of that step
-    unsigned long long wall[MAX_DEPTH_WALLS];
-    double pad1[14 - MAX_DEPTH_WALLS];
+    double pad1[14];
 };
 static_assert(sizeof(Ctrl) == 7 * 128, "Ctrl layout");
 
 constexpr unsigned long long INF_BITS = 0x7FF0000000000000ull;
-
-// Order-preserving key of a double time: unsigned comparison of the keys is
-// the comparison of the times (sign bit set for t >= 0, all bits flipped for
-// t < 0), so an atomic min over keys keeps the earliest time.
-__host__ __device__ inline unsigned long long time_key(double t) {
-    const unsigned long long b = __builtin_bit_cast(unsigned long long, t);
-    return (b >> 63) ? ~b : (b | 0x8000000000000000ull);
-}
-__host__ __device__ inline double key_time(unsigned long long k) {
-    return __builtin_bit_cast(double, (k >> 63) ? (k & 0x7FFFFFFFFFFFFFFFull) : ~k);
-}
 
 // Everything one kernel needs about one state.
 template <typename T> struct Inst {

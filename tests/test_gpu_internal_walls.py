@@ -168,10 +168,35 @@ def test_dynamic_wall_collapse_depth_api(swe):
     m = swe.Mesh(sc.nodes, sc.tri, sc.bnd_seg, sc.bnd_tag)
     with pytest.raises(swe.SweError, match="collapse depth"):
         swe.State(m, sc, precision=swe.FP64)
-    many = S.Scenario(**{**sc.__dict__, "bcs": [S.BC(100 + k, S.DYNAMIC_WALL, slope=1.0, par=0.5)
-                                                for k in range(9)]})
-    with pytest.raises(swe.SweError, match="at most 8"):
-        swe.State(m, many, precision=swe.FP64)
+
+
+def test_dynamic_wall_collapse_depth_survives_autotune(swe):
+    # the autotuners' trial steps, from t = 1 s, reach the collapse depth at
+    # the cut at t = 3.27 s; the runs, with a sink set after the trials,
+    # reach it only at t = 3.50 s: the wall's record must come back from
+    # the trials as it was
+    sc = _basin(S.BC(9, S.DYNAMIC_WALL, slope=1e30, par=0.6))
+    region = np.where(sc.centroids()[:, 0] < 20.0, 0, -1)
+    sink = [S.Source(S.SRC_AVAILABLE, S.SRC_DISCHARGE, t=np.array([0.0, 1e9]), v=np.array([-10.0, -10.0]))]
+    st = gpu_state(sc, swe.FP64, block_size=256)
+    other = gpu_state(sc, swe.FP64)
+    sim = oracle.Sim(sc)
+    for x in (st, other, sim):
+        x.run_until(1.0)
+    st.autotune(64)
+    b = swe.Batch(swe.FP64, device=device())
+    b.add(other, 1e9)
+    b.autotune(64)
+    b.close()
+    for x in (st, other, sim):
+        x.set_sources(region, sink)
+    for k in range(80):
+        dg, do = st.step(), sim.step()
+        assert abs(dg - do) <= 1e-13 * do, (k, dg, do)
+        other.step()
+    assert sim.t > 4.0
+    compare(st, sim, FP64_TOL)
+    compare(other, sim, FP64_TOL)
 
 
 def test_only_walls_on_interior_edges(swe):

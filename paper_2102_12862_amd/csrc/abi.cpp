@@ -30,6 +30,21 @@ swe_status fail(swe_status code, const std::string &msg) {
     return code;
 }
 
+// The FP32 surface's 16-bit low part, as the kernels code it: the rest
+// H - hi in units of 2^(e-40) for hi = m 2^e, m in [1/2, 1) (2^-16 of an
+// ulp of hi), rounded to nearest and clamped to the int16 range.
+int16_t lo_code_host(float hi, double rest) {
+    int e = 0;
+    (void)std::frexp(hi, &e);
+    const double k = std::nearbyint(std::ldexp(rest, 40 - e));
+    return int16_t(std::fmin(std::fmax(k, -32768.0), 32767.0));
+}
+double lo_value_host(float hi, int16_t k) {
+    int e = 0;
+    (void)std::frexp(hi, &e);
+    return std::ldexp(double(k), e - 40);
+}
+
 #define HIP_TRY(expr)                                                                     \
     do {                                                                                  \
         hipError_t _e = (expr);                                                           \
@@ -161,7 +176,7 @@ struct swe_state {
     Ctrl *ctrl = nullptr;
     double2 *partials = nullptr;
     double *mass_out = nullptr;
-    float *L0 = nullptr, *L1 = nullptr;  // FP32: low parts of the surface (ping-pong with U0/U1)
+    int16_t *L0 = nullptr, *L1 = nullptr;  // FP32: 16-bit low parts of the surface (ping-pong with U0/U1)
     double *clip_acc = nullptr;  // per 64-cell group: compensated clip volume
     int ngroups = 0;
     Ctrl *hctrl = nullptr;    // pinned host copy of the control block
@@ -302,14 +317,14 @@ struct swe_state {
         HIP_TRY(hipStreamSynchronize(stream()));
         return SWE_OK;
     }
-    // FP32: the low parts of the current level's surfaces (device order) into
-    // lo; FP64: lo left empty
-    swe_status read_lo(std::vector<float> &lo) {
+    // FP32: the codes of the low parts of the current level's surfaces
+    // (device order) into lo; FP64: lo left empty
+    swe_status read_lo(std::vector<int16_t> &lo) {
         lo.clear();
         if (prec != SWE_FP32) return SWE_OK;
         lo.resize((size_t)m->H.nc);
-        const float *src = lvl().cur ? L1 : L0;
-        HIP_TRY(hipMemcpyAsync(lo.data(), src, lo.size() * sizeof(float), hipMemcpyDeviceToHost, stream()));
+        const int16_t *src = lvl().cur ? L1 : L0;
+        HIP_TRY(hipMemcpyAsync(lo.data(), src, lo.size() * sizeof(int16_t), hipMemcpyDeviceToHost, stream()));
         HIP_TRY(hipStreamSynchronize(stream()));
         return SWE_OK;
     }
@@ -458,8 +473,8 @@ int64_t swe_state_footprint(const swe_mesh *m, int32_t precision) {
     if (!m) return 0;
     const int64_t n = m->H.nc, ns = (int64_t)m->H.slot_tag.size();
     const int64_t v4 = (int64_t)vec4_bytes(precision);
-    // FP32 adds the low parts of the surface (two buffers of 4 bytes per cell)
-    const int64_t lo = precision == SWE_FP32 ? 2 * n * 4 : 0;
+    // FP32 adds the low parts of the surface (two buffers of 2 bytes per cell)
+    const int64_t lo = precision == SWE_FP32 ? 2 * n * 2 : 0;
     const int64_t state = 2 * n * v4 + lo + n * v4 / 2 + ns * (4 + 16) + (int64_t)sizeof(Ctrl) + MASS_BLOCKS * 16 +
                           4096;
     // tile edge list (about 1.7 edges per cell: record + other-cell id) and FP64 areas
@@ -628,8 +643,8 @@ swe_status swe_state_init(const swe_mesh *m, const swe_params *params, const dou
     S->U0 = S->mem.alloc((size_t)n * v4);
     S->U1 = S->mem.alloc((size_t)n * v4);
     if (prec == SWE_FP32) {
-        S->L0 = (float *)S->mem.alloc((size_t)std::max<int64_t>(n, 1) * sizeof(float));
-        S->L1 = (float *)S->mem.alloc((size_t)std::max<int64_t>(n, 1) * sizeof(float));
+        S->L0 = (int16_t *)S->mem.alloc((size_t)std::max<int64_t>(n, 1) * sizeof(int16_t));
+        S->L1 = (int16_t *)S->mem.alloc((size_t)std::max<int64_t>(n, 1) * sizeof(int16_t));
         if (!S->L0 || !S->L1) return fail(SWE_ENOMEM, "device allocation failed (state)");
     }
     S->cellp = S->mem.alloc((size_t)n * v4 / 2);
@@ -664,11 +679,11 @@ swe_status swe_state_init(const swe_mesh *m, const swe_params *params, const dou
         using T = decltype(tag);
         std::vector<V4<T>> u((size_t)n);
         std::vector<V2<T>> cp((size_t)n);
-        std::vector<float> lo(sizeof(T) == 4 ? (size_t)n : 0);
+        std::vector<int16_t> lo(sizeof(T) == 4 ? (size_t)n : 0);
         for (int64_t p = 0; p < n; p++) {
             u[p].x = T(H[p]);
             // FP32 stores the surface as hi + lo
-            if (sizeof(T) == 4) lo[p] = float(H[p] - double(u[p].x));
+            if (sizeof(T) == 4) lo[p] = lo_code_host(float(u[p].x), H[p] - double(u[p].x));
             u[p].y = T(qx[p]);
             u[p].z = T(qy[p]);
             u[p].w = T(M.zb[p]);
@@ -679,8 +694,8 @@ swe_status swe_state_init(const swe_mesh *m, const swe_params *params, const dou
         HIP_TRY(hipMemcpyAsync(S->U0, u.data(), u.size() * sizeof(V4<T>), hipMemcpyHostToDevice, s));
         HIP_TRY(hipMemcpyAsync(S->U1, u.data(), u.size() * sizeof(V4<T>), hipMemcpyHostToDevice, s));
         if (!lo.empty()) {
-            HIP_TRY(hipMemcpyAsync(S->L0, lo.data(), lo.size() * sizeof(float), hipMemcpyHostToDevice, s));
-            HIP_TRY(hipMemcpyAsync(S->L1, lo.data(), lo.size() * sizeof(float), hipMemcpyHostToDevice, s));
+            HIP_TRY(hipMemcpyAsync(S->L0, lo.data(), lo.size() * sizeof(int16_t), hipMemcpyHostToDevice, s));
+            HIP_TRY(hipMemcpyAsync(S->L1, lo.data(), lo.size() * sizeof(int16_t), hipMemcpyHostToDevice, s));
         }
         HIP_TRY(hipMemcpyAsync(S->cellp, cp.data(), cp.size() * sizeof(V2<T>), hipMemcpyHostToDevice, s));
         HIP_TRY(hipStreamSynchronize(s));
@@ -709,8 +724,8 @@ swe_status swe_state_init(const swe_mesh *m, const swe_params *params, const dou
         using T = decltype(tag);
         I.U0 = dev_ptr((V4<T> *)S->U0);
         I.U1 = dev_ptr((V4<T> *)S->U1);
-        I.L0 = dev_ptr((T *)S->L0);
-        I.L1 = dev_ptr((T *)S->L1);
+        I.L0 = dev_ptr(S->L0);
+        I.L1 = dev_ptr(S->L1);
         const TileGeom &tg = m->geom[prec][tile_index(S->tile)];
         I.cellp = dev_ptr((const V2<T> *)S->cellp);
         tg.bind(I);
@@ -839,14 +854,14 @@ swe_status swe_state_read(const swe_state *cs, double *H, double *h, double *qx,
     auto rd = [&](auto tag) -> swe_status {
         using T = decltype(tag);
         std::vector<V4<T>> u((size_t)n);
-        std::vector<float> lo;
+        std::vector<int16_t> lo;
         HIP_TRY(hipMemcpyAsync(u.data(), src, u.size() * sizeof(V4<T>), hipMemcpyDeviceToHost, s->stream()));
         swe_status r = s->read_lo(lo);
         if (r) return r;
         for (int64_t i = 0; i < n; i++) {
             const int32_t d = M.inv[i];
             const V4<T> &v = u[d];
-            const double Hs = lo.empty() ? double(v.x) : double(v.x) + double(lo[d]);
+            const double Hs = lo.empty() ? double(v.x) : double(v.x) + lo_value_host(float(v.x), lo[d]);
             if (H) H[i] = Hs;
             if (h) h[i] = Hs - double(v.w);
             if (qx) qx[i] = double(v.y);
@@ -940,7 +955,7 @@ swe_status swe_state_set_scalars(swe_state *s, int32_t ns, const double *phi0, c
     auto up = [&](auto tag) -> swe_status {
         using T = decltype(tag);
         std::vector<V4<T>> u((size_t)n);
-        std::vector<float> lo;
+        std::vector<int16_t> lo;
         HIP_TRY(hipMemcpyAsync(u.data(), cur, u.size() * sizeof(V4<T>), hipMemcpyDeviceToHost, q));
         swe_status r = s->read_lo(lo);
         if (r) return r;
@@ -949,7 +964,7 @@ swe_status swe_state_set_scalars(swe_state *s, int32_t ns, const double *phi0, c
             for (int64_t i = 0; i < n; i++) {
                 const int32_t d = M.inv[i];
                 const V4<T> &v = u[d];
-                const double h = (lo.empty() ? double(v.x) : double(v.x) + double(lo[d])) - double(v.w);
+                const double h = (lo.empty() ? double(v.x) : double(v.x) + lo_value_host(float(v.x), lo[d])) - double(v.w);
                 const double p = phi0 ? phi0[(size_t)c * n + i] : 0.0;
                 qh[(size_t)c * n + M.inv[i]] = h > 0.0 ? T(h * p) : T(0);
             }
@@ -1351,7 +1366,7 @@ swe_status swe_autotune(swe_state *s, int32_t k, int32_t *block_size) {
     const size_t ub = (size_t)n * vec4_bytes(s->prec);
     const size_t ab = 2 * sizeof(double) * std::max(s->nslots, 1);
     const size_t cb = 2 * sizeof(double) * std::max(s->ngroups, 1);
-    const size_t lb = s->prec == SWE_FP32 ? (size_t)n * sizeof(float) : 0;
+    const size_t lb = s->prec == SWE_FP32 ? (size_t)n * sizeof(int16_t) : 0;
     void *keepU = s->mem.alloc(ub + lb);  // the state, then (FP32) the low parts of the surface
     void *keepA = s->mem.alloc(ab);
     void *keepC = s->mem.alloc(cb);
@@ -1803,7 +1818,7 @@ swe_status swe_batch_autotune(swe_batch *b, int32_t k, int32_t *block_size) {
         x.phase = s->phase;
         x.cur = x.c.s[s->phase].cur ? s->U1 : s->U0;
         x.curL = x.c.s[s->phase].cur ? (void *)s->L1 : (void *)s->L0;
-        x.lb = s->prec == SWE_FP32 ? (size_t)s->m->H.nc * sizeof(float) : 0;
+        x.lb = s->prec == SWE_FP32 ? (size_t)s->m->H.nc * sizeof(int16_t) : 0;
         x.ub = (size_t)s->m->H.nc * vec4_bytes(s->prec);
         x.ab = 2 * sizeof(double) * std::max(s->nslots, 1);
         x.cb = 2 * sizeof(double) * std::max(s->ngroups, 1);

@@ -56,15 +56,23 @@ template <> __device__ __forceinline__ double4 make4<double>(double a, double b,
 // FP64), FP64 states as hi alone.
 __device__ __forceinline__ double surface(double hi, double /*lo*/) { return hi; }
 __device__ __forceinline__ double surface(float hi, float lo) { return double(hi) + double(lo); }
-// Splits an FP64 surface into what the state stores: FP32 hi = the nearest
-// float, lo = the nearest float to the rest; FP64 keeps it whole.
-__device__ __forceinline__ void split_surface(double H, double &hi, double &lo) {
-    hi = H;
-    lo = 0.0;
+
+// FP32 states store hi = the nearest float to the surface and the rest
+// H - hi (at most half an ulp of hi) as a 16-bit integer k in units of
+// 2^-16 ulp(hi): ulp(hi) = 2^(e-24) for hi = m 2^e, m in [1/2, 1), so the
+// unit is 2^(e-40) and |k| <= 2^15 (the one code past the int16 range,
+// +2^15, is clamped).  The surface so resolves to about 2^-40 of itself at
+// 2 bytes per cell.  lo_value decodes exactly; lo_code rounds to nearest.
+__device__ __forceinline__ int lo_unit_exp(float hi) { return __builtin_amdgcn_frexp_expf(hi) - 40; }
+__device__ __forceinline__ float lo_value(float hi, int16_t k) { return ldexpf(float(k), lo_unit_exp(hi)); }
+__device__ __forceinline__ int16_t lo_code(float hi, double rest) {
+    const double k = rint(ldexp(rest, -lo_unit_exp(hi)));
+    return int16_t(fmin(fmax(k, -32768.0), 32767.0));
 }
-__device__ __forceinline__ void split_surface(double H, float &hi, float &lo) {
-    hi = float(H);
-    lo = float(H - double(hi));
+// The decoded low part of cell i's surface (FP64: none).
+template <typename T> __device__ __forceinline__ T low_part(gptr<const int16_t> L, int i, T hi) {
+    if constexpr (IS32<T>) return lo_value(hi, L[i]);
+    else return T(0);
 }
 
 // Division and square root.  FP64 uses IEEE-correct operations so that every
@@ -702,7 +710,7 @@ __device__ __forceinline__ void tile_edges(const Inst<T> &I, TileLds<T, TILE> &S
     if (i < I.n) {
         const V4<T> s = src[i];
         own = s;
-        if constexpr (IS32<T>) S.lo[c] = (cur ? I.L1 : I.L0)[i];
+        if constexpr (IS32<T>) S.lo[c] = low_part<T>(cur ? I.L1 : I.L0, i, s.x);
         // velocity only above the minimum depth (the fluxes see the surface's
         // high part)
         const double hd = double(s.x) - double(s.w);
@@ -1139,7 +1147,7 @@ __device__ __forceinline__ CandT<T> tile_update(const Inst<T> &I, const TileLds<
     const int i = tile * TILE + c;
     if (i >= I.n) return IS32<T> ? T(0) : T(INFINITY);
     const gptr<V4<T>> __restrict__ dst = cur ? I.U0 : I.U1;
-    const gptr<T> __restrict__ ldst = cur ? I.L0 : I.L1;
+    const gptr<int16_t> __restrict__ ldst = cur ? I.L0 : I.L1;
     // FP32: the low part of the cell's surface (staged in LDS with the state)
     const T slo = IS32<T> ? S.lo[c] : T(0);
     const double h_min = I.h_min;
@@ -1235,10 +1243,10 @@ __device__ __forceinline__ CandT<T> tile_update(const Inst<T> &I, const TileLds<
         Hn = Hn + (znd - double(s.w));
     }
     if (!isfinite(Hn) || !isfinite(qx) || !isfinite(qy) || !isfinite(zn)) atomicOr(&I.ctrl->flags, FLAG_NONFINITE);
-    T Hhi, Hlo;
-    split_surface(Hn, Hhi, Hlo);
+    // FP32: hi = the nearest float, the rest in the 16-bit low part
+    const T Hhi = T(Hn);
     dst[i] = make4<T>(Hhi, qx, qy, zn);
-    if constexpr (IS32<T>) ldst[i] = Hlo;
+    if constexpr (IS32<T>) ldst[i] = lo_code(Hhi, Hn - double(Hhi));
     if constexpr (NS > 0) {
         const gptr<T> __restrict__ qdst = cur ? I.Q0 : I.Q1;
         const bool dry = !(Hn - double(s.w) > 0.0);
@@ -1330,7 +1338,7 @@ __global__ void __launch_bounds__(TILE, (WAVES_PER_SIMD<T, TILE>)) k_drain(Inst<
     if (i >= I.n) return;
     const double o0 = double(S.c[0][0][c]), o1 = double(S.c[0][1][c]), o2 = double(S.c[0][2][c]);
     const double out = (o0 > 0.0 ? o0 : 0.0) + (o1 > 0.0 ? o1 : 0.0) + (o2 > 0.0 ? o2 : 0.0);
-    const double h = surface(own.x, IS32<T> ? (L.cur ? I.L1 : I.L0)[i] : T(0)) - double(own.w);
+    const double h = surface(own.x, low_part<T>(L.cur ? I.L1 : I.L0, i, own.x)) - double(own.w);
     const double vol = (h > 0.0 ? h : 0.0) * I.area[i];
     const double leave = out * L.dt;
     I.theta[i] = T(leave > vol ? vol / leave : 1.0);
@@ -1452,7 +1460,7 @@ __global__ void __launch_bounds__(TILE) k_dt_init(Inst<T> I, int phase) {
     const int i = tile * TILE + threadIdx.x;
     if (i < I.n) {
         const V2<T> cp = I.cellp[i];
-        const T slo = IS32<T> ? (L.cur ? I.L1 : I.L0)[i] : T(0);
+        const T slo = low_part<T>(L.cur ? I.L1 : I.L0, i, s.x);
         cand = tile_candidate<T, TILE>(I, S, threadIdx.x, cp.x, surface(s.x, slo), s.y, s.z, s.w);
         if (I.diff) {
             T gx[3], gy[3], gl[3];
@@ -1700,7 +1708,7 @@ __global__ void __launch_bounds__(TILE) k_diffuse(Inst<T> I, int phase) {
         const gptr<T> __restrict__ qdst = L.cur ? I.Q0 : I.Q1;
         const gptr<V2<T>> __restrict__ pdst = (gptr<V2<T>>)(L.cur ? I.P0 : I.P1);
         const V4<T> sn = udst[i];
-        const T lon = IS32<T> ? (L.cur ? I.L0 : I.L1)[i] : T(0);
+        const T lon = low_part<T>(L.cur ? I.L0 : I.L1, i, sn.x);
         const double Hn = surface(sn.x, lon);
         const bool dry = !(Hn - double(sn.w) > 0.0);
         const bool active = S.hk[0][c] > T(0);
@@ -1814,11 +1822,11 @@ template <typename T>
 __global__ void __launch_bounds__(MASS_THREADS) k_mass_partial(Inst<T> I, double2 *partials, int phase) {
     const int cur = I.ctrl->s[phase].cur;
     const gptr<const V4<T>> src = cur ? I.U1 : I.U0;
-    const gptr<const T> lsrc = cur ? I.L1 : I.L0;
+    const gptr<const int16_t> lsrc = cur ? I.L1 : I.L0;
     double s = 0.0, c = 0.0;
     for (int i = blockIdx.x * MASS_THREADS + threadIdx.x; i < I.n; i += MASS_BLOCKS * MASS_THREADS) {
         const V4<T> u = src[i];
-        neumaier(s, c, (surface(u.x, IS32<T> ? lsrc[i] : T(0)) - double(u.w)) * I.area[i]);
+        neumaier(s, c, (surface(u.x, low_part<T>(lsrc, i, u.x)) - double(u.w)) * I.area[i]);
     }
     const double2 r = block_csum(make_double2(s, c));
     if (threadIdx.x == 0) partials[blockIdx.x] = r;

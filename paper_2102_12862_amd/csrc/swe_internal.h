@@ -123,10 +123,11 @@ constexpr unsigned long long INF_BITS = 0x7FF0000000000000ull;
 template <typename T> struct Inst {
     gptr<V4<T>> U0;
     gptr<V4<T>> U1;
-    // FP32: the low part of each cell's surface, ping-pong with U0/U1 (the
-    // surface is hi + lo); unused in FP64
-    gptr<T> L0;
-    gptr<T> L1;
+    // FP32: the low part of each cell's surface as a 16-bit multiple of
+    // 2^-16 ulp(hi), ping-pong with U0/U1 (the surface is hi + lo); unused
+    // in FP64
+    gptr<int16_t> L0;
+    gptr<int16_t> L1;
     gptr<const V2<T>> cellp;    // (|cell| in FP64, 1/|cell| in FP32; friction coefficient)
     gptr<const Edge<T>> edges;  // tile edge lists
     gptr<const int> ew1;        // per edge: other cell's device id or boundary slot

@@ -302,7 +302,7 @@ def timed_steps_after(st, dev, steps, warmup):
     return timed_steps(st, dev, steps, warmup)
 
 
-def bench_batched(n_members=64, rounds=8, k=16, t_end=1800.0):
+def bench_batched(n_members=64, rounds=8, k=16, t_end=1800.0, horizon=True):
     """Batched ensemble: members of the lake generator (jittered-lattice mesh
     for generation speed) with log-uniform sizes, each fed by its own
     hydrograph, stepped together by one persistent kernel per step (tile
@@ -310,7 +310,8 @@ def bench_batched(n_members=64, rounds=8, k=16, t_end=1800.0):
     after another through the single-solve API for the same number of steps.
     Then the whole ensemble run on to its horizon t_end (members finish at
     their own step counts), with the errors of the smallest member against
-    the oracle at t_end."""
+    the oracle at t_end (horizon=False skips that part, so that a profile of
+    the run holds the timed steps only)."""
     import torch
     import oracle
     import swe_inputs as S
@@ -340,20 +341,26 @@ def bench_batched(n_members=64, rounds=8, k=16, t_end=1800.0):
     ms_b = ev[0].elapsed_time(ev[rounds])
     chunk = [1e3 * ev[i].elapsed_time(ev[i + 1]) / k for i in range(rounds)]
     # on to the horizon
-    t0 = time.perf_counter()
-    while batch.step(64):
-        pass
-    run_wall = time.perf_counter() - t0
-    member_steps = [int(st.mass()["steps"]) for st in states]
-    run_updates = sum(n * m.n_cells for n, m in zip(member_steps, members))
-    small = int(np.argmin([m.n_cells for m in members]))
-    got = states[small].read()
+    horizon_out, errs_out = None, None
+    if horizon:
+        t0 = time.perf_counter()
+        while batch.step(64):
+            pass
+        run_wall = time.perf_counter() - t0
+        member_steps = [int(st.mass()["steps"]) for st in states]
+        run_updates = sum(n * m.n_cells for n, m in zip(member_steps, members))
+        small = int(np.argmin([m.n_cells for m in members]))
+        got = states[small].read()
+        sim = oracle.Sim(members[small], omp=True)
+        sim.run_until(got["t"])
+        errs, _ = errors(got, sim)
+        horizon_out = {"t_end": t_end, "wall_s": run_wall, "member_steps_min": min(member_steps),
+                       "member_steps_max": max(member_steps), "cell_updates": run_updates,
+                       "cell_updates_per_s": run_updates / run_wall}
+        errs_out = {"member_cells": members[small].n_cells, "t": got["t"], **{kk: float(v) for kk, v in errs.items()}}
     batch.close()
     for st in states:
         st.close()
-    sim = oracle.Sim(members[small], omp=True)
-    sim.run_until(got["t"])
-    errs, _ = errors(got, sim)
     log(f"[bench] batched: {1e3 * ms_b / steps:.1f} us per step of all members; members one after another")
     # one after another
     states = [swe.State(me, m, precision=swe.FP32, steps_per_graph=k) for me, m in zip(meshes, members)]
@@ -381,11 +388,7 @@ def bench_batched(n_members=64, rounds=8, k=16, t_end=1800.0):
                          "frac": achieved / HBM_PEAK_GBS, "algorithmic_bytes_per_cell": ALGO_BYTES["fp32"],
                          "traffic": measured_traffic(f"batched_ensemble_{n_members}", "fp32", tile, batched=True),
                          "kernel": f"k_step_batched<float, {tile}, false>"},
-            "run_to_horizon": {"t_end": t_end, "wall_s": run_wall, "member_steps_min": min(member_steps),
-                               "member_steps_max": max(member_steps), "cell_updates": run_updates,
-                               "cell_updates_per_s": run_updates / run_wall},
-            "errors_vs_oracle": {"member_cells": members[small].n_cells, "t": got["t"],
-                                 **{kk: float(v) for kk, v in errs.items()}}}
+            "run_to_horizon": horizon_out, "errors_vs_oracle": errs_out}
 
 
 def _gen(args):
@@ -476,6 +479,8 @@ def main():
     ap.add_argument("--serving-requests", type=int, default=48, help="requests per arrival rate")
     ap.add_argument("--serving-long", type=int, default=512,
                     help="requests of the long served trace at 64 per second (0: none)")
+    ap.add_argument("--no-batched-horizon", action="store_true",
+                    help="skip running the batched ensemble on to its horizon (for profiles of the timed steps)")
     ap.add_argument("--batched-rounds", type=int, default=8,
                     help="timed rounds of 16 steps of the batched ensemble (and of its one-after-another baseline)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
@@ -606,7 +611,8 @@ def main():
                 log(f"[bench] {ns} species: {variants[f'{wet.name}_{args.precision}_species{ns}']}")
     if want("batched"):
         log("[bench] batched ensemble")
-        variants["batched_ensemble_fp32"] = bench_batched(rounds=args.batched_rounds)
+        variants["batched_ensemble_fp32"] = bench_batched(rounds=args.batched_rounds,
+                                                          horizon=not args.no_batched_horizon)
         log(f"[bench] batched: {variants['batched_ensemble_fp32']}")
     if want("serving"):
         log("[bench] serving traces")

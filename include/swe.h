@@ -125,7 +125,13 @@ typedef struct {
     double par;       /* Poleni factor of a weir, collapse depth [m] of a dynamic wall */
 } swe_bc;
 
-enum { SWE_FP64 = 0, SWE_FP32 = 1 };        /* precision (double is the paper's default) */
+/* Precision (section "Parallelization Strategy and Computational Backends":
+ * double by default, single optional).  FP32 states store the discharges
+ * and the bed in FP32 and the water surface as an FP32 high part plus a
+ * 16-bit low part (about 40 significant bits, so that small increments are
+ * not rounded away); depth tests, time, the time step and the tallies stay
+ * in FP64. */
+enum { SWE_FP64 = 0, SWE_FP32 = 1 };
 /* Friction closures (eq. friction_closure, Table friction_closure): the
  * per-cell parameter given to swe_state_init is Manning n [s m^-1/3],
  * Strickler k_str [m^1/3 s^-1], Chezy K_s [m] or Bezzola y_R [m]; 0 means no

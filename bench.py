@@ -303,8 +303,8 @@ def timed_steps_after(st, dev, steps, warmup):
 
 
 def bench_batched(n_members=64, rounds=8, k=16, t_end=1800.0, horizon=True):
-    """Batched ensemble: members of the lake generator (jittered-lattice mesh
-    for generation speed) with log-uniform sizes, each fed by its own
+    """Batched ensemble: members of the lake generator (its 28-degree
+    Poisson-disk Delaunay meshes) with log-uniform sizes, each fed by its own
     hydrograph, stepped together by one persistent kernel per step (tile
     chosen by the batched autotuner); against the same members stepped one
     after another through the single-solve API for the same number of steps.
@@ -318,8 +318,8 @@ def bench_batched(n_members=64, rounds=8, k=16, t_end=1800.0, horizon=True):
     from gpu_util import cached, device, errors
     from paper_2102_12862_amd import swe
     sizes = S.ensemble_sizes(n_members)
-    members = parallel_generate([("ens_lattice", S.ensemble_member, (k, int(n)), {"mesh": "lattice"})
-                                 for k, n in enumerate(sizes)])
+    members = parallel_generate([("ens", S.ensemble_member, (k, int(n)), {}) for k, n in enumerate(sizes)],
+                                workers=16)
     dev = device()
     meshes = [swe.Mesh(m.nodes, m.tri, m.bnd_seg, m.bnd_tag, device=dev) for m in members]
     total = sum(m.n_cells for m in members)

@@ -115,9 +115,10 @@ def test_rain_on_a_closed_basin(swe, prec):
     r = st.read()
     assert np.all(r["qx"] == 0.0) and np.all(r["qy"] == 0.0)
     assert np.ptp(r["H"]) == 0.0
-    # FP32 stores H in single precision: each step's increment (about 1e-6 m,
-    # some 18 units in the last place at 0.5 m) rounds by at most half a unit
-    tol = 1e-13 if prec == "fp64" else steps * 0.5 * float(np.spacing(np.float32(0.5005)))
+    # FP32 keeps the surface as a float plus a 16-bit low part in units of
+    # 2^(e-40) for a surface in [2^(e-1), 2^e) (e = 0 here): each step rounds
+    # it by at most half of that unit
+    tol = 1e-13 if prec == "fp64" else steps * 2.0 ** -41
     assert np.max(np.abs(r["h"] - (0.5 + 1e-5 * 50.0))) <= tol
     assert abs(st.source_volume() - 1e-5 * 50.0 * 200.0) <= (1e-12 if prec == "fp64" else 1e-9) * 200.0
 

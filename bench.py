@@ -559,6 +559,20 @@ def main():
             "traffic": measured_traffic(wet.name, other, o["tile"]),
             "errors_vs_oracle": error_sample(wet, other, 3, om_omp, tile=o["tile"])}
         log(f"[bench] {other}: {variants[f'{wet.name}_{other}']}")
+    if want("prep"):
+        # mesh preparation (edge table, orientation, FP64 geometry, Hilbert
+        # order, boundary slots, tile edge lists) and its upload, once per mesh
+        from paper_2102_12862_amd import swe
+        prep = []
+        for _ in range(2):
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            m = swe.Mesh(wet.nodes, wet.tri, wet.bnd_seg, wet.bnd_tag, device=_dev())
+            torch.cuda.synchronize()
+            prep.append(time.perf_counter() - t1)
+            m.close()
+        variants["mesh_prep"] = {"cells": int(N), "seconds": min(prep), "host_threads": 1}
+        log(f"[bench] mesh preparation: {variants['mesh_prep']}")
     if want("tend") and args.workload == "valley_wet":
         dry = valley_dry()
         for p in ("fp32", "fp64"):

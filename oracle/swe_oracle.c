@@ -1243,8 +1243,8 @@ typedef struct {
     int wall, open, inflow_b;
 } edge_flux_t;
 
-/* A dynamic wall (section "Hydrodynamic BCs": removed once a threshold in
- * time or in water depth is reached) stands before its collapse time and,
+/* A dynamic wall (section "Hydrodynamic BCs": it collapses at a given time
+ * or at a given water depth) stands before its collapse time and,
  * with a collapse depth, before the end of the first step that started with
  * a cell next to it at that depth (reading: the wall holds through that
  * step and is gone from the next; dynamic_wall_depths sets the time). */
@@ -1301,9 +1301,9 @@ static void wall_side(om_sim *s, int32_t K, int kK, double nx, double ny, double
     if (s->morpho) s->bcont[3 * K + kK] = 0.0;
 }
 
-/* An internal rating curve (section "Hydrodynamic BCs", internal BCs: a
- * flow relation applies on one side, wall conditions on the other, the flow
- * one way; readings): the table's discharge at the upstream cell's surface,
+/* An internal rating curve (section "Hydrodynamic BCs", internal BCs; the
+ * upstream side, where the table acts, is the one left of the tag's
+ * segments): the table's discharge at the upstream cell's surface,
  * q = Q(H_U) / (the curve's length), crosses the edge from the cell U on the
  * left of the tag's segment to the other cell D.  U's side is the imposed
  * outflow of its own state, F = (q, q^2/h + g h^2/2, q u_t); D's side is the

@@ -1,12 +1,14 @@
 """Parity at the full valley-flood size (4M cells), in the launch
 configuration the benchmark times: every output compared with the oracle
-after a few steps (the oracle takes about a second per step at this size)."""
+after a few steps (the oracle takes about a second per step at this size);
+in FP64 also with the draining-time limiter and sources and sinks, with two
+passive species, and with the Exner module."""
 import numpy as np
 import pytest
 
 import oracle
 import swe_inputs as S
-from gpu_util import cached, compare, gpu_state
+from gpu_util import cached, compare, gpu_state, rel_err
 
 pytestmark = pytest.mark.gpu
 
@@ -52,3 +54,32 @@ def test_fullsize_fp64_two_steps(valley_wet, valley_oracle):
         st.step()
         sim.step()
     compare(st, sim, 1e-10)
+
+
+@pytest.mark.parametrize("extra", ["limiter_and_sources", "species", "morpho"])
+def test_fullsize_fp64_options(valley_wet, valley_oracle, extra):
+    from paper_2102_12862_amd import swe
+    n = valley_wet.n_cells
+    cx = valley_wet.centroids()[:, 0]
+    if extra == "limiter_and_sources":
+        # rain on the upper 4 km, a sink of what is there on the lower 4 km
+        region = np.where(cx < 4000.0, 0, np.where(cx > 16000.0, 1, -1)).astype(np.int32)
+        kw = {"drain": True, "src_region": region,
+              "sources": (S.Source(S.SRC_EXACT, S.SRC_INTENSITY, np.array([0.0]), np.array([50.0])),
+                          S.Source(S.SRC_AVAILABLE, S.SRC_INTENSITY, np.array([0.0]), np.array([-2.0e4])))}
+    elif extra == "species":
+        kw = {"phi0": np.random.default_rng(3).uniform(0.0, 1.0, (2, n))}
+    else:
+        kw = {"morpho": S.Morpho("mpm", d_m=1e-3)}
+    sc = S.Scenario(**{**valley_wet.__dict__, **kw})
+    st = gpu_state(sc, swe.FP64)
+    sim = oracle.Sim(sc, mesh=valley_oracle)
+    for _ in range(2):
+        dg, do = st.step(), sim.step()
+        assert abs(dg - do) <= 1e-13 * do, (dg, do)
+    compare(st, sim, 1e-10)
+    if extra == "species":
+        q, qo = st.scalars(), sim.scalars()
+        assert all(rel_err(q[c], qo[c]) <= 1e-10 for c in range(2))
+    if extra == "morpho":
+        assert rel_err(st.bed(), sim.bed()) <= 1e-10

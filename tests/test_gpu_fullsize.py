@@ -2,13 +2,15 @@
 configuration the benchmark times: every output compared with the oracle
 after a few steps (the oracle takes about a second per step at this size);
 in FP64 also with the draining-time limiter and sources and sinks, with two
-passive species, and with the Exner module."""
+passive species, and with the Exner module; in FP32 also with two species
+and with the Exner module (on a fixed step, L1 within 1e-4 and the max
+error within the full-size bound)."""
 import numpy as np
 import pytest
 
 import oracle
 import swe_inputs as S
-from gpu_util import cached, compare, gpu_state, rel_err
+from gpu_util import cached, compare, gpu_state, l1_rel, rel_err
 
 pytestmark = pytest.mark.gpu
 
@@ -83,3 +85,29 @@ def test_fullsize_fp64_options(valley_wet, valley_oracle, extra):
         assert all(rel_err(q[c], qo[c]) <= 1e-10 for c in range(2))
     if extra == "morpho":
         assert rel_err(st.bed(), sim.bed()) <= 1e-10
+
+
+@pytest.mark.parametrize("extra", ["species", "morpho"])
+def test_fullsize_fp32_options(valley_wet, valley_oracle, extra):
+    from paper_2102_12862_amd import swe
+    n = valley_wet.n_cells
+    if extra == "species":
+        kw = {"phi0": np.random.default_rng(4).uniform(0.0, 1.0, (2, n))}
+    else:
+        kw = {"morpho": S.Morpho("mpm", d_m=1e-3)}
+    sc = S.Scenario(**{**valley_wet.__dict__, **kw})
+    sc.dt_max = 0.5 * oracle.Sim(sc, mesh=valley_oracle).next_dt()
+    st = gpu_state(sc, swe.FP32)
+    sim = oracle.Sim(sc, mesh=valley_oracle)
+    for _ in range(3):
+        st.step()
+        sim.step()
+    errs = compare(st, sim, 1e-4, metric="l1", max_bound=FULLSIZE_MAX_BOUND)
+    print(f"fp32 full size, {extra}", errs)
+    if extra == "species":
+        area = valley_oracle.geometry()["area"]
+        q, qo = st.scalars(), sim.scalars()
+        for c in range(2):
+            assert l1_rel(q[c], qo[c], area) <= 1e-4 and rel_err(q[c], qo[c]) <= FULLSIZE_MAX_BOUND
+    if extra == "morpho":
+        assert rel_err(st.bed(), sim.bed()) <= 1e-4

@@ -4,7 +4,9 @@ after a few steps (the oracle takes about a second per step at this size);
 in FP64 also with the draining-time limiter and sources and sinks, with two
 passive species, and with the Exner module; in FP32 also with two species
 and with the Exner module (on a fixed step, L1 within 1e-4 and the max
-error within the full-size bound)."""
+error within the full-size bound); in FP64 with internal conditions on
+three bands of interior edges across the valley (a static wall, a rating
+curve and a dynamic wall that collapses by depth in the first step)."""
 import numpy as np
 import pytest
 
@@ -111,3 +113,38 @@ def test_fullsize_fp32_options(valley_wet, valley_oracle, extra):
             assert l1_rel(q[c], qo[c], area) <= 1e-4 and rel_err(q[c], qo[c]) <= FULLSIZE_MAX_BOUND
     if extra == "morpho":
         assert rel_err(st.bed(), sim.bed()) <= 1e-4
+
+
+def _interior_band(sc, x0, half_width=3.0):
+    """The interior edges whose midpoints lie within half_width of x = x0, as
+    segments running towards +y (so the side left of them is the side
+    towards -x)."""
+    tri = sc.tri.astype(np.int64)
+    xy = sc.nodes[:, :2]
+    nn = len(xy) + 1
+    e = np.concatenate([tri[:, [0, 1]], tri[:, [1, 2]], tri[:, [2, 0]]])
+    key = np.minimum(e[:, 0], e[:, 1]) * nn + np.maximum(e[:, 0], e[:, 1])
+    u, cnt = np.unique(key, return_counts=True)
+    a, b = u[cnt == 2] // nn, u[cnt == 2] % nn
+    m = np.abs(0.5 * (xy[a, 0] + xy[b, 0]) - x0) < half_width
+    a, b = a[m], b[m]
+    up = xy[a, 1] <= xy[b, 1]
+    return np.c_[np.where(up, a, b), np.where(up, b, a)].astype(np.int32)
+
+
+def test_fullsize_fp64_internal_conditions(valley_wet):
+    from paper_2102_12862_amd import swe
+    bands = [_interior_band(valley_wet, x0) for x0 in (6000.0, 10000.0, 14000.0)]
+    assert all(len(bd) > 1000 for bd in bands)
+    seg = np.concatenate([valley_wet.bnd_seg] + bands).astype(np.int32)
+    tag = np.concatenate([valley_wet.bnd_tag] + [np.full(len(bd), t, np.int32) for bd, t in zip(bands, (9, 10, 11))])
+    bcs = list(valley_wet.bcs) + [S.BC(9, S.WALL),
+                                  S.BC(10, S.OUTFLOW_HQ, t=np.array([5.0, 15.0]), Q=np.array([0.0, 500.0])),
+                                  S.BC(11, S.DYNAMIC_WALL, slope=1e30, par=0.9)]
+    sc = S.Scenario(**{**valley_wet.__dict__, "bnd_seg": seg, "bnd_tag": tag, "bcs": bcs})
+    st = gpu_state(sc, swe.FP64)
+    sim = oracle.Sim(sc)
+    for _ in range(3):
+        dg, do = st.step(), sim.step()
+        assert abs(dg - do) <= 1e-13 * do, (dg, do)
+    compare(st, sim, 1e-10)

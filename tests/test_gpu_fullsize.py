@@ -2,7 +2,7 @@
 configuration the benchmark times: every output compared with the oracle
 after a few steps (the oracle takes about a second per step at this size);
 in FP64 also with the draining-time limiter and sources and sinks, with two
-passive species, and with the Exner module; in FP32 also with two species
+passive species, with their diffusion, and with the Exner module; in FP32 also with two species
 and with the Exner module (on a fixed step, L1 within 1e-4 and the max
 error within the full-size bound); in FP64 with internal conditions on
 three bands of interior edges across the valley (a static wall, a rating
@@ -60,7 +60,7 @@ def test_fullsize_fp64_two_steps(valley_wet, valley_oracle):
     compare(st, sim, 1e-10)
 
 
-@pytest.mark.parametrize("extra", ["limiter_and_sources", "species", "morpho"])
+@pytest.mark.parametrize("extra", ["limiter_and_sources", "species", "diffusion", "morpho"])
 def test_fullsize_fp64_options(valley_wet, valley_oracle, extra):
     from paper_2102_12862_amd import swe
     n = valley_wet.n_cells
@@ -71,8 +71,10 @@ def test_fullsize_fp64_options(valley_wet, valley_oracle, extra):
         kw = {"drain": True, "src_region": region,
               "sources": (S.Source(S.SRC_EXACT, S.SRC_INTENSITY, np.array([0.0]), np.array([50.0])),
                           S.Source(S.SRC_AVAILABLE, S.SRC_INTENSITY, np.array([0.0]), np.array([-2.0e4])))}
-    elif extra == "species":
+    elif extra in ("species", "diffusion"):
         kw = {"phi0": np.random.default_rng(3).uniform(0.0, 1.0, (2, n))}
+        if extra == "diffusion":
+            kw["diffusion"] = S.Diffusion(Km=(0.5, 0.05), alpha_L=5.0, alpha_T=0.5, zeta=1.0)
     else:
         kw = {"morpho": S.Morpho("mpm", d_m=1e-3)}
     sc = S.Scenario(**{**valley_wet.__dict__, **kw})
@@ -82,7 +84,7 @@ def test_fullsize_fp64_options(valley_wet, valley_oracle, extra):
         dg, do = st.step(), sim.step()
         assert abs(dg - do) <= 1e-13 * do, (dg, do)
     compare(st, sim, 1e-10)
-    if extra == "species":
+    if extra in ("species", "diffusion"):
         q, qo = st.scalars(), sim.scalars()
         assert all(rel_err(q[c], qo[c]) <= 1e-10 for c in range(2))
     if extra == "morpho":
